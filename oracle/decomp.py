@@ -1,0 +1,139 @@
+"""Overlapping subdomains and the partition of unity (oracle; test infrastructure).
+
+Follows Sec. 3 and Sec. 4.3 of the paper:
+
+* a non-overlapping partition into boxes of elements is widened by ``ovl``
+  element layers (one layer = the elements sharing a vertex with the current
+  set, which for boxes is one element per side, clipped to the grid);
+* the overlap zone of subdomain j is the set of its elements that also lie
+  in another subdomain (Sec. 3); equivalently, elements counted at least
+  twice when every subdomain adds a one per element (Sec. 4.3);
+* ``N_j`` are the dofs of the closed subdomain, ``I_j`` those not on the
+  artificial (interior) part of its boundary, ``D_j`` those of ``I_j`` that
+  are not constrained by the Dirichlet condition;
+* the partition of unity is the piecewise constant one: with c_k the number
+  of subdomains having dof k in ``I_j``, mu_{j,k} = 1/c_k on ``D_j`` and 0
+  elsewhere -- zero at Dirichlet dofs and on subdomain boundaries, summing to
+  one over j at every free dof (Sec. 4.3; Def. 3).
+
+Pins (tests/test_oracle_decomp.py): closed-form set sizes, maximal cover
+count k0 = 2^d, the partition of unity summing to 1 at every free dof and
+vanishing where required, and the overlap zone matching its set definition.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import fem
+
+
+def part_ranges(n, parts):
+    """Element ranges [lo, hi) of a near-equal split of n elements into parts;
+    the first n % parts parts get one extra element."""
+    base, extra = divmod(n, parts)
+    sizes = [base + (1 if p < extra else 0) for p in range(parts)]
+    lo = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    return [(int(l), int(l + s)) for l, s in zip(lo, sizes)]
+
+
+@dataclass
+class Subdomain:
+    j: int
+    ebox: tuple          # per axis (elo, ehi), overlapping element range
+    elems: np.ndarray    # global element ids in the box
+    dofs: np.ndarray     # N_j, sorted global dofs
+    interior: np.ndarray  # bool over N_j: in I_j (not on artificial boundary)
+    dirichlet: np.ndarray  # bool over N_j: constrained dof
+    mu: np.ndarray       # partition-of-unity weights over N_j
+    overlap_elems: np.ndarray  # global element ids of the overlap zone
+
+    @property
+    def dmask(self):
+        """D_j as a mask over N_j."""
+        return self.interior & ~self.dirichlet
+
+
+def subdomain_boxes(prob):
+    """Overlapping element boxes, subdomain j = px + Px*(py + Py*pz)."""
+    per_axis = []
+    for ax in range(prob.dim):
+        rng = part_ranges(prob.ne[ax], prob.parts[ax])
+        per_axis.append([(max(0, lo - prob.ovl), min(prob.ne[ax], hi + prob.ovl))
+                         for lo, hi in rng])
+    boxes = []
+    for idx in np.ndindex(*reversed(prob.parts)):
+        pidx = tuple(reversed(idx))  # (px, py[, pz])
+        boxes.append(tuple(per_axis[ax][pidx[ax]] for ax in range(prob.dim)))
+    return boxes
+
+
+def _box_ids(lo, hi, strides):
+    """Flattened ids of the integer box prod [lo_a, hi_a) with the given strides."""
+    ids = np.zeros(1, dtype=np.int64)
+    for ax in reversed(range(len(lo))):
+        r = np.arange(lo[ax], hi[ax], dtype=np.int64) * strides[ax]
+        ids = (ids[:, None] + r[None, :]).ravel()
+    return ids
+
+
+def build(prob):
+    """All subdomains of ``prob`` with their sets, overlap zones and weights."""
+    dim, c = prob.dim, prob.ncomp
+    ne = prob.ne
+    nn = [n + 1 for n in ne]
+    estr = np.cumprod([1] + list(ne[:-1]))
+    nstr = np.cumprod([1] + nn[:-1])
+    boxes = subdomain_boxes(prob)
+    dmask_glob = fem.dirichlet_mask(prob)
+
+    # element multiplicity: every subdomain adds one on each of its elements
+    mult = np.zeros(prob.nelem, dtype=np.int64)
+    for b in boxes:
+        mult[_box_ids([x[0] for x in b], [x[1] for x in b], estr)] += 1
+
+    subs = []
+    icount = np.zeros(prob.ndof, dtype=np.int64)
+    for j, b in enumerate(boxes):
+        lo = [x[0] for x in b]
+        hi = [x[1] for x in b]
+        elems = _box_ids(lo, hi, estr)
+        nodes = _box_ids(lo, [h + 1 for h in hi], nstr)
+        # artificial boundary: box face strictly inside the grid
+        coords = []
+        k = nodes.copy()
+        for ax in range(dim):
+            coords.append(k % nn[ax])
+            k //= nn[ax]
+        art = np.zeros(len(nodes), dtype=bool)
+        for ax in range(dim):
+            if lo[ax] > 0:
+                art |= coords[ax] == lo[ax]
+            if hi[ax] < ne[ax]:
+                art |= coords[ax] == hi[ax]
+        if c == 1:
+            dofs = nodes
+            interior = ~art
+        else:
+            dofs = (nodes[:, None] * c + np.arange(c)[None, :]).ravel()
+            interior = np.repeat(~art, c)
+        order = np.argsort(dofs, kind="stable")
+        dofs, interior = dofs[order], interior[order]
+        icount[dofs[interior]] += 1
+        subs.append(Subdomain(j=j, ebox=b, elems=elems, dofs=dofs,
+                              interior=interior,
+                              dirichlet=dmask_glob[dofs], mu=None,
+                              overlap_elems=elems[mult[elems] >= 2]))
+    for s in subs:
+        d = s.dmask
+        mu = np.zeros(len(s.dofs))
+        mu[d] = 1.0 / icount[s.dofs[d]]
+        s.mu = mu
+    return subs, mult
+
+
+def pou_sum(prob, subs):
+    """sum_j R_j^T mu_j as a global vector."""
+    out = np.zeros(prob.ndof)
+    for s in subs:
+        np.add.at(out, s.dofs, s.mu)
+    return out

@@ -1,0 +1,234 @@
+"""Q1 finite elements on a structured box grid (oracle; test infrastructure).
+
+Discretises the Darcy form (Sec. 2, eq. (2)) and the linear-elasticity form
+(Sec. 2, eq. (3), no traction term) with a conforming space of continuous
+(tri)linear Q1 functions, as the paper's Sec. 5.2 experiments use Q1
+elements.  Element integrals use the tensor 2-point Gauss rule, which is
+exact for products of Q1 gradients with a constant coefficient.
+
+Homogeneous Dirichlet conditions (``u = 0`` on the flagged faces) are
+imposed by symmetric elimination: the row and column of a constrained degree
+of freedom are zeroed, its diagonal set to 1 and its load to 0.  With zero
+boundary data the free unknowns are exactly those of the eliminated system.
+
+Pins (tests/test_oracle_fem.py): closed-form Q1 stencils, zero row sums of
+the Neumann operator, O(h^2) nodal convergence to a manufactured solution,
+the six rigid-body modes spanning the kernel of a free elasticity element and
+a patch test.
+"""
+import itertools
+
+import numpy as np
+import scipy.sparse as sp
+
+_G = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])  # on [0,1]
+_W = np.array([0.5, 0.5])
+
+
+def _local_offsets(dim):
+    """Offsets of the 2^d element vertices, vertex a <-> bits (x, y, z) of a."""
+    return np.array([[(a >> i) & 1 for i in range(dim)] for a in range(2 ** dim)])
+
+
+def _shape_and_grad(dim, xi):
+    """Q1 shape values and reference gradients at a point xi of [0,1]^d."""
+    off = _local_offsets(dim)
+    nv = len(off)
+    phi = np.ones(nv)
+    grad = np.ones((nv, dim))
+    for a in range(nv):
+        for i in range(dim):
+            f = xi[i] if off[a, i] else 1.0 - xi[i]
+            phi[a] *= f
+            for j in range(dim):
+                if j == i:
+                    grad[a, j] *= 1.0 if off[a, i] else -1.0
+                else:
+                    grad[a, j] *= f
+    return phi, grad
+
+
+def quadrature(dim):
+    """Tensor Gauss points on [0,1]^d and their weights."""
+    pts, wts = [], []
+    for idx in itertools.product(range(2), repeat=dim):
+        pts.append([_G[i] for i in idx])
+        wts.append(np.prod([_W[i] for i in idx]))
+    return np.array(pts), np.array(wts)
+
+
+def darcy_element_matrix(h):
+    """Element matrix of int grad v . grad w over one box element, kappa = 1."""
+    h = np.asarray(h, dtype=np.float64)
+    dim = len(h)
+    pts, wts = quadrature(dim)
+    vol = np.prod(h)
+    K = np.zeros((2 ** dim, 2 ** dim))
+    for x, w in zip(pts, wts):
+        _, g = _shape_and_grad(dim, x)
+        g = g / h[None, :]
+        K += w * vol * g @ g.T
+    return K
+
+
+def strain_matrix(grad_phys):
+    """6 x 24 strain-displacement matrix (Voigt 11,22,33,23,13,12; engineering shear)."""
+    nv = grad_phys.shape[0]
+    B = np.zeros((6, 3 * nv))
+    for a in range(nv):
+        dx, dy, dz = grad_phys[a]
+        c = 3 * a
+        B[0, c + 0] = dx
+        B[1, c + 1] = dy
+        B[2, c + 2] = dz
+        B[3, c + 1], B[3, c + 2] = dz, dy
+        B[4, c + 0], B[4, c + 2] = dz, dx
+        B[5, c + 0], B[5, c + 1] = dy, dx
+    return B
+
+
+def elasticity_element_matrix(h, C):
+    """Element matrix of int C eps(v):eps(w) over one box element (3D)."""
+    h = np.asarray(h, dtype=np.float64)
+    pts, wts = quadrature(3)
+    vol = np.prod(h)
+    K = np.zeros((24, 24))
+    for x, w in zip(pts, wts):
+        _, g = _shape_and_grad(3, x)
+        B = strain_matrix(g / h[None, :])
+        K += w * vol * B.T @ C @ B
+    return K
+
+
+def voigt_full(c21):
+    """Symmetric 6x6 matrix from its 21 upper-triangle entries (row major)."""
+    C = np.zeros((6, 6))
+    C[np.triu_indices(6)] = c21
+    return C + np.triu(C, 1).T
+
+
+def element_nodes(prob):
+    """(nelem, 2^d) global node numbers of every element, vertex order as in
+    :func:`_local_offsets`."""
+    ne = prob.ne
+    dim = prob.dim
+    nn = [n + 1 for n in ne]
+    grids = np.meshgrid(*[np.arange(n) for n in reversed(ne)], indexing="ij")
+    # grids[...] indexed [iz,iy,ix]; flatten in C order -> e = ix + nx*(iy+...)
+    eidx = [g.ravel() for g in reversed(grids)]  # eidx[a] = coordinate on axis a
+    off = _local_offsets(dim)
+    nodes = np.zeros((prob.nelem, 2 ** dim), dtype=np.int64)
+    for a in range(2 ** dim):
+        k = np.zeros(prob.nelem, dtype=np.int64)
+        stride = 1
+        for ax in range(dim):
+            k += (eidx[ax] + off[a, ax]) * stride
+            stride *= nn[ax]
+        nodes[:, a] = k
+    return nodes
+
+
+def element_dofs(prob):
+    """(nelem, 2^d * ncomp) global dof numbers, element vertex-major."""
+    nodes = element_nodes(prob)
+    if prob.ncomp == 1:
+        return nodes
+    c = prob.ncomp
+    return (nodes[:, :, None] * c + np.arange(c)[None, None, :]).reshape(len(nodes), -1)
+
+
+def element_matrices(prob, elems=None):
+    """Element matrices of the given elements (all by default), shape
+    (len(elems), ndofe, ndofe)."""
+    if elems is None:
+        elems = np.arange(prob.nelem)
+    elems = np.asarray(elems)
+    if prob.ncomp == 1:
+        Kref = darcy_element_matrix(prob.h)
+        return prob.coeff[elems][:, None, None] * Kref[None]
+    coeff = prob.coeff[elems]
+    uniq, inv = np.unique(coeff, axis=0, return_inverse=True)
+    Ku = np.array([elasticity_element_matrix(prob.h, voigt_full(c)) for c in uniq])
+    return Ku[inv.ravel()]
+
+
+def element_load(prob, f=None):
+    """Element load vectors int f phi_a; ``f`` is the constant body load of
+    ``prob`` unless a callable f(x) -> (ncomp,) values is given."""
+    dim, c = prob.dim, prob.ncomp
+    pts, wts = quadrature(dim)
+    h = np.asarray(prob.h)
+    vol = np.prod(h)
+    nodes = element_nodes(prob)
+    nv = 2 ** dim
+    out = np.zeros((prob.nelem, nv, c))
+    if f is None:
+        load = np.asarray(prob.load, dtype=np.float64)
+        for x, w in zip(pts, wts):
+            phi, _ = _shape_and_grad(dim, x)
+            out += w * vol * phi[None, :, None] * load[None, None, :]
+    else:
+        # element origin from its vertex 0
+        nn = [n + 1 for n in prob.ne]
+        k0 = nodes[:, 0]
+        coords = []
+        for ax in range(dim):
+            coords.append((k0 % nn[ax]) * h[ax])
+            k0 = k0 // nn[ax]
+        origin = np.stack(coords, axis=1)
+        for x, w in zip(pts, wts):
+            phi, _ = _shape_and_grad(dim, x)
+            fx = np.asarray(f(origin + x[None, :] * h[None, :]), dtype=np.float64)
+            fx = fx.reshape(prob.nelem, c)
+            out += w * vol * phi[None, :, None] * fx[:, None, :]
+    return out.reshape(prob.nelem, nv * c)
+
+
+def dirichlet_mask(prob):
+    """Boolean mask over dofs: True where a homogeneous Dirichlet condition holds."""
+    nn = [n + 1 for n in prob.ne]
+    coords = np.meshgrid(*[np.arange(n) for n in reversed(nn)], indexing="ij")
+    coords = [g.ravel() for g in reversed(coords)]
+    m = np.zeros(prob.nnodes, dtype=bool)
+    for ax in range(prob.dim):
+        if prob.dirichlet >> (2 * ax) & 1:
+            m |= coords[ax] == 0
+        if prob.dirichlet >> (2 * ax + 1) & 1:
+            m |= coords[ax] == prob.ne[ax]
+    return np.repeat(m, prob.ncomp)
+
+
+def eliminate(A, b, dmask):
+    """Symmetric elimination of zero Dirichlet data: zero rows/cols, unit diagonal."""
+    keep = sp.diags((~dmask).astype(np.float64))
+    A2 = (keep @ A @ keep + sp.diags(dmask.astype(np.float64))).tocsr()
+    A2.sum_duplicates()
+    A2.sort_indices()
+    b2 = None if b is None else np.where(dmask, 0.0, b)
+    return A2, b2
+
+
+def assemble(prob, f=None):
+    """Global CSR stiffness matrix and load vector with Dirichlet elimination."""
+    dofs = element_dofs(prob)
+    Ke = element_matrices(prob)
+    nd = dofs.shape[1]
+    rows = np.repeat(dofs, nd, axis=1).ravel()
+    cols = np.tile(dofs, (1, nd)).ravel()
+    A = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(prob.ndof, prob.ndof)).tocsr()
+    A.sum_duplicates()
+    fe = element_load(prob, f)
+    b = np.bincount(dofs.ravel(), weights=fe.ravel(), minlength=prob.ndof)
+    return eliminate(A, b, dirichlet_mask(prob))
+
+
+def assemble_neumann(prob, f=None):
+    """Global matrix without any boundary condition (for kernel/row-sum pins)."""
+    dofs = element_dofs(prob)
+    Ke = element_matrices(prob)
+    nd = dofs.shape[1]
+    rows = np.repeat(dofs, nd, axis=1).ravel()
+    cols = np.tile(dofs, (1, nd)).ravel()
+    A = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(prob.ndof, prob.ndof)).tocsr()
+    A.sum_duplicates()
+    return A

@@ -1,0 +1,156 @@
+"""Pins of the oracle's Q1 discretisation (Sec. 2, eqs. (2)-(3))."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _node(prob, *c):
+    nn = [n + 1 for n in prob.ne]
+    k, s = 0, 1
+    for ax, x in enumerate(c):
+        k += x * s
+        s *= nn[ax]
+    return k
+
+
+@pytest.mark.parametrize("n", [8, 13])
+def test_2d_stencil_closed_form(n):
+    g = _gold("q1_stencils.json")["2d"]
+    p = synth.darcy_problem("t", np.ones((n, n)), (1, 1), 1)
+    A = fem.assemble_neumann(p).toarray()
+    c = _node(p, 4, 5)
+    assert A[c, c] == pytest.approx(g["center"], rel=1e-14)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            if dx == dy == 0:
+                continue
+            kind = "corner" if dx and dy else "edge"
+            assert A[c, _node(p, 4 + dx, 5 + dy)] == pytest.approx(g[kind], rel=1e-14)
+    assert np.count_nonzero(np.abs(A[c]) > 1e-15) == 9
+
+
+def test_2d_element_matrix_closed_form():
+    g = _gold("q1_stencils.json")["element_2d"]
+    K = fem.darcy_element_matrix((0.25, 0.25))
+    # vertices 0:(0,0) 1:(1,0) 2:(0,1) 3:(1,1)
+    assert np.allclose(np.diag(K), g["diag"], rtol=1e-14)
+    assert K[0, 1] == pytest.approx(g["edge"]) and K[0, 2] == pytest.approx(g["edge"])
+    assert K[0, 3] == pytest.approx(g["opposite"]) and K[1, 2] == pytest.approx(g["opposite"])
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_3d_stencil_closed_form(n):
+    g = _gold("q1_stencils.json")["3d"]
+    h = 1.0 / n
+    p = synth.darcy_problem("t", np.ones((n, n, n)), (1, 1, 1), 1)
+    A = fem.assemble_neumann(p).tocsr()
+    c = _node(p, 3, 3, 2)
+    row = A[c].toarray().ravel()
+    names = {0: "center_over_h", 1: "face_over_h", 2: "edge_over_h", 3: "corner_over_h"}
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                nz = (dx != 0) + (dy != 0) + (dz != 0)
+                v = row[_node(p, 3 + dx, 3 + dy, 2 + dz)]
+                assert v == pytest.approx(g[names[nz]] * h, abs=1e-15)
+
+
+def test_neumann_row_sums_vanish_with_variable_kappa():
+    rng = np.random.Generator(np.random.PCG64(3))
+    k = np.exp(rng.normal(size=(7, 9)))
+    p = synth.darcy_problem("t", k, (1, 1), 1)
+    A = fem.assemble_neumann(p)
+    assert np.max(np.abs(A @ np.ones(p.ndof))) < 1e-13 * np.max(k)
+    assert abs(A - A.T).max() <= 1e-15 * np.max(k)
+
+
+def test_total_load_equals_f_times_volume():
+    p = synth.darcy_problem("t", np.ones((5, 7)), (1, 1), 1, load=3.0)
+    fe = fem.element_load(p)
+    assert fe.sum() == pytest.approx(3.0 * 1.0, rel=1e-14)
+
+
+def test_dirichlet_elimination():
+    p = synth.config1_channels(0, n=16, parts=2, n_channels=2)
+    A, b = fem.assemble(p)
+    d = fem.dirichlet_mask(p)
+    Ad = A.toarray()
+    assert np.array_equal(Ad, Ad.T)
+    assert np.all(Ad[d][:, d] == np.eye(d.sum()))
+    assert np.all(Ad[d][:, ~d] == 0) and np.all(b[d] == 0)
+    assert np.all(b[~d] > 0)
+
+
+def _manufactured_error(n):
+    p = synth.darcy_problem("t", np.ones((n, n)), (1, 1), 1)
+
+    def f(x):
+        return 2 * np.pi ** 2 * np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])
+
+    A, b = fem.assemble(p, f=f)
+    import scipy.sparse.linalg as spla
+    u = spla.spsolve(A.tocsc(), b)
+    xs = np.arange(n + 1) / n
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    ex = (np.sin(np.pi * X) * np.sin(np.pi * Y)).ravel()
+    return np.max(np.abs(u - ex))
+
+
+def test_manufactured_solution_second_order():
+    e = [_manufactured_error(n) for n in (8, 16, 32)]
+    assert e[0] / e[1] > 3.5 and e[1] / e[2] > 3.5
+    assert e[2] < 5e-3
+
+
+def _rbm(coords):
+    x, y, z = coords.T
+    o, zr = np.ones_like(x), np.zeros_like(x)
+    modes = [(o, zr, zr), (zr, o, zr), (zr, zr, o),
+             (-y, x, zr), (zr, -z, y), (z, zr, -x)]
+    return np.array([np.stack(m, axis=1).ravel() for m in modes]).T
+
+
+def test_elasticity_element_kernel_is_rigid_body_modes():
+    ply = synth.ply_stiffness(160.0, 10.0, 10.0, 5.0, 5.0, 5.0, 0.3, 0.3, 0.3)
+    for C in (ply, synth.rotate_z90(ply), synth.isotropic_stiffness(4.0, 0.35)):
+        K = fem.elasticity_element_matrix((1.0, 0.7, 1.3), C)
+        ev = np.linalg.eigvalsh(K)
+        assert np.sum(np.abs(ev) < 1e-10 * ev[-1]) == 6
+        assert ev[6] > 1e-6 * ev[-1]
+        off = np.array([[(a >> i) & 1 for i in range(3)] for a in range(8)], float)
+        R = _rbm(off * np.array([1.0, 0.7, 1.3]))
+        assert np.max(np.abs(K @ R)) < 1e-12 * ev[-1]
+
+
+def test_elasticity_patch_test():
+    C = synth.ply_stiffness(160.0, 10.0, 10.0, 5.0, 5.0, 5.0, 0.3, 0.3, 0.3)
+    ne = (4, 3, 3)
+    Cs = np.broadcast_to(C, (3, 3, 4, 6, 6))
+    p = synth.elasticity_problem("t", Cs, ne, (1, 1, 1), 1, dirichlet=0,
+                                 load=(0.0, 0.0, 0.0), h=(0.5, 1.0, 2.0))
+    A = fem.assemble_neumann(p)
+    nn = [n + 1 for n in ne]
+    k = np.arange(p.nnodes)
+    ix, iy, iz = k % nn[0], (k // nn[0]) % nn[1], k // (nn[0] * nn[1])
+    coords = np.stack([ix * 0.5, iy * 1.0, iz * 2.0], axis=1)
+    rng = np.random.Generator(np.random.PCG64(1))
+    Gm = rng.normal(size=(3, 3))
+    u = (coords @ Gm.T).ravel()
+    r = (A @ u).reshape(-1, 3)
+    inner = (ix > 0) & (ix < ne[0]) & (iy > 0) & (iy < ne[1]) & (iz > 0) & (iz < ne[2])
+    assert np.max(np.abs(r[inner])) < 1e-11 * np.max(np.abs(A.data)) * np.max(np.abs(u))
+    # six-dimensional kernel of the free assembled operator
+    R = _rbm(coords)
+    assert np.max(np.abs(A @ R)) < 1e-11 * np.max(np.abs(A.data)) * np.max(np.abs(R))
