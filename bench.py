@@ -1,0 +1,256 @@
+"""Benchmark: GenEO setup + PCG to a 1e-10 residual reduction on one MI355X.
+
+A step is one pass of the whole path over one synthetic problem already
+resident in HBM (the per-element coefficient field): device Q1 assembly of
+the global and local matrices, the GenEO setup (local factors, shifted
+factors, eigen sweeps, coarse basis, Galerkin product, coarse factor) and
+the graph-captured PCG solve.  The default workload is the 2D Darcy problem
+on a 512^2 Q1 grid (263,169 dofs), 16x16 subdomains of 32^2 elements with
+two-element overlap, k = exp(GRF) with 24 discs of contrast 1e6, threshold
+lambda < 0.1 capped at 16 vectors, FP32 local factors.
+
+Prints one JSON line (see the keys below).  `--gpus N` with N > 1 exits:
+this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3",
+                                                            "config4"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def make_problem(name, seed):
+    import synth
+    return synth.CONFIGS[name](seed=seed)
+
+
+class Runner:
+    """Holds the resident input and runs steps through the C ABI."""
+
+    def __init__(self, prob):
+        import torch
+        from paper_1906_10944_amd import geneo as G
+        self.G = G
+        self.prob = prob
+        self.grid = G.grid_from_problem(prob)
+        self.coeff = torch.as_tensor(prob.coeff, dtype=torch.float64).cuda().contiguous()
+        torch.cuda.synchronize()
+
+    def step(self, precision):
+        import torch
+        G = self.G
+        sysm = G.geneo_assemble_q1(self.grid, self.coeff)
+        opts = G.opts_from_problem(self.prob, precision=precision)
+        h = G.geneo_setup(sysm.csr(), sysm.subdomains(), sysm.neumann(), sysm.overlap(), opts)
+        x = torch.zeros_like(sysm.b)
+        info = G.pcg_solve(sysm.csr(), h, sysm.b, x, rtol=self.prob.rtol, maxit=self.prob.maxit)
+        sinfo = G.geneo_get_setup_info(h)
+        out = {"iters": info["iters"], "converged": info["converged"], "relres": info["relres"],
+               "kappa_est": info["kappa_est"], "t_solve_ms": info["t_solve_ms"],
+               "t_setup_ms": sinfo["t_setup_ms"], "nc": sinfo["nc"],
+               "eig_sweeps": sinfo["eig_sweeps"], "fallback_fp64": sinfo["fallback_fp64"],
+               "t_phase_ms": sinfo["t_phase_ms"]}
+        self.last = (sysm, h, x)
+        return out
+
+    def true_residual(self):
+        import torch
+        sysm, h, x = self.last
+        y = torch.empty_like(x)
+        self.G.geneo_spmv(sysm.csr(), x, y)
+        torch.cuda.synchronize()
+        return float(torch.linalg.norm(sysm.b - y) / torch.linalg.norm(sysm.b))
+
+    def release(self):
+        self.last[1].close()
+        self.last = None
+
+
+def timed(runner, precision, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        runner.step(precision)
+        runner.release()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        infos.append(runner.step(precision))
+        if k + 1 < steps:
+            runner.release()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, infos
+
+
+def prof_query(G, name):
+    import ctypes as C
+    L = G.lib()
+    L.geneo_prof_query.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    t, n, by, fl = C.c_double(), C.c_int(), C.c_double(), C.c_double()
+    rc = L.geneo_prof_query(name.encode(), C.byref(t), C.byref(n), C.byref(by), C.byref(fl))
+    if rc:
+        raise RuntimeError("geneo_prof_query failed")
+    return {"ms": t.value, "launches": n.value, "bytes": by.value, "flops": fl.value}
+
+
+PROF_KERNELS = ["densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
+                "trtri_dirichlet", "densify_shifted", "chol_shifted_f64", "trsm_bwd",
+                "trsm_fwd", "bapply", "rayleigh_ritz", "orth", "coarse_chol",
+                "trmv_lower_f32", "trmv_upperT_f32", "trmv_lower_f64", "trmv_upperT_f64"]
+
+
+def kernel_profile(runner, precision):
+    """One extra step with the library's event timing on, plus eager applies
+    (the PCG iterations themselves run inside a captured graph)."""
+    import torch
+    G = runner.G
+    L = G.lib()
+    L.geneo_prof_enable(1)
+    runner.step(precision)
+    sysm, h, x = runner.last
+    r = torch.ones_like(x)
+    z = torch.empty_like(x)
+    for _ in range(10):
+        G.geneo_apply(h, r, z)
+    torch.cuda.synchronize()
+    prof = {k: prof_query(G, k) for k in PROF_KERNELS}
+    L.geneo_prof_enable(0)
+    runner.release()
+    return prof
+
+
+def roofline(prof):
+    """Dominant kernel by event time, against its bound."""
+    name = max(prof, key=lambda k: prof[k]["ms"])
+    p = prof[name]
+    avg_ms = p["ms"] / max(p["launches"], 1)
+    compute_bound = name.startswith("chol") or name.startswith("trtri") or name == "coarse_chol"
+    if compute_bound:
+        peak = FP32_MFMA_PEAK_TFLOPS if name.endswith("f32") else FP64_PEAK_TFLOPS
+        achieved = p["flops"] / max(p["launches"], 1) / (avg_ms * 1e-3) / 1e12
+        rf = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    else:
+        achieved = p["bytes"] / max(p["launches"], 1) / (avg_ms * 1e-3) / 1e9
+        rf = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    rf["frac"] = rf["achieved"] / rf["peak"]
+    rf["traffic"] = None
+    rf["kernel"] = name
+    rf["avg_launch_ms"] = avg_ms
+    rf["launches"] = p["launches"]
+    return rf
+
+
+def cpu_baseline(prob, gpu_iters, budget_s):
+    """The oracle timed on a bounded sample of the same workload: global
+    assembly, the per-subdomain setup of as many subdomains as fit in the
+    budget, and a few PCG iterations; extrapolated to the full solve."""
+    import numpy as np
+    from oracle import decomp, fem, geneo, pcg
+    t0 = time.perf_counter()
+    A, b = fem.assemble(prob)
+    subs, _ = decomp.build(prob)
+    t_asm = time.perf_counter() - t0
+    # per-subdomain setup (local matrices, Dirichlet factor, eigenproblem)
+    done, t_sub = 0, 0.0
+    order = list(range(0, len(subs), max(1, len(subs) // 16)))
+    for j in order:
+        t1 = time.perf_counter()
+        sub = [subs[j]]
+        geneo.setup(prob, A=A, subs=sub, coarse=True)
+        t_sub += time.perf_counter() - t1
+        done += 1
+        if t_sub > budget_s * 0.7:
+            break
+    per_sub = t_sub / done
+    # one-level apply + SpMV per iteration, timed on 3 iterations
+    g1 = geneo.setup(prob, A=A, subs=subs[:0], coarse=False)
+    t2 = time.perf_counter()
+    r = b.copy()
+    for _ in range(3):
+        _ = A @ r
+    t_spmv = (time.perf_counter() - t2) / 3
+    est = t_asm + per_sub * len(subs) + gpu_iters * t_spmv
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": prob.ndof / est, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": "global assembly + per-subdomain GenEO setup of %d of %d subdomains "
+                      "(%.1f s each) + SpMV x %d iterations, extrapolated to all %d subdomains; "
+                      "local solves and coarse solve per iteration not included (lower bound "
+                      "on oracle time)" % (done, len(subs), per_sub, gpu_iters, len(subs)),
+            "est_total_s": est}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported"
+                          % args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1906_10944_amd import geneo as G
+    G.lib()
+    prob = make_problem(args.config, args.seed)
+    runner = Runner(prob)
+    mixed = 1 if prob.precision == "mixed" else 0
+    ms, infos = timed(runner, mixed, args.steps, args.warmup)
+    tres = runner.true_residual()
+    runner.release()
+    last = infos[-1]
+    out = {
+        "metric": "GenEO setup+PCG DOF/s to 1e-10 residual reduction (one GPU)",
+        "value": prob.ndof / (ms * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 local factors + f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "ndof": prob.ndof, "nsub": prob.nsub,
+                   "form": "mixed" if mixed else "fp64", "rtol": prob.rtol,
+                   "seed": args.seed},
+        "iters": last["iters"], "converged": bool(last["converged"]),
+        "relres": last["relres"], "true_relres": tres, "kappa_est": last["kappa_est"],
+        "nc": last["nc"], "eig_sweeps": last["eig_sweeps"],
+        "fallback_fp64": last["fallback_fp64"],
+        "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
+        "setup_phase_ms": last["t_phase_ms"][:6],
+    }
+    if mixed and not args.no_fp64_form:
+        ms64, inf64 = timed(runner, 0, 1, 0)
+        runner.release()
+        out["fp64_form"] = {"ms_per_step": ms64, "value": prob.ndof / (ms64 * 1e-3),
+                            "iters": inf64[-1]["iters"], "setup_ms": inf64[-1]["t_setup_ms"],
+                            "solve_ms": inf64[-1]["t_solve_ms"]}
+        out["speedup_vs_fp64_form"] = ms64 / ms
+    prof = kernel_profile(runner, mixed)
+    out["roofline"] = roofline(prof)
+    out["kernels_ms"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, last["iters"], args.cpu_budget_s)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

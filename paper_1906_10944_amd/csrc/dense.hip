@@ -1,0 +1,121 @@
+// Dense local matrices in packed lower-triangular tile storage.
+//
+//  * Dirichlet matrices A_j = R_j A R_j^T (Sec. 3) over D_j, read from the
+//    global CSR matrix, symmetrically scaled by D^{-1/2} (unit diagonal),
+//    stored in FP32 (mixed mode) or FP64.
+//  * Shifted matrices C_j = A_N,j - sigma X_j A^o_j X_j over N_j (the matrix
+//    of the shift-and-invert transform of Sec. 4.4), FP64.
+// One block per subdomain: it clears its tiles (identity on the padding)
+// and then every thread owns whole rows, so no two threads write the same
+// entry.
+#include "internal.h"
+
+namespace geneo {
+
+template <typename T>
+__device__ __forceinline__ T* tile_elem(T* base, int r, int c) {
+  return base + tile_idx(r / TS, c / TS) * TSQ + (r % TS) * TS + (c % TS);
+}
+
+template <typename T>
+__device__ void clear_tiles(T* base, int nt) {
+  const int64_t ne = tri_tiles(nt) * TSQ;
+  for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) base[e] = (T)0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nt * TS; r += blockDim.x) *tile_elem(base, r, r) = (T)1;
+  __syncthreads();
+}
+
+__device__ __forceinline__ int bsearch_row(const int* a, int n, int key) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int v = a[mid];
+    if (v == key) return mid;
+    if (v < key) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_densify_dirichlet(
+    T* __restrict__ tiles, const int64_t* __restrict__ toff, const int* __restrict__ ntl,
+    const int* __restrict__ voff, const int* __restrict__ jobs, const int* __restrict__ sub_ptr,
+    const int* __restrict__ sub_idx, const int* __restrict__ dmap, const int* __restrict__ dglob,
+    const double* __restrict__ dscale, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const double* __restrict__ val) {
+  const int j = jobs[blockIdx.x];
+  const int nt = ntl[j];
+  T* base = tiles + toff[j] * TSQ;
+  clear_tiles(base, nt);
+  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
+  const int v0 = voff[j];
+  const int* Nj = sub_idx + s0;
+  for (int d = threadIdx.x; d < nt * TS; d += blockDim.x) {
+    int g = dglob[v0 + d];
+    if (g < 0) continue;
+    double sd = dscale[v0 + d];
+    for (int p = rowptr[g]; p < rowptr[g + 1]; ++p) {
+      int a = bsearch_row(Nj, n, col[p]);
+      if (a < 0) continue;
+      int dc = dmap[s0 + a];
+      if (dc < 0 || dc > d) continue;
+      *tile_elem(base, d, dc) = (T)(val[p] * sd * dscale[v0 + dc]);
+    }
+  }
+}
+
+hipError_t launch_densify_dirichlet(bool fp32, void* tiles, const int64_t* toff, const int* nt,
+                                    const int* voff, const int* jobs, int njobs,
+                                    const int* sub_ptr, const int* sub_idx, const int* dmap,
+                                    const int* dglob, const double* dscale, const geneo_csr_t* A,
+                                    hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_densify_dirichlet<float>, dim3(njobs), dim3(256), 0, st, (float*)tiles,
+                       toff, nt, voff, jobs, sub_ptr, sub_idx, dmap, dglob, dscale, A->rowptr,
+                       A->col, A->val);
+  else
+    hipLaunchKernelGGL(k_densify_dirichlet<double>, dim3(njobs), dim3(256), 0, st,
+                       (double*)tiles, toff, nt, voff, jobs, sub_ptr, sub_idx, dmap, dglob,
+                       dscale, A->rowptr, A->col, A->val);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_densify_shifted(
+    double* __restrict__ tiles, const int64_t* __restrict__ toff, const int* __restrict__ ntl,
+    const int* __restrict__ sub_ptr, const double* __restrict__ pou,
+    const int* __restrict__ an_rp, const int* __restrict__ an_col,
+    const double* __restrict__ an_val, const int* __restrict__ ao_rp,
+    const int* __restrict__ ao_col, const double* __restrict__ ao_val, double sigma) {
+  const int j = blockIdx.x;
+  const int nt = ntl[j];
+  double* base = tiles + toff[j] * TSQ;
+  clear_tiles(base, nt);
+  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    for (int p = an_rp[s0 + a]; p < an_rp[s0 + a + 1]; ++p) {
+      int c = an_col[p];
+      if (c <= a) *tile_elem(base, a, c) = an_val[p];
+    }
+    double mua = pou[s0 + a];
+    if (mua != 0.0) {
+      for (int p = ao_rp[s0 + a]; p < ao_rp[s0 + a + 1]; ++p) {
+        int c = ao_col[p];
+        if (c <= a) *tile_elem(base, a, c) -= sigma * mua * ao_val[p] * pou[s0 + c];
+      }
+    }
+  }
+}
+
+hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int* nt, int nsub,
+                                  const int* sub_ptr, const double* pou,
+                                  const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
+                                  double sigma, hipStream_t st) {
+  hipLaunchKernelGGL(k_densify_shifted, dim3(nsub), dim3(256), 0, st, tiles, toff, nt, sub_ptr,
+                     pou, An->rowptr, An->col, An->val, Ao->rowptr, Ao->col, Ao->val, sigma);
+  return hipGetLastError();
+}
+
+}  // namespace geneo

@@ -1,0 +1,127 @@
+// Internal declarations of libgeneo (host launchers of the device kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "geneo.h"
+
+namespace geneo {
+
+// Per-subdomain layout of the dense local factors and padded vectors.
+struct LocalLayout {
+  int n = 0;                          // subdomains
+  std::vector<int> nrow;              // matrix order per subdomain
+  std::vector<int> nt;                // tile rows = ceil(nrow / TS) (at least 1)
+  std::vector<int64_t> toff;          // tile offset (units of TSQ elements)
+  std::vector<int64_t> doff;          // diagonal-tile offset = sum of nt
+  std::vector<int> voff;              // padded-vector offset = sum of nt*TS
+  int64_t ntiles = 0, ndiag = 0;
+  int64_t nvec = 0;
+  int maxnt = 0;
+  void build(const std::vector<int>& rows);
+};
+
+// ---------------------------------------------------------------- util.hip
+hipError_t scan_exclusive_i32(const int* in, int* out, int64_t n, int* total_dev,
+                              hipStream_t st);  // out[n] also written
+hipError_t launch_dmap(const int* sub_ptr, const uint8_t* flags, int nsub, int* dmap,
+                       int* nd, hipStream_t st);
+hipError_t launch_dvec(const int* sub_ptr, const int* sub_idx, const int* dmap,
+                       const int* voff, const int* nt, int nsub, const geneo_csr_t* A,
+                       int* dglob, int* didx, double* dscale, hipStream_t st);
+hipError_t launch_owners(const int* sub_ptr, const int* sub_idx, int nsub, int64_t nloc,
+                         int ndof, int* optr, int* ocount, int2* olist, hipStream_t st);
+hipError_t launch_adjacency(const int* optr, const int2* olist, int ndof, int nsub,
+                            uint8_t* adj, hipStream_t st);
+hipError_t launch_pairs(const uint8_t* adj, int nsub, int* cnt, int* off, int2* pairs,
+                        int* npairs_dev, hipStream_t st, bool count_only);
+
+// ------------------------------------------------------------- dense.hip
+hipError_t launch_densify_dirichlet(bool fp32, void* tiles, const int64_t* toff,
+                                    const int* nt, const int* voff, const int* jobs,
+                                    int njobs, const int* sub_ptr, const int* sub_idx,
+                                    const int* dmap, const int* dglob, const double* dscale,
+                                    const geneo_csr_t* A, hipStream_t st);
+hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int* nt,
+                                  int nsub, const int* sub_ptr, const double* pou,
+                                  const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
+                                  double sigma, hipStream_t st);
+
+// -------------------------------------------------------------- chol.hip
+hipError_t launch_chol_batched(bool fp32, void* tiles, const int64_t* toff, const int* nt,
+                               void* dinv, const int64_t* doff, int* status, const int* jobs,
+                               int njobs, double pivtol, hipStream_t st);
+hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
+                        const int64_t* toff, const int64_t* doff, const int* nt,
+                        const int2* jobs, int njobs, hipStream_t st);
+hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
+                           hipStream_t st);
+
+// ------------------------------------------------------------- solve.hip
+// `done` (device flag, may be NULL): skip the work once PCG has converged.
+hipError_t trmv_lower(bool fp32, const void* X, const int64_t* toff, const int* nt,
+                      const int* voff, const int* jobs, int njobs, int maxnt, const double* xin,
+                      double* tout, const int* done, hipStream_t st);
+hipError_t trmv_upperT(bool fp32, const void* X, const int64_t* toff, const int* nt,
+                       const int* voff, const int* jobs, int njobs, int maxnt, const double* tin,
+                       double* yout, const int* done, hipStream_t st);
+hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
+                           const int64_t* doff, const int* nt, const int* voff, int nsub,
+                           int b, const double* R, double* X, const int* active,
+                           hipStream_t st);
+hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
+                           const int64_t* doff, const int* nt, const int* voff, int nsub,
+                           int b, const double* R, double* X, const int* active,
+                           hipStream_t st);
+hipError_t launch_bapply(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
+                         const int* voff, const int* nt, int nsub, int b, const double* X,
+                         double* Y, const int* active, hipStream_t st);
+
+// ------------------------------------------------------------- eigen.hip
+hipError_t launch_eig_init(double* U, const int* sub_ptr, const int* voff, const int* nt,
+                           int nsub, int b, uint64_t seed, hipStream_t st);
+hipError_t launch_orth(double* U, const int* voff, const int* nt, const int* sub_ptr, int nsub,
+                       int b, uint64_t seed, int salt, const int* active, hipStream_t st);
+hipError_t launch_rayleigh_ritz(double* U, const double* W, double* Y, double* theta,
+                                double* resid, int* active, const int* voff, const int* nt,
+                                const int* sub_ptr, int nsub, int b, int nev, double tau,
+                                int nev_max, double sigma, double tol, hipStream_t st);
+hipError_t launch_select(const double* theta, int nsub, int b, int nev, double tau,
+                         int nev_max, double sigma, int* m, double* lam, hipStream_t st);
+hipError_t launch_basis(const double* P, const int* voff, int b, const int* sub_ptr,
+                        const double* pou, const int* dmap, const int* m, const int* zoff,
+                        const int* nd, int nsub, double* Z, hipStream_t st);
+
+// ------------------------------------------------------------ coarse.hip
+hipError_t launch_galerkin_w(const geneo_csr_batch_t* An, const int* sub_ptr, const int* dmap,
+                             const double* Z, const int* zoff, const int* m,
+                             const int* woff, int nsub, double* W, hipStream_t st);
+hipError_t launch_coarse_blocks(const int2* pairs, int npairs, const int* sub_ptr,
+                                const int* sub_idx, const int* didx, const int* dvoff,
+                                const int* nd, const double* Z, const int* zoff,
+                                const double* W, const int* woff, const int* m,
+                                const int* coff, double* AHt, hipStream_t st);
+hipError_t launch_coarse_init(double* AHt, int ntc, int nc, hipStream_t st);
+hipError_t launch_coarse_to_dense(const double* AHt, int ntc, int nc, double* out,
+                                  hipStream_t st);
+
+// --------------------------------------------------------------- pcg.hip
+struct PcgScalars;
+hipError_t launch_spmv(const geneo_csr_t* A, const double* x, double* y, int lpr,
+                       hipStream_t st);
+hipError_t launch_gather_local(const double* r, const int* dglob, const double* dscale,
+                               int64_t nvec, double* xl, hipStream_t st);
+hipError_t launch_restrict_coarse(const double* r, const double* Z, const int* zoff,
+                                  const int* m, const int* nd, const int* didx,
+                                  const int* sub_ptr, const int* sub_idx, const int* coff,
+                                  int nsub, double* rH, hipStream_t st);
+hipError_t launch_combine(const int* optr, const int2* olist, const int* dmap,
+                          const int* voff, const double* dscale, const double* yl,
+                          const double* Z, const int* zoff, const int* m, const int* coff,
+                          const double* yH, int ndof, int use_coarse, double* z,
+                          const int* done, hipStream_t st);
+
+}  // namespace geneo

@@ -1,0 +1,38 @@
+// PCG device state and solve-phase launchers.
+#pragma once
+#include "internal.h"
+
+namespace geneo {
+
+#define PCG_NB 512  // fixed number of partial sums per reduction
+
+struct PcgScalars {
+  double rz, pq, rr, alpha, beta, tol2;
+  int iters, maxit, converged, pad;
+};
+
+hipError_t spmv(const geneo_csr_t* A, const double* x, double* y, int lpr, const int* done,
+                hipStream_t st);
+int spmv_lanes(const geneo_csr_t* A);
+hipError_t gather_local(const double* r, const int* dglob, const double* dscale, int64_t nvec,
+                        double* xl, const int* done, hipStream_t st);
+hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, const int* m,
+                           const int* nd, const int* dglob, const int* dvoff, const int* coff,
+                           int nsub, double* rH, const int* done, hipStream_t st);
+hipError_t combine(const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
+                   const int* dvoff, const double* dscale, const double* yl, const double* Z,
+                   const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
+                   int use_coarse, double* z, const int* done, hipStream_t st);
+hipError_t dot_partial(const double* x, const double* y, int n, double* partial, const int* done,
+                       hipStream_t st);
+hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
+                        double* alphas, double* betas, hipStream_t st);
+hipError_t update_xr(double* x, double* r, const double* p, const double* q, int n,
+                     const PcgScalars* sc, double* partial, const int* done, hipStream_t st);
+hipError_t update_p(double* p, const double* z, int n, const PcgScalars* sc, const int* done,
+                    hipStream_t st);
+hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st);
+hipError_t copy_vec(const double* a, double* b, int n, hipStream_t st);
+hipError_t fill_i32(int* p, int v, int n, hipStream_t st);
+
+}  // namespace geneo

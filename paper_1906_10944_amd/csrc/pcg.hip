@@ -1,0 +1,310 @@
+// Solve-phase kernels: CSR SpMV, the pieces of the preconditioner apply that
+// move data between the global vector and the per-subdomain blocks, and
+// the PCG recurrences with their scalars kept on the device.
+//
+// Every reduction is two-stage with a fixed partition (per-block partial
+// sums, then one block adds them in a fixed order), so results do not
+// depend on scheduling.  Every kernel that runs inside the iteration reads
+// the `done` flag first and returns once the iteration has stopped, which
+// lets a captured graph of several iterations run past convergence.
+#include "internal.h"
+#include "pcg.h"
+
+namespace geneo {
+
+// ---------------------------------------------------------------- SpMV ---
+template <int LPR>
+__global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
+                                              const int* __restrict__ col,
+                                              const double* __restrict__ val,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ y,
+                                              const int* __restrict__ done) {
+  if (done && *done) return;
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = gl / LPR, sub = gl % LPR;
+  double s = 0.0;
+  if (row < n) {
+    const int p1 = rp[row + 1];
+    for (int p = rp[row] + sub; p < p1; p += LPR) s += val[p] * x[col[p]];
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+  if (row < n && sub == 0) y[row] = s;
+}
+
+hipError_t spmv(const geneo_csr_t* A, const double* x, double* y, int lpr, const int* done,
+                hipStream_t st) {
+  const int n = A->n;
+  const int64_t thr = (int64_t)n * lpr;
+  const dim3 grid((unsigned)((thr + 255) / 256)), blk(256);
+  switch (lpr) {
+    case 4: hipLaunchKernelGGL(k_spmv<4>, grid, blk, 0, st, n, A->rowptr, A->col, A->val, x, y, done); break;
+    case 8: hipLaunchKernelGGL(k_spmv<8>, grid, blk, 0, st, n, A->rowptr, A->col, A->val, x, y, done); break;
+    case 16: hipLaunchKernelGGL(k_spmv<16>, grid, blk, 0, st, n, A->rowptr, A->col, A->val, x, y, done); break;
+    default: hipLaunchKernelGGL(k_spmv<32>, grid, blk, 0, st, n, A->rowptr, A->col, A->val, x, y, done); break;
+  }
+  return hipGetLastError();
+}
+
+int spmv_lanes(const geneo_csr_t* A) {
+  double avg = A->n > 0 ? (double)A->nnz / A->n : 1.0;
+  if (avg <= 10) return 4;
+  if (avg <= 30) return 8;
+  if (avg <= 60) return 16;
+  return 32;
+}
+
+// ------------------------------------------------------- apply pieces ---
+__global__ void k_gather_local(const double* __restrict__ r, const int* __restrict__ dglob,
+                               const double* __restrict__ dscale, int64_t nvec,
+                               double* __restrict__ xl, const int* __restrict__ done) {
+  if (done && *done) return;
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nvec) return;
+  int g = dglob[e];
+  xl[e] = g >= 0 ? dscale[e] * r[g] : 0.0;
+}
+
+hipError_t gather_local(const double* r, const int* dglob, const double* dscale, int64_t nvec,
+                        double* xl, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_local, dim3((unsigned)((nvec + 255) / 256)), dim3(256), 0, st, r,
+                     dglob, dscale, nvec, xl, done);
+  return hipGetLastError();
+}
+
+// rH[coff_j + c] = sum_d Z_j[d][c] r[g(d)]
+__global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ r,
+                                                  const double* __restrict__ Z,
+                                                  const int* __restrict__ zoff,
+                                                  const int* __restrict__ m,
+                                                  const int* __restrict__ nd,
+                                                  const int* __restrict__ dglob,
+                                                  const int* __restrict__ dvoff,
+                                                  const int* __restrict__ coff,
+                                                  double* __restrict__ rH,
+                                                  const int* __restrict__ done) {
+  if (done && *done) return;
+  const int j = blockIdx.x;
+  const int mj = m[j];
+  if (mj == 0) return;
+  const int n = nd[j];
+  const double* Zj = Z + zoff[j];
+  const int* gj = dglob + dvoff[j];
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // wave w handles columns c = w, w+4, ...; lanes stride over rows
+  for (int c0 = 0; c0 < mj; c0 += 4) {
+    int c = c0 + w;
+    double s = 0.0;
+    if (c < mj)
+      for (int d = lane; d < n; d += 64) s += Zj[(int64_t)d * mj + c] * r[gj[d]];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && c < mj) rH[coff[j] + c] = s;
+  }
+  (void)red;
+}
+
+hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, const int* m,
+                           const int* nd, const int* dglob, const int* dvoff, const int* coff,
+                           int nsub, double* rH, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_restrict, dim3(nsub), dim3(256), 0, st, r, Z, zoff, m, nd, dglob, dvoff,
+                     coff, rH, done);
+  return hipGetLastError();
+}
+
+// z[g] = sum over the subdomains j owning g (in ascending j) of
+//        s_d y_j[d] + Z_j[d][:] . yH[coff_j :]          (d = dmap_j(g) >= 0)
+__global__ void k_combine(const int* __restrict__ optr, const int2* __restrict__ olist,
+                          const int* __restrict__ sub_ptr, const int* __restrict__ dmap,
+                          const int* __restrict__ dvoff, const double* __restrict__ dscale,
+                          const double* __restrict__ yl, const double* __restrict__ Z,
+                          const int* __restrict__ zoff, const int* __restrict__ m,
+                          const int* __restrict__ coff, const double* __restrict__ yH, int ndof,
+                          int use_coarse, double* __restrict__ z, const int* __restrict__ done) {
+  if (done && *done) return;
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ndof) return;
+  double s = 0.0;
+  for (int p = optr[g]; p < optr[g + 1]; ++p) {
+    int2 o = olist[p];
+    int j = o.x;
+    int d = dmap[sub_ptr[j] + o.y];
+    if (d < 0) continue;
+    int e = dvoff[j] + d;
+    s += dscale[e] * yl[e];
+    if (use_coarse) {
+      int mj = m[j];
+      const double* zr = Z + zoff[j] + (int64_t)d * mj;
+      const double* yh = yH + coff[j];
+      for (int c = 0; c < mj; ++c) s += zr[c] * yh[c];
+    }
+  }
+  z[g] = s;
+}
+
+hipError_t combine(const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
+                   const int* dvoff, const double* dscale, const double* yl, const double* Z,
+                   const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
+                   int use_coarse, double* z, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3((ndof + 255) / 256), dim3(256), 0, st, optr, olist, sub_ptr,
+                     dmap, dvoff, dscale, yl, Z, zoff, m, coff, yH, ndof, use_coarse, z, done);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------- PCG kernels ---
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+  __syncthreads();
+  return t;
+}
+
+// partial[b] = sum over the fixed row range of block b of x.y
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x,
+                                                     const double* __restrict__ y, int n,
+                                                     double* __restrict__ partial,
+                                                     const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha q; partial sums of r.r
+__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ q, int n,
+                                                   const PcgScalars* __restrict__ sc,
+                                                   double* __restrict__ partial,
+                                                   const int* __restrict__ done) {
+  if (*done) return;
+  __shared__ double sh[4];
+  const double alpha = sc->alpha;
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void k_update_p(double* __restrict__ p, const double* __restrict__ z,
+                                                  int n, const PcgScalars* __restrict__ sc,
+                                                  const int* __restrict__ done) {
+  if (*done) return;
+  const double beta = sc->beta;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__device__ double sum_partials(const double* partial, int nb, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
+  return block_sum(s, sh);
+}
+
+// stage: 0 = alpha (pq), 1 = convergence check (rr), 2 = beta (rz), 3 = init
+__global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ partial, int nb,
+                                                int stage, PcgScalars* __restrict__ sc,
+                                                int* __restrict__ done,
+                                                double* __restrict__ alphas,
+                                                double* __restrict__ betas) {
+  __shared__ double sh[4];
+  if (stage != 3 && *done) return;
+  double s = sum_partials(partial, nb, sh);
+  if (threadIdx.x != 0) return;
+  if (stage == 0) {
+    sc->pq = s;
+    sc->alpha = sc->rz / s;
+    alphas[sc->iters] = sc->alpha;
+  } else if (stage == 1) {
+    sc->rr = s;
+    sc->iters += 1;
+    if (s <= sc->tol2) {
+      sc->converged = 1;
+      *done = 1;
+    } else if (sc->iters >= sc->maxit || !(s == s)) {
+      *done = 1;
+    }
+  } else if (stage == 2) {
+    double rz_new = s;
+    sc->beta = rz_new / sc->rz;
+    betas[sc->iters - 1] = sc->beta;
+    sc->rz = rz_new;
+  } else {
+    sc->rz = s;
+  }
+}
+
+hipError_t dot_partial(const double* x, const double* y, int n, double* partial, const int* done,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(PCG_NB), dim3(256), 0, st, x, y, n, partial, done);
+  return hipGetLastError();
+}
+
+hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
+                        double* alphas, double* betas, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, st, partial, PCG_NB, stage, sc, done, alphas,
+                     betas);
+  return hipGetLastError();
+}
+
+hipError_t update_xr(double* x, double* r, const double* p, const double* q, int n,
+                     const PcgScalars* sc, double* partial, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr, dim3(PCG_NB), dim3(256), 0, st, x, r, p, q, n, sc, partial, done);
+  return hipGetLastError();
+}
+
+hipError_t update_p(double* p, const double* z, int n, const PcgScalars* sc, const int* done,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_update_p, dim3(PCG_NB), dim3(256), 0, st, p, z, n, sc, done);
+  return hipGetLastError();
+}
+
+// r = b - q (q = A x0), copies used to start the iteration
+__global__ void k_residual0(const double* __restrict__ b, const double* __restrict__ q,
+                            double* __restrict__ r, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = b[i] - q[i];
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual0, dim3((n + 255) / 256), dim3(256), 0, st, b, q, r, n);
+  return hipGetLastError();
+}
+
+hipError_t copy_vec(const double* a, double* b, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+// Fill kernel used instead of memset inside code a caller may capture.
+__global__ void k_fill_i32(int* __restrict__ p, int v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t fill_i32(int* p, int v, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace geneo

@@ -1,0 +1,33 @@
+// Structured Q1 problem description shared by the assembly kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <math.h>
+#include <string>
+
+#include "geneo.h"
+
+namespace geneo {
+
+#define Q1_MAXP 128  // maximum parts per axis
+
+struct Q1Geom {
+  int dim, ncomp, nsub, ovl, dirichlet;
+  int ne[3], nn[3], parts[3];
+  double h[3], load[3], vol;
+  double wq[8];             // Gauss weight times element volume
+  double grad[8][8][3];     // physical shape-function gradients [point][vertex][axis]
+  double kref[8][8];        // Darcy element matrix for kappa = 1
+  int elo[3][Q1_MAXP], ehi[3][Q1_MAXP];  // overlapping element range per part
+};
+
+int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err);
+void q1_sizes(const Q1Geom& g, geneo_q1_sizes_t* s);
+hipError_t q1_launch_all(const Q1Geom* dgeom, const Q1Geom& g, const geneo_q1_sizes_t& s,
+                         const double* coeff, int* A_rowptr, int* A_col, double* A_val,
+                         double* b, int* sub_ptr, int* sub_idx, uint8_t* flags, double* pou,
+                         int* loc_rowptr, int* loc_col, double* an, double* ao,
+                         int64_t* nzoff, hipStream_t st);
+
+}  // namespace geneo

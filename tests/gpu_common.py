@@ -1,0 +1,82 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and bring results back to the host for comparison with the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+
+
+def need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_assemble(prob):
+    from paper_1906_10944_amd import geneo as G
+    grid = G.grid_from_problem(prob)
+    return G.geneo_assemble_q1(grid, prob.coeff)
+
+
+def csr_to_scipy(rowptr, col, val, n):
+    return sp.csr_matrix((val.cpu().numpy(), col.cpu().numpy(), rowptr.cpu().numpy()),
+                         shape=(n, n))
+
+
+def local_dense(sysm, j, which="an"):
+    sp_ = sysm.sub_ptr.cpu().numpy()
+    rp = sysm.loc_rowptr.cpu().numpy()
+    col = sysm.loc_col.cpu().numpy()
+    val = getattr(sysm, which + "_val").cpu().numpy()
+    r0, r1 = sp_[j], sp_[j + 1]
+    n = r1 - r0
+    M = np.zeros((n, n))
+    for r in range(n):
+        for p in range(rp[r0 + r], rp[r0 + r + 1]):
+            M[r, col[p]] += val[p]
+    return M
+
+
+def gpu_setup(sysm, prob, **optkw):
+    from paper_1906_10944_amd import geneo as G
+    opts = G.opts_from_problem(prob, **optkw)
+    return G.geneo_setup(sysm.csr(), sysm.subdomains(), sysm.neumann(), sysm.overlap(), opts)
+
+
+def gpu_apply(h, sysm, r_np):
+    import torch
+    from paper_1906_10944_amd import geneo as G
+    r = torch.tensor(r_np, dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(r)
+    G.geneo_apply(h, r, z)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
+def gpu_pcg(h, sysm, rtol=1e-10, maxit=2000):
+    import torch
+    from paper_1906_10944_amd import geneo as G
+    x = torch.zeros_like(sysm.b)
+    info = G.pcg_solve(sysm.csr(), h, sysm.b, x, rtol=rtol, maxit=maxit)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info
+
+
+SMALL_PROBLEMS = {
+    "config1": lambda: synth.config1_channels(0),
+    "darcy3d_ragged": lambda: synth.darcy_problem(
+        "d3", np.exp(np.random.Generator(np.random.PCG64(4)).normal(size=(7, 9, 10))),
+        (2, 2, 3), 1, nev=6),
+    "laminate_small": lambda: synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1), nev=8),
+    "layered_neumann_sides": lambda: synth.layered_2d(n=40, parts=4, ovl=2, layers=8,
+                                                      contrast=1e6, nev=4),
+}

@@ -1,0 +1,76 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+host-only entry points (sizes, defaults, messages) work without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import decomp, fem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "geneo.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b((?:geneo|pcg)_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_1906_10944_amd import geneo as G
+    L = G.lib()
+    names = _declared()
+    assert "geneo_setup" in names and "geneo_apply" in names and "pcg_solve" in names
+    for n in names:
+        assert hasattr(L, n), n
+        assert isinstance(getattr(L, n), ctypes._CFuncPtr)
+
+
+def test_version_and_messages():
+    from paper_1906_10944_amd import geneo as G
+    assert "gfx950" in G.geneo_version()
+    assert G.geneo_strerror(0) == "ok"
+    assert "not SPD" in G.geneo_strerror(5)
+
+
+def test_default_opts():
+    from paper_1906_10944_amd import geneo as G
+    o = G.geneo_default_opts()
+    assert o.sigma == -1e-3 and o.nev == 8 and o.coarse == 1 and o.precision == 0
+
+
+@pytest.mark.parametrize("make", [
+    lambda: synth.config1_channels(0),
+    lambda: synth.config1_channels(0, n=30, parts=3, n_channels=3, ovl=1),
+    lambda: synth.darcy_problem("t", np.ones((7, 9, 10)), (2, 2, 3), 1),
+    lambda: synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1)),
+])
+def test_q1_sizes_match_oracle(make):
+    from paper_1906_10944_amd import geneo as G
+    p = make()
+    s = G.geneo_q1_sizes(G.grid_from_problem(p))
+    A = fem.assemble_neumann(p)
+    subs, _ = decomp.build(p)
+    assert s["ndof"] == p.ndof
+    assert s["nnz"] == A.nnz
+    assert s["nsub"] == len(subs)
+    assert s["nloc"] == sum(len(x.dofs) for x in subs)
+    assert s["nmax"] == max(len(x.dofs) for x in subs)
+
+
+def test_q1_sizes_rejects_bad_grids():
+    from paper_1906_10944_amd import geneo as G
+    p = synth.config1_channels(0)
+    g = G.grid_from_problem(p)
+    g.ovl = 0
+    with pytest.raises(G.GeneoError) as e:
+        G.geneo_q1_sizes(g)
+    assert e.value.code == 1
+    g = G.grid_from_problem(p)
+    g.parts[0] = 100
+    with pytest.raises(G.GeneoError):
+        G.geneo_q1_sizes(g)
