@@ -185,7 +185,7 @@ typedef struct {
 } geneo_opts_t;
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
- * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-9, eig_maxit 300,
+ * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-10, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1. */
 void geneo_default_opts(geneo_opts_t* opts);
 

@@ -218,7 +218,10 @@ def geneo_assemble_q1(grid, coeff, device="cuda", stream=None):
     import torch
     sizes = geneo_q1_sizes(grid)
     sysm = Q1System(sizes, device)
-    coeff = torch.as_tensor(np.ascontiguousarray(coeff), dtype=torch.float64).to(device).contiguous()
+    if isinstance(coeff, torch.Tensor):
+        coeff = coeff.to(device=device, dtype=torch.float64).contiguous()
+    else:
+        coeff = torch.as_tensor(np.ascontiguousarray(coeff), dtype=torch.float64).to(device)
     sysm.coeff = coeff
     args = [sysm.A_rowptr, sysm.A_col, sysm.A_val, sysm.b, sysm.sub_ptr, sysm.sub_idx,
             sysm.sub_flags, sysm.pou, sysm.loc_rowptr, sysm.loc_col, sysm.an_val, sysm.ao_val]
