@@ -288,8 +288,7 @@ int geneo_spmv(const geneo_csr_t* A, const double* x, double* y, void* stream);
  * Names: "assemble", "densify_dirichlet", "chol_dirichlet_f32",
  * "chol_dirichlet_f64", "trtri_dirichlet", "densify_shifted",
  * "chol_shifted_f64", "trsm_bwd", "trsm_fwd", "bapply", "rayleigh_ritz",
- * "orth", "basis", "galerkin", "coarse_chol", "trmv_lower_f32",
- * "trmv_upperT_f32", "trmv_lower_f64", "trmv_upperT_f64", "spmv".
+ * "orth", "coarse_chol", "trmv_lower", "trmv_upperT".
  */
 void geneo_prof_enable(int on);
 int geneo_prof_query(const char* kernel, double* total_ms, int* launches, double* bytes,

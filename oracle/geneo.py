@@ -20,7 +20,8 @@ Steps, in the paper's order and notation:
 4. coarse basis vectors X_j p, normalised in the l2 norm (Sec. 4.4);
 5. the coarse matrix A_H = R_H A R_H^T = Z^T A Z (Def. 2, Sec. 4.5) and its
    Cholesky factor;
-6. the two-level additive Schwarz operator
+6. the two-level additive Schwarz operator (acting as the identity on the
+   eliminated Dirichlet dofs, which lie in no D_j and have unit rows)
    M^{-1} = R_H^T A_H^{-1} R_H + sum_j R_j^T A_j^{-1} R_j (Def. 2).
 
 Readings where the paper is silent: sigma = -1e-3 (any sigma < 0 gives the
@@ -150,13 +151,17 @@ class GenEO:
     def nc(self):
         return 0 if self.Z is None else self.Z.shape[1]
 
+    def _uncovered(self):
+        """Dofs in no D_j: the eliminated Dirichlet dofs, whose rows of A are
+        unit rows; the operator acts as the identity on them."""
+        cov = np.zeros(len(self.A.indptr) - 1, dtype=bool)
+        for s in self.subs:
+            cov[s.dofs[s.dmask]] = True
+        return ~cov
+
     def apply(self, r):
-        """z = M_AS,2^{-1} r (Def. 2)."""
-        z = np.zeros_like(r)
-        for s, L in zip(self.subs, self.chol):
-            idx = s.dofs[s.dmask]
-            if len(idx):
-                z[idx] += sla.cho_solve((L, True), r[idx])
+        """z = M_AS,2^{-1} r (Def. 2), identity on the eliminated dofs."""
+        z = self.apply_one_level(r)
         if self.nc:
             rH = self.Z.T @ r
             yH = sla.cho_solve((self.LH, True), rH)
@@ -169,6 +174,8 @@ class GenEO:
             idx = s.dofs[s.dmask]
             if len(idx):
                 z[idx] += sla.cho_solve((L, True), r[idx])
+        unc = self._uncovered()
+        z[unc] = r[unc]
         return z
 
 

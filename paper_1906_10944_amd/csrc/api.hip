@@ -1,6 +1,7 @@
 // C ABI of libgeneo: argument checks, buffer ownership and the order of the
 // setup phases, the preconditioner apply and the graph-captured PCG loop.
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -122,7 +123,8 @@ struct geneo_handle_s {
   DBuf<int2> olist;
   // coarse space
   int nc = 0, ntc = 0, b = 0;
-  DBuf<int> m, zoff, coff, hjob, hnt, hvoff;
+  DBuf<int> m, zoff, coff, hnt, hvoff;
+  DBuf<int2> hjob, ljobs;  // trmv job lists: (matrix, 1 if FP64)
   DBuf<int64_t> htoff;
   DBuf<double> Z, XH, rH, tH, yH, AHdense;
   std::vector<int> m_host, nd_host, nN_host, sub_ptr_host;
@@ -136,6 +138,7 @@ struct geneo_handle_s {
   DBuf<int> done;
   int lpr = 8;
   double bytes_trmv32 = 0.0, bytes_trmv64 = 0.0;  // algorithmic bytes per launch
+  std::vector<int> f64list;                         // subdomains with FP64 local factors
   geneo_setup_info_t info{};
   ~geneo_handle_s() {
     if (hs) (void)hipStreamDestroy(hs);
@@ -153,42 +156,31 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
                          hipStream_t st) {
   hipError_t e;
   if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
+  const double lb = h->bytes_trmv32 + h->bytes_trmv64;
   {
-    ProfScope ps(h->njobs32 ? "trmv_lower_f32" : nullptr, st, h->bytes_trmv32, 2.0 * h->bytes_trmv32 / 4.0);
-    if ((e = trmv_lower(true, h->X32.p, h->toffD.p, h->ntD.p, h->voffD.p, h->jobs32.p,
-                        h->njobs32, h->LD.maxnt, h->xl.p, h->tl.p, done, st)))
+    ProfScope ps("trmv_lower", st, lb, 0.0);
+    if ((e = trmv_lower(h->X32.p, h->X64.p, h->toffD.p, h->toff64.p, h->ntD.p, h->voffD.p,
+                        h->ljobs.p, h->nsub, h->LD.maxnt, h->xl.p, h->tl.p, done, st)))
       return e;
   }
   {
-    ProfScope ps(h->njobs64 ? "trmv_lower_f64" : nullptr, st, h->bytes_trmv64, 2.0 * h->bytes_trmv64 / 8.0);
-    if ((e = trmv_lower(false, h->X64.p, h->toff64.p, h->ntD.p, h->voffD.p, h->jobs64.p,
-                        h->njobs64, h->LD.maxnt, h->xl.p, h->tl.p, done, st)))
-      return e;
-  }
-  {
-    ProfScope ps(h->njobs32 ? "trmv_upperT_f32" : nullptr, st, h->bytes_trmv32, 2.0 * h->bytes_trmv32 / 4.0);
-    if ((e = trmv_upperT(true, h->X32.p, h->toffD.p, h->ntD.p, h->voffD.p, h->jobs32.p,
-                         h->njobs32, h->LD.maxnt, h->tl.p, h->yl.p, done, st)))
-      return e;
-  }
-  {
-    ProfScope ps(h->njobs64 ? "trmv_upperT_f64" : nullptr, st, h->bytes_trmv64, 2.0 * h->bytes_trmv64 / 8.0);
-    if ((e = trmv_upperT(false, h->X64.p, h->toff64.p, h->ntD.p, h->voffD.p, h->jobs64.p,
-                         h->njobs64, h->LD.maxnt, h->tl.p, h->yl.p, done, st)))
+    ProfScope ps("trmv_upperT", st, lb, 0.0);
+    if ((e = trmv_upperT(h->X32.p, h->X64.p, h->toffD.p, h->toff64.p, h->ntD.p, h->voffD.p,
+                         h->ljobs.p, h->nsub, h->LD.maxnt, h->tl.p, h->yl.p, done, st)))
       return e;
   }
   if (h->nc > 0) {
     if ((e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
                              h->coff.p, h->nsub, h->rH.p, done, st)))
       return e;
-    if ((e = trmv_lower(false, h->XH.p, h->htoff.p, h->hnt.p, h->hvoff.p, h->hjob.p, 1, h->ntc,
-                        h->rH.p, h->tH.p, done, st)))
+    if ((e = trmv_lower(nullptr, h->XH.p, h->htoff.p, h->htoff.p, h->hnt.p, h->hvoff.p,
+                        h->hjob.p, 1, h->ntc, h->rH.p, h->tH.p, done, st)))
       return e;
-    if ((e = trmv_upperT(false, h->XH.p, h->htoff.p, h->hnt.p, h->hvoff.p, h->hjob.p, 1, h->ntc,
-                         h->tH.p, h->yH.p, done, st)))
+    if ((e = trmv_upperT(nullptr, h->XH.p, h->htoff.p, h->htoff.p, h->hnt.p, h->hvoff.p,
+                         h->hjob.p, 1, h->ntc, h->tH.p, h->yH.p, done, st)))
       return e;
   }
-  return combine(h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
+  return combine(r, h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
                  h->yl.p, h->Z.p, h->zoff.p, h->m.p, h->coff.p, h->yH.p, h->n, h->nc > 0, z, done,
                  st);
 }
@@ -210,25 +202,396 @@ __global__ void k_max_resid(const double* resid, const int* m, int nsub, int b, 
   }
 }
 
+// Scratch buffers of one setup call: kept alive until the call returns so
+// that no hipFree (which synchronises the device) splits the two streams.
+struct SetupScratch {
+  DBuf<int> status, status2, jobs, jobsN, ntN, voffN, active, pcnt, poff, npairs, woffd, cst;
+  DBuf<int64_t> toffN, doffN, hdoff;
+  DBuf<float> L32, D32;
+  DBuf<double> L64, D64, G, DG, U, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
+  DBuf<int> ebad;
+  DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
+  DBuf<uint8_t> adj;
+  DBuf<int> ocount;
+};
+
+struct PhaseTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  void start(hipStream_t st) {
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, st));
+  }
+  void stop(hipStream_t st) { HIPCHK(hipEventRecord(b, st)); }
+  double ms() {
+    if (!a || !b) return 0.0;
+    float t = 0.f;
+    HIPCHK(hipEventSynchronize(b));
+    HIPCHK(hipEventElapsedTime(&t, a, b));
+    return t;
+  }
+  ~PhaseTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Local Dirichlet factors A_j = R_j A R_j^T and their inverse factors, on
+// stream st.  Returns after the work is enqueued and the pivot tests are
+// read back.
+void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
+                 const geneo_subdomains_t* S, hipStream_t st,
+                 const std::function<void()>& after_fp32) {
+  const geneo_opts_t& o = h->opts;
+  const int nsub = h->nsub;
+  std::vector<int> all(nsub);
+  for (int j = 0; j < nsub; ++j) all[j] = j;
+  std::vector<int> f64list;
+  const bool mixed = o.precision == GENEO_PREC_MIXED;
+  X.status.alloc(nsub);
+  if (mixed) {
+    X.jobs.upload(all, st);
+    X.L32.alloc(h->LD.ntiles * TSQ);
+    X.D32.alloc(h->LD.ndiag * TSQ);
+    double pk = 0.0, fl = 0.0;
+    for (int j = 0; j < nsub; ++j) {
+      pk += packed(h->nd_host[j]);
+      fl += std::pow((double)h->nd_host[j], 3) / 3.0;
+    }
+    {
+      ProfScope ps("densify_dirichlet", st, 4.0 * h->LD.ntiles * TSQ, 0.0);
+      HIPCHK(launch_densify_dirichlet(true, X.L32.p, h->toffD.p, h->ntD.p, h->voffD.p, X.jobs.p,
+                                      nsub, S->sub_ptr, S->sub_idx, h->dmap.p, h->dglob.p,
+                                      h->dscale.p, A, st));
+    }
+    {
+      ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * pk, fl);
+      HIPCHK(launch_chol_batched(true, X.L32.p, h->toffD.p, h->ntD.p, X.D32.p, h->doffD.p,
+                                 X.status.p, X.jobs.p, nsub, o.pivot_tol, st));
+    }
+    auto stat = download(X.status.p, nsub, st);
+    after_fp32();
+    std::vector<int> ok32;
+    for (int j = 0; j < nsub; ++j) (stat[j] ? f64list : ok32).push_back(j);
+    h->njobs32 = (int)ok32.size();
+    h->jobs32.upload(ok32, st);
+    if (!ok32.empty()) {
+      std::vector<int2> tj;
+      for (int j : ok32)
+        for (int c = 0; c < h->LD.nt[j]; ++c) tj.push_back(make_int2(j, c));
+      X.tjobs32.upload(tj, st);
+      h->X32.alloc(h->LD.ntiles * TSQ);
+      double pk32 = 0.0, fl32 = 0.0;
+      for (int j : ok32) {
+        pk32 += packed(h->nd_host[j]);
+        fl32 += std::pow((double)h->nd_host[j], 3) / 3.0;
+      }
+      ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, fl32);
+      HIPCHK(launch_trtri(true, X.L32.p, X.D32.p, h->X32.p, h->toffD.p, h->doffD.p, h->ntD.p,
+                          X.tjobs32.p, (int)tj.size(), st));
+    }
+  } else {
+    f64list = all;
+    after_fp32();
+  }
+  h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
+  h->njobs64 = (int)f64list.size();
+  h->jobs64.upload(f64list, st);
+  std::vector<int64_t> toff64(nsub, 0), doff64(nsub, 0);
+  int64_t tt = 0, dd = 0;
+  for (int j : f64list) {
+    toff64[j] = tt;
+    doff64[j] = dd;
+    tt += tri_tiles(h->LD.nt[j]);
+    dd += h->LD.nt[j];
+  }
+  h->toff64.upload(toff64, st);
+  h->doff64.upload(doff64, st);
+  {
+    std::vector<int2> lj(nsub);
+    std::vector<char> f(nsub, 0);
+    for (int j : f64list) f[j] = 1;
+    for (int j = 0; j < nsub; ++j) lj[j] = make_int2(j, f[j]);
+    h->ljobs.upload(lj, st);
+  }
+  if (!f64list.empty()) {
+    X.L64.alloc(tt * TSQ);
+    X.D64.alloc(dd * TSQ);
+    double pk64 = 0.0, fl64 = 0.0;
+    for (int j : f64list) {
+      pk64 += packed(h->nd_host[j]);
+      fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
+    }
+    {
+      ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
+      HIPCHK(launch_densify_dirichlet(false, X.L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
+                                      h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
+                                      h->dmap.p, h->dglob.p, h->dscale.p, A, st));
+    }
+    {
+      ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
+      HIPCHK(launch_chol_batched(false, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p, h->doff64.p,
+                                 X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
+    }
+    std::vector<int2> tj;
+    for (int j : f64list)
+      for (int c = 0; c < h->LD.nt[j]; ++c) tj.push_back(make_int2(j, c));
+    X.tjobs64.upload(tj, st);
+    h->X64.alloc(tt * TSQ);
+    ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
+    HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, h->X64.p, h->toff64.p, h->doff64.p, h->ntD.p,
+                        X.tjobs64.p, (int)tj.size(), st));
+  }
+  double b32 = 0.0, b64 = 0.0;
+  std::vector<char> is64(nsub, 0);
+  for (int j : f64list) is64[j] = 1;
+  for (int j = 0; j < nsub; ++j) {
+    double nn = h->nd_host[j];
+    if (is64[j]) b64 += 8.0 * packed(nn) + 16.0 * nn;
+    else b32 += 4.0 * packed(nn) + 16.0 * nn;
+  }
+  h->bytes_trmv32 = b32;
+  h->bytes_trmv64 = b64;
+  h->info.bytes_local_factors = (int64_t)(h->X32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->X64.n * 8;
+  h->f64list = f64list;
+}
+
+// Shifted factors C_j = G_j G_j^T, enqueued on stream sb (no host wait).
+void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
+                   const geneo_subdomains_t* S, const geneo_csr_batch_t* An,
+                   const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm) {
+  const geneo_opts_t& o = h->opts;
+  const int nsub = h->nsub;
+  std::vector<int> all(nsub);
+  for (int j = 0; j < nsub; ++j) all[j] = j;
+  LN.build(h->nN_host);
+  X.ntN.upload(LN.nt, sb);
+  X.voffN.upload(LN.voff, sb);
+  X.toffN.upload(LN.toff, sb);
+  X.doffN.upload(LN.doff, sb);
+  X.jobsN.upload(all, sb);
+  X.status2.alloc(nsub);
+  X.G.alloc(LN.ntiles * TSQ);
+  X.DG.alloc(LN.ndiag * TSQ);
+  // eigen block size
+  const int want = o.tau > 0 ? o.nev_max : o.nev;
+  int minnt = LN.nt[0];
+  for (int j = 1; j < nsub; ++j) minnt = std::min(minnt, LN.nt[j]);
+  int b = o.eig_block;
+  if (b <= 0) {
+    b = want + std::max(8, want / 2);
+    b = ((b + 15) / 16) * 16;
+  }
+  b = std::min(b, 64);
+  b = std::min(b, minnt * TS);
+  if (b < 16 || b % 16 || want >= b)
+    fail(GENEO_ERR_ARG, "eigen block size " + std::to_string(b) +
+                            " cannot hold the requested eigenvectors");
+  h->b = b;
+  h->info.eig_block = b;
+  X.U.alloc(LN.nvec * b);
+  X.W.alloc(LN.nvec * b);
+  X.T.alloc(LN.nvec * b);
+  X.Y.alloc(LN.nvec * b);
+  X.theta.alloc((size_t)nsub * b);
+  X.resid.alloc((size_t)nsub * b);
+  X.active.alloc(nsub);
+  X.lam.alloc((size_t)nsub * b);
+  X.mr.alloc(1);
+  h->m.alloc(nsub);
+
+  tm[0].start(sb);
+  double pkN = 0.0, flN = 0.0;
+  for (int j = 0; j < nsub; ++j) {
+    pkN += packed(h->nN_host[j]);
+    flN += std::pow((double)h->nN_host[j], 3) / 3.0;
+  }
+  {
+    ProfScope ps("densify_shifted", sb, 8.0 * LN.ntiles * TSQ, 0.0);
+    HIPCHK(launch_densify_shifted(X.G.p, X.toffN.p, X.ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
+                                  o.sigma, sb));
+  }
+  {
+    ProfScope ps("chol_shifted_f64", sb, 2.0 * 8.0 * pkN, flN);
+    HIPCHK(launch_chol_batched(false, X.G.p, X.toffN.p, X.ntN.p, X.DG.p, X.doffN.p, X.status2.p,
+                               X.jobsN.p, nsub, 0.0, sb));
+  }
+  tm[0].stop(sb);
+}
+
+// Eigen sweeps, coarse basis, Galerkin product and coarse factor on sb.
+void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
+                  const geneo_subdomains_t* S, const geneo_csr_batch_t* An,
+                  const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm) {
+  const geneo_opts_t& o = h->opts;
+  const int nsub = h->nsub;
+  const int b = h->b;
+  {
+    auto stat = download(X.status2.p, nsub, sb);
+    for (int j = 0; j < nsub; ++j)
+      if (stat[j]) fail(GENEO_ERR_SHIFT_NOT_SPD, "A_N - sigma B of subdomain " +
+                                                     std::to_string(j) + " is not SPD");
+  }
+  // ---- block subspace iteration on S = G^{-1} B G^{-T}
+  tm[1].start(sb);
+  HIPCHK(fill_i32(X.active.p, 1, nsub, sb));
+  HIPCHK(launch_eig_init(X.U.p, S->sub_ptr, X.voffN.p, X.ntN.p, nsub, b, o.seed, sb));
+  EigWork wk;
+  wk.ngroups = (LN.maxnt * TS / 16 + 7) / 8;  // SLABS_PER_WG = 8
+  X.eG.alloc((size_t)nsub * b * b);
+  X.eM.alloc((size_t)nsub * b * b);
+  X.epart.alloc((size_t)nsub * wk.ngroups * b);
+  X.ebad.alloc((size_t)nsub * b);
+  wk.G = X.eG.p;
+  wk.M = X.eM.p;
+  wk.part = X.epart.p;
+  wk.badcol = X.ebad.p;
+  HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, 0, nullptr, wk, sb));
+  int sweeps = 0, nact = nsub;
+  std::vector<int> act(nsub, 1);
+  for (int it = 1; it <= o.eig_maxit; ++it) {
+    // algorithmic traffic of this sweep: the factor G_j of every active
+    // subdomain is read once per triangular solve, plus its b columns
+    double gb = 0.0, vb = 0.0, tf = 0.0;
+    for (int j = 0; j < nsub; ++j) {
+      if (!act[j]) continue;
+      double nn = h->nN_host[j];
+      gb += 8.0 * packed(nn);
+      vb += 2.0 * 8.0 * nn * b;
+      tf += 2.0 * packed(nn) * b;
+    }
+    {
+      ProfScope ps("trsm_bwd", sb, gb + vb, tf);
+      HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
+                             X.U.p, X.T.p, X.active.p, sb));
+    }
+    {
+      ProfScope ps("bapply", sb, vb, 0.0);
+      HIPCHK(launch_bapply(S->sub_ptr, S->pou, Ao, X.voffN.p, X.ntN.p, nsub, b, X.T.p, X.W.p,
+                           X.active.p, sb));
+    }
+    {
+      ProfScope ps("trsm_fwd", sb, gb + vb, tf);
+      HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
+                             X.W.p, X.T.p, X.active.p, sb));
+    }
+    {
+      ProfScope ps("rayleigh_ritz", sb, 2.0 * vb, 0.0);
+      HIPCHK(launch_rr2(X.U.p, X.T.p, X.Y.p, X.theta.p, X.resid.p, X.active.p, X.voffN.p,
+                        X.ntN.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, o.eig_tol, wk, sb));
+    }
+    sweeps = it;
+    act = download(X.active.p, nsub, sb);
+    nact = 0;
+    for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
+    if (nact == 0) break;
+    {
+      ProfScope ps("orth", sb, 2.0 * vb, 0.0);
+      HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, it, X.active.p, wk, sb));
+    }
+  }
+  h->info.eig_sweeps = sweeps;
+  if (nact > 0)
+    fail(GENEO_ERR_EIGEN_NOCONV, std::to_string(nact) + " subdomains did not converge in " +
+                                     std::to_string(o.eig_maxit) + " sweeps");
+  // eigenvectors p = G^{-T} y
+  HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b, X.Y.p,
+                         X.T.p, nullptr, sb));
+  HIPCHK(launch_select(X.theta.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, h->m.p, X.lam.p, sb));
+  h->m_host = download(h->m.p, nsub, sb);
+  h->lam_host = download(X.lam.p, (size_t)nsub * b, sb);
+  tm[1].stop(sb);
+
+  // ---- coarse basis Z, W = A_N Z, A_H = Z^T A Z
+  tm[2].start(sb);
+  std::vector<int> zoff(nsub), woff(nsub), coff(nsub + 1);
+  int64_t zs = 0, ws = 0;
+  int nc = 0;
+  for (int j = 0; j < nsub; ++j) {
+    zoff[j] = (int)zs;
+    woff[j] = (int)ws;
+    coff[j] = nc;
+    zs += (int64_t)h->nd_host[j] * h->m_host[j];
+    ws += (int64_t)h->nN_host[j] * h->m_host[j];
+    nc += h->m_host[j];
+  }
+  coff[nsub] = nc;
+  h->nc = nc;
+  h->zoff.upload(zoff, sb);
+  h->coff.upload(coff, sb);
+  h->Z.alloc(zs);
+  HIPCHK(launch_basis(X.T.p, X.voffN.p, b, S->sub_ptr, S->pou, h->dmap.p, h->m.p, h->zoff.p,
+                      h->nd.p, nsub, h->Z.p, sb));
+  hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(1), 0, sb, X.resid.p, h->m.p, nsub, b, X.mr.p);
+  h->info.eig_max_resid = download(X.mr.p, 1, sb)[0];
+  if (nc > 0) {
+    X.woffd.upload(woff, sb);
+    X.Wg.alloc(ws);
+    HIPCHK(launch_galerkin_w(An, S->sub_ptr, h->dmap.p, h->Z.p, h->zoff.p, h->m.p, X.woffd.p,
+                             nsub, X.Wg.p, sb));
+    X.adj.alloc((size_t)nsub * nsub);
+    HIPCHK(launch_adjacency(h->optr.p, h->olist.p, h->n, nsub, X.adj.p, sb));
+    X.pcnt.alloc(nsub);
+    X.poff.alloc(nsub + 1);
+    X.npairs.alloc(1);
+    HIPCHK(launch_pairs(X.adj.p, nsub, X.pcnt.p, X.poff.p, nullptr, X.npairs.p, sb, true));
+    int np = download(X.npairs.p, 1, sb)[0];
+    X.pairs.alloc(np);
+    HIPCHK(launch_pairs(X.adj.p, nsub, X.pcnt.p, X.poff.p, X.pairs.p, X.npairs.p, sb, false));
+    h->ntc = (nc + TS - 1) / TS;
+    X.AHt.alloc(tri_tiles(h->ntc) * TSQ);
+    X.DH.alloc((size_t)h->ntc * TSQ);
+    HIPCHK(launch_coarse_init(X.AHt.p, h->ntc, nc, sb));
+    HIPCHK(launch_coarse_blocks(X.pairs.p, np, S->sub_ptr, S->sub_idx, h->didx.p, h->voffD.p,
+                                h->nd.p, h->Z.p, h->zoff.p, X.Wg.p, X.woffd.p, h->m.p, h->coff.p,
+                                X.AHt.p, sb));
+    h->AHdense.alloc((size_t)nc * nc);
+    HIPCHK(launch_coarse_to_dense(X.AHt.p, h->ntc, nc, h->AHdense.p, sb));
+    tm[2].stop(sb);
+    // ---- coarse Cholesky and inverse factor
+    tm[3].start(sb);
+    X.cst.alloc(1);
+    {
+      ProfScope ps("coarse_chol", sb, 8.0 * packed(nc), std::pow((double)nc, 3) / 3.0);
+      HIPCHK(coarse_cholesky(X.AHt.p, X.DH.p, h->ntc, X.cst.p, sb));
+    }
+    if (download(X.cst.p, 1, sb)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
+    h->hjob.upload(std::vector<int2>{make_int2(0, 1)}, sb);
+    h->hnt.upload(std::vector<int>{h->ntc}, sb);
+    h->hvoff.upload(std::vector<int>{0}, sb);
+    h->htoff.upload(std::vector<int64_t>{0}, sb);
+    X.hdoff.upload(std::vector<int64_t>{0}, sb);
+    std::vector<int2> tj;
+    for (int c = 0; c < h->ntc; ++c) tj.push_back(make_int2(0, c));
+    X.tjobsH.upload(tj, sb);
+    h->XH.alloc(tri_tiles(h->ntc) * TSQ);
+    HIPCHK(launch_trtri(false, X.AHt.p, X.DH.p, h->XH.p, h->htoff.p, X.hdoff.p, h->hnt.p,
+                        X.tjobsH.p, h->ntc, sb));
+    h->rH.alloc((size_t)h->ntc * TS);
+    h->tH.alloc((size_t)h->ntc * TS);
+    h->yH.alloc((size_t)h->ntc * TS);
+    HIPCHK(hipMemsetAsync(h->rH.p, 0, h->rH.n * sizeof(double), sb));
+    tm[3].stop(sb);
+  } else {
+    tm[2].stop(sb);
+  }
+}
+
 void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_t* S,
                 const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao, hipStream_t st) {
   const geneo_opts_t& o = h->opts;
   const double t_start = now_ms();
-  double t_mark = t_start;
-  auto phase = [&](int k) {
-    HIPCHK(hipStreamSynchronize(st));
-    double t = now_ms();
-    h->info.t_phase_ms[k] = t - t_mark;
-    t_mark = t;
-  };
   const int nsub = S->nsub;
   h->n = A->n;
   h->nsub = nsub;
   h->nloc = S->nloc;
   h->lpr = spmv_lanes(A);
   HIPCHK(hipStreamCreateWithFlags(&h->hs, hipStreamNonBlocking));
+  SetupScratch X;
+  PhaseTimer tm0, tmL, tmC[4];
 
-  // ---- 0. index lists, D_j maps, scaling, owner lists
+  // ---- 0. index lists, D_j maps, scaling, owner lists (stream st)
+  tm0.start(st);
   h->sub_ptr_host = download(S->sub_ptr, nsub + 1, st);
   const auto& sp = h->sub_ptr_host;
   if (sp[0] != 0 || sp[nsub] != S->nloc) fail(GENEO_ERR_ARG, "sub_ptr does not span nloc");
@@ -255,362 +618,71 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   h->dscale.alloc(h->LD.nvec);
   HIPCHK(launch_dvec(S->sub_ptr, S->sub_idx, h->dmap.p, h->voffD.p, h->ntD.p, nsub, A,
                      h->dglob.p, h->didx.p, h->dscale.p, st));
-  {
-    DBuf<int> ocount;
-    ocount.alloc(h->n);
-    h->optr.alloc(h->n + 1);
-    h->olist.alloc(S->nloc);
-    HIPCHK(launch_owners(S->sub_ptr, S->sub_idx, nsub, S->nloc, h->n, h->optr.p, ocount.p,
-                         h->olist.p, st));
-    HIPCHK(hipStreamSynchronize(st));
-  }
-  phase(0);
-
-  // ---- 1. local Dirichlet factors A_j = R_j A R_j^T and their inverses
-  DBuf<int> status;
-  status.alloc(nsub);
-  std::vector<int> all(nsub);
-  for (int j = 0; j < nsub; ++j) all[j] = j;
-  std::vector<int> f64list;
-  const bool mixed = o.precision == GENEO_PREC_MIXED;
-  if (mixed) {
-    DBuf<int> jobs;
-    jobs.upload(all, st);
-    DBuf<float> L32, D32;
-    L32.alloc(h->LD.ntiles * TSQ);
-    D32.alloc(h->LD.ndiag * TSQ);
-    double pk = 0.0, fl = 0.0;
-    for (int j = 0; j < nsub; ++j) {
-      pk += packed(h->nd_host[j]);
-      fl += std::pow((double)h->nd_host[j], 3) / 3.0;
-    }
-    {
-      ProfScope ps("densify_dirichlet", st, 4.0 * h->LD.ntiles * TSQ, 0.0);
-      HIPCHK(launch_densify_dirichlet(true, L32.p, h->toffD.p, h->ntD.p, h->voffD.p, jobs.p,
-                                      nsub, S->sub_ptr, S->sub_idx, h->dmap.p, h->dglob.p,
-                                      h->dscale.p, A, st));
-    }
-    {
-      ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * pk, fl);
-      HIPCHK(launch_chol_batched(true, L32.p, h->toffD.p, h->ntD.p, D32.p, h->doffD.p, status.p,
-                                 jobs.p, nsub, o.pivot_tol, st));
-    }
-    auto stat = download(status.p, nsub, st);
-    std::vector<int> ok32;
-    for (int j = 0; j < nsub; ++j) (stat[j] ? f64list : ok32).push_back(j);
-    h->njobs32 = (int)ok32.size();
-    h->jobs32.upload(ok32, st);
-    if (!ok32.empty()) {
-      std::vector<int2> tj;
-      for (int j : ok32)
-        for (int c = 0; c < h->LD.nt[j]; ++c) tj.push_back(make_int2(j, c));
-      DBuf<int2> tjobs;
-      tjobs.upload(tj, st);
-      h->X32.alloc(h->LD.ntiles * TSQ);
-      double pk32 = 0.0, fl32 = 0.0;
-      for (int j : ok32) {
-        pk32 += packed(h->nd_host[j]);
-        fl32 += std::pow((double)h->nd_host[j], 3) / 3.0;
-      }
-      ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, fl32);
-      HIPCHK(launch_trtri(true, L32.p, D32.p, h->X32.p, h->toffD.p, h->doffD.p, h->ntD.p, tjobs.p,
-                          (int)tj.size(), st));
-      HIPCHK(hipStreamSynchronize(st));
-    }
-  } else {
-    f64list = all;
-  }
-  h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
-  h->njobs64 = (int)f64list.size();
-  h->jobs64.upload(f64list, st);
-  {
-    std::vector<int64_t> toff64(nsub, 0), doff64(nsub, 0);
-    int64_t tt = 0, dd = 0;
-    for (int j : f64list) {
-      toff64[j] = tt;
-      doff64[j] = dd;
-      tt += tri_tiles(h->LD.nt[j]);
-      dd += h->LD.nt[j];
-    }
-    h->toff64.upload(toff64, st);
-    h->doff64.upload(doff64, st);
-    if (!f64list.empty()) {
-      DBuf<double> L64, D64;
-      L64.alloc(tt * TSQ);
-      D64.alloc(dd * TSQ);
-      double pk64 = 0.0, fl64 = 0.0;
-      for (int j : f64list) {
-        pk64 += packed(h->nd_host[j]);
-        fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
-      }
-      {
-        ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
-        HIPCHK(launch_densify_dirichlet(false, L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                                        h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
-                                        h->dmap.p, h->dglob.p, h->dscale.p, A, st));
-      }
-      {
-        ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
-        HIPCHK(launch_chol_batched(false, L64.p, h->toff64.p, h->ntD.p, D64.p, h->doff64.p,
-                                   status.p, h->jobs64.p, h->njobs64, 0.0, st));
-      }
-      auto stat = download(status.p, nsub, st);
-      for (int j : f64list)
-        if (stat[j]) fail(GENEO_ERR_LOCAL_NOT_SPD, "local Dirichlet matrix of subdomain " +
-                                                       std::to_string(j) + " is not SPD");
-      std::vector<int2> tj;
-      for (int j : f64list)
-        for (int c = 0; c < h->LD.nt[j]; ++c) tj.push_back(make_int2(j, c));
-      DBuf<int2> tjobs;
-      tjobs.upload(tj, st);
-      h->X64.alloc(tt * TSQ);
-      ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
-      HIPCHK(launch_trtri(false, L64.p, D64.p, h->X64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                          tjobs.p, (int)tj.size(), st));
-      HIPCHK(hipStreamSynchronize(st));
-    }
-  }
-  {
-    double b32 = 0.0, b64 = 0.0;
-    for (int j = 0; j < nsub; ++j) {
-      bool is64 = std::find(f64list.begin(), f64list.end(), j) != f64list.end();
-      double nn = h->nd_host[j];
-      if (is64) b64 += 8.0 * packed(nn) + 16.0 * nn;
-      else b32 += 4.0 * packed(nn) + 16.0 * nn;
-    }
-    h->bytes_trmv32 = b32;
-    h->bytes_trmv64 = b64;
-  }
-  h->info.bytes_local_factors =
-      (int64_t)(h->X32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->X64.n * 8;
-  phase(1);
+  X.ocount.alloc(h->n);
+  h->optr.alloc(h->n + 1);
+  h->olist.alloc(S->nloc);
+  HIPCHK(launch_owners(S->sub_ptr, S->sub_idx, nsub, S->nloc, h->n, h->optr.p, X.ocount.p,
+                       h->olist.p, st));
+  h->xl.alloc(h->LD.nvec);
+  h->tl.alloc(h->LD.nvec);
+  h->yl.alloc(h->LD.nvec);
+  tm0.stop(st);
+  HIPCHK(hipStreamSynchronize(st));
 
   h->m_host.assign(nsub, 0);
   h->nc = 0;
-  if (o.coarse) {
-    if (!An || !Ao || !An->rowptr || !Ao->rowptr || !S->pou)
-      fail(GENEO_ERR_ARG, "coarse space needs the Neumann and overlap matrices and the PoU");
-    // ---- 2. shifted matrices C_j = A_N - sigma X A^o X and their Cholesky factors G_j
-    LocalLayout LN;
-    LN.build(h->nN_host);
-    DBuf<int> ntN, voffN, jobsN;
-    DBuf<int64_t> toffN, doffN;
-    ntN.upload(LN.nt, st);
-    voffN.upload(LN.voff, st);
-    toffN.upload(LN.toff, st);
-    doffN.upload(LN.doff, st);
-    jobsN.upload(all, st);
-    DBuf<double> G, DG;
-    G.alloc(LN.ntiles * TSQ);
-    DG.alloc(LN.ndiag * TSQ);
-    double pkN = 0.0, flN = 0.0;
-    for (int j = 0; j < nsub; ++j) {
-      pkN += packed(h->nN_host[j]);
-      flN += std::pow((double)h->nN_host[j], 3) / 3.0;
-    }
-    {
-      ProfScope ps("densify_shifted", st, 8.0 * LN.ntiles * TSQ, 0.0);
-      HIPCHK(launch_densify_shifted(G.p, toffN.p, ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
-                                    o.sigma, st));
-    }
-    {
-      ProfScope ps("chol_shifted_f64", st, 2.0 * 8.0 * pkN, flN);
-      HIPCHK(launch_chol_batched(false, G.p, toffN.p, ntN.p, DG.p, doffN.p, status.p, jobsN.p,
-                                 nsub, 0.0, st));
-    }
-    {
-      auto stat = download(status.p, nsub, st);
-      for (int j = 0; j < nsub; ++j)
-        if (stat[j]) fail(GENEO_ERR_SHIFT_NOT_SPD, "A_N - sigma B of subdomain " +
-                                                       std::to_string(j) + " is not SPD");
-    }
-    phase(2);
-
-    // ---- 3. block subspace iteration on S = G^{-1} B G^{-T}
-    const int want = o.tau > 0 ? o.nev_max : o.nev;
-    int minnt = LN.nt[0];
-    for (int j = 1; j < nsub; ++j) minnt = std::min(minnt, LN.nt[j]);
-    int b = o.eig_block;
-    if (b <= 0) {
-      b = want + std::max(8, want / 2);
-      b = ((b + 15) / 16) * 16;
-    }
-    b = std::min(b, 64);
-    b = std::min(b, minnt * TS);
-    if (b < 16 || b % 16 || want >= b)
-      fail(GENEO_ERR_ARG, "eigen block size " + std::to_string(b) +
-                              " cannot hold the requested eigenvectors");
-    h->b = b;
-    h->info.eig_block = b;
-    DBuf<double> U, W, T, Y, theta, resid;
-    DBuf<int> active, cnt;
-    U.alloc(LN.nvec * b);
-    W.alloc(LN.nvec * b);
-    T.alloc(LN.nvec * b);
-    Y.alloc(LN.nvec * b);
-    theta.alloc((size_t)nsub * b);
-    resid.alloc((size_t)nsub * b);
-    active.alloc(nsub);
-    cnt.alloc(1);
-    HIPCHK(fill_i32(active.p, 1, nsub, st));
-    HIPCHK(launch_eig_init(U.p, S->sub_ptr, voffN.p, ntN.p, nsub, b, o.seed, st));
-    HIPCHK(launch_orth(U.p, voffN.p, ntN.p, S->sub_ptr, nsub, b, o.seed, 0, nullptr, st));
-    int sweeps = 0, nact = nsub;
-    std::vector<int> act(nsub, 1);
-    for (int it = 1; it <= o.eig_maxit; ++it) {
-      // algorithmic traffic of this sweep: the factor G_j of every active
-      // subdomain is read once per triangular solve, plus its b columns
-      double gb = 0.0, vb = 0.0, tf = 0.0;
-      for (int j = 0; j < nsub; ++j) {
-        if (!act[j]) continue;
-        double nn = h->nN_host[j];
-        gb += 8.0 * packed(nn);
-        vb += 2.0 * 8.0 * nn * b;
-        tf += 2.0 * packed(nn) * b;
-      }
-      {
-        ProfScope ps("trsm_bwd", st, gb + vb, tf);
-        HIPCHK(launch_trsm_bwd(G.p, DG.p, toffN.p, doffN.p, ntN.p, voffN.p, nsub, b, U.p, T.p,
-                               active.p, st));
-      }
-      {
-        ProfScope ps("bapply", st, vb, 0.0);
-        HIPCHK(launch_bapply(S->sub_ptr, S->pou, Ao, voffN.p, ntN.p, nsub, b, T.p, W.p,
-                             active.p, st));
-      }
-      {
-        ProfScope ps("trsm_fwd", st, gb + vb, tf);
-        HIPCHK(launch_trsm_fwd(G.p, DG.p, toffN.p, doffN.p, ntN.p, voffN.p, nsub, b, W.p, T.p,
-                               active.p, st));
-      }
-      {
-        ProfScope ps("rayleigh_ritz", st, 2.0 * vb, 0.0);
-        HIPCHK(launch_rayleigh_ritz(U.p, T.p, Y.p, theta.p, resid.p, active.p, voffN.p, ntN.p,
-                                    S->sub_ptr, nsub, b, o.nev, o.tau, o.nev_max, o.sigma,
-                                    o.eig_tol, st));
-      }
-      sweeps = it;
-      act = download(active.p, nsub, st);
-      nact = 0;
-      for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
-      if (nact == 0) break;
-      {
-        ProfScope ps("orth", st, 2.0 * vb, 0.0);
-        HIPCHK(launch_orth(U.p, voffN.p, ntN.p, S->sub_ptr, nsub, b, o.seed, it, active.p, st));
-      }
-    }
-    h->info.eig_sweeps = sweeps;
-    if (nact > 0)
-      fail(GENEO_ERR_EIGEN_NOCONV, std::to_string(nact) + " subdomains did not converge in " +
-                                       std::to_string(o.eig_maxit) + " sweeps");
-    // eigenvectors p = G^{-T} y
-    HIPCHK(launch_trsm_bwd(G.p, DG.p, toffN.p, doffN.p, ntN.p, voffN.p, nsub, b, Y.p, T.p,
-                           nullptr, st));
-    DBuf<double> lam;
-    lam.alloc((size_t)nsub * b);
-    h->m.alloc(nsub);
-    HIPCHK(launch_select(theta.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, h->m.p, lam.p, st));
-    h->m_host = download(h->m.p, nsub, st);
-    h->lam_host = download(lam.p, (size_t)nsub * b, st);
-    phase(3);
-
-    // ---- 4. coarse basis Z, W = A_N Z, A_H = Z^T A Z
-    std::vector<int> zoff(nsub), woff(nsub), coff(nsub + 1);
-    int64_t zs = 0, ws = 0;
-    int nc = 0;
-    for (int j = 0; j < nsub; ++j) {
-      zoff[j] = (int)zs;
-      woff[j] = (int)ws;
-      coff[j] = nc;
-      zs += (int64_t)h->nd_host[j] * h->m_host[j];
-      ws += (int64_t)h->nN_host[j] * h->m_host[j];
-      nc += h->m_host[j];
-    }
-    coff[nsub] = nc;
-    h->nc = nc;
-    h->zoff.upload(zoff, st);
-    h->coff.upload(coff, st);
-    h->Z.alloc(zs);
-    HIPCHK(launch_basis(T.p, voffN.p, b, S->sub_ptr, S->pou, h->dmap.p, h->m.p, h->zoff.p,
-                        h->nd.p, nsub, h->Z.p, st));
-    {
-      DBuf<double> mr;
-      mr.alloc(1);
-      hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(1), 0, st, resid.p, h->m.p, nsub, b, mr.p);
-      h->info.eig_max_resid = download(mr.p, 1, st)[0];
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    if (nc > 0) {
-      DBuf<int> woffd;
-      woffd.upload(woff, st);
-      DBuf<double> Wg;
-      Wg.alloc(ws);
-      HIPCHK(launch_galerkin_w(An, S->sub_ptr, h->dmap.p, h->Z.p, h->zoff.p, h->m.p, woffd.p,
-                               nsub, Wg.p, st));
-      DBuf<uint8_t> adj;
-      adj.alloc((size_t)nsub * nsub);
-      HIPCHK(launch_adjacency(h->optr.p, h->olist.p, h->n, nsub, adj.p, st));
-      DBuf<int> pcnt, poff, npairs;
-      pcnt.alloc(nsub);
-      poff.alloc(nsub + 1);
-      npairs.alloc(1);
-      HIPCHK(launch_pairs(adj.p, nsub, pcnt.p, poff.p, nullptr, npairs.p, st, true));
-      int np = download(npairs.p, 1, st)[0];
-      DBuf<int2> pairs;
-      pairs.alloc(np);
-      HIPCHK(launch_pairs(adj.p, nsub, pcnt.p, poff.p, pairs.p, npairs.p, st, false));
-      h->ntc = (nc + TS - 1) / TS;
-      DBuf<double> AHt, DH;
-      AHt.alloc(tri_tiles(h->ntc) * TSQ);
-      DH.alloc((size_t)h->ntc * TSQ);
-      HIPCHK(launch_coarse_init(AHt.p, h->ntc, nc, st));
-      HIPCHK(launch_coarse_blocks(pairs.p, np, S->sub_ptr, S->sub_idx, h->didx.p, h->voffD.p,
-                                  h->nd.p, h->Z.p, h->zoff.p, Wg.p, woffd.p, h->m.p, h->coff.p,
-                                  AHt.p, st));
-      h->AHdense.alloc((size_t)nc * nc);
-      HIPCHK(launch_coarse_to_dense(AHt.p, h->ntc, nc, h->AHdense.p, st));
-      phase(4);
-      // ---- 5. coarse Cholesky and inverse factor
-      DBuf<int> cst;
-      cst.alloc(1);
-      {
-        ProfScope ps("coarse_chol", st, 8.0 * packed(nc), std::pow((double)nc, 3) / 3.0);
-        HIPCHK(coarse_cholesky(AHt.p, DH.p, h->ntc, cst.p, st));
-      }
-      if (download(cst.p, 1, st)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
-      h->hjob.upload(std::vector<int>{0}, st);
-      h->hnt.upload(std::vector<int>{h->ntc}, st);
-      h->hvoff.upload(std::vector<int>{0}, st);
-      h->htoff.upload(std::vector<int64_t>{0}, st);
-      DBuf<int64_t> hdoff;
-      hdoff.upload(std::vector<int64_t>{0}, st);
-      std::vector<int2> tj;
-      for (int c = 0; c < h->ntc; ++c) tj.push_back(make_int2(0, c));
-      DBuf<int2> tjobs;
-      tjobs.upload(tj, st);
-      h->XH.alloc(tri_tiles(h->ntc) * TSQ);
-      HIPCHK(launch_trtri(false, AHt.p, DH.p, h->XH.p, h->htoff.p, hdoff.p, h->hnt.p, tjobs.p,
-                          h->ntc, st));
-      h->rH.alloc((size_t)h->ntc * TS);
-      h->tH.alloc((size_t)h->ntc * TS);
-      h->yH.alloc((size_t)h->ntc * TS);
-      HIPCHK(hipMemsetAsync(h->rH.p, 0, h->rH.n * sizeof(double), st));
-      HIPCHK(hipStreamSynchronize(st));
-      phase(5);
-    }
+  const bool coarse = o.coarse != 0;
+  if (coarse && (!An || !Ao || !An->rowptr || !Ao->rowptr || !S->pou))
+    fail(GENEO_ERR_ARG, "coarse space needs the Neumann and overlap matrices and the PoU");
+  // The local Dirichlet factors (stream st) and the coarse-space work
+  // (stream hs) are independent: both are enqueued so that they overlap.
+  // The shifted factorization goes first on hs; the host then drives the
+  // local phase (it reads back the pivot tests) and afterwards the eigen
+  // sweeps, whose per-sweep readbacks only wait on hs.
+  if (coarse) {
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, st));
+    HIPCHK(hipStreamWaitEvent(h->hs, ev, 0));
+    HIPCHK(hipEventDestroy(ev));
   }
+  // Order: the FP32 local factorization runs alone (it fills the device);
+  // once its pivot tests are read back, the shifted factorization and the
+  // eigen sweeps start on hs while the FP64 refactors of the failed
+  // subdomains (few workgroups) and the triangular inverses run on st.
+  LocalLayout LN;
+  tmL.start(st);
+  setup_local(h, X, A, S, st, [&]() {
+    if (coarse) setup_shifted(h, X, LN, S, An, Ao, h->hs, tmC);
+  });
+  tmL.stop(st);
+  if (coarse) setup_coarse(h, X, LN, S, An, Ao, h->hs, tmC);
+  HIPCHK(hipStreamSynchronize(st));
+  {
+    auto stat = download(X.status.p, nsub, st);
+    for (int j : h->f64list)
+      if (stat[j]) fail(GENEO_ERR_LOCAL_NOT_SPD, "local Dirichlet matrix of subdomain " +
+                                                     std::to_string(j) + " is not SPD");
+  }
+  if (coarse) HIPCHK(hipStreamSynchronize(h->hs));
   if (h->nc == 0) {
     // placeholders so that the apply kernels always get valid pointers
     if (!h->m.p) h->m.upload(std::vector<int>(nsub, 0), st);
+    else HIPCHK(hipMemsetAsync(h->m.p, 0, nsub * sizeof(int), st));
     if (!h->zoff.p) h->zoff.upload(std::vector<int>(nsub, 0), st);
     if (!h->coff.p) h->coff.upload(std::vector<int>(nsub + 1, 0), st);
     if (!h->Z.p) h->Z.alloc(1);
     h->yH.alloc(1);
   }
-  h->xl.alloc(h->LD.nvec);
-  h->tl.alloc(h->LD.nvec);
-  h->yl.alloc(h->LD.nvec);
   HIPCHK(hipStreamSynchronize(st));
+  h->info.t_phase_ms[0] = tm0.ms();
+  h->info.t_phase_ms[1] = tmL.ms();
+  if (coarse) {
+    h->info.t_phase_ms[2] = tmC[0].ms();
+    h->info.t_phase_ms[3] = tmC[1].ms();
+    h->info.t_phase_ms[4] = tmC[2].ms();
+    h->info.t_phase_ms[5] = tmC[3].ms();
+  }
   h->info.nsub = nsub;
   h->info.nc = h->nc;
   h->info.t_setup_ms = now_ms() - t_start;

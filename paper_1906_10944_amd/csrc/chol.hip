@@ -18,8 +18,8 @@ namespace geneo {
 // Cholesky of the TS x TS tile held in sL (lower triangle used), in place,
 // plus its inverse in sI; executed by one wavefront.  Returns true when a
 // pivot d fails d > pivtol.
-template <typename T>
-__device__ bool diag_factor_wave(T (*sL)[TS + 1], T (*sI)[TS + 1], int lane, double pivtol) {
+template <typename T, int LDI>
+__device__ bool diag_factor_wave(T (*sL)[TS + 1], T (*sI)[LDI], int lane, double pivtol) {
   bool fail = false;
   for (int c = 0; c < TS; ++c) {
     T d = sL[c][c];
@@ -53,6 +53,14 @@ __device__ bool diag_factor_wave(T (*sL)[TS + 1], T (*sI)[TS + 1], int lane, dou
   return fail;
 }
 
+// LDS row stride for 32-column tiles: 34 elements keeps the fragment reads
+// of one wavefront (16 rows x 4 columns) free of bank conflicts for both
+// 4- and 8-byte elements.
+#define LDS_LD (TS + 2)
+// Row-k tiles staged per chunk in the update phase (bytes: CH * TS * LDS_LD
+// * sizeof(T)); 8 FP64 tiles = 68 KB.
+#define CHOL_CH 8
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_chol_batched(T* __restrict__ tiles,
                                                        const int64_t* __restrict__ toff,
@@ -66,25 +74,56 @@ __global__ __launch_bounds__(1024) void k_chol_batched(T* __restrict__ tiles,
   const int nt = ntl[j];
   T* A = tiles + toff[j] * TSQ;
   T* Di = dinv + doff[j] * TSQ;
+  __shared__ T sRow[CHOL_CH][TS][LDS_LD];
   __shared__ T sL[TS][TS + 1];
-  __shared__ T sI[TS][TS + 1];
+  __shared__ T sI[TS][LDS_LD];
   __shared__ int sfail;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const int fi = lane & 15, fk = lane >> 4;  // fragment row / k-offset of this lane
   if (tid == 0) sfail = 0;
   for (int k = 0; k < nt; ++k) {
-    // 1. A_ik -= sum_{jj<k} L_i,jj L_k,jj^T for i >= k, one 16x16 quadrant per item
+    // 1. A_ik -= sum_{jj<k} L_i,jj L_k,jj^T for i >= k.  Work item = 16-row
+    //    half of an output tile (both 16-column quadrants); the row-k tiles
+    //    L_k,jj are staged in LDS chunk by chunk and shared by all items.
     if (k > 0) {
-      const int nit = 4 * (nt - k);
-      for (int it = w; it < nit; it += nw) {
-        const int i = k + (it >> 2), rq = (it >> 1) & 1, cq = it & 1;
-        if (i == k && rq == 0 && cq == 1) continue;  // strict upper quadrant of A_kk
-        typename Mfma<T>::acc acc = acc_zero<T>();
-        const T* X = A + tile_idx(i, 0) * TSQ + rq * 16 * TS;
-        const T* Y = A + tile_idx(k, 0) * TSQ + cq * 16 * TS;
-        for (int jj = 0; jj < k; ++jj) q_xyT<T>(acc, X + jj * TSQ, TS, Y + jj * TSQ, TS, lane);
-        T* C = A + tile_idx(i, k) * TSQ + rq * 16 * TS + cq * 16;
+      const int nit = 2 * (nt - k);
+      const int rounds = (nit + nw - 1) / nw;
+      for (int rd = 0; rd < rounds; ++rd) {
+        const int it = rd * nw + w;
+        const bool active = it < nit;
+        const int i = k + (it >> 1), rq = it & 1;
+        typename Mfma<T>::acc a0 = acc_zero<T>(), a1 = acc_zero<T>();
+        const T* X = A + tile_idx(active ? i : k, 0) * TSQ + rq * 16 * TS;
+        for (int c0 = 0; c0 < k; c0 += CHOL_CH) {
+          const int cn = min(CHOL_CH, k - c0);
+          block_sync();
+          const T* Rsrc = A + tile_idx(k, c0) * TSQ;   // tiles (k, c0 .. c0+cn-1) are contiguous
+          for (int e = tid; e < cn * TSQ; e += blockDim.x) {
+            int t = e / TSQ, r = (e % TSQ) / TS, c = e % TS;
+            sRow[t][r][c] = Rsrc[e];
+          }
+          block_sync();
+          if (active) {
+            for (int t = 0; t < cn; ++t) {
+              const T* Xt = X + (int64_t)(c0 + t) * TSQ;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) C[acc_row<T>(lane, v) * TS + acc_col(lane)] -= acc[v];
+              for (int kk = 0; kk < 8; ++kk) {
+                T av = Xt[fi * TS + kk * 4 + fk];
+                a0 = Mfma<T>::run(av, sRow[t][fi][kk * 4 + fk], a0);
+                a1 = Mfma<T>::run(av, sRow[t][16 + fi][kk * 4 + fk], a1);
+              }
+            }
+          }
+        }
+        if (active) {
+          T* C = A + tile_idx(i, k) * TSQ + rq * 16 * TS;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = acc_row<T>(lane, v);
+            C[r * TS + acc_col(lane)] -= a0[v];
+            C[r * TS + 16 + acc_col(lane)] -= a1[v];
+          }
+        }
       }
     }
     block_sync();
@@ -93,7 +132,7 @@ __global__ __launch_bounds__(1024) void k_chol_batched(T* __restrict__ tiles,
       T* D = A + tile_idx(k, k) * TSQ;
       for (int e = lane; e < TSQ; e += 64) sL[e / TS][e % TS] = D[e];
       wave_sync();
-      bool fail = diag_factor_wave<T>(sL, sI, lane, pivtol);
+      bool fail = diag_factor_wave<T, LDS_LD>(sL, sI, lane, pivtol);
       for (int e = lane; e < TSQ; e += 64) {
         int r = e / TS, q = e % TS;
         D[e] = q <= r ? sL[r][q] : (T)0;
@@ -101,9 +140,7 @@ __global__ __launch_bounds__(1024) void k_chol_batched(T* __restrict__ tiles,
       }
       if (fail && lane == 0) {
         sfail = 1;
-        // first failing row of this tile
-        int row = k * TS;
-        status[j] = 1 + row;
+        status[j] = 1 + k * TS;
       }
     }
     block_sync();
@@ -114,8 +151,12 @@ __global__ __launch_bounds__(1024) void k_chol_batched(T* __restrict__ tiles,
       const int i = k + 1 + (it >> 1), rq = it & 1;
       T* X = A + tile_idx(i, k) * TSQ + rq * 16 * TS;
       typename Mfma<T>::acc a0 = acc_zero<T>(), a1 = acc_zero<T>();
-      q_xyT<T>(a0, X, TS, &sI[0][0], TS + 1, lane);
-      q_xyT<T>(a1, X, TS, &sI[16][0], TS + 1, lane);
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        T av = X[fi * TS + kk * 4 + fk];
+        a0 = Mfma<T>::run(av, sI[fi][kk * 4 + fk], a0);
+        a1 = Mfma<T>::run(av, sI[16 + fi][kk * 4 + fk], a1);
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         X[acc_row<T>(lane, v) * TS + acc_col(lane)] = a0[v];
@@ -197,7 +238,7 @@ __global__ __launch_bounds__(64) void k_cpotrf(double* __restrict__ A, double* _
   double* D = A + tile_idx(k, k) * TSQ;
   for (int e = lane; e < TSQ; e += 64) sL[e / TS][e % TS] = D[e];
   wave_sync();
-  bool fail = diag_factor_wave<double>(sL, sI, lane, 0.0);
+  bool fail = diag_factor_wave<double, TS + 1>(sL, sI, lane, 0.0);
   for (int e = lane; e < TSQ; e += 64) {
     int r = e / TS, q = e % TS;
     D[e] = q <= r ? sL[r][q] : 0.0;

@@ -70,31 +70,6 @@ __device__ void gram(const double* X, const double* Y, int npad, int b, double (
   block_sync();
 }
 
-// X[rows] <- X[rows] * M (b x b, in LDS), 16-row slabs per wavefront.
-__device__ void right_multiply(double* X, int npad, int b, const double (*M)[EIG_MAXB + 1]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ncq = b / 16;
-  const int nslab = npad / 16;
-  for (int s = w; s < nslab; s += EIG_WAVES) {
-    double* Xs = X + (int64_t)s * 16 * b;
-    d4_t acc[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = acc_zero<double>();
-    const int i = lane & 15, k = lane >> 4;
-    for (int kk = 0; kk < b / 4; ++kk) {
-      double a = Xs[i * b + kk * 4 + k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < ncq) acc[c] = Mfma<double>::run(a, M[kk * 4 + k][c * 16 + i], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (c < ncq)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Xs[acc_row<double>(lane, v) * b + c * 16 + acc_col(lane)] = acc[c][v];
-  }
-}
-
 // Cholesky of sG (b x b, unit diagonal expected) by wavefront 0 into its
 // lower triangle; returns a bitmask-free flag array bad[c] = 1 for pivots
 // below `tiny`.  Then sM = L^{-T} (upper triangular).
@@ -132,90 +107,21 @@ __device__ void chol_inv_wave(double (*sG)[EIG_MAXB + 1], double (*sM)[EIG_MAXB 
   wave_sync();
 }
 
-// --------------------------------------------------------------- orth ---
-__global__ __launch_bounds__(1024) void k_orth(double* __restrict__ U, const int* __restrict__ voff,
-                                               const int* __restrict__ ntl,
-                                               const int* __restrict__ sub_ptr, int b,
-                                               uint64_t seed, int salt,
-                                               const int* __restrict__ active) {
-  const int j = blockIdx.x;
-  if (active && !active[j]) return;
-  __shared__ double spart[EIG_WAVES][256];
-  __shared__ double sG[EIG_MAXB][EIG_MAXB + 1];
-  __shared__ double sM[EIG_MAXB][EIG_MAXB + 1];
-  __shared__ int bad[EIG_MAXB];
-  __shared__ int nbad;
-  __shared__ double scl[EIG_MAXB];
-  const int npad = ntl[j] * TS;
-  const int n = sub_ptr[j + 1] - sub_ptr[j];
-  double* Uj = U + (int64_t)voff[j] * b;
-  const int tid = threadIdx.x;
-  int pass = 0, refill = 0;
-  while (pass < 2) {
-    gram(Uj, Uj, npad, b, spart, sG);
-    // scale to unit diagonal
-    if (tid < b) {
-      double d = sG[tid][tid];
-      scl[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-    }
-    block_sync();
-    for (int t = tid; t < b * b; t += blockDim.x) {
-      int r = t / b, c = t % b;
-      sG[r][c] *= scl[r] * scl[c];
-    }
-    block_sync();
-    if (tid < 64) chol_inv_wave(sG, sM, b, bad, 1e-10);
-    if (tid == 0) {
-      int cnt = 0;
-      for (int c = 0; c < b; ++c) cnt += bad[c] || scl[c] == 0.0;
-      nbad = cnt;
-    }
-    block_sync();
-    if (nbad > 0 && refill < 4) {
-      // replace collapsed columns by fresh pseudo-random vectors and retry
-      for (int t = tid; t < npad * b; t += blockDim.x) {
-        int a = t / b, c = t % b;
-        if (bad[c] || scl[c] == 0.0)
-          Uj[t] = hash_uniform(seed + 7919ull * (salt + 1) + refill, (uint64_t)j,
-                               (uint64_t)a * 977 + c);
-      }
-      block_sync();
-      ++refill;
-      pass = 0;
-      continue;
-    }
-    // U <- U * diag(scl) * L^{-T}
-    for (int t = tid; t < b * b; t += blockDim.x) {
-      int r = t / b, c = t % b;
-      sM[r][c] *= scl[r];
-    }
-    block_sync();
-    right_multiply(Uj, npad, b, sM);
-    block_sync();
-    ++pass;
-  }
-}
-
-hipError_t launch_orth(double* U, const int* voff, const int* nt, const int* sub_ptr, int nsub,
-                       int b, uint64_t seed, int salt, const int* active, hipStream_t st) {
-  hipLaunchKernelGGL(k_orth, dim3(nsub), dim3(1024), 0, st, U, voff, nt, sub_ptr, b, seed, salt,
-                     active);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------- Jacobi (wave) ---
-// Eigen-decomposition of the symmetric sH (b x b) by cyclic Jacobi with the
-// round-robin ordering: on return diag(sH) holds the eigenvalues and sQ the
-// eigenvectors (columns).
-__device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 1], int b,
+// Eigen-decomposition of the symmetric sH (B x B) by cyclic Jacobi with the
+// round-robin ordering, executed by one wavefront: on return diag(sH) holds
+// the eigenvalues and sQ the eigenvectors (columns).  Rounds whose
+// rotations are all negligible are skipped.
+template <int B>
+__device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 1],
                             double* cs_c, double* cs_s, int* pp, int* pq) {
   const int lane = threadIdx.x & 63;
-  for (int e = lane; e < b * b; e += 64) sQ[e / b][e % b] = (e / b == e % b) ? 1.0 : 0.0;
+  for (int e = lane; e < B * B; e += 64) sQ[e / B][e % B] = (e / B == e % B) ? 1.0 : 0.0;
   wave_sync();
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = lane; e < b * b; e += 64) {
-      int r = e / b, c = e % b;
+    for (int e = lane; e < B * B; e += 64) {
+      int r = e / B, c = e % B;
       double v = sH[r][c];
       if (r != c) off += v * v;
       else dia += v * v;
@@ -225,30 +131,34 @@ __device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 
       dia += __shfl_xor(dia, m);
     }
     if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int round = 0; round < b - 1; ++round) {
-      if (lane < b / 2) {
-        int i0 = lane, i1 = b - 1 - lane;
-        int p = i0 == 0 ? 0 : ((i0 - 1 + round) % (b - 1)) + 1;
-        int q = ((i1 - 1 + round) % (b - 1)) + 1;
+    for (int round = 0; round < B - 1; ++round) {
+      int rot = 0;
+      if (lane < B / 2) {
+        int i0 = lane, i1 = B - 1 - lane;
+        int p = i0 == 0 ? 0 : ((i0 - 1 + round) % (B - 1)) + 1;
+        int q = ((i1 - 1 + round) % (B - 1)) + 1;
         if (p > q) { int t = p; p = q; q = t; }
         double apq = sH[p][q];
+        double app = sH[p][p], aqq = sH[q][q];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          double app = sH[p][p], aqq = sH[q][q];
+        if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) && apq != 0.0) {
           double tau = (aqq - app) / (2.0 * apq);
           double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
+          rot = 1;
         }
         cs_c[lane] = c;
         cs_s[lane] = s;
         pp[lane] = p;
         pq[lane] = q;
       }
+      if (!__any(rot)) continue;
       wave_sync();
       // rows p, q of H
-      for (int e = lane; e < (b / 2) * b; e += 64) {
-        int k = e / b, m = e % b;
+#pragma unroll 4
+      for (int e = lane; e < (B / 2) * B; e += 64) {
+        int k = e / B, m = e % B;
         int p = pp[k], q = pq[k];
         double c = cs_c[k], s = cs_s[k];
         double hp = sH[p][m], hq = sH[q][m];
@@ -257,8 +167,9 @@ __device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 
       }
       wave_sync();
       // columns p, q of H and of Q
-      for (int e = lane; e < (b / 2) * b; e += 64) {
-        int k = e / b, m = e % b;
+#pragma unroll 4
+      for (int e = lane; e < (B / 2) * B; e += 64) {
+        int k = e / B, m = e % B;
         int p = pp[k], q = pq[k];
         double c = cs_c[k], s = cs_s[k];
         double hp = sH[m][p], hq = sH[m][q];
@@ -273,144 +184,310 @@ __device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 
   }
 }
 
-// ------------------------------------------------------- Rayleigh-Ritz ---
-__global__ __launch_bounds__(1024) void k_rayleigh_ritz(
-    double* __restrict__ U, const double* __restrict__ W, double* __restrict__ Y,
-    double* __restrict__ theta, double* __restrict__ resid, int* __restrict__ active,
-    const int* __restrict__ voff, const int* __restrict__ ntl, int b, int nev, double tau,
-    int nev_max, double sigma, double tol) {
+// ------------------------------------------------------ batched pieces ---
+// G_j = X_j^T Y_j (b x b) for every active subdomain, one workgroup each.
+__global__ __launch_bounds__(1024) void k_gram(const double* __restrict__ X,
+                                               const double* __restrict__ Y,
+                                               const int* __restrict__ voff,
+                                               const int* __restrict__ ntl, int b,
+                                               double* __restrict__ G,
+                                               const int* __restrict__ active, int symm) {
   const int j = blockIdx.x;
-  if (!active[j]) return;
+  if (active && !active[j]) return;
   __shared__ double spart[EIG_WAVES][256];
-  __shared__ double sH[EIG_MAXB][EIG_MAXB + 1];
-  __shared__ double sQ[EIG_MAXB][EIG_MAXB + 1];
-  __shared__ double sres[EIG_WAVES][EIG_MAXB];
-  __shared__ double th[EIG_MAXB];
-  __shared__ double cs_c[EIG_MAXB / 2], cs_s[EIG_MAXB / 2];
-  __shared__ int pp[EIG_MAXB / 2], pq[EIG_MAXB / 2], perm[EIG_MAXB];
+  __shared__ double sG[EIG_MAXB][EIG_MAXB + 1];
   const int npad = ntl[j] * TS;
-  double* Uj = U + (int64_t)voff[j] * b;
-  const double* Wj = W + (int64_t)voff[j] * b;
-  double* Yj = Y + (int64_t)voff[j] * b;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // H = U^T W, symmetrised
-  gram(Uj, Wj, npad, b, spart, sH);
-  for (int t = tid; t < b * b; t += blockDim.x) {
+  gram(X + (int64_t)voff[j] * b, Y + (int64_t)voff[j] * b, npad, b, spart, sG);
+  double* Gj = G + (int64_t)j * b * b;
+  for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
     int r = t / b, c = t % b;
-    if (r < c) {
-      double v = 0.5 * (sH[r][c] + sH[c][r]);
-      sH[r][c] = v;
-      sH[c][r] = v;
-    }
-  }
-  block_sync();
-  if (w == 0) {
-    jacobi_wave(sH, sQ, b, cs_c, cs_s, pp, pq);
-    if (lane == 0) {
-      // stable selection sort, descending
-      for (int c = 0; c < b; ++c) perm[c] = c;
-      for (int c = 0; c < b; ++c) {
-        int best = c;
-        for (int q = c + 1; q < b; ++q)
-          if (sH[perm[q]][perm[q]] > sH[perm[best]][perm[best]]) best = q;
-        int t = perm[best];
-        for (int q = best; q > c; --q) perm[q] = perm[q - 1];
-        perm[c] = t;
-      }
-      for (int c = 0; c < b; ++c) th[c] = sH[perm[c]][perm[c]];
-    }
-    wave_sync();
-  }
-  block_sync();
-  // Qs = Q[:, perm] into sH
-  for (int t = tid; t < b * b; t += blockDim.x) {
-    int r = t / b, c = t % b;
-    sH[r][c] = sQ[r][perm[c]];
-  }
-  block_sync();
-  // slabs: WQ, UQ, residual partials; Y <- UQ, U <- WQ
-  for (int t = tid; t < EIG_WAVES * EIG_MAXB; t += blockDim.x) sres[t / EIG_MAXB][t % EIG_MAXB] = 0.0;
-  block_sync();
-  {
-    const int ncq = b / 16;
-    const int nslab = npad / 16;
-    const int i = lane & 15, k = lane >> 4;
-    for (int s = w; s < nslab; s += EIG_WAVES) {
-      double* Us = Uj + (int64_t)s * 16 * b;
-      const double* Ws = Wj + (int64_t)s * 16 * b;
-      double* Ys = Yj + (int64_t)s * 16 * b;
-      d4_t aw[4], au[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) { aw[c] = acc_zero<double>(); au[c] = acc_zero<double>(); }
-      for (int kk = 0; kk < b / 4; ++kk) {
-        double xw = Ws[i * b + kk * 4 + k];
-        double xu = Us[i * b + kk * 4 + k];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (c >= ncq) continue;
-          double q = sH[kk * 4 + k][c * 16 + i];
-          aw[c] = Mfma<double>::run(xw, q, aw[c]);
-          au[c] = Mfma<double>::run(xu, q, au[c]);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (c >= ncq) continue;
-        const int col = c * 16 + acc_col(lane);
-        double r2 = 0.0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double rv = aw[c][v] - th[col] * au[c][v];
-          r2 += rv * rv;
-          Ys[acc_row<double>(lane, v) * b + col] = au[c][v];
-          Us[acc_row<double>(lane, v) * b + col] = aw[c][v];
-        }
-        r2 += __shfl_xor(r2, 16);
-        r2 += __shfl_xor(r2, 32);
-        if (lane < 16) sres[w][col] += r2;
-      }
-    }
-  }
-  block_sync();
-  if (tid < b) {
-    double s = 0.0;
-    for (int q = 0; q < EIG_WAVES; ++q) s += sres[q][tid];
-    sres[0][tid] = sqrt(s);
-  }
-  block_sync();
-  if (tid == 0) {
-    const double t0 = th[0];
-    int nfin = 0;
-    for (int c = 0; c < b; ++c) nfin += (t0 > 0.0 && th[c] > 1e-14 * t0);
-    int want;
-    if (tau > 0.0) {
-      int below = 0;
-      for (int c = 0; c < nfin; ++c) below += (sigma + 1.0 / th[c] < tau);
-      want = below + 1;
-      if (want > nev_max) want = nev_max;
-    } else {
-      want = nev;
-    }
-    if (want > nfin) want = nfin;
-    if (want > b) want = b;
-    // backward-error test: ||S y - theta y|| <= tol * ||S|| with ||S|| = theta_0
-    bool ok = true;
-    for (int c = 0; c < want; ++c) ok = ok && (sres[0][c] <= tol * t0);
-    for (int c = 0; c < b; ++c) {
-      theta[(int64_t)j * b + c] = th[c];
-      resid[(int64_t)j * b + c] = t0 > 0.0 ? sres[0][c] / t0 : 0.0;
-    }
-    if (ok) active[j] = 0;
+    Gj[t] = symm ? 0.5 * (sG[r][c] + sG[c][r]) : sG[r][c];
   }
 }
 
-hipError_t launch_rayleigh_ritz(double* U, const double* W, double* Y, double* theta,
-                                double* resid, int* active, const int* voff, const int* nt,
-                                const int* sub_ptr, int nsub, int b, int nev, double tau,
-                                int nev_max, double sigma, double tol, hipStream_t st) {
-  (void)sub_ptr;
-  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(nsub), dim3(1024), 0, st, U, W, Y, theta, resid,
-                     active, voff, nt, b, nev, tau, nev_max, sigma, tol);
+// One wavefront per subdomain: Jacobi eigen-decomposition of H_j, columns
+// sorted by descending eigenvalue (stable), into Q_j and theta_j.
+template <int B>
+__global__ __launch_bounds__(64) void k_small_eig(const double* __restrict__ H,
+                                                  double* __restrict__ Q,
+                                                  double* __restrict__ theta,
+                                                  const int* __restrict__ active) {
+  constexpr int b = B;
+  const int j = blockIdx.x;
+  if (active && !active[j]) return;
+  __shared__ double sH[EIG_MAXB][EIG_MAXB + 1];
+  __shared__ double sQ[EIG_MAXB][EIG_MAXB + 1];
+  __shared__ double cs_c[EIG_MAXB / 2], cs_s[EIG_MAXB / 2];
+  __shared__ int pp[EIG_MAXB / 2], pq[EIG_MAXB / 2], perm[EIG_MAXB];
+  const int lane = threadIdx.x;
+  const double* Hj = H + (int64_t)j * b * b;
+  for (int e = lane; e < b * b; e += 64) sH[e / b][e % b] = Hj[e];
+  wave_sync();
+  jacobi_wave<B>(sH, sQ, cs_c, cs_s, pp, pq);
+  if (lane == 0) {
+    for (int c = 0; c < b; ++c) perm[c] = c;
+    for (int c = 0; c < b; ++c) {
+      int best = c;
+      for (int q = c + 1; q < b; ++q)
+        if (sH[perm[q]][perm[q]] > sH[perm[best]][perm[best]]) best = q;
+      int t = perm[best];
+      for (int q = best; q > c; --q) perm[q] = perm[q - 1];
+      perm[c] = t;
+    }
+  }
+  wave_sync();
+  double* Qj = Q + (int64_t)j * b * b;
+  for (int e = lane; e < b * b; e += 64) {
+    int r = e / b, c = e % b;
+    Qj[e] = sQ[r][perm[c]];
+  }
+  if (lane < b) theta[(int64_t)j * b + lane] = sH[perm[lane]][perm[lane]];
+}
+
+// One wavefront per subdomain: Cholesky-QR factor of the Gram matrix G_j of
+// the current block.  M_j = diag(s) L^{-T} with s = diag(G)^{-1/2} and
+// L L^T = diag(s) G diag(s).  A column whose pivot collapses (numerically
+// dependent on the previous ones) gets a zero column in M_j and its flag in
+// badcol[j*b + c].
+__global__ __launch_bounds__(64) void k_small_cholqr(const double* __restrict__ G, int b,
+                                                     double* __restrict__ M,
+                                                     int* __restrict__ badcol,
+                                                     const int* __restrict__ active) {
+  const int j = blockIdx.x;
+  if (active && !active[j]) return;
+  __shared__ double sG[EIG_MAXB][EIG_MAXB + 1];
+  __shared__ double sM[EIG_MAXB][EIG_MAXB + 1];
+  __shared__ double scl[EIG_MAXB];
+  __shared__ int sbad[EIG_MAXB];
+  const int lane = threadIdx.x;
+  const double* Gj = G + (int64_t)j * b * b;
+  if (lane < b) {
+    double d = Gj[lane * b + lane];
+    scl[lane] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  wave_sync();
+  for (int e = lane; e < b * b; e += 64) {
+    int r = e / b, c = e % b;
+    sG[r][c] = Gj[e] * scl[r] * scl[c];
+  }
+  wave_sync();
+  chol_inv_wave(sG, sM, b, sbad, 1e-10);
+  double* Mj = M + (int64_t)j * b * b;
+  for (int e = lane; e < b * b; e += 64) {
+    int r = e / b, c = e % b;
+    const bool badc = sbad[c] || scl[c] == 0.0;
+    Mj[e] = badc ? 0.0 : sM[r][c] * scl[r];
+  }
+  if (lane < b) badcol[(int64_t)j * b + lane] = (sbad[lane] || scl[lane] == 0.0) ? 1 : 0;
+}
+
+// X_j <- X_j M_j for 16-row slabs; grid (slab groups, subdomains).
+// With Yout != NULL also Yout_j = Xin_j M_j from a second input (used to
+// form U Q and W Q in one pass together with the residual partial sums).
+#define SLABS_PER_WG 8
+__global__ __launch_bounds__(256) void k_right_mul(double* __restrict__ X,
+                                                   const double* __restrict__ M,
+                                                   const int* __restrict__ voff,
+                                                   const int* __restrict__ ntl, int b,
+                                                   const int* __restrict__ active) {
+  const int j = blockIdx.y;
+  if (active && !active[j]) return;
+  const int nslab = ntl[j] * TS / 16;
+  const int s0 = blockIdx.x * SLABS_PER_WG;
+  if (s0 >= nslab) return;
+  __shared__ double sM[EIG_MAXB][EIG_MAXB + 1];
+  const double* Mj = M + (int64_t)j * b * b;
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) sM[e / b][e % b] = Mj[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ncq = b / 16;
+  double* Xj = X + (int64_t)voff[j] * b;
+  for (int s = s0 + w; s < min(nslab, s0 + SLABS_PER_WG); s += 4) {
+    double* Xs = Xj + (int64_t)s * 16 * b;
+    d4_t acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = acc_zero<double>();
+    const int i = lane & 15, k = lane >> 4;
+    for (int kk = 0; kk < b / 4; ++kk) {
+      double a = Xs[i * b + kk * 4 + k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < ncq) acc[c] = Mfma<double>::run(a, sM[kk * 4 + k][c * 16 + i], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < ncq)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xs[acc_row<double>(lane, v) * b + c * 16 + acc_col(lane)] = acc[c][v];
+  }
+}
+
+// Ritz step: Y = U Q, U <- W Q, and per-group partial sums of
+// ||W Q e_c - theta_c U Q e_c||^2; grid (slab groups, subdomains).
+__global__ __launch_bounds__(256) void k_ritz_update(double* __restrict__ U,
+                                                     const double* __restrict__ W,
+                                                     double* __restrict__ Y,
+                                                     const double* __restrict__ Q,
+                                                     const double* __restrict__ theta,
+                                                     const int* __restrict__ voff,
+                                                     const int* __restrict__ ntl, int b,
+                                                     double* __restrict__ part, int ngroups,
+                                                     const int* __restrict__ active) {
+  const int j = blockIdx.y;
+  if (active && !active[j]) return;
+  const int nslab = ntl[j] * TS / 16;
+  const int s0 = blockIdx.x * SLABS_PER_WG;
+  __shared__ double sQ[EIG_MAXB][EIG_MAXB + 1];
+  __shared__ double sres[4][EIG_MAXB];
+  __shared__ double th[EIG_MAXB];
+  const double* Qj = Q + (int64_t)j * b * b;
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) sQ[e / b][e % b] = Qj[e];
+  for (int e = threadIdx.x; e < 4 * EIG_MAXB; e += blockDim.x) sres[e / EIG_MAXB][e % EIG_MAXB] = 0.0;
+  if (threadIdx.x < b) th[threadIdx.x] = theta[(int64_t)j * b + threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ncq = b / 16;
+  double* Uj = U + (int64_t)voff[j] * b;
+  const double* Wj = W + (int64_t)voff[j] * b;
+  double* Yj = Y + (int64_t)voff[j] * b;
+  const int i = lane & 15, k = lane >> 4;
+  for (int s = s0 + w; s < min(nslab, s0 + SLABS_PER_WG); s += 4) {
+    double* Us = Uj + (int64_t)s * 16 * b;
+    const double* Ws = Wj + (int64_t)s * 16 * b;
+    double* Ys = Yj + (int64_t)s * 16 * b;
+    d4_t aw[4], au[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { aw[c] = acc_zero<double>(); au[c] = acc_zero<double>(); }
+    for (int kk = 0; kk < b / 4; ++kk) {
+      double xw = Ws[i * b + kk * 4 + k];
+      double xu = Us[i * b + kk * 4 + k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c >= ncq) continue;
+        double q = sQ[kk * 4 + k][c * 16 + i];
+        aw[c] = Mfma<double>::run(xw, q, aw[c]);
+        au[c] = Mfma<double>::run(xu, q, au[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= ncq) continue;
+      const int col = c * 16 + acc_col(lane);
+      double r2 = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double rv = aw[c][v] - th[col] * au[c][v];
+        r2 += rv * rv;
+        Ys[acc_row<double>(lane, v) * b + col] = au[c][v];
+        Us[acc_row<double>(lane, v) * b + col] = aw[c][v];
+      }
+      r2 += __shfl_xor(r2, 16);
+      r2 += __shfl_xor(r2, 32);
+      if (lane < 16) sres[w][col] += r2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < b) {
+    double t = sres[0][threadIdx.x] + sres[1][threadIdx.x] + sres[2][threadIdx.x] +
+               sres[3][threadIdx.x];
+    part[((int64_t)j * ngroups + blockIdx.x) * b + threadIdx.x] = t;
+  }
+}
+
+// Convergence test per subdomain (backward error ||r_c|| <= tol ||S||,
+// ||S|| = theta_0) over the wanted pairs; clears active[j] when done.  One
+// 64-thread block per subdomain: thread c reduces column c over the groups.
+__global__ __launch_bounds__(64) void k_ritz_check(const double* __restrict__ part, int ngroups,
+                                                   const double* __restrict__ theta,
+                                                   double* __restrict__ resid,
+                                                   int* __restrict__ active, int b, int nev,
+                                                   double tau, int nev_max, double sigma,
+                                                   double tol) {
+  const int j = blockIdx.x;
+  if (!active[j]) return;
+  __shared__ double rr[EIG_MAXB];
+  const int c = threadIdx.x;
+  const double* th = theta + (int64_t)j * b;
+  const double t0 = th[0];
+  if (c < b) {
+    double s = 0.0;
+    for (int g = 0; g < ngroups; ++g) s += part[((int64_t)j * ngroups + g) * b + c];
+    rr[c] = sqrt(s);
+    resid[(int64_t)j * b + c] = t0 > 0.0 ? rr[c] / t0 : 0.0;
+  }
+  __syncthreads();
+  if (c != 0) return;
+  int nfin = 0;
+  for (int q = 0; q < b; ++q) nfin += (t0 > 0.0 && th[q] > 1e-14 * t0);
+  int want;
+  if (tau > 0.0) {
+    int below = 0;
+    for (int q = 0; q < nfin; ++q) below += (sigma + 1.0 / th[q] < tau);
+    want = below + 1;
+    if (want > nev_max) want = nev_max;
+  } else {
+    want = nev;
+  }
+  if (want > nfin) want = nfin;
+  if (want > b) want = b;
+  bool ok = true;
+  for (int q = 0; q < want; ++q) ok = ok && (rr[q] <= tol * t0);
+  if (ok) active[j] = 0;
+}
+
+// Replace the collapsed (zeroed) columns by fresh pseudo-random vectors.
+__global__ void k_refill(double* __restrict__ U, const int* __restrict__ voff,
+                         const int* __restrict__ ntl, int b, const int* __restrict__ badcol,
+                         uint64_t seed, int salt, const int* __restrict__ active) {
+  const int j = blockIdx.x;
+  if (active && !active[j]) return;
+  const int* bj = badcol + (int64_t)j * b;
+  int any = 0;
+  for (int c = 0; c < b; ++c) any |= bj[c];
+  if (!any) return;
+  const int npad = ntl[j] * TS;
+  double* Uj = U + (int64_t)voff[j] * b;
+  for (int t = threadIdx.x; t < npad * b; t += blockDim.x) {
+    int a = t / b, c = t % b;
+    if (bj[c])
+      Uj[t] = hash_uniform(seed + 7919ull * (salt + 1), (uint64_t)j, (uint64_t)a * 977 + c);
+  }
+}
+
+// Orthonormalise the blocks: two passes of Cholesky QR; after the first,
+// collapsed columns are replaced by pseudo-random vectors, which the second
+// pass orthonormalises against the rest.
+hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int b,
+                        uint64_t seed, int salt, const int* active, const EigWork& wk,
+                        hipStream_t st) {
+  dim3 grid2(wk.ngroups, nsub);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, U, voff, nt, b, wk.G, active, 1);
+    hipLaunchKernelGGL(k_small_cholqr, dim3(nsub), dim3(64), 0, st, wk.G, b, wk.M, wk.badcol,
+                       active);
+    hipLaunchKernelGGL(k_right_mul, grid2, dim3(256), 0, st, U, wk.M, voff, nt, b, active);
+    if (pass == 0)
+      hipLaunchKernelGGL(k_refill, dim3(nsub), dim3(256), 0, st, U, voff, nt, b, wk.badcol, seed,
+                         salt, active);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, double* resid,
+                      int* active, const int* voff, const int* nt, int nsub, int b, int nev,
+                      double tau, int nev_max, double sigma, double tol, const EigWork& wk,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, W, voff, nt, b, wk.G, active, 1);
+  switch (b) {
+    case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    case 32: hipLaunchKernelGGL(k_small_eig<32>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    case 48: hipLaunchKernelGGL(k_small_eig<48>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    default: hipLaunchKernelGGL(k_small_eig<64>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+  }
+  hipLaunchKernelGGL(k_ritz_update, dim3(wk.ngroups, nsub), dim3(256), 0, st, U, W, Y, wk.M,
+                     theta, voff, nt, b, wk.part, wk.ngroups, active);
+  hipLaunchKernelGGL(k_ritz_check, dim3(nsub), dim3(64), 0, st, wk.part, wk.ngroups, theta,
+                     resid, active, b, nev, tau, nev_max, sigma, tol);
   return hipGetLastError();
 }
 

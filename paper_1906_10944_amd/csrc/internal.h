@@ -62,12 +62,15 @@ hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
-hipError_t trmv_lower(bool fp32, const void* X, const int64_t* toff, const int* nt,
-                      const int* voff, const int* jobs, int njobs, int maxnt, const double* xin,
-                      double* tout, const int* done, hipStream_t st);
-hipError_t trmv_upperT(bool fp32, const void* X, const int64_t* toff, const int* nt,
-                       const int* voff, const int* jobs, int njobs, int maxnt, const double* tin,
-                       double* yout, const int* done, hipStream_t st);
+// jobs[] = (subdomain, 1 if its inverse factor is FP64 in X64 else FP32 in X32).
+hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
+                      const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
+                      int njobs, int maxnt, const double* xin, double* tout, const int* done,
+                      hipStream_t st);
+hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff32,
+                       const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
+                       int njobs, int maxnt, const double* tin, double* yout, const int* done,
+                       hipStream_t st);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
@@ -83,12 +86,20 @@ hipError_t launch_bapply(const int* sub_ptr, const double* pou, const geneo_csr_
 // ------------------------------------------------------------- eigen.hip
 hipError_t launch_eig_init(double* U, const int* sub_ptr, const int* voff, const int* nt,
                            int nsub, int b, uint64_t seed, hipStream_t st);
-hipError_t launch_orth(double* U, const int* voff, const int* nt, const int* sub_ptr, int nsub,
-                       int b, uint64_t seed, int salt, const int* active, hipStream_t st);
-hipError_t launch_rayleigh_ritz(double* U, const double* W, double* Y, double* theta,
-                                double* resid, int* active, const int* voff, const int* nt,
-                                const int* sub_ptr, int nsub, int b, int nev, double tau,
-                                int nev_max, double sigma, double tol, hipStream_t st);
+struct EigWork {
+  double* G;     // nsub * b * b  Gram / Rayleigh quotient matrices
+  double* M;     // nsub * b * b  small factors / Ritz rotations
+  double* part;  // nsub * ngroups * b residual partial sums
+  int* badcol;   // nsub * b collapsed-column flags
+  int ngroups;   // slab groups per subdomain
+};
+hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int b,
+                        uint64_t seed, int salt, const int* active, const EigWork& wk,
+                        hipStream_t st);
+hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, double* resid,
+                      int* active, const int* voff, const int* nt, int nsub, int b, int nev,
+                      double tau, int nev_max, double sigma, double tol, const EigWork& wk,
+                      hipStream_t st);
 hipError_t launch_select(const double* theta, int nsub, int b, int nev, double tau,
                          int nev_max, double sigma, int* m, double* lam, hipStream_t st);
 hipError_t launch_basis(const double* P, const int* voff, int b, const int* sub_ptr,
@@ -118,10 +129,5 @@ hipError_t launch_restrict_coarse(const double* r, const double* Z, const int* z
                                   const int* m, const int* nd, const int* didx,
                                   const int* sub_ptr, const int* sub_idx, const int* coff,
                                   int nsub, double* rH, hipStream_t st);
-hipError_t launch_combine(const int* optr, const int2* olist, const int* dmap,
-                          const int* voff, const double* dscale, const double* yl,
-                          const double* Z, const int* zoff, const int* m, const int* coff,
-                          const double* yH, int ndof, int use_coarse, double* z,
-                          const int* done, hipStream_t st);
 
 }  // namespace geneo

@@ -19,7 +19,7 @@ hipError_t gather_local(const double* r, const int* dglob, const double* dscale,
 hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, const int* m,
                            const int* nd, const int* dglob, const int* dvoff, const int* coff,
                            int nsub, double* rH, const int* done, hipStream_t st);
-hipError_t combine(const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
+hipError_t combine(const double* r, const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
                    const int* dvoff, const double* dscale, const double* yl, const double* Z,
                    const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
                    int use_coarse, double* z, const int* done, hipStream_t st);

@@ -115,7 +115,10 @@ hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, co
 
 // z[g] = sum over the subdomains j owning g (in ascending j) of
 //        s_d y_j[d] + Z_j[d][:] . yH[coff_j :]          (d = dmap_j(g) >= 0)
-__global__ void k_combine(const int* __restrict__ optr, const int2* __restrict__ olist,
+// and z[g] = r[g] for a dof in no D_j (an eliminated Dirichlet dof: its row
+// of A is a unit row, so the operator stays SPD on every dof).
+__global__ void k_combine(const double* __restrict__ r, const int* __restrict__ optr,
+                          const int2* __restrict__ olist,
                           const int* __restrict__ sub_ptr, const int* __restrict__ dmap,
                           const int* __restrict__ dvoff, const double* __restrict__ dscale,
                           const double* __restrict__ yl, const double* __restrict__ Z,
@@ -126,11 +129,13 @@ __global__ void k_combine(const int* __restrict__ optr, const int2* __restrict__
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ndof) return;
   double s = 0.0;
+  bool covered = false;
   for (int p = optr[g]; p < optr[g + 1]; ++p) {
     int2 o = olist[p];
     int j = o.x;
     int d = dmap[sub_ptr[j] + o.y];
     if (d < 0) continue;
+    covered = true;
     int e = dvoff[j] + d;
     s += dscale[e] * yl[e];
     if (use_coarse) {
@@ -140,14 +145,14 @@ __global__ void k_combine(const int* __restrict__ optr, const int2* __restrict__
       for (int c = 0; c < mj; ++c) s += zr[c] * yh[c];
     }
   }
-  z[g] = s;
+  z[g] = covered ? s : r[g];
 }
 
-hipError_t combine(const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
+hipError_t combine(const double* r, const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
                    const int* dvoff, const double* dscale, const double* yl, const double* Z,
                    const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
                    int use_coarse, double* z, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(k_combine, dim3((ndof + 255) / 256), dim3(256), 0, st, optr, olist, sub_ptr,
+  hipLaunchKernelGGL(k_combine, dim3((ndof + 255) / 256), dim3(256), 0, st, r, optr, olist, sub_ptr,
                      dmap, dvoff, dscale, yl, Z, zoff, m, coff, yH, ndof, use_coarse, z, done);
   return hipGetLastError();
 }

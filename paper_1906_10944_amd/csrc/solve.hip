@@ -37,88 +37,152 @@ template <> struct Seg16<double> {
   }
 };
 
+// Vector of four loaded as a unit from a tile row.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+  static __device__ __forceinline__ void load(const float* p, double* o) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <> struct Vec4<double> {
+  static __device__ __forceinline__ void load(const double* p, double* o) {
+    double2 u = reinterpret_cast<const double2*>(p)[0];
+    double2 v = reinterpret_cast<const double2*>(p)[1];
+    o[0] = u.x; o[1] = u.y; o[2] = v.x; o[3] = v.y;
+  }
+};
+
+// t_i = sum_{k<=i} X_ik x_k: lane (row l/2, half l%2) owns 16 entries of a
+// tile row; two tiles per iteration keep more loads in flight.
 template <typename T>
-__global__ __launch_bounds__(64) void k_trmv_lower(const T* __restrict__ X,
-                                                   const int64_t* __restrict__ toff,
+__device__ __forceinline__ void trmv_lower_job(const T* __restrict__ Xj, int i,
+                                               const double* __restrict__ xv,
+                                               double* __restrict__ tv, int lane) {
+  const int row = lane >> 1, half = lane & 1;
+  const T* Xr = Xj + tile_idx(i, 0) * TSQ + row * TS + half * 16;
+  const double* xh = xv + half * 16;
+  double s0 = 0.0, s1 = 0.0;
+  int k = 0;
+  for (; k + 1 <= i; k += 2) {
+    double m0[16], m1[16];
+    Seg16<T>::load(Xr + (int64_t)k * TSQ, m0);
+    Seg16<T>::load(Xr + (int64_t)(k + 1) * TSQ, m1);
+    const double* x0 = xh + k * TS;
+    const double* x1 = x0 + TS;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      s0 += m0[q] * x0[q];
+      s1 += m1[q] * x1[q];
+    }
+  }
+  if (k <= i) {
+    double m0[16];
+    Seg16<T>::load(Xr + (int64_t)k * TSQ, m0);
+    const double* x0 = xh + k * TS;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s0 += m0[q] * x0[q];
+  }
+  double s = s0 + s1;
+  s += __shfl_xor(s, 1);
+  if (half == 0) tv[i * TS + row] = s;
+}
+
+// y_k = sum_{i>=k} X_ik^T t_i: lane (column group l%8, row l/8) loads four
+// 4-column row pieces (rows l/8 + 8m) of each tile with vector loads and
+// the 8 lanes of a column group are reduced at the end.
+template <typename T>
+__device__ __forceinline__ void trmv_upperT_job(const T* __restrict__ Xj, int k, int nt,
+                                                const double* __restrict__ tv,
+                                                double* __restrict__ yv, int lane) {
+  const int cg = lane & 7, r0 = lane >> 3;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = k; i < nt; ++i) {
+    const T* tile = Xj + tile_idx(i, k) * TSQ + cg * 4;
+    const double* ti = tv + i * TS;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = r0 + 8 * m;
+      double v[4];
+      Vec4<T>::load(tile + r * TS, v);
+      const double tr = ti[r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[q] += v[q] * tr;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    s[q] += __shfl_xor(s[q], 8);
+    s[q] += __shfl_xor(s[q], 16);
+    s[q] += __shfl_xor(s[q], 32);
+  }
+  if (r0 == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yv[k * TS + cg * 4 + q] = s[q];
+  }
+}
+
+// One launch for all subdomains: jobs[y] = (subdomain, 1 if its inverse
+// factor is FP64); blockIdx.x = tile row (lower) or tile column (upperT).
+__global__ __launch_bounds__(64) void k_trmv_lower(const float* __restrict__ X32,
+                                                   const double* __restrict__ X64,
+                                                   const int64_t* __restrict__ toff32,
+                                                   const int64_t* __restrict__ toff64,
                                                    const int* __restrict__ ntl,
                                                    const int* __restrict__ voff,
-                                                   const int* __restrict__ jobs,
+                                                   const int2* __restrict__ jobs,
                                                    const double* __restrict__ xin,
                                                    double* __restrict__ tout,
                                                    const int* __restrict__ done) {
   if (done && *done) return;
-  const int j = jobs[blockIdx.y];
-  const int i = blockIdx.x;
+  const int2 jb = jobs[blockIdx.y];
+  const int j = jb.x, i = blockIdx.x;
   const int nt = ntl[j];
   if (i >= nt) return;
-  const int lane = threadIdx.x, row = lane >> 1, half = lane & 1;
-  const T* Xr = X + (toff[j] + tile_idx(i, 0)) * TSQ + row * TS + half * 16;
-  const double* xv = xin + voff[j] + half * 16;
-  double s = 0.0;
-  for (int k = 0; k <= i; ++k) {
-    double m[16];
-    Seg16<T>::load(Xr + (int64_t)k * TSQ, m);
-    const double* xk = xv + k * TS;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += m[q] * xk[q];
-  }
-  s += __shfl_xor(s, 1);
-  if (half == 0) tout[voff[j] + i * TS + row] = s;
+  const double* xv = xin + voff[j];
+  double* tv = tout + voff[j];
+  if (jb.y) trmv_lower_job<double>(X64 + toff64[j] * TSQ, i, xv, tv, threadIdx.x);
+  else trmv_lower_job<float>(X32 + toff32[j] * TSQ, i, xv, tv, threadIdx.x);
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_trmv_upperT(const T* __restrict__ X,
-                                                    const int64_t* __restrict__ toff,
+__global__ __launch_bounds__(64) void k_trmv_upperT(const float* __restrict__ X32,
+                                                    const double* __restrict__ X64,
+                                                    const int64_t* __restrict__ toff32,
+                                                    const int64_t* __restrict__ toff64,
                                                     const int* __restrict__ ntl,
                                                     const int* __restrict__ voff,
-                                                    const int* __restrict__ jobs,
+                                                    const int2* __restrict__ jobs,
                                                     const double* __restrict__ tin,
                                                     double* __restrict__ yout,
                                                     const int* __restrict__ done) {
   if (done && *done) return;
-  const int j = jobs[blockIdx.y];
-  const int k = blockIdx.x;
+  const int2 jb = jobs[blockIdx.y];
+  const int j = jb.x, k = blockIdx.x;
   const int nt = ntl[j];
   if (k >= nt) return;
-  const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
-  const T* base = X + toff[j] * TSQ + (h * 16) * TS + c;
-  const double* tv = tin + voff[j] + h * 16;
-  double s = 0.0;
-  for (int i = k; i < nt; ++i) {
-    const T* tile = base + tile_idx(i, k) * TSQ;
-    const double* ti = tv + i * TS;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) s += (double)tile[r * TS] * ti[r];
-  }
-  s += __shfl_xor(s, 32);
-  if (h == 0) yout[voff[j] + k * TS + c] = s;
+  const double* tv = tin + voff[j];
+  double* yv = yout + voff[j];
+  if (jb.y) trmv_upperT_job<double>(X64 + toff64[j] * TSQ, k, nt, tv, yv, threadIdx.x);
+  else trmv_upperT_job<float>(X32 + toff32[j] * TSQ, k, nt, tv, yv, threadIdx.x);
 }
 
-hipError_t trmv_lower(bool fp32, const void* X, const int64_t* toff, const int* nt,
-                      const int* voff, const int* jobs, int njobs, int maxnt, const double* xin,
-                      double* tout, const int* done, hipStream_t st) {
+hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
+                      const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
+                      int njobs, int maxnt, const double* xin, double* tout, const int* done,
+                      hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  dim3 grid(maxnt, njobs);
-  if (fp32)
-    hipLaunchKernelGGL(k_trmv_lower<float>, grid, dim3(64), 0, st, (const float*)X, toff, nt,
-                       voff, jobs, xin, tout, done);
-  else
-    hipLaunchKernelGGL(k_trmv_lower<double>, grid, dim3(64), 0, st, (const double*)X, toff, nt,
-                       voff, jobs, xin, tout, done);
+  hipLaunchKernelGGL(k_trmv_lower, dim3(maxnt, njobs), dim3(64), 0, st, X32, X64, toff32, toff64,
+                     nt, voff, jobs, xin, tout, done);
   return hipGetLastError();
 }
 
-hipError_t trmv_upperT(bool fp32, const void* X, const int64_t* toff, const int* nt,
-                       const int* voff, const int* jobs, int njobs, int maxnt, const double* tin,
-                       double* yout, const int* done, hipStream_t st) {
+hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff32,
+                       const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
+                       int njobs, int maxnt, const double* tin, double* yout, const int* done,
+                       hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  dim3 grid(maxnt, njobs);
-  if (fp32)
-    hipLaunchKernelGGL(k_trmv_upperT<float>, grid, dim3(64), 0, st, (const float*)X, toff, nt,
-                       voff, jobs, tin, yout, done);
-  else
-    hipLaunchKernelGGL(k_trmv_upperT<double>, grid, dim3(64), 0, st, (const double*)X, toff, nt,
-                       voff, jobs, tin, yout, done);
+  hipLaunchKernelGGL(k_trmv_upperT, dim3(maxnt, njobs), dim3(64), 0, st, X32, X64, toff32,
+                     toff64, nt, voff, jobs, tin, yout, done);
   return hipGetLastError();
 }
 
@@ -264,7 +328,7 @@ hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* t
 }
 
 // Y = X_j A^o_j X_j X over the padded N_j rows (zero on padding).
-__global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
+__global__ __launch_bounds__(1024) void k_bapply(const int* __restrict__ sub_ptr,
                                                 const double* __restrict__ pou,
                                                 const int* __restrict__ rp,
                                                 const int* __restrict__ colx,
@@ -300,7 +364,7 @@ __global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
 hipError_t launch_bapply(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
                          const int* voff, const int* nt, int nsub, int b, const double* X,
                          double* Y, const int* active, hipStream_t st) {
-  hipLaunchKernelGGL(k_bapply, dim3(nsub), dim3(256), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
+  hipLaunchKernelGGL(k_bapply, dim3(nsub), dim3(1024), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
                      Ao->val, voff, nt, b, X, Y, active);
   return hipGetLastError();
 }

@@ -1,0 +1,80 @@
+"""Serving loop: results are identical alone and in the concurrent mix, and
+admission keeps the device-memory estimate under the budget."""
+import numpy as np
+import pytest
+
+from gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(t_scale):
+    import synth
+    from paper_1906_10944_amd.serve import Request
+    probs = [
+        synth.config2_grf(seed=3, n=64, parts=2, ovl=2, inclusions=2),
+        synth.config3_layers(seed=4, n=24, parts=2, ovl=1, nev=6),
+        synth.config2_grf(seed=5, n=96, parts=3, ovl=2, inclusions=3),
+        synth.config1_channels(seed=6, n=64, parts=2, n_channels=3, nev=4, precision="mixed"),
+    ]
+    reqs, rid, t = [], 0, 0.0
+    for p in probs:
+        reqs.append(Request(t, rid, "new", problem=p))
+        rid += 1
+        t += t_scale
+    rng = np.random.Generator(np.random.PCG64(9))
+    for src in (0, 2):
+        p = reqs[src].problem
+        reqs.append(Request(t, rid, "repeat", problem=p, op_id=reqs[src].rid,
+                            rhs=rng.normal(size=(2, p.ndof))))
+        rid += 1
+        t += t_scale
+    return reqs
+
+
+def _run(slots, t_scale, budget=64 << 30):
+    from paper_1906_10944_amd.serve import Server
+    srv = Server(budget, slots=slots, keep_solutions=True)
+    reqs = _stream(t_scale)
+    stats = srv.run(reqs)
+    out = {r.rid: r.result for r in srv.done}
+    errors = list(srv.errors)
+    srv.close()
+    return out, stats, errors
+
+
+def test_alone_equals_mixed():
+    need_gpu()
+    alone, st1, e1 = _run(slots=1, t_scale=0.0)
+    mixed, st2, e2 = _run(slots=3, t_scale=0.0)
+    say("[serve] alone", st1)
+    say("[serve] mixed", st2)
+    assert not e1 and not e2, (e1, e2)
+    assert sorted(alone) == sorted(mixed)
+    for rid in alone:
+        a, m = alone[rid], mixed[rid]
+        assert np.all(a["converged"]) and np.all(m["converged"])
+        assert a["iters"] == m["iters"], rid
+        assert np.array_equal(a["x"], m["x"]), rid
+
+
+def test_admission_respects_budget():
+    need_gpu()
+    from paper_1906_10944_amd.serve import footprint_bytes
+    reqs = _stream(0.0)
+    biggest = max(footprint_bytes(r.problem) for r in reqs if r.kind == "new")
+    budget = int(1.3 * biggest)
+    out, stats, errors = _run(slots=3, t_scale=0.0, budget=budget)
+    say("[serve] small budget", stats)
+    assert not errors
+    assert stats["peak_bytes"] <= budget
+    assert stats["requests"] == len(reqs)
+
+
+def test_oversized_request_is_rejected():
+    need_gpu()
+    from paper_1906_10944_amd.serve import Server
+    srv = Server(1 << 20, slots=1)
+    with pytest.raises(RuntimeError):
+        srv.run(_stream(0.0)[:1])
+    srv.close()
