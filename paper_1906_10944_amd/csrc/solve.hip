@@ -6,10 +6,13 @@
 //    column); loads are whole 64-byte row segments (lower) or coalesced row
 //    reads by 32 lanes (transposed); accumulation in FP64.  These stream
 //    the factors once each and are HBM-bound.
-//  * k_trsm_fwd / k_trsm_bwd: X = G^{-1} R and X = G^{-T} R with b right-hand
-//    sides for the shift-and-invert eigen sweeps (FP64, one workgroup per
-//    subdomain, blocked substitution with the inverted diagonal tiles and
-//    MFMA quadrant products split over tile slices).
+//  * k_trsm_win: X = G^{-1} R and X = G^{-T} R with b <= 32 right-hand sides
+//    for the shift-and-invert eigen sweeps (FP64, one workgroup per
+//    subdomain): windows of 16 tile rows held in registers, a left-looking
+//    update from the finished rows, then right-looking substitution inside
+//    the window with the inverted diagonal tiles.
+//  * k_trsm_fwd / k_trsm_bwd: the same solves row by row for wider blocks
+//    (inner sums split over tile slices, reduced in LDS).
 //  * k_bapply: Y = X_j A^o_j X_j X (the B-matrix of the GenEO eigenproblem).
 #include "internal.h"
 
@@ -311,9 +314,245 @@ __global__ __launch_bounds__(1024) void k_trsm_bwd(const double* __restrict__ G,
   }
 }
 
+// ----------------------------------------- windowed multi-RHS substitution ---
+// Forward G X = R and backward G^T X = R for the eigen sweeps, one
+// workgroup of 8 wavefronts per subdomain.  The tile rows are taken in
+// windows of TRW_W = 16; the 32 x b blocks of the current window stay in
+// registers as matrix-core accumulators (wavefront w owns window rows
+// w and w + 8).  Each window first takes its update from all finished rows
+// (left-looking; factor tiles streamed with the next one prefetched, no
+// barriers), then is solved right-looking: the owner of row i forms
+// X_i = Dinv_i acc_i (or Dinv_i^T acc_i) and publishes it, transposed, in
+// LDS; after one barrier every wavefront subtracts G_ki X_i (G_ik^T X_i)
+// from its later rows.  b = 16 * NCQ right-hand sides, b <= 32 (wider
+// blocks take the row-by-row kernels above: their accumulators would not
+// fit in registers).
+#define TRW_NW 8
+#define TRW_MR 2
+#define TRW_W (TRW_NW * TRW_MR)
+
+struct F8 { double v[8]; };
+
+// A-operand fragment of rows r0..r0+15 of a tile: lane (fi, fg) takes
+// row r0 + fi, columns 8 fg .. 8 fg + 7 (plain), or the transposed tile
+// (column r0 + fi, rows 8 fg ..) (tr).
+__device__ __forceinline__ void afrag(F8& f, const double* t, int r0, int fi, int fg) {
+  const double2* p = reinterpret_cast<const double2*>(t + (r0 + fi) * TS + 8 * fg);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double2 a = p[u];
+    f.v[2 * u] = a.x;
+    f.v[2 * u + 1] = a.y;
+  }
+}
+__device__ __forceinline__ void afrag_tr(F8& f, const double* t, int r0, int fi, int fg) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) f.v[s] = t[(8 * fg + s) * TS + r0 + fi];
+}
+// B-operand fragment of a 32 x b block stored row-major with stride b in
+// memory: lane (fi, fg) takes column c0 + fi, rows 8 fg .. 8 fg + 7.
+__device__ __forceinline__ void bfrag_g(F8& f, const double* x, int b, int c0, int fi, int fg) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) f.v[s] = x[(8 * fg + s) * b + c0 + fi];
+}
+// ... and from the transposed LDS copy sT[col][row] (row stride TRW_LD).
+#define TRW_LD (TS + 2)
+__device__ __forceinline__ void bfrag_s(F8& f, const double* sT, int c0, int fi, int fg) {
+  const double2* p = reinterpret_cast<const double2*>(sT + (c0 + fi) * TRW_LD + 8 * fg);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double2 a = p[u];
+    f.v[2 * u] = a.x;
+    f.v[2 * u + 1] = a.y;
+  }
+}
+
+// acc[.][cq] += A B_cq for one column quadrant cq.
+template <int NCQ>
+__device__ __forceinline__ void trw_mma(d4_t (&acc)[2][NCQ], const F8 (&a)[2], const F8& bf, int cq) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int rq = 0; rq < 2; ++rq)
+      acc[rq][cq] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rq].v[s], bf.v[s], acc[rq][cq], 0, 0, 0);
+}
+
+// Owner step: X_i = D acc_i, D = Dinv_i (BWD: Dinv_i^T); acc_i goes through
+// LDS (transposed) to become the B operand; X_i is written to global memory
+// and, transposed, to sXo.
+template <int NCQ, bool BWD>
+__device__ __forceinline__ void trw_finish(const d4_t (&acc)[2][NCQ], const double* Dt, double* sTmp,
+                                           double* sXo, double* Xi, int b, int lane) {
+  const int fi = lane & 15, fg = lane >> 4;
+#pragma unroll
+  for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+    for (int cq = 0; cq < NCQ; ++cq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        sTmp[(cq * 16 + acc_col(lane)) * TRW_LD + rq * 16 + acc_row<double>(lane, v)] = acc[rq][cq][v];
+  wave_sync();
+  F8 a[2];
+#pragma unroll
+  for (int rq = 0; rq < 2; ++rq) {
+    if (BWD) afrag_tr(a[rq], Dt, rq * 16, fi, fg);
+    else afrag(a[rq], Dt, rq * 16, fi, fg);
+  }
+  d4_t o[2][NCQ];
+#pragma unroll
+  for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+    for (int cq = 0; cq < NCQ; ++cq) o[rq][cq] = acc_zero<double>();
+#pragma unroll
+  for (int cq = 0; cq < NCQ; ++cq) {
+    F8 bf;
+    bfrag_s(bf, sTmp, cq * 16, fi, fg);
+    trw_mma<NCQ>(o, a, bf, cq);
+  }
+#pragma unroll
+  for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+    for (int cq = 0; cq < NCQ; ++cq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rq * 16 + acc_row<double>(lane, v), c = cq * 16 + acc_col(lane);
+        sXo[c * TRW_LD + r] = o[rq][cq][v];
+        Xi[r * b + c] = o[rq][cq][v];
+      }
+}
+
+template <int NCQ, bool BWD>
+__global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restrict__ G,
+                                                         const double* __restrict__ dinv,
+                                                         const int64_t* __restrict__ toff,
+                                                         const int64_t* __restrict__ doff,
+                                                         const int* __restrict__ ntl,
+                                                         const int* __restrict__ voff,
+                                                         const double* __restrict__ R,
+                                                         double* __restrict__ X,
+                                                         const int* __restrict__ active) {
+  constexpr int b = 16 * NCQ;
+  const int j = blockIdx.x;
+  if (active && !active[j]) return;
+  __shared__ __align__(16) double sTmp[b * TRW_LD];
+  __shared__ __align__(16) double sX[2][b * TRW_LD];
+  const int nt = ntl[j];
+  const double* Gj = G + toff[j] * TSQ;
+  const double* Dj = dinv + doff[j] * TSQ;
+  const double* Rj = R + (int64_t)voff[j] * b;
+  double* Xj = X + (int64_t)voff[j] * b;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int fi = lane & 15, fg = lane >> 4;
+  const int nwin = (nt + TRW_W - 1) / TRW_W;
+  for (int wi = 0; wi < nwin; ++wi) {
+    // window rows [p0, p1); BWD windows run from the bottom
+    const int p0 = BWD ? max(0, nt - (wi + 1) * TRW_W) : wi * TRW_W;
+    const int p1 = BWD ? nt - wi * TRW_W : min(nt, p0 + TRW_W);
+    d4_t acc[TRW_MR][2][NCQ];
+    int krow[TRW_MR];
+#pragma unroll
+    for (int m = 0; m < TRW_MR; ++m) {
+      krow[m] = p0 + w + TRW_NW * m;
+      const bool own = krow[m] < p1;
+#pragma unroll
+      for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[m][rq][cq][v] = own ? Rj[((int64_t)krow[m] * TS + rq * 16 + acc_row<double>(lane, v)) * b +
+                                         cq * 16 + acc_col(lane)]
+                                    : 0.0;
+    }
+    // ---- left-looking update from the finished rows
+    // FWD: acc_k -= sum_{jj < p0} G_k,jj X_jj      BWD: acc_k -= sum_{jj >= p1} G_jj,k^T X_jj
+    const int jlo = BWD ? p1 : 0, jhi = BWD ? nt : p0;
+#pragma unroll
+    for (int m = 0; m < TRW_MR; ++m) {
+      const int k = krow[m];
+      if (k >= p1 || jlo >= jhi) continue;
+      const double* t0 = BWD ? Gj + tile_idx(jlo, k) * TSQ : Gj + tile_idx(k, jlo) * TSQ;
+      F8 a[2];
+      auto load = [&](const double* t, F8 (&aa)[2]) {
+#pragma unroll
+        for (int rq = 0; rq < 2; ++rq) {
+          if (BWD) afrag_tr(aa[rq], t, rq * 16, fi, fg);
+          else afrag(aa[rq], t, rq * 16, fi, fg);
+#pragma unroll
+          for (int s = 0; s < 8; ++s) aa[rq].v[s] = -aa[rq].v[s];
+        }
+      };
+      load(t0, a);
+      for (int jj = jlo; jj < jhi; ++jj) {
+        const int jn = min(jj + 1, jhi - 1);
+        F8 a1[2];
+        load(BWD ? Gj + tile_idx(jn, k) * TSQ : Gj + tile_idx(k, jn) * TSQ, a1);
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) {
+          F8 bf;
+          bfrag_g(bf, Xj + (int64_t)jj * TS * b, b, cq * 16, fi, fg);
+          trw_mma<NCQ>(acc[m], a, bf, cq);
+        }
+#pragma unroll
+        for (int rq = 0; rq < 2; ++rq) a[rq] = a1[rq];
+      }
+    }
+    // ---- right-looking solve inside the window
+    for (int st = 0; st < p1 - p0; ++st) {
+      const int i = BWD ? p1 - 1 - st : p0 + st;
+      const int li = i - p0, ow = li % TRW_NW, om = li / TRW_NW;
+      double* sXo = sX[st & 1];
+      if (w == ow) {
+#pragma unroll
+        for (int m = 0; m < TRW_MR; ++m)
+          if (m == om)
+            trw_finish<NCQ, BWD>(acc[m], Dj + (int64_t)i * TSQ, sTmp, sXo,
+                                 Xj + (int64_t)i * TS * b, b, lane);
+      }
+      block_sync();
+#pragma unroll
+      for (int m = 0; m < TRW_MR; ++m) {
+        const int k = krow[m];
+        if (k >= p1 || (BWD ? k >= i : k <= i)) continue;
+        const double* t = BWD ? Gj + tile_idx(i, k) * TSQ : Gj + tile_idx(k, i) * TSQ;
+        F8 a[2];
+#pragma unroll
+        for (int rq = 0; rq < 2; ++rq) {
+          if (BWD) afrag_tr(a[rq], t, rq * 16, fi, fg);
+          else afrag(a[rq], t, rq * 16, fi, fg);
+#pragma unroll
+          for (int s = 0; s < 8; ++s) a[rq].v[s] = -a[rq].v[s];
+        }
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) {
+          F8 bf;
+          bfrag_s(bf, sXo, cq * 16, fi, fg);
+          trw_mma<NCQ>(acc[m], a, bf, cq);
+        }
+      }
+    }
+    block_sync();
+  }
+}
+
+template <bool BWD>
+static hipError_t launch_trsm_win(const double* G, const double* dinv, const int64_t* toff,
+                                  const int64_t* doff, const int* nt, const int* voff, int nsub,
+                                  int b, const double* R, double* X, const int* active,
+                                  hipStream_t st) {
+  const dim3 grid(nsub), blk(TRW_NW * 64);
+  switch (b) {
+    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active); break;
+    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, hipStream_t st) {
+  if (b <= 32) return launch_trsm_win<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
   hipLaunchKernelGGL(k_trsm_fwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
                      R, X, active);
   return hipGetLastError();
@@ -322,6 +561,7 @@ hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* t
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, hipStream_t st) {
+  if (b <= 32) return launch_trsm_win<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
   hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
                      R, X, active);
   return hipGetLastError();

@@ -79,4 +79,10 @@ SMALL_PROBLEMS = {
     "laminate_small": lambda: synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1), nev=8),
     "layered_neumann_sides": lambda: synth.layered_2d(n=40, parts=4, ovl=2, layers=8,
                                                       contrast=1e6, nev=4),
+    # threshold rule with nev_max = 16: eigen block of 32 columns, the block
+    # width of the 512^2 Darcy workload
+    "grf_threshold": lambda: synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2),
+    # nev = 24: eigen block of 48 columns
+    "layered_wide_block": lambda: synth.layered_2d(n=32, parts=2, ovl=1, layers=4,
+                                                   contrast=1e4, nev=24),
 }

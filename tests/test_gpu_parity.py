@@ -77,6 +77,18 @@ def solved(case):
     return g, h, info
 
 
+def _kappa_local(A, subs):
+    """Largest condition number of the diagonally scaled local Dirichlet
+    matrices (the matrices both sides factor)."""
+    k = 1.0
+    for s in subs:
+        AD = geneo.dirichlet_matrix(A, s)
+        d = 1.0 / np.sqrt(np.diag(AD))
+        ev = np.linalg.eigvalsh(AD * d[:, None] * d[None, :])
+        k = max(k, ev[-1] / ev[0])
+    return k
+
+
 def test_one_level_apply(case):
     name, prob, A, b, subs, sysm = case
     g = geneo.setup(prob, A=A, subs=subs, coarse=False)
@@ -85,7 +97,12 @@ def test_one_level_apply(case):
     r = rng.normal(size=prob.ndof)
     z = gpu_apply(h, sysm, r)
     zo = g.apply_one_level(r)
-    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    # both sides solve with a backward-stable FP64 factorisation of the same
+    # scaled matrices: each forward error is O(u kappa), so they may differ
+    # by that much (10 u kappa, floor 1e-12)
+    tol = max(1e-12, 10 * np.finfo(float).eps / 2 * _kappa_local(A, subs))
+    say("[one-level] rel diff %.3e tol %.3e" % (np.linalg.norm(z - zo) / np.linalg.norm(zo), tol))
+    assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
 
 
 def _cut_gap(lam, m):
