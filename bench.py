@@ -37,7 +37,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (elementwise x*1): the "
+                         "reference kernel for scaling HBM traffic counters")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain elementwise copy of known size (reads and writes 1 GiB each)."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe": {"read_bytes": 8 * n, "write_bytes": 8 * n,
+                                     "launches": 3}}))
 
 
 def make_problem(name, seed):
@@ -142,24 +158,76 @@ def kernel_profile(runner, precision):
     return prof
 
 
-def roofline(prof):
-    """Dominant kernel by event time, against its bound."""
-    name = max(prof, key=lambda k: prof[k]["ms"])
+# kernel symbol of each event-timed launch site (as rocprofv3 names it)
+PROF_SYMBOL = {"densify_dirichlet": "k_densify_dirichlet", "chol_dirichlet_f32": "k_potrf_local_f32",
+               "chol_dirichlet_f64": "k_potrf_local_f64", "trtri_dirichlet": "k_trtri<float>",
+               "densify_shifted": "k_densify_shifted", "chol_shifted_f64": "k_potrf_shifted_f64",
+               "trsm_bwd": "k_trsm_win<2, true>", "trsm_fwd": "k_trsm_win<2, false>",
+               "bapply": "k_bapply", "rayleigh_ritz": "rayleigh-ritz kernels",
+               "orth": "orthonormalisation kernels",
+               "coarse_chol": "k_cpotrf", "trmv_lower": "k_trmv_lower",
+               "trmv_upperT": "k_trmv_upperT"}
+APPLY_KERNELS = ("trmv_lower", "trmv_upperT")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_darcy512_mixed.json")
+
+
+def measured_traffic(symbol):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(symbol)
+    if not k:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+def roofline(prof, iters):
+    """The kernel with the largest time per step, against its bound.
+
+    Per-step time: average launch time x launches per step.  The apply
+    kernels run once per PCG iteration (inside the captured graph, where
+    launches are not event-timed: their average comes from eager applies);
+    the setup kernels run as often as in the profiled step."""
+    per_step = {}
+    for k, p in prof.items():
+        if not p["launches"]:
+            continue
+        avg = p["ms"] / p["launches"]
+        n = iters + 1 if k in APPLY_KERNELS else p["launches"]
+        per_step[k] = avg * n
+    name = max(per_step, key=per_step.get)
     p = prof[name]
-    avg_ms = p["ms"] / max(p["launches"], 1)
+    avg_ms = p["ms"] / p["launches"]
     compute_bound = name.startswith("chol") or name.startswith("trtri") or name == "coarse_chol"
     if compute_bound:
         peak = FP32_MFMA_PEAK_TFLOPS if name.endswith("f32") else FP64_PEAK_TFLOPS
-        achieved = p["flops"] / max(p["launches"], 1) / (avg_ms * 1e-3) / 1e12
+        achieved = p["flops"] / p["launches"] / (avg_ms * 1e-3) / 1e12
         rf = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     else:
-        achieved = p["bytes"] / max(p["launches"], 1) / (avg_ms * 1e-3) / 1e9
+        achieved = p["bytes"] / p["launches"] / (avg_ms * 1e-3) / 1e9
         rf = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     rf["frac"] = rf["achieved"] / rf["peak"]
-    rf["traffic"] = None
-    rf["kernel"] = name
+    sym = PROF_SYMBOL.get(name, name)
+    rf["traffic"] = measured_traffic(sym)
+    rf["kernel"] = sym
     rf["avg_launch_ms"] = avg_ms
-    rf["launches"] = p["launches"]
+    rf["algorithmic_bytes_per_launch"] = p["bytes"] / p["launches"]
+    rf["algorithmic_flops_per_launch"] = p["flops"] / p["launches"]
+    rf["per_step_ms_estimate"] = {k: round(v, 3) for k, v in sorted(per_step.items(),
+                                                                      key=lambda kv: -kv[1])}
     return rf
 
 
@@ -224,6 +292,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported"
                           % args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import torch
     from paper_1906_10944_amd import geneo as G
     G.lib()
@@ -261,7 +332,7 @@ def main():
                             "solve_ms": inf64[-1]["t_solve_ms"]}
         out["speedup_vs_fp64_form"] = ms64 / ms
     prof = kernel_profile(runner, mixed)
-    out["roofline"] = roofline(prof)
+    out["roofline"] = roofline(prof, last["iters"])
     out["kernels_ms"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, last["iters"], args.cpu_budget_s)

@@ -123,8 +123,12 @@ struct geneo_handle_s {
   DBuf<int2> olist;
   // coarse space
   int nc = 0, ntc = 0, b = 0;
-  DBuf<int> m, zoff, coff, hnt, hvoff;
-  DBuf<int2> hjob, ljobs;  // trmv job lists: (matrix, 1 if FP64)
+  DBuf<int> m, zoff, coff, hnt;
+  // apply job list of the triangular products: (subdomain, 1 if its factor
+  // is FP64) for every subdomain, then (nsub, 2) for the coarse factor
+  DBuf<int2> ajobs;
+  std::vector<int2> ljobs_host;
+  int najobs = 0, amaxnt = 0;
   DBuf<int64_t> htoff;
   DBuf<double> Z, XH, rH, tH, yH, AHdense;
   std::vector<int> m_host, nd_host, nN_host, sub_ptr_host;
@@ -137,7 +141,7 @@ struct geneo_handle_s {
   DBuf<PcgScalars> sc;
   DBuf<int> done;
   int lpr = 8;
-  double bytes_trmv32 = 0.0, bytes_trmv64 = 0.0;  // algorithmic bytes per launch
+  double bytes_trmv32 = 0.0, bytes_trmv64 = 0.0, bytes_trmvH = 0.0;  // algorithmic bytes per launch
   std::vector<int> f64list;                         // subdomains with FP64 local factors
   geneo_setup_info_t info{};
   ~geneo_handle_s() {
@@ -156,28 +160,23 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
                          hipStream_t st) {
   hipError_t e;
   if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
-  const double lb = h->bytes_trmv32 + h->bytes_trmv64;
+  if (h->nc > 0 &&
+      (e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
+                           h->coff.p, h->nsub, h->rH.p, done, st)))
+    return e;
+  const double lb = h->bytes_trmv32 + h->bytes_trmv64 + h->bytes_trmvH;
   {
     ProfScope ps("trmv_lower", st, lb, 0.0);
     if ((e = trmv_lower(h->X32.p, h->X64.p, h->toffD.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                        h->ljobs.p, h->nsub, h->LD.maxnt, h->xl.p, h->tl.p, done, st)))
+                        h->ajobs.p, h->najobs, h->amaxnt, h->xl.p, h->tl.p, h->XH.p, h->ntc,
+                        h->rH.p, h->tH.p, done, st)))
       return e;
   }
   {
     ProfScope ps("trmv_upperT", st, lb, 0.0);
     if ((e = trmv_upperT(h->X32.p, h->X64.p, h->toffD.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                         h->ljobs.p, h->nsub, h->LD.maxnt, h->tl.p, h->yl.p, done, st)))
-      return e;
-  }
-  if (h->nc > 0) {
-    if ((e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
-                             h->coff.p, h->nsub, h->rH.p, done, st)))
-      return e;
-    if ((e = trmv_lower(nullptr, h->XH.p, h->htoff.p, h->htoff.p, h->hnt.p, h->hvoff.p,
-                        h->hjob.p, 1, h->ntc, h->rH.p, h->tH.p, done, st)))
-      return e;
-    if ((e = trmv_upperT(nullptr, h->XH.p, h->htoff.p, h->htoff.p, h->hnt.p, h->hvoff.p,
-                         h->hjob.p, 1, h->ntc, h->tH.p, h->yH.p, done, st)))
+                         h->ajobs.p, h->najobs, h->amaxnt, h->tl.p, h->yl.p, h->XH.p, h->ntc,
+                         h->tH.p, h->yH.p, done, st)))
       return e;
   }
   return combine(r, h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
@@ -266,7 +265,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     }
     {
       ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * pk, fl);
-      HIPCHK(launch_chol_batched(true, X.L32.p, h->toffD.p, h->ntD.p, X.D32.p, h->doffD.p,
+      HIPCHK(launch_chol_batched(CholRole::LocalF32, X.L32.p, h->toffD.p, h->ntD.p, X.D32.p, h->doffD.p,
                                  X.status.p, X.jobs.p, nsub, o.pivot_tol, st));
     }
     auto stat = download(X.status.p, nsub, st);
@@ -312,7 +311,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     std::vector<char> f(nsub, 0);
     for (int j : f64list) f[j] = 1;
     for (int j = 0; j < nsub; ++j) lj[j] = make_int2(j, f[j]);
-    h->ljobs.upload(lj, st);
+    h->ljobs_host = lj;
   }
   if (!f64list.empty()) {
     X.L64.alloc(tt * TSQ);
@@ -330,7 +329,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     }
     {
       ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
-      HIPCHK(launch_chol_batched(false, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p, h->doff64.p,
+      HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p, h->doff64.p,
                                  X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
     }
     std::vector<int2> tj;
@@ -413,7 +412,7 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   }
   {
     ProfScope ps("chol_shifted_f64", sb, 2.0 * 8.0 * pkN, flN);
-    HIPCHK(launch_chol_batched(false, X.G.p, X.toffN.p, X.ntN.p, X.DG.p, X.doffN.p, X.status2.p,
+    HIPCHK(launch_chol_batched(CholRole::ShiftedF64, X.G.p, X.toffN.p, X.ntN.p, X.DG.p, X.doffN.p, X.status2.p,
                                X.jobsN.p, nsub, 0.0, sb));
   }
   tm[0].stop(sb);
@@ -556,10 +555,9 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(coarse_cholesky(X.AHt.p, X.DH.p, h->ntc, X.cst.p, sb));
     }
     if (download(X.cst.p, 1, sb)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
-    h->hjob.upload(std::vector<int2>{make_int2(0, 1)}, sb);
     h->hnt.upload(std::vector<int>{h->ntc}, sb);
-    h->hvoff.upload(std::vector<int>{0}, sb);
     h->htoff.upload(std::vector<int64_t>{0}, sb);
+    h->bytes_trmvH = 8.0 * tri_tiles(h->ntc) * TSQ + 16.0 * h->ntc * TS;
     X.hdoff.upload(std::vector<int64_t>{0}, sb);
     std::vector<int2> tj;
     for (int c = 0; c < h->ntc; ++c) tj.push_back(make_int2(0, c));
@@ -673,6 +671,13 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     if (!h->coff.p) h->coff.upload(std::vector<int>(nsub + 1, 0), st);
     if (!h->Z.p) h->Z.alloc(1);
     h->yH.alloc(1);
+  }
+  {
+    std::vector<int2> aj = h->ljobs_host;
+    if (h->nc > 0) aj.push_back(make_int2(nsub, 2));
+    h->ajobs.upload(aj, st);
+    h->najobs = (int)aj.size();
+    h->amaxnt = std::max(h->LD.maxnt, h->nc > 0 ? h->ntc : 0);
   }
   HIPCHK(hipStreamSynchronize(st));
   h->info.t_phase_ms[0] = tm0.ms();

@@ -1,6 +1,6 @@
 // Dense Cholesky factorisations on the matrix cores (16x16x4 MFMA).
 //
-//  * k_potrf: batched blocked left-looking factorisation, one workgroup of
+//  * k_potrf_*: batched blocked left-looking factorisation, one workgroup of
 //    8 wavefronts per local matrix, panels of two 32-wide tile columns.
 //    Bulk update of a panel with every finished column to its left: a work
 //    item is the 16-row half of one tile row and produces its slab of both
@@ -375,14 +375,11 @@ __device__ __forceinline__ void bulk_direct(T* A, int nt, int k0, int kn, int w,
 }
 
 template <typename T, int NW, int KB, bool STAGED>
-__global__ __launch_bounds__(NW * 64) void k_potrf(T* __restrict__ tiles,
-                                                   const int64_t* __restrict__ toff,
-                                                   const int* __restrict__ ntl,
-                                                   T* __restrict__ dinv,
-                                                   const int64_t* __restrict__ doff,
-                                                   int* __restrict__ status,
-                                                   const int* __restrict__ jobs,
-                                                   double pivtol) {
+__device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t* __restrict__ toff,
+                                           const int* __restrict__ ntl, T* __restrict__ dinv,
+                                           const int64_t* __restrict__ doff,
+                                           int* __restrict__ status, const int* __restrict__ jobs,
+                                           double pivtol) {
   typedef PotrfCfg<T, NW, KB> Cfg;
   typedef typename Mfma<T>::acc Acc;
   constexpr int LDI = Cfg::LDI;
@@ -471,16 +468,47 @@ __global__ __launch_bounds__(NW * 64) void k_potrf(T* __restrict__ tiles,
   if (tid == 0) status[j] = 0;
 }
 
-hipError_t launch_chol_batched(bool fp32, void* tiles, const int64_t* toff, const int* nt,
+// One entry point per role, so that traces and profiles tell them apart:
+// local Dirichlet factors (FP32, or FP64 for the subdomains that fail the
+// FP32 pivot test) and the shifted Neumann factors of the eigensolver.
+__global__ __launch_bounds__(512) void k_potrf_local_f32(float* tiles, const int64_t* toff,
+                                                         const int* nt, float* dinv,
+                                                         const int64_t* doff, int* status,
+                                                         const int* jobs, double pivtol) {
+  potrf_body<float, 8, 2, false>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+}
+__global__ __launch_bounds__(512) void k_potrf_local_f64(double* tiles, const int64_t* toff,
+                                                         const int* nt, double* dinv,
+                                                         const int64_t* doff, int* status,
+                                                         const int* jobs, double pivtol) {
+  potrf_body<double, 8, 2, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+}
+__global__ __launch_bounds__(512) void k_potrf_shifted_f64(double* tiles, const int64_t* toff,
+                                                           const int* nt, double* dinv,
+                                                           const int64_t* doff, int* status,
+                                                           const int* jobs, double pivtol) {
+  potrf_body<double, 8, 2, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+}
+
+hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
                                void* dinv, const int64_t* doff, int* status, const int* jobs,
                                int njobs, double pivtol, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  if (fp32)
-    hipLaunchKernelGGL((k_potrf<float, 8, 2, false>), dim3(njobs), dim3(512), 0, st,
-                       (float*)tiles, toff, nt, (float*)dinv, doff, status, jobs, pivtol);
-  else
-    hipLaunchKernelGGL((k_potrf<double, 8, 2, true>), dim3(njobs), dim3(512), 0, st,
-                       (double*)tiles, toff, nt, (double*)dinv, doff, status, jobs, pivtol);
+  const dim3 grid(njobs), blk(512);
+  switch (role) {
+    case CholRole::LocalF32:
+      hipLaunchKernelGGL(k_potrf_local_f32, grid, blk, 0, st, (float*)tiles, toff, nt,
+                         (float*)dinv, doff, status, jobs, pivtol);
+      break;
+    case CholRole::LocalF64:
+      hipLaunchKernelGGL(k_potrf_local_f64, grid, blk, 0, st, (double*)tiles, toff, nt,
+                         (double*)dinv, doff, status, jobs, pivtol);
+      break;
+    case CholRole::ShiftedF64:
+      hipLaunchKernelGGL(k_potrf_shifted_f64, grid, blk, 0, st, (double*)tiles, toff, nt,
+                         (double*)dinv, doff, status, jobs, pivtol);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int*
                                   double sigma, hipStream_t st);
 
 // -------------------------------------------------------------- chol.hip
-hipError_t launch_chol_batched(bool fp32, void* tiles, const int64_t* toff, const int* nt,
+enum class CholRole { LocalF32, LocalF64, ShiftedF64 };
+hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
                                void* dinv, const int64_t* doff, int* status, const int* jobs,
                                int njobs, double pivtol, hipStream_t st);
 hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
@@ -62,15 +63,17 @@ hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
-// jobs[] = (subdomain, 1 if its inverse factor is FP64 in X64 else FP32 in X32).
+// jobs[] = (subdomain, 1 if its inverse factor is FP64 in X64 else FP32 in
+// X32), or (., 2) for the coarse inverse factor XH with vectors xH -> tH
+// (lower) and tH -> yH (upperT).
 hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
                       const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                      int njobs, int maxnt, const double* xin, double* tout, const int* done,
-                      hipStream_t st);
+                      int njobs, int maxnt, const double* xin, double* tout, const double* XH,
+                      int ntc, const double* xH, double* tH, const int* done, hipStream_t st);
 hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff32,
                        const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                       int njobs, int maxnt, const double* tin, double* yout, const int* done,
-                       hipStream_t st);
+                       int njobs, int maxnt, const double* tin, double* yout, const double* XH,
+                       int ntc, const double* tH, double* yH, const int* done, hipStream_t st);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,

@@ -1,8 +1,8 @@
 // Triangular products and solves with the packed tile factors.
 //
 //  * k_trmv_lower / k_trmv_upperT: t = X x and y = X^T t for the inverse
-//    factors X = L^{-1} of the local Dirichlet matrices (and of the coarse
-//    matrix).  One wavefront per (matrix, tile row) resp. (matrix, tile
+//    factors X = L^{-1} of the local Dirichlet matrices and of the coarse
+//    matrix, all in one launch.  One wavefront per (matrix, tile row) resp. (matrix, tile
 //    column); loads are whole 64-byte row segments (lower) or coalesced row
 //    reads by 32 lanes (transposed); accumulation in FP64.  These stream
 //    the factors once each and are HBM-bound.
@@ -125,8 +125,10 @@ __device__ __forceinline__ void trmv_upperT_job(const T* __restrict__ Xj, int k,
   }
 }
 
-// One launch for all subdomains: jobs[y] = (subdomain, 1 if its inverse
-// factor is FP64); blockIdx.x = tile row (lower) or tile column (upperT).
+// One launch for all subdomains and the coarse problem: jobs[y] = (j, kind)
+// with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse factor (vectors
+// at voff[j]) and kind 2 = the coarse inverse factor XH (ntc tile rows,
+// vectors xH / tH); blockIdx.x = tile row (lower) or tile column (upperT).
 __global__ __launch_bounds__(64) void k_trmv_lower(const float* __restrict__ X32,
                                                    const double* __restrict__ X64,
                                                    const int64_t* __restrict__ toff32,
@@ -136,10 +138,17 @@ __global__ __launch_bounds__(64) void k_trmv_lower(const float* __restrict__ X32
                                                    const int2* __restrict__ jobs,
                                                    const double* __restrict__ xin,
                                                    double* __restrict__ tout,
+                                                   const double* __restrict__ XH, int ntc,
+                                                   const double* __restrict__ xH,
+                                                   double* __restrict__ tH,
                                                    const int* __restrict__ done) {
   if (done && *done) return;
   const int2 jb = jobs[blockIdx.y];
   const int j = jb.x, i = blockIdx.x;
+  if (jb.y == 2) {
+    if (i < ntc) trmv_lower_job<double>(XH, i, xH, tH, threadIdx.x);
+    return;
+  }
   const int nt = ntl[j];
   if (i >= nt) return;
   const double* xv = xin + voff[j];
@@ -157,10 +166,17 @@ __global__ __launch_bounds__(64) void k_trmv_upperT(const float* __restrict__ X3
                                                     const int2* __restrict__ jobs,
                                                     const double* __restrict__ tin,
                                                     double* __restrict__ yout,
+                                                    const double* __restrict__ XH, int ntc,
+                                                    const double* __restrict__ tH,
+                                                    double* __restrict__ yH,
                                                     const int* __restrict__ done) {
   if (done && *done) return;
   const int2 jb = jobs[blockIdx.y];
   const int j = jb.x, k = blockIdx.x;
+  if (jb.y == 2) {
+    if (k < ntc) trmv_upperT_job<double>(XH, k, ntc, tH, yH, threadIdx.x);
+    return;
+  }
   const int nt = ntl[j];
   if (k >= nt) return;
   const double* tv = tin + voff[j];
@@ -171,21 +187,21 @@ __global__ __launch_bounds__(64) void k_trmv_upperT(const float* __restrict__ X3
 
 hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
                       const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                      int njobs, int maxnt, const double* xin, double* tout, const int* done,
-                      hipStream_t st) {
+                      int njobs, int maxnt, const double* xin, double* tout, const double* XH,
+                      int ntc, const double* xH, double* tH, const int* done, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_trmv_lower, dim3(maxnt, njobs), dim3(64), 0, st, X32, X64, toff32, toff64,
-                     nt, voff, jobs, xin, tout, done);
+                     nt, voff, jobs, xin, tout, XH, ntc, xH, tH, done);
   return hipGetLastError();
 }
 
 hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff32,
                        const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                       int njobs, int maxnt, const double* tin, double* yout, const int* done,
-                       hipStream_t st) {
+                       int njobs, int maxnt, const double* tin, double* yout, const double* XH,
+                       int ntc, const double* tH, double* yH, const int* done, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_trmv_upperT, dim3(maxnt, njobs), dim3(64), 0, st, X32, X64, toff32,
-                     toff64, nt, voff, jobs, tin, yout, done);
+                     toff64, nt, voff, jobs, tin, yout, XH, ntc, tH, yH, done);
   return hipGetLastError();
 }
 
