@@ -86,6 +86,7 @@ class Runner:
                "kappa_est": info["kappa_est"], "t_solve_ms": info["t_solve_ms"],
                "t_setup_ms": sinfo["t_setup_ms"], "nc": sinfo["nc"],
                "eig_sweeps": sinfo["eig_sweeps"], "fallback_fp64": sinfo["fallback_fp64"],
+               "eig_stalled": sinfo["eig_stalled"], "eig_max_resid": sinfo["eig_max_resid"],
                "t_phase_ms": sinfo["t_phase_ms"]}
         self.last = (sysm, h, x)
         return out
@@ -319,7 +320,8 @@ def main():
                    "seed": args.seed},
         "iters": last["iters"], "converged": bool(last["converged"]),
         "relres": last["relres"], "true_relres": tres, "kappa_est": last["kappa_est"],
-        "nc": last["nc"], "eig_sweeps": last["eig_sweeps"],
+        "nc": last["nc"], "eig_sweeps": last["eig_sweeps"], "eig_stalled": last["eig_stalled"],
+        "eig_max_resid": last["eig_max_resid"],
         "fallback_fp64": last["fallback_fp64"],
         "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
         "setup_phase_ms": last["t_phase_ms"][:6],

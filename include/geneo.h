@@ -35,7 +35,8 @@ enum {
   GENEO_ERR_ARG = 1,            /* invalid argument or inconsistent sizes */
   GENEO_ERR_OOM = 2,            /* device allocation failed */
   GENEO_ERR_LOCAL_NOT_SPD = 3,  /* a local Dirichlet matrix failed its FP64 Cholesky */
-  GENEO_ERR_EIGEN_NOCONV = 4,   /* eigen sweeps hit eig_maxit before eig_tol */
+  GENEO_ERR_EIGEN_NOCONV = 4,   /* eigen sweeps hit eig_maxit before eig_tol
+                                   (or a stagnation above eig_floor) */
   GENEO_ERR_COARSE_NOT_SPD = 5, /* the coarse matrix A_H failed its Cholesky */
   GENEO_ERR_MAXIT = 6,          /* PCG stopped at maxit; x and info are filled */
   GENEO_ERR_HIP = 7,            /* a HIP runtime call failed */
@@ -182,11 +183,17 @@ typedef struct {
   int eig_block;      /* block size (multiple of 16, <= 64); 0 = automatic */
   uint64_t seed;      /* seed of the start block of the subspace iteration */
   int coarse;         /* 1: two-level method (Def. 2); 0: one level only */
+  int eig_stall;      /* > 0: a subdomain whose largest wanted residual has
+                         not halved for eig_stall sweeps (rounding floor of
+                         its shifted solves, or a ratio close to 1) stops if
+                         that residual is <= eig_floor * ||S|| (and counts in
+                         geneo_setup_info_t.eig_stalled).  0 disables. */
+  double eig_floor;   /* largest residual accepted at such a stagnation */
 } geneo_opts_t;
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-10, eig_maxit 300,
- * eig_block 0, seed 0, coarse 1. */
+ * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;
@@ -233,6 +240,7 @@ typedef struct {
                              factors, 3 eigen sweeps, 4 basis + Galerkin,
                              5 coarse factor, 6-7 reserved */
   int64_t bytes_local_factors;  /* bytes of the inverse local factors */
+  int eig_stalled;        /* subdomains stopped at their rounding floor */
 } geneo_setup_info_t;
 
 int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);

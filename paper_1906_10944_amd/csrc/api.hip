@@ -208,7 +208,8 @@ struct SetupScratch {
   DBuf<int64_t> toffN, doffN, hdoff;
   DBuf<float> L32, D32;
   DBuf<double> L64, D64, G, DG, U, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
-  DBuf<int> ebad;
+  DBuf<int> ebad, scount, sflag;
+  DBuf<double> sbest;
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
   DBuf<uint8_t> adj;
   DBuf<int> ocount;
@@ -445,6 +446,18 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   wk.M = X.eM.p;
   wk.part = X.epart.p;
   wk.badcol = X.ebad.p;
+  EigStall stl;
+  X.sbest.alloc(nsub);
+  X.scount.alloc(nsub);
+  X.sflag.alloc(nsub);
+  HIPCHK(hipMemsetAsync(X.sbest.p, 0x7f, nsub * sizeof(double), sb));  // ~1.4e306
+  HIPCHK(hipMemsetAsync(X.scount.p, 0, nsub * sizeof(int), sb));
+  HIPCHK(hipMemsetAsync(X.sflag.p, 0, nsub * sizeof(int), sb));
+  stl.best = X.sbest.p;
+  stl.count = X.scount.p;
+  stl.stalled = X.sflag.p;
+  stl.sweeps = o.eig_stall;
+  stl.floor = o.eig_floor;
   HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, 0, nullptr, wk, sb));
   int sweeps = 0, nact = nsub;
   std::vector<int> act(nsub, 1);
@@ -477,7 +490,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("rayleigh_ritz", sb, 2.0 * vb, 0.0);
       HIPCHK(launch_rr2(X.U.p, X.T.p, X.Y.p, X.theta.p, X.resid.p, X.active.p, X.voffN.p,
-                        X.ntN.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, o.eig_tol, wk, sb));
+                        X.ntN.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, o.eig_tol, wk, stl,
+                        sb));
     }
     sweeps = it;
     act = download(X.active.p, nsub, sb);
@@ -490,9 +504,24 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     }
   }
   h->info.eig_sweeps = sweeps;
-  if (nact > 0)
-    fail(GENEO_ERR_EIGEN_NOCONV, std::to_string(nact) + " subdomains did not converge in " +
-                                     std::to_string(o.eig_maxit) + " sweeps");
+  {
+    auto fl = download(X.sflag.p, nsub, sb);
+    int c = 0;
+    for (int v : fl) c += v != 0;
+    h->info.eig_stalled = c;
+  }
+  if (nact > 0) {
+    auto best = download(X.sbest.p, nsub, sb);
+    int jw = -1;
+    for (int j = 0; j < nsub; ++j)
+      if (act[j] && (jw < 0 || best[j] > best[jw])) jw = j;
+    char msg[256];
+    snprintf(msg, sizeof msg,
+             "%d subdomains did not converge in %d sweeps (subdomain %d: smallest largest-"
+             "wanted Ritz residual %.3e of ||S||, eig_tol %.1e, eig_floor %.1e)",
+             nact, o.eig_maxit, jw, best[jw], o.eig_tol, o.eig_floor);
+    fail(GENEO_ERR_EIGEN_NOCONV, msg);
+  }
   // eigenvectors p = G^{-T} y
   HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b, X.Y.p,
                          X.T.p, nullptr, sb));
@@ -836,6 +865,8 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->eig_block = 0;
   o->seed = 0;
   o->coarse = 1;
+  o->eig_stall = 10;
+  o->eig_floor = 1e-6;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -899,7 +930,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "invalid eigenvector count");
     if (o.eig_block && (o.eig_block % 16 || o.eig_block > 64))
       fail(GENEO_ERR_ARG, "eig_block must be a multiple of 16 up to 64");
-    if (o.eig_maxit < 1 || !(o.eig_tol > 0)) fail(GENEO_ERR_ARG, "invalid eigen tolerances");
+    if (o.eig_maxit < 1 || !(o.eig_tol > 0) || o.eig_stall < 0 || !(o.eig_floor >= 0))
+      fail(GENEO_ERR_ARG, "invalid eigen tolerances");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     return GENEO_OK;

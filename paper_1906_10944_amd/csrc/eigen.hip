@@ -402,7 +402,7 @@ __global__ __launch_bounds__(64) void k_ritz_check(const double* __restrict__ pa
                                                    double* __restrict__ resid,
                                                    int* __restrict__ active, int b, int nev,
                                                    double tau, int nev_max, double sigma,
-                                                   double tol) {
+                                                   double tol, EigStall stl) {
   const int j = blockIdx.x;
   if (!active[j]) return;
   __shared__ double rr[EIG_MAXB];
@@ -431,8 +431,28 @@ __global__ __launch_bounds__(64) void k_ritz_check(const double* __restrict__ pa
   if (want > nfin) want = nfin;
   if (want > b) want = b;
   bool ok = true;
-  for (int q = 0; q < want; ++q) ok = ok && (rr[q] <= tol * t0);
-  if (ok) active[j] = 0;
+  double rmax = 0.0;
+  for (int q = 0; q < want; ++q) {
+    ok = ok && (rr[q] <= tol * t0);
+    rmax = fmax(rmax, t0 > 0.0 ? rr[q] / t0 : 0.0);
+  }
+  if (ok) {
+    active[j] = 0;
+    return;
+  }
+  // stagnation: the largest wanted residual has not halved for stl.sweeps
+  // sweeps -- the iteration sits at the rounding floor of the shifted solves
+  // or creeps at a ratio close to 1 (a wanted pair inside a dense part of
+  // the spectrum); stop there if the residual is already acceptable
+  if (stl.sweeps > 0) {
+    if (rmax < 0.5 * stl.best[j]) {
+      stl.best[j] = rmax;
+      stl.count[j] = 0;
+    } else if (++stl.count[j] >= stl.sweeps && rmax <= stl.floor) {
+      active[j] = 0;
+      stl.stalled[j] = 1;
+    }
+  }
 }
 
 // Replace the collapsed (zeroed) columns by fresh pseudo-random vectors.
@@ -476,7 +496,7 @@ hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int
 hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, double* resid,
                       int* active, const int* voff, const int* nt, int nsub, int b, int nev,
                       double tau, int nev_max, double sigma, double tol, const EigWork& wk,
-                      hipStream_t st) {
+                      const EigStall& stl, hipStream_t st) {
   hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, W, voff, nt, b, wk.G, active, 1);
   switch (b) {
     case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
@@ -487,7 +507,7 @@ hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, doub
   hipLaunchKernelGGL(k_ritz_update, dim3(wk.ngroups, nsub), dim3(256), 0, st, U, W, Y, wk.M,
                      theta, voff, nt, b, wk.part, wk.ngroups, active);
   hipLaunchKernelGGL(k_ritz_check, dim3(nsub), dim3(64), 0, st, wk.part, wk.ngroups, theta,
-                     resid, active, b, nev, tau, nev_max, sigma, tol);
+                     resid, active, b, nev, tau, nev_max, sigma, tol, stl);
   return hipGetLastError();
 }
 

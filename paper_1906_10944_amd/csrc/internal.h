@@ -99,10 +99,18 @@ struct EigWork {
 hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int b,
                         uint64_t seed, int salt, const int* active, const EigWork& wk,
                         hipStream_t st);
+// Per-subdomain stagnation state of the eigen sweeps (see geneo_opts_t).
+struct EigStall {
+  double* best;  // nsub: smallest largest-wanted-residual so far
+  int* count;    // nsub: sweeps since the last new minimum
+  int* stalled;  // nsub: 1 once stopped at the floor
+  int sweeps;    // 0 disables
+  double floor;
+};
 hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, double* resid,
                       int* active, const int* voff, const int* nt, int nsub, int b, int nev,
                       double tau, int nev_max, double sigma, double tol, const EigWork& wk,
-                      hipStream_t st);
+                      const EigStall& stl, hipStream_t st);
 hipError_t launch_select(const double* theta, int nsub, int b, int nev, double tau,
                          int nev_max, double sigma, int* m, double* lam, hipStream_t st);
 hipError_t launch_basis(const double* P, const int* voff, int b, const int* sub_ptr,

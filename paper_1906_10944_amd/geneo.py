@@ -59,14 +59,16 @@ class Opts(C.Structure):
     _fields_ = [("nev", C.c_int), ("tau", C.c_double), ("nev_max", C.c_int),
                 ("sigma", C.c_double), ("precision", C.c_int), ("pivot_tol", C.c_double),
                 ("eig_tol", C.c_double), ("eig_maxit", C.c_int), ("eig_block", C.c_int),
-                ("seed", C.c_uint64), ("coarse", C.c_int)]
+                ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
+                ("eig_floor", C.c_double)]
 
 
 class SetupInfo(C.Structure):
     _fields_ = [("nsub", C.c_int), ("nc", C.c_int), ("fallback_fp64", C.c_int),
                 ("eig_sweeps", C.c_int), ("eig_block", C.c_int),
                 ("eig_max_resid", C.c_double), ("t_setup_ms", C.c_double),
-                ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64)]
+                ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64),
+                ("eig_stalled", C.c_int)]
 
 
 class PcgInfo(C.Structure):
