@@ -236,6 +236,20 @@ struct PhaseTimer {
   }
 };
 
+// Jobs of the inverse factors: (matrix, first tile column) in blocks of
+// trtri_cols_per_job columns, the longest columns (smallest c0) first.
+std::vector<int2> trtri_job_list(const std::vector<int>& mats, const std::vector<int>& nt,
+                                 bool fp32) {
+  const int ncol = trtri_cols_per_job(fp32);
+  int maxnt = 0;
+  for (int j : mats) maxnt = std::max(maxnt, nt[j]);
+  std::vector<int2> tj;
+  for (int c0 = 0; c0 < maxnt; c0 += ncol)
+    for (int j : mats)
+      if (c0 < nt[j]) tj.push_back(make_int2(j, c0));
+  return tj;
+}
+
 // Local Dirichlet factors A_j = R_j A R_j^T and their inverse factors, on
 // stream st.  Returns after the work is enqueued and the pivot tests are
 // read back.
@@ -276,9 +290,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     h->njobs32 = (int)ok32.size();
     h->jobs32.upload(ok32, st);
     if (!ok32.empty()) {
-      std::vector<int2> tj;
-      for (int j : ok32)
-        for (int c = 0; c < h->LD.nt[j]; ++c) tj.push_back(make_int2(j, c));
+      std::vector<int2> tj = trtri_job_list(ok32, h->LD.nt, true);
       X.tjobs32.upload(tj, st);
       h->X32.alloc(h->LD.ntiles * TSQ);
       double pk32 = 0.0, fl32 = 0.0;
@@ -333,9 +345,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
       HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p, h->doff64.p,
                                  X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
     }
-    std::vector<int2> tj;
-    for (int j : f64list)
-      for (int c = 0; c < h->LD.nt[j]; ++c) tj.push_back(make_int2(j, c));
+    std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
     X.tjobs64.upload(tj, st);
     h->X64.alloc(tt * TSQ);
     ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
@@ -588,12 +598,11 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     h->htoff.upload(std::vector<int64_t>{0}, sb);
     h->bytes_trmvH = 8.0 * tri_tiles(h->ntc) * TSQ + 16.0 * h->ntc * TS;
     X.hdoff.upload(std::vector<int64_t>{0}, sb);
-    std::vector<int2> tj;
-    for (int c = 0; c < h->ntc; ++c) tj.push_back(make_int2(0, c));
+    std::vector<int2> tj = trtri_job_list(std::vector<int>{0}, std::vector<int>{h->ntc}, false);
     X.tjobsH.upload(tj, sb);
     h->XH.alloc(tri_tiles(h->ntc) * TSQ);
     HIPCHK(launch_trtri(false, X.AHt.p, X.DH.p, h->XH.p, h->htoff.p, X.hdoff.p, h->hnt.p,
-                        X.tjobsH.p, h->ntc, sb));
+                        X.tjobsH.p, (int)tj.size(), sb));
     h->rH.alloc((size_t)h->ntc * TS);
     h->tH.alloc((size_t)h->ntc * TS);
     h->yH.alloc((size_t)h->ntc * TS);

@@ -1,21 +1,20 @@
 // Dense Cholesky factorisations on the matrix cores (16x16x4 MFMA).
 //
 //  * k_potrf_*: batched blocked left-looking factorisation, one workgroup of
-//    8 wavefronts per local matrix, panels of two 32-wide tile columns.
+//    8 wavefronts per local matrix, panels of four 32-wide tile columns.
 //    Bulk update of a panel with every finished column to its left: a work
-//    item is the 16-row half of one tile row and produces its slab of both
-//    panel tiles, so each tile L(i, jj) read from memory feeds four
-//    matrix-core products per k-step.  The panel rows L(k0.., jj) that all
-//    items share are read through the caches (FP32) or staged in LDS in
-//    double-buffered chunks (FP64, where they are twice as large).  When
-//    there are fewer items than wavefronts the jj range is split and the
-//    partial sums meet in LDS in a fixed order.  Panel: for each column c
-//    the diagonal tile is factored and inverted by one wavefront in
-//    registers, then L(i, c) = A(i, c) Dinv(c)^T, then the other panel
-//    column takes the rank-32 update from column c.  A failed pivot test
-//    stops that matrix and records 1 + the failing row in `status`.
-//  * k_trtri: X = L^{-1}, one workgroup per (matrix, tile column c): the
-//    column c of X solves L X_c = E_c by blocked forward substitution.
+//    item is the 16-row half of one tile row and produces its slab of all
+//    panel tiles, so each tile L(i, jj) read from memory feeds eight
+//    matrix-core chains per k-step.  The panel rows L(k0.., jj) that all
+//    items share are staged in LDS in double-buffered chunks.  When there
+//    are fewer items than wavefronts the jj range is split and the partial
+//    sums meet in LDS in a fixed order.  Panel: for each column c the
+//    diagonal tile is factored and inverted by one wavefront in registers,
+//    then L(i, c) = A(i, c) Dinv(c)^T, then the later panel columns take
+//    the rank-32 update from column c.  A failed pivot test stops that
+//    matrix and records 1 + the failing row in `status`.
+//  * k_trtri_win: X = L^{-1}, one workgroup per (matrix, block of tile
+//    columns): windowed forward substitution L X(:, C) = E_C on MFMA.
 //  * coarse_cholesky: right-looking tiled factorisation of the single coarse
 //    matrix, one launch per phase (diagonal, panel, trailing update) so that
 //    the trailing update spreads over the whole chip.
@@ -128,7 +127,8 @@ __device__ __noinline__ int diag_tile(const T* D, T* Lout, T* Xout, T (*sX)[LDI]
 template <typename T, int NW, int KB>
 struct PotrfCfg {
   static constexpr int LDI = DiagLd<T>::v;
-  static constexpr int CH = sizeof(T) == 8 ? 2 : 4;  // jj per staged chunk
+  // jj per staged chunk: 4 (FP64) or 8 (FP32) panel tiles per buffer
+  static constexpr int CH = (sizeof(T) == 8 ? 4 : 8) / KB > 0 ? (sizeof(T) == 8 ? 4 : 8) / KB : 1;
   // staged panel rows: [2 buffers][KB][CH][TS][LDI]
   static constexpr int YBUF = KB * CH * TS * LDI;
   static constexpr int STAGE_BYTES = 2 * YBUF * (int)sizeof(T);
@@ -140,7 +140,7 @@ struct PotrfCfg {
   static constexpr int VEC = 16 / (int)sizeof(T);
   static constexpr int NVEC = KB * CH * TSQ / VEC;
   static constexpr int VPT = (NVEC + NW * 64 - 1) / (NW * 64);
-  static_assert(SHARED_BYTES <= 96 * 1024, "panel staging exceeds the LDS budget");
+  static_assert(SHARED_BYTES <= 128 * 1024, "panel staging exceeds the LDS budget");
 };
 
 template <typename T> struct Vec16;
@@ -407,20 +407,25 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
     // ---- panel factorization
     for (int c = k0; c < k0 + kn; ++c) {
       if (c > k0) {
-        // rank-32 update of column c with column c-1 (inside the panel)
-        const int nit = 2 * (nt - c);
+        // rank-32 update of the panel columns c' >= c with column c-1:
+        // A(i, c') -= L(i, c-1) L(c', c-1)^T for i >= c'
+        const int pc = c - 1;
+        int nit = 0;
+        for (int cc = c; cc < k0 + kn; ++cc) nit += 2 * (nt - cc);
         for (int it = w; it < nit; it += NW) {
-          const int i = c + (it >> 1), rq = it & 1;
+          int cc = c, rem = it;
+          while (rem >= 2 * (nt - cc)) rem -= 2 * (nt - cc++);
+          const int i = cc + (rem >> 1), rq = rem & 1;
           V8<T> x, y[2];
-          ld8(x, A + tile_idx(i, c - 1) * TSQ + rq * 16 * TS + frag);
+          ld8(x, A + tile_idx(i, pc) * TSQ + rq * 16 * TS + frag);
 #pragma unroll
-          for (int cq = 0; cq < 2; ++cq) ld8(y[cq], A + tile_idx(c, c - 1) * TSQ + cq * 16 * TS + frag);
+          for (int cq = 0; cq < 2; ++cq) ld8(y[cq], A + tile_idx(cc, pc) * TSQ + cq * 16 * TS + frag);
           Acc acc[2] = {acc_zero<T>(), acc_zero<T>()};
 #pragma unroll
           for (int s = 0; s < 8; ++s)
 #pragma unroll
             for (int cq = 0; cq < 2; ++cq) acc[cq] = Mfma<T>::run(x.v[s], y[cq].v[s], acc[cq]);
-          T* C = A + tile_idx(i, c) * TSQ + rq * 16 * TS;
+          T* C = A + tile_idx(i, cc) * TSQ + rq * 16 * TS;
 #pragma unroll
           for (int cq = 0; cq < 2; ++cq)
 #pragma unroll
@@ -475,19 +480,19 @@ __global__ __launch_bounds__(512) void k_potrf_local_f32(float* tiles, const int
                                                          const int* nt, float* dinv,
                                                          const int64_t* doff, int* status,
                                                          const int* jobs, double pivtol) {
-  potrf_body<float, 8, 2, false>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+  potrf_body<float, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
 }
 __global__ __launch_bounds__(512) void k_potrf_local_f64(double* tiles, const int64_t* toff,
                                                          const int* nt, double* dinv,
                                                          const int64_t* doff, int* status,
                                                          const int* jobs, double pivtol) {
-  potrf_body<double, 8, 2, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+  potrf_body<double, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
 }
 __global__ __launch_bounds__(512) void k_potrf_shifted_f64(double* tiles, const int64_t* toff,
                                                            const int* nt, double* dinv,
                                                            const int64_t* doff, int* status,
                                                            const int* jobs, double pivtol) {
-  potrf_body<double, 8, 2, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+  potrf_body<double, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
 }
 
 hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
@@ -512,50 +517,186 @@ hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, 
   return hipGetLastError();
 }
 
-// X = L^{-1} for tile column c of matrix j (jobs[b] = (j, c)).
-template <typename T>
-__global__ __launch_bounds__(256) void k_trtri(const T* __restrict__ L, const T* __restrict__ dinv,
-                                               T* __restrict__ X, const int64_t* __restrict__ toff,
-                                               const int64_t* __restrict__ doff,
-                                               const int* __restrict__ ntl,
-                                               const int2* __restrict__ jobs) {
-  const int j = jobs[blockIdx.x].x, c = jobs[blockIdx.x].y;
+// ------------------------------------------------------------------------
+// k_trtri_win: X = L^{-1}, one workgroup of 8 wavefronts per (matrix, block
+// of NCT tile columns C = c0 .. c0+NCT-1): forward substitution L X(:, C) =
+// E_C over the rows c0 .. nt-1 (b = 32 NCT right-hand sides).  The rows are
+// taken in windows of 16 tile rows held in registers (wavefront w owns
+// window rows w and w + 8).  Each window first takes its update from the
+// finished rows (left-looking; the tiles L(k, jj) are streamed with the next
+// one prefetched), then is solved right-looking: the owner of row i forms
+// X(i, C) = Dinv(i) acc_i and publishes it, transposed, in LDS; after one
+// barrier every wavefront subtracts L(k, i) X(i, C) from its later rows.
+// Tiles above the diagonal (column tile > row) are zero: never read or
+// written.  Two tile columns per workgroup (FP32) halve the reads of L.
+#define TW_NW 8
+#define TW_MR 2
+#define TW_W (TW_NW * TW_MR)
+
+template <typename T, int NCT>
+__global__ __launch_bounds__(TW_NW * 64) void k_trtri_win(const T* __restrict__ L,
+                                                          const T* __restrict__ dinv,
+                                                          T* __restrict__ X,
+                                                          const int64_t* __restrict__ toff,
+                                                          const int64_t* __restrict__ doff,
+                                                          const int* __restrict__ ntl,
+                                                          const int2* __restrict__ jobs) {
+  typedef typename Mfma<T>::acc Acc;
+  constexpr int NCQ = 2 * NCT, b = 32 * NCT, LDI = DiagLd<T>::v;
+  const int j = jobs[blockIdx.x].x, c0 = jobs[blockIdx.x].y;
   const int nt = ntl[j];
+  if (c0 >= nt) return;
   const T* Lj = L + toff[j] * TSQ;
   const T* Dj = dinv + doff[j] * TSQ;
   T* Xj = X + toff[j] * TSQ;
-  __shared__ T sacc[TS][TS + 1];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int rq = w >> 1, cq = w & 1;
-  for (int e = tid; e < TSQ; e += blockDim.x) Xj[tile_idx(c, c) * TSQ + e] = Dj[(int64_t)c * TSQ + e];
-  block_sync();
-  for (int i = c + 1; i < nt; ++i) {
-    typename Mfma<T>::acc acc = acc_zero<T>();
-    for (int k = c; k < i; ++k)
-      q_xy<T>(acc, Lj + tile_idx(i, k) * TSQ + rq * 16 * TS, TS,
-              Xj + tile_idx(k, c) * TSQ + cq * 16, TS, lane);
+  __shared__ __align__(16) T sTmp[b * LDI];
+  __shared__ __align__(16) T sX[2][b * LDI];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int fi = lane & 15, fg = lane >> 4;
+  auto mma = [&](Acc (&acc)[2][NCQ], const V8<T> (&a)[2], const V8<T>& bf, int cq) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sacc[rq * 16 + acc_row<T>(lane, v)][cq * 16 + acc_col(lane)] = -acc[v];
-    block_sync();
-    typename Mfma<T>::acc o = acc_zero<T>();
-    q_xy<T>(o, Dj + (int64_t)i * TSQ + rq * 16 * TS, TS, &sacc[0][cq * 16], TS + 1, lane);
-    T* out = Xj + tile_idx(i, c) * TSQ + rq * 16 * TS + cq * 16;
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[acc_row<T>(lane, v) * TS + acc_col(lane)] = o[v];
+      for (int rq = 0; rq < 2; ++rq) acc[rq][cq] = Mfma<T>::run(a[rq].v[s], bf.v[s], acc[rq][cq]);
+  };
+  // B fragment of X(jj, C) from memory: column cq*16 + fi of the block,
+  // rows 8 fg .. 8 fg + 7 of tile (jj, c0 + cq / 2); zero above the diagonal
+  auto bfrag_mem = [&](V8<T>& f, int jj, int cq) {
+    const int tc = c0 + (cq >> 1);
+    if (tc > jj) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) f.v[s] = (T)0;
+      return;
+    }
+    const T* t = Xj + tile_idx(jj, tc) * TSQ + (cq & 1) * 16 + fi;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) f.v[s] = t[(8 * fg + s) * TS];
+  };
+  auto bfrag_lds = [&](V8<T>& f, const T* sT, int cq) {
+    const T* p = sT + (cq * 16 + fi) * LDI + 8 * fg;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) f.v[s] = p[s];
+  };
+  auto afrag_neg = [&](V8<T> (&a)[2], const T* t) {
+#pragma unroll
+    for (int rq = 0; rq < 2; ++rq) {
+      ld8(a[rq], t + (rq * 16 + fi) * TS + 8 * fg);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) a[rq].v[s] = -a[rq].v[s];
+    }
+  };
+  for (int p0 = c0; p0 < nt; p0 += TW_W) {
+    const int p1 = min(nt, p0 + TW_W);
+    Acc acc[TW_MR][2][NCQ];
+    int krow[TW_MR];
+#pragma unroll
+    for (int m = 0; m < TW_MR; ++m) {
+      krow[m] = p0 + w + TW_NW * m;
+#pragma unroll
+      for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = rq * 16 + acc_row<T>(lane, v), col = cq * 16 + acc_col(lane);
+            acc[m][rq][cq][v] = (krow[m] == c0 + (col >> 5) && r == (col & 31)) ? (T)1 : (T)0;
+          }
+    }
+    // ---- update from the finished rows c0 .. p0-1
+#pragma unroll
+    for (int m = 0; m < TW_MR; ++m) {
+      const int k = krow[m];
+      if (k >= p1 || p0 == c0) continue;
+      V8<T> a[2];
+      afrag_neg(a, Lj + tile_idx(k, c0) * TSQ);
+      for (int jj = c0; jj < p0; ++jj) {
+        V8<T> a1[2];
+        afrag_neg(a1, Lj + tile_idx(k, min(jj + 1, p0 - 1)) * TSQ);
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) {
+          V8<T> bf;
+          bfrag_mem(bf, jj, cq);
+          mma(acc[m], a, bf, cq);
+        }
+        a[0] = a1[0];
+        a[1] = a1[1];
+      }
+    }
+    // ---- right-looking solve inside the window
+    for (int st = 0; st < p1 - p0; ++st) {
+      const int i = p0 + st, ow = st % TW_NW, om = st / TW_NW;
+      T* sXo = sX[st & 1];
+      if (w == ow) {
+#pragma unroll
+        for (int m = 0; m < TW_MR; ++m) {
+          if (m != om) continue;
+#pragma unroll
+          for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+            for (int cq = 0; cq < NCQ; ++cq)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                sTmp[(cq * 16 + acc_col(lane)) * LDI + rq * 16 + acc_row<T>(lane, v)] = acc[m][rq][cq][v];
+          wave_sync();
+          V8<T> a[2];
+#pragma unroll
+          for (int rq = 0; rq < 2; ++rq) ld8(a[rq], Dj + (int64_t)i * TSQ + (rq * 16 + fi) * TS + 8 * fg);
+          Acc o[2][NCQ];
+#pragma unroll
+          for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+            for (int cq = 0; cq < NCQ; ++cq) o[rq][cq] = acc_zero<T>();
+#pragma unroll
+          for (int cq = 0; cq < NCQ; ++cq) {
+            V8<T> bf;
+            bfrag_lds(bf, sTmp, cq);
+            mma(o, a, bf, cq);
+          }
+#pragma unroll
+          for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+            for (int cq = 0; cq < NCQ; ++cq) {
+              const int tc = c0 + (cq >> 1);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int r = rq * 16 + acc_row<T>(lane, v), col = cq * 16 + acc_col(lane);
+                sXo[col * LDI + r] = o[rq][cq][v];
+                if (tc <= i) Xj[tile_idx(i, tc) * TSQ + r * TS + (col & 31)] = o[rq][cq][v];
+              }
+            }
+        }
+      }
+      block_sync();
+#pragma unroll
+      for (int m = 0; m < TW_MR; ++m) {
+        const int k = krow[m];
+        if (k >= p1 || k <= i) continue;
+        V8<T> a[2];
+        afrag_neg(a, Lj + tile_idx(k, i) * TSQ);
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) {
+          V8<T> bf;
+          bfrag_lds(bf, sXo, cq);
+          mma(acc[m], a, bf, cq);
+        }
+      }
+    }
     block_sync();
   }
 }
+
+int trtri_cols_per_job(bool fp32) { return fp32 ? 2 : 1; }
 
 hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
                         const int64_t* toff, const int64_t* doff, const int* nt,
                         const int2* jobs, int njobs, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_trtri<float>, dim3(njobs), dim3(256), 0, st, (const float*)L,
-                       (const float*)dinv, (float*)X, toff, doff, nt, jobs);
+    hipLaunchKernelGGL((k_trtri_win<float, 2>), dim3(njobs), dim3(TW_NW * 64), 0, st,
+                       (const float*)L, (const float*)dinv, (float*)X, toff, doff, nt, jobs);
   else
-    hipLaunchKernelGGL(k_trtri<double>, dim3(njobs), dim3(256), 0, st, (const double*)L,
-                       (const double*)dinv, (double*)X, toff, doff, nt, jobs);
+    hipLaunchKernelGGL((k_trtri_win<double, 1>), dim3(njobs), dim3(TW_NW * 64), 0, st,
+                       (const double*)L, (const double*)dinv, (double*)X, toff, doff, nt, jobs);
   return hipGetLastError();
 }
 

@@ -55,6 +55,9 @@ enum class CholRole { LocalF32, LocalF64, ShiftedF64 };
 hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
                                void* dinv, const int64_t* doff, int* status, const int* jobs,
                                int njobs, double pivtol, hipStream_t st);
+// jobs[] = (matrix, first tile column c0) with c0 a multiple of
+// trtri_cols_per_job(fp32); tile columns c0 .. c0 + that - 1 are done.
+int trtri_cols_per_job(bool fp32);
 hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
                         const int64_t* toff, const int64_t* doff, const int* nt,
                         const int2* jobs, int njobs, hipStream_t st);

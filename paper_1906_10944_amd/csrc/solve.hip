@@ -2,9 +2,10 @@
 //
 //  * k_trmv_lower / k_trmv_upperT: t = X x and y = X^T t for the inverse
 //    factors X = L^{-1} of the local Dirichlet matrices and of the coarse
-//    matrix, all in one launch.  One wavefront per (matrix, tile row) resp. (matrix, tile
-//    column); loads are whole 64-byte row segments (lower) or coalesced row
-//    reads by 32 lanes (transposed); accumulation in FP64.  These stream
+//    matrix, all in one launch.  One wavefront per (matrix, tile row) resp.
+//    (matrix, tile column), longest first; each step loads a whole tile
+//    as 4-column row pieces (vector loads), prefetching the next tile;
+//    accumulation in FP64.  These stream
 //    the factors once each and are HBM-bound.
 //  * k_trsm_win: X = G^{-1} R and X = G^{-T} R with b <= 32 right-hand sides
 //    for the shift-and-invert eigen sweeps (FP64, one workgroup per
@@ -17,28 +18,6 @@
 #include "internal.h"
 
 namespace geneo {
-
-template <typename T> struct Seg16;
-template <> struct Seg16<float> {
-  static __device__ __forceinline__ void load(const float* p, double* o) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      float4 v = q[u];
-      o[4 * u + 0] = v.x; o[4 * u + 1] = v.y; o[4 * u + 2] = v.z; o[4 * u + 3] = v.w;
-    }
-  }
-};
-template <> struct Seg16<double> {
-  static __device__ __forceinline__ void load(const double* p, double* o) {
-    const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      double2 v = q[u];
-      o[2 * u + 0] = v.x; o[2 * u + 1] = v.y;
-    }
-  }
-};
 
 // Vector of four loaded as a unit from a tile row.
 template <typename T> struct Vec4;
@@ -56,39 +35,47 @@ template <> struct Vec4<double> {
   }
 };
 
-// t_i = sum_{k<=i} X_ik x_k: lane (row l/2, half l%2) owns 16 entries of a
-// tile row; two tiles per iteration keep more loads in flight.
+// t_i = sum_{k<=i} X_ik x_k: lane (column group l%8, row l/8) loads the
+// 4-column pieces of rows l/8 + 8m (m < 4) of each tile with vector loads
+// (a whole tile per wavefront and step), needs only 4 entries of x per
+// tile, and the 8 column groups of a row are reduced once at the end.  The
+// next tile's pieces are loaded before the current ones are used.
 template <typename T>
 __device__ __forceinline__ void trmv_lower_job(const T* __restrict__ Xj, int i,
                                                const double* __restrict__ xv,
                                                double* __restrict__ tv, int lane) {
-  const int row = lane >> 1, half = lane & 1;
-  const T* Xr = Xj + tile_idx(i, 0) * TSQ + row * TS + half * 16;
-  const double* xh = xv + half * 16;
-  double s0 = 0.0, s1 = 0.0;
-  int k = 0;
-  for (; k + 1 <= i; k += 2) {
-    double m0[16], m1[16];
-    Seg16<T>::load(Xr + (int64_t)k * TSQ, m0);
-    Seg16<T>::load(Xr + (int64_t)(k + 1) * TSQ, m1);
-    const double* x0 = xh + k * TS;
-    const double* x1 = x0 + TS;
+  const int cg = lane & 7, r0 = lane >> 3;
+  const T* Xr = Xj + tile_idx(i, 0) * TSQ + r0 * TS + cg * 4;
+  const double* xg = xv + cg * 4;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double a[4][4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      s0 += m0[q] * x0[q];
-      s1 += m1[q] * x1[q];
-    }
-  }
-  if (k <= i) {
-    double m0[16];
-    Seg16<T>::load(Xr + (int64_t)k * TSQ, m0);
-    const double* x0 = xh + k * TS;
+  for (int m = 0; m < 4; ++m) Vec4<T>::load(Xr + 8 * m * TS, a[m]);
+  for (int k = 0; k <= i; ++k) {
+    double nx[4][4];
+    const int kn = k < i ? k + 1 : k;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s0 += m0[q] * x0[q];
+    for (int m = 0; m < 4; ++m) Vec4<T>::load(Xr + (int64_t)kn * TSQ + 8 * m * TS, nx[m]);
+    const double2 x01 = *reinterpret_cast<const double2*>(xg + k * TS);
+    const double2 x23 = *reinterpret_cast<const double2*>(xg + k * TS + 2);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      s[m] += a[m][0] * x01.x + a[m][1] * x01.y + a[m][2] * x23.x + a[m][3] * x23.y;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[m][q] = nx[m][q];
   }
-  double s = s0 + s1;
-  s += __shfl_xor(s, 1);
-  if (half == 0) tv[i * TS + row] = s;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    s[m] += __shfl_xor(s[m], 1);
+    s[m] += __shfl_xor(s[m], 2);
+    s[m] += __shfl_xor(s[m], 4);
+  }
+  if (cg == 0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) tv[i * TS + r0 + 8 * m] = s[m];
+  }
 }
 
 // y_k = sum_{i>=k} X_ik^T t_i: lane (column group l%8, row l/8) loads four
@@ -100,18 +87,27 @@ __device__ __forceinline__ void trmv_upperT_job(const T* __restrict__ Xj, int k,
                                                 double* __restrict__ yv, int lane) {
   const int cg = lane & 7, r0 = lane >> 3;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double a[4][4];
+  const T* t0 = Xj + tile_idx(k, k) * TSQ + cg * 4;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) Vec4<T>::load(t0 + (r0 + 8 * m) * TS, a[m]);
   for (int i = k; i < nt; ++i) {
-    const T* tile = Xj + tile_idx(i, k) * TSQ + cg * 4;
+    double nx[4][4];
+    const int in = i + 1 < nt ? i + 1 : i;
+    const T* tn = Xj + tile_idx(in, k) * TSQ + cg * 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Vec4<T>::load(tn + (r0 + 8 * m) * TS, nx[m]);
     const double* ti = tv + i * TS;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int r = r0 + 8 * m;
-      double v[4];
-      Vec4<T>::load(tile + r * TS, v);
-      const double tr = ti[r];
+      const double tr = ti[r0 + 8 * m];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] += v[q] * tr;
+      for (int q = 0; q < 4; ++q) s[q] += a[m][q] * tr;
     }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[m][q] = nx[m][q];
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -129,7 +125,8 @@ __device__ __forceinline__ void trmv_upperT_job(const T* __restrict__ Xj, int k,
 // with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse factor (vectors
 // at voff[j]) and kind 2 = the coarse inverse factor XH (ntc tile rows,
 // vectors xH / tH); blockIdx.x = tile row (lower) or tile column (upperT).
-__global__ __launch_bounds__(64) void k_trmv_lower(const float* __restrict__ X32,
+#define TRMV_WAVES 1
+__global__ __launch_bounds__(64 * TRMV_WAVES) void k_trmv_lower(const float* __restrict__ X32,
                                                    const double* __restrict__ X64,
                                                    const int64_t* __restrict__ toff32,
                                                    const int64_t* __restrict__ toff64,
@@ -144,20 +141,24 @@ __global__ __launch_bounds__(64) void k_trmv_lower(const float* __restrict__ X32
                                                    const int* __restrict__ done) {
   if (done && *done) return;
   const int2 jb = jobs[blockIdx.y];
-  const int j = jb.x, i = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  // the longest rows go first (row i has i + 1 tiles)
+  const int idx = blockIdx.x * TRMV_WAVES + (threadIdx.x >> 6);
+  const int j = jb.x;
   if (jb.y == 2) {
-    if (i < ntc) trmv_lower_job<double>(XH, i, xH, tH, threadIdx.x);
+    if (idx < ntc) trmv_lower_job<double>(XH, ntc - 1 - idx, xH, tH, lane);
     return;
   }
   const int nt = ntl[j];
-  if (i >= nt) return;
+  if (idx >= nt) return;
+  const int i = nt - 1 - idx;
   const double* xv = xin + voff[j];
   double* tv = tout + voff[j];
-  if (jb.y) trmv_lower_job<double>(X64 + toff64[j] * TSQ, i, xv, tv, threadIdx.x);
-  else trmv_lower_job<float>(X32 + toff32[j] * TSQ, i, xv, tv, threadIdx.x);
+  if (jb.y) trmv_lower_job<double>(X64 + toff64[j] * TSQ, i, xv, tv, lane);
+  else trmv_lower_job<float>(X32 + toff32[j] * TSQ, i, xv, tv, lane);
 }
 
-__global__ __launch_bounds__(64) void k_trmv_upperT(const float* __restrict__ X32,
+__global__ __launch_bounds__(64 * TRMV_WAVES) void k_trmv_upperT(const float* __restrict__ X32,
                                                     const double* __restrict__ X64,
                                                     const int64_t* __restrict__ toff32,
                                                     const int64_t* __restrict__ toff64,
@@ -172,17 +173,18 @@ __global__ __launch_bounds__(64) void k_trmv_upperT(const float* __restrict__ X3
                                                     const int* __restrict__ done) {
   if (done && *done) return;
   const int2 jb = jobs[blockIdx.y];
-  const int j = jb.x, k = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = jb.x, k = blockIdx.x * TRMV_WAVES + (threadIdx.x >> 6);
   if (jb.y == 2) {
-    if (k < ntc) trmv_upperT_job<double>(XH, k, ntc, tH, yH, threadIdx.x);
+    if (k < ntc) trmv_upperT_job<double>(XH, k, ntc, tH, yH, lane);
     return;
   }
   const int nt = ntl[j];
   if (k >= nt) return;
   const double* tv = tin + voff[j];
   double* yv = yout + voff[j];
-  if (jb.y) trmv_upperT_job<double>(X64 + toff64[j] * TSQ, k, nt, tv, yv, threadIdx.x);
-  else trmv_upperT_job<float>(X32 + toff32[j] * TSQ, k, nt, tv, yv, threadIdx.x);
+  if (jb.y) trmv_upperT_job<double>(X64 + toff64[j] * TSQ, k, nt, tv, yv, lane);
+  else trmv_upperT_job<float>(X32 + toff32[j] * TSQ, k, nt, tv, yv, lane);
 }
 
 hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
@@ -190,7 +192,8 @@ hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32
                       int njobs, int maxnt, const double* xin, double* tout, const double* XH,
                       int ntc, const double* xH, double* tH, const int* done, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmv_lower, dim3(maxnt, njobs), dim3(64), 0, st, X32, X64, toff32, toff64,
+  hipLaunchKernelGGL(k_trmv_lower, dim3((maxnt + TRMV_WAVES - 1) / TRMV_WAVES, njobs),
+                     dim3(64 * TRMV_WAVES), 0, st, X32, X64, toff32, toff64,
                      nt, voff, jobs, xin, tout, XH, ntc, xH, tH, done);
   return hipGetLastError();
 }
@@ -200,7 +203,8 @@ hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff3
                        int njobs, int maxnt, const double* tin, double* yout, const double* XH,
                        int ntc, const double* tH, double* yH, const int* done, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmv_upperT, dim3(maxnt, njobs), dim3(64), 0, st, X32, X64, toff32,
+  hipLaunchKernelGGL(k_trmv_upperT, dim3((maxnt + TRMV_WAVES - 1) / TRMV_WAVES, njobs),
+                     dim3(64 * TRMV_WAVES), 0, st, X32, X64, toff32,
                      toff64, nt, voff, jobs, tin, yout, XH, ntc, tH, yH, done);
   return hipGetLastError();
 }
