@@ -490,7 +490,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("bapply", sb, vb, 0.0);
       HIPCHK(launch_bapply(S->sub_ptr, S->pou, Ao, X.voffN.p, X.ntN.p, nsub, b, X.T.p, X.W.p,
-                           X.active.p, sb));
+                           X.active.p, LN.maxnt, sb));
     }
     {
       ProfScope ps("trsm_fwd", sb, gb + vb, tf);

@@ -40,6 +40,7 @@ hipError_t launch_eig_init(double* U, const int* sub_ptr, const int* voff, const
 }
 
 // ------------------------------------------------- small dense helpers ---
+#define JB_THREADS 256  // threads of the per-subdomain small dense kernels
 // Gram matrix sG = X^T Y (b x b) of npad-row blocks, MFMA quadrants split
 // over row-chunk slices, reduced in fixed order.
 __device__ void gram(const double* X, const double* Y, int npad, int b, double (*spart)[256],
@@ -70,59 +71,65 @@ __device__ void gram(const double* X, const double* Y, int npad, int b, double (
   block_sync();
 }
 
-// Cholesky of sG (b x b, unit diagonal expected) by wavefront 0 into its
-// lower triangle; returns a bitmask-free flag array bad[c] = 1 for pivots
-// below `tiny`.  Then sM = L^{-T} (upper triangular).
-__device__ void chol_inv_wave(double (*sG)[EIG_MAXB + 1], double (*sM)[EIG_MAXB + 1], int b,
-                              int* bad, double tiny) {
-  const int lane = threadIdx.x & 63;
+// Cholesky of sG (b x b, unit diagonal expected) into its lower triangle by
+// the whole workgroup (right-looking, two barriers per column); bad[c] = 1
+// for pivots at or below `tiny` (that column of L is zeroed, its diagonal
+// set to 1).  Then sM = L^{-T} (upper triangular), the inverse formed
+// right-looking: row c of X = L^{-1} is finished at step c and the rows
+// below take its rank-1 update.
+__device__ void chol_inv_block(double (*sG)[EIG_MAXB + 1], double (*sM)[EIG_MAXB + 1], int b,
+                               int* bad, double tiny) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  block_sync();
   for (int c = 0; c < b; ++c) {
-    double d = sG[c][c];
-    bool collapse = !(d > tiny);
-    if (lane == 0) bad[c] = collapse ? 1 : 0;
-    double s = collapse ? 1.0 : sqrt(d);
-    wave_sync();
-    if (lane > c && lane < b) sG[lane][c] = collapse ? 0.0 : sG[lane][c] / s;
-    if (lane == c) sG[c][c] = s;
-    wave_sync();
-    for (int e = lane; e < b * b; e += 64) {
-      int r = e / b, q = e % b;
+    const double d = sG[c][c];
+    const bool collapse = !(d > tiny);
+    const double s = collapse ? 1.0 : sqrt(d);
+    block_sync();  // every thread has read the pivot
+    if (tid == 0) bad[c] = collapse ? 1 : 0;
+    if (tid > c && tid < b) sG[tid][c] = collapse ? 0.0 : sG[tid][c] / s;
+    if (tid == c) sG[c][c] = s;
+    block_sync();  // column c is final
+    for (int e = tid; e < b * b; e += nth) {
+      const int r = e / b, q = e % b;
       if (q > c && q <= r) sG[r][q] -= sG[r][c] * sG[q][c];
     }
-    wave_sync();
+    block_sync();  // trailing update done before the next pivot is read
   }
-  // sM[q][t] = (L^{-1})[t][q]  i.e. L^{-T}; lane t solves L x = e_t
-  if (lane < b) {
-    const int t = lane;
-    for (int r = 0; r < b; ++r) {
-      double x = 0.0;
-      if (r >= t) {
-        double s = (r == t) ? 1.0 : 0.0;
-        for (int q = t; q < r; ++q) s -= sG[r][q] * sM[t][q];
-        x = s / sG[r][r];
-      }
-      sM[t][r] = x;  // row t of L^{-T} = column t of L^{-1}
+  // X = L^{-1} kept transposed in sM: sM[q][t] = X[t][q]
+  for (int e = tid; e < b * b; e += nth) sM[e / b][e % b] = (e / b == e % b) ? 1.0 : 0.0;
+  block_sync();
+  for (int c = 0; c < b; ++c) {
+    const double dinv = 1.0 / sG[c][c];
+    if (tid <= c) sM[tid][c] *= dinv;
+    block_sync();
+    for (int e = tid; e < b * b; e += nth) {
+      const int r = e / b, q = e % b;  // X[r][q] -= L[r][c] X[c][q], r > c, q <= c
+      if (r > c && q <= c) sM[q][r] -= sG[r][c] * sM[q][c];
     }
+    block_sync();
   }
-  wave_sync();
 }
 
-// ------------------------------------------------------- Jacobi (wave) ---
+// ------------------------------------------------------ Jacobi (block) ---
 // Eigen-decomposition of the symmetric sH (B x B) by cyclic Jacobi with the
-// round-robin ordering, executed by one wavefront: on return diag(sH) holds
-// the eigenvalues and sQ the eigenvectors (columns).  Rounds whose
-// rotations are all negligible are skipped.
+// round-robin ordering, executed by a workgroup of JB_THREADS threads: on
+// return diag(sH) holds the eigenvalues and sQ the eigenvectors (columns).
+// The B/2 rotations of a round are computed by B/2 threads; the row and
+// column updates are spread over all threads.  Rounds whose rotations are
+// all negligible are skipped.
 template <int B>
-__device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 1],
-                            double* cs_c, double* cs_s, int* pp, int* pq) {
-  const int lane = threadIdx.x & 63;
-  for (int e = lane; e < B * B; e += 64) sQ[e / B][e % B] = (e / B == e % B) ? 1.0 : 0.0;
-  wave_sync();
+__device__ void jacobi_block(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 1],
+                             double* cs_c, double* cs_s, int* pp, int* pq, double* red,
+                             int* sany) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < B * B; e += JB_THREADS) sQ[e / B][e % B] = (e / B == e % B) ? 1.0 : 0.0;
+  block_sync();
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = lane; e < B * B; e += 64) {
-      int r = e / B, c = e % B;
-      double v = sH[r][c];
+    for (int e = tid; e < B * B; e += JB_THREADS) {
+      const int r = e / B, c = e % B;
+      const double v = sH[r][c];
       if (r != c) off += v * v;
       else dia += v * v;
     }
@@ -130,56 +137,66 @@ __device__ void jacobi_wave(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 
       off += __shfl_xor(off, m);
       dia += __shfl_xor(dia, m);
     }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = off;
+      red[2 * (tid >> 6) + 1] = dia;
+    }
+    block_sync();
+    off = dia = 0.0;
+    for (int w = 0; w < JB_THREADS / 64; ++w) {
+      off += red[2 * w];
+      dia += red[2 * w + 1];
+    }
+    block_sync();
     if (off <= 1e-30 * dia || off == 0.0) break;
     for (int round = 0; round < B - 1; ++round) {
-      int rot = 0;
-      if (lane < B / 2) {
-        int i0 = lane, i1 = B - 1 - lane;
+      if (tid == 0) *sany = 0;
+      block_sync();
+      if (tid < B / 2) {
+        const int i0 = tid, i1 = B - 1 - tid;
         int p = i0 == 0 ? 0 : ((i0 - 1 + round) % (B - 1)) + 1;
         int q = ((i1 - 1 + round) % (B - 1)) + 1;
-        if (p > q) { int t = p; p = q; q = t; }
-        double apq = sH[p][q];
-        double app = sH[p][p], aqq = sH[q][q];
-        double c = 1.0, s = 0.0;
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double apq = sH[p][q];
+        const double app = sH[p][p], aqq = sH[q][q];
+        double c = 1.0, sn = 0.0;
         if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) && apq != 0.0) {
-          double tau = (aqq - app) / (2.0 * apq);
-          double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          rot = 1;
+          sn = t * c;
+          *sany = 1;
         }
-        cs_c[lane] = c;
-        cs_s[lane] = s;
-        pp[lane] = p;
-        pq[lane] = q;
+        cs_c[tid] = c;
+        cs_s[tid] = sn;
+        pp[tid] = p;
+        pq[tid] = q;
       }
-      if (!__any(rot)) continue;
-      wave_sync();
+      block_sync();
+      if (!*sany) continue;
       // rows p, q of H
-#pragma unroll 4
-      for (int e = lane; e < (B / 2) * B; e += 64) {
-        int k = e / B, m = e % B;
-        int p = pp[k], q = pq[k];
-        double c = cs_c[k], s = cs_s[k];
-        double hp = sH[p][m], hq = sH[q][m];
-        sH[p][m] = c * hp - s * hq;
-        sH[q][m] = s * hp + c * hq;
+      for (int e = tid; e < (B / 2) * B; e += JB_THREADS) {
+        const int k = e / B, m = e % B;
+        const int p = pp[k], q = pq[k];
+        const double c = cs_c[k], sn = cs_s[k];
+        const double hp = sH[p][m], hq = sH[q][m];
+        sH[p][m] = c * hp - sn * hq;
+        sH[q][m] = sn * hp + c * hq;
       }
-      wave_sync();
+      block_sync();
       // columns p, q of H and of Q
-#pragma unroll 4
-      for (int e = lane; e < (B / 2) * B; e += 64) {
-        int k = e / B, m = e % B;
-        int p = pp[k], q = pq[k];
-        double c = cs_c[k], s = cs_s[k];
-        double hp = sH[m][p], hq = sH[m][q];
-        sH[m][p] = c * hp - s * hq;
-        sH[m][q] = s * hp + c * hq;
-        double qp = sQ[m][p], qq = sQ[m][q];
-        sQ[m][p] = c * qp - s * qq;
-        sQ[m][q] = s * qp + c * qq;
+      for (int e = tid; e < (B / 2) * B; e += JB_THREADS) {
+        const int k = e % (B / 2), m = e / (B / 2);
+        const int p = pp[k], q = pq[k];
+        const double c = cs_c[k], sn = cs_s[k];
+        const double hp = sH[m][p], hq = sH[m][q];
+        sH[m][p] = c * hp - sn * hq;
+        sH[m][q] = sn * hp + c * hq;
+        const double qp = sQ[m][p], qq = sQ[m][q];
+        sQ[m][p] = c * qp - sn * qq;
+        sQ[m][q] = sn * qp + c * qq;
       }
-      wave_sync();
+      block_sync();
     }
   }
 }
@@ -208,10 +225,10 @@ __global__ __launch_bounds__(1024) void k_gram(const double* __restrict__ X,
 // One wavefront per subdomain: Jacobi eigen-decomposition of H_j, columns
 // sorted by descending eigenvalue (stable), into Q_j and theta_j.
 template <int B>
-__global__ __launch_bounds__(64) void k_small_eig(const double* __restrict__ H,
-                                                  double* __restrict__ Q,
-                                                  double* __restrict__ theta,
-                                                  const int* __restrict__ active) {
+__global__ __launch_bounds__(JB_THREADS) void k_small_eig(const double* __restrict__ H,
+                                                          double* __restrict__ Q,
+                                                          double* __restrict__ theta,
+                                                          const int* __restrict__ active) {
   constexpr int b = B;
   const int j = blockIdx.x;
   if (active && !active[j]) return;
@@ -219,12 +236,14 @@ __global__ __launch_bounds__(64) void k_small_eig(const double* __restrict__ H,
   __shared__ double sQ[EIG_MAXB][EIG_MAXB + 1];
   __shared__ double cs_c[EIG_MAXB / 2], cs_s[EIG_MAXB / 2];
   __shared__ int pp[EIG_MAXB / 2], pq[EIG_MAXB / 2], perm[EIG_MAXB];
-  const int lane = threadIdx.x;
+  __shared__ double red[2 * JB_THREADS / 64];
+  __shared__ int sany;
+  const int tid = threadIdx.x;
   const double* Hj = H + (int64_t)j * b * b;
-  for (int e = lane; e < b * b; e += 64) sH[e / b][e % b] = Hj[e];
-  wave_sync();
-  jacobi_wave<B>(sH, sQ, cs_c, cs_s, pp, pq);
-  if (lane == 0) {
+  for (int e = tid; e < b * b; e += JB_THREADS) sH[e / b][e % b] = Hj[e];
+  block_sync();
+  jacobi_block<B>(sH, sQ, cs_c, cs_s, pp, pq, red, &sany);
+  if (tid == 0) {
     for (int c = 0; c < b; ++c) perm[c] = c;
     for (int c = 0; c < b; ++c) {
       int best = c;
@@ -235,13 +254,13 @@ __global__ __launch_bounds__(64) void k_small_eig(const double* __restrict__ H,
       perm[c] = t;
     }
   }
-  wave_sync();
+  block_sync();
   double* Qj = Q + (int64_t)j * b * b;
-  for (int e = lane; e < b * b; e += 64) {
+  for (int e = tid; e < b * b; e += JB_THREADS) {
     int r = e / b, c = e % b;
     Qj[e] = sQ[r][perm[c]];
   }
-  if (lane < b) theta[(int64_t)j * b + lane] = sH[perm[lane]][perm[lane]];
+  if (tid < b) theta[(int64_t)j * b + tid] = sH[perm[tid]][perm[tid]];
 }
 
 // One wavefront per subdomain: Cholesky-QR factor of the Gram matrix G_j of
@@ -249,36 +268,36 @@ __global__ __launch_bounds__(64) void k_small_eig(const double* __restrict__ H,
 // L L^T = diag(s) G diag(s).  A column whose pivot collapses (numerically
 // dependent on the previous ones) gets a zero column in M_j and its flag in
 // badcol[j*b + c].
-__global__ __launch_bounds__(64) void k_small_cholqr(const double* __restrict__ G, int b,
-                                                     double* __restrict__ M,
-                                                     int* __restrict__ badcol,
-                                                     const int* __restrict__ active) {
+__global__ __launch_bounds__(JB_THREADS) void k_small_cholqr(const double* __restrict__ G, int b,
+                                                             double* __restrict__ M,
+                                                             int* __restrict__ badcol,
+                                                             const int* __restrict__ active) {
   const int j = blockIdx.x;
   if (active && !active[j]) return;
   __shared__ double sG[EIG_MAXB][EIG_MAXB + 1];
   __shared__ double sM[EIG_MAXB][EIG_MAXB + 1];
   __shared__ double scl[EIG_MAXB];
   __shared__ int sbad[EIG_MAXB];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   const double* Gj = G + (int64_t)j * b * b;
-  if (lane < b) {
-    double d = Gj[lane * b + lane];
-    scl[lane] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  if (tid < b) {
+    double d = Gj[tid * b + tid];
+    scl[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
-  wave_sync();
-  for (int e = lane; e < b * b; e += 64) {
+  block_sync();
+  for (int e = tid; e < b * b; e += JB_THREADS) {
     int r = e / b, c = e % b;
     sG[r][c] = Gj[e] * scl[r] * scl[c];
   }
-  wave_sync();
-  chol_inv_wave(sG, sM, b, sbad, 1e-10);
+  block_sync();
+  chol_inv_block(sG, sM, b, sbad, 1e-10);
   double* Mj = M + (int64_t)j * b * b;
-  for (int e = lane; e < b * b; e += 64) {
+  for (int e = tid; e < b * b; e += JB_THREADS) {
     int r = e / b, c = e % b;
     const bool badc = sbad[c] || scl[c] == 0.0;
     Mj[e] = badc ? 0.0 : sM[r][c] * scl[r];
   }
-  if (lane < b) badcol[(int64_t)j * b + lane] = (sbad[lane] || scl[lane] == 0.0) ? 1 : 0;
+  if (tid < b) badcol[(int64_t)j * b + tid] = (sbad[tid] || scl[tid] == 0.0) ? 1 : 0;
 }
 
 // X_j <- X_j M_j for 16-row slabs; grid (slab groups, subdomains).
@@ -483,7 +502,7 @@ hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int
   dim3 grid2(wk.ngroups, nsub);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, U, voff, nt, b, wk.G, active, 1);
-    hipLaunchKernelGGL(k_small_cholqr, dim3(nsub), dim3(64), 0, st, wk.G, b, wk.M, wk.badcol,
+    hipLaunchKernelGGL(k_small_cholqr, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, b, wk.M, wk.badcol,
                        active);
     hipLaunchKernelGGL(k_right_mul, grid2, dim3(256), 0, st, U, wk.M, voff, nt, b, active);
     if (pass == 0)
@@ -499,10 +518,10 @@ hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, doub
                       const EigStall& stl, hipStream_t st) {
   hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, W, voff, nt, b, wk.G, active, 1);
   switch (b) {
-    case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
-    case 32: hipLaunchKernelGGL(k_small_eig<32>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
-    case 48: hipLaunchKernelGGL(k_small_eig<48>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
-    default: hipLaunchKernelGGL(k_small_eig<64>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
+    case 32: hipLaunchKernelGGL(k_small_eig<32>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
+    case 48: hipLaunchKernelGGL(k_small_eig<48>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
+    default: hipLaunchKernelGGL(k_small_eig<64>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
   }
   hipLaunchKernelGGL(k_ritz_update, dim3(wk.ngroups, nsub), dim3(256), 0, st, U, W, Y, wk.M,
                      theta, voff, nt, b, wk.part, wk.ngroups, active);

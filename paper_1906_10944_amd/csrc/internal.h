@@ -87,7 +87,7 @@ hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* t
                            hipStream_t st);
 hipError_t launch_bapply(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
                          const int* voff, const int* nt, int nsub, int b, const double* X,
-                         double* Y, const int* active, hipStream_t st);
+                         double* Y, const int* active, int maxnt, hipStream_t st);
 
 // ------------------------------------------------------------- eigen.hip
 hipError_t launch_eig_init(double* U, const int* sub_ptr, const int* voff, const int* nt,

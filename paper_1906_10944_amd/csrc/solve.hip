@@ -588,44 +588,48 @@ hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* t
 }
 
 // Y = X_j A^o_j X_j X over the padded N_j rows (zero on padding).
-__global__ __launch_bounds__(1024) void k_bapply(const int* __restrict__ sub_ptr,
-                                                const double* __restrict__ pou,
-                                                const int* __restrict__ rp,
-                                                const int* __restrict__ colx,
-                                                const double* __restrict__ val,
-                                                const int* __restrict__ voff,
-                                                const int* __restrict__ ntl, int b,
-                                                const double* __restrict__ X,
-                                                double* __restrict__ Y,
-                                                const int* __restrict__ active) {
-  const int j = blockIdx.x;
+// One thread per (row a, column c) of the padded block, a 2D grid over
+// (element chunk, subdomain) so that the dependent index/value/X loads of
+// many rows are in flight at once.
+__global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
+                                               const double* __restrict__ pou,
+                                               const int* __restrict__ rp,
+                                               const int* __restrict__ colx,
+                                               const double* __restrict__ val,
+                                               const int* __restrict__ voff,
+                                               const int* __restrict__ ntl, int b,
+                                               const double* __restrict__ X,
+                                               double* __restrict__ Y,
+                                               const int* __restrict__ active) {
+  const int j = blockIdx.y;
   if (active && !active[j]) return;
-  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
   const int npad = ntl[j] * TS;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npad * b) return;
+  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
   const double* Xj = X + (int64_t)voff[j] * b;
-  double* Yj = Y + (int64_t)voff[j] * b;
-  for (int t = threadIdx.x; t < npad * b; t += blockDim.x) {
-    int a = t / b, c = t % b;
-    double s = 0.0;
-    if (a < n) {
-      double mua = pou[s0 + a];
-      if (mua != 0.0) {
-        for (int p = rp[s0 + a]; p < rp[s0 + a + 1]; ++p) {
-          int q = colx[p];
-          s += val[p] * pou[s0 + q] * Xj[(int64_t)q * b + c];
-        }
-        s *= mua;
+  const int a = t / b, c = t % b;
+  double s = 0.0;
+  if (a < n) {
+    const double mua = pou[s0 + a];
+    if (mua != 0.0) {
+      const int p0 = rp[s0 + a], p1 = rp[s0 + a + 1];
+      for (int p = p0; p < p1; ++p) {
+        const int q = colx[p];
+        s += val[p] * pou[s0 + q] * Xj[(int64_t)q * b + c];
       }
+      s *= mua;
     }
-    Yj[(int64_t)a * b + c] = s;
   }
+  Y[(int64_t)voff[j] * b + t] = s;
 }
 
 hipError_t launch_bapply(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
                          const int* voff, const int* nt, int nsub, int b, const double* X,
-                         double* Y, const int* active, hipStream_t st) {
-  hipLaunchKernelGGL(k_bapply, dim3(nsub), dim3(1024), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
-                     Ao->val, voff, nt, b, X, Y, active);
+                         double* Y, const int* active, int maxnt, hipStream_t st) {
+  const int nel = maxnt * TS * b;
+  hipLaunchKernelGGL(k_bapply, dim3((nel + 255) / 256, nsub), dim3(256), 0, st, sub_ptr, pou,
+                     Ao->rowptr, Ao->col, Ao->val, voff, nt, b, X, Y, active);
   return hipGetLastError();
 }
 
