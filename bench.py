@@ -37,6 +37,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode instead of the step benchmark: a seeded Poisson stream "
+                         "of new problems and repeat solves through serve.Server; prints one "
+                         "JSON line with p50/p99 latency")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (elementwise x*1): the "
                          "reference kernel for scaling HBM traffic counters")
@@ -287,6 +294,41 @@ def cpu_baseline(prob, gpu_iters, budget_s):
             "est_total_s": est}
 
 
+def serve_bench(args):
+    """p50/p99 latency of the serving loop on a seeded stream (2D Darcy of
+    128^2..1024^2 and 3D layered 48^3..96^3 new problems, repeat solves with
+    8 random right-hand sides).  The arrival rate is 0.8 x the single-slot
+    capacity measured first on a closed-loop prefix of the same stream."""
+    from paper_1906_10944_amd import serve as S
+    budget = int(args.serve_budget_gb * (1 << 30))
+    # capacity: the first requests one at a time, all arriving at once
+    probe = S.make_stream(seed=args.seed, count=8, rate=1e9)
+    srv = S.Server(budget, slots=1)
+    t0 = time.perf_counter()
+    srv.run(probe)
+    mean_service = (time.perf_counter() - t0) / len(probe)
+    srv.close()
+    rate = 0.8 / mean_service
+    reqs = S.make_stream(seed=args.seed, count=args.serve_requests, rate=rate)
+    srv = S.Server(budget, slots=args.serve_slots)
+    st = srv.run(reqs)
+    srv.close()
+    kinds = {}
+    for r in reqs:
+        kinds[r.kind] = kinds.get(r.kind, 0) + 1
+    print(json.dumps({
+        "metric": "GenEO serving latency (setup+solve or repeat solve per request)",
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "unit": "ms",
+        "higher_is_better": False, "n_gpus": 1,
+        "requests": st["requests"], "errors": st["errors"], "kinds": kinds,
+        "arrival_rate_per_s": rate, "single_slot_mean_service_ms": mean_service * 1e3,
+        "solves_per_s": st["solves_per_s"], "dof_per_s": st["dof_per_s"],
+        "slots": args.serve_slots, "peak_bytes": st["peak_bytes"], "budget_bytes": budget,
+        "data": "synthetic", "config": {"workload": "serving stream (2D GRF 128^2-1024^2, "
+                                                    "3D layers 48^3-96^3, repeats)",
+                                         "seed": args.seed}}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -295,6 +337,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.serve:
+        serve_bench(args)
         return
     import torch
     from paper_1906_10944_amd import geneo as G
