@@ -143,7 +143,7 @@ def prof_query(G, name):
 PROF_KERNELS = ["densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
                 "trtri_dirichlet", "densify_shifted", "chol_shifted_f64", "trsm_bwd",
                 "trsm_fwd", "bapply", "rayleigh_ritz", "orth", "coarse_chol",
-                "trmv_lower", "trmv_upperT"]
+                "trmv_lower", "trmv_upperT", "chebyshev"]
 
 
 def kernel_profile(runner, precision):

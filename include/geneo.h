@@ -189,11 +189,17 @@ typedef struct {
                          that residual is <= eig_floor * ||S|| (and counts in
                          geneo_setup_info_t.eig_stalled).  0 disables. */
   double eig_floor;   /* largest residual accepted at such a stagnation */
+  int eig_cheb;       /* >= 2: from the third sweep on, the Ritz block is
+                         filtered by the Chebyshev polynomial of this degree
+                         on [0, a] (a = smallest Ritz value of the block)
+                         before it is orthonormalised: eig_cheb - 1 extra
+                         shifted solves per sweep, faster convergence of the
+                         wanted pairs.  0 or 1: plain subspace iteration. */
 } geneo_opts_t;
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-10, eig_maxit 300,
- * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6. */
+ * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;

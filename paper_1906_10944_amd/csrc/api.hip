@@ -207,7 +207,7 @@ struct SetupScratch {
   DBuf<int> status, status2, jobs, jobsN, ntN, voffN, active, pcnt, poff, npairs, woffd, cst;
   DBuf<int64_t> toffN, doffN, hdoff;
   DBuf<float> L32, D32;
-  DBuf<double> L64, D64, G, DG, U, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
+  DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
   DBuf<int> ebad, scount, sflag;
   DBuf<double> sbest;
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
@@ -400,6 +400,7 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   h->b = b;
   h->info.eig_block = b;
   X.U.alloc(LN.nvec * b);
+  if (o.eig_cheb >= 2) X.P.alloc(LN.nvec * b);
   X.W.alloc(LN.nvec * b);
   X.T.alloc(LN.nvec * b);
   X.Y.alloc(LN.nvec * b);
@@ -508,6 +509,27 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     nact = 0;
     for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
     if (nact == 0) break;
+    if (o.eig_cheb >= 2 && it >= 3) {
+      // Chebyshev filter of degree m on the Ritz block Y (kept intact for
+      // the final eigenvectors): U holds S Y from the Rayleigh-Ritz step;
+      // Z_1 = (2/a) S Y - Y goes to U, Z_0 = Y to P, and each further
+      // degree costs one shifted solve; Z_m ends in U.
+      ProfScope ps("chebyshev", sb, 0.0, 0.0);
+      HIPCHK(launch_cheb(X.U.p, nullptr, X.U.p, X.Y.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,
+                         LN.maxnt, true, X.active.p, sb));
+      HIPCHK(hipMemcpyAsync(X.P.p, X.Y.p, X.Y.n * sizeof(double), hipMemcpyDeviceToDevice, sb));
+      for (int k = 1; k < o.eig_cheb; ++k) {
+        HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
+                               X.U.p, X.T.p, X.active.p, sb));
+        HIPCHK(launch_bapply(S->sub_ptr, S->pou, Ao, X.voffN.p, X.ntN.p, nsub, b, X.T.p, X.W.p,
+                             X.active.p, LN.maxnt, sb));
+        HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
+                               X.W.p, X.T.p, X.active.p, sb));
+        HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, X.P.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,
+                           LN.maxnt, false, X.active.p, sb));
+        std::swap(X.U.p, X.P.p);  // Z_{k+1} -> U, Z_k -> P
+      }
+    }
     {
       ProfScope ps("orth", sb, 2.0 * vb, 0.0);
       HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, it, X.active.p, wk, sb));
@@ -876,6 +898,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->coarse = 1;
   o->eig_stall = 10;
   o->eig_floor = 1e-6;
+  o->eig_cheb = 3;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -939,7 +962,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "invalid eigenvector count");
     if (o.eig_block && (o.eig_block % 16 || o.eig_block > 64))
       fail(GENEO_ERR_ARG, "eig_block must be a multiple of 16 up to 64");
-    if (o.eig_maxit < 1 || !(o.eig_tol > 0) || o.eig_stall < 0 || !(o.eig_floor >= 0))
+    if (o.eig_maxit < 1 || !(o.eig_tol > 0) || o.eig_stall < 0 || !(o.eig_floor >= 0) ||
+        o.eig_cheb < 0 || o.eig_cheb > 16)
       fail(GENEO_ERR_ARG, "invalid eigen tolerances");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();

@@ -530,6 +530,39 @@ hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, doub
   return hipGetLastError();
 }
 
+// --------------------------------------------------- Chebyshev filter ---
+// One step of the Chebyshev recurrence on [0, a_j], a_j = the smallest Ritz
+// value of subdomain j's block (theta sorted descending), floored at
+// 1e-14 theta_0:
+//   first  (Zp = Z_0):            Zn = (2/a) SZ - Zp
+//   later  (Zc = Z_k, Zp = Z_k-1): Zn = (4/a) SZ - 2 Zc - Zp
+// elementwise over the padded block; Zn may alias Zp or SZ.
+__global__ __launch_bounds__(256) void k_cheb(double* Zn, const double* Zc, const double* SZ,
+                                              const double* Zp, const double* __restrict__ theta,
+                                              const int* __restrict__ voff,
+                                              const int* __restrict__ ntl, int b, int first,
+                                              const int* __restrict__ active) {
+  const int j = blockIdx.y;
+  if (active && !active[j]) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nel = (int64_t)ntl[j] * TS * b;
+  if (t >= nel) return;
+  const double t0 = theta[(int64_t)j * b];
+  const double a = fmax(theta[(int64_t)j * b + b - 1], 1e-14 * t0);
+  const int64_t e = (int64_t)voff[j] * b + t;
+  if (first) Zn[e] = (2.0 / a) * SZ[e] - Zp[e];
+  else Zn[e] = (4.0 / a) * SZ[e] - 2.0 * Zc[e] - Zp[e];
+}
+
+hipError_t launch_cheb(double* Zn, const double* Zc, const double* SZ, const double* Zp,
+                       const double* theta, const int* voff, const int* nt, int nsub, int b,
+                       int maxnt, bool first, const int* active, hipStream_t st) {
+  const int64_t nel = (int64_t)maxnt * TS * b;
+  hipLaunchKernelGGL(k_cheb, dim3((unsigned)((nel + 255) / 256), nsub), dim3(256), 0, st, Zn, Zc,
+                     SZ, Zp, theta, voff, nt, b, first ? 1 : 0, active);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------- selection ---
 // m_j and the eigenvalues lam = sigma + 1/theta (ascending), +inf where
 // theta <= 1e-14 theta_max.

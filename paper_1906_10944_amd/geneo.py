@@ -60,7 +60,7 @@ class Opts(C.Structure):
                 ("sigma", C.c_double), ("precision", C.c_int), ("pivot_tol", C.c_double),
                 ("eig_tol", C.c_double), ("eig_maxit", C.c_int), ("eig_block", C.c_int),
                 ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
-                ("eig_floor", C.c_double)]
+                ("eig_floor", C.c_double), ("eig_cheb", C.c_int)]
 
 
 class SetupInfo(C.Structure):
