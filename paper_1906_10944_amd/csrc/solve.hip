@@ -172,7 +172,10 @@ __global__ __launch_bounds__(64 * TRMV_WAVES) void k_trmv_upperT(const float* __
                                                     double* __restrict__ yH,
                                                     const int* __restrict__ done) {
   if (done && *done) return;
-  const int2 jb = jobs[blockIdx.y];
+  // jobs in reverse order: the lower product that runs just before walks
+  // them forwards, so the factors it read last are still in the Infinity
+  // Cache when this pass starts on them (and vice versa for the next apply)
+  const int2 jb = jobs[gridDim.y - 1 - blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int j = jb.x, k = blockIdx.x * TRMV_WAVES + (threadIdx.x >> 6);
   if (jb.y == 2) {
