@@ -35,6 +35,43 @@ struct Err {
            std::string(#expr) + " -> " + hipGetErrorString(e_));                        \
   } while (0)
 
+// Pinned host staging for the small uploads of a setup (index lists, job
+// lists, offsets), so that they are asynchronous: one arena per host
+// thread, reused by consecutive setups of that thread.  A setup resets it
+// at the start; every copy that reads it has completed by then, since each
+// setup ends with (or, on failure, unwinds through) synchronising frees.
+struct PinnedArena {
+  std::vector<std::pair<char*, size_t>> chunks;
+  size_t chunk = 0, used = 0;
+  bool active = false;
+  void begin() {
+    chunk = used = 0;
+    active = true;
+  }
+  void end() { active = false; }
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    while (chunk < chunks.size() && used + bytes > chunks[chunk].second) {
+      ++chunk;
+      used = 0;
+    }
+    if (chunk == chunks.size()) {
+      const size_t cap = std::max(bytes, (size_t)4 << 20);
+      char* p = nullptr;
+      if (hipHostMalloc((void**)&p, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+      chunks.push_back({p, cap});
+      used = 0;
+    }
+    void* r = chunks[chunk].first + used;
+    used += bytes;
+    return r;
+  }
+  ~PinnedArena() {
+    for (auto& c : chunks) (void)hipHostFree(c.first);
+  }
+};
+thread_local PinnedArena t_arena;
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
@@ -54,10 +91,20 @@ struct DBuf {
     p = nullptr;
     n = 0;
   }
+  // Copies v to a fresh device buffer on stream st: through the pinned
+  // arena without waiting when a setup is running, else synchronously.
   void upload(const std::vector<T>& v, hipStream_t st) {
     alloc(v.size());
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (v.empty()) return;
+    const size_t bytes = v.size() * sizeof(T);
+    void* stage = t_arena.active ? t_arena.take(bytes) : nullptr;
+    if (stage) {
+      memcpy(stage, v.data(), bytes);
+      HIPCHK(hipMemcpyAsync(p, stage, bytes, hipMemcpyHostToDevice, st));
+    } else {
+      HIPCHK(hipMemcpyAsync(p, v.data(), bytes, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
   }
 };
 
@@ -112,6 +159,7 @@ struct geneo_handle_s {
   int64_t nloc = 0;
   geneo_opts_t opts{};
   hipStream_t hs = nullptr;
+  hipEvent_t shifted_done = nullptr;
   LocalLayout LD;
   DBuf<int> sub_ptr, sub_idx, dmap, nd, ntD, voffD, dglob, didx, jobs32, jobs64;
   DBuf<int64_t> toffD, doffD, toff64, doff64;
@@ -145,6 +193,7 @@ struct geneo_handle_s {
   std::vector<int> f64list;                         // subdomains with FP64 local factors
   geneo_setup_info_t info{};
   ~geneo_handle_s() {
+    if (shifted_done) (void)hipEventDestroy(shifted_done);
     if (hs) (void)hipStreamDestroy(hs);
   }
 };
@@ -285,6 +334,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     }
     auto stat = download(X.status.p, nsub, st);
     after_fp32();
+    if (h->shifted_done) HIPCHK(hipStreamWaitEvent(st, h->shifted_done, 0));
     std::vector<int> ok32;
     for (int j = 0; j < nsub; ++j) (stat[j] ? f64list : ok32).push_back(j);
     h->njobs32 = (int)ok32.size();
@@ -428,6 +478,10 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
                                X.jobsN.p, nsub, 0.0, sb));
   }
   tm[0].stop(sb);
+  // the FP64 refactors and the FP32 inverse factors on the other stream
+  // start after this factorisation and overlap the eigen sweeps instead
+  HIPCHK(hipEventCreateWithFlags(&h->shifted_done, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(h->shifted_done, sb));
 }
 
 // Eigen sweeps, coarse basis, Galerkin product and coarse factor on sb.
@@ -645,6 +699,10 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   h->nloc = S->nloc;
   h->lpr = spmv_lanes(A);
   HIPCHK(hipStreamCreateWithFlags(&h->hs, hipStreamNonBlocking));
+  struct ArenaScope {
+    ArenaScope() { t_arena.begin(); }
+    ~ArenaScope() { t_arena.end(); }
+  } arena_scope;
   SetupScratch X;
   PhaseTimer tm0, tmL, tmC[4];
 
@@ -705,9 +763,12 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     HIPCHK(hipEventDestroy(ev));
   }
   // Order: the FP32 local factorization runs alone (it fills the device);
-  // once its pivot tests are read back, the shifted factorization and the
-  // eigen sweeps start on hs while the FP64 refactors of the failed
-  // subdomains (few workgroups) and the triangular inverses run on st.
+  // once its pivot tests are read back the shifted factorization runs on
+  // hs, and the FP64 refactors of the failed subdomains and the triangular
+  // inverses follow it on st, overlapping the eigen sweeps (whose solves
+  // leave the device room) rather than competing with the factorization.
+  // Uploads go through pinned staging, so the host drives both streams
+  // without waiting on either.
   LocalLayout LN;
   tmL.start(st);
   setup_local(h, X, A, S, st, [&]() {
