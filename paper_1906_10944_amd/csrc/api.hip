@@ -175,6 +175,7 @@ struct geneo_handle_s {
   // apply job list of the triangular products: (subdomain, 1 if its factor
   // is FP64) for every subdomain, then (nsub, 2) for the coarse factor
   DBuf<int2> ajobs;
+  DBuf<double> rz_part, rr_part;  // PCG partial sums: r.z per 256 rows, r.r per PCG block
   std::vector<int2> ljobs_host;
   int najobs = 0, amaxnt = 0;
   DBuf<int64_t> htoff;
@@ -205,14 +206,25 @@ void check_csr(const geneo_csr_t* A) {
     fail(GENEO_ERR_ARG, "invalid CSR matrix");
 }
 
+// z = M^{-1} r on stream st.  Inside the PCG loop (pcg = true) the first
+// launch also performs the convergence check on the r.r partial sums and
+// the apply is skipped once `done` is set; the combine step always leaves
+// the r.z partial sums (per 256-row block) in h->rz_part.
 hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const int* done,
-                         hipStream_t st) {
+                         hipStream_t st, bool pcg = false) {
   hipError_t e;
-  if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
-  if (h->nc > 0 &&
-      (e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
-                           h->coff.p, h->nsub, h->rH.p, done, st)))
-    return e;
+  if (pcg) {
+    if ((e = check_apply_in(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, h->Z.p, h->zoff.p,
+                            h->m.p, h->nd.p, h->voffD.p, h->coff.p, h->rH.p,
+                            h->nc > 0 ? h->nsub : 0, h->rr_part.p, h->sc.p, h->done.p, st)))
+      return e;
+  } else {
+    if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
+    if (h->nc > 0 &&
+        (e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
+                             h->coff.p, h->nsub, h->rH.p, done, st)))
+      return e;
+  }
   const double lb = h->bytes_trmv32 + h->bytes_trmv64 + h->bytes_trmvH;
   {
     ProfScope ps("trmv_lower", st, lb, 0.0);
@@ -230,7 +242,7 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
   }
   return combine(r, h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
                  h->yl.p, h->Z.p, h->zoff.p, h->m.p, h->coff.p, h->yH.p, h->n, h->nc > 0, z, done,
-                 st);
+                 h->rz_part.p, st);
 }
 
 __global__ void k_count_active(const int* a, int n, int* out) {
@@ -793,6 +805,7 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     if (!h->Z.p) h->Z.alloc(1);
     h->yH.alloc(1);
   }
+  h->rz_part.alloc((size_t)(h->n + 255) / 256);
   {
     std::vector<int2> aj = h->ljobs_host;
     if (h->nc > 0) aj.push_back(make_int2(nsub, 2));
@@ -821,6 +834,7 @@ void ensure_pcg(geneo_handle_s* h, int maxit) {
     h->p.alloc(h->n);
     h->q.alloc(h->n);
     h->partial.alloc(PCG_NB);
+    h->rr_part.alloc(PCG_NB);
     h->sc.alloc(1);
     h->done.alloc(1);
     h->pcg_cap = h->n;
@@ -862,24 +876,24 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
   if (bb == 0.0 || rr0 <= init.tol2) {
     converged = 1;
   } else {
+    // z = M^{-1} r also leaves the r.z partial sums that alpha needs
     HIPCHK(apply_enqueue(h, h->r.p, h->z.p, nullptr, st));
     HIPCHK(copy_vec(h->z.p, h->p.p, n, st));
-    HIPCHK(dot_partial(h->r.p, h->z.p, n, h->partial.p, nullptr, st));
-    HIPCHK(scalar_stage(h->partial.p, 3, h->sc.p, h->done.p, h->alphas.p, h->betas.p, st));
-    // capture PCG_CHUNK iterations
+    const int nrz = (n + 255) / 256;
+    // capture PCG_CHUNK iterations: 8 launches each (SpMV, p.Ap, x/r update
+    // with alpha, check + apply input, two triangular products, combine
+    // with r.z, p update with beta)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < PCG_CHUNK; ++k) {
       HIPCHK(spmv(A, h->p.p, h->q.p, h->lpr, h->done.p, st));
       HIPCHK(dot_partial(h->p.p, h->q.p, n, h->partial.p, h->done.p, st));
-      HIPCHK(scalar_stage(h->partial.p, 0, h->sc.p, h->done.p, h->alphas.p, h->betas.p, st));
-      HIPCHK(update_xr(x, h->r.p, h->p.p, h->q.p, n, h->sc.p, h->partial.p, h->done.p, st));
-      HIPCHK(scalar_stage(h->partial.p, 1, h->sc.p, h->done.p, h->alphas.p, h->betas.p, st));
-      HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st));
-      HIPCHK(dot_partial(h->r.p, h->z.p, n, h->partial.p, h->done.p, st));
-      HIPCHK(scalar_stage(h->partial.p, 2, h->sc.p, h->done.p, h->alphas.p, h->betas.p, st));
-      HIPCHK(update_p(h->p.p, h->z.p, n, h->sc.p, h->done.p, st));
+      HIPCHK(update_xr_alpha(x, h->r.p, h->p.p, h->q.p, n, h->partial.p, h->rz_part.p, nrz, h->sc.p,
+                             h->alphas.p, h->rr_part.p, h->done.p, st));
+      HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true));
+      HIPCHK(update_p_beta(h->p.p, h->z.p, n, h->rz_part.p, nrz, h->sc.p, h->betas.p, h->done.p,
+                           st));
     }
     HIPCHK(hipStreamEndCapture(st, &graph));
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));

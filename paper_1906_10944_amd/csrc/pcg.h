@@ -22,7 +22,8 @@ hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, co
 hipError_t combine(const double* r, const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
                    const int* dvoff, const double* dscale, const double* yl, const double* Z,
                    const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
-                   int use_coarse, double* z, const int* done, hipStream_t st);
+                   int use_coarse, double* z, const int* done, double* rz_partial,
+                   hipStream_t st);  // rz_partial (may be NULL): r.z per 256-row block
 hipError_t dot_partial(const double* x, const double* y, int n, double* partial, const int* done,
                        hipStream_t st);
 hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
@@ -34,5 +35,15 @@ hipError_t update_p(double* p, const double* z, int n, const PcgScalars* sc, con
 hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st);
 hipError_t copy_vec(const double* a, double* b, int n, hipStream_t st);
 hipError_t fill_i32(int* p, int v, int n, hipStream_t st);
+// fused PCG iteration pieces (scalars formed in the consumers)
+hipError_t update_xr_alpha(double* x, double* r, const double* p, const double* q, int n,
+                           const double* pq_part, const double* rz_part, int nrz, PcgScalars* sc,
+                           double* alphas, double* rr_part, const int* done, hipStream_t st);
+hipError_t check_apply_in(const double* r, const int* dglob, const double* dscale, int64_t nvec,
+                          double* xl, const double* Z, const int* zoff, const int* m, const int* nd,
+                          const int* dvoff, const int* coff, double* rH, int nrestrict,
+                          const double* rr_part, PcgScalars* sc, int* done, hipStream_t st);
+hipError_t update_p_beta(double* p, const double* z, int n, const double* rz_part, int nrz,
+                         PcgScalars* sc, double* betas, const int* done, hipStream_t st);
 
 }  // namespace geneo

@@ -56,6 +56,44 @@ int spmv_lanes(const geneo_csr_t* A) {
 }
 
 // ------------------------------------------------------- apply pieces ---
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+  __syncthreads();
+  return t;
+}
+
+// Sum over the block, returned to every thread (fixed order).
+__device__ __forceinline__ double block_allsum(double v, double* sh) {
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) sh[4] = t;
+  __syncthreads();
+  const double r = sh[4];
+  __syncthreads();
+  return r;
+}
+
+// Sum of nb partial sums, returned to every thread of the block (the same
+// order in every block, so every block gets the same value).
+__device__ double allsum_partials(const double* partial, int nb, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
+  return block_allsum(s, sh);
+}
+
+__device__ double sum_partials(const double* partial, int nb, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
+  return block_sum(s, sh);
+}
+
+
+
 __global__ void k_gather_local(const double* __restrict__ r, const int* __restrict__ dglob,
                                const double* __restrict__ dscale, int64_t nvec,
                                double* __restrict__ xl, const int* __restrict__ done) {
@@ -73,7 +111,33 @@ hipError_t gather_local(const double* r, const int* dglob, const double* dscale,
   return hipGetLastError();
 }
 
-// rH[coff_j + c] = sum_d Z_j[d][c] r[g(d)]
+// rH[coff_j + c] = sum_d Z_j[d][c] r[g(d)] for subdomain j, 256 threads:
+// wave w takes the columns c = w, w+4, ..., lanes stride over the rows.
+__device__ __forceinline__ void restrict_block(int j, const double* __restrict__ r,
+                                               const double* __restrict__ Z,
+                                               const int* __restrict__ zoff,
+                                               const int* __restrict__ m,
+                                               const int* __restrict__ nd,
+                                               const int* __restrict__ dglob,
+                                               const int* __restrict__ dvoff,
+                                               const int* __restrict__ coff,
+                                               double* __restrict__ rH) {
+  const int mj = m[j];
+  if (mj == 0) return;
+  const int n = nd[j];
+  const double* Zj = Z + zoff[j];
+  const int* gj = dglob + dvoff[j];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < mj; c0 += 4) {
+    const int c = c0 + w;
+    double s = 0.0;
+    if (c < mj)
+      for (int d = lane; d < n; d += 64) s += Zj[(int64_t)d * mj + c] * r[gj[d]];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && c < mj) rH[coff[j] + c] = s;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ r,
                                                   const double* __restrict__ Z,
                                                   const int* __restrict__ zoff,
@@ -85,24 +149,7 @@ __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ r,
                                                   double* __restrict__ rH,
                                                   const int* __restrict__ done) {
   if (done && *done) return;
-  const int j = blockIdx.x;
-  const int mj = m[j];
-  if (mj == 0) return;
-  const int n = nd[j];
-  const double* Zj = Z + zoff[j];
-  const int* gj = dglob + dvoff[j];
-  __shared__ double red[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // wave w handles columns c = w, w+4, ...; lanes stride over rows
-  for (int c0 = 0; c0 < mj; c0 += 4) {
-    int c = c0 + w;
-    double s = 0.0;
-    if (c < mj)
-      for (int d = lane; d < n; d += 64) s += Zj[(int64_t)d * mj + c] * r[gj[d]];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && c < mj) rH[coff[j] + c] = s;
-  }
-  (void)red;
+  restrict_block(blockIdx.x, r, Z, zoff, m, nd, dglob, dvoff, coff, rH);
 }
 
 hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, const int* m,
@@ -117,59 +164,66 @@ hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, co
 //        s_d y_j[d] + Z_j[d][:] . yH[coff_j :]          (d = dmap_j(g) >= 0)
 // and z[g] = r[g] for a dof in no D_j (an eliminated Dirichlet dof: its row
 // of A is a unit row, so the operator stays SPD on every dof).
-__global__ void k_combine(const double* __restrict__ r, const int* __restrict__ optr,
-                          const int2* __restrict__ olist,
-                          const int* __restrict__ sub_ptr, const int* __restrict__ dmap,
-                          const int* __restrict__ dvoff, const double* __restrict__ dscale,
-                          const double* __restrict__ yl, const double* __restrict__ Z,
-                          const int* __restrict__ zoff, const int* __restrict__ m,
-                          const int* __restrict__ coff, const double* __restrict__ yH, int ndof,
-                          int use_coarse, double* __restrict__ z, const int* __restrict__ done) {
+__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ r,
+                                                 const int* __restrict__ optr,
+                                                 const int2* __restrict__ olist,
+                                                 const int* __restrict__ sub_ptr,
+                                                 const int* __restrict__ dmap,
+                                                 const int* __restrict__ dvoff,
+                                                 const double* __restrict__ dscale,
+                                                 const double* __restrict__ yl,
+                                                 const double* __restrict__ Z,
+                                                 const int* __restrict__ zoff,
+                                                 const int* __restrict__ m,
+                                                 const int* __restrict__ coff,
+                                                 const double* __restrict__ yH, int ndof,
+                                                 int use_coarse, double* __restrict__ z,
+                                                 const int* __restrict__ done,
+                                                 double* __restrict__ rz_partial) {
   if (done && *done) return;
-  int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ndof) return;
-  double s = 0.0;
-  bool covered = false;
-  for (int p = optr[g]; p < optr[g + 1]; ++p) {
-    int2 o = olist[p];
-    int j = o.x;
-    int d = dmap[sub_ptr[j] + o.y];
-    if (d < 0) continue;
-    covered = true;
-    int e = dvoff[j] + d;
-    s += dscale[e] * yl[e];
-    if (use_coarse) {
-      int mj = m[j];
-      const double* zr = Z + zoff[j] + (int64_t)d * mj;
-      const double* yh = yH + coff[j];
-      for (int c = 0; c < mj; ++c) s += zr[c] * yh[c];
+  __shared__ double sh[4];
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  double zg = 0.0, rg = 0.0;
+  if (g < ndof) {
+    double s = 0.0;
+    bool covered = false;
+    for (int p = optr[g]; p < optr[g + 1]; ++p) {
+      int2 o = olist[p];
+      int j = o.x;
+      int d = dmap[sub_ptr[j] + o.y];
+      if (d < 0) continue;
+      covered = true;
+      int e = dvoff[j] + d;
+      s += dscale[e] * yl[e];
+      if (use_coarse) {
+        int mj = m[j];
+        const double* zr = Z + zoff[j] + (int64_t)d * mj;
+        const double* yh = yH + coff[j];
+        for (int c = 0; c < mj; ++c) s += zr[c] * yh[c];
+      }
     }
+    rg = r[g];
+    zg = covered ? s : rg;
+    z[g] = zg;
   }
-  z[g] = covered ? s : r[g];
+  if (rz_partial) {
+    // this block's share of r.z (rows 256 b .. 256 b + 255), fixed order
+    const double t = block_sum(rg * zg, sh);
+    if (threadIdx.x == 0) rz_partial[blockIdx.x] = t;
+  }
 }
 
 hipError_t combine(const double* r, const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
                    const int* dvoff, const double* dscale, const double* yl, const double* Z,
                    const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
-                   int use_coarse, double* z, const int* done, hipStream_t st) {
+                   int use_coarse, double* z, const int* done, double* rz_partial, hipStream_t st) {
   hipLaunchKernelGGL(k_combine, dim3((ndof + 255) / 256), dim3(256), 0, st, r, optr, olist, sub_ptr,
-                     dmap, dvoff, dscale, yl, Z, zoff, m, coff, yH, ndof, use_coarse, z, done);
+                     dmap, dvoff, dscale, yl, Z, zoff, m, coff, yH, ndof, use_coarse, z, done,
+                     rz_partial);
   return hipGetLastError();
 }
 
 // -------------------------------------------------------- PCG kernels ---
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
-  __syncthreads();
-  return t;
-}
-
 // partial[b] = sum over the fixed row range of block b of x.y
 __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x,
                                                      const double* __restrict__ y, int n,
@@ -213,12 +267,6 @@ __global__ __launch_bounds__(256) void k_update_p(double* __restrict__ p, const 
   const double beta = sc->beta;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
-}
-
-__device__ double sum_partials(const double* partial, int nb, double* sh) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
-  return block_sum(s, sh);
 }
 
 // stage: 0 = alpha (pq), 1 = convergence check (rr), 2 = beta (rz), 3 = init
@@ -276,6 +324,129 @@ hipError_t update_xr(double* x, double* r, const double* p, const double* q, int
 hipError_t update_p(double* p, const double* z, int n, const PcgScalars* sc, const int* done,
                     hipStream_t st) {
   hipLaunchKernelGGL(k_update_p, dim3(PCG_NB), dim3(256), 0, st, p, z, n, sc, done);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ fused PCG iteration ---
+// The scalars of an iteration are not formed by separate one-thread
+// kernels: every block of the kernel that needs one sums the fixed-order
+// partial sums itself (identical in every block); block 0 records it.
+
+// alpha = (r.z) / (p.A p); x += alpha p, r -= alpha q; partial sums of r.r.
+__global__ __launch_bounds__(256) void k_update_xr_a(double* __restrict__ x,
+                                                     double* __restrict__ r,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ q, int n,
+                                                     const double* __restrict__ pq_part, int npq,
+                                                     const double* __restrict__ rz_part, int nrz,
+                                                     PcgScalars* __restrict__ sc,
+                                                     double* __restrict__ alphas,
+                                                     double* __restrict__ rr_part,
+                                                     const int* __restrict__ done) {
+  if (*done) return;
+  __shared__ double sh[8];
+  const double pq = allsum_partials(pq_part, npq, sh);
+  const double rz = allsum_partials(rz_part, nrz, sh);
+  const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->rz = rz;
+    sc->alpha = alpha;
+    alphas[sc->iters] = alpha;
+    sc->iters += 1;
+  }
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
+}
+
+// Convergence check on r.r, then the first pieces of the apply: blocks
+// [0, ngather) gather the scaled local vectors, the next nrestrict blocks
+// form the coarse restriction of one subdomain each.
+__global__ __launch_bounds__(256) void k_check_apply_in(const double* __restrict__ r,
+                                                        const int* __restrict__ dglob,
+                                                        const double* __restrict__ dscale,
+                                                        int64_t nvec, double* __restrict__ xl,
+                                                        int ngather, const double* __restrict__ Z,
+                                                        const int* __restrict__ zoff,
+                                                        const int* __restrict__ m,
+                                                        const int* __restrict__ nd,
+                                                        const int* __restrict__ dvoff,
+                                                        const int* __restrict__ coff,
+                                                        double* __restrict__ rH,
+                                                        const double* __restrict__ rr_part, int nrr,
+                                                        PcgScalars* __restrict__ sc,
+                                                        int* __restrict__ done) {
+  if (*done) return;
+  __shared__ double sh[8];
+  const double rr = allsum_partials(rr_part, nrr, sh);
+  const bool conv = rr <= sc->tol2;
+  const bool stop = conv || sc->iters >= sc->maxit || !(rr == rr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rr = rr;
+    if (conv) sc->converged = 1;
+    if (stop) *done = 1;
+  }
+  if (stop) return;
+  if ((int)blockIdx.x < ngather) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < nvec) {
+      const int g = dglob[e];
+      xl[e] = g >= 0 ? dscale[e] * r[g] : 0.0;
+    }
+  } else {
+    restrict_block(blockIdx.x - ngather, r, Z, zoff, m, nd, dglob, dvoff, coff, rH);
+  }
+}
+
+// beta = (r.z)_new / (r.z)_old; p = z + beta p.
+__global__ __launch_bounds__(256) void k_update_p_b(double* __restrict__ p,
+                                                    const double* __restrict__ z, int n,
+                                                    const double* __restrict__ rz_part, int nrz,
+                                                    PcgScalars* __restrict__ sc,
+                                                    double* __restrict__ betas,
+                                                    const int* __restrict__ done) {
+  if (*done) return;
+  __shared__ double sh[8];
+  const double rz_new = allsum_partials(rz_part, nrz, sh);
+  const double beta = rz_new / sc->rz;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->beta = beta;
+    betas[sc->iters - 1] = beta;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+hipError_t update_xr_alpha(double* x, double* r, const double* p, const double* q, int n,
+                           const double* pq_part, const double* rz_part, int nrz, PcgScalars* sc,
+                           double* alphas, double* rr_part, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr_a, dim3(PCG_NB), dim3(256), 0, st, x, r, p, q, n, pq_part, PCG_NB,
+                     rz_part, nrz, sc, alphas, rr_part, done);
+  return hipGetLastError();
+}
+
+hipError_t check_apply_in(const double* r, const int* dglob, const double* dscale, int64_t nvec,
+                          double* xl, const double* Z, const int* zoff, const int* m, const int* nd,
+                          const int* dvoff, const int* coff, double* rH, int nrestrict,
+                          const double* rr_part, PcgScalars* sc, int* done, hipStream_t st) {
+  const int ngather = (int)((nvec + 255) / 256);
+  hipLaunchKernelGGL(k_check_apply_in, dim3(ngather + nrestrict), dim3(256), 0, st, r, dglob,
+                     dscale, nvec, xl, ngather, Z, zoff, m, nd, dvoff, coff, rH, rr_part, PCG_NB,
+                     sc, done);
+  return hipGetLastError();
+}
+
+hipError_t update_p_beta(double* p, const double* z, int n, const double* rz_part, int nrz,
+                         PcgScalars* sc, double* betas, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_p_b, dim3(PCG_NB), dim3(256), 0, st, p, z, n, rz_part, nrz, sc,
+                     betas, done);
   return hipGetLastError();
 }
 
