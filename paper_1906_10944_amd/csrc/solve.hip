@@ -532,20 +532,36 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
             trw_finish<NCQ, BWD>(acc[m], Dj + (int64_t)i * TSQ, sTmp, sXo,
                                  Xj + (int64_t)i * TS * b, b, lane);
       }
+      // the factor tile of the first row's update does not depend on X_i:
+      // its loads are in flight while the wavefront waits at the barrier
+      // (the second row's load then overlaps the first row's products)
+      auto load_neg = [&](F8 (&aa)[2], int k) {
+        const double* t = BWD ? Gj + tile_idx(i, k) * TSQ : Gj + tile_idx(k, i) * TSQ;
+#pragma unroll
+        for (int rq = 0; rq < 2; ++rq) {
+          if (BWD) afrag_tr(aa[rq], t, rq * 16, fi, fg);
+          else afrag(aa[rq], t, rq * 16, fi, fg);
+        }
+      };
+      auto wants = [&](int k) { return k < p1 && (BWD ? k < i : k > i); };
+      F8 a0[2];
+      if (wants(krow[0])) load_neg(a0, krow[0]);
       block_sync();
 #pragma unroll
       for (int m = 0; m < TRW_MR; ++m) {
         const int k = krow[m];
-        if (k >= p1 || (BWD ? k >= i : k <= i)) continue;
-        const double* t = BWD ? Gj + tile_idx(i, k) * TSQ : Gj + tile_idx(k, i) * TSQ;
+        if (!wants(k)) continue;
         F8 a[2];
+        if (m == 0) {
+          a[0] = a0[0];
+          a[1] = a0[1];
+        } else {
+          load_neg(a, k);
+        }
 #pragma unroll
-        for (int rq = 0; rq < 2; ++rq) {
-          if (BWD) afrag_tr(a[rq], t, rq * 16, fi, fg);
-          else afrag(a[rq], t, rq * 16, fi, fg);
+        for (int rq = 0; rq < 2; ++rq)
 #pragma unroll
           for (int s = 0; s < 8; ++s) a[rq].v[s] = -a[rq].v[s];
-        }
 #pragma unroll
         for (int cq = 0; cq < NCQ; ++cq) {
           F8 bf;
