@@ -143,7 +143,7 @@ def prof_query(G, name):
 PROF_KERNELS = ["densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
                 "trtri_dirichlet", "densify_shifted", "chol_shifted_f64", "trsm_bwd",
                 "trsm_fwd", "bapply", "rayleigh_ritz", "orth", "coarse_chol",
-                "trmv_lower", "trmv_upperT", "chebyshev"]
+                "lauum_dirichlet", "symv", "symv_cols", "chebyshev"]
 
 
 def kernel_profile(runner, precision):
@@ -168,14 +168,14 @@ def kernel_profile(runner, precision):
 
 # kernel symbol of each event-timed launch site (as rocprofv3 names it)
 PROF_SYMBOL = {"densify_dirichlet": "k_densify_dirichlet", "chol_dirichlet_f32": "k_potrf_local_f32",
-               "chol_dirichlet_f64": "k_potrf_local_f64", "trtri_dirichlet": "k_trtri<float>",
+               "chol_dirichlet_f64": "k_potrf_local_f64", "trtri_dirichlet": "k_trtri_win<float, 2>",
                "densify_shifted": "k_densify_shifted", "chol_shifted_f64": "k_potrf_shifted_f64",
                "trsm_bwd": "k_trsm_win<2, true>", "trsm_fwd": "k_trsm_win<2, false>",
                "bapply": "k_bapply", "rayleigh_ritz": "rayleigh-ritz kernels",
                "orth": "orthonormalisation kernels",
-               "coarse_chol": "k_cpotrf", "trmv_lower": "k_trmv_lower",
-               "trmv_upperT": "k_trmv_upperT"}
-APPLY_KERNELS = ("trmv_lower", "trmv_upperT")
+               "coarse_chol": "k_cpotrf", "lauum_dirichlet": "k_lauum<float>",
+               "symv": "k_symv_rows", "symv_cols": "k_symv_cols"}
+APPLY_KERNELS = ("symv", "symv_cols")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_darcy512_mixed.json")
 
 
@@ -219,7 +219,8 @@ def roofline(prof, iters):
     name = max(per_step, key=per_step.get)
     p = prof[name]
     avg_ms = p["ms"] / p["launches"]
-    compute_bound = name.startswith("chol") or name.startswith("trtri") or name == "coarse_chol"
+    compute_bound = (name.startswith("chol") or name.startswith("trtri") or name == "coarse_chol"
+                     or name.startswith("lauum"))
     if compute_bound:
         peak = FP32_MFMA_PEAK_TFLOPS if name.endswith("f32") else FP64_PEAK_TFLOPS
         achieved = p["flops"] / p["launches"] / (avg_ms * 1e-3) / 1e12

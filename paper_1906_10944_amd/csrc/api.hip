@@ -164,33 +164,33 @@ struct geneo_handle_s {
   DBuf<int> sub_ptr, sub_idx, dmap, nd, ntD, voffD, dglob, didx, jobs32, jobs64;
   DBuf<int64_t> toffD, doffD, toff64, doff64;
   DBuf<double> dscale;
-  DBuf<float> X32;
-  DBuf<double> X64;
+  DBuf<float> S32, W32;  // symmetric inverses A_j^{-1} (FP32 subdomains), symv partials
+  DBuf<double> S64, W64;
   int njobs32 = 0, njobs64 = 0;
   DBuf<int> optr;
   DBuf<int2> olist;
   // coarse space
   int nc = 0, ntc = 0, b = 0;
   DBuf<int> m, zoff, coff, hnt;
-  // apply job list of the triangular products: (subdomain, 1 if its factor
-  // is FP64) for every subdomain, then (nsub, 2) for the coarse factor
+  // apply job list of the symmetric products: (subdomain, 1 if its inverse
+  // is FP64) for every subdomain, then (nsub, 2) for the coarse inverse
   DBuf<int2> ajobs;
   DBuf<double> rz_part, rr_part;  // PCG partial sums: r.z per 256 rows, r.r per PCG block
   std::vector<int2> ljobs_host;
   int najobs = 0, amaxnt = 0;
   DBuf<int64_t> htoff;
-  DBuf<double> Z, XH, rH, tH, yH, AHdense;
+  DBuf<double> Z, SH, WH, rH, yH, AHdense;
   std::vector<int> m_host, nd_host, nN_host, sub_ptr_host;
   std::vector<double> lam_host;
   // apply workspace
-  DBuf<double> xl, tl, yl;
+  DBuf<double> xl, yl;
   // pcg workspace
   int pcg_cap = 0, pcg_maxit = 0;
   DBuf<double> r, z, p, q, partial, alphas, betas;
   DBuf<PcgScalars> sc;
   DBuf<int> done;
   int lpr = 8;
-  double bytes_trmv32 = 0.0, bytes_trmv64 = 0.0, bytes_trmvH = 0.0;  // algorithmic bytes per launch
+  double bytes_symv32 = 0.0, bytes_symv64 = 0.0, bytes_symvH = 0.0;  // algorithmic bytes per apply
   std::vector<int> f64list;                         // subdomains with FP64 local factors
   geneo_setup_info_t info{};
   ~geneo_handle_s() {
@@ -225,20 +225,32 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
                              h->coff.p, h->nsub, h->rH.p, done, st)))
       return e;
   }
-  const double lb = h->bytes_trmv32 + h->bytes_trmv64 + h->bytes_trmvH;
+  SymvArgs sa;
+  sa.S32 = h->S32.p;
+  sa.S64 = h->S64.p;
+  sa.toff32 = h->toffD.p;
+  sa.toff64 = h->toff64.p;
+  sa.nt = h->ntD.p;
+  sa.voff = h->voffD.p;
+  sa.jobs = h->ajobs.p;
+  sa.njobs = h->najobs;
+  sa.maxnt = h->amaxnt;
+  sa.SH = h->SH.p;
+  sa.ntc = h->ntc;
+  sa.W32 = h->W32.p;
+  sa.W64 = h->W64.p;
+  sa.WH = h->WH.p;
+  sa.x = h->xl.p;
+  sa.y = h->yl.p;
+  sa.xH = h->rH.p;
+  sa.yH = h->yH.p;
   {
-    ProfScope ps("trmv_lower", st, lb, 0.0);
-    if ((e = trmv_lower(h->X32.p, h->X64.p, h->toffD.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                        h->ajobs.p, h->najobs, h->amaxnt, h->xl.p, h->tl.p, h->XH.p, h->ntc,
-                        h->rH.p, h->tH.p, done, st)))
-      return e;
+    ProfScope ps("symv", st, h->bytes_symv32 + h->bytes_symv64 + h->bytes_symvH, 0.0);
+    if ((e = symv_rows(sa, done, st))) return e;
   }
   {
-    ProfScope ps("trmv_upperT", st, lb, 0.0);
-    if ((e = trmv_upperT(h->X32.p, h->X64.p, h->toffD.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                         h->ajobs.p, h->najobs, h->amaxnt, h->tl.p, h->yl.p, h->XH.p, h->ntc,
-                         h->tH.p, h->yH.p, done, st)))
-      return e;
+    ProfScope ps("symv_cols", st, 0.0, 0.0);
+    if ((e = symv_cols(sa, done, st))) return e;
   }
   return combine(r, h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
                  h->yl.p, h->Z.p, h->zoff.p, h->m.p, h->coff.p, h->yH.p, h->n, h->nc > 0, z, done,
@@ -267,7 +279,9 @@ __global__ void k_max_resid(const double* resid, const int* m, int nsub, int b, 
 struct SetupScratch {
   DBuf<int> status, status2, jobs, jobsN, ntN, voffN, active, pcnt, poff, npairs, woffd, cst;
   DBuf<int64_t> toffN, doffN, hdoff;
-  DBuf<float> L32, D32;
+  DBuf<float> L32, D32, XT32;
+  DBuf<double> XT64, XTH;
+  DBuf<int2> ljobs32, ljobs64, ljobsH;
   DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
   DBuf<int> ebad, scount, sflag;
   DBuf<double> sbest;
@@ -311,7 +325,21 @@ std::vector<int2> trtri_job_list(const std::vector<int>& mats, const std::vector
   return tj;
 }
 
-// Local Dirichlet factors A_j = R_j A R_j^T and their inverse factors, on
+// Jobs of S = X^T X: (matrix, I << 16 | J0) for the output tiles (I, J0 ..
+// J0 + lauum_tiles_per_job() - 1) of each tile row I, matrix by matrix and
+// within a matrix the longest rows (small I) first.
+std::vector<int2> lauum_job_list(const std::vector<int>& mats, const std::vector<int>& nt) {
+  const int w = lauum_tiles_per_job();
+  std::vector<int2> lj;
+  for (int j : mats) {
+    if (nt[j] >= 32768) fail(GENEO_ERR_ARG, "local matrix too large for the dense inverse");
+    for (int I = 0; I < nt[j]; ++I)
+      for (int J0 = 0; J0 <= I; J0 += w) lj.push_back(make_int2(j, (I << 16) | J0));
+  }
+  return lj;
+}
+
+// Local Dirichlet factors A_j = R_j A R_j^T and their inverses, on
 // stream st.  Returns after the work is enqueued and the pivot tests are
 // read back.
 void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
@@ -354,15 +382,24 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     if (!ok32.empty()) {
       std::vector<int2> tj = trtri_job_list(ok32, h->LD.nt, true);
       X.tjobs32.upload(tj, st);
-      h->X32.alloc(h->LD.ntiles * TSQ);
+      std::vector<int2> lj = lauum_job_list(ok32, h->LD.nt);
+      X.ljobs32.upload(lj, st);
+      X.XT32.alloc(h->LD.ntiles * TSQ);
       double pk32 = 0.0, fl32 = 0.0;
       for (int j : ok32) {
         pk32 += packed(h->nd_host[j]);
         fl32 += std::pow((double)h->nd_host[j], 3) / 3.0;
       }
-      ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, fl32);
-      HIPCHK(launch_trtri(true, X.L32.p, X.D32.p, h->X32.p, h->toffD.p, h->doffD.p, h->ntD.p,
-                          X.tjobs32.p, (int)tj.size(), st));
+      {
+        ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, fl32);
+        HIPCHK(launch_trtri(true, X.L32.p, X.D32.p, X.XT32.p, h->toffD.p, h->doffD.p, h->ntD.p,
+                            X.tjobs32.p, (int)tj.size(), st));
+      }
+      h->S32.alloc(h->LD.ntiles * TSQ);
+      h->W32.alloc(h->LD.ntiles * TS);
+      ProfScope ps("lauum_dirichlet", st, 2.0 * 4.0 * pk32, fl32);
+      HIPCHK(launch_lauum(true, X.XT32.p, h->S32.p, h->toffD.p, h->ntD.p, X.ljobs32.p,
+                          (int)lj.size(), st));
     }
   } else {
     f64list = all;
@@ -409,10 +446,19 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     }
     std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
     X.tjobs64.upload(tj, st);
-    h->X64.alloc(tt * TSQ);
-    ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
-    HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, h->X64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                        X.tjobs64.p, (int)tj.size(), st));
+    std::vector<int2> lj = lauum_job_list(f64list, h->LD.nt);
+    X.ljobs64.upload(lj, st);
+    X.XT64.alloc(tt * TSQ);
+    {
+      ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
+      HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, X.XT64.p, h->toff64.p, h->doff64.p, h->ntD.p,
+                          X.tjobs64.p, (int)tj.size(), st));
+    }
+    h->S64.alloc(tt * TSQ);
+    h->W64.alloc(tt * TS);
+    ProfScope ps("lauum_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
+    HIPCHK(launch_lauum(false, X.XT64.p, h->S64.p, h->toff64.p, h->ntD.p, X.ljobs64.p,
+                        (int)lj.size(), st));
   }
   double b32 = 0.0, b64 = 0.0;
   std::vector<char> is64(nsub, 0);
@@ -422,9 +468,9 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     if (is64[j]) b64 += 8.0 * packed(nn) + 16.0 * nn;
     else b32 += 4.0 * packed(nn) + 16.0 * nn;
   }
-  h->bytes_trmv32 = b32;
-  h->bytes_trmv64 = b64;
-  h->info.bytes_local_factors = (int64_t)(h->X32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->X64.n * 8;
+  h->bytes_symv32 = b32;
+  h->bytes_symv64 = b64;
+  h->info.bytes_local_factors = (int64_t)(h->S32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->S64.n * 8;
   h->f64list = f64list;
 }
 
@@ -684,15 +730,20 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     if (download(X.cst.p, 1, sb)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
     h->hnt.upload(std::vector<int>{h->ntc}, sb);
     h->htoff.upload(std::vector<int64_t>{0}, sb);
-    h->bytes_trmvH = 8.0 * tri_tiles(h->ntc) * TSQ + 16.0 * h->ntc * TS;
+    h->bytes_symvH = 8.0 * packed(nc) + 16.0 * nc;
     X.hdoff.upload(std::vector<int64_t>{0}, sb);
     std::vector<int2> tj = trtri_job_list(std::vector<int>{0}, std::vector<int>{h->ntc}, false);
     X.tjobsH.upload(tj, sb);
-    h->XH.alloc(tri_tiles(h->ntc) * TSQ);
-    HIPCHK(launch_trtri(false, X.AHt.p, X.DH.p, h->XH.p, h->htoff.p, X.hdoff.p, h->hnt.p,
+    std::vector<int2> lj = lauum_job_list(std::vector<int>{0}, std::vector<int>{h->ntc});
+    X.ljobsH.upload(lj, sb);
+    X.XTH.alloc(tri_tiles(h->ntc) * TSQ);
+    HIPCHK(launch_trtri(false, X.AHt.p, X.DH.p, X.XTH.p, h->htoff.p, X.hdoff.p, h->hnt.p,
                         X.tjobsH.p, (int)tj.size(), sb));
+    h->SH.alloc(tri_tiles(h->ntc) * TSQ);
+    h->WH.alloc(tri_tiles(h->ntc) * TS);
+    HIPCHK(launch_lauum(false, X.XTH.p, h->SH.p, h->htoff.p, h->hnt.p, X.ljobsH.p, (int)lj.size(),
+                        sb));
     h->rH.alloc((size_t)h->ntc * TS);
-    h->tH.alloc((size_t)h->ntc * TS);
     h->yH.alloc((size_t)h->ntc * TS);
     HIPCHK(hipMemsetAsync(h->rH.p, 0, h->rH.n * sizeof(double), sb));
     tm[3].stop(sb);
@@ -752,7 +803,6 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   HIPCHK(launch_owners(S->sub_ptr, S->sub_idx, nsub, S->nloc, h->n, h->optr.p, X.ocount.p,
                        h->olist.p, st));
   h->xl.alloc(h->LD.nvec);
-  h->tl.alloc(h->LD.nvec);
   h->yl.alloc(h->LD.nvec);
   tm0.stop(st);
   HIPCHK(hipStreamSynchronize(st));

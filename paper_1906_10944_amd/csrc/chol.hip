@@ -529,6 +529,8 @@ hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, 
 // barrier every wavefront subtracts L(k, i) X(i, C) from its later rows.
 // Tiles above the diagonal (column tile > row) are zero: never read or
 // written.  Two tile columns per workgroup (FP32) halve the reads of L.
+// The tiles of X are stored transposed (tile (i, k) holds X(i, k)^T), the
+// layout in which k_lauum reads them.
 #define TW_NW 8
 #define TW_MR 2
 #define TW_W (TW_NW * TW_MR)
@@ -560,7 +562,8 @@ __global__ __launch_bounds__(TW_NW * 64) void k_trtri_win(const T* __restrict__ 
       for (int rq = 0; rq < 2; ++rq) acc[rq][cq] = Mfma<T>::run(a[rq].v[s], bf.v[s], acc[rq][cq]);
   };
   // B fragment of X(jj, C) from memory: column cq*16 + fi of the block,
-  // rows 8 fg .. 8 fg + 7 of tile (jj, c0 + cq / 2); zero above the diagonal
+  // rows 8 fg .. 8 fg + 7 of tile (jj, c0 + cq / 2), i.e. 8 consecutive
+  // entries of a row of the stored (transposed) tile; zero above the diagonal
   auto bfrag_mem = [&](V8<T>& f, int jj, int cq) {
     const int tc = c0 + (cq >> 1);
     if (tc > jj) {
@@ -568,9 +571,7 @@ __global__ __launch_bounds__(TW_NW * 64) void k_trtri_win(const T* __restrict__ 
       for (int s = 0; s < 8; ++s) f.v[s] = (T)0;
       return;
     }
-    const T* t = Xj + tile_idx(jj, tc) * TSQ + (cq & 1) * 16 + fi;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) f.v[s] = t[(8 * fg + s) * TS];
+    ld8(f, Xj + tile_idx(jj, tc) * TSQ + ((cq & 1) * 16 + fi) * TS + 8 * fg);
   };
   auto bfrag_lds = [&](V8<T>& f, const T* sT, int cq) {
     const T* p = sT + (cq * 16 + fi) * LDI + 8 * fg;
@@ -661,7 +662,16 @@ __global__ __launch_bounds__(TW_NW * 64) void k_trtri_win(const T* __restrict__ 
               for (int v = 0; v < 4; ++v) {
                 const int r = rq * 16 + acc_row<T>(lane, v), col = cq * 16 + acc_col(lane);
                 sXo[col * LDI + r] = o[rq][cq][v];
-                if (tc <= i) Xj[tile_idx(i, tc) * TSQ + r * TS + (col & 31)] = o[rq][cq][v];
+              }
+              if (tc > i) continue;
+              // stored transposed: row (col & 31) of the tile holds column col of X
+              T* dst = Xj + tile_idx(i, tc) * TSQ + ((cq & 1) * 16 + acc_col(lane)) * TS + rq * 16;
+              if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<float4*>(dst + 4 * (lane >> 4)) =
+                    make_float4(o[rq][cq][0], o[rq][cq][1], o[rq][cq][2], o[rq][cq][3]);
+              } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dst[acc_row<T>(lane, v)] = o[rq][cq][v];
               }
             }
         }
@@ -697,6 +707,91 @@ hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
   else
     hipLaunchKernelGGL((k_trtri_win<double, 1>), dim3(njobs), dim3(TW_NW * 64), 0, st,
                        (const double*)L, (const double*)dinv, (double*)X, toff, doff, nt, jobs);
+  return hipGetLastError();
+}
+
+// k_lauum: the symmetric inverse S = X^T X = A^{-1} from the inverse factor
+// X = L^{-1} (transposed tiles, as k_trtri_win leaves them): S(I, J) =
+// sum_{K >= I} X(K, I)^T X(K, J) for J <= I, written row-major in the packed
+// format, the diagonal tiles in full.  One wavefront per output tile; the
+// LA_NW wavefronts of a workgroup take consecutive tiles of one tile row,
+// so they read the same X(K, I) (served from L1).  With the transposed
+// tiles both operands of every product are rows of stored tiles: each lane
+// reads 8 consecutive entries (two vector loads) per fragment, the next
+// K's fragments loaded while the current ones are multiplied.  Jobs come
+// matrix by matrix; blocks are handed to the 8 XCDs in contiguous slices of
+// the job list (block b runs on XCD b % 8), so each XCD works on its own
+// matrices and keeps their factors in its L2.
+#define LA_NW 4
+
+template <typename T>
+__global__ __launch_bounds__(LA_NW * 64) void k_lauum(const T* __restrict__ XT, T* __restrict__ S,
+                                                      const int64_t* __restrict__ toff,
+                                                      const int* __restrict__ ntl,
+                                                      const int2* __restrict__ jobs, int njobs,
+                                                      int per_xcd) {
+  typedef typename Mfma<T>::acc Acc;
+  const int q = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (q >= njobs) return;
+  const int2 jb = jobs[q];
+  const int j = jb.x, I = jb.y >> 16, J = (jb.y & 0xffff) + (threadIdx.x >> 6);
+  if (J > I) return;  // no barriers below: a wavefront may leave early
+  const int nt = ntl[j];
+  const int lane = threadIdx.x & 63, fi = lane & 15, fg = lane >> 4;
+  const T* Xj = XT + toff[j] * TSQ + fi * TS + 8 * fg;
+  Acc acc[2][2];
+#pragma unroll
+  for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+    for (int cq = 0; cq < 2; ++cq) acc[rq][cq] = acc_zero<T>();
+  V8<T> a[2], b[2];
+  auto load = [&](V8<T> (&fa)[2], V8<T> (&fb)[2], int K) {
+    const T* ta = Xj + tile_idx(K, I) * TSQ;
+    const T* tb = Xj + tile_idx(K, J) * TSQ;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      ld8(fa[h], ta + h * 16 * TS);
+      ld8(fb[h], tb + h * 16 * TS);
+    }
+  };
+  load(a, b, I);
+  for (int K = I; K < nt; ++K) {
+    V8<T> an[2], bn[2];
+    load(an, bn, K + 1 < nt ? K + 1 : K);
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+        for (int cq = 0; cq < 2; ++cq) acc[rq][cq] = Mfma<T>::run(a[rq].v[s], b[cq].v[s], acc[rq][cq]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h] = an[h];
+      b[h] = bn[h];
+    }
+  }
+  T* Sj = S + (toff[j] + tile_idx(I, J)) * TSQ;
+#pragma unroll
+  for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+    for (int cq = 0; cq < 2; ++cq)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Sj[(rq * 16 + acc_row<T>(lane, v)) * TS + cq * 16 + acc_col(lane)] = acc[rq][cq][v];
+}
+
+int lauum_tiles_per_job() { return LA_NW; }
+
+hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff, const int* nt,
+                        const int2* jobs, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const int per = (njobs + 7) / 8;
+  if (fp32)
+    hipLaunchKernelGGL(k_lauum<float>, dim3(8 * per), dim3(LA_NW * 64), 0, st,
+                       (const float*)XT, (float*)S, toff, nt, jobs, njobs, per);
+  else
+    hipLaunchKernelGGL(k_lauum<double>, dim3(8 * per), dim3(LA_NW * 64), 0, st,
+                       (const double*)XT, (double*)S, toff, nt, jobs, njobs, per);
   return hipGetLastError();
 }
 

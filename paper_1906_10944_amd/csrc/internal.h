@@ -61,22 +61,45 @@ int trtri_cols_per_job(bool fp32);
 hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
                         const int64_t* toff, const int64_t* doff, const int* nt,
                         const int2* jobs, int njobs, hipStream_t st);
+// S = X^T X (= A^{-1} for X = L^{-1}) from the transposed tiles k_trtri_win
+// writes; jobs[] = (matrix, I << 16 | J0) for the output tiles (I, J0 ..
+// J0 + lauum_tiles_per_job() - 1), J <= I, in the packed layout of toff.
+int lauum_tiles_per_job();
+hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff, const int* nt,
+                        const int2* jobs, int njobs, hipStream_t st);
 hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
                            hipStream_t st);
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
-// jobs[] = (subdomain, 1 if its inverse factor is FP64 in X64 else FP32 in
-// X32), or (., 2) for the coarse inverse factor XH with vectors xH -> tH
-// (lower) and tH -> yH (upperT).
-hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
-                      const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                      int njobs, int maxnt, const double* xin, double* tout, const double* XH,
-                      int ntc, const double* xH, double* tH, const int* done, hipStream_t st);
-hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff32,
-                       const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                       int njobs, int maxnt, const double* tin, double* yout, const double* XH,
-                       int ntc, const double* tH, double* yH, const int* done, hipStream_t st);
+// y = S x for the symmetric inverses (packed lower tiles, diagonal tiles in
+// full) of all subdomains and the coarse matrix: symv_rows forms the row
+// sums and the partials W, symv_cols then adds the partials (stream order).
+// jobs[] = (subdomain, 1 if its inverse is FP64 in S64 (tiles at toff64)
+// else FP32 in S32 (tiles at toff32)), or (., 2) for the coarse inverse SH
+// with vectors xH -> yH.  W32 / W64 / WH hold TS partials per tile of S32 /
+// S64 / SH, at the same tile offsets.
+struct SymvArgs {
+  const float* S32;
+  const double* S64;
+  const int64_t* toff32;
+  const int64_t* toff64;
+  const int* nt;
+  const int* voff;
+  const int2* jobs;
+  int njobs, maxnt;  // maxnt covers ntc
+  const double* SH;
+  int ntc;
+  float* W32;
+  double* W64;
+  double* WH;
+  const double* x;
+  double* y;
+  const double* xH;
+  double* yH;
+};
+hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st);
+hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,

@@ -1,12 +1,13 @@
-// Triangular products and solves with the packed tile factors.
+// Products with the packed symmetric inverses and triangular solves with the
+// packed tile factors.
 //
-//  * k_trmv_lower / k_trmv_upperT: t = X x and y = X^T t for the inverse
-//    factors X = L^{-1} of the local Dirichlet matrices and of the coarse
-//    matrix, all in one launch.  One wavefront per (matrix, tile row) resp.
-//    (matrix, tile column), longest first; each step loads a whole tile
-//    as 4-column row pieces (vector loads), prefetching the next tile;
-//    accumulation in FP64.  These stream
-//    the factors once each and are HBM-bound.
+//  * k_symv_rows / k_symv_cols: y = S x for the symmetric inverses S =
+//    A^{-1} of the local Dirichlet matrices and of the coarse matrix, all
+//    in one launch each.  The first reads every stored tile once (one
+//    wavefront per (matrix, tile row), longest first), forms the row sums
+//    and leaves the transposed products of the off-diagonal tiles as
+//    partial sums; the second adds those in a fixed order.  HBM-bound on
+//    the one read of S.
 //  * k_trsm_win: X = G^{-1} R and X = G^{-T} R with b <= 32 right-hand sides
 //    for the shift-and-invert eigen sweeps (FP64, one workgroup per
 //    subdomain): windows of 16 tile rows held in registers, a left-looking
@@ -35,32 +36,58 @@ template <> struct Vec4<double> {
   }
 };
 
-// t_i = sum_{k<=i} X_ik x_k: lane (column group l%8, row l/8) loads the
-// 4-column pieces of rows l/8 + 8m (m < 4) of each tile with vector loads
-// (a whole tile per wavefront and step), needs only 4 entries of x per
-// tile, and the 8 column groups of a row are reduced once at the end.  The
-// next tile's pieces are loaded before the current ones are used.
+// Row i of y = S x for one symmetric inverse S (packed lower tiles, the
+// diagonal tiles in full): y_i = sum_{k<=i} S_ik x_k, and for k < i the
+// transposed contribution S_ik^T x_i of the same tile goes to W(i, k) (32
+// partial sums), which k_symv_cols adds to y_k.  So each tile is read once.
+// Lane (column group l%8, row l/8) loads the 4-column pieces of rows l/8 +
+// 8m (m < 4) of each tile with vector loads (a whole tile per wavefront and
+// step), the next tile's pieces before the current ones are used.  The row
+// sums stay in the lane until the end; the column sums are reduced over the
+// 8 lanes of a column group per tile, the 4 sums of a lane spread over the
+// group as they are reduced (4 exchanges instead of 12).  FP64 arithmetic.
 template <typename T>
-__device__ __forceinline__ void trmv_lower_job(const T* __restrict__ Xj, int i,
-                                               const double* __restrict__ xv,
-                                               double* __restrict__ tv, int lane) {
+__device__ __forceinline__ void symv_row(const T* __restrict__ Sj, int i,
+                                         const double* __restrict__ xv, double* __restrict__ yv,
+                                         T* __restrict__ Wj, int lane) {
   const int cg = lane & 7, r0 = lane >> 3;
-  const T* Xr = Xj + tile_idx(i, 0) * TSQ + r0 * TS + cg * 4;
+  const bool h3 = lane & 8, h4 = lane & 16;
+  const T* Sr = Sj + tile_idx(i, 0) * TSQ + r0 * TS + cg * 4;
   const double* xg = xv + cg * 4;
+  double xi[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) xi[m] = xv[i * TS + r0 + 8 * m];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   double a[4][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) Vec4<T>::load(Xr + 8 * m * TS, a[m]);
+  for (int m = 0; m < 4; ++m) Vec4<T>::load(Sr + 8 * m * TS, a[m]);
   for (int k = 0; k <= i; ++k) {
     double nx[4][4];
     const int kn = k < i ? k + 1 : k;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) Vec4<T>::load(Xr + (int64_t)kn * TSQ + 8 * m * TS, nx[m]);
+    for (int m = 0; m < 4; ++m) Vec4<T>::load(Sr + (int64_t)kn * TSQ + 8 * m * TS, nx[m]);
     const double2 x01 = *reinterpret_cast<const double2*>(xg + k * TS);
     const double2 x23 = *reinterpret_cast<const double2*>(xg + k * TS + 2);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
       s[m] += a[m][0] * x01.x + a[m][1] * x01.y + a[m][2] * x23.x + a[m][3] * x23.y;
+    if (k < i) {
+      double c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        c[q] = a[0][q] * xi[0] + a[1][q] * xi[1] + a[2][q] * xi[2] + a[3][q] * xi[3];
+      // bit 3: keep columns 2h3, 2h3+1, pass the other two; bit 4: keep
+      // column 2h3+h4; bit 5: plain sum.  Lanes 0..31 then hold the 32 sums.
+      double k0 = h3 ? c[2] : c[0], k1 = h3 ? c[3] : c[1];
+      const double o0 = h3 ? c[0] : c[2], o1 = h3 ? c[1] : c[3];
+      k0 += __shfl_xor(o0, 8);
+      k1 += __shfl_xor(o1, 8);
+      double e = h4 ? k1 : k0;
+      const double f = h4 ? k0 : k1;
+      e += __shfl_xor(f, 16);
+      e += __shfl_xor(e, 32);
+      if (lane < 32) Wj[tile_idx(i, k) * TS + cg * 4 + 2 * h3 + h4] = (T)e;
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -74,141 +101,69 @@ __device__ __forceinline__ void trmv_lower_job(const T* __restrict__ Xj, int i,
   }
   if (cg == 0) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) tv[i * TS + r0 + 8 * m] = s[m];
-  }
-}
-
-// y_k = sum_{i>=k} X_ik^T t_i: lane (column group l%8, row l/8) loads four
-// 4-column row pieces (rows l/8 + 8m) of each tile with vector loads and
-// the 8 lanes of a column group are reduced at the end.
-template <typename T>
-__device__ __forceinline__ void trmv_upperT_job(const T* __restrict__ Xj, int k, int nt,
-                                                const double* __restrict__ tv,
-                                                double* __restrict__ yv, int lane) {
-  const int cg = lane & 7, r0 = lane >> 3;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  double a[4][4];
-  const T* t0 = Xj + tile_idx(k, k) * TSQ + cg * 4;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) Vec4<T>::load(t0 + (r0 + 8 * m) * TS, a[m]);
-  for (int i = k; i < nt; ++i) {
-    double nx[4][4];
-    const int in = i + 1 < nt ? i + 1 : i;
-    const T* tn = Xj + tile_idx(in, k) * TSQ + cg * 4;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) Vec4<T>::load(tn + (r0 + 8 * m) * TS, nx[m]);
-    const double* ti = tv + i * TS;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const double tr = ti[r0 + 8 * m];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] += a[m][q] * tr;
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[m][q] = nx[m][q];
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    s[q] += __shfl_xor(s[q], 8);
-    s[q] += __shfl_xor(s[q], 16);
-    s[q] += __shfl_xor(s[q], 32);
-  }
-  if (r0 == 0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) yv[k * TS + cg * 4 + q] = s[q];
+    for (int m = 0; m < 4; ++m) yv[i * TS + r0 + 8 * m] = s[m];
   }
 }
 
 // One launch for all subdomains and the coarse problem: jobs[y] = (j, kind)
-// with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse factor (vectors
-// at voff[j]) and kind 2 = the coarse inverse factor XH (ntc tile rows,
-// vectors xH / tH); blockIdx.x = tile row (lower) or tile column (upperT).
-#define TRMV_WAVES 1
-__global__ __launch_bounds__(64 * TRMV_WAVES) void k_trmv_lower(const float* __restrict__ X32,
-                                                   const double* __restrict__ X64,
-                                                   const int64_t* __restrict__ toff32,
-                                                   const int64_t* __restrict__ toff64,
-                                                   const int* __restrict__ ntl,
-                                                   const int* __restrict__ voff,
-                                                   const int2* __restrict__ jobs,
-                                                   const double* __restrict__ xin,
-                                                   double* __restrict__ tout,
-                                                   const double* __restrict__ XH, int ntc,
-                                                   const double* __restrict__ xH,
-                                                   double* __restrict__ tH,
-                                                   const int* __restrict__ done) {
+// with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse (vectors at
+// voff[j], partials at toff[j] * TS) and kind 2 = the coarse inverse SH
+// (ntc tile rows, vectors xH / yH, partials WH); one wavefront per tile
+// row, the longest rows first.
+__global__ __launch_bounds__(64) void k_symv_rows(SymvArgs A, const int* __restrict__ done) {
   if (done && *done) return;
-  const int2 jb = jobs[blockIdx.y];
-  const int lane = threadIdx.x & 63;
-  // the longest rows go first (row i has i + 1 tiles)
-  const int idx = blockIdx.x * TRMV_WAVES + (threadIdx.x >> 6);
-  const int j = jb.x;
+  const int2 jb = A.jobs[blockIdx.y];
+  const int lane = threadIdx.x, idx = blockIdx.x;
   if (jb.y == 2) {
-    if (idx < ntc) trmv_lower_job<double>(XH, ntc - 1 - idx, xH, tH, lane);
+    if (idx < A.ntc) symv_row<double>(A.SH, A.ntc - 1 - idx, A.xH, A.yH, A.WH, lane);
     return;
   }
-  const int nt = ntl[j];
+  const int j = jb.x, nt = A.nt[j];
   if (idx >= nt) return;
-  const int i = nt - 1 - idx;
-  const double* xv = xin + voff[j];
-  double* tv = tout + voff[j];
-  if (jb.y) trmv_lower_job<double>(X64 + toff64[j] * TSQ, i, xv, tv, lane);
-  else trmv_lower_job<float>(X32 + toff32[j] * TSQ, i, xv, tv, lane);
+  const double* xv = A.x + A.voff[j];
+  double* yv = A.y + A.voff[j];
+  if (jb.y)
+    symv_row<double>(A.S64 + A.toff64[j] * TSQ, nt - 1 - idx, xv, yv, A.W64 + A.toff64[j] * TS,
+                     lane);
+  else
+    symv_row<float>(A.S32 + A.toff32[j] * TSQ, nt - 1 - idx, xv, yv, A.W32 + A.toff32[j] * TS,
+                    lane);
 }
 
-__global__ __launch_bounds__(64 * TRMV_WAVES) void k_trmv_upperT(const float* __restrict__ X32,
-                                                    const double* __restrict__ X64,
-                                                    const int64_t* __restrict__ toff32,
-                                                    const int64_t* __restrict__ toff64,
-                                                    const int* __restrict__ ntl,
-                                                    const int* __restrict__ voff,
-                                                    const int2* __restrict__ jobs,
-                                                    const double* __restrict__ tin,
-                                                    double* __restrict__ yout,
-                                                    const double* __restrict__ XH, int ntc,
-                                                    const double* __restrict__ tH,
-                                                    double* __restrict__ yH,
-                                                    const int* __restrict__ done) {
+// y_k += sum_{i>k} W(i, k), i ascending: thread (tile column
+// blockIdx.x * 8 + tid / 32, entry tid % 32) of matrix jobs[blockIdx.y].
+template <typename T>
+__device__ __forceinline__ void symv_col(const T* __restrict__ Wj, int k, int nt, int c,
+                                         double* __restrict__ yv) {
+  double acc = 0.0;
+  for (int i = k + 1; i < nt; ++i) acc += (double)Wj[tile_idx(i, k) * TS + c];
+  yv[k * TS + c] += acc;
+}
+
+__global__ __launch_bounds__(256) void k_symv_cols(SymvArgs A, const int* __restrict__ done) {
   if (done && *done) return;
-  // jobs in reverse order: the lower product that runs just before walks
-  // them forwards, so the factors it read last are still in the Infinity
-  // Cache when this pass starts on them (and vice versa for the next apply)
-  const int2 jb = jobs[gridDim.y - 1 - blockIdx.y];
-  const int lane = threadIdx.x & 63;
-  const int j = jb.x, k = blockIdx.x * TRMV_WAVES + (threadIdx.x >> 6);
+  const int2 jb = A.jobs[blockIdx.y];
+  const int k = blockIdx.x * 8 + (threadIdx.x >> 5), c = threadIdx.x & 31;
   if (jb.y == 2) {
-    if (k < ntc) trmv_upperT_job<double>(XH, k, ntc, tH, yH, lane);
+    if (k < A.ntc) symv_col<double>(A.WH, k, A.ntc, c, A.yH);
     return;
   }
-  const int nt = ntl[j];
+  const int j = jb.x, nt = A.nt[j];
   if (k >= nt) return;
-  const double* tv = tin + voff[j];
-  double* yv = yout + voff[j];
-  if (jb.y) trmv_upperT_job<double>(X64 + toff64[j] * TSQ, k, nt, tv, yv, lane);
-  else trmv_upperT_job<float>(X32 + toff32[j] * TSQ, k, nt, tv, yv, lane);
+  double* yv = A.y + A.voff[j];
+  if (jb.y) symv_col<double>(A.W64 + A.toff64[j] * TS, k, nt, c, yv);
+  else symv_col<float>(A.W32 + A.toff32[j] * TS, k, nt, c, yv);
 }
 
-hipError_t trmv_lower(const float* X32, const double* X64, const int64_t* toff32,
-                      const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                      int njobs, int maxnt, const double* xin, double* tout, const double* XH,
-                      int ntc, const double* xH, double* tH, const int* done, hipStream_t st) {
-  if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmv_lower, dim3((maxnt + TRMV_WAVES - 1) / TRMV_WAVES, njobs),
-                     dim3(64 * TRMV_WAVES), 0, st, X32, X64, toff32, toff64,
-                     nt, voff, jobs, xin, tout, XH, ntc, xH, tH, done);
+hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st) {
+  if (a.njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symv_rows, dim3(a.maxnt, a.njobs), dim3(64), 0, st, a, done);
   return hipGetLastError();
 }
 
-hipError_t trmv_upperT(const float* X32, const double* X64, const int64_t* toff32,
-                       const int64_t* toff64, const int* nt, const int* voff, const int2* jobs,
-                       int njobs, int maxnt, const double* tin, double* yout, const double* XH,
-                       int ntc, const double* tH, double* yH, const int* done, hipStream_t st) {
-  if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmv_upperT, dim3((maxnt + TRMV_WAVES - 1) / TRMV_WAVES, njobs),
-                     dim3(64 * TRMV_WAVES), 0, st, X32, X64, toff32,
-                     toff64, nt, voff, jobs, tin, yout, XH, ntc, tH, yH, done);
+hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st) {
+  if (a.njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symv_cols, dim3((a.maxnt + 7) / 8, a.njobs), dim3(256), 0, st, a, done);
   return hipGetLastError();
 }
 
