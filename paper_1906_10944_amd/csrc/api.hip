@@ -178,6 +178,11 @@ struct geneo_handle_s {
   DBuf<double> rz_part, rr_part;  // PCG partial sums: r.z per 256 rows, r.r per PCG block
   std::vector<int2> ljobs_host;
   int najobs = 0, amaxnt = 0;
+  bool apply_rev = false;  // direction of the next standalone apply
+  DBuf<int2> chunks;       // row chunks of the symmetric products, and their
+  DBuf<int> cstart;        // first chunk per row; row partials per job
+  DBuf<double> Rpart;
+  int nchunk = 0;
   DBuf<int64_t> htoff;
   DBuf<double> Z, SH, WH, rH, yH, AHdense;
   std::vector<int> m_host, nd_host, nN_host, sub_ptr_host;
@@ -209,9 +214,10 @@ void check_csr(const geneo_csr_t* A) {
 // z = M^{-1} r on stream st.  Inside the PCG loop (pcg = true) the first
 // launch also performs the convergence check on the r.r partial sums and
 // the apply is skipped once `done` is set; the combine step always leaves
-// the r.z partial sums (per 256-row block) in h->rz_part.
+// the r.z partial sums (per 256-row block) in h->rz_part.  rev: walk the
+// subdomains in reverse order (consecutive applies alternate).
 hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const int* done,
-                         hipStream_t st, bool pcg = false) {
+                         hipStream_t st, bool pcg, bool rev) {
   hipError_t e;
   if (pcg) {
     if ((e = check_apply_in(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, h->Z.p, h->zoff.p,
@@ -244,6 +250,11 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
   sa.y = h->yl.p;
   sa.xH = h->rH.p;
   sa.yH = h->yH.p;
+  sa.rev = rev;
+  sa.chunks = h->chunks.p;
+  sa.cstart = h->cstart.p;
+  sa.nchunk = h->nchunk;
+  sa.R = h->Rpart.p;
   {
     ProfScope ps("symv", st, h->bytes_symv32 + h->bytes_symv64 + h->bytes_symvH, 0.0);
     if ((e = symv_rows(sa, done, st))) return e;
@@ -862,6 +873,18 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     h->ajobs.upload(aj, st);
     h->najobs = (int)aj.size();
     h->amaxnt = std::max(h->LD.maxnt, h->nc > 0 ? h->ntc : 0);
+    const int cw = symv_chunk_tiles();
+    std::vector<int2> ch;
+    std::vector<int> cs(h->amaxnt + 1);
+    for (int i = 0; i < h->amaxnt; ++i) {
+      cs[i] = (int)ch.size();
+      for (int k0 = 0; k0 <= i; k0 += cw) ch.push_back(make_int2(i, k0));
+    }
+    cs[h->amaxnt] = (int)ch.size();
+    h->nchunk = (int)ch.size();
+    h->chunks.upload(ch, st);
+    h->cstart.upload(cs, st);
+    h->Rpart.alloc((size_t)h->najobs * h->nchunk * TS);
   }
   HIPCHK(hipStreamSynchronize(st));
   h->info.t_phase_ms[0] = tm0.ms();
@@ -927,11 +950,12 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
     converged = 1;
   } else {
     // z = M^{-1} r also leaves the r.z partial sums that alpha needs
-    HIPCHK(apply_enqueue(h, h->r.p, h->z.p, nullptr, st));
+    HIPCHK(apply_enqueue(h, h->r.p, h->z.p, nullptr, st, false, false));
     HIPCHK(copy_vec(h->z.p, h->p.p, n, st));
     const int nrz = (n + 255) / 256;
     // capture PCG_CHUNK iterations: 8 launches each (SpMV, p.Ap, x/r update
-    // with alpha, check + apply input, two triangular products, combine
+    // with alpha, check + apply input, symmetric product and its column
+    // sums, combine
     // with r.z, p update with beta)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -941,7 +965,7 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
       HIPCHK(dot_partial(h->p.p, h->q.p, n, h->partial.p, h->done.p, st));
       HIPCHK(update_xr_alpha(x, h->r.p, h->p.p, h->q.p, n, h->partial.p, h->rz_part.p, nrz, h->sc.p,
                              h->alphas.p, h->rr_part.p, h->done.p, st));
-      HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true));
+      HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true, (k & 1) == 0));
       HIPCHK(update_p_beta(h->p.p, h->z.p, n, h->rz_part.p, nrz, h->sc.p, h->betas.p, h->done.p,
                            st));
     }
@@ -1100,7 +1124,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
 
 int geneo_apply(geneo_handle_t h, const double* r, double* z, void* stream) {
   if (!h || !r || !z || r == z) return finish(GENEO_ERR_ARG, "invalid apply arguments");
-  hipError_t e = apply_enqueue(h, r, z, nullptr, (hipStream_t)stream);
+  hipError_t e = apply_enqueue(h, r, z, nullptr, (hipStream_t)stream, false, h->apply_rev);
+  h->apply_rev = !h->apply_rev;
   if (e != hipSuccess) return finish(GENEO_ERR_HIP, hipGetErrorString(e));
   return GENEO_OK;
 }

@@ -73,8 +73,8 @@ hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
 // y = S x for the symmetric inverses (packed lower tiles, diagonal tiles in
-// full) of all subdomains and the coarse matrix: symv_rows forms the row
-// sums and the partials W, symv_cols then adds the partials (stream order).
+// full) of all subdomains and the coarse matrix: symv_rows forms the
+// partial sums R and W, symv_cols then adds them into y (stream order).
 // jobs[] = (subdomain, 1 if its inverse is FP64 in S64 (tiles at toff64)
 // else FP32 in S32 (tiles at toff32)), or (., 2) for the coarse inverse SH
 // with vectors xH -> yH.  W32 / W64 / WH hold TS partials per tile of S32 /
@@ -97,7 +97,16 @@ struct SymvArgs {
   double* y;
   const double* xH;
   double* yH;
+  int rev;  // take the jobs in reverse order
+  // chunks of the tile rows of the largest matrix (maxnt rows): chunks[t] =
+  // (row, first tile), rows in order; cstart[i] = first chunk of row i
+  // (maxnt + 1 entries); R holds njobs * nchunk row partials of TS sums
+  const int2* chunks;
+  const int* cstart;
+  int nchunk;
+  double* R;
 };
+int symv_chunk_tiles();
 hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,

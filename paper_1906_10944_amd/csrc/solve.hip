@@ -4,10 +4,10 @@
 //  * k_symv_rows / k_symv_cols: y = S x for the symmetric inverses S =
 //    A^{-1} of the local Dirichlet matrices and of the coarse matrix, all
 //    in one launch each.  The first reads every stored tile once (one
-//    wavefront per (matrix, tile row), longest first), forms the row sums
-//    and leaves the transposed products of the off-diagonal tiles as
-//    partial sums; the second adds those in a fixed order.  HBM-bound on
-//    the one read of S.
+//    wavefront per chunk of up to 8 tiles of a tile row) and leaves partial
+//    sums: its chunk's share of the row sums and the transposed products of
+//    the off-diagonal tiles; the second adds those in a fixed order.
+//    HBM-bound on the one read of S.
 //  * k_trsm_win: X = G^{-1} R and X = G^{-T} R with b <= 32 right-hand sides
 //    for the shift-and-invert eigen sweeps (FP64, one workgroup per
 //    subdomain): windows of 16 tile rows held in registers, a left-looking
@@ -20,36 +20,44 @@
 
 namespace geneo {
 
-// Vector of four loaded as a unit from a tile row.
-template <typename T> struct Vec4;
-template <> struct Vec4<float> {
-  static __device__ __forceinline__ void load(const float* p, double* o) {
-    float4 v = *reinterpret_cast<const float4*>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+// Four consecutive entries of a tile row as stored (raw, converted to FP64
+// only where they are used, so a prefetched tile costs 16 / 32 VGPRs).
+template <typename T> struct Piece;
+template <> struct Piece<float> {
+  float4 v;
+  __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
+  __device__ __forceinline__ double at(int q) const {
+    return (double)(q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w);
   }
 };
-template <> struct Vec4<double> {
-  static __device__ __forceinline__ void load(const double* p, double* o) {
-    double2 u = reinterpret_cast<const double2*>(p)[0];
-    double2 v = reinterpret_cast<const double2*>(p)[1];
-    o[0] = u.x; o[1] = u.y; o[2] = v.x; o[3] = v.y;
+template <> struct Piece<double> {
+  double2 u, w;
+  __device__ __forceinline__ void load(const double* p) {
+    u = reinterpret_cast<const double2*>(p)[0];
+    w = reinterpret_cast<const double2*>(p)[1];
+  }
+  __device__ __forceinline__ double at(int q) const {
+    return q == 0 ? u.x : q == 1 ? u.y : q == 2 ? w.x : w.y;
   }
 };
 
-// Row i of y = S x for one symmetric inverse S (packed lower tiles, the
-// diagonal tiles in full): y_i = sum_{k<=i} S_ik x_k, and for k < i the
-// transposed contribution S_ik^T x_i of the same tile goes to W(i, k) (32
-// partial sums), which k_symv_cols adds to y_k.  So each tile is read once.
-// Lane (column group l%8, row l/8) loads the 4-column pieces of rows l/8 +
-// 8m (m < 4) of each tile with vector loads (a whole tile per wavefront and
-// step), the next tile's pieces before the current ones are used.  The row
-// sums stay in the lane until the end; the column sums are reduced over the
-// 8 lanes of a column group per tile, the 4 sums of a lane spread over the
-// group as they are reduced (4 exchanges instead of 12).  FP64 arithmetic.
-template <typename T>
-__device__ __forceinline__ void symv_row(const T* __restrict__ Sj, int i,
-                                         const double* __restrict__ xv, double* __restrict__ yv,
-                                         T* __restrict__ Wj, int lane) {
+// One chunk of row i of y = S x for a symmetric inverse S (packed lower
+// tiles, the diagonal tiles in full): tiles k0 .. k1-1 of the row.  Their
+// share of y_i = sum_{k<=i} S_ik x_k goes to the row partial R (32 sums),
+// and for k < i the transposed product S_ik^T x_i of the same tile to W(i,
+// k) (32 sums): every tile is read once, both partials are added in a
+// fixed order by k_symv_cols.  Lane (column group l%8, row l/8) loads the
+// 4-column pieces of rows l/8 + 8m (m < 4) of a tile with vector loads,
+// with the 4 entries of x_k they multiply; NB tiles are loaded at a time
+// (NB = 4 for FP32 tiles, 2 for FP64: 16 KB in flight per wavefront) and
+// nothing stays in flight from one batch to the next.  The row sums stay
+// in the lane until the end; the column sums are reduced over the 8 lanes
+// of a column group per tile, the 4 sums of a lane spread over the group as
+// they are reduced (4 exchanges instead of 12).  FP64 arithmetic.
+template <typename T, int NB = (sizeof(T) == 4 ? 4 : 2)>
+__device__ __forceinline__ void symv_chunk(const T* __restrict__ Sj, int i, int k0, int k1,
+                                           const double* __restrict__ xv, double* __restrict__ R,
+                                           T* __restrict__ Wj, int lane) {
   const int cg = lane & 7, r0 = lane >> 3;
   const bool h3 = lane & 8, h4 = lane & 16;
   const T* Sr = Sj + tile_idx(i, 0) * TSQ + r0 * TS + cg * 4;
@@ -58,40 +66,57 @@ __device__ __forceinline__ void symv_row(const T* __restrict__ Sj, int i,
 #pragma unroll
   for (int m = 0; m < 4; ++m) xi[m] = xv[i * TS + r0 + 8 * m];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  double a[4][4];
+  struct Buf {
+    Piece<T> a[4];
+    double2 x01, x23;
+  };
+  auto load = [&](Buf& b, int k) {
+    const int kk = min(k, k1 - 1);
+    const T* t = Sr + (int64_t)kk * TSQ;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) Vec4<T>::load(Sr + 8 * m * TS, a[m]);
-  for (int k = 0; k <= i; ++k) {
-    double nx[4][4];
-    const int kn = k < i ? k + 1 : k;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) Vec4<T>::load(Sr + (int64_t)kn * TSQ + 8 * m * TS, nx[m]);
-    const double2 x01 = *reinterpret_cast<const double2*>(xg + k * TS);
-    const double2 x23 = *reinterpret_cast<const double2*>(xg + k * TS + 2);
+    for (int m = 0; m < 4; ++m) b.a[m].load(t + 8 * m * TS);
+    b.x01 = *reinterpret_cast<const double2*>(xg + kk * TS);
+    b.x23 = *reinterpret_cast<const double2*>(xg + kk * TS + 2);
+  };
+  // tile k (in cur) into the row sums; for k < i returns this lane's share
+  // of the transposed product
+  auto use = [&](const Buf& cur, bool offdiag) -> double {
+    const Piece<T>(&a)[4] = cur.a;
+    const double2 x01 = cur.x01, x23 = cur.x23;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-      s[m] += a[m][0] * x01.x + a[m][1] * x01.y + a[m][2] * x23.x + a[m][3] * x23.y;
-    if (k < i) {
-      double c[4];
+      s[m] += a[m].at(0) * x01.x + a[m].at(1) * x01.y + a[m].at(2) * x23.x + a[m].at(3) * x23.y;
+    if (!offdiag) return 0.0;
+    double c[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        c[q] = a[0][q] * xi[0] + a[1][q] * xi[1] + a[2][q] * xi[2] + a[3][q] * xi[3];
-      // bit 3: keep columns 2h3, 2h3+1, pass the other two; bit 4: keep
-      // column 2h3+h4; bit 5: plain sum.  Lanes 0..31 then hold the 32 sums.
-      double k0 = h3 ? c[2] : c[0], k1 = h3 ? c[3] : c[1];
-      const double o0 = h3 ? c[0] : c[2], o1 = h3 ? c[1] : c[3];
-      k0 += __shfl_xor(o0, 8);
-      k1 += __shfl_xor(o1, 8);
-      double e = h4 ? k1 : k0;
-      const double f = h4 ? k0 : k1;
-      e += __shfl_xor(f, 16);
-      e += __shfl_xor(e, 32);
-      if (lane < 32) Wj[tile_idx(i, k) * TS + cg * 4 + 2 * h3 + h4] = (T)e;
+    for (int q = 0; q < 4; ++q)
+      c[q] = a[0].at(q) * xi[0] + a[1].at(q) * xi[1] + a[2].at(q) * xi[2] + a[3].at(q) * xi[3];
+    // bit 3: keep columns 2h3, 2h3+1, pass the other two; bit 4: keep
+    // column 2h3+h4; bit 5: plain sum.  Lanes 0..31 then hold the 32 sums.
+    double e0 = h3 ? c[2] : c[0], e1 = h3 ? c[3] : c[1];
+    const double o0 = h3 ? c[0] : c[2], o1 = h3 ? c[1] : c[3];
+    e0 += __shfl_xor(o0, 8);
+    e1 += __shfl_xor(o1, 8);
+    double e = h4 ? e1 : e0;
+    const double f = h4 ? e0 : e1;
+    e += __shfl_xor(f, 16);
+    e += __shfl_xor(e, 32);
+    return e;
+  };
+  for (int k = k0; k < k1; k += NB) {
+    Buf b[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) load(b[u], k + u);
+    // keep the loads ahead of the arithmetic
+    __builtin_amdgcn_sched_barrier(0);
+    double e[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) e[u] = k + u < k1 ? use(b[u], k + u < i) : 0.0;
+    if (lane < 32) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (k + u < k1 && k + u < i) Wj[tile_idx(i, k + u) * TS + cg * 4 + 2 * h3 + h4] = (T)e[u];
     }
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[m][q] = nx[m][q];
   }
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -101,63 +126,88 @@ __device__ __forceinline__ void symv_row(const T* __restrict__ Sj, int i,
   }
   if (cg == 0) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) yv[i * TS + r0 + 8 * m] = s[m];
+    for (int m = 0; m < 4; ++m) R[r0 + 8 * m] = s[m];
   }
 }
 
-// One launch for all subdomains and the coarse problem: jobs[y] = (j, kind)
-// with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse (vectors at
-// voff[j], partials at toff[j] * TS) and kind 2 = the coarse inverse SH
-// (ntc tile rows, vectors xH / yH, partials WH); one wavefront per tile
-// row, the longest rows first.
+#define SYMV_CHUNK 8
+int symv_chunk_tiles() { return SYMV_CHUNK; }
+
+// One launch for all subdomains and the coarse problem: job q = jobs[.] =
+// (j, kind) with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse
+// (vectors at voff[j], partials W at toff[j] * TS) and kind 2 = the coarse
+// inverse SH (ntc tile rows, vectors xH / yH, partials WH); one wavefront
+// per chunk t = blockIdx.x = (row, first tile) of chunks[] (rows in order,
+// SYMV_CHUNK tiles per chunk), its row partial at R[(q * nchunk + t) *
+// TS].  A job's chunks are dispatched together; with A.rev the jobs are
+// taken in reverse order: consecutive applies alternate, so each starts on
+// the matrices the previous one read last, which are still in the Infinity
+// Cache.
 __global__ __launch_bounds__(64) void k_symv_rows(SymvArgs A, const int* __restrict__ done) {
   if (done && *done) return;
-  const int2 jb = A.jobs[blockIdx.y];
-  const int lane = threadIdx.x, idx = blockIdx.x;
+  const int q = A.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
+  const int2 jb = A.jobs[q];
+  const int lane = threadIdx.x, t = blockIdx.x;
+  const int j = jb.x, nt = jb.y == 2 ? A.ntc : A.nt[j];
+  if (t >= A.cstart[nt]) return;
+  const int2 ch = A.chunks[t];
+  const int i = ch.x, k0 = ch.y, k1 = min(k0 + SYMV_CHUNK, i + 1);
+  double* R = A.R + ((int64_t)q * A.nchunk + t) * TS;
   if (jb.y == 2) {
-    if (idx < A.ntc) symv_row<double>(A.SH, A.ntc - 1 - idx, A.xH, A.yH, A.WH, lane);
+    symv_chunk<double>(A.SH, i, k0, k1, A.xH, R, A.WH, lane);
     return;
   }
-  const int j = jb.x, nt = A.nt[j];
-  if (idx >= nt) return;
   const double* xv = A.x + A.voff[j];
-  double* yv = A.y + A.voff[j];
   if (jb.y)
-    symv_row<double>(A.S64 + A.toff64[j] * TSQ, nt - 1 - idx, xv, yv, A.W64 + A.toff64[j] * TS,
-                     lane);
+    symv_chunk<double>(A.S64 + A.toff64[j] * TSQ, i, k0, k1, xv, R, A.W64 + A.toff64[j] * TS,
+                       lane);
   else
-    symv_row<float>(A.S32 + A.toff32[j] * TSQ, nt - 1 - idx, xv, yv, A.W32 + A.toff32[j] * TS,
-                    lane);
+    symv_chunk<float>(A.S32 + A.toff32[j] * TSQ, i, k0, k1, xv, R, A.W32 + A.toff32[j] * TS,
+                      lane);
 }
 
-// y_k += sum_{i>k} W(i, k), i ascending: thread (tile column
-// blockIdx.x * 8 + tid / 32, entry tid % 32) of matrix jobs[blockIdx.y].
+// y_k = sum of the row partials of row k (chunks in order) + sum_{i>k}
+// W(i, k) (i ascending): thread (tile column blockIdx.x * 8 + tid / 32,
+// entry tid % 32) of job blockIdx.y.
 template <typename T>
-__device__ __forceinline__ void symv_col(const T* __restrict__ Wj, int k, int nt, int c,
+__device__ __forceinline__ void symv_col(const T* __restrict__ Wj, const double* __restrict__ Rq,
+                                         const int* __restrict__ cstart, int k, int nt, int c,
                                          double* __restrict__ yv) {
   double acc = 0.0;
-  for (int i = k + 1; i < nt; ++i) acc += (double)Wj[tile_idx(i, k) * TS + c];
-  yv[k * TS + c] += acc;
+  for (int t = cstart[k]; t < cstart[k + 1]; ++t) acc += Rq[t * TS + c];
+  int i = k + 1;
+  // eight loads in flight, added in order
+  for (; i + 8 <= nt; i += 8) {
+    T w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = Wj[tile_idx(i + u, k) * TS + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)w[u];
+  }
+  for (; i < nt; ++i) acc += (double)Wj[tile_idx(i, k) * TS + c];
+  yv[k * TS + c] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_symv_cols(SymvArgs A, const int* __restrict__ done) {
   if (done && *done) return;
-  const int2 jb = A.jobs[blockIdx.y];
+  const int q = blockIdx.y;
+  const int2 jb = A.jobs[q];
   const int k = blockIdx.x * 8 + (threadIdx.x >> 5), c = threadIdx.x & 31;
+  const double* Rq = A.R + (int64_t)q * A.nchunk * TS;
   if (jb.y == 2) {
-    if (k < A.ntc) symv_col<double>(A.WH, k, A.ntc, c, A.yH);
+    if (k < A.ntc) symv_col<double>(A.WH, Rq, A.cstart, k, A.ntc, c, A.yH);
     return;
   }
   const int j = jb.x, nt = A.nt[j];
   if (k >= nt) return;
   double* yv = A.y + A.voff[j];
-  if (jb.y) symv_col<double>(A.W64 + A.toff64[j] * TS, k, nt, c, yv);
-  else symv_col<float>(A.W32 + A.toff32[j] * TS, k, nt, c, yv);
+  if (jb.y) symv_col<double>(A.W64 + A.toff64[j] * TS, Rq, A.cstart, k, nt, c, yv);
+  else symv_col<float>(A.W32 + A.toff32[j] * TS, Rq, A.cstart, k, nt, c, yv);
 }
 
 hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st) {
   if (a.njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_symv_rows, dim3(a.maxnt, a.njobs), dim3(64), 0, st, a, done);
+  hipLaunchKernelGGL(k_symv_rows, dim3(a.nchunk, a.njobs), dim3(64), 0, st, a, done);
   return hipGetLastError();
 }
 
