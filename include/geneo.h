@@ -231,8 +231,16 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* subs,
  * returns after enqueueing on `stream`. */
 int geneo_apply(geneo_handle_t h, const double* r, double* z, void* stream);
 
-/* Releases every device buffer of the handle.  NULL is ignored. */
+/* Releases every device buffer of the handle (synchronises the device
+ * first).  NULL is ignored.  The library keeps released device blocks, up
+ * to 64 GiB per device, for reuse by later setups; geneo_trim() returns
+ * them to the driver. */
 void geneo_destroy(geneo_handle_t h);
+
+/* Returns the device blocks the library keeps for reuse (released by
+ * destroyed handles and finished setups) to the driver, for the current
+ * device.  Synchronises the device.  GENEO_OK or GENEO_ERR_HIP. */
+int geneo_trim(void);
 
 typedef struct {
   int nsub;

@@ -5,7 +5,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,7 +41,7 @@ struct Err {
 // lists, offsets), so that they are asynchronous: one arena per host
 // thread, reused by consecutive setups of that thread.  A setup resets it
 // at the start; every copy that reads it has completed by then, since each
-// setup ends with (or, on failure, unwinds through) synchronising frees.
+// setup ends (also on failure) with the device synchronised.
 struct PinnedArena {
   std::vector<std::pair<char*, size_t>> chunks;
   size_t chunk = 0, used = 0;
@@ -72,6 +74,111 @@ struct PinnedArena {
 };
 thread_local PinnedArena t_arena;
 
+// Device blocks of the library, kept for reuse: a setup of the same shape
+// as an earlier one then takes its buffers from here instead of the driver
+// (whose allocations, and frees, cost milliseconds each at these sizes and
+// whose frees synchronise the device).  A released block goes to a pending
+// list and becomes reusable only at settle(), which its callers reach after
+// the device has been synchronised: no kernel of the call that released it
+// can still be running.  Reuse takes the smallest free block of at least
+// the request and at most 1/8 larger.  At most kCacheMax free bytes are
+// kept per device; trim() hands all free blocks back (also done, with one
+// retry, when the driver reports out of memory).
+class DevCache {
+ public:
+  static constexpr size_t kCacheMax = (size_t)64 << 30;
+  static DevCache& get() {
+    static DevCache* c = new DevCache;  // never destroyed: no frees at exit
+    return *c;
+  }
+  hipError_t alloc(void** p, size_t bytes, int* dev) {
+    HIPCHK(hipGetDevice(dev));
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto& f = pools_[*dev].free;
+      auto it = f.lower_bound(bytes);
+      if (it != f.end() && it->first <= bytes + bytes / 8) {
+        *p = it->second;
+        sizes_[*p] = it->first;
+        pools_[*dev].free_bytes -= it->first;
+        f.erase(it);
+        return hipSuccess;
+      }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      trim(*dev);
+      e = hipMalloc(p, bytes);
+    }
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> g(mu_);
+      sizes_[*p] = bytes;
+    }
+    return e;
+  }
+  void release(void* p, int dev) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = sizes_.find(p);
+    const size_t bytes = it != sizes_.end() ? it->second : 0;
+    if (it != sizes_.end()) sizes_.erase(it);
+    pools_[dev].pending.push_back({bytes, p});
+  }
+  // the device dev has been synchronised since the pending blocks were released
+  void settle(int dev) {
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      Pool& pl = pools_[dev];
+      for (auto& b : pl.pending) {
+        pl.free.insert(b);
+        pl.free_bytes += b.first;
+      }
+      pl.pending.clear();
+      while (pl.free_bytes > kCacheMax && !pl.free.empty()) {
+        auto it = std::prev(pl.free.end());
+        pl.free_bytes -= it->first;
+        drop.push_back(it->second);
+        pl.free.erase(it);
+      }
+    }
+    for (void* q : drop) (void)hipFree(q);
+  }
+  void trim(int dev) {
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      Pool& pl = pools_[dev];
+      for (auto& b : pl.free) drop.push_back(b.second);
+      pl.free.clear();
+      pl.free_bytes = 0;
+    }
+    for (void* q : drop) (void)hipFree(q);
+  }
+  size_t free_bytes(int dev) {
+    std::lock_guard<std::mutex> g(mu_);
+    return pools_[dev].free_bytes;
+  }
+
+ private:
+  struct Pool {
+    std::multimap<size_t, void*> free;
+    std::vector<std::pair<size_t, void*>> pending;
+    size_t free_bytes = 0;
+  };
+  std::mutex mu_;
+  std::map<int, Pool> pools_;
+  std::map<void*, size_t> sizes_;
+};
+
+// settle() of the current device after synchronising it
+void settle_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  (void)hipDeviceSynchronize();
+  DevCache::get().settle(dev);
+}
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
@@ -80,14 +187,17 @@ struct DBuf {
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
+  int dev = 0;
   void alloc(size_t cnt) {
     release();
     if (cnt == 0) cnt = 1;
-    HIPCHK(hipMalloc((void**)&p, cnt * sizeof(T)));
+    void* q = nullptr;
+    HIPCHK(DevCache::get().alloc(&q, cnt * sizeof(T), &dev));
+    p = (T*)q;
     n = cnt;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) DevCache::get().release(p, dev);
     p = nullptr;
     n = 0;
   }
@@ -1085,6 +1195,9 @@ int geneo_assemble_q1(const geneo_grid_t* grid, const double* coeff, int* A_rowp
     HIPCHK(q1_launch_all(dg.p, g, s, coeff, A_rowptr, A_col, A_val, b, sub_ptr, sub_idx, sub_flags,
                          pou, loc_rowptr, loc_col, an_val, ao_val, nzoff.p, st));
     HIPCHK(hipStreamSynchronize(st));
+    dg.release();
+    nzoff.release();
+    settle_device();
     return GENEO_OK;
   } catch (Err& e) {
     return finish(e.code, e.msg);
@@ -1116,8 +1229,10 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "invalid eigen tolerances");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
+    settle_device();  // the setup's scratch blocks become reusable
     return GENEO_OK;
   } catch (Err& e) {
+    settle_device();
     return finish(e.code, e.msg);
   }
 }
@@ -1134,6 +1249,15 @@ void geneo_destroy(geneo_handle_t h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   delete h;
+  settle_device();
+}
+
+int geneo_trim(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return finish(GENEO_ERR_HIP, "hipGetDevice failed");
+  settle_device();
+  DevCache::get().trim(dev);
+  return GENEO_OK;
 }
 
 int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info) {

@@ -270,6 +270,11 @@ def geneo_destroy(handle):
     handle.close()
 
 
+def geneo_trim():
+    """Return the device blocks the library keeps for reuse to the driver."""
+    _check(lib().geneo_trim())
+
+
 def geneo_get_setup_info(handle):
     info = SetupInfo()
     _check(lib().geneo_get_setup_info(handle.value, C.byref(info)))

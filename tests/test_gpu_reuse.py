@@ -1,0 +1,49 @@
+"""Setups on reused device blocks.
+
+The library keeps the device blocks of destroyed handles and finished
+setups and hands them to the next setup of a similar size; such blocks
+still hold the previous operator's data.  An operator built on them must
+equal, bit for bit, the same operator built on blocks fresh from the
+driver: no kernel may read device memory it has not written.  The stale
+data comes from a different problem on the same mesh (another coefficient
+field, so other eigenvectors, coarse sizes and fallback sets)."""
+import numpy as np
+import pytest
+import synth
+
+from gpu_common import gpu_apply, gpu_assemble, gpu_pcg, gpu_setup, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(sysm, prob, precision, r):
+    h = gpu_setup(sysm, prob, precision=precision)
+    z1 = gpu_apply(h, sysm, r)
+    z2 = gpu_apply(h, sysm, r)  # consecutive applies walk the subdomains in opposite orders
+    x, info = gpu_pcg(h, sysm)
+    h.close()
+    return z1, z2, x, info["iters"]
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_reused_blocks_give_the_same_operator(precision):
+    need_gpu()
+    from paper_1906_10944_amd import geneo as G
+    pb = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    pa = synth.config2_grf(seed=4, n=48, parts=2, ovl=2, inclusions=2)
+    sb, sa = gpu_assemble(pb), gpu_assemble(pa)
+    r = np.random.default_rng(7).standard_normal(pb.ndof)
+    G.geneo_trim()
+    say("[reuse] precision", precision, "fresh blocks")
+    ref = _run(sb, pb, precision, r)
+    assert np.array_equal(ref[0], ref[1])
+    say("[reuse] stale blocks of another coefficient field")
+    _run(sa, pa, precision, r)
+    again = _run(sb, pb, precision, r)
+    say("[reuse] stale blocks of the same operator")
+    third = _run(sb, pb, precision, r)
+    for got in (again, third):
+        for a, b in zip(got[:3], ref[:3]):
+            assert np.array_equal(a, b)
+        assert got[3] == ref[3]
+    G.geneo_trim()
