@@ -264,11 +264,18 @@ int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);
  * row filled with the further computed Ritz values or +inf). */
 int geneo_get_eigenvalues(geneo_handle_t h, int* m, double* lam, int ldl);
 
-/* Host copies of the coarse basis as dense columns over N_j:
- * zoff [nsub+1] column offsets; z [nloc * ?]: see geneo_get_coarse_basis
- * layout below.  `z` receives, for each subdomain j, |N_j| x m_j values
- * row major at offset sum_{i<j} |N_i|*m_i (size sum_j |N_j| m_j).
- * `ah` (optional, may be NULL) receives A_H as nc x nc row major. */
+/* Host copy of the precision of each local inverse A_j^{-1} (Sec. 3):
+ * fp64 [nsub] receives 1 where it is kept in FP64 (FP64 mode, or in mixed
+ * mode a subdomain whose FP32 factor failed the pivot test) and 0 where it
+ * is FP32. */
+int geneo_get_local_precision(geneo_handle_t h, int* fp64);
+
+/* Host copies of the coarse basis as dense columns over N_j: zoff
+ * [nsub+1] receives the column offsets (zoff[j] = sum_{i<j} m_i).  `z`
+ * (optional) receives, for each subdomain j, |N_j| x m_j values row major
+ * at offset sum_{i<j} |N_i| m_i; zsize is its length, at least
+ * sum_j |N_j| m_j.  `ah` (optional, may be NULL) receives A_H as nc x nc
+ * row major. */
 int geneo_get_coarse(geneo_handle_t h, int* zoff, double* z, int64_t zsize,
                      double* ah);
 

@@ -289,10 +289,11 @@ struct geneo_handle_s {
   std::vector<int2> ljobs_host;
   int najobs = 0, amaxnt = 0;
   bool apply_rev = false;  // direction of the next standalone apply
-  DBuf<int2> chunks;       // row chunks of the symmetric products, and their
-  DBuf<int> cstart;        // first chunk per row; row partials per job
+  DBuf<SymvTask> tasks_fwd, tasks_rev;  // symmetric-product tasks, both walk orders
+  DBuf<int> cstart;        // first row chunk per tile row; row partials per job
   DBuf<double> Rpart;
-  int nchunk = 0;
+  int nchunk = 0, ntasks = 0;
+  std::vector<int64_t> toff64_host;
   DBuf<int64_t> htoff;
   DBuf<double> Z, SH, WH, rH, yH, AHdense;
   std::vector<int> m_host, nd_host, nN_host, sub_ptr_host;
@@ -360,8 +361,8 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
   sa.y = h->yl.p;
   sa.xH = h->rH.p;
   sa.yH = h->yH.p;
-  sa.rev = rev;
-  sa.chunks = h->chunks.p;
+  sa.tasks = rev ? h->tasks_rev.p : h->tasks_fwd.p;
+  sa.ntasks = h->ntasks;
   sa.cstart = h->cstart.p;
   sa.nchunk = h->nchunk;
   sa.R = h->Rpart.p;
@@ -539,6 +540,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
   }
   h->toff64.upload(toff64, st);
   h->doff64.upload(doff64, st);
+  h->toff64_host = toff64;
   {
     std::vector<int2> lj(nsub);
     std::vector<char> f(nsub, 0);
@@ -992,9 +994,41 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     }
     cs[h->amaxnt] = (int)ch.size();
     h->nchunk = (int)ch.size();
-    h->chunks.upload(ch, st);
     h->cstart.upload(cs, st);
     h->Rpart.alloc((size_t)h->najobs * h->nchunk * TS);
+    if ((int64_t)h->najobs * h->nchunk * TS > INT32_MAX)
+      fail(GENEO_ERR_ARG, "too many row chunks for the symmetric product");
+    // tasks of job q: its chunks in row order; the two walk orders differ
+    // only in the order of the jobs
+    auto add_job = [&](std::vector<SymvTask>& out, int q) {
+      const int2 jb = aj[q];
+      int64_t toff = 0;
+      int xoff = 0, nt = h->ntc;
+      if (jb.y != 2) {
+        toff = jb.y ? h->toff64_host[jb.x] : h->LD.toff[jb.x];
+        xoff = h->LD.voff[jb.x];
+        nt = h->LD.nt[jb.x];
+      }
+      for (int t = 0; t < cs[nt]; ++t) {
+        SymvTask k;
+        const int i = ch[t].x, k0 = ch[t].y;
+        k.s_row = (toff + tile_idx(i, 0)) * TSQ;
+        k.w_row = (toff + tile_idx(i, 0)) * TS;
+        k.xoff = xoff;
+        k.r_off = (q * h->nchunk + t) * TS;
+        k.i = (short)i;
+        k.k0 = (short)k0;
+        k.k1 = (short)std::min(k0 + cw, i + 1);
+        k.kind = (short)jb.y;
+        out.push_back(k);
+      }
+    };
+    std::vector<SymvTask> tf, tr;
+    for (int q = 0; q < h->najobs; ++q) add_job(tf, q);
+    for (int q = h->najobs - 1; q >= 0; --q) add_job(tr, q);
+    h->ntasks = (int)tf.size();
+    h->tasks_fwd.upload(tf, st);
+    h->tasks_rev.upload(tr, st);
   }
   HIPCHK(hipStreamSynchronize(st));
   h->info.t_phase_ms[0] = tm0.ms();
@@ -1275,6 +1309,12 @@ int geneo_get_eigenvalues(geneo_handle_t h, int* m, double* lam, int ldl) {
                                       ? h->lam_host[(int64_t)j * h->b + c]
                                       : INFINITY;
   }
+  return GENEO_OK;
+}
+
+int geneo_get_local_precision(geneo_handle_t h, int* fp64) {
+  if (!h || !fp64) return finish(GENEO_ERR_ARG, "NULL argument");
+  for (int j = 0; j < h->nsub; ++j) fp64[j] = h->ljobs_host[j].y;
   return GENEO_OK;
 }
 

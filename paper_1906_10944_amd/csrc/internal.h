@@ -79,6 +79,17 @@ hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
 // else FP32 in S32 (tiles at toff32)), or (., 2) for the coarse inverse SH
 // with vectors xH -> yH.  W32 / W64 / WH hold TS partials per tile of S32 /
 // S64 / SH, at the same tile offsets.
+// One wavefront's work in symv_rows: tiles k0 .. k1-1 of tile row i of one
+// matrix, kind 0 / 1 / 2 = FP32 subdomain (S32, W32), FP64 subdomain (S64,
+// W64), coarse (SH, WH, vectors xH / yH).  Built on the host, one load per
+// wavefront.
+struct SymvTask {
+  int64_t s_row;  // element offset of tile (i, 0) in S32 / S64 / SH
+  int64_t w_row;  // element offset of W(i, 0) in W32 / W64 / WH
+  int xoff;       // offset of the matrix's vectors in x / y (0 for the coarse)
+  int r_off;      // element offset of this chunk's row partial in R
+  short i, k0, k1, kind;
+};
 struct SymvArgs {
   const float* S32;
   const double* S64;
@@ -97,11 +108,13 @@ struct SymvArgs {
   double* y;
   const double* xH;
   double* yH;
-  int rev;  // take the jobs in reverse order
-  // chunks of the tile rows of the largest matrix (maxnt rows): chunks[t] =
-  // (row, first tile), rows in order; cstart[i] = first chunk of row i
-  // (maxnt + 1 entries); R holds njobs * nchunk row partials of TS sums
-  const int2* chunks;
+  // symv_rows: one task per wavefront (ntasks), jobs in walk order
+  const SymvTask* tasks;
+  int ntasks;
+  // chunks of the tile rows of the largest matrix (maxnt rows), rows in
+  // order, symv_chunk_tiles() tiles each: cstart[i] = first chunk of row i
+  // (maxnt + 1 entries); R holds njobs * nchunk row partials of TS sums,
+  // job q's chunk t at (q * nchunk + t) * TS
   const int* cstart;
   int nchunk;
   double* R;

@@ -55,12 +55,12 @@ template <> struct Piece<double> {
 // of a column group per tile, the 4 sums of a lane spread over the group as
 // they are reduced (4 exchanges instead of 12).  FP64 arithmetic.
 template <typename T, int NB = (sizeof(T) == 4 ? 4 : 2)>
-__device__ __forceinline__ void symv_chunk(const T* __restrict__ Sj, int i, int k0, int k1,
+__device__ __forceinline__ void symv_chunk(const T* __restrict__ Srow, int i, int k0, int k1,
                                            const double* __restrict__ xv, double* __restrict__ R,
-                                           T* __restrict__ Wj, int lane) {
+                                           T* __restrict__ Wrow, int lane) {
   const int cg = lane & 7, r0 = lane >> 3;
   const bool h3 = lane & 8, h4 = lane & 16;
-  const T* Sr = Sj + tile_idx(i, 0) * TSQ + r0 * TS + cg * 4;
+  const T* Sr = Srow + r0 * TS + cg * 4;
   const double* xg = xv + cg * 4;
   double xi[4];
 #pragma unroll
@@ -115,7 +115,7 @@ __device__ __forceinline__ void symv_chunk(const T* __restrict__ Sj, int i, int 
     if (lane < 32) {
 #pragma unroll
       for (int u = 0; u < NB; ++u)
-        if (k + u < k1 && k + u < i) Wj[tile_idx(i, k + u) * TS + cg * 4 + 2 * h3 + h4] = (T)e[u];
+        if (k + u < k1 && k + u < i) Wrow[(k + u) * TS + cg * 4 + 2 * h3 + h4] = (T)e[u];
     }
   }
 #pragma unroll
@@ -133,36 +133,25 @@ __device__ __forceinline__ void symv_chunk(const T* __restrict__ Sj, int i, int 
 #define SYMV_CHUNK 8
 int symv_chunk_tiles() { return SYMV_CHUNK; }
 
-// One launch for all subdomains and the coarse problem: job q = jobs[.] =
-// (j, kind) with kind 0 / 1 = subdomain j with an FP32 / FP64 inverse
-// (vectors at voff[j], partials W at toff[j] * TS) and kind 2 = the coarse
-// inverse SH (ntc tile rows, vectors xH / yH, partials WH); one wavefront
-// per chunk t = blockIdx.x = (row, first tile) of chunks[] (rows in order,
-// SYMV_CHUNK tiles per chunk), its row partial at R[(q * nchunk + t) *
-// TS].  A job's chunks are dispatched together; with A.rev the jobs are
-// taken in reverse order: consecutive applies alternate, so each starts on
-// the matrices the previous one read last, which are still in the Infinity
-// Cache.
+// One launch for all subdomains and the coarse problem, one wavefront per
+// task (a chunk of up to SYMV_CHUNK tiles of a tile row), whose
+// descriptor is the wavefront's only dependent load before it streams
+// tiles.  The tasks of a job are consecutive; the host passes the tasks in
+// one of two walk orders over the jobs, alternating between applies, so
+// each apply starts on the matrices the previous one read last, which are
+// still in the Infinity Cache.
 __global__ __launch_bounds__(64) void k_symv_rows(SymvArgs A, const int* __restrict__ done) {
   if (done && *done) return;
-  const int q = A.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
-  const int2 jb = A.jobs[q];
-  const int lane = threadIdx.x, t = blockIdx.x;
-  const int j = jb.x, nt = jb.y == 2 ? A.ntc : A.nt[j];
-  if (t >= A.cstart[nt]) return;
-  const int2 ch = A.chunks[t];
-  const int i = ch.x, k0 = ch.y, k1 = min(k0 + SYMV_CHUNK, i + 1);
-  double* R = A.R + ((int64_t)q * A.nchunk + t) * TS;
-  if (jb.y == 2) {
-    symv_chunk<double>(A.SH, i, k0, k1, A.xH, R, A.WH, lane);
-    return;
-  }
-  const double* xv = A.x + A.voff[j];
-  if (jb.y)
-    symv_chunk<double>(A.S64 + A.toff64[j] * TSQ, i, k0, k1, xv, R, A.W64 + A.toff64[j] * TS,
+  const SymvTask tk = A.tasks[blockIdx.x];
+  const int lane = threadIdx.x;
+  double* R = A.R + tk.r_off;
+  if (tk.kind == 2)
+    symv_chunk<double>(A.SH + tk.s_row, tk.i, tk.k0, tk.k1, A.xH, R, A.WH + tk.w_row, lane);
+  else if (tk.kind == 1)
+    symv_chunk<double>(A.S64 + tk.s_row, tk.i, tk.k0, tk.k1, A.x + tk.xoff, R, A.W64 + tk.w_row,
                        lane);
   else
-    symv_chunk<float>(A.S32 + A.toff32[j] * TSQ, i, k0, k1, xv, R, A.W32 + A.toff32[j] * TS,
+    symv_chunk<float>(A.S32 + tk.s_row, tk.i, tk.k0, tk.k1, A.x + tk.xoff, R, A.W32 + tk.w_row,
                       lane);
 }
 
@@ -206,8 +195,8 @@ __global__ __launch_bounds__(256) void k_symv_cols(SymvArgs A, const int* __rest
 }
 
 hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st) {
-  if (a.njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_symv_rows, dim3(a.nchunk, a.njobs), dim3(64), 0, st, a, done);
+  if (a.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symv_rows, dim3(a.ntasks), dim3(64), 0, st, a, done);
   return hipGetLastError();
 }
 

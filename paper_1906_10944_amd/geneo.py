@@ -105,6 +105,7 @@ def lib():
     L.geneo_get_setup_info.argtypes = [vp, C.POINTER(SetupInfo)]
     L.geneo_get_eigenvalues.argtypes = [vp, vp, vp, i]
     L.geneo_get_coarse.argtypes = [vp, vp, vp, i64, vp]
+    L.geneo_get_local_precision.argtypes = [vp, vp]
     L.pcg_solve.argtypes = [C.POINTER(Csr), vp, vp, vp, i, d, i, C.POINTER(PcgInfo), vp]
     L.geneo_spmv.argtypes = [C.POINTER(Csr), vp, vp, vp]
     for f in ("geneo_q1_sizes", "geneo_assemble_q1", "geneo_setup", "geneo_apply",
@@ -288,6 +289,13 @@ def geneo_get_eigenvalues(handle, nsub, ldl=64):
     lam = np.zeros((nsub, ldl), dtype=np.float64)
     _check(lib().geneo_get_eigenvalues(handle.value, m.ctypes.data, lam.ctypes.data, ldl))
     return m, lam
+
+
+def geneo_get_local_precision(handle, nsub):
+    """1 where subdomain j's local inverse is FP64, 0 where it is FP32."""
+    f = np.zeros(nsub, dtype=np.int32)
+    _check(lib().geneo_get_local_precision(handle.value, f.ctypes.data))
+    return f
 
 
 def geneo_get_coarse(handle, nsub, with_ah=True):
