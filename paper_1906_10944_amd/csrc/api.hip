@@ -405,7 +405,7 @@ struct SetupScratch {
   DBuf<double> XT64, XTH;
   DBuf<int2> ljobs32, ljobs64, ljobsH;
   DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
-  DBuf<int> ebad, scount, sflag;
+  DBuf<int> ebad, scount, sflag, hjob;
   DBuf<double> sbest;
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
   DBuf<uint8_t> adj;
@@ -446,6 +446,9 @@ std::vector<int2> trtri_job_list(const std::vector<int>& mats, const std::vector
       if (c0 < nt[j]) tj.push_back(make_int2(j, c0));
   return tj;
 }
+
+// Up to this many FP64 refactors use the tile-column-step factorisation.
+constexpr int kStepCholMax = 32;
 
 // Jobs of S = X^T X: (matrix, I << 16 | J0) for the output tiles (I, J0 ..
 // J0 + lauum_tiles_per_job() - 1) of each tile row I, matrix by matrix and
@@ -563,9 +566,19 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
                                       h->dmap.p, h->dglob.p, h->dscale.p, A, st));
     }
     {
+      // a few refactors (mixed mode): tile-column steps over many short
+      // workgroups, which leave the CUs to the eigen sweeps in between; a
+      // full batch (FP64 mode): one workgroup per matrix
       ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
-      HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p, h->doff64.p,
-                                 X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
+      if (h->njobs64 <= kStepCholMax) {
+        int mx = 0;
+        for (int j : f64list) mx = std::max(mx, h->LD.nt[j]);
+        HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
+                                 h->jobs64.p, h->njobs64, mx, X.status.p, st));
+      } else {
+        HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p,
+                                   h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
+      }
     }
     std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
     X.tjobs64.upload(tj, st);
@@ -846,15 +859,17 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     // ---- coarse Cholesky and inverse factor
     tm[3].start(sb);
     X.cst.alloc(1);
-    {
-      ProfScope ps("coarse_chol", sb, 8.0 * packed(nc), std::pow((double)nc, 3) / 3.0);
-      HIPCHK(coarse_cholesky(X.AHt.p, X.DH.p, h->ntc, X.cst.p, sb));
-    }
-    if (download(X.cst.p, 1, sb)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
     h->hnt.upload(std::vector<int>{h->ntc}, sb);
     h->htoff.upload(std::vector<int64_t>{0}, sb);
-    h->bytes_symvH = 8.0 * packed(nc) + 16.0 * nc;
     X.hdoff.upload(std::vector<int64_t>{0}, sb);
+    X.hjob.upload(std::vector<int>{0}, sb);
+    {
+      ProfScope ps("coarse_chol", sb, 8.0 * packed(nc), std::pow((double)nc, 3) / 3.0);
+      HIPCHK(launch_chol_steps(X.AHt.p, X.DH.p, h->htoff.p, X.hdoff.p, h->hnt.p, X.hjob.p, 1,
+                               h->ntc, X.cst.p, sb));
+    }
+    if (download(X.cst.p, 1, sb)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
+    h->bytes_symvH = 8.0 * packed(nc) + 16.0 * nc;
     std::vector<int2> tj = trtri_job_list(std::vector<int>{0}, std::vector<int>{h->ntc}, false);
     X.tjobsH.upload(tj, sb);
     std::vector<int2> lj = lauum_job_list(std::vector<int>{0}, std::vector<int>{h->ntc});

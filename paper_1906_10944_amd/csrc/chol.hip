@@ -15,9 +15,11 @@
 //    matrix and records 1 + the failing row in `status`.
 //  * k_trtri_win: X = L^{-1}, one workgroup per (matrix, block of tile
 //    columns): windowed forward substitution L X(:, C) = E_C on MFMA.
-//  * coarse_cholesky: right-looking tiled factorisation of the single coarse
-//    matrix, one launch per phase (diagonal, panel, trailing update) so that
-//    the trailing update spreads over the whole chip.
+//  * k_step_potrf / k_step_trsm / k_step_update: right-looking tiled
+//    factorisation of a few matrices (the coarse matrix, the FP64 refactors
+//    of mixed mode) by tile-column steps, one launch per phase (diagonal,
+//    panel, trailing update) over all of them, so that the trailing update
+//    spreads over the whole chip.
 //
 // The contraction index of every 32-wide product is permuted so that a lane
 // reads 8 consecutive elements of one row (vector loads): lane
@@ -796,25 +798,45 @@ hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff,
 }
 
 // ------------------------------------------------------- coarse matrix ---
-__global__ __launch_bounds__(64) void k_cpotrf(double* __restrict__ A, double* __restrict__ Di,
-                                               int k, int* __restrict__ status) {
+// Right-looking Cholesky by tile-column steps, batched over matrices
+// jobs[blockIdx.y] (tiles at toff, inverted diagonal tiles at doff): step k
+// factors and inverts the diagonal tile (one wavefront), forms the column
+// panel L_ik = A_ik Linv_kk^T (one workgroup per tile) and updates the
+// trailing matrix A_ij -= L_ik L_jk^T (one workgroup per tile).  For a few
+// matrices (the coarse matrix, the FP64 refactors of mixed mode) this uses
+// many short workgroups instead of holding one CU per matrix for the whole
+// factorisation.  status[j] = 0, or TS k + f at the first failed pivot
+// (set by step 0, later steps then skip the matrix).
+__global__ __launch_bounds__(64) void k_step_potrf(double* __restrict__ A, double* __restrict__ Di,
+                                                   const int64_t* __restrict__ toff,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int* __restrict__ ntl,
+                                                   const int* __restrict__ jobs, int k,
+                                                   int* __restrict__ status) {
   __shared__ double sRp[TS];
-  if (*status) return;
-  double* D = A + tile_idx(k, k) * TSQ;
-  const int f = diag_tile<double, TS + 2>(D, D, Di + (int64_t)k * TSQ, nullptr, sRp, threadIdx.x, 0.0);
-  if (f && threadIdx.x == 0) *status = k * TS + f;
+  const int j = jobs[blockIdx.x];
+  if (k >= ntl[j] || (k > 0 && status[j])) return;
+  double* D = A + (toff[j] + tile_idx(k, k)) * TSQ;
+  const int f = diag_tile<double, TS + 2>(D, D, Di + (doff[j] + k) * TSQ, nullptr, sRp,
+                                          threadIdx.x, 0.0);
+  if (threadIdx.x == 0 && (f || k == 0)) status[j] = f ? k * TS + f : 0;
 }
 
 // L_ik = A_ik Linv_kk^T, one workgroup per tile i > k
-__global__ __launch_bounds__(256) void k_ctrsm(double* __restrict__ A,
-                                               const double* __restrict__ Di, int k,
-                                               const int* __restrict__ status) {
-  if (*status) return;
+__global__ __launch_bounds__(256) void k_step_trsm(double* __restrict__ A,
+                                                   const double* __restrict__ Di,
+                                                   const int64_t* __restrict__ toff,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int* __restrict__ ntl,
+                                                   const int* __restrict__ jobs, int k,
+                                                   const int* __restrict__ status) {
+  const int j = jobs[blockIdx.y];
   const int i = k + 1 + blockIdx.x;
+  if (i >= ntl[j] || status[j]) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rq = w >> 1, cq = w & 1;
-  double* X = A + tile_idx(i, k) * TSQ;
-  const double* Y = Di + (int64_t)k * TSQ;
+  double* X = A + (toff[j] + tile_idx(i, k)) * TSQ;
+  const double* Y = Di + (doff[j] + k) * TSQ;
   d4_t acc = acc_zero<double>();
   q_xyT<double>(acc, X + rq * 16 * TS, TS, Y + cq * 16 * TS, TS, lane);
   block_sync();
@@ -823,10 +845,15 @@ __global__ __launch_bounds__(256) void k_ctrsm(double* __restrict__ A,
 }
 
 // A_ij -= L_ik L_jk^T for k < j <= i; blockIdx.x enumerates the trailing tiles
-__global__ __launch_bounds__(256) void k_cupdate(double* __restrict__ A, int k, int nt,
-                                                 const int* __restrict__ status) {
-  if (*status) return;
-  // map blockIdx.x -> (i, j) over the lower triangle of the trailing matrix
+__global__ __launch_bounds__(256) void k_step_update(double* __restrict__ A,
+                                                     const int64_t* __restrict__ toff,
+                                                     const int* __restrict__ ntl,
+                                                     const int* __restrict__ jobs, int k,
+                                                     const int* __restrict__ status) {
+  const int j = jobs[blockIdx.y];
+  const int nt = ntl[j];
+  if (status[j]) return;
+  // map blockIdx.x -> (i, jj) over the lower triangle of the trailing matrix
   int t = blockIdx.x;
   int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
@@ -838,24 +865,28 @@ __global__ __launch_bounds__(256) void k_cupdate(double* __restrict__ A, int k, 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rq = w >> 1, cq = w & 1;
   if (i == jj && rq == 0 && cq == 1) return;
+  const double* Aj = A + toff[j] * TSQ;
   d4_t acc = acc_zero<double>();
-  q_xyT<double>(acc, A + tile_idx(i, k) * TSQ + rq * 16 * TS, TS,
-                A + tile_idx(jj, k) * TSQ + cq * 16 * TS, TS, lane);
-  double* C = A + tile_idx(i, jj) * TSQ + rq * 16 * TS + cq * 16;
+  q_xyT<double>(acc, Aj + tile_idx(i, k) * TSQ + rq * 16 * TS, TS,
+                Aj + tile_idx(jj, k) * TSQ + cq * 16 * TS, TS, lane);
+  double* C = A + (toff[j] + tile_idx(i, jj)) * TSQ + rq * 16 * TS + cq * 16;
 #pragma unroll
   for (int v = 0; v < 4; ++v) C[acc_row<double>(lane, v) * TS + acc_col(lane)] -= acc[v];
 }
 
-hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(status, 0, sizeof(int), st);
-  if (e != hipSuccess) return e;
-  for (int k = 0; k < nt; ++k) {
-    hipLaunchKernelGGL(k_cpotrf, dim3(1), dim3(64), 0, st, tiles, dinv, k, status);
-    int rem = nt - k - 1;
+hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
+                             const int64_t* doff, const int* nt, const int* jobs, int njobs,
+                             int maxnt, int* status, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  for (int k = 0; k < maxnt; ++k) {
+    hipLaunchKernelGGL(k_step_potrf, dim3(njobs), dim3(64), 0, st, tiles, dinv, toff, doff, nt,
+                       jobs, k, status);
+    const int rem = maxnt - k - 1;
     if (rem > 0) {
-      hipLaunchKernelGGL(k_ctrsm, dim3(rem), dim3(256), 0, st, tiles, dinv, k, status);
-      int nupd = rem * (rem + 1) / 2;
-      hipLaunchKernelGGL(k_cupdate, dim3(nupd), dim3(256), 0, st, tiles, k, nt, status);
+      hipLaunchKernelGGL(k_step_trsm, dim3(rem, njobs), dim3(256), 0, st, tiles, dinv, toff,
+                         doff, nt, jobs, k, status);
+      hipLaunchKernelGGL(k_step_update, dim3(rem * (rem + 1) / 2, njobs), dim3(256), 0, st,
+                         tiles, toff, nt, jobs, k, status);
     }
   }
   return hipGetLastError();

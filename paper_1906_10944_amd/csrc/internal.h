@@ -67,8 +67,14 @@ hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
 int lauum_tiles_per_job();
 hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff, const int* nt,
                         const int2* jobs, int njobs, hipStream_t st);
-hipError_t coarse_cholesky(double* tiles, double* dinv, int nt, int* status,
-                           hipStream_t st);
+// FP64 Cholesky of matrices jobs[0 .. njobs-1] (tiles at toff, inverted
+// diagonal tiles to doff) by right-looking tile-column steps, 3 launches per
+// step over all of them (maxnt = largest tile order): for a few matrices,
+// where one workgroup per matrix would hold CUs for the whole
+// factorisation.  status[j] = 0 or TS k + f at the first failed pivot.
+hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
+                             const int64_t* doff, const int* nt, const int* jobs, int njobs,
+                             int maxnt, int* status, hipStream_t st);
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
