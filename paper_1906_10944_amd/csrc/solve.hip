@@ -21,11 +21,18 @@
 namespace geneo {
 
 // Four consecutive entries of a tile row as stored (raw, converted to FP64
-// only where they are used, so a prefetched tile costs 16 / 32 VGPRs).
+// only where they are used, so a prefetched tile costs 16 / 32 VGPRs).  The
+// inverses are streamed once per apply with nontemporal loads, which keeps
+// them from displacing the vectors and partial sums in the caches (those
+// are then read back by k_symv_cols without going to HBM).
 template <typename T> struct Piece;
 template <> struct Piece<float> {
   float4 v;
-  __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const float4*>(p); }
+  __device__ __forceinline__ void load(const float* p) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    v = make_float4(t[0], t[1], t[2], t[3]);
+  }
   __device__ __forceinline__ double at(int q) const {
     return (double)(q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w);
   }
@@ -33,8 +40,11 @@ template <> struct Piece<float> {
 template <> struct Piece<double> {
   double2 u, w;
   __device__ __forceinline__ void load(const double* p) {
-    u = reinterpret_cast<const double2*>(p)[0];
-    w = reinterpret_cast<const double2*>(p)[1];
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    const d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p) + 1);
+    u = make_double2(a[0], a[1]);
+    w = make_double2(b[0], b[1]);
   }
   __device__ __forceinline__ double at(int q) const {
     return q == 0 ? u.x : q == 1 ? u.y : q == 2 ? w.x : w.y;
