@@ -405,7 +405,8 @@ struct SetupScratch {
   DBuf<double> XT64, XTH;
   DBuf<int2> ljobs32, ljobs64, ljobsH;
   DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
-  DBuf<int> ebad, scount, sflag, hjob;
+  DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol;
+  DBuf<double> bval;
   DBuf<double> sbest;
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
   DBuf<uint8_t> adj;
@@ -693,6 +694,16 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   }
   // ---- block subspace iteration on S = G^{-1} B G^{-T}
   tm[1].start(sb);
+  {
+    // compact B_j = X_j A^o_j X_j, sized by the nonzeros of the A^o batch
+    const int nnz = download(Ao->rowptr + h->nloc, 1, sb)[0];
+    X.bcnt.alloc(h->nloc);
+    X.brp.alloc(h->nloc + 1);
+    X.bcol.alloc(std::max(nnz, 1));
+    X.bval.alloc(std::max(nnz, 1));
+    HIPCHK(launch_bcompact(S->sub_ptr, S->pou, Ao, nsub, h->nloc, LN.maxnt * TS, X.bcnt.p,
+                           X.brp.p, X.bcol.p, X.bval.p, sb));
+  }
   HIPCHK(fill_i32(X.active.p, 1, nsub, sb));
   HIPCHK(launch_eig_init(X.U.p, S->sub_ptr, X.voffN.p, X.ntN.p, nsub, b, o.seed, sb));
   EigWork wk;
@@ -738,8 +749,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     }
     {
       ProfScope ps("bapply", sb, vb, 0.0);
-      HIPCHK(launch_bapply(S->sub_ptr, S->pou, Ao, X.voffN.p, X.ntN.p, nsub, b, X.T.p, X.W.p,
-                           X.active.p, LN.maxnt, sb));
+      HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.voffN.p, X.ntN.p, nsub, b,
+                           X.T.p, X.W.p, X.active.p, LN.maxnt, sb));
     }
     {
       ProfScope ps("trsm_fwd", sb, gb + vb, tf);
@@ -769,8 +780,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       for (int k = 1; k < o.eig_cheb; ++k) {
         HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
                                X.U.p, X.T.p, X.active.p, sb));
-        HIPCHK(launch_bapply(S->sub_ptr, S->pou, Ao, X.voffN.p, X.ntN.p, nsub, b, X.T.p, X.W.p,
-                             X.active.p, LN.maxnt, sb));
+        HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.voffN.p, X.ntN.p, nsub,
+                             b, X.T.p, X.W.p, X.active.p, LN.maxnt, sb));
         HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
                                X.W.p, X.T.p, X.active.p, sb));
         HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, X.P.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,

@@ -15,7 +15,8 @@
 //    the window with the inverted diagonal tiles.
 //  * k_trsm_fwd / k_trsm_bwd: the same solves row by row for wider blocks
 //    (inner sums split over tile slices, reduced in LDS).
-//  * k_bapply: Y = X_j A^o_j X_j X (the B-matrix of the GenEO eigenproblem).
+//  * k_bapply: Y = X_j A^o_j X_j X (the B-matrix of the GenEO eigenproblem),
+//    from a compact copy of B_j built once per setup (k_bcompact).
 #include "internal.h"
 
 namespace geneo {
@@ -610,15 +611,65 @@ hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* t
   return hipGetLastError();
 }
 
-// Y = X_j A^o_j X_j X over the padded N_j rows (zero on padding).
-// One thread per (row a, column c) of the padded block, a 2D grid over
-// (element chunk, subdomain) so that the dependent index/value/X loads of
-// many rows are in flight at once.
+// B_j = X_j A^o_j X_j (the B-matrix of the GenEO eigenproblem) in compact
+// CSR over the local rows: only the entries that are nonzero in B_j (the
+// overlap matrix shares the Neumann matrix's pattern and is zero away from
+// the overlap zone), scaled by mu_a mu_q.  Built once per setup: a count
+// pass, an exclusive scan, a fill pass (thread per local row, 2D grid over
+// (row chunk, subdomain)).
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_bcompact(const int* __restrict__ sub_ptr,
+                                                  const double* __restrict__ pou,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ colx,
+                                                  const double* __restrict__ val,
+                                                  int* __restrict__ cnt,
+                                                  const int* __restrict__ brp,
+                                                  int* __restrict__ bcol,
+                                                  double* __restrict__ bval) {
+  const int j = blockIdx.y;
+  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const double mua = pou[s0 + a];
+  int k = 0;
+  const int o = FILL ? brp[s0 + a] : 0;
+  if (mua != 0.0) {
+    for (int p = rp[s0 + a]; p < rp[s0 + a + 1]; ++p) {
+      const int q = colx[p];
+      const double w = mua * val[p] * pou[s0 + q];
+      if (w == 0.0) continue;
+      if (FILL) {
+        bcol[o + k] = q;
+        bval[o + k] = w;
+      }
+      ++k;
+    }
+  }
+  if (!FILL) cnt[s0 + a] = k;
+}
+
+hipError_t launch_bcompact(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
+                           int nsub, int64_t nloc, int maxrows, int* cnt, int* brp, int* bcol,
+                           double* bval, hipStream_t st) {
+  const dim3 grid((maxrows + 255) / 256, nsub);
+  hipLaunchKernelGGL(k_bcompact<false>, grid, dim3(256), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
+                     Ao->val, cnt, nullptr, nullptr, nullptr);
+  hipError_t e = scan_exclusive_i32(cnt, brp, nloc, nullptr, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bcompact<true>, grid, dim3(256), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
+                     Ao->val, nullptr, brp, bcol, bval);
+  return hipGetLastError();
+}
+
+// Y = B_j X over the padded N_j rows (zero on padding and away from the
+// overlap zone).  One thread per (row a, column c) of the padded block, a 2D
+// grid over (element chunk, subdomain) so that the dependent index/value/X
+// loads of many rows are in flight at once.
 __global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
-                                               const double* __restrict__ pou,
-                                               const int* __restrict__ rp,
-                                               const int* __restrict__ colx,
-                                               const double* __restrict__ val,
+                                               const int* __restrict__ brp,
+                                               const int* __restrict__ bcol,
+                                               const double* __restrict__ bval,
                                                const int* __restrict__ voff,
                                                const int* __restrict__ ntl, int b,
                                                const double* __restrict__ X,
@@ -634,25 +685,18 @@ __global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
   const int a = t / b, c = t % b;
   double s = 0.0;
   if (a < n) {
-    const double mua = pou[s0 + a];
-    if (mua != 0.0) {
-      const int p0 = rp[s0 + a], p1 = rp[s0 + a + 1];
-      for (int p = p0; p < p1; ++p) {
-        const int q = colx[p];
-        s += val[p] * pou[s0 + q] * Xj[(int64_t)q * b + c];
-      }
-      s *= mua;
-    }
+    const int p0 = brp[s0 + a], p1 = brp[s0 + a + 1];
+    for (int p = p0; p < p1; ++p) s += bval[p] * Xj[(int64_t)bcol[p] * b + c];
   }
   Y[(int64_t)voff[j] * b + t] = s;
 }
 
-hipError_t launch_bapply(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
+hipError_t launch_bapply(const int* sub_ptr, const int* brp, const int* bcol, const double* bval,
                          const int* voff, const int* nt, int nsub, int b, const double* X,
                          double* Y, const int* active, int maxnt, hipStream_t st) {
   const int nel = maxnt * TS * b;
-  hipLaunchKernelGGL(k_bapply, dim3((nel + 255) / 256, nsub), dim3(256), 0, st, sub_ptr, pou,
-                     Ao->rowptr, Ao->col, Ao->val, voff, nt, b, X, Y, active);
+  hipLaunchKernelGGL(k_bapply, dim3((nel + 255) / 256, nsub), dim3(256), 0, st, sub_ptr, brp,
+                     bcol, bval, voff, nt, b, X, Y, active);
   return hipGetLastError();
 }
 
