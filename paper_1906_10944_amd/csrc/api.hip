@@ -269,7 +269,7 @@ struct geneo_handle_s {
   int64_t nloc = 0;
   geneo_opts_t opts{};
   hipStream_t hs = nullptr;
-  hipEvent_t shifted_done = nullptr;
+  hipEvent_t shifted_done = nullptr, f32_done = nullptr;
   LocalLayout LD;
   DBuf<int> sub_ptr, sub_idx, dmap, nd, ntD, voffD, dglob, didx, jobs32, jobs64;
   DBuf<int64_t> toffD, doffD, toff64, doff64;
@@ -311,6 +311,7 @@ struct geneo_handle_s {
   geneo_setup_info_t info{};
   ~geneo_handle_s() {
     if (shifted_done) (void)hipEventDestroy(shifted_done);
+    if (f32_done) (void)hipEventDestroy(f32_done);
     if (hs) (void)hipStreamDestroy(hs);
   }
 };
@@ -470,7 +471,7 @@ std::vector<int2> lauum_job_list(const std::vector<int>& mats, const std::vector
 // read back.
 void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
                  const geneo_subdomains_t* S, hipStream_t st,
-                 const std::function<void()>& after_fp32) {
+                 const std::function<void(hipEvent_t)>& after_fp32) {
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   std::vector<int> all(nsub);
@@ -498,8 +499,12 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
       HIPCHK(launch_chol_batched(CholRole::LocalF32, X.L32.p, h->toffD.p, h->ntD.p, X.D32.p, h->doffD.p,
                                  X.status.p, X.jobs.p, nsub, o.pivot_tol, st));
     }
+    // the shifted factorisation follows the FP32 one on the device (an
+    // event, no host round trip) while the host reads the pivot tests
+    HIPCHK(hipEventCreateWithFlags(&h->f32_done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->f32_done, st));
+    after_fp32(h->f32_done);
     auto stat = download(X.status.p, nsub, st);
-    after_fp32();
     if (h->shifted_done) HIPCHK(hipStreamWaitEvent(st, h->shifted_done, 0));
     std::vector<int> ok32;
     for (int j = 0; j < nsub; ++j) (stat[j] ? f64list : ok32).push_back(j);
@@ -529,7 +534,7 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     }
   } else {
     f64list = all;
-    after_fp32();
+    after_fp32(nullptr);
   }
   h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
   h->njobs64 = (int)f64list.size();
@@ -611,10 +616,13 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
   h->f64list = f64list;
 }
 
-// Shifted factors C_j = G_j G_j^T, enqueued on stream sb (no host wait).
+// Shifted matrices C_j = A_N,j - sigma B_j and their factors C_j = G_j G_j^T,
+// enqueued on stream sb (no host wait) after the event `after` (may be
+// NULL) has completed.
 void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
                    const geneo_subdomains_t* S, const geneo_csr_batch_t* An,
-                   const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm) {
+                   const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm,
+                   hipEvent_t after) {
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   std::vector<int> all(nsub);
@@ -656,6 +664,7 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   X.mr.alloc(1);
   h->m.alloc(nsub);
 
+  if (after) HIPCHK(hipStreamWaitEvent(sb, after, 0));
   tm[0].start(sb);
   double pkN = 0.0, flN = 0.0;
   for (int j = 0; j < nsub; ++j) {
@@ -974,16 +983,17 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     HIPCHK(hipEventDestroy(ev));
   }
   // Order: the FP32 local factorization runs alone (it fills the device);
-  // once its pivot tests are read back the shifted factorization runs on
-  // hs, and the FP64 refactors of the failed subdomains and the triangular
-  // inverses follow it on st, overlapping the eigen sweeps (whose solves
-  // leave the device room) rather than competing with the factorization.
-  // Uploads go through pinned staging, so the host drives both streams
-  // without waiting on either.
+  // the shifted factorization follows it on hs (an event orders them on the
+  // device, the host meanwhile reads the pivot tests), and the FP64
+  // refactors of the failed subdomains and the inverses follow it on st,
+  // overlapping the eigen sweeps (whose solves leave the device room)
+  // rather than competing with the factorization.  Uploads go through
+  // pinned staging, so the host drives both streams without waiting on
+  // either.
   LocalLayout LN;
   tmL.start(st);
-  setup_local(h, X, A, S, st, [&]() {
-    if (coarse) setup_shifted(h, X, LN, S, An, Ao, h->hs, tmC);
+  setup_local(h, X, A, S, st, [&](hipEvent_t after) {
+    if (coarse) setup_shifted(h, X, LN, S, An, Ao, h->hs, tmC, after);
   });
   tmL.stop(st);
   if (coarse) setup_coarse(h, X, LN, S, An, Ao, h->hs, tmC);
@@ -1125,8 +1135,7 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
     const int nrz = (n + 255) / 256;
     // capture PCG_CHUNK iterations: 8 launches each (SpMV, p.Ap, x/r update
     // with alpha, check + apply input, symmetric product and its column
-    // sums, combine
-    // with r.z, p update with beta)
+    // sums, combine with r.z, p update with beta)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
