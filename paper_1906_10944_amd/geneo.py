@@ -17,6 +17,15 @@ GENEO_OK = 0
 GENEO_PREC_FP64 = 0
 GENEO_PREC_MIXED = 1
 
+GENEO_ERR_ARG = 1
+GENEO_ERR_OOM = 2
+GENEO_ERR_LOCAL_NOT_SPD = 3
+GENEO_ERR_EIGEN_NOCONV = 4
+GENEO_ERR_COARSE_NOT_SPD = 5
+GENEO_ERR_MAXIT = 6
+GENEO_ERR_HIP = 7
+GENEO_ERR_SHIFT_NOT_SPD = 8
+
 ERRORS = {
     1: "GENEO_ERR_ARG", 2: "GENEO_ERR_OOM", 3: "GENEO_ERR_LOCAL_NOT_SPD",
     4: "GENEO_ERR_EIGEN_NOCONV", 5: "GENEO_ERR_COARSE_NOT_SPD",

@@ -74,3 +74,15 @@ def test_q1_sizes_rejects_bad_grids():
     g.parts[0] = 100
     with pytest.raises(G.GeneoError):
         G.geneo_q1_sizes(g)
+
+
+def test_error_codes_match_the_header():
+    """The binding's error constants are the header's enum values."""
+    from paper_1906_10944_amd import geneo as G
+    txt = open(os.path.join(ROOT, "include", "geneo.h")).read()
+    found = dict((m.group(1), int(m.group(2)))
+                 for m in re.finditer(r"\b(GENEO_(?:OK|ERR_[A-Z_]+))\s*=\s*(\d+)", txt))
+    assert found["GENEO_OK"] == G.GENEO_OK == 0
+    for name, code in found.items():
+        if name != "GENEO_OK":
+            assert getattr(G, name) == code and G.ERRORS[code] == name

@@ -1,0 +1,88 @@
+"""Failure handling of the device path, forced from the host with valid
+inputs (every kernel still runs to its normal exit):
+
+* a local Dirichlet matrix that is not SPD (one diagonal entry of A made
+  negative inside subdomain 0): the factorisation records the failed pivot
+  and the setup returns GENEO_ERR_LOCAL_NOT_SPD, in FP64 and in mixed mode
+  (where the FP32 pivot test fails first and the FP64 refactor then fails);
+* PCG stopped by maxit: GENEO_ERR_MAXIT with the iterations done reported;
+* eigen sweeps stopped by eig_maxit: GENEO_ERR_EIGEN_NOCONV.
+
+After each error the library keeps working: a correct setup and apply
+follow on the same device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import gpu_apply, gpu_assemble, gpu_setup, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    need_gpu()
+    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    return prob, gpu_assemble(prob)
+
+
+def _healthy(prob, sysm):
+    h = gpu_setup(sysm, prob, precision=1)
+    z = gpu_apply(h, sysm, np.ones(prob.ndof))
+    h.close()
+    assert np.all(np.isfinite(z))
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_local_matrix_not_spd(small, precision):
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    # an interior dof of subdomain 0 (in D_0 only), its diagonal made negative
+    sp_ = sysm.sub_ptr.cpu().numpy()
+    idx = sysm.sub_idx.cpu().numpy()
+    fl = sysm.sub_flags.cpu().numpy()
+    seg = slice(sp_[0], sp_[1])
+    cand = idx[seg][(fl[seg] & 1).astype(bool)]
+    g = int(cand[len(cand) // 2])
+    rp = sysm.A_rowptr.cpu().numpy()
+    col = sysm.A_col.cpu().numpy()
+    pos = rp[g] + int(np.nonzero(col[rp[g]:rp[g + 1]] == g)[0][0])
+    saved = sysm.A_val[pos].item()
+    sysm.A_val[pos] = -abs(saved)
+    torch.cuda.synchronize()
+    try:
+        with pytest.raises(G.GeneoError) as e:
+            gpu_setup(sysm, prob, precision=precision)
+        say("[errors]", e.value)
+        assert e.value.code == G.GENEO_ERR_LOCAL_NOT_SPD
+        assert "subdomain 0" in str(e.value)
+    finally:
+        sysm.A_val[pos] = saved
+        torch.cuda.synchronize()
+    _healthy(prob, sysm)
+
+
+def test_pcg_maxit(small):
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    h = gpu_setup(sysm, prob, precision=1)
+    x = torch.zeros_like(sysm.b)
+    with pytest.raises(G.GeneoError) as e:
+        G.pcg_solve(sysm.csr(), h, sysm.b, x, rtol=1e-10, maxit=3)
+    assert e.value.code == G.GENEO_ERR_MAXIT
+    info = G.pcg_solve(sysm.csr(), h, sysm.b, x, rtol=1e-10, maxit=3, check=False)
+    assert info["iters"] == 3 and not info["converged"] and info["relres"] > 1e-10
+    h.close()
+    _healthy(prob, sysm)
+
+
+def test_eigen_no_convergence(small):
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    with pytest.raises(G.GeneoError) as e:
+        gpu_setup(sysm, prob, precision=1, eig_maxit=1)
+    say("[errors]", e.value)
+    assert e.value.code == G.GENEO_ERR_EIGEN_NOCONV
+    _healthy(prob, sysm)
