@@ -94,6 +94,7 @@ class Runner:
                "t_setup_ms": sinfo["t_setup_ms"], "nc": sinfo["nc"],
                "eig_sweeps": sinfo["eig_sweeps"], "fallback_fp64": sinfo["fallback_fp64"],
                "eig_stalled": sinfo["eig_stalled"], "eig_max_resid": sinfo["eig_max_resid"],
+               "symv_tiles": sinfo["symv_tiles"],
                "t_phase_ms": sinfo["t_phase_ms"]}
         self.last = (sysm, h, x)
         return out
@@ -370,13 +371,13 @@ def main():
         "iters": last["iters"], "converged": bool(last["converged"]),
         "relres": last["relres"], "true_relres": tres, "kappa_est": last["kappa_est"],
         "nc": last["nc"], "eig_sweeps": last["eig_sweeps"], "eig_stalled": last["eig_stalled"],
-        "eig_max_resid": last["eig_max_resid"],
+        "eig_max_resid": last["eig_max_resid"], "symv_tiles": last["symv_tiles"],
         "fallback_fp64": last["fallback_fp64"],
         "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
         "setup_phase_ms": last["t_phase_ms"][:6],
     }
     if mixed and not args.no_fp64_form:
-        ms64, inf64 = timed(runner, 0, 1, 0)
+        ms64, inf64 = timed(runner, 0, 1, 1)
         runner.release()
         out["fp64_form"] = {"ms_per_step": ms64, "value": prob.ndof / (ms64 * 1e-3),
                             "iters": inf64[-1]["iters"], "setup_ms": inf64[-1]["t_setup_ms"],

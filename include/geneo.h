@@ -195,11 +195,17 @@ typedef struct {
                          before it is orthonormalised: eig_cheb - 1 extra
                          shifted solves per sweep, faster convergence of the
                          wanted pairs.  0 or 1: plain subspace iteration. */
+  int symv_tiles;     /* tiles per wavefront in the products with the local
+                         inverses: 8, 16 or 32, or 0 = the fastest of these,
+                         timed on the device at the first setup of each
+                         problem shape and kept for that device and shape
+                         (results are bitwise the same for every value) */
 } geneo_opts_t;
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-10, eig_maxit 300,
- * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3. */
+ * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
+ * symv_tiles 0. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;
@@ -255,6 +261,7 @@ typedef struct {
                              5 coarse factor, 6-7 reserved */
   int64_t bytes_local_factors;  /* bytes of the inverse local factors */
   int eig_stalled;        /* subdomains stopped at their rounding floor */
+  int symv_tiles;         /* tiles per wavefront of the local products */
 } geneo_setup_info_t;
 
 int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);

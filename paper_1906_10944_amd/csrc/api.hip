@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -323,26 +324,8 @@ void check_csr(const geneo_csr_t* A) {
     fail(GENEO_ERR_ARG, "invalid CSR matrix");
 }
 
-// z = M^{-1} r on stream st.  Inside the PCG loop (pcg = true) the first
-// launch also performs the convergence check on the r.r partial sums and
-// the apply is skipped once `done` is set; the combine step always leaves
-// the r.z partial sums (per 256-row block) in h->rz_part.  rev: walk the
-// subdomains in reverse order (consecutive applies alternate).
-hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const int* done,
-                         hipStream_t st, bool pcg, bool rev) {
-  hipError_t e;
-  if (pcg) {
-    if ((e = check_apply_in(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, h->Z.p, h->zoff.p,
-                            h->m.p, h->nd.p, h->voffD.p, h->coff.p, h->rH.p,
-                            h->nc > 0 ? h->nsub : 0, h->rr_part.p, h->sc.p, h->done.p, st)))
-      return e;
-  } else {
-    if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
-    if (h->nc > 0 &&
-        (e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
-                             h->coff.p, h->nsub, h->rH.p, done, st)))
-      return e;
-  }
+// Arguments of the symmetric products of the apply (rev: reverse walk).
+SymvArgs symv_args(const geneo_handle_s* h, bool rev) {
   SymvArgs sa;
   sa.S32 = h->S32.p;
   sa.S64 = h->S64.p;
@@ -367,6 +350,30 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
   sa.cstart = h->cstart.p;
   sa.nchunk = h->nchunk;
   sa.R = h->Rpart.p;
+  return sa;
+}
+
+// z = M^{-1} r on stream st.  Inside the PCG loop (pcg = true) the first
+// launch also performs the convergence check on the r.r partial sums and
+// the apply is skipped once `done` is set; the combine step always leaves
+// the r.z partial sums (per 256-row block) in h->rz_part.  rev: walk the
+// subdomains in reverse order (consecutive applies alternate).
+hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const int* done,
+                         hipStream_t st, bool pcg, bool rev) {
+  hipError_t e;
+  if (pcg) {
+    if ((e = check_apply_in(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, h->Z.p, h->zoff.p,
+                            h->m.p, h->nd.p, h->voffD.p, h->coff.p, h->rH.p,
+                            h->nc > 0 ? h->nsub : 0, h->rr_part.p, h->sc.p, h->done.p, st)))
+      return e;
+  } else {
+    if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
+    if (h->nc > 0 &&
+        (e = restrict_coarse(r, h->Z.p, h->zoff.p, h->m.p, h->nd.p, h->dglob.p, h->voffD.p,
+                             h->coff.p, h->nsub, h->rH.p, done, st)))
+      return e;
+  }
+  const SymvArgs sa = symv_args(h, rev);
   {
     ProfScope ps("symv", st, h->bytes_symv32 + h->bytes_symv64 + h->bytes_symvH, 0.0);
     if ((e = symv_rows(sa, done, st))) return e;
@@ -378,6 +385,53 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
   return combine(r, h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
                  h->yl.p, h->Z.p, h->zoff.p, h->m.p, h->coff.p, h->yH.p, h->n, h->nc > 0, z, done,
                  h->rz_part.p, st);
+}
+
+// Tiles per wavefront of the symmetric product (g row chunks per task): on
+// the first setup of a shape each candidate is timed on the device (one
+// warm launch, then three timed ones, on stream st) and the fastest is kept
+// for that device and shape for the life of the process.  Every candidate
+// computes bitwise the same result (the row partials are per chunk).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int64_t, int, int>, int> g_tune;
+
+int tune_symv_group(geneo_handle_s* h, hipStream_t st,
+                    const std::function<void(int, bool)>& build) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, h->najobs, h->amaxnt, (int64_t)h->LD.ntiles,
+                                   (int)h->f64list.size(), h->ntc);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  HIPCHK(hipMemsetAsync(h->xl.p, 0, h->xl.n * sizeof(double), st));
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  int best = 1;
+  float best_ms = 0.f;
+  for (int g : {1, 2, 4}) {
+    build(g, false);
+    const SymvArgs sa = symv_args(h, false);
+    HIPCHK(symv_rows(sa, nullptr, st));
+    HIPCHK(hipEventRecord(a, st));
+    for (int r = 0; r < 3; ++r) HIPCHK(symv_rows(sa, nullptr, st));
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    if (g == 1 || ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = best;
+  return best;
 }
 
 __global__ void k_count_active(const int* a, int n, int* out) {
@@ -1034,9 +1088,10 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     h->Rpart.alloc((size_t)h->najobs * h->nchunk * TS);
     if ((int64_t)h->najobs * h->nchunk * TS > INT32_MAX)
       fail(GENEO_ERR_ARG, "too many row chunks for the symmetric product");
-    // tasks of job q: its chunks in row order; the two walk orders differ
-    // only in the order of the jobs
-    auto add_job = [&](std::vector<SymvTask>& out, int q) {
+    // tasks of job q: its row chunks in row order, g consecutive chunks of
+    // a row per task; the two walk orders differ only in the order of the
+    // jobs
+    auto add_job = [&](std::vector<SymvTask>& out, int q, int g) {
       const int2 jb = aj[q];
       int64_t toff = 0;
       int xoff = 0, nt = h->ntc;
@@ -1045,26 +1100,35 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
         xoff = h->LD.voff[jb.x];
         nt = h->LD.nt[jb.x];
       }
-      for (int t = 0; t < cs[nt]; ++t) {
-        SymvTask k;
-        const int i = ch[t].x, k0 = ch[t].y;
-        k.s_row = (toff + tile_idx(i, 0)) * TSQ;
-        k.w_row = (toff + tile_idx(i, 0)) * TS;
-        k.xoff = xoff;
-        k.r_off = (q * h->nchunk + t) * TS;
-        k.i = (short)i;
-        k.k0 = (short)k0;
-        k.k1 = (short)std::min(k0 + cw, i + 1);
-        k.kind = (short)jb.y;
-        out.push_back(k);
+      for (int i = 0; i < nt; ++i)
+        for (int t = cs[i]; t < cs[i + 1]; t += g) {
+          SymvTask k;
+          const int k0 = ch[t].y;
+          k.s_row = (toff + tile_idx(i, 0)) * TSQ;
+          k.w_row = (toff + tile_idx(i, 0)) * TS;
+          k.xoff = xoff;
+          k.r_off = (q * h->nchunk + t) * TS;
+          k.i = (short)i;
+          k.k0 = (short)k0;
+          k.k1 = (short)std::min(k0 + g * cw, i + 1);
+          k.kind = (short)jb.y;
+          out.push_back(k);
+        }
+    };
+    auto build = [&](int g, bool both) {
+      std::vector<SymvTask> tf, tr;
+      for (int q = 0; q < h->najobs; ++q) add_job(tf, q, g);
+      h->ntasks = (int)tf.size();
+      h->tasks_fwd.upload(tf, st);
+      if (both) {
+        for (int q = h->najobs - 1; q >= 0; --q) add_job(tr, q, g);
+        h->tasks_rev.upload(tr, st);
       }
     };
-    std::vector<SymvTask> tf, tr;
-    for (int q = 0; q < h->najobs; ++q) add_job(tf, q);
-    for (int q = h->najobs - 1; q >= 0; --q) add_job(tr, q);
-    h->ntasks = (int)tf.size();
-    h->tasks_fwd.upload(tf, st);
-    h->tasks_rev.upload(tr, st);
+    int g = o.symv_tiles / cw;
+    if (g == 0) g = tune_symv_group(h, st, build);
+    build(g, true);
+    h->info.symv_tiles = g * cw;
   }
   HIPCHK(hipStreamSynchronize(st));
   h->info.t_phase_ms[0] = tm0.ms();
@@ -1227,6 +1291,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->eig_stall = 10;
   o->eig_floor = 1e-6;
   o->eig_cheb = 3;
+  o->symv_tiles = 0;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -1296,6 +1361,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
     if (o.eig_maxit < 1 || !(o.eig_tol > 0) || o.eig_stall < 0 || !(o.eig_floor >= 0) ||
         o.eig_cheb < 0 || o.eig_cheb > 16)
       fail(GENEO_ERR_ARG, "invalid eigen tolerances");
+    if (o.symv_tiles != 0 && o.symv_tiles != 8 && o.symv_tiles != 16 && o.symv_tiles != 32)
+      fail(GENEO_ERR_ARG, "symv_tiles must be 0, 8, 16 or 32");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     settle_device();  // the setup's scratch blocks become reusable

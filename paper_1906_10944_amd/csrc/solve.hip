@@ -21,6 +21,10 @@
 
 namespace geneo {
 
+// Tiles of a tile row per row partial of the symmetric product (a wavefront
+// takes one or more such groups).
+#define SYMV_CHUNK 8
+
 // Four consecutive entries of a tile row as stored (raw, converted to FP64
 // only where they are used, so a prefetched tile costs 16 / 32 VGPRs).  The
 // inverses are streamed once per apply with nontemporal loads, which keeps
@@ -52,12 +56,13 @@ template <> struct Piece<double> {
   }
 };
 
-// One chunk of row i of y = S x for a symmetric inverse S (packed lower
-// tiles, the diagonal tiles in full): tiles k0 .. k1-1 of the row.  Their
-// share of y_i = sum_{k<=i} S_ik x_k goes to the row partial R (32 sums),
-// and for k < i the transposed product S_ik^T x_i of the same tile to W(i,
-// k) (32 sums): every tile is read once, both partials are added in a
-// fixed order by k_symv_cols.  Lane (column group l%8, row l/8) loads the
+// Tiles k0 .. k1-1 of row i of y = S x for a symmetric inverse S (packed
+// lower tiles, the diagonal tiles in full), in groups of SYMV_CHUNK tiles
+// (k0 a multiple of it).  A group's share of y_i = sum_{k<=i} S_ik x_k goes
+// to its row partial (32 sums at R + TS g for group g), and for k < i the
+// transposed product S_ik^T x_i of each tile to W(i, k) (32 sums): every
+// tile is read once, both partials are added in a fixed order by
+// k_symv_cols.  Lane (column group l%8, row l/8) loads the
 // 4-column pieces of rows l/8 + 8m (m < 4) of a tile with vector loads,
 // with the 4 entries of x_k they multiply; NB tiles are loaded at a time
 // (NB = 4 for FP32 tiles, 2 for FP64: 16 KB in flight per wavefront) and
@@ -76,13 +81,14 @@ __device__ __forceinline__ void symv_chunk(const T* __restrict__ Srow, int i, in
   double xi[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) xi[m] = xv[i * TS + r0 + 8 * m];
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double s[4];
+  int kend = k1;  // end of the current group of tiles
   struct Buf {
     Piece<T> a[4];
     double2 x01, x23;
   };
   auto load = [&](Buf& b, int k) {
-    const int kk = min(k, k1 - 1);
+    const int kk = min(k, kend - 1);
     const T* t = Sr + (int64_t)kk * TSQ;
 #pragma unroll
     for (int m = 0; m < 4; ++m) b.a[m].load(t + 8 * m * TS);
@@ -114,34 +120,40 @@ __device__ __forceinline__ void symv_chunk(const T* __restrict__ Srow, int i, in
     e += __shfl_xor(e, 32);
     return e;
   };
-  for (int k = k0; k < k1; k += NB) {
-    Buf b[NB];
+  // groups of SYMV_CHUNK tiles, each with its own row partial: the sums do
+  // not depend on how many groups one wavefront takes
+  for (int g0 = k0, gi = 0; g0 < k1; g0 += SYMV_CHUNK, ++gi) {
+    kend = min(g0 + SYMV_CHUNK, k1);
 #pragma unroll
-    for (int u = 0; u < NB; ++u) load(b[u], k + u);
-    // keep the loads ahead of the arithmetic
-    __builtin_amdgcn_sched_barrier(0);
-    double e[NB];
+    for (int m = 0; m < 4; ++m) s[m] = 0.0;
+    for (int k = g0; k < kend; k += NB) {
+      Buf b[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) e[u] = k + u < k1 ? use(b[u], k + u < i) : 0.0;
-    if (lane < 32) {
+      for (int u = 0; u < NB; ++u) load(b[u], k + u);
+      // keep the loads ahead of the arithmetic
+      __builtin_amdgcn_sched_barrier(0);
+      double e[NB];
 #pragma unroll
-      for (int u = 0; u < NB; ++u)
-        if (k + u < k1 && k + u < i) Wrow[(k + u) * TS + cg * 4 + 2 * h3 + h4] = (T)e[u];
+      for (int u = 0; u < NB; ++u) e[u] = k + u < kend ? use(b[u], k + u < i) : 0.0;
+      if (lane < 32) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+          if (k + u < kend && k + u < i) Wrow[(k + u) * TS + cg * 4 + 2 * h3 + h4] = (T)e[u];
+      }
     }
-  }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    s[m] += __shfl_xor(s[m], 1);
-    s[m] += __shfl_xor(s[m], 2);
-    s[m] += __shfl_xor(s[m], 4);
-  }
-  if (cg == 0) {
+    for (int m = 0; m < 4; ++m) {
+      s[m] += __shfl_xor(s[m], 1);
+      s[m] += __shfl_xor(s[m], 2);
+      s[m] += __shfl_xor(s[m], 4);
+    }
+    if (cg == 0) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) R[r0 + 8 * m] = s[m];
+      for (int m = 0; m < 4; ++m) R[gi * TS + r0 + 8 * m] = s[m];
+    }
   }
 }
 
-#define SYMV_CHUNK 8
 int symv_chunk_tiles() { return SYMV_CHUNK; }
 
 // One launch for all subdomains and the coarse problem, one wavefront per

@@ -69,7 +69,7 @@ class Opts(C.Structure):
                 ("sigma", C.c_double), ("precision", C.c_int), ("pivot_tol", C.c_double),
                 ("eig_tol", C.c_double), ("eig_maxit", C.c_int), ("eig_block", C.c_int),
                 ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
-                ("eig_floor", C.c_double), ("eig_cheb", C.c_int)]
+                ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int)]
 
 
 class SetupInfo(C.Structure):
@@ -77,7 +77,7 @@ class SetupInfo(C.Structure):
                 ("eig_sweeps", C.c_int), ("eig_block", C.c_int),
                 ("eig_max_resid", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64),
-                ("eig_stalled", C.c_int)]
+                ("eig_stalled", C.c_int), ("symv_tiles", C.c_int)]
 
 
 class PcgInfo(C.Structure):

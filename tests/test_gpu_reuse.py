@@ -47,3 +47,23 @@ def test_reused_blocks_give_the_same_operator(precision):
             assert np.array_equal(a, b)
         assert got[3] == ref[3]
     G.geneo_trim()
+
+
+def test_symv_tiles_give_the_same_operator():
+    """The tiles per wavefront of the local symmetric products (forced, or
+    chosen by timing) change the work split, never the arithmetic."""
+    need_gpu()
+    from paper_1906_10944_amd import geneo as G
+    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    sysm = gpu_assemble(prob)
+    r = np.random.default_rng(9).standard_normal(prob.ndof)
+    outs = {}
+    for tiles in (8, 16, 32, 0):
+        h = gpu_setup(sysm, prob, precision=1, symv_tiles=tiles)
+        used = G.geneo_get_setup_info(h)["symv_tiles"]
+        assert used == tiles or (tiles == 0 and used in (8, 16, 32))
+        outs[tiles] = gpu_apply(h, sysm, r)
+        h.close()
+        say("[symv tiles]", tiles, "->", used)
+    for tiles in (16, 32, 0):
+        assert np.array_equal(outs[tiles], outs[8])
