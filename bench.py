@@ -94,7 +94,7 @@ class Runner:
                "t_setup_ms": sinfo["t_setup_ms"], "nc": sinfo["nc"],
                "eig_sweeps": sinfo["eig_sweeps"], "fallback_fp64": sinfo["fallback_fp64"],
                "eig_stalled": sinfo["eig_stalled"], "eig_max_resid": sinfo["eig_max_resid"],
-               "symv_tiles": sinfo["symv_tiles"],
+               "symv_tiles": sinfo["symv_tiles"], "eig_block": sinfo["eig_block"],
                "t_phase_ms": sinfo["t_phase_ms"]}
         self.last = (sysm, h, x)
         return out
@@ -171,11 +171,24 @@ def kernel_profile(runner, precision):
 PROF_SYMBOL = {"densify_dirichlet": "k_densify_dirichlet", "chol_dirichlet_f32": "k_potrf_local_f32",
                "chol_dirichlet_f64": "k_potrf_local_f64", "trtri_dirichlet": "k_trtri_win<float, 2>",
                "densify_shifted": "k_densify_shifted", "chol_shifted_f64": "k_potrf_shifted_f64",
-               "trsm_bwd": "k_trsm_win<2, true>", "trsm_fwd": "k_trsm_win<2, false>",
                "bapply": "k_bapply", "rayleigh_ritz": "rayleigh-ritz kernels",
                "orth": "orthonormalisation kernels",
-               "coarse_chol": "k_cpotrf", "lauum_dirichlet": "k_lauum<float>",
+               "coarse_chol": "tile-column step kernels", "lauum_dirichlet": "k_lauum<float>",
                "symv": "k_symv_rows", "symv_cols": "k_symv_cols"}
+
+
+def prof_symbol(name, info):
+    """The kernel a launch site ran, where it depends on the setup: the eigen
+    block width picks the solve kernel, the number of FP64 refactors their
+    factorisation."""
+    if name in ("trsm_fwd", "trsm_bwd"):
+        b, bwd = info.get("eig_block", 32), name == "trsm_bwd"
+        if b <= 32:
+            return "k_trsm_win<%d, %s>" % (b // 16, "true" if bwd else "false")
+        return "k_trsm_bwd" if bwd else "k_trsm_fwd"
+    if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
+        return "tile-column step kernels"
+    return PROF_SYMBOL.get(name, name)
 APPLY_KERNELS = ("symv", "symv_cols")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_darcy512_mixed.json")
 
@@ -203,7 +216,7 @@ def measured_traffic(symbol):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def roofline(prof, iters):
+def roofline(prof, iters, info):
     """The kernel with the largest time per step, against its bound.
 
     Per-step time: average launch time x launches per step.  The apply
@@ -233,7 +246,7 @@ def roofline(prof, iters):
         achieved = p["bytes"] / p["launches"] / (avg_ms * 1e-3) / 1e9
         rf = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     rf["frac"] = rf["achieved"] / rf["peak"]
-    sym = PROF_SYMBOL.get(name, name)
+    sym = prof_symbol(name, info)
     rf["traffic"] = measured_traffic(sym)
     rf["kernel"] = sym
     rf["avg_launch_ms"] = avg_ms
@@ -384,7 +397,7 @@ def main():
                             "solve_ms": inf64[-1]["t_solve_ms"]}
         out["speedup_vs_fp64_form"] = ms64 / ms
     prof = kernel_profile(runner, mixed)
-    out["roofline"] = roofline(prof, last["iters"])
+    out["roofline"] = roofline(prof, last["iters"], last)
     out["kernels_ms"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, last["iters"], args.cpu_budget_s)
