@@ -28,10 +28,6 @@ hipError_t dot_partial(const double* x, const double* y, int n, double* partial,
                        hipStream_t st);
 hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
                         double* alphas, double* betas, hipStream_t st);
-hipError_t update_xr(double* x, double* r, const double* p, const double* q, int n,
-                     const PcgScalars* sc, double* partial, const int* done, hipStream_t st);
-hipError_t update_p(double* p, const double* z, int n, const PcgScalars* sc, const int* done,
-                    hipStream_t st);
 hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st);
 hipError_t copy_vec(const double* a, double* b, int n, hipStream_t st);
 hipError_t fill_i32(int* p, int v, int n, hipStream_t st);

@@ -92,8 +92,6 @@ __device__ double sum_partials(const double* partial, int nb, double* sh) {
   return block_sum(s, sh);
 }
 
-
-
 __global__ void k_gather_local(const double* __restrict__ r, const int* __restrict__ dglob,
                                const double* __restrict__ dscale, int64_t nvec,
                                double* __restrict__ xl, const int* __restrict__ done) {
@@ -238,37 +236,6 @@ __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ 
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// x += alpha p, r -= alpha q; partial sums of r.r
-__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ q, int n,
-                                                   const PcgScalars* __restrict__ sc,
-                                                   double* __restrict__ partial,
-                                                   const int* __restrict__ done) {
-  if (*done) return;
-  __shared__ double sh[4];
-  const double alpha = sc->alpha;
-  double s = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    s += ri * ri;
-  }
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-// p = z + beta p
-__global__ __launch_bounds__(256) void k_update_p(double* __restrict__ p, const double* __restrict__ z,
-                                                  int n, const PcgScalars* __restrict__ sc,
-                                                  const int* __restrict__ done) {
-  if (*done) return;
-  const double beta = sc->beta;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
-}
-
 // stage: 0 = alpha (pq), 1 = convergence check (rr), 2 = beta (rz), 3 = init
 __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ partial, int nb,
                                                 int stage, PcgScalars* __restrict__ sc,
@@ -312,18 +279,6 @@ hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* d
                         double* alphas, double* betas, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, st, partial, PCG_NB, stage, sc, done, alphas,
                      betas);
-  return hipGetLastError();
-}
-
-hipError_t update_xr(double* x, double* r, const double* p, const double* q, int n,
-                     const PcgScalars* sc, double* partial, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_xr, dim3(PCG_NB), dim3(256), 0, st, x, r, p, q, n, sc, partial, done);
-  return hipGetLastError();
-}
-
-hipError_t update_p(double* p, const double* z, int n, const PcgScalars* sc, const int* done,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_update_p, dim3(PCG_NB), dim3(256), 0, st, p, z, n, sc, done);
   return hipGetLastError();
 }
 
