@@ -280,6 +280,7 @@ struct geneo_handle_s {
   int njobs32 = 0, njobs64 = 0;
   DBuf<int> optr;
   DBuf<int2> olist;
+  DBuf<int4> oent;  // owner entries resolved for the combine
   // coarse space
   int nc = 0, ntc = 0, b = 0;
   DBuf<int> m, zoff, coff, hnt;
@@ -382,9 +383,8 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
     ProfScope ps("symv_cols", st, 0.0, 0.0);
     if ((e = symv_cols(sa, done, st))) return e;
   }
-  return combine(r, h->optr.p, h->olist.p, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->dscale.p,
-                 h->yl.p, h->Z.p, h->zoff.p, h->m.p, h->coff.p, h->yH.p, h->n, h->nc > 0, z, done,
-                 h->rz_part.p, st);
+  return combine(r, h->optr.p, h->oent.p, h->dscale.p, h->yl.p, h->Z.p, h->yH.p, h->n, h->nc > 0,
+                 z, done, h->rz_part.p, st);
 }
 
 // Tiles per wavefront of the symmetric product (g row chunks per task): on
@@ -1069,6 +1069,9 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     h->yH.alloc(1);
   }
   h->rz_part.alloc((size_t)(h->n + 255) / 256);
+  h->oent.alloc(h->nloc);
+  HIPCHK(owner_entries(h->olist.p, h->nloc, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->zoff.p,
+                       h->m.p, h->coff.p, h->oent.p, st));
   {
     std::vector<int2> aj = h->ljobs_host;
     if (h->nc > 0) aj.push_back(make_int2(nsub, 2));

@@ -19,10 +19,14 @@ hipError_t gather_local(const double* r, const int* dglob, const double* dscale,
 hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, const int* m,
                            const int* nd, const int* dglob, const int* dvoff, const int* coff,
                            int nsub, double* rH, const int* done, hipStream_t st);
-hipError_t combine(const double* r, const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
-                   const int* dvoff, const double* dscale, const double* yl, const double* Z,
-                   const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
-                   int use_coarse, double* z, const int* done, double* rz_partial,
+// oent[p]: owner entry p resolved to (D-vector position or -1, offset of
+// its row of Z_j, coarse offset of j, m_j)
+hipError_t owner_entries(const int2* olist, int64_t nent, const int* sub_ptr, const int* dmap,
+                         const int* dvoff, const int* zoff, const int* m, const int* coff,
+                         int4* oent, hipStream_t st);
+hipError_t combine(const double* r, const int* optr, const int4* oent, const double* dscale,
+                   const double* yl, const double* Z, const double* yH, int ndof, int use_coarse,
+                   double* z, const int* done, double* rz_partial,
                    hipStream_t st);  // rz_partial (may be NULL): r.z per 256-row block
 hipError_t dot_partial(const double* x, const double* y, int n, double* partial, const int* done,
                        hipStream_t st);

@@ -158,22 +158,50 @@ hipError_t restrict_coarse(const double* r, const double* Z, const int* zoff, co
   return hipGetLastError();
 }
 
+// Owner entries of the combine, resolved once per setup: for the owner
+// entry (j, local index a) of a dof, e = the D_j-vector position of a (or -1
+// when a is not in D_j), the offset of its row of Z_j, the coarse offset of
+// subdomain j and m_j.
+__global__ __launch_bounds__(256) void k_owner_entries(const int2* __restrict__ olist,
+                                                       int64_t nent,
+                                                       const int* __restrict__ sub_ptr,
+                                                       const int* __restrict__ dmap,
+                                                       const int* __restrict__ dvoff,
+                                                       const int* __restrict__ zoff,
+                                                       const int* __restrict__ m,
+                                                       const int* __restrict__ coff,
+                                                       int4* __restrict__ oent) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= nent) return;
+  const int2 o = olist[p];
+  const int j = o.x;
+  const int d = dmap[sub_ptr[j] + o.y];
+  const int mj = m[j];
+  oent[p] = d < 0 ? make_int4(-1, 0, 0, 0)
+                  : make_int4(dvoff[j] + d, zoff[j] + d * mj, coff[j], mj);
+}
+
+hipError_t owner_entries(const int2* olist, int64_t nent, const int* sub_ptr, const int* dmap,
+                         const int* dvoff, const int* zoff, const int* m, const int* coff,
+                         int4* oent, hipStream_t st) {
+  if (nent <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_owner_entries, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, st,
+                     olist, nent, sub_ptr, dmap, dvoff, zoff, m, coff, oent);
+  return hipGetLastError();
+}
+
 // z[g] = sum over the subdomains j owning g (in ascending j) of
 //        s_d y_j[d] + Z_j[d][:] . yH[coff_j :]          (d = dmap_j(g) >= 0)
 // and z[g] = r[g] for a dof in no D_j (an eliminated Dirichlet dof: its row
-// of A is a unit row, so the operator stays SPD on every dof).
+// of A is a unit row, so the operator stays SPD on every dof).  The owner
+// entries come resolved (k_owner_entries): one load each, then independent
+// loads of the scale, the local value and the coarse row.
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ r,
                                                  const int* __restrict__ optr,
-                                                 const int2* __restrict__ olist,
-                                                 const int* __restrict__ sub_ptr,
-                                                 const int* __restrict__ dmap,
-                                                 const int* __restrict__ dvoff,
+                                                 const int4* __restrict__ oent,
                                                  const double* __restrict__ dscale,
                                                  const double* __restrict__ yl,
                                                  const double* __restrict__ Z,
-                                                 const int* __restrict__ zoff,
-                                                 const int* __restrict__ m,
-                                                 const int* __restrict__ coff,
                                                  const double* __restrict__ yH, int ndof,
                                                  int use_coarse, double* __restrict__ z,
                                                  const int* __restrict__ done,
@@ -186,18 +214,14 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ r,
     double s = 0.0;
     bool covered = false;
     for (int p = optr[g]; p < optr[g + 1]; ++p) {
-      int2 o = olist[p];
-      int j = o.x;
-      int d = dmap[sub_ptr[j] + o.y];
-      if (d < 0) continue;
+      const int4 o = oent[p];
+      if (o.x < 0) continue;
       covered = true;
-      int e = dvoff[j] + d;
-      s += dscale[e] * yl[e];
+      s += dscale[o.x] * yl[o.x];
       if (use_coarse) {
-        int mj = m[j];
-        const double* zr = Z + zoff[j] + (int64_t)d * mj;
-        const double* yh = yH + coff[j];
-        for (int c = 0; c < mj; ++c) s += zr[c] * yh[c];
+        const double* zr = Z + o.y;
+        const double* yh = yH + o.z;
+        for (int c = 0; c < o.w; ++c) s += zr[c] * yh[c];
       }
     }
     rg = r[g];
@@ -211,13 +235,11 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ r,
   }
 }
 
-hipError_t combine(const double* r, const int* optr, const int2* olist, const int* sub_ptr, const int* dmap,
-                   const int* dvoff, const double* dscale, const double* yl, const double* Z,
-                   const int* zoff, const int* m, const int* coff, const double* yH, int ndof,
-                   int use_coarse, double* z, const int* done, double* rz_partial, hipStream_t st) {
-  hipLaunchKernelGGL(k_combine, dim3((ndof + 255) / 256), dim3(256), 0, st, r, optr, olist, sub_ptr,
-                     dmap, dvoff, dscale, yl, Z, zoff, m, coff, yH, ndof, use_coarse, z, done,
-                     rz_partial);
+hipError_t combine(const double* r, const int* optr, const int4* oent, const double* dscale,
+                   const double* yl, const double* Z, const double* yH, int ndof, int use_coarse,
+                   double* z, const int* done, double* rz_partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3((ndof + 255) / 256), dim3(256), 0, st, r, optr, oent, dscale,
+                     yl, Z, yH, ndof, use_coarse, z, done, rz_partial);
   return hipGetLastError();
 }
 
