@@ -304,7 +304,7 @@ struct geneo_handle_s {
   DBuf<double> xl, yl;
   // pcg workspace
   int pcg_cap = 0, pcg_maxit = 0;
-  DBuf<double> r, z, p, q, partial, alphas, betas;
+  DBuf<double> r, z, p, p2, q, partial, alphas, betas;
   DBuf<PcgScalars> sc;
   DBuf<int> done;
   int lpr = 8;
@@ -466,6 +466,8 @@ struct SetupScratch {
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
   DBuf<uint8_t> adj;
   DBuf<int> ocount;
+  EigWork wk;
+  EigStall stl;
 };
 
 struct PhaseTimer {
@@ -670,6 +672,54 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
   h->f64list = f64list;
 }
 
+// Start of the eigen sweeps, independent of the shifted factors: the
+// compact B_j, the pseudo-random start blocks (orthonormalised) and the
+// work buffers.  Enqueued on sb ahead of the shifted factorisation: it
+// then runs alone (between the FP32 local factorisation and the shifted
+// one) instead of beside the inverse-factor kernels, which would hold the
+// device while its many short launches wait.
+void eigen_prepare(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
+                   const geneo_subdomains_t* S, const geneo_csr_batch_t* Ao, int nnz,
+                   hipStream_t sb) {
+  const geneo_opts_t& o = h->opts;
+  const int nsub = h->nsub;
+  const int b = h->b;
+  {
+    // compact B_j = X_j A^o_j X_j, sized by the nnz nonzeros of the A^o batch
+    X.bcnt.alloc(h->nloc);
+    X.brp.alloc(h->nloc + 1);
+    X.bcol.alloc(std::max(nnz, 1));
+    X.bval.alloc(std::max(nnz, 1));
+    HIPCHK(launch_bcompact(S->sub_ptr, S->pou, Ao, nsub, h->nloc, LN.maxnt * TS, X.bcnt.p,
+                           X.brp.p, X.bcol.p, X.bval.p, sb));
+  }
+  HIPCHK(fill_i32(X.active.p, 1, nsub, sb));
+  HIPCHK(launch_eig_init(X.U.p, S->sub_ptr, X.voffN.p, X.ntN.p, nsub, b, o.seed, sb));
+  EigWork& wk = X.wk;
+  wk.ngroups = (LN.maxnt * TS / 16 + 7) / 8;  // SLABS_PER_WG = 8
+  X.eG.alloc((size_t)nsub * b * b);
+  X.eM.alloc((size_t)nsub * b * b);
+  X.epart.alloc((size_t)nsub * wk.ngroups * b);
+  X.ebad.alloc((size_t)nsub * b);
+  wk.G = X.eG.p;
+  wk.M = X.eM.p;
+  wk.part = X.epart.p;
+  wk.badcol = X.ebad.p;
+  EigStall& stl = X.stl;
+  X.sbest.alloc(nsub);
+  X.scount.alloc(nsub);
+  X.sflag.alloc(nsub);
+  HIPCHK(hipMemsetAsync(X.sbest.p, 0x7f, nsub * sizeof(double), sb));  // ~1.4e306
+  HIPCHK(hipMemsetAsync(X.scount.p, 0, nsub * sizeof(int), sb));
+  HIPCHK(hipMemsetAsync(X.sflag.p, 0, nsub * sizeof(int), sb));
+  stl.best = X.sbest.p;
+  stl.count = X.scount.p;
+  stl.stalled = X.sflag.p;
+  stl.sweeps = o.eig_stall;
+  stl.floor = o.eig_floor;
+  HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, 0, nullptr, wk, sb));
+}
+
 // Shifted matrices C_j = A_N,j - sigma B_j and their factors C_j = G_j G_j^T,
 // enqueued on stream sb (no host wait) after the event `after` (may be
 // NULL) has completed.
@@ -718,7 +768,10 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   X.mr.alloc(1);
   h->m.alloc(nsub);
 
+  // (read while the stream is still idle)
+  const int nnzB = download(Ao->rowptr + h->nloc, 1, sb)[0];
   if (after) HIPCHK(hipStreamWaitEvent(sb, after, 0));
+  eigen_prepare(h, X, LN, S, Ao, nnzB, sb);
   tm[0].start(sb);
   double pkN = 0.0, flN = 0.0;
   for (int j = 0; j < nsub; ++j) {
@@ -757,43 +810,35 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   }
   // ---- block subspace iteration on S = G^{-1} B G^{-T}
   tm[1].start(sb);
-  {
-    // compact B_j = X_j A^o_j X_j, sized by the nonzeros of the A^o batch
-    const int nnz = download(Ao->rowptr + h->nloc, 1, sb)[0];
-    X.bcnt.alloc(h->nloc);
-    X.brp.alloc(h->nloc + 1);
-    X.bcol.alloc(std::max(nnz, 1));
-    X.bval.alloc(std::max(nnz, 1));
-    HIPCHK(launch_bcompact(S->sub_ptr, S->pou, Ao, nsub, h->nloc, LN.maxnt * TS, X.bcnt.p,
-                           X.brp.p, X.bcol.p, X.bval.p, sb));
-  }
-  HIPCHK(fill_i32(X.active.p, 1, nsub, sb));
-  HIPCHK(launch_eig_init(X.U.p, S->sub_ptr, X.voffN.p, X.ntN.p, nsub, b, o.seed, sb));
-  EigWork wk;
-  wk.ngroups = (LN.maxnt * TS / 16 + 7) / 8;  // SLABS_PER_WG = 8
-  X.eG.alloc((size_t)nsub * b * b);
-  X.eM.alloc((size_t)nsub * b * b);
-  X.epart.alloc((size_t)nsub * wk.ngroups * b);
-  X.ebad.alloc((size_t)nsub * b);
-  wk.G = X.eG.p;
-  wk.M = X.eM.p;
-  wk.part = X.epart.p;
-  wk.badcol = X.ebad.p;
-  EigStall stl;
-  X.sbest.alloc(nsub);
-  X.scount.alloc(nsub);
-  X.sflag.alloc(nsub);
-  HIPCHK(hipMemsetAsync(X.sbest.p, 0x7f, nsub * sizeof(double), sb));  // ~1.4e306
-  HIPCHK(hipMemsetAsync(X.scount.p, 0, nsub * sizeof(int), sb));
-  HIPCHK(hipMemsetAsync(X.sflag.p, 0, nsub * sizeof(int), sb));
-  stl.best = X.sbest.p;
-  stl.count = X.scount.p;
-  stl.stalled = X.sflag.p;
-  stl.sweeps = o.eig_stall;
-  stl.floor = o.eig_floor;
-  HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, 0, nullptr, wk, sb));
+  const EigWork& wk = X.wk;
+  const EigStall& stl = X.stl;
   int sweeps = 0, nact = nsub;
   std::vector<int> act(nsub, 1);
+  // The active flags of sweep it are copied to pinned memory and read by
+  // the host after sweep it+1 has been enqueued, so the device never waits
+  // for the host between sweeps.  Every kernel skips inactive subdomains,
+  // so a sweep enqueued after the last one needed costs only empty
+  // launches and changes nothing.  With per-kernel timing on, each sweep is
+  // read at once (its byte counts then follow the active set exactly).
+  int* aflag[2] = {nullptr, nullptr};
+  hipEvent_t aev[2] = {nullptr, nullptr};
+  bool lag = !prof_on() && t_arena.active;
+  for (int k = 0; k < 2 && lag; ++k) {
+    aflag[k] = (int*)t_arena.take((size_t)nsub * sizeof(int));
+    lag = aflag[k] != nullptr;
+  }
+  for (int k = 0; k < 2 && lag; ++k) HIPCHK(hipEventCreateWithFlags(&aev[k], hipEventDisableTiming));
+  auto read_active = [&](int it) {
+    if (lag) {
+      HIPCHK(hipEventSynchronize(aev[it & 1]));
+      act.assign(aflag[it & 1], aflag[it & 1] + nsub);
+    } else {
+      act = download(X.active.p, nsub, sb);
+    }
+    nact = 0;
+    for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
+  };
+  bool finished = false;
   for (int it = 1; it <= o.eig_maxit; ++it) {
     // algorithmic traffic of this sweep: the factor G_j of every active
     // subdomain is read once per triangular solve, plus its b columns
@@ -826,11 +871,26 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                         X.ntN.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, o.eig_tol, wk, stl,
                         sb));
     }
+    if (lag) {
+      HIPCHK(hipMemcpyAsync(aflag[it & 1], X.active.p, (size_t)nsub * sizeof(int),
+                            hipMemcpyDeviceToHost, sb));
+      HIPCHK(hipEventRecord(aev[it & 1], sb));
+      if (it > 1) {
+        read_active(it - 1);
+        if (nact == 0) {
+          finished = true;
+          break;
+        }
+      }
+    } else {
+      read_active(it);
+      if (nact == 0) {
+        sweeps = it;
+        finished = true;
+        break;
+      }
+    }
     sweeps = it;
-    act = download(X.active.p, nsub, sb);
-    nact = 0;
-    for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
-    if (nact == 0) break;
     if (o.eig_cheb >= 2 && it >= 3) {
       // Chebyshev filter of degree m on the Ritz block Y (kept intact for
       // the final eigenvectors): U holds S Y from the Rayleigh-Ritz step;
@@ -857,6 +917,9 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, it, X.active.p, wk, sb));
     }
   }
+  if (lag && !finished && sweeps > 0) read_active(sweeps);
+  for (int k = 0; k < 2; ++k)
+    if (aev[k]) HIPCHK(hipEventDestroy(aev[k]));
   h->info.eig_sweeps = sweeps;
   {
     auto fl = download(X.sflag.p, nsub, sb);
@@ -1152,8 +1215,9 @@ void ensure_pcg(geneo_handle_s* h, int maxit) {
     h->r.alloc(h->n);
     h->z.alloc(h->n);
     h->p.alloc(h->n);
+    h->p2.alloc(h->n);
     h->q.alloc(h->n);
-    h->partial.alloc(PCG_NB);
+    h->partial.alloc(std::max(PCG_NB, PCG_NB_SPMV));
     h->rr_part.alloc(PCG_NB);
     h->sc.alloc(1);
     h->done.alloc(1);
@@ -1198,22 +1262,22 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
   } else {
     // z = M^{-1} r also leaves the r.z partial sums that alpha needs
     HIPCHK(apply_enqueue(h, h->r.p, h->z.p, nullptr, st, false, false));
-    HIPCHK(copy_vec(h->z.p, h->p.p, n, st));
     const int nrz = (n + 255) / 256;
-    // capture PCG_CHUNK iterations: 8 launches each (SpMV, p.Ap, x/r update
-    // with alpha, check + apply input, symmetric product and its column
-    // sums, combine with r.z, p update with beta)
+    // capture PCG_CHUNK iterations: 6 launches each (p update with beta,
+    // SpMV and p.Ap; x/r update with alpha; check + apply input; symmetric
+    // product and its column sums; combine with r.z).  p alternates between
+    // two buffers (PCG_CHUNK is even, so every replay starts on the first).
+    double* pb[2] = {h->p.p, h->p2.p};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < PCG_CHUNK; ++k) {
-      HIPCHK(spmv(A, h->p.p, h->q.p, h->lpr, h->done.p, st));
-      HIPCHK(dot_partial(h->p.p, h->q.p, n, h->partial.p, h->done.p, st));
-      HIPCHK(update_xr_alpha(x, h->r.p, h->p.p, h->q.p, n, h->partial.p, h->rz_part.p, nrz, h->sc.p,
-                             h->alphas.p, h->rr_part.p, h->done.p, st));
+      double* pk = pb[(k + 1) & 1];
+      HIPCHK(p_spmv(A, h->lpr, h->z.p, pb[k & 1], pk, h->q.p, h->rz_part.p, nrz, h->sc.p,
+                    h->betas.p, h->partial.p, PCG_NB_SPMV, h->done.p, st));
+      HIPCHK(update_xr_alpha(x, h->r.p, pk, h->q.p, n, h->partial.p, PCG_NB_SPMV, h->rz_part.p,
+                             nrz, h->sc.p, h->alphas.p, h->rr_part.p, h->done.p, st));
       HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true, (k & 1) == 0));
-      HIPCHK(update_p_beta(h->p.p, h->z.p, n, h->rz_part.p, nrz, h->sc.p, h->betas.p, h->done.p,
-                           st));
     }
     HIPCHK(hipStreamEndCapture(st, &graph));
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));

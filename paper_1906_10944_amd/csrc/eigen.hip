@@ -40,7 +40,6 @@ hipError_t launch_eig_init(double* U, const int* sub_ptr, const int* voff, const
 }
 
 // ------------------------------------------------- small dense helpers ---
-#define JB_THREADS 256  // threads of the per-subdomain small dense kernels
 // Gram matrix sG = X^T Y (b x b) of npad-row blocks, MFMA quadrants split
 // over row-chunk slices, reduced in fixed order.
 __device__ void gram(const double* X, const double* Y, int npad, int b, double (*spart)[256],
@@ -71,63 +70,75 @@ __device__ void gram(const double* X, const double* Y, int npad, int b, double (
   block_sync();
 }
 
-// Cholesky of sG (b x b, unit diagonal expected) into its lower triangle by
-// the whole workgroup (right-looking, two barriers per column); bad[c] = 1
-// for pivots at or below `tiny` (that column of L is zeroed, its diagonal
-// set to 1).  Then sM = L^{-T} (upper triangular), the inverse formed
-// right-looking: row c of X = L^{-1} is finished at step c and the rows
-// below take its rank-1 update.
-__device__ void chol_inv_block(double (*sG)[EIG_MAXB + 1], double (*sM)[EIG_MAXB + 1], int b,
-                               int* bad, double tiny) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  block_sync();
+// Cholesky of sG (b x b, unit diagonal expected, b <= 64) into its lower
+// triangle by one wavefront (right-looking); bad[c] = 1 for pivots at or
+// below `tiny` (that column of L is zeroed, its diagonal set to 1).  Then
+// sM = L^{-T} (upper triangular), the inverse formed right-looking: row c of
+// X = L^{-1} is finished at step c and the rows below take its rank-1
+// update.  Each step's updates are spread over the 64 lanes, element by
+// element; a wavefront needs no barrier between the steps.
+__device__ void chol_inv_wave(double (*sG)[EIG_MAXB + 1], double (*sM)[EIG_MAXB + 1], int b,
+                              int* bad, double tiny) {
+  const int lane = threadIdx.x;
+  wave_sync();
   for (int c = 0; c < b; ++c) {
     const double d = sG[c][c];
     const bool collapse = !(d > tiny);
     const double s = collapse ? 1.0 : sqrt(d);
-    block_sync();  // every thread has read the pivot
-    if (tid == 0) bad[c] = collapse ? 1 : 0;
-    if (tid > c && tid < b) sG[tid][c] = collapse ? 0.0 : sG[tid][c] / s;
-    if (tid == c) sG[c][c] = s;
-    block_sync();  // column c is final
-    for (int e = tid; e < b * b; e += nth) {
-      const int r = e / b, q = e % b;
-      if (q > c && q <= r) sG[r][q] -= sG[r][c] * sG[q][c];
+    wave_sync();  // every lane has read the pivot
+    if (lane == 0) bad[c] = collapse ? 1 : 0;
+    if (lane > c && lane < b) sG[lane][c] = collapse ? 0.0 : sG[lane][c] / s;
+    if (lane == c) sG[c][c] = s;
+    wave_sync();  // column c is final
+    // trailing update of the rows and columns c+1 .. b-1 (lower part)
+    const int w = b - 1 - c;
+    for (int e = lane; e < w * w; e += 64) {
+      const int r = c + 1 + e / w, q = c + 1 + e % w;
+      if (q <= r) sG[r][q] -= sG[r][c] * sG[q][c];
     }
-    block_sync();  // trailing update done before the next pivot is read
+    wave_sync();
   }
   // X = L^{-1} kept transposed in sM: sM[q][t] = X[t][q]
-  for (int e = tid; e < b * b; e += nth) sM[e / b][e % b] = (e / b == e % b) ? 1.0 : 0.0;
-  block_sync();
+  for (int e = lane; e < b * b; e += 64) sM[e / b][e % b] = (e / b == e % b) ? 1.0 : 0.0;
+  wave_sync();
   for (int c = 0; c < b; ++c) {
     const double dinv = 1.0 / sG[c][c];
-    if (tid <= c) sM[tid][c] *= dinv;
-    block_sync();
-    for (int e = tid; e < b * b; e += nth) {
-      const int r = e / b, q = e % b;  // X[r][q] -= L[r][c] X[c][q], r > c, q <= c
-      if (r > c && q <= c) sM[q][r] -= sG[r][c] * sM[q][c];
+    if (lane <= c) sM[lane][c] *= dinv;
+    wave_sync();
+    // X[r][q] -= L[r][c] X[c][q] for r > c, q <= c
+    const int w = c + 1;
+    for (int e = lane; e < (b - 1 - c) * w; e += 64) {
+      const int r = c + 1 + e / w, q = e % w;
+      sM[q][r] -= sG[r][c] * sM[q][c];
     }
-    block_sync();
+    wave_sync();
   }
 }
 
-// ------------------------------------------------------ Jacobi (block) ---
-// Eigen-decomposition of the symmetric sH (B x B) by cyclic Jacobi with the
-// round-robin ordering, executed by a workgroup of JB_THREADS threads: on
-// return diag(sH) holds the eigenvalues and sQ the eigenvectors (columns).
-// The B/2 rotations of a round are computed by B/2 threads; the row and
-// column updates are spread over all threads.  Rounds whose rotations are
-// all negligible are skipped.
+// ---------------------------------------------------- Jacobi (wavefront) ---
+// Eigen-decomposition of the symmetric sH (B x B, B <= 64) by cyclic Jacobi
+// with the round-robin ordering, by one wavefront: on return diag(sH) holds
+// the eigenvalues and sQ the eigenvectors (columns).  Lanes k < B/2 compute
+// the B/2 rotations (c_k, s_k) of a round into an LDS table (the pairs
+// (p_k, q_k) are formed by every lane from k and the round); then every
+// 2 x 2 block H({p_k, q_k}, {p_l, q_l}) takes rotation k from the left and
+// rotation l from the right in one pass (the blocks partition H, so no lane
+// touches another's entries), and Q its right rotations.  Rounds whose rotations are all negligible are
+// skipped; sweeps stop when the off-diagonal mass is below 1e-30 of the
+// diagonal's.
 template <int B>
-__device__ void jacobi_block(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB + 1],
-                             double* cs_c, double* cs_s, int* pp, int* pq, double* red,
-                             int* sany) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < B * B; e += JB_THREADS) sQ[e / B][e % B] = (e / B == e % B) ? 1.0 : 0.0;
-  block_sync();
+__device__ void jacobi_wave(double (*sH)[B + 1], double (*sQ)[B + 1], double* cs_c,
+                            double* cs_s) {
+  constexpr int P = B / 2;
+  static_assert(B % 16 == 0 && B <= 64, "block width: a multiple of 16, at most 64");
+  constexpr int NB = P * P / 64;  // 2 x 2 blocks of H per lane
+  constexpr int NQ = B * P / 64;  // entry pairs of Q per lane
+  const int lane = threadIdx.x;
+  for (int e = lane; e < B * B; e += 64) sQ[e / B][e % B] = (e / B == e % B) ? 1.0 : 0.0;
+  wave_sync();
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = tid; e < B * B; e += JB_THREADS) {
+    for (int e = lane; e < B * B; e += 64) {
       const int r = e / B, c = e % B;
       const double v = sH[r][c];
       if (r != c) off += v * v;
@@ -137,66 +148,95 @@ __device__ void jacobi_block(double (*sH)[EIG_MAXB + 1], double (*sQ)[EIG_MAXB +
       off += __shfl_xor(off, m);
       dia += __shfl_xor(dia, m);
     }
-    if ((tid & 63) == 0) {
-      red[2 * (tid >> 6)] = off;
-      red[2 * (tid >> 6) + 1] = dia;
-    }
-    block_sync();
-    off = dia = 0.0;
-    for (int w = 0; w < JB_THREADS / 64; ++w) {
-      off += red[2 * w];
-      dia += red[2 * w + 1];
-    }
-    block_sync();
     if (off <= 1e-30 * dia || off == 0.0) break;
     for (int round = 0; round < B - 1; ++round) {
-      if (tid == 0) *sany = 0;
-      block_sync();
-      if (tid < B / 2) {
-        const int i0 = tid, i1 = B - 1 - tid;
-        int p = i0 == 0 ? 0 : ((i0 - 1 + round) % (B - 1)) + 1;
-        int q = ((i1 - 1 + round) % (B - 1)) + 1;
-        if (p > q) { const int t = p; p = q; q = t; }
-        const double apq = sH[p][q];
-        const double app = sH[p][p], aqq = sH[q][q];
+      // pair k of the round: index 0 stays, the others turn round a circle
+      auto pair = [&](int k, int& p, int& q) {
+        const int u = k == 0 ? 0 : ((k - 1 + round) % (B - 1)) + 1;
+        const int v = ((B - 2 - k + round) % (B - 1)) + 1;
+        p = min(u, v);
+        q = max(u, v);
+      };
+      // rotation of pair `lane`: t = tan(theta) is the smaller root of
+      // t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq), written as
+      // 2 a_pq / (d + sign r) with d = a_qq - a_pp, r = sqrt(d^2 + 4 a_pq^2)
+      // (one square root and one division on the dependent chain)
+      int rot = 0;
+      if (lane < P) {
+        int p, q;
+        pair(lane, p, q);
+        const double apq = sH[p][q], app = sH[p][p], aqq = sH[q][q];
         double c = 1.0, sn = 0.0;
-        if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) && apq != 0.0) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+        if (apq * apq > 1e-36 * fabs(app * aqq) && apq != 0.0) {
+          const double d = aqq - app;
+          const double r = sqrt(d * d + 4.0 * apq * apq);
+          const double den = (d > 0.0 || (d == 0.0 && apq > 0.0)) ? d + r : d - r;
+          const double t = 2.0 * apq / den;
+          c = rsqrt(1.0 + t * t);
           sn = t * c;
-          *sany = 1;
+          rot = 1;
         }
-        cs_c[tid] = c;
-        cs_s[tid] = sn;
-        pp[tid] = p;
-        pq[tid] = q;
+        cs_c[lane] = c;
+        cs_s[lane] = sn;
       }
-      block_sync();
-      if (!*sany) continue;
-      // rows p, q of H
-      for (int e = tid; e < (B / 2) * B; e += JB_THREADS) {
-        const int k = e / B, m = e % B;
-        const int p = pp[k], q = pq[k];
-        const double c = cs_c[k], sn = cs_s[k];
-        const double hp = sH[p][m], hq = sH[q][m];
-        sH[p][m] = c * hp - sn * hq;
-        sH[q][m] = sn * hp + c * hq;
+      if (!__any(rot)) continue;
+      wave_sync();
+      // every entry a lane updates is read before any is written (the
+      // compiler cannot tell the reads of one block from the writes of
+      // another, so a read-write-read order would serialise them)
+      double hv[NB][4], rk[NB][2], rl[NB][2];
+      int hp[NB][4];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int e = lane + 64 * u, k = e / P, l = e % P;
+        int pk, qk, pl, ql;
+        pair(k, pk, qk);
+        pair(l, pl, ql);
+        hp[u][0] = pk * (B + 1) + pl;
+        hp[u][1] = pk * (B + 1) + ql;
+        hp[u][2] = qk * (B + 1) + pl;
+        hp[u][3] = qk * (B + 1) + ql;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) hv[u][v] = (&sH[0][0])[hp[u][v]];
+        rk[u][0] = cs_c[k];
+        rk[u][1] = cs_s[k];
+        rl[u][0] = cs_c[l];
+        rl[u][1] = cs_s[l];
       }
-      block_sync();
-      // columns p, q of H and of Q
-      for (int e = tid; e < (B / 2) * B; e += JB_THREADS) {
-        const int k = e % (B / 2), m = e / (B / 2);
-        const int p = pp[k], q = pq[k];
-        const double c = cs_c[k], sn = cs_s[k];
-        const double hp = sH[m][p], hq = sH[m][q];
-        sH[m][p] = c * hp - sn * hq;
-        sH[m][q] = sn * hp + c * hq;
-        const double qp = sQ[m][p], qq = sQ[m][q];
-        sQ[m][p] = c * qp - sn * qq;
-        sQ[m][q] = sn * qp + c * qq;
+      double qv[NQ][2], rq[NQ][2];
+      int qi[NQ][2];
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const int e = lane + 64 * u, m = e / P, l = e % P;
+        int pl, ql;
+        pair(l, pl, ql);
+        qi[u][0] = m * (B + 1) + pl;
+        qi[u][1] = m * (B + 1) + ql;
+        qv[u][0] = (&sQ[0][0])[qi[u][0]];
+        qv[u][1] = (&sQ[0][0])[qi[u][1]];
+        rq[u][0] = cs_c[l];
+        rq[u][1] = cs_s[l];
       }
-      block_sync();
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const double ck = rk[u][0], sk = rk[u][1], cl = rl[u][0], sl = rl[u][1];
+        const double a = hv[u][0], bb = hv[u][1], c = hv[u][2], d = hv[u][3];
+        // rows p_k, q_k
+        const double a1 = ck * a - sk * c, c1 = sk * a + ck * c;
+        const double b1 = ck * bb - sk * d, d1 = sk * bb + ck * d;
+        // columns p_l, q_l
+        (&sH[0][0])[hp[u][0]] = cl * a1 - sl * b1;
+        (&sH[0][0])[hp[u][1]] = sl * a1 + cl * b1;
+        (&sH[0][0])[hp[u][2]] = cl * c1 - sl * d1;
+        (&sH[0][0])[hp[u][3]] = sl * c1 + cl * d1;
+      }
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const double cl = rq[u][0], sl = rq[u][1], qp = qv[u][0], qq = qv[u][1];
+        (&sQ[0][0])[qi[u][0]] = cl * qp - sl * qq;
+        (&sQ[0][0])[qi[u][1]] = sl * qp + cl * qq;
+      }
+      wave_sync();
     }
   }
 }
@@ -223,44 +263,48 @@ __global__ __launch_bounds__(1024) void k_gram(const double* __restrict__ X,
 }
 
 // One wavefront per subdomain: Jacobi eigen-decomposition of H_j, columns
-// sorted by descending eigenvalue (stable), into Q_j and theta_j.
+// sorted by descending eigenvalue (stable: equal values keep their index
+// order; NaN after every number), into Q_j and theta_j.  Lane c places
+// column c at its rank.
 template <int B>
-__global__ __launch_bounds__(JB_THREADS) void k_small_eig(const double* __restrict__ H,
-                                                          double* __restrict__ Q,
-                                                          double* __restrict__ theta,
-                                                          const int* __restrict__ active) {
+__global__ __launch_bounds__(64) void k_small_eig(const double* __restrict__ H,
+                                                  double* __restrict__ Q,
+                                                  double* __restrict__ theta,
+                                                  const int* __restrict__ active) {
   constexpr int b = B;
   const int j = blockIdx.x;
   if (active && !active[j]) return;
-  __shared__ double sH[EIG_MAXB][EIG_MAXB + 1];
-  __shared__ double sQ[EIG_MAXB][EIG_MAXB + 1];
-  __shared__ double cs_c[EIG_MAXB / 2], cs_s[EIG_MAXB / 2];
-  __shared__ int pp[EIG_MAXB / 2], pq[EIG_MAXB / 2], perm[EIG_MAXB];
-  __shared__ double red[2 * JB_THREADS / 64];
-  __shared__ int sany;
-  const int tid = threadIdx.x;
+  __shared__ double sH[B][B + 1];
+  __shared__ double sQ[B][B + 1];
+  __shared__ double cs_c[B / 2], cs_s[B / 2];
+  __shared__ int perm[B];
+  const int lane = threadIdx.x;
   const double* Hj = H + (int64_t)j * b * b;
-  for (int e = tid; e < b * b; e += JB_THREADS) sH[e / b][e % b] = Hj[e];
-  block_sync();
-  jacobi_block<B>(sH, sQ, cs_c, cs_s, pp, pq, red, &sany);
-  if (tid == 0) {
-    for (int c = 0; c < b; ++c) perm[c] = c;
-    for (int c = 0; c < b; ++c) {
-      int best = c;
-      for (int q = c + 1; q < b; ++q)
-        if (sH[perm[q]][perm[q]] > sH[perm[best]][perm[best]]) best = q;
-      int t = perm[best];
-      for (int q = best; q > c; --q) perm[q] = perm[q - 1];
-      perm[c] = t;
+  for (int e = lane; e < b * b; e += 64) sH[e / b][e % b] = Hj[e];
+  wave_sync();
+  jacobi_wave<B>(sH, sQ, cs_c, cs_s);
+  if (lane < b) {
+    // q goes before c: larger value, or equal value and smaller index;
+    // NaN ranks below every number
+    const double d = sH[lane][lane];
+    const bool dn = d != d;
+    int rank = 0;
+    for (int q = 0; q < b; ++q) {
+      const double v = sH[q][q];
+      const bool vn = v != v;
+      const bool gt = vn ? false : (dn ? true : v > d);
+      const bool eq = vn ? dn : (!dn && v == d);
+      rank += (gt || (eq && q < lane)) ? 1 : 0;
     }
+    perm[rank] = lane;
   }
-  block_sync();
+  wave_sync();
   double* Qj = Q + (int64_t)j * b * b;
-  for (int e = tid; e < b * b; e += JB_THREADS) {
-    int r = e / b, c = e % b;
+  for (int e = lane; e < b * b; e += 64) {
+    const int r = e / b, c = e % b;
     Qj[e] = sQ[r][perm[c]];
   }
-  if (tid < b) theta[(int64_t)j * b + tid] = sH[perm[tid]][perm[tid]];
+  if (lane < b) theta[(int64_t)j * b + lane] = sH[perm[lane]][perm[lane]];
 }
 
 // One wavefront per subdomain: Cholesky-QR factor of the Gram matrix G_j of
@@ -268,7 +312,7 @@ __global__ __launch_bounds__(JB_THREADS) void k_small_eig(const double* __restri
 // L L^T = diag(s) G diag(s).  A column whose pivot collapses (numerically
 // dependent on the previous ones) gets a zero column in M_j and its flag in
 // badcol[j*b + c].
-__global__ __launch_bounds__(JB_THREADS) void k_small_cholqr(const double* __restrict__ G, int b,
+__global__ __launch_bounds__(64) void k_small_cholqr(const double* __restrict__ G, int b,
                                                              double* __restrict__ M,
                                                              int* __restrict__ badcol,
                                                              const int* __restrict__ active) {
@@ -284,15 +328,14 @@ __global__ __launch_bounds__(JB_THREADS) void k_small_cholqr(const double* __res
     double d = Gj[tid * b + tid];
     scl[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
-  block_sync();
-  for (int e = tid; e < b * b; e += JB_THREADS) {
+  wave_sync();
+  for (int e = tid; e < b * b; e += 64) {
     int r = e / b, c = e % b;
     sG[r][c] = Gj[e] * scl[r] * scl[c];
   }
-  block_sync();
-  chol_inv_block(sG, sM, b, sbad, 1e-10);
+  chol_inv_wave(sG, sM, b, sbad, 1e-10);
   double* Mj = M + (int64_t)j * b * b;
-  for (int e = tid; e < b * b; e += JB_THREADS) {
+  for (int e = tid; e < b * b; e += 64) {
     int r = e / b, c = e % b;
     const bool badc = sbad[c] || scl[c] == 0.0;
     Mj[e] = badc ? 0.0 : sM[r][c] * scl[r];
@@ -502,7 +545,7 @@ hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int
   dim3 grid2(wk.ngroups, nsub);
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, U, voff, nt, b, wk.G, active, 1);
-    hipLaunchKernelGGL(k_small_cholqr, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, b, wk.M, wk.badcol,
+    hipLaunchKernelGGL(k_small_cholqr, dim3(nsub), dim3(64), 0, st, wk.G, b, wk.M, wk.badcol,
                        active);
     hipLaunchKernelGGL(k_right_mul, grid2, dim3(256), 0, st, U, wk.M, voff, nt, b, active);
     if (pass == 0)
@@ -518,10 +561,10 @@ hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, doub
                       const EigStall& stl, hipStream_t st) {
   hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, W, voff, nt, b, wk.G, active, 1);
   switch (b) {
-    case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
-    case 32: hipLaunchKernelGGL(k_small_eig<32>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
-    case 48: hipLaunchKernelGGL(k_small_eig<48>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
-    default: hipLaunchKernelGGL(k_small_eig<64>, dim3(nsub), dim3(JB_THREADS), 0, st, wk.G, wk.M, theta, active); break;
+    case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    case 32: hipLaunchKernelGGL(k_small_eig<32>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    case 48: hipLaunchKernelGGL(k_small_eig<48>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
+    default: hipLaunchKernelGGL(k_small_eig<64>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
   }
   hipLaunchKernelGGL(k_ritz_update, dim3(wk.ngroups, nsub), dim3(256), 0, st, U, W, Y, wk.M,
                      theta, voff, nt, b, wk.part, wk.ngroups, active);

@@ -5,6 +5,7 @@
 namespace geneo {
 
 #define PCG_NB 512  // fixed number of partial sums per reduction
+#define PCG_NB_SPMV 2048  // blocks (and p.q partial sums) of the fused p / SpMV launch
 
 struct PcgScalars {
   double rz, pq, rr, alpha, beta, tol2;
@@ -33,17 +34,19 @@ hipError_t dot_partial(const double* x, const double* y, int n, double* partial,
 hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
                         double* alphas, double* betas, hipStream_t st);
 hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st);
-hipError_t copy_vec(const double* a, double* b, int n, hipStream_t st);
 hipError_t fill_i32(int* p, int v, int n, hipStream_t st);
 // fused PCG iteration pieces (scalars formed in the consumers)
+// p = z + beta p (pin -> pout), q = A p, p.q partials (npq blocks)
+hipError_t p_spmv(const geneo_csr_t* A, int lpr, const double* z, const double* pin,
+                  double* pout, double* q, const double* rz_part, int nrz, PcgScalars* sc,
+                  double* betas, double* pq_part, int npq, const int* done, hipStream_t st);
 hipError_t update_xr_alpha(double* x, double* r, const double* p, const double* q, int n,
-                           const double* pq_part, const double* rz_part, int nrz, PcgScalars* sc,
-                           double* alphas, double* rr_part, const int* done, hipStream_t st);
+                           const double* pq_part, int npq, const double* rz_part, int nrz,
+                           PcgScalars* sc, double* alphas, double* rr_part, const int* done,
+                           hipStream_t st);
 hipError_t check_apply_in(const double* r, const int* dglob, const double* dscale, int64_t nvec,
                           double* xl, const double* Z, const int* zoff, const int* m, const int* nd,
                           const int* dvoff, const int* coff, double* rH, int nrestrict,
                           const double* rr_part, PcgScalars* sc, int* done, hipStream_t st);
-hipError_t update_p_beta(double* p, const double* z, int n, const double* rz_part, int nrz,
-                         PcgScalars* sc, double* betas, const int* done, hipStream_t st);
 
 }  // namespace geneo

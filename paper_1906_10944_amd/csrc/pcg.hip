@@ -382,29 +382,85 @@ __global__ __launch_bounds__(256) void k_check_apply_in(const double* __restrict
   }
 }
 
-// beta = (r.z)_new / (r.z)_old; p = z + beta p.
-__global__ __launch_bounds__(256) void k_update_p_b(double* __restrict__ p,
-                                                    const double* __restrict__ z, int n,
-                                                    const double* __restrict__ rz_part, int nrz,
-                                                    PcgScalars* __restrict__ sc,
-                                                    double* __restrict__ betas,
-                                                    const int* __restrict__ done) {
+// One launch for the start of a PCG iteration: beta = (r.z)_new / (r.z)_old
+// (none on the first iteration, where p = z), p = z + beta p, q = A p and
+// the partial sums of p.q.  A row needs p at its neighbours: those entries
+// are formed again from z and the previous p, which stays untouched in the
+// other buffer (pin and pout alternate between iterations), so no block
+// reads an entry that another block rewrites; every copy of an entry is the
+// same expression of the same inputs, hence the same value.  LPR lanes per
+// row in the summation order of k_spmv; the block takes row groups in
+// grid-stride order and leaves its rows' p.q in pq_part[blockIdx.x].
+template <int LPR>
+__global__ __launch_bounds__(256) void k_p_spmv(int n, const int* __restrict__ rp,
+                                                const int* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ z,
+                                                const double* __restrict__ pin,
+                                                double* __restrict__ pout, double* __restrict__ q,
+                                                const double* __restrict__ rz_part, int nrz,
+                                                PcgScalars* __restrict__ sc,
+                                                double* __restrict__ betas,
+                                                double* __restrict__ pq_part,
+                                                const int* __restrict__ done) {
   if (*done) return;
   __shared__ double sh[8];
-  const double rz_new = allsum_partials(rz_part, nrz, sh);
-  const double beta = rz_new / sc->rz;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->beta = beta;
-    betas[sc->iters - 1] = beta;
+  const int it = sc->iters;
+  double beta = 0.0;
+  if (it > 0) {
+    beta = allsum_partials(rz_part, nrz, sh) / sc->rz;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->beta = beta;
+      betas[it - 1] = beta;
+    }
   }
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+  auto pnew = [&](int j) { return it > 0 ? z[j] + beta * pin[j] : z[j]; };
+  constexpr int RPB = 256 / LPR;  // rows per block and pass
+  const int sub = threadIdx.x % LPR;
+  double dot = 0.0;
+  for (int r0 = blockIdx.x * RPB; r0 < n; r0 += gridDim.x * RPB) {
+    const int row = r0 + threadIdx.x / LPR;
+    double s = 0.0;
+    if (row < n) {
+      const int p1 = rp[row + 1];
+      for (int k = rp[row] + sub; k < p1; k += LPR) s += val[k] * pnew(col[k]);
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+    if (row < n && sub == 0) {
+      const double pr = pnew(row);
+      pout[row] = pr;
+      q[row] = s;
+      dot += pr * s;
+    }
+  }
+  dot = block_sum(dot, sh);
+  if (threadIdx.x == 0) pq_part[blockIdx.x] = dot;
+}
+
+hipError_t p_spmv(const geneo_csr_t* A, int lpr, const double* z, const double* pin,
+                  double* pout, double* q, const double* rz_part, int nrz, PcgScalars* sc,
+                  double* betas, double* pq_part, int npq, const int* done, hipStream_t st) {
+  const dim3 grid(npq), blk(256);
+  const int n = A->n;
+#define GENEO_P_SPMV(L)                                                                        \
+  hipLaunchKernelGGL(k_p_spmv<L>, grid, blk, 0, st, n, A->rowptr, A->col, A->val, z, pin, pout, \
+                     q, rz_part, nrz, sc, betas, pq_part, done)
+  switch (lpr) {
+    case 4: GENEO_P_SPMV(4); break;
+    case 8: GENEO_P_SPMV(8); break;
+    case 16: GENEO_P_SPMV(16); break;
+    default: GENEO_P_SPMV(32); break;
+  }
+#undef GENEO_P_SPMV
+  return hipGetLastError();
 }
 
 hipError_t update_xr_alpha(double* x, double* r, const double* p, const double* q, int n,
-                           const double* pq_part, const double* rz_part, int nrz, PcgScalars* sc,
-                           double* alphas, double* rr_part, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_xr_a, dim3(PCG_NB), dim3(256), 0, st, x, r, p, q, n, pq_part, PCG_NB,
+                           const double* pq_part, int npq, const double* rz_part, int nrz,
+                           PcgScalars* sc, double* alphas, double* rr_part, const int* done,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr_a, dim3(PCG_NB), dim3(256), 0, st, x, r, p, q, n, pq_part, npq,
                      rz_part, nrz, sc, alphas, rr_part, done);
   return hipGetLastError();
 }
@@ -420,23 +476,11 @@ hipError_t check_apply_in(const double* r, const int* dglob, const double* dscal
   return hipGetLastError();
 }
 
-hipError_t update_p_beta(double* p, const double* z, int n, const double* rz_part, int nrz,
-                         PcgScalars* sc, double* betas, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_p_b, dim3(PCG_NB), dim3(256), 0, st, p, z, n, rz_part, nrz, sc,
-                     betas, done);
-  return hipGetLastError();
-}
-
-// r = b - q (q = A x0), copies used to start the iteration
+// r = b - q (q = A x0), used to start the iteration
 __global__ void k_residual0(const double* __restrict__ b, const double* __restrict__ q,
                             double* __restrict__ r, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) r[i] = b[i] - q[i];
-}
-
-__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
 }
 
 hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st) {
@@ -444,10 +488,6 @@ hipError_t residual0(const double* b, const double* q, double* r, int n, hipStre
   return hipGetLastError();
 }
 
-hipError_t copy_vec(const double* a, double* b, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, st, a, b, n);
-  return hipGetLastError();
-}
 
 // Fill kernel used instead of memset inside code a caller may capture.
 __global__ void k_fill_i32(int* __restrict__ p, int v, int n) {

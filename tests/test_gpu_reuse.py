@@ -67,3 +67,33 @@ def test_symv_tiles_give_the_same_operator():
         say("[symv tiles]", tiles, "->", used)
     for tiles in (16, 32, 0):
         assert np.array_equal(outs[tiles], outs[8])
+
+
+def test_sweep_flags_read_late_or_at_once_give_the_same_operator():
+    """The host reads the eigen sweeps' convergence flags one sweep late
+    (per-kernel timing off) or after every sweep (timing on); the extra
+    sweep enqueued in the first case finds every subdomain inactive and
+    changes nothing: eigenvalues, sweep counts and the operator agree bit
+    for bit."""
+    need_gpu()
+    from paper_1906_10944_amd import geneo as G
+    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    sysm = gpu_assemble(prob)
+    r = np.random.default_rng(11).standard_normal(prob.ndof)
+    L = G.lib()
+    outs = []
+    for timing in (0, 1, 0):
+        L.geneo_prof_enable(timing)
+        try:
+            h = gpu_setup(sysm, prob, precision=1)
+        finally:
+            L.geneo_prof_enable(0)
+        info = G.geneo_get_setup_info(h)
+        m, lam = G.geneo_get_eigenvalues(h, prob.nsub)
+        outs.append((info["eig_sweeps"], m, lam, gpu_apply(h, sysm, r)))
+        h.close()
+        say("[sweep flags] timing", timing, "sweeps", info["eig_sweeps"], "nc", int(m.sum()))
+    for got in outs[1:]:
+        assert got[0] == outs[0][0]
+        for a, b in zip(got[1:], outs[0][1:]):
+            assert np.array_equal(a, b)
