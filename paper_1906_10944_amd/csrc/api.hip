@@ -462,6 +462,10 @@ struct SetupScratch {
   DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
   DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol;
   DBuf<double> bval;
+  DBuf<int> brpos;
+  DBuf<int2> brows;
+  int nbrows = 0;  // rows of B that hold entries
+  int nnzB = 0;    // entries of B
   DBuf<double> sbest;
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
   DBuf<uint8_t> adj;
@@ -690,9 +694,15 @@ void eigen_prepare(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     X.brp.alloc(h->nloc + 1);
     X.bcol.alloc(std::max(nnz, 1));
     X.bval.alloc(std::max(nnz, 1));
+    X.nnzB = nnz;
+    X.brpos.alloc(h->nloc + 1);
+    X.brows.alloc(std::max<int64_t>(h->nloc, 1));
     HIPCHK(launch_bcompact(S->sub_ptr, S->pou, Ao, nsub, h->nloc, LN.maxnt * TS, X.bcnt.p,
-                           X.brp.p, X.bcol.p, X.bval.p, sb));
+                           X.brp.p, X.bcol.p, X.bval.p, X.brpos.p, X.brows.p, sb));
   }
+  // W = B T is zero away from the rows of B that hold entries: cleared
+  // once, the products then write only those rows
+  HIPCHK(hipMemsetAsync(X.W.p, 0, X.W.n * sizeof(double), sb));
   HIPCHK(fill_i32(X.active.p, 1, nsub, sb));
   HIPCHK(launch_eig_init(X.U.p, S->sub_ptr, X.voffN.p, X.ntN.p, nsub, b, o.seed, sb));
   EigWork& wk = X.wk;
@@ -807,6 +817,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     for (int j = 0; j < nsub; ++j)
       if (stat[j]) fail(GENEO_ERR_SHIFT_NOT_SPD, "A_N - sigma B of subdomain " +
                                                      std::to_string(j) + " is not SPD");
+    X.nbrows = download(X.brpos.p + h->nloc, 1, sb)[0];
   }
   // ---- block subspace iteration on S = G^{-1} B G^{-T}
   tm[1].start(sb);
@@ -856,9 +867,11 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                              X.U.p, X.T.p, X.active.p, sb));
     }
     {
-      ProfScope ps("bapply", sb, vb, 0.0);
-      HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.voffN.p, X.ntN.p, nsub, b,
-                           X.T.p, X.W.p, X.active.p, LN.maxnt, sb));
+      // the B entries, the T rows they reach (once each) and the W rows
+      // written, over all subdomains
+      ProfScope ps("bapply", sb, 12.0 * X.nnzB + 2.0 * 8.0 * X.nbrows * b, 0.0);
+      HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.brows.p, X.nbrows, X.voffN.p,
+                           b, X.T.p, X.W.p, X.active.p, sb));
     }
     {
       ProfScope ps("trsm_fwd", sb, gb + vb, tf);
@@ -903,8 +916,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       for (int k = 1; k < o.eig_cheb; ++k) {
         HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
                                X.U.p, X.T.p, X.active.p, sb));
-        HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.voffN.p, X.ntN.p, nsub,
-                             b, X.T.p, X.W.p, X.active.p, LN.maxnt, sb));
+        HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.brows.p, X.nbrows,
+                             X.voffN.p, b, X.T.p, X.W.p, X.active.p, sb));
         HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
                                X.W.p, X.T.p, X.active.p, sb));
         HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, X.P.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,

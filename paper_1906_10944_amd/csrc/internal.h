@@ -139,12 +139,14 @@ hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* t
 // B_j = X_j A^o_j X_j in compact CSR over the nloc local rows: brp [nloc+1]
 // (cnt [nloc] scratch), bcol / bval sized by the nonzeros of the A^o batch;
 // maxrows bounds |N_j|.
+// rpos (nloc + 1) / rows (up to nloc): the rows of B that hold entries,
+// rpos[nloc] their number
 hipError_t launch_bcompact(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
                            int nsub, int64_t nloc, int maxrows, int* cnt, int* brp, int* bcol,
-                           double* bval, hipStream_t st);
+                           double* bval, int* rpos, int2* rows, hipStream_t st);
 hipError_t launch_bapply(const int* sub_ptr, const int* brp, const int* bcol, const double* bval,
-                         const int* voff, const int* nt, int nsub, int b, const double* X,
-                         double* Y, const int* active, int maxnt, hipStream_t st);
+                         const int2* rows, int nrows, const int* voff, int b, const double* X,
+                         double* Y, const int* active, hipStream_t st);
 
 // ------------------------------------------------------------- eigen.hip
 hipError_t launch_eig_init(double* U, const int* sub_ptr, const int* voff, const int* nt,

@@ -16,7 +16,8 @@
 //  * k_trsm_fwd / k_trsm_bwd: the same solves row by row for wider blocks
 //    (inner sums split over tile slices, reduced in LDS).
 //  * k_bapply: Y = X_j A^o_j X_j X (the B-matrix of the GenEO eigenproblem),
-//    from a compact copy of B_j built once per setup (k_bcompact).
+//    from a compact copy of B_j built once per setup (k_bcompact), on the
+//    rows of B_j that hold entries only.
 #include "internal.h"
 
 namespace geneo {
@@ -661,9 +662,23 @@ __global__ __launch_bounds__(256) void k_bcompact(const int* __restrict__ sub_pt
   if (!FILL) cnt[s0 + a] = k;
 }
 
+// Rows of the compact B with at least one entry, as (subdomain, local row):
+// flag pass (into cnt, after its counts are scanned), exclusive scan into
+// rpos (rpos[nloc] = the number of such rows), fill pass.
+__global__ __launch_bounds__(256) void k_brows(const int* __restrict__ sub_ptr, int* __restrict__ cnt,
+                                               const int* __restrict__ rpos,
+                                               int2* __restrict__ rows, int fill) {
+  const int j = blockIdx.y;
+  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  if (!fill) cnt[s0 + a] = cnt[s0 + a] > 0 ? 1 : 0;
+  else if (cnt[s0 + a]) rows[rpos[s0 + a]] = make_int2(j, a);
+}
+
 hipError_t launch_bcompact(const int* sub_ptr, const double* pou, const geneo_csr_batch_t* Ao,
                            int nsub, int64_t nloc, int maxrows, int* cnt, int* brp, int* bcol,
-                           double* bval, hipStream_t st) {
+                           double* bval, int* rpos, int2* rows, hipStream_t st) {
   const dim3 grid((maxrows + 255) / 256, nsub);
   hipLaunchKernelGGL(k_bcompact<false>, grid, dim3(256), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
                      Ao->val, cnt, nullptr, nullptr, nullptr);
@@ -671,44 +686,46 @@ hipError_t launch_bcompact(const int* sub_ptr, const double* pou, const geneo_cs
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bcompact<true>, grid, dim3(256), 0, st, sub_ptr, pou, Ao->rowptr, Ao->col,
                      Ao->val, nullptr, brp, bcol, bval);
+  hipLaunchKernelGGL(k_brows, grid, dim3(256), 0, st, sub_ptr, cnt, nullptr, nullptr, 0);
+  e = scan_exclusive_i32(cnt, rpos, nloc, nullptr, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_brows, grid, dim3(256), 0, st, sub_ptr, cnt, rpos, rows, 1);
   return hipGetLastError();
 }
 
-// Y = B_j X over the padded N_j rows (zero on padding and away from the
-// overlap zone).  One thread per (row a, column c) of the padded block, a 2D
-// grid over (element chunk, subdomain) so that the dependent index/value/X
-// loads of many rows are in flight at once.
+// Y = B_j X on the rows of B_j that hold entries (the listed rows); the
+// other rows of Y are zero and stay so (the caller clears Y once), so a
+// product writes only the overlap zone.  One thread per (listed row,
+// column).
 __global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
                                                const int* __restrict__ brp,
                                                const int* __restrict__ bcol,
                                                const double* __restrict__ bval,
-                                               const int* __restrict__ voff,
-                                               const int* __restrict__ ntl, int b,
+                                               const int2* __restrict__ rows, int nrows,
+                                               const int* __restrict__ voff, int b,
                                                const double* __restrict__ X,
                                                double* __restrict__ Y,
                                                const int* __restrict__ active) {
-  const int j = blockIdx.y;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int r = (int)(t / b), c = (int)(t % b);
+  if (r >= nrows) return;
+  const int2 ja = rows[r];
+  const int j = ja.x, a = ja.y;
   if (active && !active[j]) return;
-  const int npad = ntl[j] * TS;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= npad * b) return;
-  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
+  const int g = sub_ptr[j] + a;
   const double* Xj = X + (int64_t)voff[j] * b;
-  const int a = t / b, c = t % b;
   double s = 0.0;
-  if (a < n) {
-    const int p0 = brp[s0 + a], p1 = brp[s0 + a + 1];
-    for (int p = p0; p < p1; ++p) s += bval[p] * Xj[(int64_t)bcol[p] * b + c];
-  }
-  Y[(int64_t)voff[j] * b + t] = s;
+  for (int p = brp[g]; p < brp[g + 1]; ++p) s += bval[p] * Xj[(int64_t)bcol[p] * b + c];
+  Y[((int64_t)voff[j] + a) * b + c] = s;
 }
 
 hipError_t launch_bapply(const int* sub_ptr, const int* brp, const int* bcol, const double* bval,
-                         const int* voff, const int* nt, int nsub, int b, const double* X,
-                         double* Y, const int* active, int maxnt, hipStream_t st) {
-  const int nel = maxnt * TS * b;
-  hipLaunchKernelGGL(k_bapply, dim3((nel + 255) / 256, nsub), dim3(256), 0, st, sub_ptr, brp,
-                     bcol, bval, voff, nt, b, X, Y, active);
+                         const int2* rows, int nrows, const int* voff, int b, const double* X,
+                         double* Y, const int* active, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  const int64_t nel = (int64_t)nrows * b;
+  hipLaunchKernelGGL(k_bapply, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, st, sub_ptr,
+                     brp, bcol, bval, rows, nrows, voff, b, X, Y, active);
   return hipGetLastError();
 }
 
