@@ -75,6 +75,47 @@ struct PinnedArena {
 };
 thread_local PinnedArena t_arena;
 
+// Small pinned host blocks that outlive their handles: a destroyed handle
+// returns its blocks here for the next one, and none is ever freed, since
+// freeing pinned memory synchronises the device (and would break a graph
+// capture running in another thread).
+class PinnedPool {
+ public:
+  static PinnedPool& get() {
+    static PinnedPool* p = new PinnedPool();  // never destroyed
+    return *p;
+  }
+  // a block of at least `bytes` (power-of-two size class, 256 B minimum)
+  void* take(size_t bytes) {
+    size_t cls = 256;
+    while (cls < bytes) cls <<= 1;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto& fl = free_[cls];
+      if (!fl.empty()) {
+        void* q = fl.back();
+        fl.pop_back();
+        return q;
+      }
+    }
+    void* q = nullptr;
+    if (hipHostMalloc(&q, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(mu_);
+    size_[q] = cls;
+    return q;
+  }
+  void give(void* q) {
+    if (!q) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_[size_[q]].push_back(q);
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<size_t, std::vector<void*>> free_;
+  std::map<void*, size_t> size_;
+};
+
 // Device blocks of the library, kept for reuse: a setup of the same shape
 // as an earlier one then takes its buffers from here instead of the driver
 // (whose allocations, and frees, cost milliseconds each at these sizes and
@@ -292,6 +333,7 @@ struct geneo_handle_s {
   int najobs = 0, amaxnt = 0;
   bool apply_rev = false;  // direction of the next standalone apply
   DBuf<SymvTask> tasks_fwd, tasks_rev;  // symmetric-product tasks, both walk orders
+  DBuf<SymvJob> symv_jobs;              // their per-matrix descriptors
   DBuf<int> cstart;        // first row chunk per tile row; row partials per job
   DBuf<double> Rpart;
   int nchunk = 0, ntasks = 0;
@@ -311,7 +353,17 @@ struct geneo_handle_s {
   double bytes_symv32 = 0.0, bytes_symv64 = 0.0, bytes_symvH = 0.0;  // algorithmic bytes per apply
   std::vector<int> f64list;                         // subdomains with FP64 local factors
   geneo_setup_info_t info{};
+  // pinned host words of the PCG loop: done flags of two chunks, scalars
+  int* hflag = nullptr;
+  PcgScalars* hsc = nullptr;  // two chunk slots and the final read
+  double* hab = nullptr;  // alphas then betas, pcg_maxit each
+  hipEvent_t fev[2] = {nullptr, nullptr};
   ~geneo_handle_s() {
+    PinnedPool::get().give(hflag);
+    PinnedPool::get().give(hab);
+    PinnedPool::get().give(hsc);
+    for (hipEvent_t e : fev)
+      if (e) (void)hipEventDestroy(e);
     if (shifted_done) (void)hipEventDestroy(shifted_done);
     if (f32_done) (void)hipEventDestroy(f32_done);
     if (hs) (void)hipStreamDestroy(hs);
@@ -1155,54 +1207,51 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     h->najobs = (int)aj.size();
     h->amaxnt = std::max(h->LD.maxnt, h->nc > 0 ? h->ntc : 0);
     const int cw = symv_chunk_tiles();
-    std::vector<int2> ch;
     std::vector<int> cs(h->amaxnt + 1);
-    for (int i = 0; i < h->amaxnt; ++i) {
-      cs[i] = (int)ch.size();
-      for (int k0 = 0; k0 <= i; k0 += cw) ch.push_back(make_int2(i, k0));
-    }
-    cs[h->amaxnt] = (int)ch.size();
-    h->nchunk = (int)ch.size();
+    for (int i = 0; i <= h->amaxnt; ++i) cs[i] = (int)symv_tasks_before(i, cw);
+    h->nchunk = cs[h->amaxnt];
     h->cstart.upload(cs, st);
     h->Rpart.alloc((size_t)h->najobs * h->nchunk * TS);
     if ((int64_t)h->najobs * h->nchunk * TS > INT32_MAX)
       fail(GENEO_ERR_ARG, "too many row chunks for the symmetric product");
     // tasks of job q: its row chunks in row order, g consecutive chunks of
-    // a row per task; the two walk orders differ only in the order of the
-    // jobs
-    auto add_job = [&](std::vector<SymvTask>& out, int q, int g) {
-      const int2 jb = aj[q];
-      int64_t toff = 0;
-      int xoff = 0, nt = h->ntc;
-      if (jb.y != 2) {
-        toff = jb.y ? h->toff64_host[jb.x] : h->LD.toff[jb.x];
-        xoff = h->LD.voff[jb.x];
-        nt = h->LD.nt[jb.x];
-      }
-      for (int i = 0; i < nt; ++i)
-        for (int t = cs[i]; t < cs[i + 1]; t += g) {
-          SymvTask k;
-          const int k0 = ch[t].y;
-          k.s_row = (toff + tile_idx(i, 0)) * TSQ;
-          k.w_row = (toff + tile_idx(i, 0)) * TS;
-          k.xoff = xoff;
-          k.r_off = (q * h->nchunk + t) * TS;
-          k.i = (short)i;
-          k.k0 = (short)k0;
-          k.k1 = (short)std::min(k0 + g * cw, i + 1);
-          k.kind = (short)jb.y;
-          out.push_back(k);
-        }
-    };
+    // a row per task, generated on the device from one descriptor per job;
+    // the two walk orders differ only in the order of the jobs
     auto build = [&](int g, bool both) {
-      std::vector<SymvTask> tf, tr;
-      for (int q = 0; q < h->najobs; ++q) add_job(tf, q, g);
-      h->ntasks = (int)tf.size();
-      h->tasks_fwd.upload(tf, st);
-      if (both) {
-        for (int q = h->najobs - 1; q >= 0; --q) add_job(tr, q, g);
-        h->tasks_rev.upload(tr, st);
+      std::vector<SymvJob> js(h->najobs);
+      std::vector<int64_t> cnt(h->najobs);
+      for (int q = 0; q < h->najobs; ++q) {
+        const int2 jb = aj[q];
+        SymvJob& d = js[q];
+        d.toff = 0;
+        d.xoff = 0;
+        d.nt = h->ntc;
+        d.kind = jb.y;
+        d.pad = 0;
+        if (jb.y != 2) {
+          d.toff = jb.y ? h->toff64_host[jb.x] : h->LD.toff[jb.x];
+          d.xoff = h->LD.voff[jb.x];
+          d.nt = h->LD.nt[jb.x];
+        }
+        cnt[q] = symv_tasks_before(d.nt, g * cw);
       }
+      int64_t off = 0;
+      for (int q = 0; q < h->najobs; ++q) {
+        js[q].off_f = (int)off;
+        off += cnt[q];
+      }
+      if (off > INT32_MAX) fail(GENEO_ERR_ARG, "too many tasks for the symmetric product");
+      int64_t offr = 0;
+      for (int q = h->najobs - 1; q >= 0; --q) {
+        js[q].off_r = (int)offr;
+        offr += cnt[q];
+      }
+      h->ntasks = (int)off;
+      h->symv_jobs.upload(js, st);
+      h->tasks_fwd.alloc(std::max<int64_t>(off, 1));
+      if (both) h->tasks_rev.alloc(std::max<int64_t>(off, 1));
+      HIPCHK(symv_make_tasks(h->symv_jobs.p, h->najobs, g, h->nchunk, h->tasks_fwd.p,
+                             both ? h->tasks_rev.p : nullptr, st));
     };
     int g = o.symv_tiles / cw;
     if (g == 0) g = tune_symv_group(h, st, build);
@@ -1236,55 +1285,53 @@ void ensure_pcg(geneo_handle_s* h, int maxit) {
     h->done.alloc(1);
     h->pcg_cap = h->n;
   }
+  if (!h->hflag) {
+    h->hflag = (int*)PinnedPool::get().take(2 * sizeof(int));
+    h->hsc = (PcgScalars*)PinnedPool::get().take(3 * sizeof(PcgScalars));
+    if (!h->hflag || !h->hsc) fail(GENEO_ERR_OOM, "pinned host memory for the PCG flags");
+    for (hipEvent_t& e : h->fev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   if (h->pcg_maxit < maxit + 1) {
     h->alphas.alloc(maxit + 1);
     h->betas.alloc(maxit + 1);
+    PinnedPool::get().give(h->hab);
+    h->hab = (double*)PinnedPool::get().take(2 * (size_t)(maxit + 1) * sizeof(double));
+    if (!h->hab) fail(GENEO_ERR_OOM, "pinned host memory for the PCG records");
     h->pcg_maxit = maxit + 1;
   }
 }
 
 #define PCG_CHUNK 8
+#define PCG_TAIL 2
 
 void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x, double rtol,
              int maxit, geneo_pcg_info_t* info) {
   hipStream_t st = h->hs;
   const int n = h->n;
   double t0 = now_ms();
-  // start: r = b - A x, z = M^{-1} r, p = z
-  PcgScalars init{};
-  init.maxit = maxit;
-  HIPCHK(hipMemcpyAsync(h->sc.p, &init, sizeof(init), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(fill_i32(h->done.p, 0, 1, st));
+  // start, all on the device: b.b and tol2, r = b - A x, r.r (done when
+  // already converged), z = M^{-1} r (which also leaves the r.z partial
+  // sums that the first alpha needs)
   HIPCHK(dot_partial(b, b, n, h->partial.p, nullptr, st));
-  HIPCHK(scalar_stage(h->partial.p, 3, h->sc.p, h->done.p, h->alphas.p, h->betas.p, st));
-  auto sc0 = download(h->sc.p, 1, st)[0];
-  const double bb = sc0.rz;
-  init.tol2 = rtol * rtol * bb;
-  HIPCHK(hipMemcpyAsync(h->sc.p, &init, sizeof(init), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(pcg_start(h->partial.p, 0, h->sc.p, h->done.p, rtol * rtol, maxit, st));
   HIPCHK(spmv(A, x, h->q.p, h->lpr, nullptr, st));
   HIPCHK(residual0(b, h->q.p, h->r.p, n, st));
   HIPCHK(dot_partial(h->r.p, h->r.p, n, h->partial.p, nullptr, st));
-  HIPCHK(scalar_stage(h->partial.p, 3, h->sc.p, h->done.p, h->alphas.p, h->betas.p, st));
-  double rr0 = download(h->sc.p, 1, st)[0].rz;
-  int iters = 0, converged = 0;
-  double rr = rr0;
-  if (bb == 0.0 || rr0 <= init.tol2) {
-    converged = 1;
-  } else {
-    // z = M^{-1} r also leaves the r.z partial sums that alpha needs
-    HIPCHK(apply_enqueue(h, h->r.p, h->z.p, nullptr, st, false, false));
-    const int nrz = (n + 255) / 256;
-    // capture PCG_CHUNK iterations: 6 launches each (p update with beta,
-    // SpMV and p.Ap; x/r update with alpha; check + apply input; symmetric
-    // product and its column sums; combine with r.z).  p alternates between
-    // two buffers (PCG_CHUNK is even, so every replay starts on the first).
-    double* pb[2] = {h->p.p, h->p2.p};
+  HIPCHK(pcg_start(h->partial.p, 1, h->sc.p, h->done.p, rtol * rtol, maxit, st));
+  HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, false, false));
+  const int nrz = (n + 255) / 256;
+  // Two graphs, of PCG_CHUNK and PCG_TAIL iterations: 6 launches each
+  // (p update with beta, SpMV and p.Ap; x/r update with alpha; check +
+  // apply input; symmetric product and its column sums; combine with r.z).
+  // p alternates between two buffers (both lengths are even, so every
+  // replay starts on the first).  Every kernel returns at once when done is
+  // set.
+  double* pb[2] = {h->p.p, h->p2.p};
+  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  for (int gi = 0; gi < 2; ++gi) {
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < PCG_CHUNK; ++k) {
+    for (int k = 0; k < (gi ? PCG_TAIL : PCG_CHUNK); ++k) {
       double* pk = pb[(k + 1) & 1];
       HIPCHK(p_spmv(A, h->lpr, h->z.p, pb[k & 1], pk, h->q.p, h->rz_part.p, nrz, h->sc.p,
                     h->betas.p, h->partial.p, PCG_NB_SPMV, h->done.p, st));
@@ -1293,27 +1340,78 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
       HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true, (k & 1) == 0));
     }
     HIPCHK(hipStreamEndCapture(st, &graph));
-    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    int dn = 0;
-    for (int rep = 0; rep * PCG_CHUNK < maxit + PCG_CHUNK; ++rep) {
-      HIPCHK(hipGraphLaunch(exec, st));
-      dn = download(h->done.p, 1, st)[0];
-      if (dn) break;
-    }
-    (void)hipGraphExecDestroy(exec);
+    HIPCHK(hipGraphInstantiate(&ex[gi], graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);
-    PcgScalars s = download(h->sc.p, 1, st)[0];
-    iters = s.iters;
-    converged = s.converged;
-    rr = s.rr;
   }
+  // Up to two chunks in flight: after each launch the done flag and the
+  // scalars are copied to pinned memory, and the host reads a chunk's copy
+  // while the next chunk runs, so the device never waits for the host.
+  // From the residual history the host predicts the iterations left: no
+  // chunk is queued that the chunks in flight are expected to make
+  // unnecessary, and the last iterations go in short chunks, which bounds
+  // the launches that find done set (each costs a few microseconds).
+  struct Slot { int iters; };
+  Slot fl[2];
+  int head = 0, nfl = 0, queued = 0;  // queued: iterations launched so far
+  const int cap = maxit + PCG_CHUNK;
+  auto launch = [&](bool tail) {
+    const int sl = (head + nfl) & 1;
+    HIPCHK(hipGraphLaunch(ex[tail ? 1 : 0], st));
+    HIPCHK(hipMemcpyAsync(&h->hflag[sl], h->done.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&h->hsc[sl], h->sc.p, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->fev[sl], st));
+    fl[sl].iters = tail ? PCG_TAIL : PCG_CHUNK;
+    queued += fl[sl].iters;
+    ++nfl;
+  };
+  double rr_a = -1.0;
+  int it_a = 0;
+  int64_t left = INT64_MAX;  // predicted iterations still needed after the last read
+  launch(false);
+  for (;;) {
+    int ahead = 0;
+    for (int u = 0; u < nfl; ++u) ahead += fl[(head + u) & 1].iters;
+    if (nfl < 2 && queued < cap && left > ahead)
+      launch(left - ahead <= PCG_CHUNK);
+    if (nfl == 0) break;  // nothing in flight and nothing worth launching
+    HIPCHK(hipEventSynchronize(h->fev[head]));
+    const int dn = h->hflag[head];
+    const PcgScalars sc = h->hsc[head];
+    head ^= 1;
+    --nfl;
+    if (dn) break;
+    // geometric fit of the residual decrease over the last two reads
+    left = INT64_MAX;
+    if (rr_a > 0.0 && sc.rr > 0.0 && sc.iters > it_a && sc.rr < rr_a && sc.tol2 > 0.0) {
+      const double f = std::log(sc.rr / rr_a) / (sc.iters - it_a);  // per iteration
+      const double need = std::log(sc.tol2 / sc.rr) / f;
+      if (need >= 0.0 && need < 1e9) left = (int64_t)std::ceil(need);
+    }
+    rr_a = sc.rr;
+    it_a = sc.iters;
+    if (nfl == 0 && left <= 0) left = 1;  // never stop on a prediction alone
+    if (nfl == 0 && queued >= cap) break;
+  }
+  // drain: every launch is complete before the handle's buffers are read
+  // the scalars and the alpha / beta records (for the Lanczos estimate of
+  // kappa), read back together
+  const size_t nab = (size_t)std::min(maxit + 1, h->pcg_maxit);
+  HIPCHK(hipMemcpyAsync(&h->hsc[2], h->sc.p, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h->hab, h->alphas.p, nab * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h->hab + h->pcg_maxit, h->betas.p, nab * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (hipGraphExec_t e : ex) (void)hipGraphExecDestroy(e);
+  const PcgScalars s = h->hsc[2];
+  const int iters = s.iters, converged = s.converged;
+  const double rr = s.rr, bb = s.bb;
   info->iters = iters;
   info->converged = converged;
   info->relres = bb > 0 ? sqrt(rr / bb) : 0.0;
   info->kappa_est = 1.0;
   if (iters > 0) {
-    auto al = download(h->alphas.p, iters, st);
-    auto be = download(h->betas.p, std::max(iters - 1, 1), st);
+    const double* al = h->hab;
+    const double* be = h->hab + h->pcg_maxit;
     std::vector<double> d(iters), e(iters > 1 ? iters - 1 : 0);
     for (int i = 0; i < iters; ++i) {
       d[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);

@@ -126,6 +126,24 @@ struct SymvArgs {
   double* R;
 };
 int symv_chunk_tiles();
+// One matrix of the symmetric products, for the task generator: its tiles
+// at toff (S32 / S64 / SH by kind), its vectors at xoff, nt tile rows, and
+// the first index of its tasks in the forward and the reverse lists.
+struct SymvJob {
+  int64_t toff;
+  int xoff, nt, kind, off_f, off_r, pad;
+};
+// Tasks of row i of a matrix with g chunk groups per task: ceil((i+1) / G),
+// G = g * symv_chunk_tiles(); tasks of rows 0 .. i-1 (and chunks of rows
+// 0 .. i-1 with G = symv_chunk_tiles()):
+__host__ __device__ inline int64_t symv_tasks_before(int i, int G) {
+  const int64_t f = i / G, r = i % G;
+  return G * f * (f + 1) / 2 + r * (f + 1);
+}
+// Writes the tasks of every job q (g groups of symv_chunk_tiles() tiles per
+// task, row partials at (q * nchunk + chunk) * TS) into fwd and rev.
+hipError_t symv_make_tasks(const SymvJob* jobs, int njobs, int g, int nchunk, SymvTask* fwd,
+                           SymvTask* rev, hipStream_t st);
 hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,

@@ -8,7 +8,7 @@ namespace geneo {
 #define PCG_NB_SPMV 2048  // blocks (and p.q partial sums) of the fused p / SpMV launch
 
 struct PcgScalars {
-  double rz, pq, rr, alpha, beta, tol2;
+  double rz, pq, rr, alpha, beta, tol2, bb;
   int iters, maxit, converged, pad;
 };
 
@@ -31,8 +31,10 @@ hipError_t combine(const double* r, const int* optr, const int4* oent, const dou
                    hipStream_t st);  // rz_partial (may be NULL): r.z per 256-row block
 hipError_t dot_partial(const double* x, const double* y, int n, double* partial, const int* done,
                        hipStream_t st);
-hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
-                        double* alphas, double* betas, hipStream_t st);
+// device-side start: stage 0 from the b.b partials (scalars reset, tol2,
+// done for b = 0), stage 1 from the r0.r0 partials (done if within tol2)
+hipError_t pcg_start(const double* partial, int stage, PcgScalars* sc, int* done, double rtol2,
+                     int maxit, hipStream_t st);
 hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st);
 hipError_t fill_i32(int* p, int v, int n, hipStream_t st);
 // fused PCG iteration pieces (scalars formed in the consumers)

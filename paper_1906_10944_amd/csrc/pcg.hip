@@ -258,36 +258,30 @@ __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ 
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// stage: 0 = alpha (pq), 1 = convergence check (rr), 2 = beta (rz), 3 = init
-__global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ partial, int nb,
-                                                int stage, PcgScalars* __restrict__ sc,
-                                                int* __restrict__ done,
-                                                double* __restrict__ alphas,
-                                                double* __restrict__ betas) {
+// Start of PCG on the device (no host round trip).  stage 0: b.b from the
+// partial sums; every scalar reset, tol2 = rtol^2 b.b, done = (b = 0).
+// stage 1: r0.r0; done (and converged) when it is already within tol2.
+__global__ __launch_bounds__(256) void k_pcg_start(const double* __restrict__ partial, int nb,
+                                                   int stage, PcgScalars* __restrict__ sc,
+                                                   int* __restrict__ done, double rtol2,
+                                                   int maxit) {
   __shared__ double sh[4];
-  if (stage != 3 && *done) return;
-  double s = sum_partials(partial, nb, sh);
+  const double s = sum_partials(partial, nb, sh);
   if (threadIdx.x != 0) return;
   if (stage == 0) {
-    sc->pq = s;
-    sc->alpha = sc->rz / s;
-    alphas[sc->iters] = sc->alpha;
-  } else if (stage == 1) {
+    PcgScalars z{};
+    z.bb = s;
+    z.tol2 = rtol2 * s;
+    z.maxit = maxit;
+    z.converged = s == 0.0 ? 1 : 0;
+    *sc = z;
+    *done = z.converged;
+  } else {
     sc->rr = s;
-    sc->iters += 1;
-    if (s <= sc->tol2) {
+    if (!*done && s <= sc->tol2) {
       sc->converged = 1;
       *done = 1;
-    } else if (sc->iters >= sc->maxit || !(s == s)) {
-      *done = 1;
     }
-  } else if (stage == 2) {
-    double rz_new = s;
-    sc->beta = rz_new / sc->rz;
-    betas[sc->iters - 1] = sc->beta;
-    sc->rz = rz_new;
-  } else {
-    sc->rz = s;
   }
 }
 
@@ -297,10 +291,10 @@ hipError_t dot_partial(const double* x, const double* y, int n, double* partial,
   return hipGetLastError();
 }
 
-hipError_t scalar_stage(const double* partial, int stage, PcgScalars* sc, int* done,
-                        double* alphas, double* betas, hipStream_t st) {
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, st, partial, PCG_NB, stage, sc, done, alphas,
-                     betas);
+hipError_t pcg_start(const double* partial, int stage, PcgScalars* sc, int* done, double rtol2,
+                     int maxit, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(256), 0, st, partial, PCG_NB, stage, sc, done,
+                     rtol2, maxit);
   return hipGetLastError();
 }
 

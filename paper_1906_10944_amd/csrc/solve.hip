@@ -157,6 +157,43 @@ __device__ __forceinline__ void symv_chunk(const T* __restrict__ Srow, int i, in
 
 int symv_chunk_tiles() { return SYMV_CHUNK; }
 
+// The task lists of the symmetric products, one workgroup per job, one
+// thread per tile row: row i has ceil((i + 1) / SYMV_CHUNK) chunks, taken
+// g at a time; its tasks follow those of rows 0 .. i-1 (a closed form), at
+// the job's offsets in the forward and the reverse list.
+__global__ __launch_bounds__(256) void k_symv_tasks(const SymvJob* __restrict__ jobs, int g,
+                                                    int nchunk, SymvTask* __restrict__ fwd,
+                                                    SymvTask* __restrict__ rev) {
+  const int q = blockIdx.x;
+  const SymvJob jb = jobs[q];
+  const int G = g * SYMV_CHUNK;
+  for (int i = threadIdx.x; i < jb.nt; i += blockDim.x) {
+    const int64_t p0 = symv_tasks_before(i, G);
+    const int c0 = (int)symv_tasks_before(i, SYMV_CHUNK);  // first chunk of row i
+    const int ntk = (i + G) / G;
+    for (int u = 0; u < ntk; ++u) {
+      SymvTask k;
+      k.s_row = (jb.toff + tile_idx(i, 0)) * TSQ;
+      k.w_row = (jb.toff + tile_idx(i, 0)) * TS;
+      k.xoff = jb.xoff;
+      k.r_off = (q * nchunk + c0 + u * g) * TS;
+      k.i = (short)i;
+      k.k0 = (short)(u * G);
+      k.k1 = (short)min(u * G + G, i + 1);
+      k.kind = (short)jb.kind;
+      fwd[jb.off_f + p0 + u] = k;
+      if (rev) rev[jb.off_r + p0 + u] = k;
+    }
+  }
+}
+
+hipError_t symv_make_tasks(const SymvJob* jobs, int njobs, int g, int nchunk, SymvTask* fwd,
+                           SymvTask* rev, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symv_tasks, dim3(njobs), dim3(256), 0, st, jobs, g, nchunk, fwd, rev);
+  return hipGetLastError();
+}
+
 // One launch for all subdomains and the coarse problem, one wavefront per
 // task (a chunk of up to SYMV_CHUNK tiles of a tile row), whose
 // descriptor is the wavefront's only dependent load before it streams
