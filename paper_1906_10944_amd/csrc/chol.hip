@@ -1,7 +1,8 @@
 // Dense Cholesky factorisations on the matrix cores (16x16x4 MFMA).
 //
 //  * k_potrf_*: batched blocked left-looking factorisation, one workgroup of
-//    8 wavefronts per local matrix, panels of four 32-wide tile columns.
+//    8 (FP64) or 16 (FP32) wavefronts per local matrix, panels of four
+//    32-wide tile columns.
 //    Bulk update of a panel with every finished column to its left: a work
 //    item is the 16-row half of one tile row and produces its slab of all
 //    panel tiles, so each tile L(i, jj) read from memory feeds eight
@@ -475,14 +476,21 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
   if (tid == 0) status[j] = 0;
 }
 
+// Wavefronts of the FP32 local factorisation: its registers (128) and LDS
+// (one workgroup per CU) allow 16, which gives the bulk updates twice the
+// items in flight of the FP64 kernels (whose registers allow 8).
+#define POTRF32_NW 16
+
 // One entry point per role, so that traces and profiles tell them apart:
 // local Dirichlet factors (FP32, or FP64 for the subdomains that fail the
 // FP32 pivot test) and the shifted Neumann factors of the eigensolver.
-__global__ __launch_bounds__(512) void k_potrf_local_f32(float* tiles, const int64_t* toff,
-                                                         const int* nt, float* dinv,
-                                                         const int64_t* doff, int* status,
-                                                         const int* jobs, double pivtol) {
-  potrf_body<float, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+__global__ __launch_bounds__(POTRF32_NW * 64) void k_potrf_local_f32(float* tiles,
+                                                                     const int64_t* toff,
+                                                                     const int* nt, float* dinv,
+                                                                     const int64_t* doff,
+                                                                     int* status, const int* jobs,
+                                                                     double pivtol) {
+  potrf_body<float, POTRF32_NW, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
 }
 __global__ __launch_bounds__(512) void k_potrf_local_f64(double* tiles, const int64_t* toff,
                                                          const int* nt, double* dinv,
@@ -504,7 +512,7 @@ hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, 
   const dim3 grid(njobs), blk(512);
   switch (role) {
     case CholRole::LocalF32:
-      hipLaunchKernelGGL(k_potrf_local_f32, grid, blk, 0, st, (float*)tiles, toff, nt,
+      hipLaunchKernelGGL(k_potrf_local_f32, grid, dim3(POTRF32_NW * 64), 0, st, (float*)tiles, toff, nt,
                          (float*)dinv, doff, status, jobs, pivtol);
       break;
     case CholRole::LocalF64:
