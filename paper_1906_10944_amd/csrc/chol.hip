@@ -528,25 +528,29 @@ hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, 
 }
 
 // ------------------------------------------------------------------------
-// k_trtri_win: X = L^{-1}, one workgroup of 8 wavefronts per (matrix, block
-// of NCT tile columns C = c0 .. c0+NCT-1): forward substitution L X(:, C) =
-// E_C over the rows c0 .. nt-1 (b = 32 NCT right-hand sides).  The rows are
-// taken in windows of 16 tile rows held in registers (wavefront w owns
-// window rows w and w + 8).  Each window first takes its update from the
-// finished rows (left-looking; the tiles L(k, jj) are streamed with the next
-// one prefetched), then is solved right-looking: the owner of row i forms
+// k_trtri_win: X = L^{-1}, one workgroup per (matrix, block of NCT tile
+// columns C = c0 .. c0+NCT-1): forward substitution L X(:, C) = E_C over the
+// rows c0 .. nt-1 (b = 32 NCT right-hand sides).  The rows are taken in
+// windows of 16 tile rows held in registers (FP32: 16 wavefronts, one
+// window row each; FP64: 8 wavefronts, wavefront w owns rows w and w + 8).
+// Each window first takes its update from the finished rows (left-looking;
+// the tiles L(k, jj) are streamed with the next one prefetched), then is
+// solved right-looking: the owner of row i forms
 // X(i, C) = Dinv(i) acc_i and publishes it, transposed, in LDS; after one
 // barrier every wavefront subtracts L(k, i) X(i, C) from its later rows.
 // Tiles above the diagonal (column tile > row) are zero: never read or
 // written.  Two tile columns per workgroup (FP32) halve the reads of L.
 // The tiles of X are stored transposed (tile (i, k) holds X(i, k)^T), the
 // layout in which k_lauum reads them.
-#define TW_NW 8
-#define TW_MR 2
-#define TW_W (TW_NW * TW_MR)
+// wavefronts per workgroup and window rows per wavefront: FP32 16 x 1 (its
+// 112 registers allow 4 wavefronts per SIMD), FP64 8 x 2
+template <typename T> struct TwCfg {
+  static constexpr int NW = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int MR = sizeof(T) == 4 ? 1 : 2;
+};
 
 template <typename T, int NCT>
-__global__ __launch_bounds__(TW_NW * 64) void k_trtri_win(const T* __restrict__ L,
+__global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __restrict__ L,
                                                           const T* __restrict__ dinv,
                                                           T* __restrict__ X,
                                                           const int64_t* __restrict__ toff,
@@ -555,6 +559,7 @@ __global__ __launch_bounds__(TW_NW * 64) void k_trtri_win(const T* __restrict__ 
                                                           const int2* __restrict__ jobs) {
   typedef typename Mfma<T>::acc Acc;
   constexpr int NCQ = 2 * NCT, b = 32 * NCT, LDI = DiagLd<T>::v;
+  constexpr int TW_NW = TwCfg<T>::NW, TW_MR = TwCfg<T>::MR, TW_W = TW_NW * TW_MR;
   const int j = jobs[blockIdx.x].x, c0 = jobs[blockIdx.x].y;
   const int nt = ntl[j];
   if (c0 >= nt) return;
@@ -712,10 +717,10 @@ hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
                         const int2* jobs, int njobs, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL((k_trtri_win<float, 2>), dim3(njobs), dim3(TW_NW * 64), 0, st,
+    hipLaunchKernelGGL((k_trtri_win<float, 2>), dim3(njobs), dim3(TwCfg<float>::NW * 64), 0, st,
                        (const float*)L, (const float*)dinv, (float*)X, toff, doff, nt, jobs);
   else
-    hipLaunchKernelGGL((k_trtri_win<double, 1>), dim3(njobs), dim3(TW_NW * 64), 0, st,
+    hipLaunchKernelGGL((k_trtri_win<double, 1>), dim3(njobs), dim3(TwCfg<double>::NW * 64), 0, st,
                        (const double*)L, (const double*)dinv, (double*)X, toff, doff, nt, jobs);
   return hipGetLastError();
 }
