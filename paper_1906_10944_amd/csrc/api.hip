@@ -959,12 +959,12 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     if (o.eig_cheb >= 2 && it >= 3) {
       // Chebyshev filter of degree m on the Ritz block Y (kept intact for
       // the final eigenvectors): U holds S Y from the Rayleigh-Ritz step;
-      // Z_1 = (2/a) S Y - Y goes to U, Z_0 = Y to P, and each further
-      // degree costs one shifted solve; Z_m ends in U.
+      // Z_1 = (2/a) S Y - Y goes to U, Z_0 is Y itself, and each further
+      // degree costs one shifted solve; Z_{k+1} goes to P (then swapped
+      // with U), Z_m ends in U.
       ProfScope ps("chebyshev", sb, 0.0, 0.0);
       HIPCHK(launch_cheb(X.U.p, nullptr, X.U.p, X.Y.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,
                          LN.maxnt, true, X.active.p, sb));
-      HIPCHK(hipMemcpyAsync(X.P.p, X.Y.p, X.Y.n * sizeof(double), hipMemcpyDeviceToDevice, sb));
       for (int k = 1; k < o.eig_cheb; ++k) {
         HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
                                X.U.p, X.T.p, X.active.p, sb));
@@ -972,8 +972,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                              X.voffN.p, b, X.T.p, X.W.p, X.active.p, sb));
         HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
                                X.W.p, X.T.p, X.active.p, sb));
-        HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, X.P.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,
-                           LN.maxnt, false, X.active.p, sb));
+        HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, k == 1 ? X.Y.p : X.P.p, X.theta.p, X.voffN.p,
+                           X.ntN.p, nsub, b, LN.maxnt, false, X.active.p, sb));
         std::swap(X.U.p, X.P.p);  // Z_{k+1} -> U, Z_k -> P
       }
     }
