@@ -9,6 +9,7 @@
 #include <memory>
 #include <tuple>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,24 @@ struct Err {
            std::string(#expr) + " -> " + hipGetErrorString(e_));                        \
   } while (0)
 
+// Graph captures against device-wide synchronisation.  A device-wide
+// synchronisation, or a driver allocation or free (which may synchronise),
+// in one thread invalidates a stream capture running in another.  Captures
+// hold this lock shared; those calls hold it exclusively (re-entrant within
+// a thread, so nested uses do not deadlock).
+std::shared_mutex g_capture_mu;
+thread_local int t_driver_depth = 0;
+struct DriverLock {
+  DriverLock() {
+    if (t_driver_depth++ == 0) g_capture_mu.lock();
+  }
+  ~DriverLock() {
+    if (--t_driver_depth == 0) g_capture_mu.unlock();
+  }
+  DriverLock(const DriverLock&) = delete;
+  DriverLock& operator=(const DriverLock&) = delete;
+};
+
 // Pinned host staging for the small uploads of a setup (index lists, job
 // lists, offsets), so that they are asynchronous: one arena per host
 // thread, reused by consecutive setups of that thread.  A setup resets it
@@ -61,6 +80,7 @@ struct PinnedArena {
     if (chunk == chunks.size()) {
       const size_t cap = std::max(bytes, (size_t)4 << 20);
       char* p = nullptr;
+      DriverLock dl;
       if (hipHostMalloc((void**)&p, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
       chunks.push_back({p, cap});
       used = 0;
@@ -70,6 +90,8 @@ struct PinnedArena {
     return r;
   }
   ~PinnedArena() {
+    if (chunks.empty()) return;
+    DriverLock dl;
     for (auto& c : chunks) (void)hipHostFree(c.first);
   }
 };
@@ -99,7 +121,10 @@ class PinnedPool {
       }
     }
     void* q = nullptr;
-    if (hipHostMalloc(&q, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    {
+      DriverLock dl;
+      if (hipHostMalloc(&q, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    }
     std::lock_guard<std::mutex> g(mu_);
     size_[q] = cls;
     return q;
@@ -147,6 +172,7 @@ class DevCache {
         return hipSuccess;
       }
     }
+    DriverLock dl;
     hipError_t e = hipMalloc(p, bytes);
     if (e == hipErrorOutOfMemory) {
       (void)hipGetLastError();
@@ -168,6 +194,7 @@ class DevCache {
   }
   // the device dev has been synchronised since the pending blocks were released
   void settle(int dev) {
+    DriverLock dl;
     std::vector<void*> drop;
     {
       std::lock_guard<std::mutex> g(mu_);
@@ -187,6 +214,7 @@ class DevCache {
     for (void* q : drop) (void)hipFree(q);
   }
   void trim(int dev) {
+    DriverLock dl;
     std::vector<void*> drop;
     {
       std::lock_guard<std::mutex> g(mu_);
@@ -217,6 +245,7 @@ class DevCache {
 void settle_device() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
+  DriverLock dl;
   (void)hipDeviceSynchronize();
   DevCache::get().settle(dev);
 }
@@ -1101,7 +1130,10 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   h->nsub = nsub;
   h->nloc = S->nloc;
   h->lpr = spmv_lanes(A);
-  HIPCHK(hipStreamCreateWithFlags(&h->hs, hipStreamNonBlocking));
+  {
+    DriverLock dl;
+    HIPCHK(hipStreamCreateWithFlags(&h->hs, hipStreamNonBlocking));
+  }
   struct ArenaScope {
     ArenaScope() { t_arena.begin(); }
     ~ArenaScope() { t_arena.end(); }
@@ -1327,10 +1359,30 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
   // replay starts on the first).  Every kernel returns at once when done is
   // set.
   double* pb[2] = {h->p.p, h->p2.p};
-  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  struct Execs {  // destroyed on every exit, errors included
+    hipGraphExec_t e[2] = {nullptr, nullptr};
+    ~Execs() {
+      for (hipGraphExec_t x : e)
+        if (x) (void)hipGraphExecDestroy(x);
+    }
+  } execs;
+  hipGraphExec_t* ex = execs.e;
+  // an error inside a capture ends it, so that the stream stays usable
+  struct Capture {
+    hipStream_t st;
+    bool on = false;
+    ~Capture() {
+      if (!on) return;
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(st, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    }
+  };
+  std::shared_lock<std::shared_mutex> capture_lock(g_capture_mu);
   for (int gi = 0; gi < 2; ++gi) {
     hipGraph_t graph = nullptr;
+    Capture cap{st};
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    cap.on = true;
     for (int k = 0; k < (gi ? PCG_TAIL : PCG_CHUNK); ++k) {
       double* pk = pb[(k + 1) & 1];
       HIPCHK(p_spmv(A, h->lpr, h->z.p, pb[k & 1], pk, h->q.p, h->rz_part.p, nrz, h->sc.p,
@@ -1339,10 +1391,13 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
                              nrz, h->sc.p, h->alphas.p, h->rr_part.p, h->done.p, st));
       HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true, (k & 1) == 0));
     }
+    cap.on = false;
     HIPCHK(hipStreamEndCapture(st, &graph));
-    HIPCHK(hipGraphInstantiate(&ex[gi], graph, nullptr, nullptr, 0));
+    const hipError_t ie = hipGraphInstantiate(&ex[gi], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
+    HIPCHK(ie);
   }
+  capture_lock.unlock();
   // Up to two chunks in flight: after each launch the done flag and the
   // scalars are copied to pinned memory, and the host reads a chunk's copy
   // while the next chunk runs, so the device never waits for the host.
@@ -1401,7 +1456,6 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
   HIPCHK(hipMemcpyAsync(h->hab + h->pcg_maxit, h->betas.p, nab * sizeof(double),
                         hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  for (hipGraphExec_t e : ex) (void)hipGraphExecDestroy(e);
   const PcgScalars s = h->hsc[2];
   const int iters = s.iters, converged = s.converged;
   const double rr = s.rr, bb = s.bb;
@@ -1561,6 +1615,7 @@ int geneo_apply(geneo_handle_t h, const double* r, double* z, void* stream) {
 
 void geneo_destroy(geneo_handle_t h) {
   if (!h) return;
+  DriverLock dl;
   (void)hipDeviceSynchronize();
   delete h;
   settle_device();
