@@ -109,8 +109,11 @@ hipError_t gather_local(const double* r, const int* dglob, const double* dscale,
   return hipGetLastError();
 }
 
-// rH[coff_j + c] = sum_d Z_j[d][c] r[g(d)] for subdomain j, 256 threads:
-// wave w takes the columns c = w, w+4, ..., lanes stride over the rows.
+// r_H entries of subdomain j, (Z_j^T R_j r)_c for c < m_j, by one block of
+// 256 threads: thread t takes the rows t, t + 256, ... of the D_j block of Z
+// (row-major, m_j entries a row, read contiguously) with r at their global
+// dofs, for up to 16 columns at a time; the column sums are reduced within
+// each wavefront and then over the 4 wavefronts in a fixed order.
 __device__ __forceinline__ void restrict_block(int j, const double* __restrict__ r,
                                                const double* __restrict__ Z,
                                                const int* __restrict__ zoff,
@@ -120,19 +123,41 @@ __device__ __forceinline__ void restrict_block(int j, const double* __restrict__
                                                const int* __restrict__ dvoff,
                                                const int* __restrict__ coff,
                                                double* __restrict__ rH) {
+  __shared__ double sred[4][16];
   const int mj = m[j];
   if (mj == 0) return;
   const int n = nd[j];
   const double* Zj = Z + zoff[j];
   const int* gj = dglob + dvoff[j];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int c0 = 0; c0 < mj; c0 += 4) {
-    const int c = c0 + w;
-    double s = 0.0;
-    if (c < mj)
-      for (int d = lane; d < n; d += 64) s += Zj[(int64_t)d * mj + c] * r[gj[d]];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && c < mj) rH[coff[j] + c] = s;
+  for (int c0 = 0; c0 < mj; c0 += 16) {
+    const int nc = min(16, mj - c0);
+    double s[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s[c] = 0.0;
+#pragma unroll 4
+    for (int d = threadIdx.x; d < n; d += 256) {
+      const double rv = r[gj[d]];
+      const double* zr = Zj + (int64_t)d * mj + c0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < nc) s[c] += zr[c] * rv;
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c >= nc) break;
+      for (int o = 32; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < nc) sred[w][c] = s[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < nc)
+      rH[coff[j] + c0 + threadIdx.x] =
+          sred[0][threadIdx.x] + sred[1][threadIdx.x] + sred[2][threadIdx.x] + sred[3][threadIdx.x];
+    __syncthreads();
   }
 }
 
