@@ -86,3 +86,39 @@ def test_eigen_no_convergence(small):
     say("[errors]", e.value)
     assert e.value.code == G.GENEO_ERR_EIGEN_NOCONV
     _healthy(prob, sysm)
+
+
+def test_pcg_start_cases(small):
+    """The PCG start runs on the device: a zero right-hand side and an initial
+    guess that already meets the tolerance both stop before the first
+    iteration (converged, x untouched); the iterations run in captured
+    chunks of 8 and 2, and every iteration limit, multiple of neither or
+    not, stops exactly there."""
+    import torch
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    h = gpu_setup(sysm, prob, precision=1)
+    A = sysm.csr()
+    # b = 0, x0 = 0: nothing to do
+    zero = torch.zeros_like(sysm.b)
+    x = torch.zeros_like(sysm.b)
+    info = G.pcg_solve(A, h, zero, x, rtol=1e-10, maxit=100)
+    assert info["iters"] == 0 and info["converged"] and info["relres"] == 0.0
+    assert not torch.any(x)
+    # full solve from zero
+    x = torch.zeros_like(sysm.b)
+    full = G.pcg_solve(A, h, sysm.b, x, rtol=1e-10, maxit=500)
+    assert full["converged"] and full["iters"] > 2
+    # restart from the solution with a tolerance its true residual meets
+    # (the recurrence residual reached 1e-10, the true one has an FP64 floor)
+    x2 = x.clone()
+    again = G.pcg_solve(A, h, sysm.b, x2, rtol=1e-5, maxit=500)
+    say("[pcg start] full", full["iters"], "restart", again["iters"], again["relres"])
+    assert again["converged"] and again["iters"] == 0
+    assert torch.equal(x2, x)
+    # each iteration limit below the full count stops exactly there
+    for mx in (1, 2, 3, 7, 9, 10, full["iters"] - 1):
+        xm = torch.zeros_like(sysm.b)
+        part = G.pcg_solve(A, h, sysm.b, xm, rtol=1e-10, maxit=mx, check=False)
+        assert part["iters"] == mx and not part["converged"], (mx, part)
+    h.close()
