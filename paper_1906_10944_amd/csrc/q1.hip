@@ -172,29 +172,54 @@ __device__ __forceinline__ void sub_box(const Q1Geom& g, int j, int* elo, int* e
   }
 }
 
-// Serial prefix sums over the (few) subdomains: sub_ptr and the nnz offsets
-// of the batched local matrices.
-__global__ void k_q1_subptr(const Q1Geom* __restrict__ gp, int* __restrict__ sub_ptr,
-                            int64_t* __restrict__ locnnz_off) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Prefix sums over the subdomains: sub_ptr and the nnz offsets of the
+// batched local matrices.  One block of 1024 threads, one subdomain per
+// thread in rounds of 1024 with a running carry (scan in LDS).
+__global__ __launch_bounds__(1024) void k_q1_subptr(const Q1Geom* __restrict__ gp,
+                                                    int* __restrict__ sub_ptr,
+                                                    int64_t* __restrict__ locnnz_off) {
+  __shared__ int64_t sn[1024], sz[1024];
   const Q1Geom& g = *gp;
-  int64_t acc = 0, accz = 0;
-  for (int j = 0; j < g.nsub; ++j) {
-    int elo[3], ehi[3], p[3];
-    sub_box(g, j, elo, ehi, p);
-    int64_t nodes = 1, nzn = 1;
-    for (int ax = 0; ax < 3; ++ax) {
-      int nb = ehi[ax] - elo[ax] + 1;
-      nodes *= nb;
-      nzn *= (nb == 1 ? 1 : 3 * (int64_t)nb - 2);
+  const int t = threadIdx.x;
+  int64_t carry_n = 0, carry_z = 0;
+  for (int base = 0; base < g.nsub; base += 1024) {
+    const int j = base + t;
+    int64_t nodes = 0, nzn = 0;
+    if (j < g.nsub) {
+      int elo[3], ehi[3], p[3];
+      sub_box(g, j, elo, ehi, p);
+      nodes = 1;
+      nzn = 1;
+      for (int ax = 0; ax < 3; ++ax) {
+        int nb = ehi[ax] - elo[ax] + 1;
+        nodes *= nb;
+        nzn *= (nb == 1 ? 1 : 3 * (int64_t)nb - 2);
+      }
+      nodes *= g.ncomp;
+      nzn *= g.ncomp * g.ncomp;
     }
-    sub_ptr[j] = (int)acc;
-    locnnz_off[j] = accz;
-    acc += nodes * g.ncomp;
-    accz += nzn * g.ncomp * g.ncomp;
+    sn[t] = nodes;
+    sz[t] = nzn;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int64_t an = t >= off ? sn[t - off] : 0, az = t >= off ? sz[t - off] : 0;
+      __syncthreads();
+      sn[t] += an;
+      sz[t] += az;
+      __syncthreads();
+    }
+    if (j < g.nsub) {
+      sub_ptr[j] = (int)(carry_n + sn[t] - nodes);
+      locnnz_off[j] = carry_z + sz[t] - nzn;
+    }
+    carry_n += sn[1023];
+    carry_z += sz[1023];
+    __syncthreads();
   }
-  sub_ptr[g.nsub] = (int)acc;
-  locnnz_off[g.nsub] = accz;
+  if (t == 0) {
+    sub_ptr[g.nsub] = (int)carry_n;
+    locnnz_off[g.nsub] = carry_z;
+  }
 }
 
 // Number of parts along `ax` whose node range [elo + (elo>0), ehi - (ehi<ne)]
@@ -246,7 +271,8 @@ __global__ void k_q1_sublists(const Q1Geom* __restrict__ gp, const int* __restri
 }
 
 // Batched local Neumann (all box elements) and overlap-zone matrices with
-// local column indices; one block per subdomain, one thread per local row.
+// local column indices; grid (subdomain, chunk of 256 local rows), one
+// thread per local row.
 __global__ void k_q1_local(const Q1Geom* __restrict__ gp, const double* __restrict__ coeff,
                            const int* __restrict__ sub_ptr, const int64_t* __restrict__ nzoff,
                            int* __restrict__ loc_rowptr, int* __restrict__ loc_col,
@@ -261,7 +287,7 @@ __global__ void k_q1_local(const Q1Geom* __restrict__ gp, const double* __restri
   const int nc = g.ncomp;
   int bhi[3] = {ehi[0], ehi[1], ehi[2]};
   for (int ax = g.dim; ax < 3; ++ax) bhi[ax] = 1;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+  for (int r = blockIdx.y * blockDim.x + threadIdx.x; r < n; r += blockDim.x * gridDim.y) {
     int ln = r / nc, c = r % nc;
     int l[3] = {ln % nb[0], (ln / nb[0]) % nb[1], ln / (nb[0] * nb[1])};
     int cnt[3];
@@ -415,11 +441,12 @@ hipError_t q1_launch_all(const Q1Geom* dgeom, const Q1Geom& g, const geneo_q1_si
   int bs = 256;
   hipLaunchKernelGGL(k_q1_global, dim3((unsigned)((nrows + bs - 1) / bs)), dim3(bs), 0, st,
                      dgeom, coeff, A_rowptr, A_col, A_val, b, nrows);
-  hipLaunchKernelGGL(k_q1_subptr, dim3(1), dim3(64), 0, st, dgeom, sub_ptr, nzoff);
+  hipLaunchKernelGGL(k_q1_subptr, dim3(1), dim3(1024), 0, st, dgeom, sub_ptr, nzoff);
   hipLaunchKernelGGL(k_q1_sublists, dim3(g.nsub), dim3(256), 0, st, dgeom, sub_ptr, sub_idx,
                      flags, pou);
-  hipLaunchKernelGGL(k_q1_local, dim3(g.nsub), dim3(256), 0, st, dgeom, coeff, sub_ptr, nzoff,
-                     loc_rowptr, loc_col, an, ao);
+  const unsigned rchunks = (unsigned)std::max<int64_t>(1, (s.nmax + 255) / 256);
+  hipLaunchKernelGGL(k_q1_local, dim3(g.nsub, rchunks), dim3(256), 0, st, dgeom, coeff, sub_ptr,
+                     nzoff, loc_rowptr, loc_col, an, ao);
   return hipGetLastError();
 }
 
