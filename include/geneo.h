@@ -299,10 +299,17 @@ typedef struct {
  * Preconditioned CG (x0 = 0 is NOT assumed: x holds the start vector) for
  * A x = b with the two-level preconditioner M, stopped as soon as the
  * recurrence residual satisfies ||r_k||_2 <= rtol ||b||_2 (the residual
- * reduction used in Sec. 5), iteration count = products with A.
+ * reduction used in Sec. 5), iteration count = products with A.  A zero b,
+ * or a start vector already within the tolerance, returns 0 iterations
+ * with x unchanged.
  *  A     device CSR; b, x device [n] (x in: start vector, out: solution);
  *  nrhs  right-hand sides stored one after the other (b, x of size n*nrhs),
  *        solved independently; info (host) has nrhs entries.
+ * The iterations run on M's own stream, ordered after the work already
+ * enqueued on `stream`, and `stream` is ordered after them; the call
+ * returns once the solve is complete.  Solves on one handle must not
+ * overlap (they share its work vectors); different handles may solve
+ * from different threads at once.
  * Returns GENEO_ERR_MAXIT if any right-hand side did not converge.
  */
 int pcg_solve(const geneo_csr_t* A, geneo_handle_t M, const double* b,
@@ -321,10 +328,13 @@ int geneo_spmv(const geneo_csr_t* A, const double* x, double* y, void* stream);
  * carries the algorithmic bytes and flops of that launch.
  * geneo_prof_query sums the records of one kernel name (host pointers):
  * total_ms (event time), launches, bytes and flops (either may be NULL).
- * Names: "assemble", "densify_dirichlet", "chol_dirichlet_f32",
- * "chol_dirichlet_f64", "trtri_dirichlet", "densify_shifted",
+ * Names: "densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
+ * "trtri_dirichlet", "lauum_dirichlet", "densify_shifted",
  * "chol_shifted_f64", "trsm_bwd", "trsm_fwd", "bapply", "rayleigh_ritz",
- * "orth", "coarse_chol", "trmv_lower", "trmv_upperT".
+ * "chebyshev", "orth", "coarse_chol", "symv", "symv_cols".  While timing is
+ * on, the eigen sweeps read their convergence flags after every sweep
+ * (instead of one sweep late), so that the byte counts follow the active
+ * set exactly.
  */
 void geneo_prof_enable(int on);
 int geneo_prof_query(const char* kernel, double* total_ms, int* launches, double* bytes,
