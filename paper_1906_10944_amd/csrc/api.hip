@@ -545,6 +545,7 @@ struct SetupScratch {
   DBuf<double> bval;
   DBuf<int> brpos;
   DBuf<int2> brows;
+  bool check_cst = false;  // the coarse factor's status is read at the end
   int nbrows = 0;  // rows of B that hold entries
   int nnzB = 0;    // entries of B
   DBuf<double> sbest;
@@ -1015,12 +1016,6 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   for (int k = 0; k < 2; ++k)
     if (aev[k]) HIPCHK(hipEventDestroy(aev[k]));
   h->info.eig_sweeps = sweeps;
-  {
-    auto fl = download(X.sflag.p, nsub, sb);
-    int c = 0;
-    for (int v : fl) c += v != 0;
-    h->info.eig_stalled = c;
-  }
   if (nact > 0) {
     auto best = download(X.sbest.p, nsub, sb);
     int jw = -1;
@@ -1062,7 +1057,6 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   HIPCHK(launch_basis(X.T.p, X.voffN.p, b, S->sub_ptr, S->pou, h->dmap.p, h->m.p, h->zoff.p,
                       h->nd.p, nsub, h->Z.p, sb));
   hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(1), 0, sb, X.resid.p, h->m.p, nsub, b, X.mr.p);
-  h->info.eig_max_resid = download(X.mr.p, 1, sb)[0];
   if (nc > 0) {
     X.woffd.upload(woff, sb);
     X.Wg.alloc(ws);
@@ -1099,7 +1093,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(launch_chol_steps(X.AHt.p, X.DH.p, h->htoff.p, X.hdoff.p, h->hnt.p, X.hjob.p, 1,
                                h->ntc, X.cst.p, sb));
     }
-    if (download(X.cst.p, 1, sb)[0]) fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
+    X.check_cst = true;  // read at the end of the setup (a failed factor only costs its inverse)
     h->bytes_symvH = 8.0 * packed(nc) + 16.0 * nc;
     std::vector<int2> tj = trtri_job_list(std::vector<int>{0}, std::vector<int>{h->ntc}, false);
     X.tjobsH.upload(tj, sb);
@@ -1177,7 +1171,6 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   h->xl.alloc(h->LD.nvec);
   h->yl.alloc(h->LD.nvec);
   tm0.stop(st);
-  HIPCHK(hipStreamSynchronize(st));
 
   h->m_host.assign(nsub, 0);
   h->nc = 0;
@@ -1218,7 +1211,18 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
       if (stat[j]) fail(GENEO_ERR_LOCAL_NOT_SPD, "local Dirichlet matrix of subdomain " +
                                                      std::to_string(j) + " is not SPD");
   }
-  if (coarse) HIPCHK(hipStreamSynchronize(h->hs));
+  if (coarse) {
+    HIPCHK(hipStreamSynchronize(h->hs));
+    // read back once the stream has finished: sweep statistics and the
+    // coarse factor's pivot test
+    const auto fl = download(X.sflag.p, nsub, h->hs);
+    int c = 0;
+    for (int v : fl) c += v != 0;
+    h->info.eig_stalled = c;
+    h->info.eig_max_resid = download(X.mr.p, 1, h->hs)[0];
+    if (X.check_cst && download(X.cst.p, 1, h->hs)[0])
+      fail(GENEO_ERR_COARSE_NOT_SPD, "coarse matrix A_H is not SPD");
+  }
   if (h->nc == 0) {
     // placeholders so that the apply kernels always get valid pointers
     if (!h->m.p) h->m.upload(std::vector<int>(nsub, 0), st);
