@@ -86,7 +86,12 @@ class Runner:
         sysm = G.geneo_assemble_q1(self.grid, self.coeff)
         opts = G.opts_from_problem(self.prob, precision=precision)
         h = G.geneo_setup(sysm.csr(), sysm.subdomains(), sysm.neumann(), sysm.overlap(), opts)
-        x = torch.zeros_like(sysm.b)
+        # the solution vector is the caller's: one buffer for all steps,
+        # zeroed (x0 = 0) at the start of each
+        if getattr(self, "xbuf", None) is None or self.xbuf.shape != sysm.b.shape:
+            self.xbuf = torch.empty_like(sysm.b)
+        x = self.xbuf
+        x.zero_()
         info = G.pcg_solve(sysm.csr(), h, sysm.b, x, rtol=self.prob.rtol, maxit=self.prob.maxit)
         sinfo = G.geneo_get_setup_info(h)
         out = {"iters": info["iters"], "converged": info["converged"], "relres": info["relres"],
