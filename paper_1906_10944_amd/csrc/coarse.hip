@@ -60,7 +60,9 @@ hipError_t launch_galerkin_w(const geneo_csr_batch_t* An, const int* sub_ptr, co
 
 #define CB_CHUNK 2048
 
-// Block (i, j), j <= i, of A_H into the tiled lower triangle.
+// Block (i, j), j <= i, of A_H into the tiled lower triangle: the rows d of
+// D_i found in N_j (binary search, in chunks of CB_CHUNK) contribute
+// Z_i(d, p) W_j(b(d), q).
 __global__ __launch_bounds__(256) void k_coarse_blocks(
     const int2* __restrict__ pairs, const int* __restrict__ sub_ptr,
     const int* __restrict__ sub_idx, const int* __restrict__ didx,
@@ -77,7 +79,43 @@ __global__ __launch_bounds__(256) void k_coarse_blocks(
   const double* Zi = Z + zoff[i];
   const double* Wj = W + woff[j];
   const int npq = mi * mj;
-  // each thread owns up to 16 (p, q) outputs
+  if (npq <= 256) {
+    // thread = (output pq, row group rg): P >= npq outputs padded to a
+    // power of two, G = 256 / P row groups each taking every G-th row of
+    // D_i; the G partial sums of an output are added in a fixed order
+    __shared__ double red[256];
+    int P = 1;
+    while (P < npq) P <<= 1;
+    const int G = 256 / P;
+    const int pq = threadIdx.x % P, rg = threadIdx.x / P;
+    const int p = pq / mj, q = pq % mj;
+    double s = 0.0;
+    for (int base = 0; base < ndi; base += CB_CHUNK) {
+      const int cnt = min(CB_CHUNK, ndi - base);
+      __syncthreads();
+      for (int d = threadIdx.x; d < cnt; d += blockDim.x) {
+        int a = didx[dvoff[i] + base + d];
+        int g = sub_idx[si + a];
+        match[d] = bsearch_sorted(sub_idx + sj, nj, g);
+      }
+      __syncthreads();
+      if (pq < npq)
+        for (int d = rg; d < cnt; d += G) {
+          const int b = match[d];
+          if (b >= 0) s += Zi[(int64_t)(base + d) * mi + p] * Wj[(int64_t)b * mj + q];
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (rg == 0 && pq < npq) {
+      double t = 0.0;
+      for (int g2 = 0; g2 < G; ++g2) t += red[g2 * P + pq];
+      const int R = coff[i] + p, C = coff[j] + q;
+      if (R >= C) AHt[tile_idx(R / TS, C / TS) * TSQ + (R % TS) * TS + (C % TS)] = t;
+    }
+    return;
+  }
+  // larger blocks: each thread owns up to 16 (p, q) outputs
   double acc[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) acc[u] = 0.0;
