@@ -632,9 +632,11 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     }
     {
       ProfScope ps("densify_dirichlet", st, 4.0 * h->LD.ntiles * TSQ, 0.0);
+      HIPCHK(hipMemsetAsync(X.L32.p, 0, X.L32.n * sizeof(float), st));
       HIPCHK(launch_densify_dirichlet(true, X.L32.p, h->toffD.p, h->ntD.p, h->voffD.p, X.jobs.p,
                                       nsub, S->sub_ptr, S->sub_idx, h->dmap.p, h->dglob.p,
-                                      h->dscale.p, A, st));
+                                      h->dscale.p, A,
+                                      *std::max_element(h->LD.nt.begin(), h->LD.nt.end()), st));
     }
     {
       ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * pk, fl);
@@ -703,15 +705,18 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     X.L64.alloc(tt * TSQ);
     X.D64.alloc(dd * TSQ);
     double pk64 = 0.0, fl64 = 0.0;
+    int mx = 0;
     for (int j : f64list) {
+      mx = std::max(mx, h->LD.nt[j]);
       pk64 += packed(h->nd_host[j]);
       fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
     }
     {
       ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
+      HIPCHK(hipMemsetAsync(X.L64.p, 0, X.L64.n * sizeof(double), st));
       HIPCHK(launch_densify_dirichlet(false, X.L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
                                       h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
-                                      h->dmap.p, h->dglob.p, h->dscale.p, A, st));
+                                      h->dmap.p, h->dglob.p, h->dscale.p, A, mx, st));
     }
     {
       // a few refactors (mixed mode): tile-column steps over many short
@@ -719,8 +724,6 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
       // full batch (FP64 mode): one workgroup per matrix
       ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
       if (h->njobs64 <= kStepCholMax) {
-        int mx = 0;
-        for (int j : f64list) mx = std::max(mx, h->LD.nt[j]);
         HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
                                  h->jobs64.p, h->njobs64, mx, X.status.p, st));
       } else {
@@ -872,6 +875,7 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   }
   {
     ProfScope ps("densify_shifted", sb, 8.0 * LN.ntiles * TSQ, 0.0);
+    HIPCHK(hipMemsetAsync(X.G.p, 0, X.G.n * sizeof(double), sb));
     HIPCHK(launch_densify_shifted(X.G.p, X.toffN.p, X.ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
                                   o.sigma, sb));
   }
@@ -1060,8 +1064,11 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   if (nc > 0) {
     X.woffd.upload(woff, sb);
     X.Wg.alloc(ws);
+    int64_t maxwork = 0;
+    for (int j = 0; j < nsub; ++j)
+      maxwork = std::max<int64_t>(maxwork, (int64_t)h->nN_host[j] * h->m_host[j]);
     HIPCHK(launch_galerkin_w(An, S->sub_ptr, h->dmap.p, h->Z.p, h->zoff.p, h->m.p, X.woffd.p,
-                             nsub, X.Wg.p, sb));
+                             nsub, maxwork, X.Wg.p, sb));
     X.adj.alloc((size_t)nsub * nsub);
     HIPCHK(launch_adjacency(h->optr.p, h->olist.p, h->n, nsub, X.adj.p, sb));
     X.pcnt.alloc(nsub);

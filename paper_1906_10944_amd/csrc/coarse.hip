@@ -22,7 +22,8 @@ __device__ __forceinline__ int bsearch_sorted(const int* a, int n, int key) {
   return -1;
 }
 
-// W_j[a][c] = sum_b A_N,j[a][b] Z_j[dmap(b)][c], rows a over N_j.
+// W_j[a][c] = sum_b A_N,j[a][b] Z_j[dmap(b)][c], rows a over N_j; grid
+// (subdomain, chunk of 256 outputs), one thread per output.
 __global__ __launch_bounds__(256) void k_galerkin_w(const int* __restrict__ rp,
                                                     const int* __restrict__ colx,
                                                     const double* __restrict__ val,
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w(const int* __restrict__ rp,
   const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
   const double* Zj = Z + zoff[j];
   double* Wj = W + woff[j];
-  for (int t = threadIdx.x; t < n * mj; t += blockDim.x) {
+  for (int t = blockIdx.y * blockDim.x + threadIdx.x; t < n * mj; t += blockDim.x * gridDim.y) {
     int a = t / mj, c = t % mj;
     double s = 0.0;
     for (int p = rp[s0 + a]; p < rp[s0 + a + 1]; ++p) {
@@ -52,9 +53,10 @@ __global__ __launch_bounds__(256) void k_galerkin_w(const int* __restrict__ rp,
 
 hipError_t launch_galerkin_w(const geneo_csr_batch_t* An, const int* sub_ptr, const int* dmap,
                              const double* Z, const int* zoff, const int* m, const int* woff,
-                             int nsub, double* W, hipStream_t st) {
-  hipLaunchKernelGGL(k_galerkin_w, dim3(nsub), dim3(256), 0, st, An->rowptr, An->col, An->val,
-                     sub_ptr, dmap, Z, zoff, m, woff, W);
+                             int nsub, int64_t maxwork, double* W, hipStream_t st) {
+  const unsigned ny = (unsigned)std::max<int64_t>(1, (maxwork + 255) / 256);
+  hipLaunchKernelGGL(k_galerkin_w, dim3(nsub, ny), dim3(256), 0, st, An->rowptr, An->col,
+                     An->val, sub_ptr, dmap, Z, zoff, m, woff, W);
   return hipGetLastError();
 }
 

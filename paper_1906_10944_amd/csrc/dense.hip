@@ -5,9 +5,10 @@
 //    stored in FP32 (mixed mode) or FP64.
 //  * Shifted matrices C_j = A_N,j - sigma X_j A^o_j X_j over N_j (the matrix
 //    of the shift-and-invert transform of Sec. 4.4), FP64.
-// One block per subdomain: it clears its tiles (identity on the padding)
-// and then every thread owns whole rows, so no two threads write the same
-// entry.
+// The caller clears the tiles (one device-wide fill); the grid is
+// (subdomain[, group of 256 rows]) and every thread owns whole rows (a unit
+// diagonal first, the identity on padding rows, then the row's entries), so
+// no two threads write the same entry.
 #include "internal.h"
 
 namespace geneo {
@@ -15,15 +16,6 @@ namespace geneo {
 template <typename T>
 __device__ __forceinline__ T* tile_elem(T* base, int r, int c) {
   return base + tile_idx(r / TS, c / TS) * TSQ + (r % TS) * TS + (c % TS);
-}
-
-template <typename T>
-__device__ void clear_tiles(T* base, int nt) {
-  const int64_t ne = tri_tiles(nt) * TSQ;
-  for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) base[e] = (T)0;
-  __syncthreads();
-  for (int r = threadIdx.x; r < nt * TS; r += blockDim.x) *tile_elem(base, r, r) = (T)1;
-  __syncthreads();
 }
 
 __device__ __forceinline__ int bsearch_row(const int* a, int n, int key) {
@@ -48,11 +40,11 @@ __global__ __launch_bounds__(256) void k_densify_dirichlet(
   const int j = jobs[blockIdx.x];
   const int nt = ntl[j];
   T* base = tiles + toff[j] * TSQ;
-  clear_tiles(base, nt);
   const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
   const int v0 = voff[j];
   const int* Nj = sub_idx + s0;
-  for (int d = threadIdx.x; d < nt * TS; d += blockDim.x) {
+  for (int d = blockIdx.y * blockDim.x + threadIdx.x; d < nt * TS; d += blockDim.x * gridDim.y) {
+    *tile_elem(base, d, d) = (T)1;
     int g = dglob[v0 + d];
     if (g < 0) continue;
     double sd = dscale[v0 + d];
@@ -70,14 +62,15 @@ hipError_t launch_densify_dirichlet(bool fp32, void* tiles, const int64_t* toff,
                                     const int* voff, const int* jobs, int njobs,
                                     const int* sub_ptr, const int* sub_idx, const int* dmap,
                                     const int* dglob, const double* dscale, const geneo_csr_t* A,
-                                    hipStream_t st) {
+                                    int ntmax, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
+  const dim3 grid(njobs, std::max(1, (ntmax * TS + 255) / 256));
   if (fp32)
-    hipLaunchKernelGGL(k_densify_dirichlet<float>, dim3(njobs), dim3(256), 0, st, (float*)tiles,
+    hipLaunchKernelGGL(k_densify_dirichlet<float>, grid, dim3(256), 0, st, (float*)tiles,
                        toff, nt, voff, jobs, sub_ptr, sub_idx, dmap, dglob, dscale, A->rowptr,
                        A->col, A->val);
   else
-    hipLaunchKernelGGL(k_densify_dirichlet<double>, dim3(njobs), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_densify_dirichlet<double>, grid, dim3(256), 0, st,
                        (double*)tiles, toff, nt, voff, jobs, sub_ptr, sub_idx, dmap, dglob,
                        dscale, A->rowptr, A->col, A->val);
   return hipGetLastError();
@@ -92,9 +85,10 @@ __global__ __launch_bounds__(256) void k_densify_shifted(
   const int j = blockIdx.x;
   const int nt = ntl[j];
   double* base = tiles + toff[j] * TSQ;
-  clear_tiles(base, nt);
   const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
-  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+  for (int a = blockIdx.y * blockDim.x + threadIdx.x; a < nt * TS; a += blockDim.x * gridDim.y) {
+    *tile_elem(base, a, a) = 1.0;
+    if (a >= n) continue;
     for (int p = an_rp[s0 + a]; p < an_rp[s0 + a + 1]; ++p) {
       int c = an_col[p];
       if (c <= a) *tile_elem(base, a, c) = an_val[p];
@@ -113,6 +107,9 @@ hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int*
                                   const int* sub_ptr, const double* pou,
                                   const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
                                   double sigma, hipStream_t st) {
+  // one workgroup per subdomain: measured faster here than splitting the
+  // rows over several (the Dirichlet fill, launched for fewer matrices,
+  // splits them)
   hipLaunchKernelGGL(k_densify_shifted, dim3(nsub), dim3(256), 0, st, tiles, toff, nt, sub_ptr,
                      pou, An->rowptr, An->col, An->val, Ao->rowptr, Ao->col, Ao->val, sigma);
   return hipGetLastError();

@@ -44,7 +44,8 @@ hipError_t launch_densify_dirichlet(bool fp32, void* tiles, const int64_t* toff,
                                     const int* nt, const int* voff, const int* jobs,
                                     int njobs, const int* sub_ptr, const int* sub_idx,
                                     const int* dmap, const int* dglob, const double* dscale,
-                                    const geneo_csr_t* A, hipStream_t st);
+                                    const geneo_csr_t* A, int ntmax /* max tile count */,
+                                    hipStream_t st);
 hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int* nt,
                                   int nsub, const int* sub_ptr, const double* pou,
                                   const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
@@ -205,7 +206,7 @@ hipError_t launch_basis(const double* P, const int* voff, int b, const int* sub_
 // ------------------------------------------------------------ coarse.hip
 hipError_t launch_galerkin_w(const geneo_csr_batch_t* An, const int* sub_ptr, const int* dmap,
                              const double* Z, const int* zoff, const int* m,
-                             const int* woff, int nsub, double* W, hipStream_t st);
+                             const int* woff, int nsub, int64_t maxwork /* max_j |N_j| m_j */, double* W, hipStream_t st);
 hipError_t launch_coarse_blocks(const int2* pairs, int npairs, const int* sub_ptr,
                                 const int* sub_idx, const int* didx, const int* dvoff,
                                 const int* nd, const double* Z, const int* zoff,
