@@ -135,9 +135,11 @@ struct PotrfCfg {
   // staged panel rows: [2 buffers][KB][CH][TS][LDI]
   static constexpr int YBUF = KB * CH * TS * LDI;
   static constexpr int STAGE_BYTES = 2 * YBUF * (int)sizeof(T);
-  // slice partial sums: one wavefront's accumulators per slot, NW-1 slots
+  // split updates use at most NWS wavefronts (FP64: 8, to keep the partial
+  // sums within LDS); one wavefront's accumulators per slot, NWS-1 slots
+  static constexpr int NWS = (sizeof(T) == 8 && NW > 8) ? 8 : NW;
   static constexpr int PART = 2 * KB * 4 * 64;
-  static constexpr int PART_BYTES = (NW - 1) * PART * (int)sizeof(T);
+  static constexpr int PART_BYTES = (NWS - 1) * PART * (int)sizeof(T);
   static constexpr int SHARED_BYTES = STAGE_BYTES > PART_BYTES ? STAGE_BYTES : PART_BYTES;
   // 16-byte vectors per thread when staging one chunk
   static constexpr int VEC = 16 / (int)sizeof(T);
@@ -261,7 +263,7 @@ __device__ __forceinline__ void bulk_split(T* A, int nt, int k0, int kn, int w, 
   const int fi = lane & 15, fg = lane >> 4;
   const int frag = fi * TS + 8 * fg;
   const int nit = 2 * (nt - k0);
-  const int ns = min(NW / nit, k0);
+  const int ns = min(Cfg::NWS / nit, k0);
   const int it = w % nit, sl = w / nit;
   const bool act = sl < ns;
   const int i = k0 + (it >> 1), rq = it & 1;
@@ -403,7 +405,8 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
     const int kn = min(KB, nt - k0);
     // ---- bulk update of the panel with columns 0 .. k0-1
     if (k0 > 0) {
-      if (2 * (nt - k0) < NW) bulk_split<T, NW, KB>(A, nt, k0, kn, w, lane, sBuf);
+      // split only while every item gets at least one of the NWS slices
+      if (2 * (nt - k0) < Cfg::NWS) bulk_split<T, NW, KB>(A, nt, k0, kn, w, lane, sBuf);
       else if (STAGED) bulk_staged<T, NW, KB>(A, nt, k0, kn, w, tid, lane, sBuf);
       else bulk_direct<T, NW, KB>(A, nt, k0, kn, w, lane);
     }
@@ -498,11 +501,11 @@ __global__ __launch_bounds__(512) void k_potrf_local_f64(double* tiles, const in
                                                          const int* jobs, double pivtol) {
   potrf_body<double, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
 }
-__global__ __launch_bounds__(512) void k_potrf_shifted_f64(double* tiles, const int64_t* toff,
-                                                           const int* nt, double* dinv,
-                                                           const int64_t* doff, int* status,
-                                                           const int* jobs, double pivtol) {
-  potrf_body<double, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+#define POTRF64S_NW 12
+__global__ __launch_bounds__(POTRF64S_NW * 64) void k_potrf_shifted_f64(
+    double* tiles, const int64_t* toff, const int* nt, double* dinv, const int64_t* doff,
+    int* status, const int* jobs, double pivtol) {
+  potrf_body<double, POTRF64S_NW, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
 }
 
 hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
@@ -520,7 +523,7 @@ hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, 
                          (double*)dinv, doff, status, jobs, pivtol);
       break;
     case CholRole::ShiftedF64:
-      hipLaunchKernelGGL(k_potrf_shifted_f64, grid, blk, 0, st, (double*)tiles, toff, nt,
+      hipLaunchKernelGGL(k_potrf_shifted_f64, grid, dim3(POTRF64S_NW * 64), 0, st, (double*)tiles, toff, nt,
                          (double*)dinv, doff, status, jobs, pivtol);
       break;
   }
