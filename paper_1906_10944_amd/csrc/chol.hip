@@ -1,15 +1,15 @@
 // Dense Cholesky factorisations on the matrix cores (16x16x4 MFMA).
 //
 //  * k_potrf_*: batched blocked left-looking factorisation, one workgroup of
-//    8 (FP64) or 16 (FP32) wavefronts per local matrix, panels of four
-//    32-wide tile columns.
+//    8 (local FP64), 12 (shifted FP64) or 16 (FP32) wavefronts per matrix,
+//    panels of four 32-wide tile columns.
 //    Bulk update of a panel with every finished column to its left: a work
 //    item is the 16-row half of one tile row and produces its slab of all
 //    panel tiles, so each tile L(i, jj) read from memory feeds eight
 //    matrix-core chains per k-step.  The panel rows L(k0.., jj) that all
 //    items share are staged in LDS in double-buffered chunks.  When there
-//    are fewer items than wavefronts the jj range is split and the partial
-//    sums meet in LDS in a fixed order.  Panel: for each column c the
+//    are fewer items than wavefronts (FP64: than 8) the jj range is split
+//    and the partial sums meet in LDS in a fixed order.  Panel: for each column c the
 //    diagonal tile is factored and inverted by one wavefront in registers,
 //    then L(i, c) = A(i, c) Dinv(c)^T, then the later panel columns take
 //    the rank-32 update from column c.  A failed pivot test stops that
