@@ -52,8 +52,31 @@ __device__ void gram(const double* X, const double* Y, int npad, int b, double (
   const int rq = qd / ncq, cq = qd % ncq;
   d4_t acc = acc_zero<double>();
   if (sl < ns && w < nq * ns) {
+    // chunks t, t + ns, ... in that order, two chunks' loads in flight
     const int nchunk = npad / TS;
-    for (int t = sl; t < nchunk; t += ns)
+    const int i = lane & 15, k = lane >> 4;
+    const double* Xq = X + rq * 16 + k * b + i;
+    const double* Yq = Y + cq * 16 + k * b + i;
+    int t = sl;
+    for (; t + ns < nchunk; t += 2 * ns) {
+      double xa[8], ya[8], xb[8], yb[8];
+      const int64_t oa = (int64_t)t * TS * b, ob = (int64_t)(t + ns) * TS * b;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        xa[kk] = Xq[oa + kk * 4 * b];
+        ya[kk] = Yq[oa + kk * 4 * b];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        xb[kk] = Xq[ob + kk * 4 * b];
+        yb[kk] = Yq[ob + kk * 4 * b];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) acc = Mfma<double>::run(xa[kk], ya[kk], acc);
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) acc = Mfma<double>::run(xb[kk], yb[kk], acc);
+    }
+    if (t < nchunk)
       q_xTy<double>(acc, X + (int64_t)t * TS * b + rq * 16, b, Y + (int64_t)t * TS * b + cq * 16,
                     b, lane);
   }
