@@ -548,6 +548,14 @@ struct SetupScratch {
   bool check_cst = false;  // the coarse factor's status is read at the end
   int nbrows = 0;  // rows of B that hold entries
   int nnzB = 0;    // entries of B
+  // pinned copies (NULL without pinned staging): the row count of B with
+  // the event after its copy, and the shifted factor's pivot tests
+  int* pin_nb = nullptr;
+  hipEvent_t ev_nb = nullptr;
+  int* pin_st2 = nullptr;
+  ~SetupScratch() {
+    if (ev_nb) (void)hipEventDestroy(ev_nb);
+  }
   DBuf<double> sbest;
   DBuf<int2> tjobs32, tjobs64, tjobsH, pairs;
   DBuf<uint8_t> adj;
@@ -784,6 +792,13 @@ void eigen_prepare(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     X.brows.alloc(std::max<int64_t>(h->nloc, 1));
     HIPCHK(launch_bcompact(S->sub_ptr, S->pou, Ao, nsub, h->nloc, LN.maxnt * TS, X.bcnt.p,
                            X.brp.p, X.bcol.p, X.bval.p, X.brpos.p, X.brows.p, sb));
+    // the row count goes to pinned memory now; the sweeps read it much later
+    X.pin_nb = t_arena.active ? (int*)t_arena.take(sizeof(int)) : nullptr;
+    if (X.pin_nb) {
+      HIPCHK(hipMemcpyAsync(X.pin_nb, X.brpos.p + h->nloc, sizeof(int), hipMemcpyDeviceToHost, sb));
+      HIPCHK(hipEventCreateWithFlags(&X.ev_nb, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(X.ev_nb, sb));
+    }
   }
   // W = B T is zero away from the rows of B that hold entries: cleared
   // once, the products then write only those rows
@@ -883,6 +898,10 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
     ProfScope ps("chol_shifted_f64", sb, 2.0 * 8.0 * pkN, flN);
     HIPCHK(launch_chol_batched(CholRole::ShiftedF64, X.G.p, X.toffN.p, X.ntN.p, X.DG.p, X.doffN.p, X.status2.p,
                                X.jobsN.p, nsub, 0.0, sb));
+    X.pin_st2 = t_arena.active ? (int*)t_arena.take((size_t)nsub * sizeof(int)) : nullptr;
+    if (X.pin_st2)
+      HIPCHK(hipMemcpyAsync(X.pin_st2, X.status2.p, (size_t)nsub * sizeof(int),
+                            hipMemcpyDeviceToHost, sb));
   }
   tm[0].stop(sb);
   // the FP64 refactors and the FP32 inverse factors on the other stream
@@ -898,13 +917,27 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   const int b = h->b;
-  {
-    auto stat = download(X.status2.p, nsub, sb);
+  // No host wait before the first sweeps: the row count of B was copied
+  // to pinned memory before the shifted factorisation, and the pivot tests
+  // of that factorisation are checked at the first read of the sweep flags
+  // (a failed factor makes only wrong numbers in the sweeps meanwhile:
+  // every loop bound and address is independent of the matrix values).
+  if (X.pin_nb) {
+    HIPCHK(hipEventSynchronize(X.ev_nb));
+    X.nbrows = *X.pin_nb;
+    HIPCHK(hipEventDestroy(X.ev_nb));
+    X.ev_nb = nullptr;
+  } else {
+    X.nbrows = download(X.brpos.p + h->nloc, 1, sb)[0];
+  }
+  bool shift_checked = false;
+  auto check_shifted = [&](const int* stat) {
+    shift_checked = true;
     for (int j = 0; j < nsub; ++j)
       if (stat[j]) fail(GENEO_ERR_SHIFT_NOT_SPD, "A_N - sigma B of subdomain " +
                                                      std::to_string(j) + " is not SPD");
-    X.nbrows = download(X.brpos.p + h->nloc, 1, sb)[0];
-  }
+  };
+  if (!X.pin_st2) check_shifted(download(X.status2.p, nsub, sb).data());
   // ---- block subspace iteration on S = G^{-1} B G^{-T}
   tm[1].start(sb);
   const EigWork& wk = X.wk;
@@ -918,7 +951,14 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   // launches and changes nothing.  With per-kernel timing on, each sweep is
   // read at once (its byte counts then follow the active set exactly).
   int* aflag[2] = {nullptr, nullptr};
-  hipEvent_t aev[2] = {nullptr, nullptr};
+  struct EvPair {  // destroyed also when a check below throws
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~EvPair() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } aevs;
+  hipEvent_t* aev = aevs.e;
   bool lag = !prof_on() && t_arena.active;
   for (int k = 0; k < 2 && lag; ++k) {
     aflag[k] = (int*)t_arena.take((size_t)nsub * sizeof(int));
@@ -932,6 +972,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     } else {
       act = download(X.active.p, nsub, sb);
     }
+    // the pivot-test copy precedes every sweep on sb, so it has landed
+    if (!shift_checked) check_shifted(X.pin_st2);
     nact = 0;
     for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
   };
@@ -1017,8 +1059,10 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     }
   }
   if (lag && !finished && sweeps > 0) read_active(sweeps);
-  for (int k = 0; k < 2; ++k)
-    if (aev[k]) HIPCHK(hipEventDestroy(aev[k]));
+  if (!shift_checked) {
+    HIPCHK(hipStreamSynchronize(sb));
+    check_shifted(X.pin_st2);
+  }
   h->info.eig_sweeps = sweeps;
   if (nact > 0) {
     auto best = download(X.sbest.p, nsub, sb);

@@ -5,6 +5,10 @@ inputs (every kernel still runs to its normal exit):
   negative inside subdomain 0): the factorisation records the failed pivot
   and the setup returns GENEO_ERR_LOCAL_NOT_SPD, in FP64 and in mixed mode
   (where the FP32 pivot test fails first and the FP64 refactor then fails);
+* a shifted matrix A_N - sigma B that is not SPD (one diagonal entry of a
+  local Neumann matrix made strongly negative inside subdomain 1): the
+  setup returns GENEO_ERR_SHIFT_NOT_SPD (the pivot tests are read back
+  while the first eigen sweeps are already queued);
 * PCG stopped by maxit: GENEO_ERR_MAXIT with the iterations done reported;
 * eigen sweeps stopped by eig_maxit: GENEO_ERR_EIGEN_NOCONV.
 
@@ -60,6 +64,31 @@ def test_local_matrix_not_spd(small, precision):
         assert "subdomain 0" in str(e.value)
     finally:
         sysm.A_val[pos] = saved
+        torch.cuda.synchronize()
+    _healthy(prob, sysm)
+
+
+def test_shifted_matrix_not_spd(small):
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    sp_ = sysm.sub_ptr.cpu().numpy()
+    rp = sysm.loc_rowptr.cpu().numpy()
+    col = sysm.loc_col.cpu().numpy()
+    r0, n = int(sp_[1]), int(sp_[2] - sp_[1])
+    r = n // 2
+    pos = int(rp[r0 + r]) + int(np.nonzero(col[rp[r0 + r]:rp[r0 + r + 1]] == r)[0][0])
+    saved = sysm.an_val[pos].item()
+    sysm.an_val[pos] = -1e3 * abs(saved)
+    torch.cuda.synchronize()
+    try:
+        for precision in (1, 0):
+            with pytest.raises(G.GeneoError) as e:
+                gpu_setup(sysm, prob, precision=precision)
+            say("[errors]", e.value)
+            assert e.value.code == G.GENEO_ERR_SHIFT_NOT_SPD
+            assert "subdomain 1" in str(e.value)
+    finally:
+        sysm.an_val[pos] = saved
         torch.cuda.synchronize()
     _healthy(prob, sysm)
 
