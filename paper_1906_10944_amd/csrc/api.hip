@@ -619,9 +619,9 @@ std::vector<int2> lauum_job_list(const std::vector<int>& mats, const std::vector
 // Local Dirichlet factors A_j = R_j A R_j^T and their inverses, on
 // stream st.  Returns after the work is enqueued and the pivot tests are
 // read back.
-void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
-                 const geneo_subdomains_t* S, hipStream_t st,
-                 const std::function<void(hipEvent_t)>& after_fp32) {
+std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
+                                  const geneo_subdomains_t* S, hipStream_t st,
+                                  const std::function<void(hipEvent_t)>& after_fp32) {
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   std::vector<int> all(nsub);
@@ -688,85 +688,91 @@ void setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
     f64list = all;
     after_fp32(nullptr);
   }
-  h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
-  h->njobs64 = (int)f64list.size();
-  h->jobs64.upload(f64list, st);
-  std::vector<int64_t> toff64(nsub, 0), doff64(nsub, 0);
-  int64_t tt = 0, dd = 0;
-  for (int j : f64list) {
-    toff64[j] = tt;
-    doff64[j] = dd;
-    tt += tri_tiles(h->LD.nt[j]);
-    dd += h->LD.nt[j];
-  }
-  h->toff64.upload(toff64, st);
-  h->doff64.upload(doff64, st);
-  h->toff64_host = toff64;
-  {
-    std::vector<int2> lj(nsub);
-    std::vector<char> f(nsub, 0);
-    for (int j : f64list) f[j] = 1;
-    for (int j = 0; j < nsub; ++j) lj[j] = make_int2(j, f[j]);
-    h->ljobs_host = lj;
-  }
-  if (!f64list.empty()) {
-    X.L64.alloc(tt * TSQ);
-    X.D64.alloc(dd * TSQ);
-    double pk64 = 0.0, fl64 = 0.0;
-    int mx = 0;
+  // The FP64 refactors of the subdomains that failed the pivot test (and
+  // their inverses) go back to the caller as a step to enqueue later: their
+  // many short launches take host time that the first eigen sweep should
+  // not wait for.
+  return [h, &X, A, S, st, nsub, mixed, f64list = std::move(f64list)]() mutable {
+    h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
+    h->njobs64 = (int)f64list.size();
+    h->jobs64.upload(f64list, st);
+    std::vector<int64_t> toff64(nsub, 0), doff64(nsub, 0);
+    int64_t tt = 0, dd = 0;
     for (int j : f64list) {
-      mx = std::max(mx, h->LD.nt[j]);
-      pk64 += packed(h->nd_host[j]);
-      fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
+      toff64[j] = tt;
+      doff64[j] = dd;
+      tt += tri_tiles(h->LD.nt[j]);
+      dd += h->LD.nt[j];
     }
+    h->toff64.upload(toff64, st);
+    h->doff64.upload(doff64, st);
+    h->toff64_host = toff64;
     {
-      ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
-      HIPCHK(hipMemsetAsync(X.L64.p, 0, X.L64.n * sizeof(double), st));
-      HIPCHK(launch_densify_dirichlet(false, X.L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                                      h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
-                                      h->dmap.p, h->dglob.p, h->dscale.p, A, mx, st));
+      std::vector<int2> lj(nsub);
+      std::vector<char> f(nsub, 0);
+      for (int j : f64list) f[j] = 1;
+      for (int j = 0; j < nsub; ++j) lj[j] = make_int2(j, f[j]);
+      h->ljobs_host = lj;
     }
-    {
-      // a few refactors (mixed mode): tile-column steps over many short
-      // workgroups, which leave the CUs to the eigen sweeps in between; a
-      // full batch (FP64 mode): one workgroup per matrix
-      ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
-      if (h->njobs64 <= kStepCholMax) {
-        HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                                 h->jobs64.p, h->njobs64, mx, X.status.p, st));
-      } else {
-        HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p,
-                                   h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
+    if (!f64list.empty()) {
+      X.L64.alloc(tt * TSQ);
+      X.D64.alloc(dd * TSQ);
+      double pk64 = 0.0, fl64 = 0.0;
+      int mx = 0;
+      for (int j : f64list) {
+        mx = std::max(mx, h->LD.nt[j]);
+        pk64 += packed(h->nd_host[j]);
+        fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
       }
+      {
+        ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
+        HIPCHK(hipMemsetAsync(X.L64.p, 0, X.L64.n * sizeof(double), st));
+        HIPCHK(launch_densify_dirichlet(false, X.L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
+                                        h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
+                                        h->dmap.p, h->dglob.p, h->dscale.p, A, mx, st));
+      }
+      {
+        // a few refactors (mixed mode): tile-column steps over many short
+        // workgroups, which leave the CUs to the eigen sweeps in between; a
+        // full batch (FP64 mode): one workgroup per matrix
+        ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
+        if (h->njobs64 <= kStepCholMax) {
+          HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
+                                   h->jobs64.p, h->njobs64, mx, X.status.p, st));
+        } else {
+          HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p,
+                                     h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
+        }
+      }
+      std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
+      X.tjobs64.upload(tj, st);
+      std::vector<int2> lj = lauum_job_list(f64list, h->LD.nt);
+      X.ljobs64.upload(lj, st);
+      X.XT64.alloc(tt * TSQ);
+      {
+        ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
+        HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, X.XT64.p, h->toff64.p, h->doff64.p, h->ntD.p,
+                            X.tjobs64.p, (int)tj.size(), st));
+      }
+      h->S64.alloc(tt * TSQ);
+      h->W64.alloc(tt * TS);
+      ProfScope ps("lauum_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
+      HIPCHK(launch_lauum(false, X.XT64.p, h->S64.p, h->toff64.p, h->ntD.p, X.ljobs64.p,
+                          (int)lj.size(), st));
     }
-    std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
-    X.tjobs64.upload(tj, st);
-    std::vector<int2> lj = lauum_job_list(f64list, h->LD.nt);
-    X.ljobs64.upload(lj, st);
-    X.XT64.alloc(tt * TSQ);
-    {
-      ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
-      HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, X.XT64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                          X.tjobs64.p, (int)tj.size(), st));
+    double b32 = 0.0, b64 = 0.0;
+    std::vector<char> is64(nsub, 0);
+    for (int j : f64list) is64[j] = 1;
+    for (int j = 0; j < nsub; ++j) {
+      double nn = h->nd_host[j];
+      if (is64[j]) b64 += 8.0 * packed(nn) + 16.0 * nn;
+      else b32 += 4.0 * packed(nn) + 16.0 * nn;
     }
-    h->S64.alloc(tt * TSQ);
-    h->W64.alloc(tt * TS);
-    ProfScope ps("lauum_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
-    HIPCHK(launch_lauum(false, X.XT64.p, h->S64.p, h->toff64.p, h->ntD.p, X.ljobs64.p,
-                        (int)lj.size(), st));
-  }
-  double b32 = 0.0, b64 = 0.0;
-  std::vector<char> is64(nsub, 0);
-  for (int j : f64list) is64[j] = 1;
-  for (int j = 0; j < nsub; ++j) {
-    double nn = h->nd_host[j];
-    if (is64[j]) b64 += 8.0 * packed(nn) + 16.0 * nn;
-    else b32 += 4.0 * packed(nn) + 16.0 * nn;
-  }
-  h->bytes_symv32 = b32;
-  h->bytes_symv64 = b64;
-  h->info.bytes_local_factors = (int64_t)(h->S32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->S64.n * 8;
-  h->f64list = f64list;
+    h->bytes_symv32 = b32;
+    h->bytes_symv64 = b64;
+    h->info.bytes_local_factors = (int64_t)(h->S32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->S64.n * 8;
+    h->f64list = f64list;
+  };
 }
 
 // Start of the eigen sweeps, independent of the shifted factors: the
@@ -911,9 +917,12 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
 }
 
 // Eigen sweeps, coarse basis, Galerkin product and coarse factor on sb.
+// after_first_sweep is called once, right after the first sweep is enqueued
+// (or before any error return that follows it).
 void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                   const geneo_subdomains_t* S, const geneo_csr_batch_t* An,
-                  const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm) {
+                  const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm,
+                  const std::function<void()>& after_first_sweep) {
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   const int b = h->b;
@@ -978,6 +987,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     for (int j = 0; j < nsub; ++j) nact += act[j] != 0;
   };
   bool finished = false;
+  bool local_done = false;
   for (int it = 1; it <= o.eig_maxit; ++it) {
     // algorithmic traffic of this sweep: the factor G_j of every active
     // subdomain is read once per triangular solve, plus its b columns
@@ -1016,6 +1026,12 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(hipMemcpyAsync(aflag[it & 1], X.active.p, (size_t)nsub * sizeof(int),
                             hipMemcpyDeviceToHost, sb));
       HIPCHK(hipEventRecord(aev[it & 1], sb));
+    }
+    if (!local_done) {
+      local_done = true;
+      after_first_sweep();
+    }
+    if (lag) {
       if (it > 1) {
         read_active(it - 1);
         if (nact == 0) {
@@ -1058,6 +1074,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, it, X.active.p, wk, sb));
     }
   }
+  if (!local_done) after_first_sweep();
   if (lag && !finished && sweeps > 0) read_active(sweeps);
   if (!shift_checked) {
     HIPCHK(hipStreamSynchronize(sb));
@@ -1250,11 +1267,16 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   // either.
   LocalLayout LN;
   tmL.start(st);
-  setup_local(h, X, A, S, st, [&](hipEvent_t after) {
+  std::function<void()> refactor = setup_local(h, X, A, S, st, [&](hipEvent_t after) {
     if (coarse) setup_shifted(h, X, LN, S, An, Ao, h->hs, tmC, after);
   });
-  tmL.stop(st);
-  if (coarse) setup_coarse(h, X, LN, S, An, Ao, h->hs, tmC);
+  // the FP64 refactors are enqueued once the first eigen sweep is
+  const std::function<void()> local_rest = [&]() {
+    refactor();
+    tmL.stop(st);
+  };
+  if (coarse) setup_coarse(h, X, LN, S, An, Ao, h->hs, tmC, local_rest);
+  else local_rest();
   HIPCHK(hipStreamSynchronize(st));
   {
     auto stat = download(X.status.p, nsub, st);
