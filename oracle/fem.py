@@ -13,8 +13,11 @@ boundary data the free unknowns are exactly those of the eliminated system.
 
 Pins (tests/test_oracle_fem.py): closed-form Q1 stencils, zero row sums of
 the Neumann operator, O(h^2) nodal convergence to a manufactured solution,
-the six rigid-body modes spanning the kernel of a free elasticity element and
-a patch test.
+the six rigid-body modes spanning the kernel of a free elasticity element, a
+patch test, the element energy of every linear field (vol * eps^T C eps with
+engineering shear strains, written out independently of the strain matrix)
+and a bar in uniaxial stress whose displacement follows from the engineering
+constants (E, nu) in closed form.
 """
 import itertools
 

@@ -154,3 +154,111 @@ def test_elasticity_patch_test():
     # six-dimensional kernel of the free assembled operator
     R = _rbm(coords)
     assert np.max(np.abs(A @ R)) < 1e-11 * np.max(np.abs(A.data)) * np.max(np.abs(R))
+
+
+# ------------------------------------------------ elasticity constitutive pins
+# Sec. 2, eq. (3): the bilinear form integrates C eps(u) : eps(v).  The pins
+# below fix the strain-displacement map (engineering shear, Voigt order 11,
+# 22, 33, 23, 13, 12) and the constitutive coupling independently of the
+# oracle's strain matrix: the six-zero-mode and patch pins above hold for
+# any symmetric C and any scaling of the shear rows.
+
+def _engineering_strain(G):
+    """Voigt strain of the linear field u(x) = G x, written out from the
+    definition eps_ij = (G_ij + G_ji) / 2 with engineering shear 2 eps_ij."""
+    return np.array([G[0, 0], G[1, 1], G[2, 2],
+                     G[1, 2] + G[2, 1], G[0, 2] + G[2, 0], G[0, 1] + G[1, 0]])
+
+
+def _random_spd_voigt(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = rng.normal(size=(6, 6))
+    return M @ M.T + 6.0 * np.eye(6)
+
+
+@pytest.mark.parametrize("which", ["ply", "ply90", "resin", "random"])
+def test_elasticity_element_energy_of_linear_fields(which):
+    """For u = G x the strain is constant, 2-point Gauss is exact, and the
+    element energy is u^T K_e u = vol * eps(G)^T C eps(G)."""
+    ply = synth.ply_stiffness(160.0, 10.0, 10.0, 5.0, 5.0, 5.0, 0.3, 0.3, 0.3)
+    C = {"ply": ply, "ply90": synth.rotate_z90(ply),
+         "resin": synth.isotropic_stiffness(4.0, 0.35), "random": _random_spd_voigt(5)}[which]
+    h = np.array([0.8, 1.1, 0.6])
+    K = fem.elasticity_element_matrix(h, C)
+    off = np.array([[(a >> i) & 1 for i in range(3)] for a in range(8)], float) * h
+    rng = np.random.Generator(np.random.PCG64(17))
+    for _ in range(6):
+        G = rng.normal(size=(3, 3))
+        u = (off @ G.T).ravel()            # vertex-major, 3 components
+        eps = _engineering_strain(G)
+        exact = np.prod(h) * eps @ C @ eps
+        assert u @ K @ u == pytest.approx(exact, rel=1e-12)
+    # pure shear fields excite only the shear block of C
+    for (i, j, v) in ((0, 1, 5), (0, 2, 4), (1, 2, 3)):
+        G = np.zeros((3, 3))
+        G[i, j] = 1.0
+        u = (off @ G.T).ravel()
+        assert u @ K @ u == pytest.approx(np.prod(h) * C[v, v], rel=1e-12)
+
+
+def _bar_nodal_traction(prob, sigma0):
+    """Consistent nodal loads of the uniform tractions +-sigma0 e_x on the
+    end faces x = 0 and x = L of a box: each bilinear face element passes a
+    quarter of its force to each of its four nodes."""
+    nx, ny, nz = prob.ne
+    hx, hy, hz = prob.h
+    f = np.zeros((prob.nnodes, 3))
+    wy = np.full(ny + 1, hy)
+    wy[[0, -1]] = hy / 2
+    wz = np.full(nz + 1, hz)
+    wz[[0, -1]] = hz / 2
+    for iz in range(nz + 1):
+        for iy in range(ny + 1):
+            w = wy[iy] * wz[iz]
+            k0 = 0 + (nx + 1) * (iy + (ny + 1) * iz)
+            k1 = nx + (nx + 1) * (iy + (ny + 1) * iz)
+            f[k0, 0] -= sigma0 * w
+            f[k1, 0] += sigma0 * w
+    return f.ravel()
+
+
+@pytest.mark.parametrize("which", ["resin", "ply", "ply90"])
+def test_elasticity_uniaxial_bar_closed_form(which):
+    """A bar pulled by end tractions sigma0, held only against rigid motions
+    (six single-component supports), is in uniaxial stress: its displacement
+    is u = diag(eps_1, eps_2, eps_3) x with eps from the engineering
+    constants (eps_1 = sigma0 / E_x, eps_2 = -nu_xy sigma0 / E_x, ...), which
+    Q1 reproduces exactly."""
+    E1, E2, E3, G12, nu12, nu13, nu23 = 160.0, 10.0, 10.0, 5.0, 0.3, 0.3, 0.3
+    ply = synth.ply_stiffness(E1, E2, E3, G12, G12, G12, nu12, nu13, nu23)
+    sigma0 = 0.37
+    if which == "resin":
+        E, nu = 4.0, 0.35
+        C = synth.isotropic_stiffness(E, nu)
+        eps = sigma0 / E * np.array([1.0, -nu, -nu])
+    elif which == "ply":
+        C = ply
+        eps = sigma0 / E1 * np.array([1.0, -nu12, -nu13])
+    else:   # fibre along y: pulled across the fibres, nu_21 = nu_12 E2 / E1
+        C = synth.rotate_z90(ply)
+        eps = sigma0 / E2 * np.array([1.0, -nu12 * E2 / E1, -nu23])
+    ne, h = (6, 2, 3), (0.5, 0.4, 0.3)
+    Cs = np.broadcast_to(C, (ne[2], ne[1], ne[0], 6, 6))
+    p = synth.elasticity_problem("bar", Cs, ne, (1, 1, 1), 1, dirichlet=0,
+                                 load=(0.0, 0.0, 0.0), h=h)
+    K = fem.assemble_neumann(p).tocsr()
+    f = _bar_nodal_traction(p, sigma0)
+    # supports: node (0,0,0) all components, (L,0,0) y and z, (0,H,0) z
+    nx, ny = ne[0], ne[1]
+    fixed = [0, 1, 2, 3 * nx + 1, 3 * nx + 2, 3 * (nx + 1) * ny + 2]
+    free = np.setdiff1d(np.arange(p.ndof), fixed)
+    import scipy.sparse.linalg as spla
+    u = np.zeros(p.ndof)
+    u[free] = spla.spsolve(K[free][:, free].tocsc(), f[free])
+    k = np.arange(p.nnodes)
+    coords = np.stack([(k % (nx + 1)) * h[0], ((k // (nx + 1)) % (ny + 1)) * h[1],
+                       (k // ((nx + 1) * (ny + 1))) * h[2]], axis=1)
+    exact = (coords * eps[None, :]).ravel()
+    assert np.max(np.abs(u - exact)) <= 1e-11 * np.max(np.abs(exact))
+    # the supports carry no reaction: the end tractions are self-equilibrated
+    assert np.max(np.abs((K @ exact - f))) <= 1e-11 * sigma0

@@ -169,3 +169,61 @@ def test_inverted_cg_coefficient_is_caught(monkeypatch):
         return res
     monkeypatch.setattr(pcg, "pcg", bad_pcg)
     assert _caught(monkeypatch)
+
+
+# ---------------------------------------------- elasticity element mutations
+def _elasticity_pins_hold():
+    """The closed-form elasticity pins of test_oracle_fem, run as booleans."""
+    import test_oracle_fem as T
+    ok = True
+    for which in ("ply", "ply90", "resin", "random"):
+        try:
+            T.test_elasticity_element_energy_of_linear_fields(which)
+        except AssertionError:
+            ok = False
+    for which in ("resin", "ply", "ply90"):
+        try:
+            T.test_elasticity_uniaxial_bar_closed_form(which)
+        except AssertionError:
+            ok = False
+    return ok
+
+
+def test_elasticity_pins_hold_on_the_real_oracle():
+    assert _elasticity_pins_hold()
+
+
+def test_tensorial_shear_strain_is_caught(monkeypatch):
+    """Shear rows of the strain matrix halved (tensorial instead of
+    engineering shear): the kernel and patch pins still pass, the energy
+    pin must not."""
+    orig = fem.strain_matrix
+
+    def bad(grad_phys):
+        B = orig(grad_phys)
+        B[3:, :] *= 0.5
+        return B
+    monkeypatch.setattr(fem, "strain_matrix", bad)
+    assert not _elasticity_pins_hold()
+
+
+def test_scaled_shear_modulus_is_caught(monkeypatch):
+    orig = fem.elasticity_element_matrix
+
+    def bad(h, C):
+        C2 = np.array(C, dtype=float)
+        C2[3:, 3:] *= 2.0
+        return orig(h, C2)
+    monkeypatch.setattr(fem, "elasticity_element_matrix", bad)
+    assert not _elasticity_pins_hold()
+
+
+def test_dropped_poisson_coupling_is_caught(monkeypatch):
+    orig = fem.elasticity_element_matrix
+
+    def bad(h, C):
+        C2 = np.array(C, dtype=float)
+        C2[:3, :3] = np.diag(np.diag(C2[:3, :3]))
+        return orig(h, C2)
+    monkeypatch.setattr(fem, "elasticity_element_matrix", bad)
+    assert not _elasticity_pins_hold()
