@@ -19,7 +19,8 @@ Steps, in the paper's order and notation:
    count below a threshold capped at a maximum (Thm. 1, the threshold rule);
 4. coarse basis vectors X_j p, normalised in the l2 norm (Sec. 4.4);
 5. the coarse matrix A_H = R_H A R_H^T = Z^T A Z (Def. 2, Sec. 4.5) and its
-   Cholesky factor;
+   Cholesky factor (a pivot at or below n_c eps max_k (A_H)_kk counts as
+   singular);
 6. the two-level additive Schwarz operator (acting as the identity on the
    eliminated Dirichlet dofs, which lie in no D_j and have unit rows)
    M^{-1} = R_H^T A_H^{-1} R_H + sum_j R_j^T A_j^{-1} R_j (Def. 2).
@@ -224,11 +225,24 @@ def setup(prob, A=None, nev=None, tau=None, nev_max=None, coarse=True,
                             shape=(prob.ndof, off))
         AH = (g.Z.T @ (A @ g.Z)).toarray()
         g.AH = 0.5 * (AH + AH.T)
-        try:
-            g.LH = np.linalg.cholesky(g.AH)
-        except np.linalg.LinAlgError as e:
-            raise np.linalg.LinAlgError("coarse matrix is not SPD") from e
+        g.LH = coarse_cholesky(g.AH)
     return g
+
+
+def coarse_cholesky(AH):
+    """Cholesky factor of A_H (Def. 2).  A_H is SPD exactly when the basis
+    vectors are linearly independent; a pivot at or below
+    n_c * eps * max_k (A_H)_kk (what rounding alone leaves where the exact
+    pivot vanishes, e.g. for a repeated basis vector) is taken as singular."""
+    nc = AH.shape[0]
+    try:
+        L = np.linalg.cholesky(AH)
+    except np.linalg.LinAlgError as e:
+        raise np.linalg.LinAlgError("coarse matrix is not SPD") from e
+    tol = nc * np.finfo(np.float64).eps * np.max(np.diag(AH))
+    if np.min(np.diag(L)) ** 2 <= tol:
+        raise np.linalg.LinAlgError("coarse matrix is numerically singular")
+    return L
 
 
 def coarse_offsets(m):

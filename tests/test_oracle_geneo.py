@@ -241,3 +241,20 @@ def test_basis_vectors_normalised_signed_supported():
         for k in range(blk.shape[1]):
             i = np.argmax(np.abs(blk[:, k]))
             assert blk[i, k] > 0
+
+
+def test_coarse_cholesky_rejects_repeated_basis_vector():
+    """A_H is SPD iff the columns of Z are independent (Def. 2): a repeated
+    column makes it singular, and the factor must say so whatever sign the
+    rounding leaves on the vanishing pivot."""
+    p = synth.config1_channels(0, n=16, parts=2, n_channels=2, nev=3)
+    A, _ = fem.assemble(p)
+    g = geneo.setup(p, A=A)
+    Z = g.Z.toarray()
+    L = geneo.coarse_cholesky(g.AH)
+    assert np.allclose(L @ L.T, g.AH, rtol=0, atol=1e-13 * np.abs(g.AH).max())
+    for k in (0, g.nc // 2, g.nc - 1):
+        Zd = np.column_stack([Z, Z[:, k]])
+        AHd = Zd.T @ (A @ Zd)
+        with pytest.raises(np.linalg.LinAlgError):
+            geneo.coarse_cholesky(0.5 * (AHd + AHd.T))
