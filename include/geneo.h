@@ -37,7 +37,10 @@ enum {
   GENEO_ERR_LOCAL_NOT_SPD = 3,  /* a local Dirichlet matrix failed its FP64 Cholesky */
   GENEO_ERR_EIGEN_NOCONV = 4,   /* eigen sweeps hit eig_maxit before eig_tol
                                    (or a stagnation above eig_floor) */
-  GENEO_ERR_COARSE_NOT_SPD = 5, /* the coarse matrix A_H failed its Cholesky */
+  GENEO_ERR_COARSE_NOT_SPD = 5, /* the coarse matrix A_H failed its Cholesky:
+                                   a pivot at or below nc * eps * max_k (A_H)_kk
+                                   (numerically singular, e.g. a repeated
+                                   basis vector) */
   GENEO_ERR_MAXIT = 6,          /* PCG stopped at maxit; x and info are filled */
   GENEO_ERR_HIP = 7,            /* a HIP runtime call failed */
   GENEO_ERR_SHIFT_NOT_SPD = 8   /* A_N,j - sigma*B_j failed its Cholesky */
@@ -277,13 +280,15 @@ int geneo_get_eigenvalues(geneo_handle_t h, int* m, double* lam, int ldl);
  * is FP32. */
 int geneo_get_local_precision(geneo_handle_t h, int* fp64);
 
-/* Host copies of the coarse basis as dense columns over N_j: zoff
- * [nsub+1] receives the column offsets (zoff[j] = sum_{i<j} m_i).  `z`
- * (optional) receives, for each subdomain j, |N_j| x m_j values row major
- * at offset sum_{i<j} |N_i| m_i; zsize is its length, at least
- * sum_j |N_j| m_j.  `ah` (optional, may be NULL) receives A_H as nc x nc
- * row major. */
-int geneo_get_coarse(geneo_handle_t h, int* zoff, double* z, int64_t zsize,
+/* Host copies of the coarse basis (Def. 4) as dense columns over N_j:
+ * zoff [nsub+1] (host) receives the VALUE offsets of the blocks,
+ * zoff[j] = sum_{i<j} |N_i| m_i, so zoff[nsub] is the length z needs (the
+ * column offsets sum_{i<j} m_i follow from geneo_get_eigenvalues' counts).
+ * `z` (optional, host) receives, for each subdomain j, the |N_j| x m_j
+ * block row major at offset zoff[j]; zsize is its length, at least
+ * zoff[nsub], else GENEO_ERR_ARG.  `ah` (optional, host, may be NULL)
+ * receives A_H = Z^T A Z (Def. 2) as nc x nc row major. */
+int geneo_get_coarse(geneo_handle_t h, int64_t* zoff, double* z, int64_t zsize,
                      double* ah);
 
 /* -------------------------------------------------------------- the solve */

@@ -540,7 +540,8 @@ struct SetupScratch {
   DBuf<float> L32, D32, XT32;
   DBuf<double> XT64, XTH;
   DBuf<int2> ljobs32, ljobs64, ljobsH;
-  DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart;
+  DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart,
+      cpiv;
   DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol;
   DBuf<double> bval;
   DBuf<int> brpos;
@@ -1152,6 +1153,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     // ---- coarse Cholesky and inverse factor
     tm[3].start(sb);
     X.cst.alloc(1);
+    X.cpiv.alloc(1);
+    HIPCHK(launch_coarse_pivtol(X.AHt.p, nc, X.cpiv.p, sb));
     h->hnt.upload(std::vector<int>{h->ntc}, sb);
     h->htoff.upload(std::vector<int64_t>{0}, sb);
     X.hdoff.upload(std::vector<int64_t>{0}, sb);
@@ -1159,7 +1162,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("coarse_chol", sb, 8.0 * packed(nc), std::pow((double)nc, 3) / 3.0);
       HIPCHK(launch_chol_steps(X.AHt.p, X.DH.p, h->htoff.p, X.hdoff.p, h->hnt.p, X.hjob.p, 1,
-                               h->ntc, X.cst.p, sb));
+                               h->ntc, X.cst.p, sb, X.cpiv.p));
     }
     X.check_cst = true;  // read at the end of the setup (a failed factor only costs its inverse)
     h->bytes_symvH = 8.0 * packed(nc) + 16.0 * nc;
@@ -1730,16 +1733,16 @@ int geneo_get_local_precision(geneo_handle_t h, int* fp64) {
   return GENEO_OK;
 }
 
-int geneo_get_coarse(geneo_handle_t h, int* zoff, double* z, int64_t zsize, double* ah) {
+int geneo_get_coarse(geneo_handle_t h, int64_t* zoff, double* z, int64_t zsize, double* ah) {
   if (!h || !zoff) return finish(GENEO_ERR_ARG, "NULL argument");
   try {
     hipStream_t st = h->hs;
     int64_t tot = 0;
     for (int j = 0; j < h->nsub; ++j) {
-      zoff[j] = (int)tot;
+      zoff[j] = tot;
       tot += (int64_t)h->nN_host[j] * h->m_host[j];
     }
-    zoff[h->nsub] = (int)tot;
+    zoff[h->nsub] = tot;
     if (z) {
       if (zsize < tot) fail(GENEO_ERR_ARG, "z buffer too small");
       std::vector<double> zin;

@@ -828,13 +828,14 @@ __global__ __launch_bounds__(64) void k_step_potrf(double* __restrict__ A, doubl
                                                    const int64_t* __restrict__ doff,
                                                    const int* __restrict__ ntl,
                                                    const int* __restrict__ jobs, int k,
-                                                   int* __restrict__ status) {
+                                                   int* __restrict__ status,
+                                                   const double* __restrict__ pivtol) {
   __shared__ double sRp[TS];
   const int j = jobs[blockIdx.x];
   if (k >= ntl[j] || (k > 0 && status[j])) return;
   double* D = A + (toff[j] + tile_idx(k, k)) * TSQ;
   const int f = diag_tile<double, TS + 2>(D, D, Di + (doff[j] + k) * TSQ, nullptr, sRp,
-                                          threadIdx.x, 0.0);
+                                          threadIdx.x, pivtol ? *pivtol : 0.0);
   if (threadIdx.x == 0 && (f || k == 0)) status[j] = f ? k * TS + f : 0;
 }
 
@@ -892,11 +893,11 @@ __global__ __launch_bounds__(256) void k_step_update(double* __restrict__ A,
 
 hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
                              const int64_t* doff, const int* nt, const int* jobs, int njobs,
-                             int maxnt, int* status, hipStream_t st) {
+                             int maxnt, int* status, hipStream_t st, const double* pivtol) {
   if (njobs <= 0) return hipSuccess;
   for (int k = 0; k < maxnt; ++k) {
     hipLaunchKernelGGL(k_step_potrf, dim3(njobs), dim3(64), 0, st, tiles, dinv, toff, doff, nt,
-                       jobs, k, status);
+                       jobs, k, status, pivtol);
     const int rem = maxnt - k - 1;
     if (rem > 0) {
       hipLaunchKernelGGL(k_step_trsm, dim3(rem, njobs), dim3(256), 0, st, tiles, dinv, toff,

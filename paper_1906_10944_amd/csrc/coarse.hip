@@ -187,6 +187,29 @@ hipError_t launch_coarse_init(double* AHt, int ntc, int nc, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Pivot threshold of the coarse Cholesky: a pivot at or below
+// nc * eps * max_k (A_H)_kk marks A_H as numerically singular (the rounding
+// of the factorisation alone leaves pivots of up to about (k+1) u (A_H)_kk
+// where the exact one vanishes, as for a repeated basis vector).
+__global__ void k_coarse_pivtol(const double* __restrict__ AHt, int nc, double* __restrict__ tol) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int k = threadIdx.x; k < nc; k += blockDim.x)
+    mx = fmax(mx, AHt[tile_idx(k / TS, k / TS) * TSQ + (k % TS) * (TS + 1)]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *tol = (double)nc * 2.220446049250313e-16 * red[0];
+}
+
+hipError_t launch_coarse_pivtol(const double* AHt, int nc, double* tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_pivtol, dim3(1), dim3(256), 0, st, AHt, nc, tol);
+  return hipGetLastError();
+}
+
 __global__ void k_coarse_to_dense(const double* __restrict__ AHt, int nc, double* __restrict__ out) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)nc * nc) return;

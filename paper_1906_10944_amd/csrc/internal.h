@@ -72,10 +72,12 @@ hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff,
 // diagonal tiles to doff) by right-looking tile-column steps, 3 launches per
 // step over all of them (maxnt = largest tile order): for a few matrices,
 // where one workgroup per matrix would hold CUs for the whole
-// factorisation.  status[j] = 0 or TS k + f at the first failed pivot.
+// factorisation.  status[j] = 0 or TS k + f at the first failed pivot: a
+// pivot d fails unless d > *pivtol (pivtol: device, NULL = 0).
 hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
                              const int64_t* doff, const int* nt, const int* jobs, int njobs,
-                             int maxnt, int* status, hipStream_t st);
+                             int maxnt, int* status, hipStream_t st,
+                             const double* pivtol = nullptr);
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
@@ -213,6 +215,8 @@ hipError_t launch_coarse_blocks(const int2* pairs, int npairs, const int* sub_pt
                                 const double* W, const int* woff, const int* m,
                                 const int* coff, double* AHt, hipStream_t st);
 hipError_t launch_coarse_init(double* AHt, int ntc, int nc, hipStream_t st);
+// *tol = nc * eps * max_k (A_H)_kk: the coarse factor's pivot threshold
+hipError_t launch_coarse_pivtol(const double* AHt, int nc, double* tol, hipStream_t st);
 hipError_t launch_coarse_to_dense(const double* AHt, int ntc, int nc, double* out,
                                   hipStream_t st);
 

@@ -308,7 +308,7 @@ def geneo_get_local_precision(handle, nsub):
 
 
 def geneo_get_coarse(handle, nsub, with_ah=True):
-    zoff = np.zeros(nsub + 1, dtype=np.int32)
+    zoff = np.zeros(nsub + 1, dtype=np.int64)
     _check(lib().geneo_get_coarse(handle.value, zoff.ctypes.data, None, 0, None))
     z = np.zeros(max(int(zoff[-1]), 1), dtype=np.float64)
     info = geneo_get_setup_info(handle)

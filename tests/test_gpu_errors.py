@@ -151,3 +151,48 @@ def test_pcg_start_cases(small):
         part = G.pcg_solve(A, h, sysm.b, xm, rtol=1e-10, maxit=mx, check=False)
         assert part["iters"] == mx and not part["converged"], (mx, part)
     h.close()
+
+
+def test_coarse_matrix_not_spd_repeated_subdomain(small):
+    """Def. 2: A_H = Z^T A Z is SPD only for independent basis vectors.  A
+    subdomain listed twice (valid index lists and local matrices, the copy
+    appended at the end) gives every one of its basis vectors twice, so A_H
+    is singular and the setup returns GENEO_ERR_COARSE_NOT_SPD."""
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    sp_ = sysm.sub_ptr.cpu().numpy().astype(np.int64)
+    rp = sysm.loc_rowptr.cpu().numpy().astype(np.int64)
+    r0, r1 = int(sp_[0]), int(sp_[1])
+    nloc, nnz = int(sp_[-1]), int(rp[-1])
+    e0, e1 = int(rp[r0]), int(rp[r1])
+    dev = sysm.sub_ptr.device
+    i32 = lambda a: torch.as_tensor(np.asarray(a, dtype=np.int32), device=dev)
+    sub_ptr = i32(np.concatenate([sp_, [nloc + (r1 - r0)]]))
+    sub_idx = torch.cat([sysm.sub_idx, sysm.sub_idx[r0:r1]])
+    flags = torch.cat([sysm.sub_flags, sysm.sub_flags[r0:r1]])
+    pou = torch.cat([sysm.pou, sysm.pou[r0:r1]])
+    loc_rowptr = i32(np.concatenate([rp, nnz + (rp[r0 + 1:r1 + 1] - e0)]))
+    loc_col = torch.cat([sysm.loc_col, sysm.loc_col[e0:e1]])
+    an = torch.cat([sysm.an_val, sysm.an_val[e0:e1]])
+    ao = torch.cat([sysm.ao_val, sysm.ao_val[e0:e1]])
+    torch.cuda.synchronize()
+    subs = G.Subdomains(prob.nsub + 1, nloc + (r1 - r0), sub_ptr.data_ptr(), sub_idx.data_ptr(),
+                        flags.data_ptr(), pou.data_ptr())
+    An = G.CsrBatch(loc_rowptr.data_ptr(), loc_col.data_ptr(), an.data_ptr())
+    Ao = G.CsrBatch(loc_rowptr.data_ptr(), loc_col.data_ptr(), ao.data_ptr())
+    # a fixed count m at the widest gap of subdomain 0's spectrum (oracle),
+    # so that both copies select the same invariant subspace
+    from oracle import decomp, geneo as og
+    s0 = decomp.build(prob)[0][0]
+    AN, Ao_ = og.local_matrices(prob, s0)
+    lam = og.generalized_eigen(AN, s0.mu[:, None] * Ao_ * s0.mu[None, :]).lam
+    m = 1 + int(np.argmax([(lam[k + 1] - lam[k]) / lam[k + 1] for k in range(6)]))
+    say("[errors] repeated subdomain, m =", m, "lam", lam[:m + 1])
+    for precision in (0, 1):
+        opts = G.opts_from_problem(prob, precision=precision, tau=0.0, nev=m)
+        with pytest.raises(G.GeneoError) as e:
+            G.geneo_setup(sysm.csr(), subs, An, Ao, opts)
+        say("[errors]", e.value)
+        assert e.value.code == G.GENEO_ERR_COARSE_NOT_SPD
+    # the same lists without the copy are fine
+    _healthy(prob, sysm)
