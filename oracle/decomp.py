@@ -14,11 +14,16 @@ Follows Sec. 3 and Sec. 4.3 of the paper:
 * the partition of unity is the piecewise constant one: with c_k the number
   of subdomains having dof k in ``I_j``, mu_{j,k} = 1/c_k on ``D_j`` and 0
   elsewhere -- zero at Dirichlet dofs and on subdomain boundaries, summing to
-  one over j at every free dof (Sec. 4.3; Def. 3).
+  one over j at every free dof (Sec. 4.3; Def. 3); or, for problems with
+  ``pou == "sarkis"``, the smooth one of Fig. 1 (right): weights
+  proportional to the distance from each subdomain's artificial boundary.
 
 Pins (tests/test_oracle_decomp.py): closed-form set sizes, maximal cover
 count k0 = 2^d, the partition of unity summing to 1 at every free dof and
-vanishing where required, and the overlap zone matching its set definition.
+vanishing where required, and the overlap zone matching its set definition;
+for the Sarkis weights the linear ramp across a strip of overlap in closed
+form, equality with the piecewise-constant weights at overlap 1, and the
+same sum and support pins.
 """
 from dataclasses import dataclass
 
@@ -123,6 +128,9 @@ def build(prob):
                               interior=interior,
                               dirichlet=dmask_glob[dofs], mu=None,
                               overlap_elems=elems[mult[elems] >= 2]))
+    if getattr(prob, "pou", "constant") == "sarkis":
+        _sarkis_weights(prob, subs, boxes)
+        return subs, mult
     for s in subs:
         d = s.dmask
         mu = np.zeros(len(s.dofs))
@@ -131,9 +139,64 @@ def build(prob):
     return subs, mult
 
 
+def artificial_distance(prob, box, nodes):
+    """Distance of the given nodes of box Omega_j from the artificial part of
+    its boundary (the faces of the box that lie inside Omega), in physical
+    units; +inf for a box without such faces.  For a point of a box the
+    nearest point of a face lies on the face's plane, so this is the
+    smallest distance to the planes of the artificial faces."""
+    nn = [n + 1 for n in prob.ne]
+    k = np.asarray(nodes).copy()
+    d = np.full(len(k), np.inf)
+    for ax in range(prob.dim):
+        x = k % nn[ax]
+        k //= nn[ax]
+        lo, hi = box[ax]
+        if lo > 0:
+            d = np.minimum(d, (x - lo) * prob.h[ax])
+        if hi < prob.ne[ax]:
+            d = np.minimum(d, (hi - x) * prob.h[ax])
+    return d
+
+
+def _sarkis_weights(prob, subs, boxes):
+    """Smooth partition of unity of Sarkis type (Fig. 1 right): the weight of
+    subdomain j at node x is d_j(x) / sum_i d_i(x), with d_i the distance
+    of x from the artificial boundary of Omega_i (zero on it, and zero for
+    the subdomains not containing x); zero at Dirichlet dofs.  A box without
+    artificial faces (one subdomain) has weight 1."""
+    c = prob.ncomp
+    dist = []
+    total = np.zeros(prob.nnodes)
+    for s, b in zip(subs, boxes):
+        nodes = s.dofs[::c] // c
+        d = artificial_distance(prob, b, nodes)
+        d = np.where(np.isinf(d), 1.0, d)
+        dist.append(d)
+        np.add.at(total, nodes, d)
+    for s, d in zip(subs, dist):
+        nodes = s.dofs[::c] // c
+        mu = np.repeat(d / np.where(total[nodes] > 0, total[nodes], 1.0), c)
+        s.mu = np.where(s.dmask, mu, 0.0)
+
+
 def pou_sum(prob, subs):
     """sum_j R_j^T mu_j as a global vector."""
     out = np.zeros(prob.ndof)
     for s in subs:
         np.add.at(out, s.dofs, s.mu)
+    return out
+
+
+def thm1_threshold(prob, subs):
+    """delta_j / H_j of Thm. 1 for every subdomain: H_j = diam(Omega_j), the
+    diagonal of its element box; delta_j the width of its overlap zone, the
+    strips of 2 * ovl element layers along each artificial face (ovl from
+    the subdomain's own extension, ovl from the neighbour's), in the
+    smallest edge length."""
+    delta = 2 * prob.ovl * min(prob.h)
+    out = np.zeros(len(subs))
+    for s in subs:
+        ext = [(hi - lo) * prob.h[ax] for ax, (lo, hi) in enumerate(s.ebox)]
+        out[s.j] = delta / np.sqrt(np.sum(np.square(ext)))
     return out

@@ -4,7 +4,10 @@ Discretises the Darcy form (Sec. 2, eq. (2)) and the linear-elasticity form
 (Sec. 2, eq. (3), no traction term) with a conforming space of continuous
 (tri)linear Q1 functions, as the paper's Sec. 5.2 experiments use Q1
 elements.  Element integrals use the tensor 2-point Gauss rule, which is
-exact for products of Q1 gradients with a constant coefficient.
+exact for products of Q1 gradients with a constant coefficient; the Darcy
+element matrix is taken in its closed form (1D stiffness and mass factors),
+which is that integral up to rounding.  Every global and local matrix entry
+sums its element contributions in ascending element order, from zero.
 
 Homogeneous Dirichlet conditions (``u = 0`` on the flagged faces) are
 imposed by symmetric elimination: the row and column of a constrained degree
@@ -60,8 +63,42 @@ def quadrature(dim):
     return np.array(pts), np.array(wts)
 
 
+def darcy_element_matrix_exact(h):
+    """The same element matrix in closed form.  With the 1D stiffness
+    k(i, j) = +-1 and the 1D mass m(i, j) = (1/3, 1/6) = mi / 6 (mi = 2, 1),
+
+        K_ab = 6^{1-d} sum_x (prod_{y != x} h_y / h_x) k(a_x, b_x) prod_{y != x} mi(a_y, b_y),
+
+    evaluated in this order: the ratio of the edge lengths, times the
+    integer factor (a power of two, exact), summed over the axes in order,
+    divided by 6^{d-1} once.  Every step but the ratios and the final
+    division is exact, so the rows sum to zero up to those two roundings."""
+    h = np.asarray(h, dtype=np.float64)
+    dim = len(h)
+    off = _local_offsets(dim)
+    nv = 2 ** dim
+    K = np.zeros((nv, nv))
+    for a in range(nv):
+        for b in range(nv):
+            s = 0.0
+            for ax in range(dim):
+                c = 1.0
+                for o in range(dim):
+                    if o != ax:
+                        c = c * h[o]
+                c = c / h[ax]
+                f = 1 if off[a, ax] == off[b, ax] else -1
+                for o in range(dim):
+                    if o != ax:
+                        f *= 2 if off[a, o] == off[b, o] else 1
+                s = s + c * float(f)
+            K[a, b] = s / (6.0 ** (dim - 1))
+    return K
+
+
 def darcy_element_matrix(h):
-    """Element matrix of int grad v . grad w over one box element, kappa = 1."""
+    """Element matrix of int grad v . grad w over one box element, kappa = 1,
+    by the tensor 2-point Gauss rule."""
     h = np.asarray(h, dtype=np.float64)
     dim = len(h)
     pts, wts = quadrature(dim)
@@ -147,7 +184,7 @@ def element_matrices(prob, elems=None):
         elems = np.arange(prob.nelem)
     elems = np.asarray(elems)
     if prob.ncomp == 1:
-        Kref = darcy_element_matrix(prob.h)
+        Kref = darcy_element_matrix_exact(prob.h)
         return prob.coeff[elems][:, None, None] * Kref[None]
     coeff = prob.coeff[elems]
     uniq, inv = np.unique(coeff, axis=0, return_inverse=True)
@@ -211,15 +248,30 @@ def eliminate(A, b, dmask):
     return A2, b2
 
 
+def _sum_in_element_order(prob, rows, cols, vals):
+    """CSR matrix whose entry (i, j) is the sum of the contributions to it,
+    added in the order they come (ascending element), starting from 0."""
+    pat = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(prob.ndof, prob.ndof))
+    pat.sum_duplicates()
+    pat.sort_indices()
+    n = np.int64(prob.ndof)
+    allkey = np.repeat(np.arange(prob.ndof, dtype=np.int64), np.diff(pat.indptr)) * n \
+        + pat.indices.astype(np.int64)
+    pos = np.searchsorted(allkey, rows.astype(np.int64) * n + cols.astype(np.int64))
+    data = np.zeros(pat.nnz)
+    np.add.at(data, pos, vals)      # in the order of vals, from 0
+    return sp.csr_matrix((data, pat.indices, pat.indptr), shape=pat.shape)
+
+
 def assemble(prob, f=None):
-    """Global CSR stiffness matrix and load vector with Dirichlet elimination."""
+    """Global CSR stiffness matrix and load vector with Dirichlet elimination.
+    Each entry sums its element contributions in ascending element order."""
     dofs = element_dofs(prob)
     Ke = element_matrices(prob)
     nd = dofs.shape[1]
     rows = np.repeat(dofs, nd, axis=1).ravel()
     cols = np.tile(dofs, (1, nd)).ravel()
-    A = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(prob.ndof, prob.ndof)).tocsr()
-    A.sum_duplicates()
+    A = _sum_in_element_order(prob, rows, cols, Ke.ravel())
     fe = element_load(prob, f)
     b = np.bincount(dofs.ravel(), weights=fe.ravel(), minlength=prob.ndof)
     return eliminate(A, b, dirichlet_mask(prob))
@@ -232,6 +284,4 @@ def assemble_neumann(prob, f=None):
     nd = dofs.shape[1]
     rows = np.repeat(dofs, nd, axis=1).ravel()
     cols = np.tile(dofs, (1, nd)).ravel()
-    A = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(prob.ndof, prob.ndof)).tocsr()
-    A.sum_duplicates()
-    return A
+    return _sum_in_element_order(prob, rows, cols, Ke.ravel())

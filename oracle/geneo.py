@@ -15,6 +15,9 @@ Steps, in the paper's order and notation:
    the same eigenvectors and nu = 1/(lambda - sigma).  The dense symmetric
    form G^{-1} B_j G^{-T} y = nu y with C = G G^T, p = G^{-T} y, is solved
    with a library symmetric eigensolver;
+   Above LANCZOS_MIN_N local dofs only the wanted end of the spectrum is
+   computed, by implicitly restarted Lanczos (ARPACK, as in Sec. 4.4) on the
+   same symmetric operator;
 3. selection of the m_j smallest eigenvalues (Def. 4): a fixed count, or the
    count below a threshold capped at a maximum (Thm. 1, the threshold rule);
 4. coarse basis vectors X_j p, normalised in the l2 norm (Sec. 4.4);
@@ -114,6 +117,40 @@ def generalized_eigen(AN, B, sigma=SIGMA):
     return EigenResult(lam=lam[order], P=P[:, order])
 
 
+LANCZOS_MIN_N = 1500
+
+
+def generalized_eigen_lanczos(AN, B, k, sigma=SIGMA):
+    """The k smallest eigenpairs of AN p = lam B p through the same
+    shift-and-invert transform (Sec. 4.4), by implicitly restarted Lanczos
+    (ARPACK, the solver the paper uses) on S = G^{-1} B G^{-T} for its k
+    largest eigenvalues nu = 1 / (lam - sigma), to machine precision.  Used
+    for large subdomains, where the full spectrum costs too much; returns
+    the same quantities as :func:`generalized_eigen` for the k pairs."""
+    import scipy.sparse.linalg as spla
+    n = AN.shape[0]
+    C = AN - sigma * B
+    G = np.linalg.cholesky(C)
+    Bs = sp.csr_matrix(B)
+
+    def S(v):
+        w = sla.solve_triangular(G, v, lower=True, trans="T")      # G^{-T} v
+        return sla.solve_triangular(G, Bs @ w, lower=True)         # G^{-1} B G^{-T} v
+
+    op = spla.LinearOperator((n, n), matvec=S, dtype=np.float64)
+    v0 = np.ones(n) / np.sqrt(n)
+    nu, Y = spla.eigsh(op, k=k, which="LA", tol=0.0, v0=v0, ncv=min(n, max(2 * k + 1, 48)))
+    order = np.argsort(-nu, kind="stable")                        # descending nu
+    nu, Y = nu[order], Y[:, order]
+    numax = max(nu[0], 0.0)
+    finite = nu > NU_ZERO_REL * numax if numax > 0 else np.zeros(len(nu), bool)
+    lam = np.full(len(nu), np.inf)
+    lam[finite] = sigma + 1.0 / nu[finite]
+    P = sla.solve_triangular(G, Y, lower=True, trans="T")         # p = G^{-T} y
+    order = np.argsort(lam, kind="stable")
+    return EigenResult(lam=lam[order], P=P[:, order])
+
+
 def select_count(lam, nev=None, tau=None, nev_max=None):
     """m_j: a fixed count, or #{lam < tau} capped at nev_max (finite lam only)."""
     nfin = int(np.sum(np.isfinite(lam)))
@@ -180,10 +217,36 @@ class GenEO:
         return z
 
 
+def local_setup(prob, A, s, nev, tau, nev_max, coarse, keep_eigvecs, eig_method):
+    """Everything one subdomain contributes: the Cholesky factor of its
+    Dirichlet matrix A_j (Sec. 3), its eigenvalues (Sec. 4.3-4.4), the count
+    m_j (Def. 4 / Thm. 1) and its coarse basis block (Sec. 4.4)."""
+    AD = dirichlet_matrix(A, s)
+    L = np.linalg.cholesky(AD) if len(AD) else np.zeros((0, 0))
+    if not coarse:
+        return L, np.zeros(0), 0, None, None
+    AN, Ao = local_matrices(prob, s)
+    B = s.mu[:, None] * Ao * s.mu[None, :]
+    lanczos = eig_method == "lanczos" or (eig_method == "auto" and
+                                           len(s.dofs) > LANCZOS_MIN_N)
+    want = nev if tau is None else nev_max
+    if lanczos and want + 8 < len(s.dofs) - 1:
+        ev = generalized_eigen_lanczos(AN, B, want + 8)
+    else:
+        ev = generalized_eigen(AN, B)
+    mj = select_count(ev.lam, nev=nev, tau=tau, nev_max=nev_max)
+    Zj = basis_vectors(s.mu, ev.P[:, :mj]) if mj else None
+    return L, ev.lam, mj, (ev.P if keep_eigvecs else None), Zj
+
+
 def setup(prob, A=None, nev=None, tau=None, nev_max=None, coarse=True,
-          subs=None, keep_eigvecs=False):
+          subs=None, keep_eigvecs=False, eig_method="auto", locs=None):
     """Build the two-level preconditioner of ``prob`` (options default to the
-    problem's own)."""
+    problem's own).  ``eig_method``: "full" spectrum, "lanczos" for the
+    wanted pairs only, or "auto" (Lanczos above LANCZOS_MIN_N local dofs).
+    ``locs``: the :func:`local_setup` results of every subdomain, if they
+    were computed elsewhere (e.g. in parallel processes); else computed
+    here, one subdomain after the other."""
     if A is None:
         A, _ = fem.assemble(prob)
     if subs is None:
@@ -191,25 +254,21 @@ def setup(prob, A=None, nev=None, tau=None, nev_max=None, coarse=True,
     if nev is None and tau is None:
         nev, tau, nev_max = prob.nev, prob.tau, prob.nev_max
     g = GenEO(prob=prob, A=A, subs=subs)
-    cols = []
     g.eigvecs = [] if keep_eigvecs else None
-    for s in subs:
-        AD = dirichlet_matrix(A, s)
-        g.chol.append(np.linalg.cholesky(AD) if len(AD) else np.zeros((0, 0)))
-        if not coarse:
-            g.lam.append(np.zeros(0))
-            g.m.append(0)
-            continue
-        AN, Ao = local_matrices(prob, s)
-        B = s.mu[:, None] * Ao * s.mu[None, :]
-        ev = generalized_eigen(AN, B)
-        mj = select_count(ev.lam, nev=nev, tau=tau, nev_max=nev_max)
-        g.lam.append(ev.lam)
+    if locs is None:
+        # tau: one threshold, or one per subdomain (e.g. delta_j / H_j, Thm. 1)
+        taus = [None if tau is None else (float(tau) if np.isscalar(tau) else float(tau[s.j]))
+                for s in subs]
+        locs = [local_setup(prob, A, s, nev, t, nev_max, coarse, keep_eigvecs, eig_method)
+                for s, t in zip(subs, taus)]
+    cols = []
+    for s, (L, lam, mj, P, Zj) in zip(subs, locs):
+        g.chol.append(L)
+        g.lam.append(lam)
         g.m.append(mj)
         if keep_eigvecs:
-            g.eigvecs.append(ev.P)
+            g.eigvecs.append(P)
         if mj:
-            Zj = basis_vectors(s.mu, ev.P[:, :mj])
             cols.append((s, Zj))
     if coarse and cols:
         rows, cidx, vals = [], [], []

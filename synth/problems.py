@@ -47,6 +47,7 @@ class Problem:
     tau: Optional[float] = None       # threshold: take lambda < tau ...
     nev_max: Optional[int] = None     # ... capped at nev_max
     precision: str = "fp64"           # "fp64" or "mixed"
+    pou: str = "constant"             # partition of unity: "constant" or "sarkis"
     rtol: float = 1e-10
     maxit: int = 2000
     meta: dict = field(default_factory=dict)
@@ -80,6 +81,7 @@ class Problem:
         else:
             assert self.dim == 3 and self.coeff.shape == (self.nelem, 21)
         assert len(self.load) == self.ncomp
+        assert self.pou in ("constant", "sarkis")
         for n, p in zip(self.ne, self.parts):
             assert 1 <= p <= n
 

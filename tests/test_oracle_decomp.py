@@ -120,3 +120,68 @@ def test_box_ids_enumeration():
     brute = sorted(x + 10 * y + 100 * z for x, y, z in
                    itertools.product(range(1, 3), range(2, 4), range(3, 5)))
     assert ids.tolist() == brute
+
+
+# ------------------------------------------------- Sarkis partition of unity
+def _sarkis(prob):
+    prob.pou = "sarkis"
+    subs, _ = decomp.build(prob)
+    return subs
+
+
+def test_sarkis_linear_ramp_across_overlap_strip():
+    """Two subdomains side by side in x with overlap 2: the parts are
+    [0, 8) and [8, 16), widened to [0, 10) and [6, 16).  Across the strip of
+    nodes x = 6 .. 10 the left weight is (10 - x) / 4 in closed form (the
+    distance to x = 10 over the sum of the distances to x = 10 and x = 6);
+    1 to the left of it, 0 to the right; the same on every row."""
+    p = synth.darcy_problem("t", np.ones((5, 16)), (2, 1), 2, dirichlet=0)
+    subs = _sarkis(p)
+    s = subs[0]
+    x = (s.dofs % 17).astype(float)
+    expect = np.clip((10.0 - x) / 4.0, 0.0, 1.0)
+    assert np.allclose(s.mu, expect, rtol=0, atol=1e-15)
+    tot = decomp.pou_sum(p, subs)
+    assert np.allclose(tot, 1.0, rtol=0, atol=1e-15)
+
+
+def test_sarkis_equals_piecewise_constant_at_overlap_one():
+    """With one element layer of overlap every node of the strip is at
+    distance 0 or h from each artificial boundary, so the distance weights
+    are the counting weights 1/c_k."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    for shape, parts in (((12, 15), (3, 4)), ((6, 7, 8), (2, 2, 3))):
+        k = np.exp(rng.normal(size=shape))
+        p = synth.darcy_problem("t", k, parts, 1)
+        const, _ = decomp.build(p)
+        sark = _sarkis(synth.darcy_problem("t", k, parts, 1))
+        for a, b in zip(const, sark):
+            assert np.allclose(a.mu, b.mu, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("shape,parts,ovl,dirichlet", [((24, 24), (3, 3), 3, 0b1111),
+                                                        ((10, 9, 8), (2, 3, 2), 2, 0b000011),
+                                                        ((20, 12), (4, 2), 2, 0b0101)])
+def test_sarkis_sums_to_one_and_vanishes_where_required(shape, parts, ovl, dirichlet):
+    p = synth.darcy_problem("t", np.ones(shape), parts, ovl, dirichlet=dirichlet)
+    subs = _sarkis(p)
+    d = fem.dirichlet_mask(p)
+    tot = decomp.pou_sum(p, subs)
+    assert np.max(np.abs(tot[~d] - 1.0)) <= 1e-15
+    assert np.all(tot[d] == 0.0)
+    for s in subs:
+        assert np.all(s.mu[~s.dmask] == 0.0)      # artificial boundary and Dirichlet
+        assert np.all((s.mu >= 0.0) & (s.mu <= 1.0))
+        assert np.all(s.mu[s.dmask & ~s.dirichlet] > 0.0)
+
+
+def test_sarkis_elasticity_components_share_weights():
+    C = synth.isotropic_stiffness(4.0, 0.35)
+    p = synth.elasticity_problem("t", np.broadcast_to(C, (4, 4, 8, 6, 6)), (8, 4, 4), (2, 1, 1),
+                                 2, dirichlet=1, load=(0.0, 0.0, -1.0), h=(1.0, 1.0, 1.0))
+    subs = _sarkis(p)
+    for s in subs:
+        m = s.mu.reshape(-1, 3)
+        assert np.all(m[:, 0] == m[:, 1]) and np.all(m[:, 0] == m[:, 2])
+    tot = decomp.pou_sum(p, subs)
+    assert np.max(np.abs(tot[~fem.dirichlet_mask(p)] - 1.0)) <= 1e-15

@@ -262,3 +262,38 @@ def test_elasticity_uniaxial_bar_closed_form(which):
     assert np.max(np.abs(u - exact)) <= 1e-11 * np.max(np.abs(exact))
     # the supports carry no reaction: the end tractions are self-equilibrated
     assert np.max(np.abs((K @ exact - f))) <= 1e-11 * sigma0
+
+
+@pytest.mark.parametrize("h", [(0.25, 0.25), (0.1, 0.37), (1.0 / 96, 1.0 / 96, 1.0 / 96),
+                               (0.5, 1.0, 2.0)])
+def test_closed_form_darcy_element_matrix_matches_quadrature(h):
+    """The closed-form element matrix the assembly uses and the 2-point
+    Gauss rule (exact for it) agree to rounding, and both have (near) zero
+    row sums."""
+    Kq = fem.darcy_element_matrix(h)
+    Kc = fem.darcy_element_matrix_exact(h)
+    scale = np.abs(Kq).max()
+    assert np.max(np.abs(Kq - Kc)) <= 4e-16 * scale
+    assert np.max(np.abs(Kc.sum(axis=1))) <= 4e-16 * scale
+    assert np.array_equal(Kc, Kc.T)
+
+
+def test_assembly_sums_contributions_in_element_order():
+    """Each entry is the sum of its element contributions added in ascending
+    element order from 0 (the order the device uses), for a field with
+    contributions of very different sizes."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    k = 10.0 ** rng.uniform(-6, 6, size=(5, 6))
+    p = synth.darcy_problem("t", k, (1, 1), 1, dirichlet=0)
+    A = fem.assemble_neumann(p).tolil()
+    Ao, _ = fem.assemble(p)
+    Kc = fem.darcy_element_matrix_exact(p.h)
+    dofs = fem.element_dofs(p)
+    ref = {}
+    for e in range(p.nelem):
+        for a in range(4):
+            for b in range(4):
+                key = (dofs[e, a], dofs[e, b])
+                ref[key] = ref.get(key, 0.0) + k.ravel()[e] * Kc[a, b]
+    for (i, j), v in ref.items():
+        assert Ao[i, j] == v          # bitwise

@@ -111,13 +111,87 @@ def test_geneo_flat_in_subdomain_count_one_level_grows():
     assert kap1[-1] > 5 * kap1[0] and its1[-1] > its1[0] + 20, (kap1, its1)
 
 
+def test_thm1_threshold_closed_form():
+    """delta_j / H_j for a 40 x 40 grid (h = 1/40) in 4 x 4 parts with
+    overlap 2: interior boxes span 10 + 2 + 2 = 14 elements per side, corner
+    boxes 12, edge boxes 14 x 12; delta = 2 * 2 / 40.  So tau = 4 / (14
+    sqrt 2) inside, 4 / (12 sqrt 2) at the corners, 4 / sqrt(14^2 + 12^2)
+    along the edges."""
+    from oracle import decomp
+    p = synth.layered_2d(n=40, parts=4, ovl=2, layers=8, contrast=1.0, nev=4)
+    subs, _ = decomp.build(p)
+    t = decomp.thm1_threshold(p, subs).reshape(4, 4)
+    assert t[1, 1] == pytest.approx(0.2020305089104421, rel=1e-14)
+    assert t[0, 0] == pytest.approx(0.2357022603955158, rel=1e-14)
+    assert t[0, 1] == pytest.approx(0.21693045781865616, rel=1e-14)
+    assert np.allclose(t, t.T) and np.allclose(t, t[::-1, ::-1])
+
+
 def test_threshold_selection_and_kappa_bound():
-    """Thm. 1: with m_j = #{lam < delta/H} the estimate stays under the bound."""
-    n, parts, ovl = 48, 4, 2
-    p = synth.layered_2d(n=n, parts=parts, ovl=ovl, layers=8, contrast=1e6, nev=16)
-    H_over_delta = (n / parts + 2 * ovl) / ovl
-    it, kap, g = _iters(p, tau=1.0 / H_over_delta, nev_max=64)
+    """Thm. 1: with m_j = #{lam < delta_j / H_j} the condition estimate stays
+    under (1 + k0)[2 + k0 (2 k0 + 1) max_j (1 + H_j / delta_j)], k0 = 4."""
+    from oracle import decomp
+    p = synth.layered_2d(n=48, parts=4, ovl=2, layers=8, contrast=1e6, nev=16)
+    subs, _ = decomp.build(p)
+    tau = decomp.thm1_threshold(p, subs)
+    it, kap, g = _iters(p, tau=tau, nev_max=64)
     k0 = 4
-    bound = (1 + k0) * (2 + k0 * (2 * k0 + 1) * (1 + H_over_delta))
+    bound = (1 + k0) * (2 + k0 * (2 * k0 + 1) * np.max(1 + 1 / tau))
     assert kap <= bound
-    assert all(np.sum(l < 1.0 / H_over_delta) == m for l, m in zip(g.lam, g.m))
+    assert all(np.sum(l < t) == m for l, m, t in zip(g.lam, g.m, tau))
+    assert max(g.m) < 64
+
+
+def test_extended_residual_against_exact_rationals():
+    """residual_extended carries about 64 bits: on a small system with
+    ill-scaled entries it matches the exact rational residual, rounded to
+    FP64, where the FP64 residual is visibly off."""
+    from fractions import Fraction
+    import scipy.sparse as sp
+    rng = np.random.Generator(np.random.PCG64(13))
+    n = 30
+    M = sp.random(n, n, density=0.3, random_state=1, format="csr")
+    M.data = rng.normal(size=M.nnz) * 10.0 ** rng.integers(-6, 7, size=M.nnz)
+    x = rng.normal(size=n)
+    b = M @ x + rng.normal(size=n) * 1e-12
+    r = pcg.residual_extended(M, b, x)
+    exact = []
+    for i in range(n):
+        s = Fraction(b[i])
+        for k in range(M.indptr[i], M.indptr[i + 1]):
+            s -= Fraction(M.data[k]) * Fraction(x[M.indices[k]])
+        exact.append(float(s))
+    exact = np.array(exact)
+    # per row the terms reach |a_ij x_j| <= scale; FP64 sums err by about
+    # u scale, the extended ones by about 2^-64 scale (plus the final
+    # rounding of a residual of size 1e-12)
+    scale = np.abs(M).max() * np.abs(x).max()
+    err_ext = np.max(np.abs(r - exact))
+    err_64 = np.max(np.abs((b - M @ x) - exact))
+    assert err_ext <= 2.0 ** -60 * scale + 1e-27
+    assert err_64 >= 100 * err_ext
+
+
+def test_refined_geneo_pcg_matches_refined_sparse_lu():
+    """Two independent routes to A^{-1} b on a badly conditioned layered
+    problem (contrast 1e6, Neumann sides): GenEO-PCG to 1e-10 and sparse LU
+    differ at the FP64 floor u kappa(A); after refinement with extended
+    residuals they agree to 1e-13."""
+    p = synth.layered_2d(n=40, parts=4, ovl=2, layers=8, contrast=1e6, nev=4)
+    A, b = fem.assemble(p)
+    g = geneo.setup(p, A=A)
+    res = pcg.pcg(A, b, g.apply, rtol=1e-10)
+    lu = spla.splu(A.tocsc())
+    x_lu = lu.solve(b)
+    x1 = pcg.refine(A, b, res.x, lambda r: pcg.pcg(A, r, g.apply, rtol=1e-6).x, steps=3)
+    x2 = pcg.refine(A, b, x_lu, lu.solve, steps=3)
+    nx = np.linalg.norm(x2)
+    ev = np.linalg.eigvalsh(A.toarray())
+    u = np.finfo(float).eps / 2
+    print("kappa %.2e plain PCG vs LU %.2e refined %.2e" % (
+        ev[-1] / ev[0], np.linalg.norm(res.x - x_lu) / nx, np.linalg.norm(x1 - x2) / nx))
+    # attainable accuracy of refinement: about u + u_ext kappa(A)
+    kappa = ev[-1] / ev[0]
+    assert np.linalg.norm(x1 - x2) <= 10 * (u + 2.0 ** -64 * kappa) * nx
+    assert np.linalg.norm(x1 - x2) <= 1e-2 * np.linalg.norm(res.x - x_lu)
+    assert np.linalg.norm(res.x - x2) <= 10 * u * kappa * nx
