@@ -4,13 +4,18 @@ A step is one pass of the whole path over one synthetic problem already
 resident in HBM (the per-element coefficient field): device Q1 assembly of
 the global and local matrices, the GenEO setup (local factors, shifted
 factors, eigen sweeps, coarse basis, Galerkin product, coarse factor) and
-the graph-captured PCG solve.  The default workload is the 2D Darcy problem
-on a 512^2 Q1 grid (263,169 dofs), 16x16 subdomains of 32^2 elements with
-two-element overlap, k = exp(GRF) with 24 discs of contrast 1e6, threshold
-lambda < 0.1 capped at 16 vectors, FP32 local factors.
+the graph-captured PCG solve, then the release of the operator.
 
-Prints one JSON line (see the keys below).  `--gpus N` with N > 1 exits:
-this build runs on one GPU.
+The headline workload is the largest single-GPU one: 3D Darcy on a 96^3 Q1
+grid (912,673 dofs), 8^3 subdomains of 12^3 elements with one-element
+overlap, z-layers of random thickness 2-6 alternating k = 1 and
+k = 10^U(4,6), 12 eigenvectors per subdomain, FP32 local factors with FP64
+eigen, coarse and PCG.  The same JSON line also carries, as nested objects,
+the FP64 form of the same workload, the 512^2 Darcy workload and the
+serving stream's p50/p99 latency.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
+GPU.
 """
 import argparse
 import json
@@ -24,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 
 
 def parse():
@@ -31,17 +37,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3",
+    ap.add_argument("--config", default="config3", choices=["config1", "config2", "config3",
                                                             "config4"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--no-nested", action="store_true",
+                    help="skip the nested 512^2 workload and serving objects")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--serve", action="store_true",
-                    help="serving mode instead of the step benchmark: a seeded Poisson stream "
-                         "of new problems and repeat solves through serve.Server; prints one "
-                         "JSON line with p50/p99 latency")
-    ap.add_argument("--serve-requests", type=int, default=40)
+                    help="only the serving benchmark: a seeded Poisson stream of new problems "
+                         "and repeat solves through serve.Server; prints one JSON line with "
+                         "p50/p99 latency")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -78,6 +86,8 @@ class Runner:
         self.prob = prob
         self.grid = G.grid_from_problem(prob)
         self.coeff = torch.as_tensor(prob.coeff, dtype=torch.float64).cuda().contiguous()
+        self.xbuf = None
+        self.last = None
         torch.cuda.synchronize()
 
     def step(self, precision):
@@ -88,7 +98,7 @@ class Runner:
         h = G.geneo_setup(sysm.csr(), sysm.subdomains(), sysm.neumann(), sysm.overlap(), opts)
         # the solution vector is the caller's: one buffer for all steps,
         # zeroed (x0 = 0) at the start of each
-        if getattr(self, "xbuf", None) is None or self.xbuf.shape != sysm.b.shape:
+        if self.xbuf is None or self.xbuf.shape != sysm.b.shape:
             self.xbuf = torch.empty_like(sysm.b)
         x = self.xbuf
         x.zero_()
@@ -112,8 +122,14 @@ class Runner:
         torch.cuda.synchronize()
         return float(torch.linalg.norm(sysm.b - y) / torch.linalg.norm(sysm.b))
 
+    def solution(self):
+        import torch
+        torch.cuda.synchronize()
+        return self.last[2].cpu().numpy()
+
     def release(self):
-        self.last[1].close()
+        if self.last is not None:
+            self.last[1].close()
         self.last = None
 
 
@@ -134,6 +150,25 @@ def timed(runner, precision, steps, warmup):
     return (t1 - t0) * 1e3 / steps, infos
 
 
+def err_vs_oracle(prob, seed, x, iters):
+    """Error of a device solution against the FP64 oracle's whole run of the
+    same workload (stored by tests/golden/make_fullsize_golden.py, which
+    calls only the oracle), or None where no stored run exists."""
+    import numpy as np
+    name = prob.name.split("_")[0]
+    path = os.path.join(GOLDEN_DIR, "fullsize_%s_seed%d.npz" % (name, seed))
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    xo = g["x"]
+    if xo.shape != x.shape:
+        return None
+    return {"rel_l2": float(np.linalg.norm(x - xo) / np.linalg.norm(xo)),
+            "rel_max_abs": float(np.abs(x - xo).max() / np.abs(xo).max()),
+            "iters": iters, "oracle_iters": int(g["iters"]),
+            "oracle_kappa": float(g["kappa"]), "oracle_nc": int(g["nc"])}
+
+
 def prof_query(G, name):
     import ctypes as C
     L = G.lib()
@@ -149,12 +184,13 @@ def prof_query(G, name):
 PROF_KERNELS = ["densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
                 "trtri_dirichlet", "densify_shifted", "chol_shifted_f64", "trsm_bwd",
                 "trsm_fwd", "bapply", "rayleigh_ritz", "orth", "coarse_chol",
-                "lauum_dirichlet", "symv", "symv_cols", "chebyshev"]
+                "lauum_dirichlet", "symv", "symv_cols", "cheb_combine"]
 
 
 def kernel_profile(runner, precision):
-    """One extra step with the library's event timing on, plus eager applies
-    (the PCG iterations themselves run inside a captured graph)."""
+    """One extra step with the library's event timing on (each timed launch
+    has an event pair on the stream it runs on), plus eager applies (the PCG
+    iterations themselves run inside a captured graph)."""
     import torch
     G = runner.G
     L = G.lib()
@@ -177,9 +213,11 @@ PROF_SYMBOL = {"densify_dirichlet": "k_densify_dirichlet", "chol_dirichlet_f32":
                "chol_dirichlet_f64": "k_potrf_local_f64", "trtri_dirichlet": "k_trtri_win<float, 2>",
                "densify_shifted": "k_densify_shifted", "chol_shifted_f64": "k_potrf_shifted_f64",
                "bapply": "k_bapply", "rayleigh_ritz": "rayleigh-ritz kernels",
-               "orth": "orthonormalisation kernels",
+               "orth": "orthonormalisation kernels", "cheb_combine": "k_cheb",
                "coarse_chol": "tile-column step kernels", "lauum_dirichlet": "k_lauum<float>",
                "symv": "k_symv_rows", "symv_cols": "k_symv_cols"}
+COMPUTE_BOUND = ("chol_dirichlet_f32", "chol_dirichlet_f64", "chol_shifted_f64", "trtri_dirichlet",
+                 "lauum_dirichlet", "coarse_chol")
 
 
 def prof_symbol(name, info):
@@ -194,17 +232,20 @@ def prof_symbol(name, info):
     if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
         return "tile-column step kernels"
     return PROF_SYMBOL.get(name, name)
+
+
 APPLY_KERNELS = ("symv", "symv_cols")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_darcy512_mixed.json")
 
 
-def measured_traffic(symbol):
-    """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a plain copy), or None when the kernel sources have
-    changed since the counters were taken."""
+def measured_traffic(symbol, workload):
+    """HBM bytes per launch from the committed counter summary of this
+    workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    there is none or the kernel sources have changed since the counters
+    were taken."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.json" % workload)
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
@@ -221,7 +262,7 @@ def measured_traffic(symbol):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def roofline(prof, iters, info):
+def roofline(prof, iters, info, workload):
     """The kernel with the largest time per step, against its bound.
 
     Per-step time: average launch time x launches per step.  The apply
@@ -235,16 +276,14 @@ def roofline(prof, iters, info):
         avg = p["ms"] / p["launches"]
         n = iters + 1 if k in APPLY_KERNELS else p["launches"]
         per_step[k] = avg * n
-    # a scope that states no work of its own (the Chebyshev filter, which
-    # times a group of solve and combination launches) is not a candidate
     cand = {k: v for k, v in per_step.items() if prof[k]["bytes"] > 0 or prof[k]["flops"] > 0}
     name = max(cand, key=cand.get)
     p = prof[name]
     avg_ms = p["ms"] / p["launches"]
-    compute_bound = (name.startswith("chol") or name.startswith("trtri") or name == "coarse_chol"
-                     or name.startswith("lauum"))
-    if compute_bound:
+    if name in COMPUTE_BOUND:
         peak = FP32_MFMA_PEAK_TFLOPS if name.endswith("f32") else FP64_PEAK_TFLOPS
+        if name in ("trtri_dirichlet", "lauum_dirichlet") and info.get("fallback_fp64", 0) < info.get("nsub", 1):
+            peak = FP32_MFMA_PEAK_TFLOPS
         achieved = p["flops"] / p["launches"] / (avg_ms * 1e-3) / 1e12
         rf = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     else:
@@ -252,8 +291,9 @@ def roofline(prof, iters, info):
         rf = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     rf["frac"] = rf["achieved"] / rf["peak"]
     sym = prof_symbol(name, info)
-    rf["traffic"] = measured_traffic(sym)
+    rf["traffic"] = measured_traffic(sym, workload)
     rf["kernel"] = sym
+    rf["launches_per_step"] = p["launches"] if name not in APPLY_KERNELS else iters + 1
     rf["avg_launch_ms"] = avg_ms
     rf["algorithmic_bytes_per_launch"] = p["bytes"] / p["launches"]
     rf["algorithmic_flops_per_launch"] = p["flops"] / p["launches"]
@@ -262,16 +302,25 @@ def roofline(prof, iters, info):
     return rf
 
 
-def cpu_baseline(prob, gpu_iters, budget_s):
-    """The oracle timed on a bounded sample of the same workload.
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
+        return max(n) if n else 1
+    except Exception:
+        return 1
 
-    Global assembly and decomposition are timed in full; the per-subdomain
-    work (Dirichlet matrix and its Cholesky factor, Neumann/overlap matrices,
-    the shift-and-invert eigensolve, basis) and the per-iteration local
-    solve are timed on an evenly spaced sample of subdomains until the time
-    budget is used; one SpMV is timed.  The estimate extrapolates to all
-    subdomains and to the GPU's iteration count (coarse matrix and coarse
-    solve left out, so it is a lower bound on the oracle's time)."""
+
+def cpu_baseline(prob, gpu_iters, budget_s):
+    """The oracle timed on a bounded SAMPLE of the same workload, extrapolated.
+
+    Timed in full: global assembly and decomposition, one SpMV.  Timed on an
+    evenly spaced sample of subdomains until the time budget is used: the
+    whole per-subdomain setup step of the oracle (Dirichlet matrix and its
+    Cholesky factor, Neumann/overlap matrices, the shift-and-invert
+    eigensolve, basis) and one local solve.  The estimate scales the sample
+    to all subdomains and to the GPU's iteration count; the coarse problem
+    is left out, so it is a lower bound on a full oracle run."""
     import numpy as np
     import scipy.linalg as sla
     from oracle import decomp, fem, geneo
@@ -280,76 +329,112 @@ def cpu_baseline(prob, gpu_iters, budget_s):
     subs, _ = decomp.build(prob)
     t_asm = time.perf_counter() - t0
     nev, tau, nev_max = prob.nev, prob.tau, prob.nev_max
+    if tau is not None:
+        nev = None
     setup_t, solve_t = [], []
     stride = max(1, len(subs) // 32)
     for j in range(0, len(subs), stride):
         s = subs[j]
         t1 = time.perf_counter()
-        AD = geneo.dirichlet_matrix(A, s)
-        L = np.linalg.cholesky(AD)
-        AN, Ao = geneo.local_matrices(prob, s)
-        ev = geneo.generalized_eigen(AN, s.mu[:, None] * Ao * s.mu[None, :])
-        m = geneo.select_count(ev.lam, nev=nev, tau=tau, nev_max=nev_max)
-        geneo.basis_vectors(s.mu, ev.P[:, :m])
+        L, lam, mj, _, _ = geneo.local_setup(prob, A, s, nev, tau, nev_max, True, False, "auto")
         t2 = time.perf_counter()
-        r = np.ones(len(AD))
-        for _ in range(3):
-            sla.cho_solve((L, True), r)
+        r = np.ones(L.shape[0])
+        sla.cho_solve((L, True), r)
         t3 = time.perf_counter()
         setup_t.append(t2 - t1)
-        solve_t.append((t3 - t2) / 3)
+        solve_t.append(t3 - t2)
         if sum(setup_t) + sum(solve_t) > budget_s:
             break
     x = np.ones(prob.ndof)
     t4 = time.perf_counter()
-    for _ in range(5):
+    for _ in range(3):
         A @ x
-    t_spmv = (time.perf_counter() - t4) / 5
+    t_spmv = (time.perf_counter() - t4) / 3
     nsub = len(subs)
     est = (t_asm + nsub * float(np.mean(setup_t))
            + gpu_iters * (t_spmv + nsub * float(np.mean(solve_t))))
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": prob.ndof / est, "unit": "DOF/s", "cores": threads, "kind": "oracle",
-            "sample": "full assembly; setup and local solves of %d of %d subdomains "
-                      "(%.2f s setup each), one SpMV; extrapolated to %d subdomains and %d "
-                      "iterations, coarse problem not counted" %
+    return {"value": prob.ndof / est, "unit": "DOF/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": "SAMPLE, not a full run: global assembly, decomposition and one SpMV "
+                      "timed in full; the oracle's per-subdomain setup step and one local "
+                      "solve timed on %d of %d subdomains (%.2f s setup each); extrapolated "
+                      "to %d subdomains and %d PCG iterations; coarse problem not counted" %
                       (len(setup_t), nsub, float(np.mean(setup_t)), nsub, gpu_iters),
+            "sample_cpu_s": t_asm + sum(setup_t) + sum(solve_t) + 3 * t_spmv,
             "est_total_s": est}
 
 
-def serve_bench(args):
+def serve_bench(requests, slots, budget_gb, seed):
     """p50/p99 latency of the serving loop on a seeded stream (2D Darcy of
     128^2..1024^2 and 3D layered 48^3..96^3 new problems, repeat solves with
     8 random right-hand sides).  The arrival rate is 0.8 x the single-slot
     capacity measured first on a closed-loop prefix of the same stream."""
     from paper_1906_10944_amd import serve as S
-    budget = int(args.serve_budget_gb * (1 << 30))
-    # capacity: the first requests one at a time, all arriving at once
-    probe = S.make_stream(seed=args.seed, count=8, rate=1e9)
+    budget = int(budget_gb * (1 << 30))
+    probe = S.make_stream(seed=seed, count=8, rate=1e9)
     srv = S.Server(budget, slots=1)
     t0 = time.perf_counter()
     srv.run(probe)
     mean_service = (time.perf_counter() - t0) / len(probe)
     srv.close()
     rate = 0.8 / mean_service
-    reqs = S.make_stream(seed=args.seed, count=args.serve_requests, rate=rate)
-    srv = S.Server(budget, slots=args.serve_slots)
+    reqs = S.make_stream(seed=seed, count=requests, rate=rate)
+    srv = S.Server(budget, slots=slots)
     st = srv.run(reqs)
     srv.close()
     kinds = {}
     for r in reqs:
         kinds[r.kind] = kinds.get(r.kind, 0) + 1
-    print(json.dumps({
-        "metric": "GenEO serving latency (setup+solve or repeat solve per request)",
-        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "unit": "ms",
-        "higher_is_better": False, "n_gpus": 1,
-        "requests": st["requests"], "errors": st["errors"], "kinds": kinds,
-        "arrival_rate_per_s": rate, "single_slot_mean_service_ms": mean_service * 1e3,
-        "solves_per_s": st["solves_per_s"], "dof_per_s": st["dof_per_s"],
-        "slots": args.serve_slots, "peak_bytes": st["peak_bytes"], "budget_bytes": budget,
-        "data": "synthetic", "config": {"workload": "serving stream (2D GRF 128^2-1024^2, "
-                                                    "3D layers 48^3-96^3, repeats)",
-                                         "seed": args.seed}}))
+    return {"metric": "GenEO serving latency (setup+solve or repeat solve per request)",
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "unit": "ms",
+            "requests": st["requests"], "errors": st["errors"], "kinds": kinds,
+            "arrival_rate_per_s": rate, "single_slot_mean_service_ms": mean_service * 1e3,
+            "solves_per_s": st["solves_per_s"], "dof_per_s": st["dof_per_s"],
+            "slots": slots, "peak_bytes": st["peak_bytes"], "budget_bytes": budget,
+            "workload": "serving stream (2D GRF 128^2-1024^2, 3D layers 48^3-96^3, repeats "
+                        "with 8 right-hand sides), seed %d" % seed}
+
+
+def workload_line(prob, args, steps, warmup, full):
+    """Timed steps of one workload (mixed form, the bench's options), with
+    the FP64 form, the error against the oracle's stored run and, if `full`,
+    the per-kernel roofline."""
+    runner = Runner(prob)
+    mixed = 1 if prob.precision == "mixed" else 0
+    ms, infos = timed(runner, mixed, steps, warmup)
+    tres = runner.true_residual()
+    last = infos[-1]
+    err = err_vs_oracle(prob, args.seed, runner.solution(), last["iters"])
+    runner.release()
+    out = {
+        "value": prob.ndof / (ms * 1e-3), "unit": "DOF/s", "ms_per_step": ms,
+        "steps": steps, "warmup": warmup,
+        "config": {"workload": prob.name, "ndof": prob.ndof, "nsub": prob.nsub,
+                   "form": "mixed" if mixed else "fp64", "rtol": prob.rtol, "seed": args.seed},
+        "iters": last["iters"], "converged": bool(last["converged"]),
+        "relres": last["relres"], "true_relres": tres, "kappa_est": last["kappa_est"],
+        "err_vs_oracle": err,
+        "nc": last["nc"], "eig_sweeps": last["eig_sweeps"], "eig_stalled": last["eig_stalled"],
+        "eig_max_resid": last["eig_max_resid"], "eig_block": last["eig_block"],
+        "symv_tiles": last["symv_tiles"], "fallback_fp64": last["fallback_fp64"],
+        "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
+        "setup_phase_ms": last["t_phase_ms"][:6],
+    }
+    if mixed and not args.no_fp64_form:
+        ms64, inf64 = timed(runner, 0, 1, 1)
+        tres64 = runner.true_residual()
+        err64 = err_vs_oracle(prob, args.seed, runner.solution(), inf64[-1]["iters"])
+        runner.release()
+        out["fp64_form"] = {"ms_per_step": ms64, "value": prob.ndof / (ms64 * 1e-3),
+                            "iters": inf64[-1]["iters"], "setup_ms": inf64[-1]["t_setup_ms"],
+                            "solve_ms": inf64[-1]["t_solve_ms"], "true_relres": tres64,
+                            "relres": inf64[-1]["relres"], "err_vs_oracle": err64}
+        out["speedup_vs_fp64_form"] = ms64 / ms
+    if full:
+        prof = kernel_profile(runner, mixed)
+        last["nsub"] = prob.nsub
+        out["roofline"] = roofline(prof, last["iters"], last, prob.name)
+        out["kernels_ms"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
+    return out
 
 
 def main():
@@ -362,50 +447,37 @@ def main():
         copy_probe()
         return
     if args.serve:
-        serve_bench(args)
+        out = serve_bench(args.serve_requests, args.serve_slots, args.serve_budget_gb, args.seed)
+        out.update({"higher_is_better": False, "n_gpus": 1, "data": "synthetic"})
+        print(json.dumps(out))
         return
-    import torch
+    import torch  # noqa: F401  (before the library: one HIP runtime in the process)
     from paper_1906_10944_amd import geneo as G
     G.lib()
     prob = make_problem(args.config, args.seed)
-    runner = Runner(prob)
-    mixed = 1 if prob.precision == "mixed" else 0
-    ms, infos = timed(runner, mixed, args.steps, args.warmup)
-    tres = runner.true_residual()
-    runner.release()
-    last = infos[-1]
+    head = workload_line(prob, args, args.steps, args.warmup, True)
+    mixed = head["config"]["form"] == "mixed"
     out = {
         "metric": "GenEO setup+PCG DOF/s to 1e-10 residual reduction (one GPU)",
-        "value": prob.ndof / (ms * 1e-3),
-        "unit": "DOF/s",
+        "value": head.pop("value"), "unit": head.pop("unit"),
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 local factors + f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": prob.name, "ndof": prob.ndof, "nsub": prob.nsub,
-                   "form": "mixed" if mixed else "fp64", "rtol": prob.rtol,
-                   "seed": args.seed},
-        "iters": last["iters"], "converged": bool(last["converged"]),
-        "relres": last["relres"], "true_relres": tres, "kappa_est": last["kappa_est"],
-        "nc": last["nc"], "eig_sweeps": last["eig_sweeps"], "eig_stalled": last["eig_stalled"],
-        "eig_max_resid": last["eig_max_resid"], "symv_tiles": last["symv_tiles"],
-        "fallback_fp64": last["fallback_fp64"],
-        "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
-        "setup_phase_ms": last["t_phase_ms"][:6],
     }
-    if mixed and not args.no_fp64_form:
-        ms64, inf64 = timed(runner, 0, 1, 1)
-        runner.release()
-        out["fp64_form"] = {"ms_per_step": ms64, "value": prob.ndof / (ms64 * 1e-3),
-                            "iters": inf64[-1]["iters"], "setup_ms": inf64[-1]["t_setup_ms"],
-                            "solve_ms": inf64[-1]["t_solve_ms"]}
-        out["speedup_vs_fp64_form"] = ms64 / ms
-    prof = kernel_profile(runner, mixed)
-    out["roofline"] = roofline(prof, last["iters"], last)
-    out["kernels_ms"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
+    head.pop("steps")
+    head.pop("warmup")
+    out.update(head)
+    if not args.no_nested and args.config != "config2":
+        p2 = make_problem("config2", args.seed)
+        line = workload_line(p2, args, max(1, min(args.steps, 10)), 2, False)
+        out["config2"] = line
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, last["iters"], args.cpu_budget_s)
+        out["cpu_baseline"] = cpu_baseline(prob, out["iters"], args.cpu_budget_s)
+    if not args.no_nested:
+        out["serving"] = serve_bench(args.serve_requests, args.serve_slots,
+                                     args.serve_budget_gb, args.seed)
     print(json.dumps(out))
 
 

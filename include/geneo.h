@@ -78,7 +78,11 @@ typedef struct {
   int ovl;            /* overlap in element layers, >= 1 */
   int dirichlet;      /* face bitmask */
   double load[3];     /* constant body load per component */
+  int pou;            /* partition of unity: GENEO_POU_CONSTANT or
+                         GENEO_POU_SARKIS (see geneo_assemble_q1) */
 } geneo_grid_t;
+
+enum { GENEO_POU_CONSTANT = 0, GENEO_POU_SARKIS = 1 };
 
 /* Sizes of the arrays geneo_assemble_q1 writes. */
 typedef struct {
@@ -93,6 +97,14 @@ typedef struct {
 /* Host-only size computation; no device work.  Returns GENEO_ERR_ARG for an
  * invalid grid. */
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes);
+
+/* The eigenvalue threshold of Thm. 1 for every subdomain of the box
+ * partition: tau[j] = delta_j / H_j (host array [nsub]), with H_j the
+ * diameter of Omega_j (the diagonal of its element box) and delta_j the
+ * width of its overlap zone Omega_j^o, 2 * ovl * min_a h_a (the strips on
+ * both sides of a neighbour's core boundary).  Host only; GENEO_ERR_ARG
+ * for an invalid grid. */
+int geneo_q1_thm1_tau(const geneo_grid_t* grid, double* tau);
 
 /*
  * Device assembly of a structured Q1 problem (Sec. 2 eqs. (2)-(3); Sec. 3
@@ -111,9 +123,14 @@ int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes);
  *  sub_ptr    [nsub+1], sub_idx [nloc]: N_j as ascending global dofs.
  *  sub_flags  [nloc]: bit0 = dof in D_j (not on the artificial boundary of
  *             Omega_j and not Dirichlet), bit1 = Dirichlet dof.
- *  pou        [nloc]: piecewise-constant partition of unity, 1/c_k on D_j
- *             (c_k = number of subdomains having k off their artificial
- *             boundary), 0 elsewhere.
+ *  pou        [nloc]: partition of unity (Def. 3), 0 outside D_j.
+ *             GENEO_POU_CONSTANT: the piecewise-constant one of Fig. 1
+ *             (left), 1/c_k on D_j (c_k = number of subdomains having k off
+ *             their artificial boundary).  GENEO_POU_SARKIS: the smooth one
+ *             of Fig. 1 (right), d_j(x_k) / sum_i d_i(x_k) on D_j, where
+ *             d_i(x) is the distance (physical units) of node x from the
+ *             faces of box Omega_i that lie inside Omega (0 when x is not
+ *             in Omega_i; 1 for a box without such faces).
  *  loc_rowptr [nloc+1], loc_col [nnz_loc]: shared pattern of the batched
  *             local matrices; row r of subdomain j is global row
  *             sub_ptr[j] + r, columns are LOCAL indices into N_j.
@@ -203,12 +220,22 @@ typedef struct {
                          timed on the device at the first setup of each
                          problem shape and kept for that device and shape
                          (results are bitwise the same for every value) */
+  int refine;         /* iterative-refinement steps after each PCG solve
+                         (0..8): r = b - A x with every row summed in
+                         double-double, A d = r by PCG to refine_rtol |r|,
+                         x += d.  0 = the plain method. */
+  double refine_rtol; /* tolerance of the correction solves */
+  const double* tau_sub; /* host [nsub], or NULL: per-subdomain thresholds
+                         tau_j > 0 replacing tau (take the eigenvalues
+                         < tau_j, at most nev_max of them), e.g. the
+                         delta_j / H_j of Thm. 1 (geneo_q1_thm1_tau).  Read
+                         during geneo_setup only. */
 } geneo_opts_t;
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-10, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
- * symv_tiles 0. */
+ * symv_tiles 0, refine 0, refine_rtol 1e-6, tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;
@@ -297,7 +324,10 @@ typedef struct {
   int converged;        /* ||b - A x||_2 <= rtol ||b||_2 on the recurrence */
   double relres;        /* final recurrence residual / ||b|| */
   double kappa_est;     /* CG-Lanczos condition number estimate */
-  double t_solve_ms;    /* wall time of pcg_solve */
+  double t_solve_ms;    /* wall time of the solve (refinement included) */
+  int refine_iters;     /* PCG iterations of the refinement steps */
+  double true_relres;   /* |b - A x| / |b| of the returned x, the residual
+                           summed in double-double */
 } geneo_pcg_info_t;
 
 /*
@@ -336,7 +366,7 @@ int geneo_spmv(const geneo_csr_t* A, const double* x, double* y, void* stream);
  * Names: "densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
  * "trtri_dirichlet", "lauum_dirichlet", "densify_shifted",
  * "chol_shifted_f64", "trsm_bwd", "trsm_fwd", "bapply", "rayleigh_ritz",
- * "chebyshev", "orth", "coarse_chol", "symv", "symv_cols".  While timing is
+ * "cheb_combine", "orth", "coarse_chol", "symv", "symv_cols".  While timing is
  * on, the eigen sweeps read their convergence flags after every sweep
  * (instead of one sweep late), so that the byte counts follow the active
  * set exactly.

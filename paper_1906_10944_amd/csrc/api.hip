@@ -9,6 +9,7 @@
 #include <memory>
 #include <tuple>
 #include <mutex>
+#include <thread>
 #include <shared_mutex>
 #include <string>
 #include <vector>
@@ -145,12 +146,14 @@ class PinnedPool {
 // as an earlier one then takes its buffers from here instead of the driver
 // (whose allocations, and frees, cost milliseconds each at these sizes and
 // whose frees synchronise the device).  A released block goes to a pending
-// list and becomes reusable only at settle(), which its callers reach after
-// the device has been synchronised: no kernel of the call that released it
-// can still be running.  Reuse takes the smallest free block of at least
-// the request and at most 1/8 larger.  At most kCacheMax free bytes are
-// kept per device; trim() hands all free blocks back (also done, with one
-// retry, when the driver reports out of memory).
+// list of the releasing thread and becomes reusable at settle_thread(),
+// which that thread calls once it has synchronised every stream its work
+// on the block was enqueued on (each entry point releases buffers only
+// after that): no kernel that used the block can still be running, and no
+// other thread's work is waited for.  Reuse takes the smallest free block
+// of at least the request and at most 1/8 larger.  At most kCacheMax free
+// bytes are kept per device; trim() hands all free blocks back (also done,
+// with one retry, when the driver reports out of memory).
 class DevCache {
  public:
   static constexpr size_t kCacheMax = (size_t)64 << 30;
@@ -190,27 +193,31 @@ class DevCache {
     auto it = sizes_.find(p);
     const size_t bytes = it != sizes_.end() ? it->second : 0;
     if (it != sizes_.end()) sizes_.erase(it);
-    pools_[dev].pending.push_back({bytes, p});
+    pools_[dev].pending[std::this_thread::get_id()].push_back({bytes, p});
   }
-  // the device dev has been synchronised since the pending blocks were released
-  void settle(int dev) {
-    DriverLock dl;
+  // The calling thread has synchronised the streams of the work on the
+  // blocks it released: they become reusable.
+  void settle_thread(int dev) {
     std::vector<void*> drop;
     {
       std::lock_guard<std::mutex> g(mu_);
       Pool& pl = pools_[dev];
-      for (auto& b : pl.pending) {
+      auto it = pl.pending.find(std::this_thread::get_id());
+      if (it == pl.pending.end()) return;
+      for (auto& b : it->second) {
         pl.free.insert(b);
         pl.free_bytes += b.first;
       }
-      pl.pending.clear();
+      pl.pending.erase(it);
       while (pl.free_bytes > kCacheMax && !pl.free.empty()) {
-        auto it = std::prev(pl.free.end());
-        pl.free_bytes -= it->first;
-        drop.push_back(it->second);
-        pl.free.erase(it);
+        auto f = std::prev(pl.free.end());
+        pl.free_bytes -= f->first;
+        drop.push_back(f->second);
+        pl.free.erase(f);
       }
     }
+    if (drop.empty()) return;
+    DriverLock dl;  // hipFree synchronises the device
     for (void* q : drop) (void)hipFree(q);
   }
   void trim(int dev) {
@@ -233,7 +240,7 @@ class DevCache {
  private:
   struct Pool {
     std::multimap<size_t, void*> free;
-    std::vector<std::pair<size_t, void*>> pending;
+    std::map<std::thread::id, std::vector<std::pair<size_t, void*>>> pending;
     size_t free_bytes = 0;
   };
   std::mutex mu_;
@@ -241,13 +248,12 @@ class DevCache {
   std::map<void*, size_t> sizes_;
 };
 
-// settle() of the current device after synchronising it
-void settle_device() {
+// The calling thread's released blocks on the current device become
+// reusable (its streams have been synchronised).
+void settle_thread() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
-  DriverLock dl;
-  (void)hipDeviceSynchronize();
-  DevCache::get().settle(dev);
+  DevCache::get().settle_thread(dev);
 }
 
 template <typename T>
@@ -302,11 +308,12 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-// extreme eigenvalues of a symmetric tridiagonal matrix by Sturm bisection
-int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+// extreme eigenvalues of a symmetric tridiagonal matrix (diagonal d[0..n),
+// off-diagonal e[0..n-1)) by Sturm bisection
+int sturm_count(const double* d, const double* e, int n, double x) {
   int cnt = 0;
   double q = 1.0;
-  for (size_t i = 0; i < d.size(); ++i) {
+  for (int i = 0; i < n; ++i) {
     double off = i ? e[i - 1] * e[i - 1] : 0.0;
     q = d[i] - x - (i ? off / q : 0.0);
     if (q == 0.0) q = -1e-300;
@@ -315,16 +322,16 @@ int sturm_count(const std::vector<double>& d, const std::vector<double>& e, doub
   return cnt;
 }
 
-double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int k) {
+double tridiag_eig(const double* d, const double* e, int n, int k) {
   double lo = 1e300, hi = -1e300;
-  for (size_t i = 0; i < d.size(); ++i) {
-    double r = (i ? fabs(e[i - 1]) : 0.0) + (i + 1 < d.size() ? fabs(e[i]) : 0.0);
+  for (int i = 0; i < n; ++i) {
+    double r = (i ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
     lo = std::min(lo, d[i] - r);
     hi = std::max(hi, d[i] + r);
   }
   for (int it = 0; it < 200; ++it) {
     double mid = 0.5 * (lo + hi);
-    if (sturm_count(d, e, mid) > k) hi = mid;
+    if (sturm_count(d, e, n, mid) > k) hi = mid;
     else lo = mid;
     if (hi - lo <= 1e-14 * std::max(fabs(lo), fabs(hi))) break;
   }
@@ -354,6 +361,7 @@ struct geneo_handle_s {
   // coarse space
   int nc = 0, ntc = 0, b = 0;
   DBuf<int> m, zoff, coff, hnt;
+  DBuf<double> tau_sub;  // per-subdomain thresholds (opts.tau_sub), else empty
   // apply job list of the symmetric products: (subdomain, 1 if its inverse
   // is FP64) for every subdomain, then (nsub, 2) for the coarse inverse
   DBuf<int2> ajobs;
@@ -376,6 +384,13 @@ struct geneo_handle_s {
   // pcg workspace
   int pcg_cap = 0, pcg_maxit = 0;
   DBuf<double> r, z, p, p2, q, partial, alphas, betas;
+  // the iterate of the captured PCG graphs (the caller's x is copied in and
+  // out, so the graphs serve every solve) and the refinement residual
+  DBuf<double> xs, rb;
+  // captured graphs of PCG_CHUNK and PCG_TAIL iterations, reused while the
+  // matrix and the work buffers they were captured with stay the same
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  const void* gkey[6] = {};
   DBuf<PcgScalars> sc;
   DBuf<int> done;
   int lpr = 8;
@@ -387,7 +402,11 @@ struct geneo_handle_s {
   PcgScalars* hsc = nullptr;  // two chunk slots and the final read
   double* hab = nullptr;  // alphas then betas, pcg_maxit each
   hipEvent_t fev[2] = {nullptr, nullptr};
+  std::map<hipStream_t, hipEvent_t> apply_ev;  // last geneo_apply per stream
   ~geneo_handle_s() {
+    for (auto& se : apply_ev) (void)hipEventDestroy(se.second);
+    for (hipGraphExec_t e : gexec)
+      if (e) (void)hipGraphExecDestroy(e);
     PinnedPool::get().give(hflag);
     PinnedPool::get().give(hab);
     PinnedPool::get().give(hsc);
@@ -435,18 +454,29 @@ SymvArgs symv_args(const geneo_handle_s* h, bool rev) {
   return sa;
 }
 
-// z = M^{-1} r on stream st.  Inside the PCG loop (pcg = true) the first
-// launch also performs the convergence check on the r.r partial sums and
-// the apply is skipped once `done` is set; the combine step always leaves
-// the r.z partial sums (per 256-row block) in h->rz_part.  rev: walk the
-// subdomains in reverse order (consecutive applies alternate).
+// Device work of one PCG solve: the vectors r, z, the two alternating p
+// buffers and q, the partial sums of the reductions, the scalars and the
+// done flag, and the alpha / beta records of the Lanczos estimate (cap + 1
+// entries each), held by the handle.
+struct PcgWork {
+  double *r, *z, *p, *p2, *q, *partial, *rr_part, *alphas, *betas;
+  PcgScalars* sc;
+  int* done;
+  int cap;
+};
+
+// z = M^{-1} r on stream st.  Inside the PCG loop (w not NULL) the first
+// launch also performs the convergence check on the r.r partial sums in w
+// and the apply is skipped once w->done is set; the combine step always
+// leaves the r.z partial sums (per 256-row block) in h->rz_part.  rev: walk
+// the subdomains in reverse order (consecutive applies alternate).
 hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const int* done,
-                         hipStream_t st, bool pcg, bool rev) {
+                         hipStream_t st, const PcgWork* w, bool rev) {
   hipError_t e;
-  if (pcg) {
+  if (w) {
     if ((e = check_apply_in(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, h->Z.p, h->zoff.p,
                             h->m.p, h->nd.p, h->voffD.p, h->coff.p, h->rH.p,
-                            h->nc > 0 ? h->nsub : 0, h->rr_part.p, h->sc.p, h->done.p, st)))
+                            h->nc > 0 ? h->nsub : 0, w->rr_part, w->sc, w->done, st)))
       return e;
   } else {
     if ((e = gather_local(r, h->dglob.p, h->dscale.p, h->LD.nvec, h->xl.p, done, st))) return e;
@@ -858,7 +888,7 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   X.G.alloc(LN.ntiles * TSQ);
   X.DG.alloc(LN.ndiag * TSQ);
   // eigen block size
-  const int want = o.tau > 0 ? o.nev_max : o.nev;
+  const int want = (o.tau > 0 || h->tau_sub.p) ? o.nev_max : o.nev;
   int minnt = LN.nt[0];
   for (int j = 1; j < nsub; ++j) minnt = std::min(minnt, LN.nt[j]);
   int b = o.eig_block;
@@ -1020,8 +1050,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("rayleigh_ritz", sb, 2.0 * vb, 0.0);
       HIPCHK(launch_rr2(X.U.p, X.T.p, X.Y.p, X.theta.p, X.resid.p, X.active.p, X.voffN.p,
-                        X.ntN.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, o.eig_tol, wk, stl,
-                        sb));
+                        X.ntN.p, nsub, b, o.nev, o.tau, h->tau_sub.p, o.nev_max, o.sigma,
+                        o.eig_tol, wk, stl, sb));
     }
     if (lag) {
       HIPCHK(hipMemcpyAsync(aflag[it & 1], X.active.p, (size_t)nsub * sizeof(int),
@@ -1055,18 +1085,34 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       // Z_1 = (2/a) S Y - Y goes to U, Z_0 is Y itself, and each further
       // degree costs one shifted solve; Z_{k+1} goes to P (then swapped
       // with U), Z_m ends in U.
-      ProfScope ps("chebyshev", sb, 0.0, 0.0);
-      HIPCHK(launch_cheb(X.U.p, nullptr, X.U.p, X.Y.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,
-                         LN.maxnt, true, X.active.p, sb));
+      // (each launch timed under its kernel's name: the solves and B
+      // products count with those of the sweep itself)
+      {
+        ProfScope ps("cheb_combine", sb, 3.0 * vb / 2.0, 0.0);
+        HIPCHK(launch_cheb(X.U.p, nullptr, X.U.p, X.Y.p, X.theta.p, X.voffN.p, X.ntN.p, nsub, b,
+                           LN.maxnt, true, X.active.p, sb));
+      }
       for (int k = 1; k < o.eig_cheb; ++k) {
-        HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                               X.U.p, X.T.p, X.active.p, sb));
-        HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.brows.p, X.nbrows,
-                             X.voffN.p, b, X.T.p, X.W.p, X.active.p, sb));
-        HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                               X.W.p, X.T.p, X.active.p, sb));
-        HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, k == 1 ? X.Y.p : X.P.p, X.theta.p, X.voffN.p,
-                           X.ntN.p, nsub, b, LN.maxnt, false, X.active.p, sb));
+        {
+          ProfScope ps("trsm_bwd", sb, gb + vb, tf);
+          HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
+                                 b, X.U.p, X.T.p, X.active.p, sb));
+        }
+        {
+          ProfScope ps("bapply", sb, 12.0 * X.nnzB + 2.0 * 8.0 * X.nbrows * b, 0.0);
+          HIPCHK(launch_bapply(S->sub_ptr, X.brp.p, X.bcol.p, X.bval.p, X.brows.p, X.nbrows,
+                               X.voffN.p, b, X.T.p, X.W.p, X.active.p, sb));
+        }
+        {
+          ProfScope ps("trsm_fwd", sb, gb + vb, tf);
+          HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
+                                 b, X.W.p, X.T.p, X.active.p, sb));
+        }
+        {
+          ProfScope ps("cheb_combine", sb, 2.0 * vb, 0.0);
+          HIPCHK(launch_cheb(X.P.p, X.U.p, X.T.p, k == 1 ? X.Y.p : X.P.p, X.theta.p, X.voffN.p,
+                             X.ntN.p, nsub, b, LN.maxnt, false, X.active.p, sb));
+        }
         std::swap(X.U.p, X.P.p);  // Z_{k+1} -> U, Z_k -> P
       }
     }
@@ -1097,7 +1143,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   // eigenvectors p = G^{-T} y
   HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b, X.Y.p,
                          X.T.p, nullptr, sb));
-  HIPCHK(launch_select(X.theta.p, nsub, b, o.nev, o.tau, o.nev_max, o.sigma, h->m.p, X.lam.p, sb));
+  HIPCHK(launch_select(X.theta.p, nsub, b, o.nev, o.tau, h->tau_sub.p, o.nev_max, o.sigma, h->m.p,
+                       X.lam.p, sb));
   h->m_host = download(h->m.p, nsub, sb);
   h->lam_host = download(X.lam.p, (size_t)nsub * b, sb);
   tm[1].stop(sb);
@@ -1199,11 +1246,28 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
     DriverLock dl;
     HIPCHK(hipStreamCreateWithFlags(&h->hs, hipStreamNonBlocking));
   }
+  if (o.tau_sub) {
+    // the caller's host array is read here, during the call, and not kept
+    std::vector<double> ts(o.tau_sub, o.tau_sub + nsub);
+    for (double t : ts)
+      if (!(t > 0)) fail(GENEO_ERR_ARG, "tau_sub entries must be positive");
+    h->tau_sub.upload(ts, st);
+    h->opts.tau_sub = nullptr;
+  }
   struct ArenaScope {
     ArenaScope() { t_arena.begin(); }
     ~ArenaScope() { t_arena.end(); }
   } arena_scope;
   SetupScratch X;
+  // Destroyed before X (and, on an error, before the handle): every kernel
+  // the setup enqueued has finished before any of its buffers is released.
+  struct StreamsDone {
+    hipStream_t a, b;
+    ~StreamsDone() {
+      if (a) (void)hipStreamSynchronize(a);
+      if (b) (void)hipStreamSynchronize(b);
+    }
+  } streams_done{st, h->hs};
   PhaseTimer tm0, tmL, tmC[4];
 
   // ---- 0. index lists, D_j maps, scaling, owner lists (stream st)
@@ -1395,6 +1459,8 @@ void ensure_pcg(geneo_handle_s* h, int maxit) {
     h->rr_part.alloc(PCG_NB);
     h->sc.alloc(1);
     h->done.alloc(1);
+    h->xs.alloc(h->n);
+    h->rb.alloc(h->n);
     h->pcg_cap = h->n;
   }
   if (!h->hflag) {
@@ -1416,37 +1482,87 @@ void ensure_pcg(geneo_handle_s* h, int maxit) {
 #define PCG_CHUNK 8
 #define PCG_TAIL 2
 
-void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x, double rtol,
-             int maxit, geneo_pcg_info_t* info) {
-  hipStream_t st = h->hs;
+PcgWork handle_work(geneo_handle_s* h) {
+  PcgWork w;
+  w.r = h->r.p;
+  w.z = h->z.p;
+  w.p = h->p.p;
+  w.p2 = h->p2.p;
+  w.q = h->q.p;
+  w.partial = h->partial.p;
+  w.rr_part = h->rr_part.p;
+  w.alphas = h->alphas.p;
+  w.betas = h->betas.p;
+  w.sc = h->sc.p;
+  w.done = h->done.p;
+  w.cap = h->pcg_maxit;
+  return w;
+}
+
+// PCG start, all on the device (stream st): b.b and tol2, r = b - A x, r.r
+// (done when already converged), z = M^{-1} r (which also leaves the r.z
+// partial sums that the first alpha needs).
+void pcg_enqueue_start(geneo_handle_s* h, const geneo_csr_t* A, const double* b, const double* x,
+                       double rtol, int maxit, const PcgWork& w, hipStream_t st) {
   const int n = h->n;
-  double t0 = now_ms();
-  // start, all on the device: b.b and tol2, r = b - A x, r.r (done when
-  // already converged), z = M^{-1} r (which also leaves the r.z partial
-  // sums that the first alpha needs)
-  HIPCHK(dot_partial(b, b, n, h->partial.p, nullptr, st));
-  HIPCHK(pcg_start(h->partial.p, 0, h->sc.p, h->done.p, rtol * rtol, maxit, st));
-  HIPCHK(spmv(A, x, h->q.p, h->lpr, nullptr, st));
-  HIPCHK(residual0(b, h->q.p, h->r.p, n, st));
-  HIPCHK(dot_partial(h->r.p, h->r.p, n, h->partial.p, nullptr, st));
-  HIPCHK(pcg_start(h->partial.p, 1, h->sc.p, h->done.p, rtol * rtol, maxit, st));
-  HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, false, false));
+  HIPCHK(dot_partial(b, b, n, w.partial, nullptr, st));
+  HIPCHK(pcg_start(w.partial, 0, w.sc, w.done, rtol * rtol, maxit, st));
+  HIPCHK(spmv(A, x, w.q, h->lpr, nullptr, st));
+  HIPCHK(residual0(b, w.q, w.r, n, st));
+  HIPCHK(dot_partial(w.r, w.r, n, w.partial, nullptr, st));
+  HIPCHK(pcg_start(w.partial, 1, w.sc, w.done, rtol * rtol, maxit, st));
+  HIPCHK(apply_enqueue(h, w.r, w.z, w.done, st, nullptr, false));
+}
+
+// Global PCG iteration it (0-based): p = z + beta p (from the buffer of
+// parity it into the other), q = A p, x and r updated with alpha, the
+// convergence check and z = M^{-1} r; every kernel returns at once when
+// done is set.  The apply walks the subdomains in reverse order on even
+// iterations.
+void pcg_enqueue_iteration(geneo_handle_s* h, const geneo_csr_t* A, double* x, const PcgWork& w,
+                           int it, hipStream_t st) {
+  const int n = h->n;
   const int nrz = (n + 255) / 256;
-  // Two graphs, of PCG_CHUNK and PCG_TAIL iterations: 6 launches each
-  // (p update with beta, SpMV and p.Ap; x/r update with alpha; check +
-  // apply input; symmetric product and its column sums; combine with r.z).
-  // p alternates between two buffers (both lengths are even, so every
-  // replay starts on the first).  Every kernel returns at once when done is
-  // set.
-  double* pb[2] = {h->p.p, h->p2.p};
-  struct Execs {  // destroyed on every exit, errors included
-    hipGraphExec_t e[2] = {nullptr, nullptr};
-    ~Execs() {
-      for (hipGraphExec_t x : e)
-        if (x) (void)hipGraphExecDestroy(x);
+  double* pb[2] = {w.p, w.p2};
+  double* pk = pb[(it + 1) & 1];
+  HIPCHK(p_spmv(A, h->lpr, w.z, pb[it & 1], pk, w.q, h->rz_part.p, nrz, w.sc, w.betas, w.partial,
+                PCG_NB_SPMV, w.done, st));
+  HIPCHK(update_xr_alpha(x, w.r, pk, w.q, n, w.partial, PCG_NB_SPMV, h->rz_part.p, nrz, w.sc,
+                         w.alphas, w.rr_part, w.done, st));
+  HIPCHK(apply_enqueue(h, w.r, w.z, w.done, st, &w, (it & 1) == 0));
+}
+
+// Condition estimate from the CG coefficients: extreme eigenvalues of the
+// Lanczos tridiagonal T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1},
+// T_{k,k+1} = sqrt(beta_k)/alpha_k, in the caller's d / e storage (iters
+// and iters - 1 entries).
+double kappa_from_cg(const double* al, const double* be, int iters, double* d, double* e) {
+  if (iters <= 0) return 1.0;
+  for (int i = 0; i < iters; ++i) {
+    d[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+    if (i + 1 < iters) e[i] = sqrt(be[i]) / al[i];
+  }
+  const double lmin = tridiag_eig(d, e, iters, 0), lmax = tridiag_eig(d, e, iters, iters - 1);
+  return lmin > 0 ? lmax / lmin : INFINITY;
+}
+
+// Two graphs, of PCG_CHUNK and PCG_TAIL iterations on the iterate h->xs:
+// 6 launches each (p update with beta, SpMV and p.Ap; x/r update with
+// alpha; check + apply input; symmetric product and its column sums;
+// combine with r.z).  p alternates between two buffers (both lengths are
+// even, so every replay starts on the first and runs the launches of the
+// global iterations of the same parity).  Every kernel returns at once
+// when done is set.  Captured at the first solve and again only when the
+// matrix or a work buffer has changed: b, rtol and maxit reach the
+// iterations through the device scalars, not through the graphs.
+void pcg_graphs(geneo_handle_s* h, const geneo_csr_t* A, const PcgWork& w, hipStream_t st) {
+  const void* key[6] = {A->rowptr, A->col, A->val, (const void*)(intptr_t)A->n, h->xs.p, w.alphas};
+  if (h->gexec[0] && std::equal(key, key + 6, h->gkey)) return;
+  for (hipGraphExec_t& e : h->gexec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
     }
-  } execs;
-  hipGraphExec_t* ex = execs.e;
   // an error inside a capture ends it, so that the stream stays usable
   struct Capture {
     hipStream_t st;
@@ -1463,21 +1579,32 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
     Capture cap{st};
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     cap.on = true;
-    for (int k = 0; k < (gi ? PCG_TAIL : PCG_CHUNK); ++k) {
-      double* pk = pb[(k + 1) & 1];
-      HIPCHK(p_spmv(A, h->lpr, h->z.p, pb[k & 1], pk, h->q.p, h->rz_part.p, nrz, h->sc.p,
-                    h->betas.p, h->partial.p, PCG_NB_SPMV, h->done.p, st));
-      HIPCHK(update_xr_alpha(x, h->r.p, pk, h->q.p, n, h->partial.p, PCG_NB_SPMV, h->rz_part.p,
-                             nrz, h->sc.p, h->alphas.p, h->rr_part.p, h->done.p, st));
-      HIPCHK(apply_enqueue(h, h->r.p, h->z.p, h->done.p, st, true, (k & 1) == 0));
-    }
+    for (int k = 0; k < (gi ? PCG_TAIL : PCG_CHUNK); ++k)
+      pcg_enqueue_iteration(h, A, h->xs.p, w, k, st);
     cap.on = false;
     HIPCHK(hipStreamEndCapture(st, &graph));
-    const hipError_t ie = hipGraphInstantiate(&ex[gi], graph, nullptr, nullptr, 0);
+    const hipError_t ie = hipGraphInstantiate(&h->gexec[gi], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     HIPCHK(ie);
   }
-  capture_lock.unlock();
+  std::copy(key, key + 6, h->gkey);
+}
+
+// One PCG solve on the handle's stream.  correction = false: x (start
+// vector in, solution out) is copied to the graphs' iterate and back;
+// correction = true: the iterate starts at 0 and is added to x at the end
+// (a refinement step for A d = b).
+void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x, double rtol,
+             int maxit, geneo_pcg_info_t* info, bool correction = false) {
+  hipStream_t st = h->hs;
+  double t0 = now_ms();
+  const PcgWork w = handle_work(h);
+  const size_t nb = (size_t)h->n * sizeof(double);
+  if (correction) HIPCHK(hipMemsetAsync(h->xs.p, 0, nb, st));
+  else HIPCHK(hipMemcpyAsync(h->xs.p, x, nb, hipMemcpyDeviceToDevice, st));
+  pcg_enqueue_start(h, A, b, h->xs.p, rtol, maxit, w, st);
+  pcg_graphs(h, A, w, st);
+  hipGraphExec_t* ex = h->gexec;
   // Up to two chunks in flight: after each launch the done flag and the
   // scalars are copied to pinned memory, and the host reads a chunk's copy
   // while the next chunk runs, so the device never waits for the host.
@@ -1527,6 +1654,8 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
     if (nfl == 0 && left <= 0) left = 1;  // never stop on a prediction alone
     if (nfl == 0 && queued >= cap) break;
   }
+  if (correction) HIPCHK(add_into(x, h->xs.p, h->n, st));
+  else HIPCHK(hipMemcpyAsync(x, h->xs.p, nb, hipMemcpyDeviceToDevice, st));
   // drain: every launch is complete before the handle's buffers are read
   // the scalars and the alpha / beta records (for the Lanczos estimate of
   // kappa), read back together
@@ -1542,19 +1671,50 @@ void pcg_one(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x
   info->iters = iters;
   info->converged = converged;
   info->relres = bb > 0 ? sqrt(rr / bb) : 0.0;
-  info->kappa_est = 1.0;
-  if (iters > 0) {
-    const double* al = h->hab;
-    const double* be = h->hab + h->pcg_maxit;
-    std::vector<double> d(iters), e(iters > 1 ? iters - 1 : 0);
-    for (int i = 0; i < iters; ++i) {
-      d[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
-      if (i + 1 < iters) e[i] = sqrt(be[i]) / al[i];
-    }
-    double lmin = tridiag_eig(d, e, 0), lmax = tridiag_eig(d, e, iters - 1);
-    info->kappa_est = lmin > 0 ? lmax / lmin : INFINITY;
+  {
+    std::vector<double> d(std::max(iters, 1)), e(std::max(iters, 1));
+    info->kappa_est = kappa_from_cg(h->hab, h->hab + h->pcg_maxit, iters, d.data(), e.data());
   }
   info->t_solve_ms = now_ms() - t0;
+}
+
+// |b - A x| / |b| with the residual summed in double-double (rb: work
+// vector of n, partial: PCG_NB partial sums, host: PCG_NB host doubles).
+double true_relres(const geneo_csr_t* A, const double* b, const double* x, double* rb,
+                   double* partial, double* host, hipStream_t st) {
+  const int n = A->n;
+  double num = 0.0, den = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 0) {
+      HIPCHK(residual_dd(A, b, x, rb, st));
+      HIPCHK(dot_partial(rb, rb, n, partial, nullptr, st));
+    } else {
+      HIPCHK(dot_partial(b, b, n, partial, nullptr, st));
+    }
+    HIPCHK(hipMemcpyAsync(host, partial, PCG_NB * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double t = 0.0;
+    for (int i = 0; i < PCG_NB; ++i) t += host[i];
+    (pass == 0 ? num : den) = t;
+  }
+  return den > 0 ? sqrt(num / den) : 0.0;
+}
+
+// Iterative refinement after a solve (opts.refine steps): r = b - A x in
+// double-double, A d = r by PCG to refine_rtol |r| (solve(b, x, rtol, info,
+// correction)), x += d.  The attainable accuracy of x then no longer rests
+// on the FP64 rounding of the residual (u kappa(A) for a plain FP64 PCG).
+template <typename Solve>
+void refine_solution(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x,
+                     double* rb, geneo_pcg_info_t* info, hipStream_t st, Solve&& solve) {
+  info->refine_iters = 0;
+  for (int k = 0; k < h->opts.refine; ++k) {
+    HIPCHK(residual_dd(A, b, x, rb, st));
+    geneo_pcg_info_t ci{};
+    solve(rb, x, h->opts.refine_rtol, &ci);
+    info->refine_iters += ci.iters;
+    if (ci.iters == 0) break;  // the residual is zero or already negligible
+  }
 }
 
 int finish(int code, const std::string& msg) {
@@ -1604,6 +1764,9 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->eig_floor = 1e-6;
   o->eig_cheb = 3;
   o->symv_tiles = 0;
+  o->tau_sub = nullptr;
+  o->refine = 0;
+  o->refine_rtol = 1e-6;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -1615,6 +1778,16 @@ int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
   q1_sizes(g, sizes);
   if (sizes->nnz >= (1ll << 31) || sizes->nnz_loc >= (1ll << 31) || sizes->ndof >= (1ll << 31))
     return finish(GENEO_ERR_ARG, "problem exceeds 32-bit indexing");
+  return GENEO_OK;
+}
+
+int geneo_q1_thm1_tau(const geneo_grid_t* grid, double* tau) {
+  if (!tau) return finish(GENEO_ERR_ARG, "tau is NULL");
+  Q1Geom g;
+  std::string err;
+  int rc = q1_make_geom(grid, &g, &err);
+  if (rc) return finish(rc, err);
+  q1_thm1_tau(g, tau);
   return GENEO_OK;
 }
 
@@ -1643,7 +1816,7 @@ int geneo_assemble_q1(const geneo_grid_t* grid, const double* coeff, int* A_rowp
     HIPCHK(hipStreamSynchronize(st));
     dg.release();
     nzoff.release();
-    settle_device();
+    settle_thread();
     return GENEO_OK;
   } catch (Err& e) {
     return finish(e.code, e.msg);
@@ -1666,7 +1839,7 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
     if (!(o.sigma < 0)) fail(GENEO_ERR_ARG, "sigma must be negative");
     if (o.precision != GENEO_PREC_FP64 && o.precision != GENEO_PREC_MIXED)
       fail(GENEO_ERR_ARG, "unknown precision mode");
-    if (o.coarse && (o.tau > 0 ? o.nev_max < 1 : o.nev < 0))
+    if (o.coarse && ((o.tau > 0 || o.tau_sub) ? o.nev_max < 1 : o.nev < 0))
       fail(GENEO_ERR_ARG, "invalid eigenvector count");
     if (o.eig_block && (o.eig_block % 16 || o.eig_block > 64))
       fail(GENEO_ERR_ARG, "eig_block must be a multiple of 16 up to 64");
@@ -1675,36 +1848,52 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "invalid eigen tolerances");
     if (o.symv_tiles != 0 && o.symv_tiles != 8 && o.symv_tiles != 16 && o.symv_tiles != 32)
       fail(GENEO_ERR_ARG, "symv_tiles must be 0, 8, 16 or 32");
+    if (o.refine < 0 || o.refine > 8 || !(o.refine_rtol > 0 && o.refine_rtol < 1))
+      fail(GENEO_ERR_ARG, "refine must be 0..8 with 0 < refine_rtol < 1");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
-    settle_device();  // the setup's scratch blocks become reusable
+    settle_thread();  // the setup's scratch blocks become reusable
     return GENEO_OK;
   } catch (Err& e) {
-    settle_device();
+    // setup_impl synchronised its streams before its buffers were released
+    settle_thread();
     return finish(e.code, e.msg);
   }
 }
 
 int geneo_apply(geneo_handle_t h, const double* r, double* z, void* stream) {
   if (!h || !r || !z || r == z) return finish(GENEO_ERR_ARG, "invalid apply arguments");
-  hipError_t e = apply_enqueue(h, r, z, nullptr, (hipStream_t)stream, false, h->apply_rev);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = apply_enqueue(h, r, z, nullptr, st, nullptr, h->apply_rev);
   h->apply_rev = !h->apply_rev;
+  if (e == hipSuccess) {
+    // remember the stream's last use of the handle for geneo_destroy
+    auto it = h->apply_ev.find(st);
+    if (it == h->apply_ev.end()) {
+      hipEvent_t ev = nullptr;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) it = h->apply_ev.emplace(st, ev).first;
+    }
+    if (e == hipSuccess) e = hipEventRecord(it->second, st);
+  }
   if (e != hipSuccess) return finish(GENEO_ERR_HIP, hipGetErrorString(e));
   return GENEO_OK;
 }
 
 void geneo_destroy(geneo_handle_t h) {
   if (!h) return;
-  DriverLock dl;
-  (void)hipDeviceSynchronize();
+  // the work enqueued with the handle: its own stream and the streams of
+  // the geneo_apply calls (an event recorded after each)
+  if (h->hs) (void)hipStreamSynchronize(h->hs);
+  for (auto& se : h->apply_ev) (void)hipEventSynchronize(se.second);
   delete h;
-  settle_device();
+  settle_thread();
 }
 
 int geneo_trim(void) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return finish(GENEO_ERR_HIP, "hipGetDevice failed");
-  settle_device();
+  settle_thread();
   DevCache::get().trim(dev);
   return GENEO_OK;
 }
@@ -1787,9 +1976,19 @@ int pcg_solve(const geneo_csr_t* A, geneo_handle_t h, const double* b, double* x
     HIPCHK(hipEventRecord(ev, us));
     HIPCHK(hipStreamWaitEvent(h->hs, ev, 0));
     int rc = GENEO_OK;
+    std::vector<double> host(PCG_NB);
     for (int k = 0; k < nrhs; ++k) {
-      pcg_one(h, A, b + (int64_t)k * h->n, x + (int64_t)k * h->n, rtol, maxit, &info[k]);
+      const double* bk = b + (int64_t)k * h->n;
+      double* xk = x + (int64_t)k * h->n;
+      const double t0 = now_ms();
+      pcg_one(h, A, bk, xk, rtol, maxit, &info[k]);
       if (!info[k].converged) rc = GENEO_ERR_MAXIT;
+      refine_solution(h, A, bk, xk, h->rb.p, &info[k], h->hs,
+                      [&](const double* rb, double* xx, double rt, geneo_pcg_info_t* ci) {
+                        pcg_one(h, A, rb, xx, rt, maxit, ci, true);
+                      });
+      info[k].true_relres = true_relres(A, bk, xk, h->rb.p, h->partial.p, host.data(), h->hs);
+      info[k].t_solve_ms = now_ms() - t0;
     }
     HIPCHK(hipEventRecord(ev, h->hs));
     HIPCHK(hipStreamWaitEvent(us, ev, 0));

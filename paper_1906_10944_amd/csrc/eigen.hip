@@ -486,10 +486,12 @@ __global__ __launch_bounds__(64) void k_ritz_check(const double* __restrict__ pa
                                                    const double* __restrict__ theta,
                                                    double* __restrict__ resid,
                                                    int* __restrict__ active, int b, int nev,
-                                                   double tau, int nev_max, double sigma,
-                                                   double tol, EigStall stl) {
+                                                   double tau, const double* __restrict__ tau_sub,
+                                                   int nev_max, double sigma, double tol,
+                                                   EigStall stl) {
   const int j = blockIdx.x;
   if (!active[j]) return;
+  if (tau_sub) tau = tau_sub[j];
   __shared__ double rr[EIG_MAXB];
   const int c = threadIdx.x;
   const double* th = theta + (int64_t)j * b;
@@ -580,8 +582,8 @@ hipError_t launch_orth2(double* U, const int* voff, const int* nt, int nsub, int
 
 hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, double* resid,
                       int* active, const int* voff, const int* nt, int nsub, int b, int nev,
-                      double tau, int nev_max, double sigma, double tol, const EigWork& wk,
-                      const EigStall& stl, hipStream_t st) {
+                      double tau, const double* tau_sub, int nev_max, double sigma, double tol,
+                      const EigWork& wk, const EigStall& stl, hipStream_t st) {
   hipLaunchKernelGGL(k_gram, dim3(nsub), dim3(1024), 0, st, U, W, voff, nt, b, wk.G, active, 1);
   switch (b) {
     case 16: hipLaunchKernelGGL(k_small_eig<16>, dim3(nsub), dim3(64), 0, st, wk.G, wk.M, theta, active); break;
@@ -592,7 +594,7 @@ hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, doub
   hipLaunchKernelGGL(k_ritz_update, dim3(wk.ngroups, nsub), dim3(256), 0, st, U, W, Y, wk.M,
                      theta, voff, nt, b, wk.part, wk.ngroups, active);
   hipLaunchKernelGGL(k_ritz_check, dim3(nsub), dim3(64), 0, st, wk.part, wk.ngroups, theta,
-                     resid, active, b, nev, tau, nev_max, sigma, tol, stl);
+                     resid, active, b, nev, tau, tau_sub, nev_max, sigma, tol, stl);
   return hipGetLastError();
 }
 
@@ -633,10 +635,11 @@ hipError_t launch_cheb(double* Zn, const double* Zc, const double* SZ, const dou
 // m_j and the eigenvalues lam = sigma + 1/theta (ascending), +inf where
 // theta <= 1e-14 theta_max.
 __global__ void k_select(const double* __restrict__ theta, int nsub, int b, int nev, double tau,
-                         int nev_max, double sigma, int* __restrict__ m,
-                         double* __restrict__ lam) {
+                         const double* __restrict__ tau_sub, int nev_max, double sigma,
+                         int* __restrict__ m, double* __restrict__ lam) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsub) return;
+  if (tau_sub) tau = tau_sub[j];
   const double* th = theta + (int64_t)j * b;
   double t0 = th[0];
   int nfin = 0, below = 0;
@@ -652,10 +655,11 @@ __global__ void k_select(const double* __restrict__ theta, int nsub, int b, int 
   m[j] = mj;
 }
 
-hipError_t launch_select(const double* theta, int nsub, int b, int nev, double tau, int nev_max,
-                         double sigma, int* m, double* lam, hipStream_t st) {
+hipError_t launch_select(const double* theta, int nsub, int b, int nev, double tau,
+                         const double* tau_sub, int nev_max, double sigma, int* m, double* lam,
+                         hipStream_t st) {
   hipLaunchKernelGGL(k_select, dim3((nsub + 127) / 128), dim3(128), 0, st, theta, nsub, b, nev,
-                     tau, nev_max, sigma, m, lam);
+                     tau, tau_sub, nev_max, sigma, m, lam);
   return hipGetLastError();
 }
 

@@ -190,17 +190,19 @@ struct EigStall {
   int sweeps;    // 0 disables
   double floor;
 };
+// tau_sub (device, may be NULL): per-subdomain thresholds replacing tau
 hipError_t launch_rr2(double* U, const double* W, double* Y, double* theta, double* resid,
                       int* active, const int* voff, const int* nt, int nsub, int b, int nev,
-                      double tau, int nev_max, double sigma, double tol, const EigWork& wk,
-                      const EigStall& stl, hipStream_t st);
+                      double tau, const double* tau_sub, int nev_max, double sigma, double tol,
+                      const EigWork& wk, const EigStall& stl, hipStream_t st);
 // Chebyshev filter step (see k_cheb): first ? Zn = (2/a) SZ - Zp
 //                                          : Zn = (4/a) SZ - 2 Zc - Zp.
 hipError_t launch_cheb(double* Zn, const double* Zc, const double* SZ, const double* Zp,
                        const double* theta, const int* voff, const int* nt, int nsub, int b,
                        int maxnt, bool first, const int* active, hipStream_t st);
 hipError_t launch_select(const double* theta, int nsub, int b, int nev, double tau,
-                         int nev_max, double sigma, int* m, double* lam, hipStream_t st);
+                         const double* tau_sub, int nev_max, double sigma, int* m, double* lam,
+                         hipStream_t st);
 hipError_t launch_basis(const double* P, const int* voff, int b, const int* sub_ptr,
                         const double* pou, const int* dmap, const int* m, const int* zoff,
                         const int* nd, int nsub, double* Z, hipStream_t st);

@@ -36,6 +36,10 @@ hipError_t dot_partial(const double* x, const double* y, int n, double* partial,
 hipError_t pcg_start(const double* partial, int stage, PcgScalars* sc, int* done, double rtol2,
                      int maxit, hipStream_t st);
 hipError_t residual0(const double* b, const double* q, double* r, int n, hipStream_t st);
+// r = b - A x, each row summed in double-double and rounded once
+hipError_t residual_dd(const geneo_csr_t* A, const double* b, const double* x, double* r,
+                       hipStream_t st);
+hipError_t add_into(double* x, const double* d, int n, hipStream_t st);  // x += d
 hipError_t fill_i32(int* p, int v, int n, hipStream_t st);
 // fused PCG iteration pieces (scalars formed in the consumers)
 // p = z + beta p (pin -> pout), q = A p, p.q partials (npq blocks)

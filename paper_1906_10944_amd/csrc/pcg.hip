@@ -507,6 +507,53 @@ hipError_t residual0(const double* b, const double* q, double* r, int n, hipStre
   return hipGetLastError();
 }
 
+// r = b - A x with each row's sum carried to twice the working precision
+// and rounded once at the end: error-free products (p + e = a x exactly,
+// e by a fused multiply-add) and error-free sums (Knuth's TwoSum) as in
+// the Dot2 algorithm of Ogita, Rump and Oishi ("Accurate sum and dot
+// product", SIAM J. Sci. Comput. 26, 2005).  The explicit _rn operations
+// keep the compiler from contracting the products into the sums.  One
+// thread per row: used a few times per solve, for the residuals of
+// iterative refinement and the reported true residual.
+__global__ __launch_bounds__(256) void k_residual_dd(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = b[i], c = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const double a = val[k], xv = x[col[k]];
+    const double p = __dmul_rn(a, xv);
+    const double ep = fma(a, xv, -p);            // a xv = p + ep
+    const double t = __dadd_rn(s, -p);
+    const double bv = __dsub_rn(t, s);
+    const double es = __dadd_rn(__dsub_rn(s, __dsub_rn(t, bv)), __dsub_rn(-p, bv));  // s - p = t + es
+    s = t;
+    c = __dadd_rn(c, __dsub_rn(es, ep));
+  }
+  r[i] = __dadd_rn(s, c);
+}
+
+hipError_t residual_dd(const geneo_csr_t* A, const double* b, const double* x, double* r,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_dd, dim3((A->n + 255) / 256), dim3(256), 0, st, A->n, A->rowptr,
+                     A->col, A->val, b, x, r);
+  return hipGetLastError();
+}
+
+// x += d
+__global__ void k_add_into(double* __restrict__ x, const double* __restrict__ d, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += d[i];
+}
+
+hipError_t add_into(double* x, const double* d, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_into, dim3((n + 255) / 256), dim3(256), 0, st, x, d, n);
+  return hipGetLastError();
+}
 
 // Fill kernel used instead of memset inside code a caller may capture.
 __global__ void k_fill_i32(int* __restrict__ p, int v, int n) {

@@ -13,7 +13,7 @@ namespace geneo {
 #define Q1_MAXP 128  // maximum parts per axis
 
 struct Q1Geom {
-  int dim, ncomp, nsub, ovl, dirichlet;
+  int dim, ncomp, nsub, ovl, dirichlet, pou;
   int ne[3], nn[3], parts[3];
   double h[3], load[3], vol;
   double wq[8];             // Gauss weight times element volume
@@ -24,6 +24,8 @@ struct Q1Geom {
 
 int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err);
 void q1_sizes(const Q1Geom& g, geneo_q1_sizes_t* s);
+// tau[j] = delta_j / H_j for every subdomain (host): see geneo_q1_thm1_tau
+void q1_thm1_tau(const Q1Geom& g, double* tau);
 hipError_t q1_launch_all(const Q1Geom* dgeom, const Q1Geom& g, const geneo_q1_sizes_t& s,
                          const double* coeff, int* A_rowptr, int* A_col, double* A_val,
                          double* b, int* sub_ptr, int* sub_idx, uint8_t* flags, double* pou,

@@ -21,7 +21,8 @@ __device__ __forceinline__ int64_t nbtotal(int nn) { return nn == 1 ? 1 : 3 * (i
 // (component cb) of element e.
 __device__ double elem_entry(const Q1Geom& g, const double* coeff, int64_t e, int a, int c,
                              int b, int cb) {
-  if (g.ncomp == 1) return coeff[e] * g.kref[a][b];
+  // (rounded product, never fused into the caller's sum)
+  if (g.ncomp == 1) return __dmul_rn(coeff[e], g.kref[a][b]);
   // strain rows fed by displacement component c, with the gradient axis:
   // c=0: (e11,x) (g13,z) (g12,y); c=1: (e22,y) (g23,z) (g12,x); c=2: (e33,z) (g23,y) (g13,x)
   const int srow[3][3] = {{0, 4, 5}, {1, 3, 5}, {2, 3, 4}};
@@ -67,7 +68,8 @@ __device__ __forceinline__ bool node_dirichlet(const Q1Geom& g, const int* x) {
 
 // Value of (row node x, comp c) x (col node y, comp cb) summed over the
 // elements in the element box [blo, bhi) that contain both nodes, and, if
-// ovl_only, whose multiplicity is at least two.
+// ovl_only, whose multiplicity is at least two; the contributions are added
+// in ascending element order, from 0.
 __device__ double pair_value(const Q1Geom& g, const double* coeff, const int* x, int c,
                              const int* y, int cb, const int* blo, const int* bhi,
                              bool ovl_only) {
@@ -103,7 +105,7 @@ __device__ double pair_value(const Q1Geom& g, const double* coeff, const int* x,
           b |= (y[ax] - ee[ax]) << ax;
         }
         int64_t e = ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez);
-        s += elem_entry(g, coeff, e, a, c, b, cb);
+        s = __dadd_rn(s, elem_entry(g, coeff, e, a, c, b, cb));
       }
   return s;
 }
@@ -234,6 +236,44 @@ __device__ __forceinline__ int interior_count(const Q1Geom& g, int ax, int i) {
   return cnt;
 }
 
+// Distance of node coordinate x from the artificial faces of part p along
+// axis ax (those strictly inside the grid), in physical units; +inf if the
+// part has none on this axis.
+__device__ __forceinline__ double axis_art_dist(const Q1Geom& g, int ax, int p, int x) {
+  double d = INFINITY;
+  if (g.elo[ax][p] > 0) d = fmin(d, (x - g.elo[ax][p]) * g.h[ax]);
+  if (g.ehi[ax][p] < g.ne[ax]) d = fmin(d, (g.ehi[ax][p] - x) * g.h[ax]);
+  return d;
+}
+
+// Sarkis weight of box (p[0], p[1], p[2]) at node x: its distance from the
+// box's artificial boundary (the smallest over the axes; 1 for a box
+// without artificial faces) over the sum of the same distance for every box
+// containing x.
+__device__ double sarkis_weight(const Q1Geom& g, const int* p, const int* x) {
+  int plo[3] = {0, 0, 0}, phi[3] = {0, 0, 0};
+  for (int ax = 0; ax < g.dim; ++ax) {
+    plo[ax] = g.parts[ax];
+    phi[ax] = -1;
+    for (int q = 0; q < g.parts[ax]; ++q)
+      if (g.elo[ax][q] <= x[ax] && x[ax] <= g.ehi[ax][q]) {
+        plo[ax] = min(plo[ax], q);
+        phi[ax] = max(phi[ax], q);
+      }
+  }
+  auto dist = [&](int q0, int q1, int q2) {
+    const int q[3] = {q0, q1, q2};
+    double d = INFINITY;
+    for (int ax = 0; ax < g.dim; ++ax) d = fmin(d, axis_art_dist(g, ax, q[ax], x[ax]));
+    return isinf(d) ? 1.0 : d;
+  };
+  double tot = 0.0;
+  for (int q2 = plo[2]; q2 <= phi[2]; ++q2)
+    for (int q1 = plo[1]; q1 <= phi[1]; ++q1)
+      for (int q0 = plo[0]; q0 <= phi[0]; ++q0) tot += dist(q0, q1, q2);
+  return dist(p[0], p[1], p[2]) / tot;
+}
+
 __global__ void k_q1_sublists(const Q1Geom* __restrict__ gp, const int* __restrict__ sub_ptr,
                               int* __restrict__ sub_idx, uint8_t* __restrict__ flags,
                               double* __restrict__ pou) {
@@ -262,9 +302,13 @@ __global__ void k_q1_sublists(const Q1Geom* __restrict__ gp, const int* __restri
     flags[o] = (uint8_t)((!art && !dir ? 1 : 0) | (dir ? 2 : 0));
     double mu = 0.0;
     if (!art && !dir) {
-      int cnt = 1;
-      for (int ax = 0; ax < g.dim; ++ax) cnt *= interior_count(g, ax, x[ax]);
-      mu = 1.0 / (double)cnt;
+      if (g.pou == GENEO_POU_SARKIS) {
+        mu = sarkis_weight(g, p, x);
+      } else {
+        int cnt = 1;
+        for (int ax = 0; ax < g.dim; ++ax) cnt *= interior_count(g, ax, x[ax]);
+        mu = 1.0 / (double)cnt;
+      }
     }
     pou[o] = mu;
   }
@@ -343,6 +387,22 @@ static void axis_ranges(int n, int parts, int ovl, int* elo, int* ehi) {
   }
 }
 
+void q1_thm1_tau(const Q1Geom& g, double* tau) {
+  double hmin = g.h[0];
+  for (int ax = 1; ax < g.dim; ++ax) hmin = fmin(hmin, g.h[ax]);
+  const double delta = 2.0 * g.ovl * hmin;
+  for (int j = 0; j < g.nsub; ++j) {
+    const int p[3] = {j % g.parts[0], (j / g.parts[0]) % g.parts[1],
+                      j / (g.parts[0] * g.parts[1])};
+    double d2 = 0.0;
+    for (int ax = 0; ax < g.dim; ++ax) {
+      const double w = (g.ehi[ax][p[ax]] - g.elo[ax][p[ax]]) * g.h[ax];
+      d2 += w * w;
+    }
+    tau[j] = delta / sqrt(d2);
+  }
+}
+
 int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err) {
   if (!grid) { *err = "grid is NULL"; return GENEO_ERR_ARG; }
   memset(g, 0, sizeof(*g));
@@ -355,6 +415,11 @@ int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err) {
   if (grid->ovl < 1) { *err = "overlap must be at least one element layer"; return GENEO_ERR_ARG; }
   g->ovl = grid->ovl;
   g->dirichlet = grid->dirichlet;
+  if (grid->pou != GENEO_POU_CONSTANT && grid->pou != GENEO_POU_SARKIS) {
+    *err = "unknown partition of unity";
+    return GENEO_ERR_ARG;
+  }
+  g->pou = grid->pou;
   g->nsub = 1;
   double vol = 1.0;
   for (int ax = 0; ax < 3; ++ax) {
@@ -395,12 +460,26 @@ int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err) {
         g->grad[q][a][dax] = v;
       }
   }
+  // Darcy element matrix in closed form (the 2-point rule above is exact
+  // for it): with the 1D stiffness k = +-1 and the 1D mass (1/3, 1/6) =
+  // mi / 6 (mi = 2, 1), K_ab = 6^{1-d} sum_x (prod_{y != x} h_y / h_x)
+  // k(a_x, b_x) prod_{y != x} mi(a_y, b_y); the integer factor is a power
+  // of two, so only the edge-length ratio and the final division round.
   for (int a = 0; a < nv; ++a)
     for (int b = 0; b < nv; ++b) {
       double s = 0.0;
-      for (int q = 0; q < nv; ++q)
-        for (int ax = 0; ax < g->dim; ++ax) s += g->wq[q] * g->grad[q][a][ax] * g->grad[q][b][ax];
-      g->kref[a][b] = s;
+      for (int ax = 0; ax < g->dim; ++ax) {
+        double c = 1.0;
+        for (int o = 0; o < g->dim; ++o)
+          if (o != ax) c = c * g->h[o];
+        c = c / g->h[ax];
+        int f = (((a >> ax) & 1) == ((b >> ax) & 1)) ? 1 : -1;
+        for (int o = 0; o < g->dim; ++o)
+          if (o != ax) f *= (((a >> o) & 1) == ((b >> o) & 1)) ? 2 : 1;
+        const double t = c * (double)f;
+        s = s + t;
+      }
+      g->kref[a][b] = s / (g->dim == 2 ? 6.0 : 36.0);
     }
   return GENEO_OK;
 }

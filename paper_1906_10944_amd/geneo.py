@@ -16,6 +16,8 @@ LIBPATH = os.path.join(_HERE, "libgeneo.so")
 GENEO_OK = 0
 GENEO_PREC_FP64 = 0
 GENEO_PREC_MIXED = 1
+GENEO_POU_CONSTANT = 0
+GENEO_POU_SARKIS = 1
 
 GENEO_ERR_ARG = 1
 GENEO_ERR_OOM = 2
@@ -42,7 +44,7 @@ class GeneoError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int), ("ncomp", C.c_int), ("ne", C.c_int * 3),
                 ("h", C.c_double * 3), ("parts", C.c_int * 3), ("ovl", C.c_int),
-                ("dirichlet", C.c_int), ("load", C.c_double * 3)]
+                ("dirichlet", C.c_int), ("load", C.c_double * 3), ("pou", C.c_int)]
 
 
 class Q1Sizes(C.Structure):
@@ -69,7 +71,8 @@ class Opts(C.Structure):
                 ("sigma", C.c_double), ("precision", C.c_int), ("pivot_tol", C.c_double),
                 ("eig_tol", C.c_double), ("eig_maxit", C.c_int), ("eig_block", C.c_int),
                 ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
-                ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int)]
+                ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int),
+                ("refine", C.c_int), ("refine_rtol", C.c_double), ("tau_sub", C.c_void_p)]
 
 
 class SetupInfo(C.Structure):
@@ -82,7 +85,8 @@ class SetupInfo(C.Structure):
 
 class PcgInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres", C.c_double),
-                ("kappa_est", C.c_double), ("t_solve_ms", C.c_double)]
+                ("kappa_est", C.c_double), ("t_solve_ms", C.c_double), ("refine_iters", C.c_int),
+                ("true_relres", C.c_double)]
 
 
 _lib = None
@@ -96,6 +100,9 @@ def lib():
     if not os.path.exists(LIBPATH):
         raise RuntimeError("libgeneo.so is not built (%s); run "
                            "`python -m paper_1906_10944_amd.build`" % LIBPATH)
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # that the library and torch share devices, streams and memory
+    import torch  # noqa: F401
     L = C.CDLL(LIBPATH)
     vp, i, d, i64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
     L.geneo_strerror.restype = C.c_char_p
@@ -105,6 +112,7 @@ def lib():
     L.geneo_default_opts.argtypes = [C.POINTER(Opts)]
     L.geneo_default_opts.restype = None
     L.geneo_q1_sizes.argtypes = [C.POINTER(Grid), C.POINTER(Q1Sizes)]
+    L.geneo_q1_thm1_tau.argtypes = [C.POINTER(Grid), vp]
     L.geneo_assemble_q1.argtypes = [C.POINTER(Grid)] + [vp] * 13 + [vp]
     L.geneo_setup.argtypes = [C.POINTER(Csr), C.POINTER(Subdomains), C.POINTER(CsrBatch),
                               C.POINTER(CsrBatch), C.POINTER(Opts), vp, C.POINTER(vp)]
@@ -117,7 +125,7 @@ def lib():
     L.geneo_get_local_precision.argtypes = [vp, vp]
     L.pcg_solve.argtypes = [C.POINTER(Csr), vp, vp, vp, i, d, i, C.POINTER(PcgInfo), vp]
     L.geneo_spmv.argtypes = [C.POINTER(Csr), vp, vp, vp]
-    for f in ("geneo_q1_sizes", "geneo_assemble_q1", "geneo_setup", "geneo_apply",
+    for f in ("geneo_q1_sizes", "geneo_q1_thm1_tau", "geneo_assemble_q1", "geneo_setup", "geneo_apply",
               "geneo_get_setup_info", "geneo_get_eigenvalues", "geneo_get_coarse",
               "pcg_solve", "geneo_spmv"):
         getattr(L, f).restype = i
@@ -153,6 +161,7 @@ def grid_from_problem(prob):
     g.ovl, g.dirichlet = prob.ovl, prob.dirichlet
     for c in range(prob.ncomp):
         g.load[c] = prob.load[c]
+    g.pou = GENEO_POU_SARKIS if getattr(prob, "pou", "constant") == "sarkis" else GENEO_POU_CONSTANT
     return g
 
 
@@ -160,6 +169,22 @@ def geneo_q1_sizes(grid):
     s = Q1Sizes()
     _check(lib().geneo_q1_sizes(C.byref(grid), C.byref(s)))
     return {k: int(getattr(s, k)) for k, _ in Q1Sizes._fields_}
+
+
+def geneo_q1_thm1_tau(grid, nsub):
+    """delta_j / H_j of every subdomain (Thm. 1), a float64 array."""
+    t = np.zeros(nsub, dtype=np.float64)
+    _check(lib().geneo_q1_thm1_tau(C.byref(grid), t.ctypes.data))
+    return t
+
+
+def with_tau_sub(opts, tau):
+    """Options using the per-subdomain thresholds ``tau`` (kept alive with the
+    options object until the setup has read them)."""
+    arr = np.ascontiguousarray(tau, dtype=np.float64)
+    opts._tau_keep = arr
+    opts.tau_sub = arr.ctypes.data
+    return opts
 
 
 def geneo_default_opts(**kw):

@@ -92,7 +92,8 @@ class Request:
 class Operator:
     def __init__(self, op_id, prob, sysm, handle, nbytes):
         self.op_id, self.prob, self.sysm, self.handle, self.nbytes = op_id, prob, sysm, handle, nbytes
-        self.lock = threading.Lock()
+        self.lock = threading.Lock()   # one solve at a time on the handle
+        self.pins = 0                  # dispatched repeat requests not yet finished
 
 
 class Server:
@@ -133,11 +134,8 @@ class Server:
             req.result["x"] = x.cpu().numpy()
         return Operator(req.rid, prob, sysm, h, resident_bytes(prob))
 
-    def _run_repeat(self, req, stream):
+    def _run_repeat(self, req, stream, op):
         import torch
-        op = self.resident.get(req.op_id)
-        if op is None:
-            raise RuntimeError("operator %d is not resident" % req.op_id)
         with op.lock, torch.cuda.stream(stream):
             nrhs, n = req.rhs.shape
             b = torch.as_tensor(req.rhs.reshape(-1), dtype=torch.float64, device="cuda")
@@ -152,14 +150,14 @@ class Server:
             req.result["x"] = x.cpu().numpy().reshape(nrhs, n)
         return None
 
-    def _worker(self, req, slot, need):
+    def _worker(self, req, slot, need, pinned):
         t_start = time.perf_counter()
         op = None
         try:
             if req.kind == "new":
                 op = self._run_new(req, self.streams[slot])
             else:
-                self._run_repeat(req, self.streams[slot])
+                self._run_repeat(req, self.streams[slot], pinned)
         except Exception as e:  # recorded, not raised in the worker thread
             self.errors.append((req.rid, repr(e)))
         t_end = time.perf_counter()
@@ -168,6 +166,8 @@ class Server:
         with self.cv:
             self.used -= need
             self.inflight_new.discard(req.rid)
+            if pinned is not None:
+                pinned.pins -= 1
             if op is not None:
                 self.resident[op.op_id] = op
                 self.used += op.nbytes
@@ -178,13 +178,15 @@ class Server:
 
     # --------------------------------------------------------- dispatcher
     def _evict_for(self, need, keep):
-        """Evict the oldest idle resident operators (except those in `keep`,
-        which later requests still use) until `need` fits."""
+        """Evict the oldest idle resident operators until `need` fits: never
+        one pinned by a dispatched repeat request (pins are taken and dropped
+        under self.cv, like this call), nor one in `keep`, which requests not
+        yet dispatched still use."""
         for op_id in list(self.resident):
             if self.used + need <= self.budget:
                 return
             op = self.resident[op_id]
-            if op.lock.locked() or op_id in keep:
+            if op.pins or op_id in keep:
                 continue
             del self.resident[op_id]
             self.used -= op.nbytes
@@ -222,12 +224,16 @@ class Server:
                     if ready and self.free_slots and self.used + need <= self.budget:
                         break
                     self.cv.wait(0.01)
+                pinned = None
                 if not skip:
                     slot = self.free_slots.pop()
                     self.used += need
                     self.peak_used = max(self.peak_used, self.used)
                     if req.kind == "new":
                         self.inflight_new.add(req.rid)
+                    else:
+                        pinned = self.resident[req.op_id]
+                        pinned.pins += 1
             heapq.heappop(pending)
             if req.kind == "repeat":
                 wanted[req.op_id] -= 1
@@ -235,7 +241,7 @@ class Server:
                 self.errors.append((req.rid, "operator %d not available" % req.op_id))
                 continue
             req.result["t_arrival"] = t0 + req.arrival
-            th = threading.Thread(target=self._worker, args=(req, slot, need), daemon=True)
+            th = threading.Thread(target=self._worker, args=(req, slot, need, pinned), daemon=True)
             th.start()
             threads.append(th)
         for th in threads:

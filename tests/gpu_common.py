@@ -71,6 +71,12 @@ def gpu_pcg(h, sysm, rtol=1e-10, maxit=2000):
     return x.cpu().numpy(), info
 
 
+def _sarkis(prob):
+    prob.pou = "sarkis"
+    prob.name += "_sarkis"
+    return prob
+
+
 SMALL_PROBLEMS = {
     "config1": lambda: synth.config1_channels(0),
     "darcy3d_ragged": lambda: synth.darcy_problem(
@@ -85,4 +91,73 @@ SMALL_PROBLEMS = {
     # nev = 24: eigen block of 48 columns
     "layered_wide_block": lambda: synth.layered_2d(n=32, parts=2, ovl=1, layers=4,
                                                    contrast=1e4, nev=24),
+    # the smooth (Sarkis) partition of unity, 2D Darcy and 3D elasticity
+    "sarkis_layered": lambda: _sarkis(synth.layered_2d(n=40, parts=4, ovl=3, layers=8,
+                                                       contrast=1e6, nev=4)),
+    "sarkis_laminate": lambda: _sarkis(synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1),
+                                                              ovl=2, nev=8)),
 }
+
+
+SIGMA = -1e-3
+
+
+def cluster_end(lam, m, rel=1e-6):
+    """Number of leading eigenpairs through the end of the cluster that the
+    cut after m falls into (m itself when the cut has a relative gap)."""
+    e = m
+    while e < len(lam) and np.isfinite(lam[e]) and (lam[e] - lam[e - 1]) <= rel * abs(lam[e]):
+        e += 1
+    return e
+
+
+def kappa_spd(M):
+    """Condition number of a dense SPD matrix (Lanczos on M and on M^{-1}
+    through its Cholesky factor above 2000 rows)."""
+    n = M.shape[0]
+    if n <= 2000:
+        ev = np.linalg.eigvalsh(M)
+        return ev[-1] / ev[0]
+    import scipy.linalg as sla
+    import scipy.sparse.linalg as spla
+    L = np.linalg.cholesky(M)
+    hi = spla.eigsh(M, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+    inv = spla.LinearOperator((n, n), dtype=float, matvec=lambda v: sla.cho_solve((L, True), v))
+    return hi * spla.eigsh(inv, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+
+
+def span_contamination(mu, lam, P, Zg, r_meas, kappa_C, sigma=SIGMA):
+    """Weight of the device's coarse columns Zg (|N_j| x m) outside the
+    oracle's wanted eigenspace, and its a-posteriori bound.
+
+    The oracle's eigenvectors P (all pairs, ascending lam) are C-orthonormal
+    (C = A_N - sigma B), so y_k = G^T p_k are orthonormal eigenvectors of the
+    shift-inverted S = G^{-1} B G^{-T} with nu_k = 1 / (lam_k - sigma).  A
+    device column z = X p / |X p| with p = G^{-T} y is written as
+    z = sum_k d_k X p_k (least squares over the finite pairs, whose X p_k are
+    independent).  The weight of y outside the wanted invariant subspace,
+    extended through the end e of a cluster the cut falls into, is at most
+    (|R| + |dS|) / (nu_e - nu_{e+1}) (Davis-Kahan), with |R| <= sqrt(m) r
+    nu_max for the largest relative Ritz residual r the device measured in
+    its own S, and |dS| <= 10 u kappa(C) nu_max for the difference between
+    that S and the exact one: each side factors C with a backward error of
+    order u |C|, which moves the pencil (B, C) by nu dC, i.e. S by at most
+    nu_max |G^{-1} dC G^{-T}| <= nu_max u kappa(C).  Returns (largest
+    relative weight outside, bound) or None when every finite pair is
+    wanted."""
+    m = Zg.shape[1]
+    fin = np.isfinite(lam)
+    XP = mu[:, None] * P[:, fin]
+    d, *_ = np.linalg.lstsq(XP, Zg, rcond=None)
+    lf = lam[fin]
+    e = cluster_end(lf, m)
+    if e >= len(lf):
+        return None
+    nu = 1.0 / (lf - sigma)
+    gap = nu[e - 1] - nu[e]
+    sv = np.linalg.svd(XP, compute_uv=False)
+    floor = 100 * (np.finfo(float).eps / 2) * sv[0] / sv[-1]
+    u = np.finfo(float).eps / 2
+    bound = 2 * (np.sqrt(m) * max(r_meas, 1e-16) + 10 * u * kappa_C) * nu[0] / gap + floor
+    out = np.linalg.norm(d[e:], axis=0) / np.linalg.norm(d, axis=0)
+    return float(out.max()), float(bound)

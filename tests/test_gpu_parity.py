@@ -1,16 +1,31 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerances: assembly and index work are exact or within a few ulps of the
-summation order (1e-13 relative); FP64 solver results within 1e-12 for the
-one-level operator, 1e-8 relative for eigenvalues, solutions and the
-two-level operator, PCG iterations within +-2 of the oracle.
+Tolerances:
+* assembly and index work: exact, or within a few ulps of the summation
+  order (1e-13 relative);
+* one-level operator: 10 u kappa of the scaled local matrices (both sides
+  solve with backward-stable FP64 factors), normwise and element-wise;
+* eigenvalues: 1e-8 relative;
+* coarse basis: each device column, written in the oracle's C-orthonormal
+  eigenvectors (C = A_N - sigma B), has no more weight outside the selected
+  eigenspace (extended through the end of a cluster the cut splits) than
+  the device's measured Ritz residual over the measured gap allows
+  (Davis-Kahan in the shift-inverted operator);
+* two-level operator: the oracle's formula (Def. 2) evaluated with the
+  device's basis, to the rounding of the two solves (10 u kappa);
+* PCG: solution within 1e-8 relative (normwise and element-wise) of the
+  oracle's at a 1e-10 residual reduction, and iterations within +-2, for
+  the FP64 and the mixed form; and the solutions after two refinement
+  steps (residuals in double-double / extended precision) within 1e-8 of
+  each other too.
 """
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
 from gpu_common import (SMALL_PROBLEMS, csr_to_scipy, gpu_apply, gpu_assemble, gpu_pcg,
-                        gpu_setup, local_dense, need_gpu, say)
+                        gpu_setup, kappa_spd, local_dense, need_gpu, say,
+                        span_contamination)
 from oracle import decomp, fem, geneo, pcg
 
 pytestmark = pytest.mark.gpu
@@ -28,10 +43,16 @@ def case(request):
 
 
 def test_assembly_global(case):
+    """Both sides sum every entry's element contributions in ascending
+    element order from the same closed-form Darcy element matrix: the Darcy
+    matrices agree bit for bit; the elasticity ones (quadrature on both
+    sides, different operation orders) to rounding."""
     name, prob, A, b, subs, sysm = case
     n = prob.ndof
     Ag = csr_to_scipy(sysm.A_rowptr, sysm.A_col, sysm.A_val, n)
     scale = abs(A).max()
+    if prob.ncomp == 1:
+        assert abs(Ag - A).max() == 0.0
     assert abs(Ag - A).max() <= 1e-13 * scale
     assert np.allclose(sysm.b.cpu().numpy(), b, rtol=1e-14, atol=1e-14 * abs(b).max())
     rp = sysm.A_rowptr.cpu().numpy()
@@ -61,8 +82,9 @@ def test_local_matrices(case):
     for s in subs[:: max(1, len(subs) // 6)]:
         AN, Ao = geneo.local_matrices(prob, s)
         scale = np.abs(AN).max()
-        assert np.abs(local_dense(sysm, s.j, "an") - AN).max() <= 1e-13 * scale
-        assert np.abs(local_dense(sysm, s.j, "ao") - Ao).max() <= 1e-13 * scale
+        tol = 0.0 if prob.ncomp == 1 else 1e-13 * scale
+        assert np.abs(local_dense(sysm, s.j, "an") - AN).max() <= tol
+        assert np.abs(local_dense(sysm, s.j, "ao") - Ao).max() <= tol
 
 
 @pytest.fixture(scope="module")
@@ -101,14 +123,11 @@ def test_one_level_apply(case):
     # scaled matrices: each forward error is O(u kappa), so they may differ
     # by that much (10 u kappa, floor 1e-12)
     tol = max(1e-12, 10 * np.finfo(float).eps / 2 * _kappa_local(A, subs))
-    say("[one-level] rel diff %.3e tol %.3e" % (np.linalg.norm(z - zo) / np.linalg.norm(zo), tol))
+    mx = np.abs(z - zo).max() / np.abs(zo).max()
+    say("[one-level] rel diff %.3e max-abs %.3e tol %.3e" %
+        (np.linalg.norm(z - zo) / np.linalg.norm(zo), mx, tol))
     assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
-
-
-def _cut_gap(lam, m):
-    if m == 0 or m >= len(lam) or not np.isfinite(lam[m]):
-        return np.inf
-    return (lam[m] - lam[m - 1]) / max(abs(lam[m]), 1e-300)
+    assert mx <= tol
 
 
 def test_eigenvalues(case, solved):
@@ -123,121 +142,158 @@ def test_eigenvalues(case, solved):
             assert lam[j, c] == pytest.approx(lo[c], rel=1e-8, abs=1e-11), (j, c)
 
 
-def test_coarse_matrix_is_galerkin_product(case, solved):
-    name, prob, A, b, subs, sysm = case
-    g, h, info = solved
+def _gpu_basis(h, subs, nc):
+    """Device coarse basis as dense blocks over N_j, and as a global sparse Z."""
     from paper_1906_10944_amd import geneo as G
     zoff, z, ah = G.geneo_get_coarse(h, len(subs))
-    nc = info["nc"]
-    if nc == 0:
-        return
-    cols, off = [], 0
-    rows, cidx, vals = [], [], []
     m, _ = G.geneo_get_eigenvalues(h, len(subs))
+    blocks, rows, cidx, vals, off = [], [], [], [], 0
     for s in subs:
-        mj = m[s.j]
+        mj = int(m[s.j])
         blk = z[zoff[s.j]:zoff[s.j + 1]].reshape(len(s.dofs), mj)
+        blocks.append(blk)
         r_, c_ = np.nonzero(blk)
         rows.append(s.dofs[r_])
         cidx.append(c_ + off)
         vals.append(blk[r_, c_])
         off += mj
-    Z = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cidx))),
-                      shape=(prob.ndof, nc))
+    return blocks, rows, cidx, vals, ah, m
+
+
+def _zsparse(prob, rows, cidx, vals, nc):
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cidx))),
+                         shape=(prob.ndof, nc))
+
+
+def test_coarse_matrix_is_galerkin_product(case, solved):
+    name, prob, A, b, subs, sysm = case
+    g, h, info = solved
+    nc = info["nc"]
+    if nc == 0:
+        return
+    blocks, rows, cidx, vals, ah, m = _gpu_basis(h, subs, nc)
+    Z = _zsparse(prob, rows, cidx, vals, nc)
     AH = (Z.T @ (A @ Z)).toarray()
     assert np.abs(ah - AH).max() <= 1e-12 * np.abs(AH).max()
     # columns unit l2 and supported on D_j
     assert np.allclose(np.sqrt(np.asarray(Z.multiply(Z).sum(axis=0))).ravel(), 1.0, rtol=1e-12)
-    # span agrees with the oracle's wherever the cut is not degenerate; the
-    # angle between the spans is bounded by (Ritz residual)/(gap) in the
-    # shift-inverted problem, nu = 1/(lam - sigma), residual <= eig_tol * nu_1
-    Zo = g.Z.toarray()
-    eig_tol, sigma = 1e-10, -1e-3
-    off = 0
-    for s in subs:
-        mj = m[s.j]
-        lo = g.lam[s.j]
-        if mj and _cut_gap(lo, mj) > 1e-6:
-            bound = _span_bound(lo, mj, eig_tol, sigma) + 1e-10
-            Zg = Z[:, off:off + mj].toarray()
-            Zoj = Zo[:, off:off + mj]
-            Q, _ = np.linalg.qr(Zg)
-            err = np.linalg.norm(Zoj - Q @ (Q.T @ Zoj)) / np.linalg.norm(Zoj)
-            assert err <= bound, (s.j, err, bound)
-        off += mj
+    for s, blk in zip(subs, blocks):
+        assert np.all(blk[~s.dmask] == 0.0)
 
 
-def _span_bound(lam, m, eig_tol=1e-10, sigma=-1e-3):
-    """Heuristic angle bound between computed and exact span of the first m
-    basis vectors: Ritz residual over the gap in the shift-inverted problem
-    (Davis-Kahan), with a factor 100 for sqrt(m) and for the change of
-    variables p = G^{-T} y, z = X p."""
-    if m == 0 or m >= len(lam) or not np.isfinite(lam[m]):
-        return 1e-12
-    nu = 1.0 / (np.asarray(lam[:m + 1]) - sigma)
-    return 100 * eig_tol * nu[0] / (nu[m - 1] - nu[m])
+def test_coarse_basis_spans_geneo_eigenspace(case, solved):
+    """Def. 4 with the shift-invert solve of Sec. 4.4: every device column
+    lies in X times the oracle's wanted eigenspace (through the end of a
+    cluster the cut splits) up to the measured Ritz residual over the gap
+    (``gpu_common.span_contamination``)."""
+    name, prob, A, b, subs, sysm = case
+    g, h, info = solved
+    nc = info["nc"]
+    if nc == 0:
+        return
+    blocks, *_ = _gpu_basis(h, subs, nc)
+    worst = 0.0
+    for s, blk in zip(subs, blocks):
+        if blk.shape[1] == 0:
+            continue
+        AN, Ao = geneo.local_matrices(prob, s)
+        kC = kappa_spd(AN + 1e-3 * (s.mu[:, None] * Ao * s.mu[None, :]))
+        res = span_contamination(s.mu, g.lam[s.j], g.eigvecs[s.j], blk, info["eig_max_resid"], kC)
+        if res is None:
+            continue
+        out, bound = res
+        worst = max(worst, out / bound)
+        assert out <= bound, (s.j, blk.shape[1], out, bound)
+    say("[span]", name, "r_meas %.2e worst fraction of bound %.3f" % (info["eig_max_resid"], worst))
+
+
+def _cond(M):
+    ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+    return ev[-1] / ev[0]
 
 
 def test_two_level_apply(case, solved):
+    """M^{-1} r = R_H^T A_H^{-1} R_H r + sum_j R_j^T A_j^{-1} R_j r (Def. 2),
+    the oracle's formula evaluated with the device's coarse basis (whose
+    span is checked above).  Both sides solve with backward-stable FP64
+    factors (the device with explicit symmetric inverses), so the parts
+    differ by 10 u kappa of their matrices."""
     name, prob, A, b, subs, sysm = case
     g, h, info = solved
-    degenerate = any(_cut_gap(l, mm) <= 1e-6 for l, mm in zip(g.lam, g.m))
+    nc = info["nc"]
     rng = np.random.Generator(np.random.PCG64(12))
     r = rng.normal(size=prob.ndof)
     z = gpu_apply(h, sysm, r)
-    zo = g.apply(r)
-    bound = max(_span_bound(l, mm) for l, mm in zip(g.lam, g.m))
-    tol = 1e-3 if degenerate else max(1e-9, 10 * bound)
-    say("[two-level apply]", name, "rel diff", np.linalg.norm(z - zo) / np.linalg.norm(zo),
-        "tol", tol)
-    assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
+    u = np.finfo(float).eps / 2
+    z1 = g.apply_one_level(r)
+    zc = np.zeros_like(z1)
+    kH = 1.0
+    if nc:
+        _, rows, cidx, vals, ah, m = _gpu_basis(h, subs, nc)
+        Z = _zsparse(prob, rows, cidx, vals, nc)
+        AH = (Z.T @ (A @ Z)).toarray()
+        AH = 0.5 * (AH + AH.T)
+        zc = Z @ np.linalg.solve(AH, Z.T @ r)
+        kH = _cond(AH)
+    zo = z1 + zc
+    kl = _kappa_local(A, subs)
+    tol_abs = 10 * u * (kl * np.linalg.norm(z1) + kH * np.linalg.norm(zc)) \
+        + 1e-13 * np.linalg.norm(zo)
+    diff = np.linalg.norm(z - zo)
+    say("[two-level apply] %s rel diff %.3e tol %.3e (kappa_loc %.2e kappa_H %.2e) "
+        "max-abs %.3e" % (name, diff / np.linalg.norm(zo), tol_abs / np.linalg.norm(zo), kl, kH,
+                          np.abs(z - zo).max() / np.abs(zo).max()))
+    assert tol_abs <= 1e-6 * np.linalg.norm(zo)
+    assert diff <= tol_abs
+    assert np.abs(z - zo).max() <= tol_abs / np.linalg.norm(zo) * np.abs(zo).max()
     # symmetry of the operator the GPU applies
     y = rng.normal(size=prob.ndof)
     zy = gpu_apply(h, sysm, y)
     assert abs(y @ z - r @ zy) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(z) * 10
 
 
-def _lam_min(A):
-    import scipy.sparse.linalg as spla
-    if A.shape[0] <= 6000:
-        return np.linalg.eigvalsh(A.toarray())[0]
-    return spla.eigsh(A.tocsc(), k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
-
-
-def _check_solution(prob, A, b, sysm, h, apply_ref, tag):
-    """Iterations within +-2 and solution within 1e-8 of the oracle at a
-    1e-10 residual reduction, where the problem's conditioning determines
-    the solution that well.  Two solutions x_g (of the device system A_g,
-    b_g) and x_o (of A, b) with residuals r_g, r_o differ by at most
-    (|r_g| + |r_o| + |A_g - A| |x| + |b_g - b|) / lambda_min(A); the
-    tolerance is max(1e-8 |x_o|, that bound)."""
+def _check_solution(prob, A, b, sysm, h, apply_ref, tag, precision):
+    """At a 1e-10 residual reduction: iterations within +-2 of the oracle's
+    and the solution within 1e-8 relative (2-norm and max-abs) of the
+    oracle's.  Then with two refinement steps on both sides (residuals in
+    double-double on the device, in extended precision in the oracle): the
+    refined solutions within 1e-8 as well, which holds whatever the
+    conditioning of A (a plain FP64 solve is only accurate to about
+    u kappa(A))."""
     x, inf = gpu_pcg(h, sysm, rtol=1e-10)
     ref = pcg.pcg(A, b, apply_ref, rtol=1e-10)
     say("[pcg %s]" % tag, prob.name, "gpu it", inf["iters"], "oracle it", ref.iters,
         "kappa", inf["kappa_est"], pcg.kappa_estimate(ref.alphas, ref.betas))
     assert inf["converged"]
+    assert abs(inf["iters"] - ref.iters) <= 2
     Ag = csr_to_scipy(sysm.A_rowptr, sysm.A_col, sysm.A_val, prob.ndof)
     bg = sysm.b.cpu().numpy()
-    rg = np.linalg.norm(bg - Ag @ x)
-    ro = np.linalg.norm(b - A @ ref.x)
     fro = np.sqrt((Ag.multiply(Ag)).sum())
     # the device residual is the recurrence's, up to the rounding floor of A x
-    assert rg <= 2e-10 * np.linalg.norm(bg) + 1e-15 * fro * np.linalg.norm(x)
-    nx = np.linalg.norm(ref.x)
-    dA = (Ag - A)
-    dA = np.sqrt((dA.multiply(dA)).sum())
-    bound = (rg + ro + dA * nx + np.linalg.norm(bg - b)) / _lam_min(A)
-    diff = np.linalg.norm(x - ref.x)
-    say("   rel diff %.2e  bound %.2e" % (diff / nx, bound / nx))
-    assert diff <= max(1e-8 * nx, 1.01 * bound)
+    assert np.linalg.norm(bg - Ag @ x) <= 2e-10 * np.linalg.norm(bg) + 1e-15 * fro * np.linalg.norm(x)
+    x_ref = pcg.refine(A, b, ref.x, lambda r: pcg.pcg(A, r, apply_ref, rtol=1e-6).x, steps=2)
+    h2 = gpu_setup(sysm, prob, precision=precision, refine=2)
+    xr, infr = gpu_pcg(h2, sysm, rtol=1e-10)
+    h2.close()
+    assert infr["iters"] == inf["iters"]
+    out = {}
+    for key, xg, xo in (("plain", x, ref.x), ("refined", xr, x_ref)):
+        nx = np.linalg.norm(xo)
+        diff = np.linalg.norm(xg - xo) / nx
+        mx = np.abs(xg - xo).max() / np.abs(xo).max()
+        out[key] = (diff, mx)
+    say("   plain: rel diff %.2e max-abs %.2e | refined (+%d its): rel diff %.2e max-abs %.2e "
+        "| plain vs refined oracle %.2e" % (out["plain"] + (infr["refine_iters"],) + out["refined"]
+                                           + (np.linalg.norm(ref.x - x_ref) / np.linalg.norm(x_ref),)))
+    for key in out:
+        assert out[key][0] <= 1e-8 and out[key][1] <= 1e-8, (key, out[key])
     return inf, ref
 
 
 def test_pcg_fp64(case, solved):
     name, prob, A, b, subs, sysm = case
     g, h, info = solved
-    inf, ref = _check_solution(prob, A, b, sysm, h, g.apply, "fp64")
-    assert abs(inf["iters"] - ref.iters) <= 2
+    _check_solution(prob, A, b, sysm, h, g.apply, "fp64", 0)
 
 
 def test_pcg_mixed(case):
@@ -247,5 +303,4 @@ def test_pcg_mixed(case):
     from paper_1906_10944_amd import geneo as G
     info = G.geneo_get_setup_info(h)
     say("[mixed] fallback subdomains", info["fallback_fp64"])
-    inf, ref = _check_solution(prob, A, b, sysm, h, g.apply, "mixed")
-    assert inf["iters"] <= ref.iters + 4
+    _check_solution(prob, A, b, sysm, h, g.apply, "mixed", 1)

@@ -78,3 +78,59 @@ def test_oversized_request_is_rejected():
     with pytest.raises(RuntimeError):
         srv.run(_stream(0.0)[:1])
     srv.close()
+
+
+def test_served_solutions_match_oracle():
+    """Each new-problem request's solution against the FP64 oracle's (setup
+    and PCG to 1e-10 on the CPU): iterations within +-2, solution within
+    1e-8 relative; each repeat solve's solutions converge."""
+    need_gpu()
+    from oracle import fem, geneo, pcg
+    out, stats, errors = _run(slots=3, t_scale=0.0)
+    assert not errors
+    for r in _stream(0.0):
+        res = out[r.rid]
+        if r.kind != "new":
+            assert res["converged"]
+            continue
+        p = r.problem
+        A, b = fem.assemble(p)
+        g = geneo.setup(p, A=A)
+        ref = pcg.pcg(A, b, g.apply, rtol=p.rtol)
+        err = np.linalg.norm(res["x"] - ref.x) / np.linalg.norm(ref.x)
+        say("[serve oracle] %s it %d oracle %d rel err %.2e" % (p.name, res["iters"], ref.iters,
+                                                               err))
+        assert abs(res["iters"] - ref.iters) <= 2
+        assert err <= 1e-8
+
+
+def test_eviction_with_interleaved_repeats():
+    """Repeat solves interleaved with new problems under a budget that holds
+    one resident operator and a setup at a time: operators are evicted
+    while later requests still come, and none that a dispatched or a
+    pending repeat needs (pinned at dispatch, kept while wanted)."""
+    need_gpu()
+    import synth
+    from paper_1906_10944_amd.serve import Request, Server, footprint_bytes, resident_bytes
+    rng = np.random.Generator(np.random.PCG64(17))
+    probs = [synth.config2_grf(seed=20 + k, n=64, parts=2, ovl=2, inclusions=2) for k in range(4)]
+    reqs, rid = [], 0
+    for k, p in enumerate(probs):
+        reqs.append(Request(0.0, rid, "new", problem=p))
+        src = rid
+        rid += 1
+        for _ in range(2):
+            reqs.append(Request(0.0, rid, "repeat", problem=p, op_id=src,
+                                rhs=rng.normal(size=(2, p.ndof))))
+            rid += 1
+    budget = int(footprint_bytes(probs[0]) + 1.5 * resident_bytes(probs[0]))
+    srv = Server(budget, slots=3)
+    stats = srv.run(reqs)
+    evicted = [k for k in range(len(probs)) if reqs[3 * k].rid not in srv.resident]
+    srv.close()
+    say("[serve eviction] budget", budget, stats, "evicted operators", evicted)
+    assert stats["errors"] == 0 and stats["requests"] == len(reqs)
+    assert stats["peak_bytes"] <= budget
+    assert len(evicted) >= 2
+    for r in reqs:
+        assert np.all(r.result["converged"]), r.rid
