@@ -351,6 +351,28 @@ int pcg_solve(const geneo_csr_t* A, geneo_handle_t M, const double* b,
               double* x, int nrhs, double rtol, int maxit,
               geneo_pcg_info_t* info, void* stream);
 
+/*
+ * pcg_solve without any allocation, for callers that cannot allocate device
+ * memory during the solve (tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, semantics and results as pcg_solve (the
+ * same kernels in the same order), with these differences:
+ *  - the PCG vectors, the refinement correction and residual, partial
+ *    sums, scalars and coefficient records live in one fixed device array
+ *    of the library (56.1 MiB per GPU, held from the first call on that GPU
+ *    until the process ends) instead of buffers the handle allocates; no
+ *    hipMalloc, hipFree, pinned allocation, event or graph is created;
+ *  - limits: n <= 1048576 and maxit <= 4096, else GENEO_ERR_ARG;
+ *  - the iterations run directly on `stream`, without graph capture, and
+ *    the host reads the done flag every 8 iterations, so the call is not
+ *    capturable itself;
+ *  - every call on one GPU shares that array, and it keeps the last call's
+ *    contents: calls that overlap on one GPU (any handles, any streams)
+ *    race and must be serialised by the caller.
+ */
+int pcg_solve_noalloc(const geneo_csr_t* A, geneo_handle_t M, const double* b,
+                      double* x, int nrhs, double rtol, int maxit,
+                      geneo_pcg_info_t* info, void* stream);
+
 /* y = A x with the library's CSR kernel (device arrays). */
 int geneo_spmv(const geneo_csr_t* A, const double* x, double* y, void* stream);
 

@@ -457,7 +457,8 @@ SymvArgs symv_args(const geneo_handle_s* h, bool rev) {
 // Device work of one PCG solve: the vectors r, z, the two alternating p
 // buffers and q, the partial sums of the reductions, the scalars and the
 // done flag, and the alpha / beta records of the Lanczos estimate (cap + 1
-// entries each), held by the handle.
+// entries each).  Held by the handle (pcg_solve) or carved from the
+// library's fixed device array (pcg_solve_noalloc).
 struct PcgWork {
   double *r, *z, *p, *p2, *q, *partial, *rr_part, *alphas, *betas;
   PcgScalars* sc;
@@ -1722,6 +1723,95 @@ int finish(int code, const std::string& msg) {
   return code;
 }
 
+// ------------------------------------------------- allocation-free solve
+// The work of pcg_solve_noalloc lives in one fixed device array per GPU,
+// laid out as: r, z, p, p2, q, the refinement correction d and residual
+// (kNoallocMaxN doubles each), the partial sums (PCG_NB_SPMV, then PCG_NB),
+// the alpha and beta records (kNoallocMaxIt + 1 each), the scalars and the
+// done flag; every piece starts on a 256-byte boundary.  56.1 MiB in all.
+constexpr int kNoallocMaxN = 1 << 20;
+constexpr int kNoallocMaxIt = 4096;
+constexpr int64_t kAlign = 32;  // doubles
+constexpr int64_t al_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+constexpr int64_t kOffPartial = 7 * (int64_t)kNoallocMaxN;
+constexpr int64_t kOffRr = kOffPartial + al_up(PCG_NB_SPMV > PCG_NB ? PCG_NB_SPMV : PCG_NB);
+constexpr int64_t kOffAlpha = kOffRr + al_up(PCG_NB);
+constexpr int64_t kOffBeta = kOffAlpha + al_up(kNoallocMaxIt + 1);
+constexpr int64_t kOffSc = kOffBeta + al_up(kNoallocMaxIt + 1);
+constexpr int64_t kOffDone = kOffSc + al_up((sizeof(PcgScalars) + 7) / 8);
+constexpr int64_t kScratchDoubles = kOffDone + kAlign;
+
+}  // namespace
+
+// file scope: its device address is taken once per device (below)
+static __device__ __align__(256) double pcg_scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of pcg_scratch on the current device, looked up once per
+// device with that device current (each device holds its own copy).
+double* scratch_on_current_device() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(GENEO_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(pcg_scratch)));
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+// alpha / beta records and the Lanczos tridiagonal of the last solve, per
+// host thread (no host allocation during the solve)
+thread_local double t_noalloc_ab[2 * (kNoallocMaxIt + 1)];
+thread_local double t_noalloc_de[2 * (kNoallocMaxIt + 1)];
+thread_local double t_noalloc_part[PCG_NB];
+
+// PCG without graphs, on the caller's stream: chunks of PCG_CHUNK
+// iterations are enqueued and the done flag is read after each, so past
+// convergence at most one chunk of launches finds done set.  The launches
+// are those of pcg_one in the same order, hence the same results.  The
+// correction mode iterates on d (from 0) and adds it to x at the end.
+void pcg_one_noalloc(geneo_handle_s* h, const geneo_csr_t* A, const double* b, double* x,
+                     double rtol, int maxit, geneo_pcg_info_t* info, const PcgWork& w,
+                     hipStream_t st, double* d = nullptr) {
+  const double t0 = now_ms();
+  double* xi = x;
+  if (d) {
+    HIPCHK(hipMemsetAsync(d, 0, (size_t)h->n * sizeof(double), st));
+    xi = d;
+  }
+  pcg_enqueue_start(h, A, b, xi, rtol, maxit, w, st);
+  int it = 0;
+  PcgScalars hs{};
+  int hdone = 0;
+  for (;;) {
+    for (int k = 0; k < PCG_CHUNK; ++k) pcg_enqueue_iteration(h, A, xi, w, it++, st);
+    HIPCHK(hipMemcpyAsync(&hdone, w.done, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hdone || it >= maxit + PCG_CHUNK) break;
+  }
+  if (d) HIPCHK(add_into(x, d, h->n, st));
+  HIPCHK(hipMemcpyAsync(&hs, w.sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+  const int nab = std::min(maxit + 1, kNoallocMaxIt + 1);
+  HIPCHK(hipMemcpyAsync(t_noalloc_ab, w.alphas, nab * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(t_noalloc_ab + kNoallocMaxIt + 1, w.betas, nab * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  info->iters = hs.iters;
+  info->converged = hs.converged;
+  info->relres = hs.bb > 0 ? sqrt(hs.rr / hs.bb) : 0.0;
+  info->kappa_est = kappa_from_cg(t_noalloc_ab, t_noalloc_ab + kNoallocMaxIt + 1, hs.iters,
+                                  t_noalloc_de, t_noalloc_de + kNoallocMaxIt + 1);
+  info->t_solve_ms = now_ms() - t0;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1993,6 +2083,56 @@ int pcg_solve(const geneo_csr_t* A, geneo_handle_t h, const double* b, double* x
     HIPCHK(hipEventRecord(ev, h->hs));
     HIPCHK(hipStreamWaitEvent(us, ev, 0));
     HIPCHK(hipEventDestroy(ev));
+    if (rc) return finish(rc, "PCG did not converge within maxit");
+    return GENEO_OK;
+  } catch (Err& e) {
+    return finish(e.code, e.msg);
+  }
+}
+
+int pcg_solve_noalloc(const geneo_csr_t* A, geneo_handle_t h, const double* b, double* x,
+                      int nrhs, double rtol, int maxit, geneo_pcg_info_t* info, void* stream) {
+  try {
+    check_csr(A);
+    if (!h || !b || !x || !info || nrhs < 1 || maxit < 1 || !(rtol > 0))
+      fail(GENEO_ERR_ARG, "invalid pcg arguments");
+    if (A->n != h->n) fail(GENEO_ERR_ARG, "matrix size differs from the preconditioner's");
+    if (h->n > kNoallocMaxN || maxit > kNoallocMaxIt)
+      fail(GENEO_ERR_ARG, "pcg_solve_noalloc is limited to n <= " +
+                              std::to_string(kNoallocMaxN) + " and maxit <= " +
+                              std::to_string(kNoallocMaxIt) + " (got n = " +
+                              std::to_string(h->n) + ", maxit = " + std::to_string(maxit) + ")");
+    hipStream_t st = (hipStream_t)stream;
+    double* s0 = scratch_on_current_device();
+    PcgWork w;
+    w.r = s0;
+    w.z = s0 + kNoallocMaxN;
+    w.p = s0 + 2 * (int64_t)kNoallocMaxN;
+    w.p2 = s0 + 3 * (int64_t)kNoallocMaxN;
+    w.q = s0 + 4 * (int64_t)kNoallocMaxN;
+    w.partial = s0 + kOffPartial;
+    w.rr_part = s0 + kOffRr;
+    w.alphas = s0 + kOffAlpha;
+    w.betas = s0 + kOffBeta;
+    w.sc = (PcgScalars*)(s0 + kOffSc);
+    w.done = (int*)(s0 + kOffDone);
+    w.cap = kNoallocMaxIt + 1;
+    double* dvec = s0 + 5 * (int64_t)kNoallocMaxN;
+    double* rvec = s0 + 6 * (int64_t)kNoallocMaxN;
+    int rc = GENEO_OK;
+    for (int k = 0; k < nrhs; ++k) {
+      const double* bk = b + (int64_t)k * h->n;
+      double* xk = x + (int64_t)k * h->n;
+      const double t0 = now_ms();
+      pcg_one_noalloc(h, A, bk, xk, rtol, maxit, &info[k], w, st);
+      if (!info[k].converged) rc = GENEO_ERR_MAXIT;
+      refine_solution(h, A, bk, xk, rvec, &info[k], st,
+                      [&](const double* rb, double* xx, double rt, geneo_pcg_info_t* ci) {
+                        pcg_one_noalloc(h, A, rb, xx, rt, maxit, ci, w, st, dvec);
+                      });
+      info[k].true_relres = true_relres(A, bk, xk, rvec, w.partial, t_noalloc_part, st);
+      info[k].t_solve_ms = now_ms() - t0;
+    }
     if (rc) return finish(rc, "PCG did not converge within maxit");
     return GENEO_OK;
   } catch (Err& e) {

@@ -124,10 +124,11 @@ def lib():
     L.geneo_get_coarse.argtypes = [vp, vp, vp, i64, vp]
     L.geneo_get_local_precision.argtypes = [vp, vp]
     L.pcg_solve.argtypes = [C.POINTER(Csr), vp, vp, vp, i, d, i, C.POINTER(PcgInfo), vp]
+    L.pcg_solve_noalloc.argtypes = [C.POINTER(Csr), vp, vp, vp, i, d, i, C.POINTER(PcgInfo), vp]
     L.geneo_spmv.argtypes = [C.POINTER(Csr), vp, vp, vp]
     for f in ("geneo_q1_sizes", "geneo_q1_thm1_tau", "geneo_assemble_q1", "geneo_setup", "geneo_apply",
               "geneo_get_setup_info", "geneo_get_eigenvalues", "geneo_get_coarse",
-              "pcg_solve", "geneo_spmv"):
+              "pcg_solve", "pcg_solve_noalloc", "geneo_spmv"):
         getattr(L, f).restype = i
     _lib = L
     return L
@@ -348,6 +349,17 @@ def pcg_solve(A, handle, b, x, rtol=1e-10, maxit=2000, nrhs=1, stream=None, chec
     infos = (PcgInfo * nrhs)()
     rc = lib().pcg_solve(C.byref(A), handle.value, _ptr(b), _ptr(x), nrhs, rtol, maxit, infos,
                          _stream(stream))
+    out = [{k: getattr(inf, k) for k, _ in PcgInfo._fields_} for inf in infos]
+    if check and rc not in (GENEO_OK,):
+        _check(rc)
+    return out if nrhs > 1 else out[0]
+
+
+def pcg_solve_noalloc(A, handle, b, x, rtol=1e-10, maxit=2000, nrhs=1, stream=None, check=True):
+    """pcg_solve with the library's fixed device work array (no allocation)."""
+    infos = (PcgInfo * nrhs)()
+    rc = lib().pcg_solve_noalloc(C.byref(A), handle.value, _ptr(b), _ptr(x), nrhs, rtol, maxit,
+                                 infos, _stream(stream))
     out = [{k: getattr(inf, k) for k, _ in PcgInfo._fields_} for inf in infos]
     if check and rc not in (GENEO_OK,):
         _check(rc)
