@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-nested", action="store_true",
                     help="skip the nested 512^2 workload and serving objects")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--eig-tol", type=float, default=None,
+                    help="eigen residual tolerance (default: the library's)")
     ap.add_argument("--serve", action="store_true",
                     help="only the serving benchmark: a seeded Poisson stream of new problems "
                          "and repeat solves through serve.Server; prints one JSON line with "
@@ -79,11 +81,12 @@ def make_problem(name, seed):
 class Runner:
     """Holds the resident input and runs steps through the C ABI."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, **extra):
         import torch
         from paper_1906_10944_amd import geneo as G
         self.G = G
         self.prob = prob
+        self.extra = extra   # further setup options
         self.grid = G.grid_from_problem(prob)
         self.coeff = torch.as_tensor(prob.coeff, dtype=torch.float64).cuda().contiguous()
         self.xbuf = None
@@ -94,7 +97,7 @@ class Runner:
         import torch
         G = self.G
         sysm = G.geneo_assemble_q1(self.grid, self.coeff)
-        opts = G.opts_from_problem(self.prob, precision=precision)
+        opts = G.opts_from_problem(self.prob, precision=precision, **self.extra)
         h = G.geneo_setup(sysm.csr(), sysm.subdomains(), sysm.neumann(), sysm.overlap(), opts)
         # the solution vector is the caller's: one buffer for all steps,
         # zeroed (x0 = 0) at the start of each
@@ -160,11 +163,14 @@ def err_vs_oracle(prob, seed, x, iters):
     if not os.path.exists(path):
         return None
     g = np.load(path)
-    xo = g["x"]
+    xr, xo = g["x_ref"], g["x"]
     if xo.shape != x.shape:
         return None
-    return {"rel_l2": float(np.linalg.norm(x - xo) / np.linalg.norm(xo)),
-            "rel_max_abs": float(np.abs(x - xo).max() / np.abs(xo).max()),
+    return {"rel_l2": float(np.linalg.norm(x - xr) / np.linalg.norm(xr)),
+            "rel_max_abs": float(np.abs(x - xr).max() / np.abs(xr).max()),
+            "rel_l2_vs_oracle_pcg": float(np.linalg.norm(x - xo) / np.linalg.norm(xo)),
+            "reference": "the oracle's PCG solution refined twice with extended-precision "
+                         "residuals (rel_l2_vs_oracle_pcg: against its plain PCG solution)",
             "iters": iters, "oracle_iters": int(g["iters"]),
             "oracle_kappa": float(g["kappa"]), "oracle_nc": int(g["nc"])}
 
@@ -228,6 +234,8 @@ def prof_symbol(name, info):
         b, bwd = info.get("eig_block", 32), name == "trsm_bwd"
         if b <= 32:
             return "k_trsm_win<%d, %s>" % (b // 16, "true" if bwd else "false")
+        if b == 48:
+            return "k_trsm_w1<3, %s, 1, false>" % ("true" if bwd else "false")
         return "k_trsm_bwd" if bwd else "k_trsm_fwd"
     if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
         return "tile-column step kernels"
@@ -398,7 +406,7 @@ def workload_line(prob, args, steps, warmup, full):
     """Timed steps of one workload (mixed form, the bench's options), with
     the FP64 form, the error against the oracle's stored run and, if `full`,
     the per-kernel roofline."""
-    runner = Runner(prob)
+    runner = Runner(prob, **({"eig_tol": args.eig_tol} if args.eig_tol else {}))
     mixed = 1 if prob.precision == "mixed" else 0
     ms, infos = timed(runner, mixed, steps, warmup)
     tres = runner.true_residual()

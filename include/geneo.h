@@ -233,7 +233,7 @@ typedef struct {
 } geneo_opts_t;
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
- * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-10, eig_maxit 300,
+ * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-8, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
  * symv_tiles 0, refine 0, refine_rtol 1e-6, tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);

@@ -1845,7 +1845,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->sigma = -1e-3;
   o->precision = GENEO_PREC_FP64;
   o->pivot_tol = 1e-3;
-  o->eig_tol = 1e-10;
+  o->eig_tol = 1e-8;
   o->eig_maxit = 300;
   o->eig_block = 0;
   o->seed = 0;

@@ -13,7 +13,9 @@
 //    subdomain): windows of 16 tile rows held in registers, a left-looking
 //    update from the finished rows, then right-looking substitution inside
 //    the window with the inverted diagonal tiles.
-//  * k_trsm_fwd / k_trsm_bwd: the same solves row by row for wider blocks
+//  * k_trsm_w1: the same with b = 48, one tile row per wavefront (windows
+//    of 8) and deeper load pipelines.
+//  * k_trsm_fwd / k_trsm_bwd: the same solves row by row for b = 64
 //    (inner sums split over tile slices, reduced in LDS).
 //  * k_bapply: Y = X_j A^o_j X_j X (the B-matrix of the GenEO eigenproblem),
 //    from a compact copy of B_j built once per setup (k_bcompact), on the
@@ -458,7 +460,8 @@ __device__ __forceinline__ void trw_mma(d4_t (&acc)[2][NCQ], const F8 (&a)[2], c
 // Owner step: X_i = D acc_i, D = Dinv_i (BWD: Dinv_i^T); acc_i goes through
 // LDS (transposed) to become the B operand; X_i is written to global memory
 // and, transposed, to sXo.
-template <int NCQ, bool BWD>
+// NEG: the accumulator holds the negated right-hand side (-acc_i is used).
+template <int NCQ, bool BWD, bool NEG = false>
 __device__ __forceinline__ void trw_finish(const d4_t (&acc)[2][NCQ], const double* Dt, double* sTmp,
                                            double* sXo, double* Xi, int b, int lane) {
   const int fi = lane & 15, fg = lane >> 4;
@@ -468,7 +471,8 @@ __device__ __forceinline__ void trw_finish(const d4_t (&acc)[2][NCQ], const doub
     for (int cq = 0; cq < NCQ; ++cq)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        sTmp[(cq * 16 + acc_col(lane)) * TRW_LD + rq * 16 + acc_row<double>(lane, v)] = acc[rq][cq][v];
+        sTmp[(cq * 16 + acc_col(lane)) * TRW_LD + rq * 16 + acc_row<double>(lane, v)] =
+            NEG ? -acc[rq][cq][v] : acc[rq][cq][v];
   wave_sync();
   F8 a[2];
 #pragma unroll
@@ -629,6 +633,157 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
   }
 }
 
+// Windowed substitution with deeper load pipelines.  One workgroup of
+// TW1_NW = 8 wavefronts per subdomain; windows of 8 tile rows, wavefront w
+// owning window row p0 + w (its 32 x b block as matrix-core accumulators,
+// holding -R + the products so far).  The left-looking update streams the
+// row's factor tiles with AD tiles in flight beyond the one in use and,
+// with BP, loads the right-hand block X_jj of the next step one step ahead,
+// so that neither the HBM latency of the factor nor the L2 latency of X
+// stalls the matrix cores (an FP64 tile product with b = 32 right-hand
+// sides is 32 MFMAs, about one HBM round trip).  AD and BP are chosen per
+// block width so that the pipelines fit in 256 VGPRs without spills.  The
+// substitution inside the window is the right-looking one of k_trsm_win.
+#define TW1_NW 8
+
+template <int NCQ, bool BWD, int AD, bool BP>
+__global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restrict__ G,
+                                                        const double* __restrict__ dinv,
+                                                        const int64_t* __restrict__ toff,
+                                                        const int64_t* __restrict__ doff,
+                                                        const int* __restrict__ ntl,
+                                                        const int* __restrict__ voff,
+                                                        const double* __restrict__ R,
+                                                        double* __restrict__ X,
+                                                        const int* __restrict__ active) {
+  static_assert(AD == 1 || AD == 2, "factor tiles in flight");
+  constexpr int b = 16 * NCQ;
+  const int j = blockIdx.x;
+  if (active && !active[j]) return;
+  __shared__ __align__(16) double sTmp[b * TRW_LD];
+  __shared__ __align__(16) double sX[2][b * TRW_LD];
+  const int nt = ntl[j];
+  const double* Gj = G + toff[j] * TSQ;
+  const double* Dj = dinv + doff[j] * TSQ;
+  const double* Rj = R + (int64_t)voff[j] * b;
+  double* Xj = X + (int64_t)voff[j] * b;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int fi = lane & 15, fg = lane >> 4;
+  const int nwin = (nt + TW1_NW - 1) / TW1_NW;
+  // factor tile (k, jj) (FWD) or (jj, k) read transposed (BWD)
+  auto loadA = [&](F8 (&aa)[2], int k, int jj) {
+    const double* t = BWD ? Gj + tile_idx(jj, k) * TSQ : Gj + tile_idx(k, jj) * TSQ;
+#pragma unroll
+    for (int rq = 0; rq < 2; ++rq) {
+      if (BWD) afrag_tr(aa[rq], t, rq * 16, fi, fg);
+      else afrag(aa[rq], t, rq * 16, fi, fg);
+    }
+  };
+  auto loadB = [&](F8& bb, int jj, int cq) { bfrag_g(bb, Xj + (int64_t)jj * TS * b, b, cq * 16, fi, fg); };
+  for (int wi = 0; wi < nwin; ++wi) {
+    // window rows [p0, p1); BWD windows run from the bottom
+    const int p0 = BWD ? max(0, nt - (wi + 1) * TW1_NW) : wi * TW1_NW;
+    const int p1 = BWD ? nt - wi * TW1_NW : min(nt, p0 + TW1_NW);
+    const int k = p0 + w;
+    const bool own = k < p1;
+    d4_t acc[2][NCQ];
+#pragma unroll
+    for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+      for (int cq = 0; cq < NCQ; ++cq)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[rq][cq][v] = own ? -Rj[((int64_t)k * TS + rq * 16 + acc_row<double>(lane, v)) * b +
+                                     cq * 16 + acc_col(lane)]
+                               : 0.0;
+    // ---- left-looking update from the finished rows
+    // FWD: acc_k += sum_{jj < p0} G_k,jj X_jj      BWD: acc_k += sum_{jj >= p1} G_jj,k^T X_jj
+    const int jlo = BWD ? p1 : 0, jhi = BWD ? nt : p0;
+    if (own && jlo < jhi && BP) {
+      // whole next right-hand block in flight during this step's products
+      F8 a0[2], a1[2], a2[2];
+      F8 bc[NCQ], bn[NCQ];
+      loadA(a0, k, jlo);
+      if (jlo + 1 < jhi) loadA(a1, k, jlo + 1);
+#pragma unroll
+      for (int cq = 0; cq < NCQ; ++cq) loadB(bc[cq], jlo, cq);
+      for (int jj = jlo; jj < jhi; ++jj) {
+        // the loads of the steps ahead go out before this step's products
+        if (AD == 2 && jj + 2 < jhi) loadA(a2, k, jj + 2);
+        if (jj + 1 < jhi) {
+#pragma unroll
+          for (int cq = 0; cq < NCQ; ++cq) loadB(bn[cq], jj + 1, cq);
+        }
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) trw_mma<NCQ>(acc, a0, bc[cq], cq);
+#pragma unroll
+        for (int rq = 0; rq < 2; ++rq) {
+          a0[rq] = a1[rq];
+          if (AD == 2) a1[rq] = a2[rq];
+        }
+        if (AD == 1 && jj + 2 < jhi) loadA(a1, k, jj + 2);
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) bc[cq] = bn[cq];
+      }
+    } else if (own && jlo < jhi) {
+      // one column group of the right-hand block in flight: group q + 1 is
+      // loaded during the products with group q, group 0 of the next step
+      // during the last group of this one
+      F8 a0[2], a1[2];
+      F8 bcur, bnxt;
+      loadA(a0, k, jlo);
+      if (jlo + 1 < jhi) loadA(a1, k, jlo + 1);
+      loadB(bcur, jlo, 0);
+      for (int jj = jlo; jj < jhi; ++jj) {
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) {
+          if (cq + 1 < NCQ) loadB(bnxt, jj, cq + 1);
+          else if (jj + 1 < jhi) loadB(bnxt, jj + 1, 0);
+          trw_mma<NCQ>(acc, a0, bcur, cq);
+          bcur = bnxt;
+        }
+#pragma unroll
+        for (int rq = 0; rq < 2; ++rq) a0[rq] = a1[rq];
+        if (jj + 2 < jhi) loadA(a1, k, jj + 2);
+      }
+    }
+    // ---- right-looking solve inside the window
+    for (int st = 0; st < p1 - p0; ++st) {
+      const int i = BWD ? p1 - 1 - st : p0 + st;
+      double* sXo = sX[st & 1];
+      if (w == i - p0)
+        trw_finish<NCQ, BWD, true>(acc, Dj + (int64_t)i * TSQ, sTmp, sXo,
+                                   Xj + (int64_t)i * TS * b, b, lane);
+      const bool want = own && (BWD ? k < i : k > i);
+      F8 a[2];
+      if (want) loadA(a, k, i);
+      block_sync();
+      if (want) {
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) {
+          F8 bf;
+          bfrag_s(bf, sXo, cq * 16, fi, fg);
+          trw_mma<NCQ>(acc, a, bf, cq);
+        }
+      }
+    }
+    block_sync();
+  }
+}
+
+template <bool BWD>
+static hipError_t launch_trsm_w1(const double* G, const double* dinv, const int64_t* toff,
+                                 const int64_t* doff, const int* nt, const int* voff, int nsub,
+                                 int b, const double* R, double* X, const int* active,
+                                 hipStream_t st) {
+  const dim3 grid(nsub), blk(TW1_NW * 64);
+  switch (b) {
+    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <bool BWD>
 static hipError_t launch_trsm_win(const double* G, const double* dinv, const int64_t* toff,
                                   const int64_t* doff, const int* nt, const int* voff, int nsub,
@@ -646,7 +801,11 @@ static hipError_t launch_trsm_win(const double* G, const double* dinv, const int
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, hipStream_t st) {
+  // b <= 32: two rows per wavefront (each right-hand block feeds both);
+  // b = 48: one row per wavefront with deeper load pipelines (measured
+  // faster at each width)
   if (b <= 32) return launch_trsm_win<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
+  if (b == 48) return launch_trsm_w1<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
   hipLaunchKernelGGL(k_trsm_fwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
                      R, X, active);
   return hipGetLastError();
@@ -656,6 +815,7 @@ hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* t
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, hipStream_t st) {
   if (b <= 32) return launch_trsm_win<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
+  if (b == 48) return launch_trsm_w1<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
   hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
                      R, X, active);
   return hipGetLastError();

@@ -183,3 +183,35 @@ def test_pcg_and_operator(big):
     say("[operator %s] relative asymmetry %.2e" % (name, asym))
     assert asym <= 1e-9
     assert r @ zr > 0 and y @ zy > 0
+
+
+def test_solution_matches_oracle_run(big):
+    """The oracle's whole FP64 run of the workload (setup with the Lanczos
+    eigen path and PCG to 1e-10, stored by golden/make_fullsize_golden.py,
+    which calls only the oracle): eigenvector counts equal, iterations
+    within +-2, the plain solution within 1e-8 of the oracle's and the
+    solution after two refinement steps within 1e-8 of the oracle's refined
+    reference."""
+    import os
+    name, prob, A, b, subs, sysm, h, info = big
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "fullsize_%s_seed0.npz" % name)
+    gold = np.load(path)
+    from paper_1906_10944_amd import geneo as G
+    m, _ = G.geneo_get_eigenvalues(h, len(subs))
+    x0, inf0 = gpu_pcg(h, sysm, rtol=prob.rtol, maxit=prob.maxit)
+    h2 = gpu_setup(sysm, prob, precision=1, refine=2)
+    x, inf = gpu_pcg(h2, sysm, rtol=prob.rtol, maxit=prob.maxit)
+    h2.close()
+    res = {}
+    for key, xg, xo in (("plain", x0, gold["x"]), ("refined", x, gold["x_ref"])):
+        res[key] = (np.linalg.norm(xg - xo) / np.linalg.norm(xo),
+                    np.abs(xg - xo).max() / np.abs(xo).max())
+    say("[solution %s] iters %d oracle %d, nc %d oracle %d, plain rel diff %.3e max-abs %.3e, "
+        "refined (+%d its) rel diff %.3e max-abs %.3e" %
+        (name, inf0["iters"], int(gold["iters"]), info["nc"], int(gold["nc"]), res["plain"][0],
+         res["plain"][1], inf["refine_iters"], res["refined"][0], res["refined"][1]))
+    assert np.array_equal(m, gold["m"])
+    assert abs(inf0["iters"] - int(gold["iters"])) <= 2
+    for key in res:
+        assert res[key][0] <= 1e-8 and res[key][1] <= 1e-8, (key, res[key])
