@@ -362,6 +362,7 @@ struct geneo_handle_s {
   int nc = 0, ntc = 0, b = 0;
   DBuf<int> m, zoff, coff, hnt;
   DBuf<double> tau_sub;  // per-subdomain thresholds (opts.tau_sub), else empty
+  int trsm_variant = 0;  // kernel of the eigen sweeps' triangular solves
   // apply job list of the symmetric products: (subdomain, 1 if its inverse
   // is FP64) for every subdomain, then (nsub, 2) for the coarse inverse
   DBuf<int2> ajobs;
@@ -573,7 +574,7 @@ struct SetupScratch {
   DBuf<int2> ljobs32, ljobs64, ljobsH;
   DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart,
       cpiv;
-  DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol;
+  DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol, orderN;
   DBuf<double> bval;
   DBuf<int> brpos;
   DBuf<int2> brows;
@@ -596,6 +597,55 @@ struct SetupScratch {
   EigStall stl;
 };
 
+// Kernel of the eigen sweeps' triangular solves: when the block width has
+// several (trsm_variants; all give bitwise the same solution), each is
+// timed once on the device at the first setup of a shape, on the start
+// block (a backward solve into T, which the first sweep then overwrites),
+// after one warm launch; the fastest is kept for that device and shape.
+std::mutex g_trsm_mu;
+std::map<std::tuple<int, int, int, int64_t, int>, int> g_trsm_tune;
+
+int tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, hipStream_t sb) {
+  const int b = h->b;
+  const int nv = trsm_variants(b);
+  if (nv < 2) return 0;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, h->nsub, LN.maxnt, (int64_t)LN.ntiles, b);
+  {
+    std::lock_guard<std::mutex> g(g_trsm_mu);
+    auto it = g_trsm_tune.find(key);
+    if (it != g_trsm_tune.end()) return it->second;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.f;
+  for (int v = 0; v < nv; ++v) {
+    auto run = [&]() {
+      HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, h->nsub, b,
+                             X.U.p, X.T.p, nullptr, X.orderN.p, v, sb));
+    };
+    run();
+    HIPCHK(hipEventRecord(e0, sb));
+    run();
+    HIPCHK(hipEventRecord(e1, sb));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (v == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> g(g_trsm_mu);
+  g_trsm_tune[key] = best;
+  return best;
+}
+
 struct PhaseTimer {
   hipEvent_t a = nullptr, b = nullptr;
   void start(hipStream_t st) {
@@ -616,6 +666,17 @@ struct PhaseTimer {
     if (b) (void)hipEventDestroy(b);
   }
 };
+
+// Subdomains by decreasing size (stable): the dispatch order of the
+// one-workgroup-per-subdomain launches, so that the hardware's workgroup
+// queue hands out the longest jobs first (largest-first scheduling over
+// uneven subdomains).
+std::vector<int> largest_first(const std::vector<int>& size) {
+  std::vector<int> o(size.size());
+  for (size_t j = 0; j < o.size(); ++j) o[j] = (int)j;
+  std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return size[a] > size[b]; });
+  return o;
+}
 
 // Jobs of the inverse factors: (matrix, first tile column) in blocks of
 // trtri_cols_per_job columns, the longest columns (smallest c0) first.
@@ -662,7 +723,7 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
   const bool mixed = o.precision == GENEO_PREC_MIXED;
   X.status.alloc(nsub);
   if (mixed) {
-    X.jobs.upload(all, st);
+    X.jobs.upload(largest_first(h->nd_host), st);
     X.L32.alloc(h->LD.ntiles * TSQ);
     X.D32.alloc(h->LD.ndiag * TSQ);
     double pk = 0.0, fl = 0.0;
@@ -884,7 +945,11 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   X.voffN.upload(LN.voff, sb);
   X.toffN.upload(LN.toff, sb);
   X.doffN.upload(LN.doff, sb);
-  X.jobsN.upload(all, sb);
+  {
+    const std::vector<int> ord = largest_first(h->nN_host);
+    X.jobsN.upload(ord, sb);
+    X.orderN.upload(ord, sb);
+  }
   X.status2.alloc(nsub);
   X.G.alloc(LN.ntiles * TSQ);
   X.DG.alloc(LN.ndiag * TSQ);
@@ -981,6 +1046,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   if (!X.pin_st2) check_shifted(download(X.status2.p, nsub, sb).data());
   // ---- block subspace iteration on S = G^{-1} B G^{-T}
   tm[1].start(sb);
+  h->trsm_variant = o.eig_solve > 0 ? o.eig_solve - 1 : tune_trsm(h, X, LN, sb);
+  h->info.eig_solve = h->trsm_variant + 1;
   const EigWork& wk = X.wk;
   const EigStall& stl = X.stl;
   int sweeps = 0, nact = nsub;
@@ -1034,7 +1101,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("trsm_bwd", sb, gb + vb, tf);
       HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                             X.U.p, X.T.p, X.active.p, sb));
+                             X.U.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant, sb));
     }
     {
       // the B entries, the T rows they reach (once each) and the W rows
@@ -1046,7 +1113,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("trsm_fwd", sb, gb + vb, tf);
       HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                             X.W.p, X.T.p, X.active.p, sb));
+                             X.W.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant, sb));
     }
     {
       ProfScope ps("rayleigh_ritz", sb, 2.0 * vb, 0.0);
@@ -1097,7 +1164,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
         {
           ProfScope ps("trsm_bwd", sb, gb + vb, tf);
           HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
-                                 b, X.U.p, X.T.p, X.active.p, sb));
+                                 b, X.U.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant,
+                                 sb));
         }
         {
           ProfScope ps("bapply", sb, 12.0 * X.nnzB + 2.0 * 8.0 * X.nbrows * b, 0.0);
@@ -1107,7 +1175,8 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
         {
           ProfScope ps("trsm_fwd", sb, gb + vb, tf);
           HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
-                                 b, X.W.p, X.T.p, X.active.p, sb));
+                                 b, X.W.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant,
+                                 sb));
         }
         {
           ProfScope ps("cheb_combine", sb, 2.0 * vb, 0.0);
@@ -1143,7 +1212,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   }
   // eigenvectors p = G^{-T} y
   HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b, X.Y.p,
-                         X.T.p, nullptr, sb));
+                         X.T.p, nullptr, X.orderN.p, h->trsm_variant, sb));
   HIPCHK(launch_select(X.theta.p, nsub, b, o.nev, o.tau, h->tau_sub.p, o.nev_max, o.sigma, h->m.p,
                        X.lam.p, sb));
   h->m_host = download(h->m.p, nsub, sb);
@@ -1857,6 +1926,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->tau_sub = nullptr;
   o->refine = 0;
   o->refine_rtol = 1e-6;
+  o->eig_solve = 0;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -1940,6 +2010,7 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "symv_tiles must be 0, 8, 16 or 32");
     if (o.refine < 0 || o.refine > 8 || !(o.refine_rtol > 0 && o.refine_rtol < 1))
       fail(GENEO_ERR_ARG, "refine must be 0..8 with 0 < refine_rtol < 1");
+    if (o.eig_solve < 0 || o.eig_solve > 2) fail(GENEO_ERR_ARG, "eig_solve must be 0, 1 or 2");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     settle_thread();  // the setup's scratch blocks become reusable

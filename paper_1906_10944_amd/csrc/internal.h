@@ -149,14 +149,18 @@ hipError_t symv_make_tasks(const SymvJob* jobs, int njobs, int g, int nchunk, Sy
                            SymvTask* rev, hipStream_t st);
 hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
+// Triangular solves with the shifted factors, one workgroup per subdomain,
+// dispatched in the order `order` (may be NULL = by index); `variant`
+// picks one of trsm_variants(b) kernels, all giving bitwise the same X.
+int trsm_variants(int b);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
-                           hipStream_t st);
+                           const int* order, int variant, hipStream_t st);
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
-                           hipStream_t st);
+                           const int* order, int variant, hipStream_t st);
 // B_j = X_j A^o_j X_j in compact CSR over the nloc local rows: brp [nloc+1]
 // (cnt [nloc] scratch), bcol / bval sized by the nonzeros of the A^o batch;
 // maxrows bounds |N_j|.

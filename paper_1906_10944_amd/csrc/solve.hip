@@ -512,9 +512,10 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
                                                          const int* __restrict__ voff,
                                                          const double* __restrict__ R,
                                                          double* __restrict__ X,
-                                                         const int* __restrict__ active) {
+                                                         const int* __restrict__ active,
+                                                         const int* __restrict__ order) {
   constexpr int b = 16 * NCQ;
-  const int j = blockIdx.x;
+  const int j = order ? order[blockIdx.x] : blockIdx.x;
   if (active && !active[j]) return;
   __shared__ __align__(16) double sTmp[b * TRW_LD];
   __shared__ __align__(16) double sX[2][b * TRW_LD];
@@ -655,10 +656,11 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
                                                         const int* __restrict__ voff,
                                                         const double* __restrict__ R,
                                                         double* __restrict__ X,
-                                                        const int* __restrict__ active) {
+                                                        const int* __restrict__ active,
+                                                        const int* __restrict__ order) {
   static_assert(AD == 1 || AD == 2, "factor tiles in flight");
   constexpr int b = 16 * NCQ;
-  const int j = blockIdx.x;
+  const int j = order ? order[blockIdx.x] : blockIdx.x;
   if (active && !active[j]) return;
   __shared__ __align__(16) double sTmp[b * TRW_LD];
   __shared__ __align__(16) double sX[2][b * TRW_LD];
@@ -775,10 +777,12 @@ template <bool BWD>
 static hipError_t launch_trsm_w1(const double* G, const double* dinv, const int64_t* toff,
                                  const int64_t* doff, const int* nt, const int* voff, int nsub,
                                  int b, const double* R, double* X, const int* active,
-                                 hipStream_t st) {
+                                 const int* order, hipStream_t st) {
   const dim3 grid(nsub), blk(TW1_NW * 64);
   switch (b) {
-    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active); break;
+    case 16: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
+    case 32: hipLaunchKernelGGL((k_trsm_w1<2, BWD, 1, true>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
+    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -788,24 +792,30 @@ template <bool BWD>
 static hipError_t launch_trsm_win(const double* G, const double* dinv, const int64_t* toff,
                                   const int64_t* doff, const int* nt, const int* voff, int nsub,
                                   int b, const double* R, double* X, const int* active,
-                                  hipStream_t st) {
+                                  const int* order, hipStream_t st) {
   const dim3 grid(nsub), blk(TRW_NW * 64);
   switch (b) {
-    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active); break;
-    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active); break;
+    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
+    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+int trsm_variants(int b) { return b <= 32 ? 2 : 1; }
+
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
-                           const double* R, double* X, const int* active, hipStream_t st) {
-  // b <= 32: two rows per wavefront (each right-hand block feeds both);
-  // b = 48: one row per wavefront with deeper load pipelines (measured
-  // faster at each width)
-  if (b <= 32) return launch_trsm_win<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
-  if (b == 48) return launch_trsm_w1<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
+                           const double* R, double* X, const int* active, const int* order,
+                           int variant, hipStream_t st) {
+  // b <= 32: variant 0 two rows per wavefront (each right-hand block feeds
+  // both), variant 1 one row per wavefront with deeper load pipelines (the
+  // same sums in the same order: bitwise the same result); b = 48: one row
+  // per wavefront; b = 64: row by row
+  if (b <= 32 && variant == 0)
+    return launch_trsm_win<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
+  if (b <= 48)
+    return launch_trsm_w1<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
   hipLaunchKernelGGL(k_trsm_fwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
                      R, X, active);
   return hipGetLastError();
@@ -813,9 +823,12 @@ hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* t
 
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
-                           const double* R, double* X, const int* active, hipStream_t st) {
-  if (b <= 32) return launch_trsm_win<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
-  if (b == 48) return launch_trsm_w1<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, st);
+                           const double* R, double* X, const int* active, const int* order,
+                           int variant, hipStream_t st) {
+  if (b <= 32 && variant == 0)
+    return launch_trsm_win<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
+  if (b <= 48)
+    return launch_trsm_w1<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
   hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
                      R, X, active);
   return hipGetLastError();

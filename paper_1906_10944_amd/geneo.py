@@ -72,7 +72,8 @@ class Opts(C.Structure):
                 ("eig_tol", C.c_double), ("eig_maxit", C.c_int), ("eig_block", C.c_int),
                 ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
                 ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int),
-                ("refine", C.c_int), ("refine_rtol", C.c_double), ("tau_sub", C.c_void_p)]
+                ("refine", C.c_int), ("refine_rtol", C.c_double), ("eig_solve", C.c_int),
+                ("tau_sub", C.c_void_p)]
 
 
 class SetupInfo(C.Structure):
@@ -80,7 +81,7 @@ class SetupInfo(C.Structure):
                 ("eig_sweeps", C.c_int), ("eig_block", C.c_int),
                 ("eig_max_resid", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64),
-                ("eig_stalled", C.c_int), ("symv_tiles", C.c_int)]
+                ("eig_stalled", C.c_int), ("symv_tiles", C.c_int), ("eig_solve", C.c_int)]
 
 
 class PcgInfo(C.Structure):

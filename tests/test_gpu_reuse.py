@@ -97,3 +97,35 @@ def test_sweep_flags_read_late_or_at_once_give_the_same_operator():
         assert got[0] == outs[0][0]
         for a, b in zip(got[1:], outs[0][1:]):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nev,tau", [(4, None), (None, 0.1)], ids=["b16", "b32"])
+def test_every_eigen_solve_kernel_gives_the_same_operator(nev, tau):
+    """The eigen sweeps' triangular solves have two kernels for blocks of
+    16 and 32 columns (two tile rows per wavefront, or one with deeper load
+    pipelines) that form the same sums in the same order; the setup times
+    them and keeps the faster one.  Forced either way (and tuned), the
+    sweep count, the eigenvalues, the coarse basis and the operator agree
+    bit for bit."""
+    need_gpu()
+    from paper_1906_10944_amd import geneo as G
+    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    if tau is None:
+        prob.tau, prob.nev = None, nev
+    sysm = gpu_assemble(prob)
+    r = np.random.default_rng(13).standard_normal(prob.ndof)
+    outs = []
+    for v in (1, 2, 0):
+        h = gpu_setup(sysm, prob, precision=1, eig_solve=v)
+        info = G.geneo_get_setup_info(h)
+        m, lam = G.geneo_get_eigenvalues(h, prob.nsub)
+        zoff, z, ah = G.geneo_get_coarse(h, prob.nsub)
+        outs.append((info["eig_sweeps"], m, lam, z, ah, gpu_apply(h, sysm, r)))
+        say("[eig solve] forced", v, "used", info["eig_solve"], "block", info["eig_block"],
+            "sweeps", info["eig_sweeps"])
+        assert info["eig_solve"] == v or (v == 0 and info["eig_solve"] in (1, 2))
+        h.close()
+    for got in outs[1:]:
+        assert got[0] == outs[0][0]
+        for a, b in zip(got[1:], outs[0][1:]):
+            assert np.array_equal(a, b)
