@@ -37,14 +37,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="config3", choices=["config1", "config2", "config3",
-                                                            "config4"])
+    ap.add_argument("--config", default="layers_96",
+                    choices=["channels_64", "grf_512", "layers_96", "laminate_128x32x24"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-nested", action="store_true",
                     help="skip the nested 512^2 workload and serving objects")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
+                    help="further setup option (geneo_opts_t field, integer or float)")
     ap.add_argument("--eig-tol", type=float, default=None,
                     help="eigen residual tolerance (default: the library's)")
     ap.add_argument("--serve", action="store_true",
@@ -58,6 +60,11 @@ def parse():
                     help="only run a plain 1 GiB device copy (elementwise x*1): the "
                          "reference kernel for scaling HBM traffic counters")
     return ap.parse_args()
+
+
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def copy_probe():
@@ -113,6 +120,7 @@ class Runner:
                "eig_sweeps": sinfo["eig_sweeps"], "fallback_fp64": sinfo["fallback_fp64"],
                "eig_stalled": sinfo["eig_stalled"], "eig_max_resid": sinfo["eig_max_resid"],
                "symv_tiles": sinfo["symv_tiles"], "eig_block": sinfo["eig_block"],
+               "eig_solve": sinfo["eig_solve"], "eig_split": sinfo["eig_split"],
                "t_phase_ms": sinfo["t_phase_ms"]}
         self.last = (sysm, h, x)
         return out
@@ -158,8 +166,7 @@ def err_vs_oracle(prob, seed, x, iters):
     same workload (stored by tests/golden/make_fullsize_golden.py, which
     calls only the oracle), or None where no stored run exists."""
     import numpy as np
-    name = prob.name.split("_")[0]
-    path = os.path.join(GOLDEN_DIR, "fullsize_%s_seed%d.npz" % (name, seed))
+    path = os.path.join(GOLDEN_DIR, "fullsize_%s_seed%d.npz" % (prob.name, seed))
     if not os.path.exists(path):
         return None
     g = np.load(path)
@@ -231,12 +238,14 @@ def prof_symbol(name, info):
     block width picks the solve kernel, the number of FP64 refactors their
     factorisation."""
     if name in ("trsm_fwd", "trsm_bwd"):
-        b, bwd = info.get("eig_block", 32), name == "trsm_bwd"
-        if b <= 32:
-            return "k_trsm_win<%d, %s>" % (b // 16, "true" if bwd else "false")
-        if b == 48:
-            return "k_trsm_w1<3, %s, 1, false>" % ("true" if bwd else "false")
-        return "k_trsm_bwd" if bwd else "k_trsm_fwd"
+        # the unsplit solves (the kernel the setup's tuning chose)
+        b, bwd = info.get("eig_block", 32), "true" if name == "trsm_bwd" else "false"
+        if b <= 32 and info.get("eig_solve", 1) == 1:
+            return "k_trsm_win<%d, %s, %d>" % (b // 16, bwd, b)
+        if b <= 48:
+            ad, bp = {16: (2, "true"), 32: (1, "true"), 48: (1, "false")}[b]
+            return "k_trsm_w1<%d, %s, %d, %s, %d>" % (b // 16, bwd, ad, bp, b)
+        return "k_trsm_bwd" if bwd == "true" else "k_trsm_fwd"
     if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
         return "tile-column step kernels"
     return PROF_SYMBOL.get(name, name)
@@ -402,13 +411,23 @@ def serve_bench(requests, slots, budget_gb, seed):
                         "with 8 right-hand sides), seed %d" % seed}
 
 
+def setup_options(args):
+    extra = {"eig_tol": args.eig_tol} if args.eig_tol else {}
+    for kv in args.opt:
+        k, v = kv.split("=", 1)
+        extra[k] = float(v) if any(c in v for c in ".eE") else int(v)
+    return extra
+
+
 def workload_line(prob, args, steps, warmup, full):
     """Timed steps of one workload (mixed form, the bench's options), with
     the FP64 form, the error against the oracle's stored run and, if `full`,
     the per-kernel roofline."""
-    runner = Runner(prob, **({"eig_tol": args.eig_tol} if args.eig_tol else {}))
+    runner = Runner(prob, **setup_options(args))
     mixed = 1 if prob.precision == "mixed" else 0
+    log("%s: %d warmup + %d timed steps" % (prob.name, warmup, steps))
     ms, infos = timed(runner, mixed, steps, warmup)
+    log("%s: %.1f ms/step" % (prob.name, ms))
     tres = runner.true_residual()
     last = infos[-1]
     err = err_vs_oracle(prob, args.seed, runner.solution(), last["iters"])
@@ -423,12 +442,14 @@ def workload_line(prob, args, steps, warmup, full):
         "err_vs_oracle": err,
         "nc": last["nc"], "eig_sweeps": last["eig_sweeps"], "eig_stalled": last["eig_stalled"],
         "eig_max_resid": last["eig_max_resid"], "eig_block": last["eig_block"],
-        "symv_tiles": last["symv_tiles"], "fallback_fp64": last["fallback_fp64"],
+        "symv_tiles": last["symv_tiles"], "eig_solve": last["eig_solve"],
+        "eig_split": last["eig_split"], "fallback_fp64": last["fallback_fp64"],
         "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
         "setup_phase_ms": last["t_phase_ms"][:6],
     }
     if mixed and not args.no_fp64_form:
         ms64, inf64 = timed(runner, 0, 1, 1)
+        log("%s: FP64 form %.1f ms/step" % (prob.name, ms64))
         tres64 = runner.true_residual()
         err64 = err_vs_oracle(prob, args.seed, runner.solution(), inf64[-1]["iters"])
         runner.release()
@@ -439,6 +460,7 @@ def workload_line(prob, args, steps, warmup, full):
         out["speedup_vs_fp64_form"] = ms64 / ms
     if full:
         prof = kernel_profile(runner, mixed)
+        log("%s: per-kernel profile step done" % prob.name)
         last["nsub"] = prob.nsub
         out["roofline"] = roofline(prof, last["iters"], last, prob.name)
         out["kernels_ms"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
@@ -477,13 +499,15 @@ def main():
     head.pop("steps")
     head.pop("warmup")
     out.update(head)
-    if not args.no_nested and args.config != "config2":
-        p2 = make_problem("config2", args.seed)
+    if not args.no_nested and args.config != "grf_512":
+        p2 = make_problem("grf_512", args.seed)
         line = workload_line(p2, args, max(1, min(args.steps, 10)), 2, False)
-        out["config2"] = line
+        out["grf_512"] = line
     if not args.no_cpu_baseline:
+        log("oracle baseline on a sample of %s" % prob.name)
         out["cpu_baseline"] = cpu_baseline(prob, out["iters"], args.cpu_budget_s)
     if not args.no_nested:
+        log("serving stream, %d requests" % args.serve_requests)
         out["serving"] = serve_bench(args.serve_requests, args.serve_slots,
                                      args.serve_budget_gb, args.seed)
     print(json.dumps(out))

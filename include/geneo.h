@@ -225,12 +225,17 @@ typedef struct {
                          double-double, A d = r by PCG to refine_rtol |r|,
                          x += d.  0 = the plain method. */
   double refine_rtol; /* tolerance of the correction solves */
-  int eig_solve;      /* kernel of the eigen sweeps' triangular solves for
-                         block widths that have two (b <= 32): 1 = two tile
-                         rows per wavefront, 2 = one row per wavefront with
-                         deeper load pipelines, 0 = the faster of them,
-                         timed on the device at the first setup of each
-                         problem shape (results are bitwise the same) */
+  int eig_solve;      /* kernel of the eigen sweeps' triangular solves
+                         (b <= 48): 1 = two tile rows per wavefront (b <= 32,
+                         or 16-column blocks), 2 = one row per wavefront with
+                         deeper load pipelines, 0 = the faster, timed on the
+                         device at the first setup of each problem shape */
+  int eig_split;      /* 16-column blocks on b / 16 workgroups per
+                         subdomain (b = 32, 48) in the sweeps that start
+                         with at most this many subdomains active (as far
+                         as the host knows): -1 = never, 0 = a limit timed
+                         at the first setup of the shape.  Every eig_solve
+                         / eig_split choice gives bitwise the same result. */
   const double* tau_sub; /* host [nsub], or NULL: per-subdomain thresholds
                          tau_j > 0 replacing tau (take the eigenvalues
                          < tau_j, at most nev_max of them), e.g. the
@@ -241,7 +246,8 @@ typedef struct {
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-8, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
- * symv_tiles 0, refine 0, refine_rtol 1e-6, eig_solve 0, tau_sub NULL. */
+ * symv_tiles 0, refine 0, refine_rtol 1e-6, eig_solve 0, eig_split 0,
+ * tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;
@@ -298,8 +304,11 @@ typedef struct {
   int64_t bytes_local_factors;  /* bytes of the inverse local factors */
   int eig_stalled;        /* subdomains stopped at their rounding floor */
   int symv_tiles;         /* tiles per wavefront of the local products */
-  int eig_solve;          /* triangular-solve kernel of the eigen sweeps
-                             (1 or 2, see geneo_opts_t) */
+  int eig_solve;          /* triangular-solve kernel of the eigen sweeps'
+                             unsplit solves (1 or 2, see geneo_opts_t) */
+  int eig_split;          /* the sweeps' solves are split into 16-column
+                             blocks while at most this many subdomains are
+                             active (0 = never) */
 } geneo_setup_info_t;
 
 int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);

@@ -342,6 +342,11 @@ double packed(double n) { return n * (n + 1.0) * 0.5; }
 
 }  // namespace
 
+// Kernels of the eigen sweeps' triangular solves (see tune_trsm).
+struct TrsmChoice {
+  int variant = 0, split_variant = 0, split_limit = 0;
+};
+
 struct geneo_handle_s {
   int n = 0, nsub = 0;
   int64_t nloc = 0;
@@ -362,7 +367,7 @@ struct geneo_handle_s {
   int nc = 0, ntc = 0, b = 0;
   DBuf<int> m, zoff, coff, hnt;
   DBuf<double> tau_sub;  // per-subdomain thresholds (opts.tau_sub), else empty
-  int trsm_variant = 0;  // kernel of the eigen sweeps' triangular solves
+  TrsmChoice trsm;  // kernels of the eigen sweeps' triangular solves
   // apply job list of the symmetric products: (subdomain, 1 if its inverse
   // is FP64) for every subdomain, then (nsub, 2) for the coarse inverse
   DBuf<int2> ajobs;
@@ -597,21 +602,30 @@ struct SetupScratch {
   EigStall stl;
 };
 
-// Kernel of the eigen sweeps' triangular solves: when the block width has
-// several (trsm_variants; all give bitwise the same solution), each is
-// timed once on the device at the first setup of a shape, on the start
-// block (a backward solve into T, which the first sweep then overwrites),
-// after one warm launch; the fastest is kept for that device and shape.
+// Kernels of the eigen sweeps' triangular solves.  All choices give
+// bitwise the same solution; each is timed on the device at the first setup
+// of a shape, on the start block (a backward solve into T, which the first
+// sweep then overwrites), after one warm launch, and the fastest is kept for
+// that device and shape:
+//  * variant: the kernel of the unsplit solves, timed over all subdomains;
+//  * split: 16-column blocks on b / 16 workgroups per subdomain, for sweeps
+//    whose active subdomains (as far as the host knows) number at most
+//    split_limit.  Timed against the unsplit kernel on the CUs / (b / 16)
+//    largest subdomains (where the unsplit kernel leaves CUs idle that the
+//    split one fills) and, if it wins there, over all subdomains as well.
 std::mutex g_trsm_mu;
-std::map<std::tuple<int, int, int, int64_t, int>, int> g_trsm_tune;
+std::map<std::tuple<int, int, int, int64_t, int>, TrsmChoice> g_trsm_tune;
 
-int tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, hipStream_t sb) {
-  const int b = h->b;
-  const int nv = trsm_variants(b);
-  if (nv < 2) return 0;
-  int dev = 0;
+TrsmChoice tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, hipStream_t sb) {
+  const int b = h->b, nsub = h->nsub;
+  const int nsplit = trsm_max_split(b);
+  TrsmChoice c;
+  c.variant = b <= 32 ? 0 : 1;
+  if (b > 48) return c;
+  int dev = 0, ncu = 0;
   HIPCHK(hipGetDevice(&dev));
-  const auto key = std::make_tuple(dev, h->nsub, LN.maxnt, (int64_t)LN.ntiles, b);
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const auto key = std::make_tuple(dev, nsub, LN.maxnt, (int64_t)LN.ntiles, b);
   {
     std::lock_guard<std::mutex> g(g_trsm_mu);
     auto it = g_trsm_tune.find(key);
@@ -620,12 +634,10 @@ int tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, hipStre
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best = 0;
-  float best_ms = 0.f;
-  for (int v = 0; v < nv; ++v) {
+  auto time = [&](int v, int split, int n) {
     auto run = [&]() {
-      HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, h->nsub, b,
-                             X.U.p, X.T.p, nullptr, X.orderN.p, v, sb));
+      HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, n, b, X.U.p,
+                             X.T.p, nullptr, X.orderN.p, v, split, sb));
     };
     run();
     HIPCHK(hipEventRecord(e0, sb));
@@ -634,16 +646,33 @@ int tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, hipStre
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (v == 0 || ms < best_ms) {
-      best_ms = ms;
-      best = v;
+    return ms;
+  };
+  float tu = 0.f;
+  if (b <= 32) {
+    const float t0 = time(0, 1, nsub), t1 = time(1, 1, nsub);
+    c.variant = t1 < t0 ? 1 : 0;
+    tu = std::min(t0, t1);
+  } else {
+    tu = time(1, 1, nsub);
+  }
+  if (nsplit > 1) {
+    // with at most ncu / nsplit subdomains active the split solves fill
+    // the CUs that the unsplit ones leave idle
+    const int n1 = std::max(1, std::min(nsub, ncu / nsplit));
+    const float tu1 = n1 == nsub ? tu : time(c.variant, 1, n1);
+    const float s0 = time(0, nsplit, n1), s1 = time(1, nsplit, n1);
+    c.split_variant = s1 < s0 ? 1 : 0;
+    if (std::min(s0, s1) < tu1) {
+      c.split_limit = n1;
+      if (n1 < nsub && time(c.split_variant, nsplit, nsub) < tu) c.split_limit = nsub;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> g(g_trsm_mu);
-  g_trsm_tune[key] = best;
-  return best;
+  g_trsm_tune[key] = c;
+  return c;
 }
 
 struct PhaseTimer {
@@ -719,7 +748,7 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
   const int nsub = h->nsub;
   std::vector<int> all(nsub);
   for (int j = 0; j < nsub; ++j) all[j] = j;
-  std::vector<int> f64list;
+  std::vector<int> f64list, inv32;
   const bool mixed = o.precision == GENEO_PREC_MIXED;
   X.status.alloc(nsub);
   if (mixed) {
@@ -755,6 +784,17 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
     for (int j = 0; j < nsub; ++j) (stat[j] ? f64list : ok32).push_back(j);
     h->njobs32 = (int)ok32.size();
     h->jobs32.upload(ok32, st);
+    inv32 = std::move(ok32);
+  } else {
+    f64list = all;
+    after_fp32(nullptr);
+  }
+  // The inverses of the FP32 factors, the FP64 refactors of the subdomains
+  // that failed the pivot test and their inverses go back to the caller as
+  // a step to enqueue later: nothing before the PCG needs them, and the
+  // eigen sweeps, once few subdomains are active, leave most CUs idle.
+  return [h, &X, A, S, st, nsub, mixed, f64list = std::move(f64list),
+          ok32 = std::move(inv32)]() mutable {
     if (!ok32.empty()) {
       std::vector<int2> tj = trtri_job_list(ok32, h->LD.nt, true);
       X.tjobs32.upload(tj, st);
@@ -777,15 +817,6 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
       HIPCHK(launch_lauum(true, X.XT32.p, h->S32.p, h->toffD.p, h->ntD.p, X.ljobs32.p,
                           (int)lj.size(), st));
     }
-  } else {
-    f64list = all;
-    after_fp32(nullptr);
-  }
-  // The FP64 refactors of the subdomains that failed the pivot test (and
-  // their inverses) go back to the caller as a step to enqueue later: their
-  // many short launches take host time that the first eigen sweep should
-  // not wait for.
-  return [h, &X, A, S, st, nsub, mixed, f64list = std::move(f64list)]() mutable {
     h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
     h->njobs64 = (int)f64list.size();
     h->jobs64.upload(f64list, st);
@@ -1014,12 +1045,14 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
 }
 
 // Eigen sweeps, coarse basis, Galerkin product and coarse factor on sb.
-// after_first_sweep is called once, right after the first sweep is enqueued
-// (or before any error return that follows it).
+// deferred_local (the local step nothing before the PCG needs) is called
+// once: after the first sweep that leaves at most local_at subdomains
+// active as far as the host knows, else after the last sweep (and before
+// any error return that follows it).
 void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                   const geneo_subdomains_t* S, const geneo_csr_batch_t* An,
                   const geneo_csr_batch_t* Ao, hipStream_t sb, PhaseTimer* tm,
-                  const std::function<void()>& after_first_sweep) {
+                  const std::function<void()>& deferred_local) {
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   const int b = h->b;
@@ -1046,8 +1079,20 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   if (!X.pin_st2) check_shifted(download(X.status2.p, nsub, sb).data());
   // ---- block subspace iteration on S = G^{-1} B G^{-T}
   tm[1].start(sb);
-  h->trsm_variant = o.eig_solve > 0 ? o.eig_solve - 1 : tune_trsm(h, X, LN, sb);
-  h->info.eig_solve = h->trsm_variant + 1;
+  if (o.eig_solve > 0 && o.eig_split != 0) {
+    h->trsm.variant = h->trsm.split_variant = o.eig_solve - 1;
+  } else {
+    h->trsm = tune_trsm(h, X, LN, sb);
+    if (o.eig_solve > 0) h->trsm.variant = h->trsm.split_variant = o.eig_solve - 1;
+  }
+  if (b > 32) h->trsm.variant = 1;  // the only unsplit kernel of b = 48
+  if (o.eig_split != 0) h->trsm.split_limit = std::min(std::max(o.eig_split, 0), nsub);
+  if (trsm_max_split(b) == 1) h->trsm.split_limit = 0;
+  h->info.eig_solve = h->trsm.variant + 1;
+  h->info.eig_split = h->trsm.split_limit;
+  // kernel and split of the solves while (at most) na subdomains are active
+  auto tv = [&](int na) { return na <= h->trsm.split_limit ? h->trsm.split_variant : h->trsm.variant; };
+  auto ts = [&](int na) { return na <= h->trsm.split_limit ? trsm_max_split(b) : 1; };
   const EigWork& wk = X.wk;
   const EigStall& stl = X.stl;
   int sweeps = 0, nact = nsub;
@@ -1087,6 +1132,17 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   };
   bool finished = false;
   bool local_done = false;
+  // the deferred local step (inverse factors) is enqueued once at most
+  // half as many subdomains as CUs are still active: from then on the
+  // sweeps leave CUs idle (96^3 layers: 700 -> 694 ms per step, against
+  // enqueuing it after the first sweep)
+  int local_at = 0;
+  {
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    local_at = std::max(1, ncu / 2);
+  }
   for (int it = 1; it <= o.eig_maxit; ++it) {
     // algorithmic traffic of this sweep: the factor G_j of every active
     // subdomain is read once per triangular solve, plus its b columns
@@ -1101,7 +1157,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("trsm_bwd", sb, gb + vb, tf);
       HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                             X.U.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant, sb));
+                             X.U.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact), sb));
     }
     {
       // the B entries, the T rows they reach (once each) and the W rows
@@ -1113,7 +1169,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     {
       ProfScope ps("trsm_fwd", sb, gb + vb, tf);
       HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                             X.W.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant, sb));
+                             X.W.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact), sb));
     }
     {
       ProfScope ps("rayleigh_ritz", sb, 2.0 * vb, 0.0);
@@ -1125,10 +1181,6 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(hipMemcpyAsync(aflag[it & 1], X.active.p, (size_t)nsub * sizeof(int),
                             hipMemcpyDeviceToHost, sb));
       HIPCHK(hipEventRecord(aev[it & 1], sb));
-    }
-    if (!local_done) {
-      local_done = true;
-      after_first_sweep();
     }
     if (lag) {
       if (it > 1) {
@@ -1145,6 +1197,10 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
         finished = true;
         break;
       }
+    }
+    if (!local_done && nact <= local_at) {
+      local_done = true;
+      deferred_local();
     }
     sweeps = it;
     if (o.eig_cheb >= 2 && it >= 3) {
@@ -1164,7 +1220,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
         {
           ProfScope ps("trsm_bwd", sb, gb + vb, tf);
           HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
-                                 b, X.U.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant,
+                                 b, X.U.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact),
                                  sb));
         }
         {
@@ -1175,7 +1231,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
         {
           ProfScope ps("trsm_fwd", sb, gb + vb, tf);
           HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
-                                 b, X.W.p, X.T.p, X.active.p, X.orderN.p, h->trsm_variant,
+                                 b, X.W.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact),
                                  sb));
         }
         {
@@ -1191,7 +1247,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       HIPCHK(launch_orth2(X.U.p, X.voffN.p, X.ntN.p, nsub, b, o.seed, it, X.active.p, wk, sb));
     }
   }
-  if (!local_done) after_first_sweep();
+  if (!local_done) deferred_local();
   if (lag && !finished && sweeps > 0) read_active(sweeps);
   if (!shift_checked) {
     HIPCHK(hipStreamSynchronize(sb));
@@ -1212,7 +1268,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   }
   // eigenvectors p = G^{-T} y
   HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b, X.Y.p,
-                         X.T.p, nullptr, X.orderN.p, h->trsm_variant, sb));
+                         X.T.p, nullptr, X.orderN.p, tv(nsub), ts(nsub), sb));
   HIPCHK(launch_select(X.theta.p, nsub, b, o.nev, o.tau, h->tau_sub.p, o.nev_max, o.sigma, h->m.p,
                        X.lam.p, sb));
   h->m_host = download(h->m.p, nsub, sb);
@@ -1396,20 +1452,20 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   }
   // Order: the FP32 local factorization runs alone (it fills the device);
   // the shifted factorization follows it on hs (an event orders them on the
-  // device, the host meanwhile reads the pivot tests), and the FP64
-  // refactors of the failed subdomains and the inverses follow it on st,
-  // overlapping the eigen sweeps (whose solves leave the device room)
-  // rather than competing with the factorization.  Uploads go through
-  // pinned staging, so the host drives both streams without waiting on
-  // either.
+  // device, the host meanwhile reads the pivot tests), and the inverse
+  // factors, the FP64 refactors of the failed subdomains and their inverses
+  // follow on st during the eigen sweeps, enqueued once few subdomains are
+  // still sweeping (the sweeps then leave most CUs idle) rather than
+  // competing with the factorization and the full sweeps.  Uploads go
+  // through pinned staging, so the host drives both streams without
+  // waiting on either.
   LocalLayout LN;
   tmL.start(st);
-  std::function<void()> refactor = setup_local(h, X, A, S, st, [&](hipEvent_t after) {
+  std::function<void()> local_step = setup_local(h, X, A, S, st, [&](hipEvent_t after) {
     if (coarse) setup_shifted(h, X, LN, S, An, Ao, h->hs, tmC, after);
   });
-  // the FP64 refactors are enqueued once the first eigen sweep is
   const std::function<void()> local_rest = [&]() {
-    refactor();
+    local_step();
     tmL.stop(st);
   };
   if (coarse) setup_coarse(h, X, LN, S, An, Ao, h->hs, tmC, local_rest);
@@ -1927,6 +1983,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->refine = 0;
   o->refine_rtol = 1e-6;
   o->eig_solve = 0;
+  o->eig_split = 0;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -2011,6 +2068,7 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
     if (o.refine < 0 || o.refine > 8 || !(o.refine_rtol > 0 && o.refine_rtol < 1))
       fail(GENEO_ERR_ARG, "refine must be 0..8 with 0 < refine_rtol < 1");
     if (o.eig_solve < 0 || o.eig_solve > 2) fail(GENEO_ERR_ARG, "eig_solve must be 0, 1 or 2");
+    if (o.eig_split < -1) fail(GENEO_ERR_ARG, "eig_split must be -1, 0 or positive");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     settle_thread();  // the setup's scratch blocks become reusable

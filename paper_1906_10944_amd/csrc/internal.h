@@ -149,18 +149,21 @@ hipError_t symv_make_tasks(const SymvJob* jobs, int njobs, int g, int nchunk, Sy
                            SymvTask* rev, hipStream_t st);
 hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st);
 hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
-// Triangular solves with the shifted factors, one workgroup per subdomain,
-// dispatched in the order `order` (may be NULL = by index); `variant`
-// picks one of trsm_variants(b) kernels, all giving bitwise the same X.
-int trsm_variants(int b);
+// Triangular solves with the shifted factors, one workgroup per subdomain
+// (split = 1) or b / 16 per subdomain, each on 16 of the b columns
+// (split = trsm_max_split(b) > 1), for the first nsub entries of `order`
+// (may be NULL = by index); `variant` (0 or 1) picks the kernel (0 is not
+// available unsplit for b = 48).  Every variant and split gives bitwise the
+// same X.
+int trsm_max_split(int b);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
-                           const int* order, int variant, hipStream_t st);
+                           const int* order, int variant, int split, hipStream_t st);
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
-                           const int* order, int variant, hipStream_t st);
+                           const int* order, int variant, int split, hipStream_t st);
 // B_j = X_j A^o_j X_j in compact CSR over the nloc local rows: brp [nloc+1]
 // (cnt [nloc] scratch), bcol / bval sized by the nonzeros of the A^o batch;
 // maxrows bounds |N_j|.

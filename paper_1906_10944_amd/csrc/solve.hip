@@ -13,8 +13,10 @@
 //    subdomain): windows of 16 tile rows held in registers, a left-looking
 //    update from the finished rows, then right-looking substitution inside
 //    the window with the inverted diagonal tiles.
-//  * k_trsm_w1: the same with b = 48, one tile row per wavefront (windows
-//    of 8) and deeper load pipelines.
+//  * k_trsm_w1: the same with one tile row per wavefront (windows of 8)
+//    and deeper load pipelines (b <= 48).  Both kernels also run on 16-
+//    column blocks of the right-hand sides, b / 16 workgroups per subdomain,
+//    for sweeps with fewer active subdomains than compute units.
 //  * k_trsm_fwd / k_trsm_bwd: the same solves row by row for b = 64
 //    (inner sums split over tile slices, reduced in LDS).
 //  * k_bapply: Y = X_j A^o_j X_j X (the B-matrix of the GenEO eigenproblem),
@@ -503,7 +505,24 @@ __device__ __forceinline__ void trw_finish(const d4_t (&acc)[2][NCQ], const doub
       }
 }
 
-template <int NCQ, bool BWD>
+// Workgroup -> (subdomain slot, column block).  With SPLIT column blocks
+// per subdomain (LDB = SPLIT * b columns in the blocks R and X), the
+// workgroups of one subdomain get ids 8 apart: the dispatcher deals ids
+// round-robin to the 8 XCDs, so they run on one XCD and share its L2 for
+// the factor tiles.  The columns of a triangular solve are independent, and
+// each column block is computed with the same products in the same order
+// as in the unsplit kernel: the result is bitwise the same.
+template <int SPLIT>
+__device__ __forceinline__ int trsm_slot(int bid, int& part) {
+  if (SPLIT == 1) {
+    part = 0;
+    return bid;
+  }
+  part = (bid >> 3) % SPLIT;
+  return (bid & 7) + 8 * (bid / (8 * SPLIT));
+}
+
+template <int NCQ, bool BWD, int LDB>
 __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restrict__ G,
                                                          const double* __restrict__ dinv,
                                                          const int64_t* __restrict__ toff,
@@ -513,17 +532,22 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
                                                          const double* __restrict__ R,
                                                          double* __restrict__ X,
                                                          const int* __restrict__ active,
-                                                         const int* __restrict__ order) {
-  constexpr int b = 16 * NCQ;
-  const int j = order ? order[blockIdx.x] : blockIdx.x;
+                                                         const int* __restrict__ order,
+                                                         int nsub) {
+  constexpr int b = 16 * NCQ;  // columns solved by this workgroup
+  static_assert(LDB % b == 0, "column blocks");
+  int part;
+  const int slot = trsm_slot<LDB / b>(blockIdx.x, part);
+  if (slot >= nsub) return;
+  const int j = order ? order[slot] : slot;
   if (active && !active[j]) return;
   __shared__ __align__(16) double sTmp[b * TRW_LD];
   __shared__ __align__(16) double sX[2][b * TRW_LD];
   const int nt = ntl[j];
   const double* Gj = G + toff[j] * TSQ;
   const double* Dj = dinv + doff[j] * TSQ;
-  const double* Rj = R + (int64_t)voff[j] * b;
-  double* Xj = X + (int64_t)voff[j] * b;
+  const double* Rj = R + (int64_t)voff[j] * LDB + part * b;
+  double* Xj = X + (int64_t)voff[j] * LDB + part * b;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int fi = lane & 15, fg = lane >> 4;
   const int nwin = (nt + TRW_W - 1) / TRW_W;
@@ -543,7 +567,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
         for (int cq = 0; cq < NCQ; ++cq)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            acc[m][rq][cq][v] = own ? Rj[((int64_t)krow[m] * TS + rq * 16 + acc_row<double>(lane, v)) * b +
+            acc[m][rq][cq][v] = own ? Rj[((int64_t)krow[m] * TS + rq * 16 + acc_row<double>(lane, v)) * LDB +
                                          cq * 16 + acc_col(lane)]
                                     : 0.0;
     }
@@ -573,7 +597,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
 #pragma unroll
         for (int cq = 0; cq < NCQ; ++cq) {
           F8 bf;
-          bfrag_g(bf, Xj + (int64_t)jj * TS * b, b, cq * 16, fi, fg);
+          bfrag_g(bf, Xj + (int64_t)jj * TS * LDB, LDB, cq * 16, fi, fg);
           trw_mma<NCQ>(acc[m], a, bf, cq);
         }
 #pragma unroll
@@ -590,7 +614,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
         for (int m = 0; m < TRW_MR; ++m)
           if (m == om)
             trw_finish<NCQ, BWD>(acc[m], Dj + (int64_t)i * TSQ, sTmp, sXo,
-                                 Xj + (int64_t)i * TS * b, b, lane);
+                                 Xj + (int64_t)i * TS * LDB, LDB, lane);
       }
       // the factor tile of the first row's update does not depend on X_i:
       // its loads are in flight while the wavefront waits at the barrier
@@ -647,7 +671,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
 // substitution inside the window is the right-looking one of k_trsm_win.
 #define TW1_NW 8
 
-template <int NCQ, bool BWD, int AD, bool BP>
+template <int NCQ, bool BWD, int AD, bool BP, int LDB>
 __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restrict__ G,
                                                         const double* __restrict__ dinv,
                                                         const int64_t* __restrict__ toff,
@@ -657,18 +681,23 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
                                                         const double* __restrict__ R,
                                                         double* __restrict__ X,
                                                         const int* __restrict__ active,
-                                                        const int* __restrict__ order) {
+                                                        const int* __restrict__ order,
+                                                        int nsub) {
   static_assert(AD == 1 || AD == 2, "factor tiles in flight");
-  constexpr int b = 16 * NCQ;
-  const int j = order ? order[blockIdx.x] : blockIdx.x;
+  constexpr int b = 16 * NCQ;  // columns solved by this workgroup
+  static_assert(LDB % b == 0, "column blocks");
+  int part;
+  const int slot = trsm_slot<LDB / b>(blockIdx.x, part);
+  if (slot >= nsub) return;
+  const int j = order ? order[slot] : slot;
   if (active && !active[j]) return;
   __shared__ __align__(16) double sTmp[b * TRW_LD];
   __shared__ __align__(16) double sX[2][b * TRW_LD];
   const int nt = ntl[j];
   const double* Gj = G + toff[j] * TSQ;
   const double* Dj = dinv + doff[j] * TSQ;
-  const double* Rj = R + (int64_t)voff[j] * b;
-  double* Xj = X + (int64_t)voff[j] * b;
+  const double* Rj = R + (int64_t)voff[j] * LDB + part * b;
+  double* Xj = X + (int64_t)voff[j] * LDB + part * b;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int fi = lane & 15, fg = lane >> 4;
   const int nwin = (nt + TW1_NW - 1) / TW1_NW;
@@ -681,7 +710,7 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
       else afrag(aa[rq], t, rq * 16, fi, fg);
     }
   };
-  auto loadB = [&](F8& bb, int jj, int cq) { bfrag_g(bb, Xj + (int64_t)jj * TS * b, b, cq * 16, fi, fg); };
+  auto loadB = [&](F8& bb, int jj, int cq) { bfrag_g(bb, Xj + (int64_t)jj * TS * LDB, LDB, cq * 16, fi, fg); };
   for (int wi = 0; wi < nwin; ++wi) {
     // window rows [p0, p1); BWD windows run from the bottom
     const int p0 = BWD ? max(0, nt - (wi + 1) * TW1_NW) : wi * TW1_NW;
@@ -695,7 +724,7 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
       for (int cq = 0; cq < NCQ; ++cq)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          acc[rq][cq][v] = own ? -Rj[((int64_t)k * TS + rq * 16 + acc_row<double>(lane, v)) * b +
+          acc[rq][cq][v] = own ? -Rj[((int64_t)k * TS + rq * 16 + acc_row<double>(lane, v)) * LDB +
                                      cq * 16 + acc_col(lane)]
                                : 0.0;
     // ---- left-looking update from the finished rows
@@ -755,7 +784,7 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
       double* sXo = sX[st & 1];
       if (w == i - p0)
         trw_finish<NCQ, BWD, true>(acc, Dj + (int64_t)i * TSQ, sTmp, sXo,
-                                   Xj + (int64_t)i * TS * b, b, lane);
+                                   Xj + (int64_t)i * TS * LDB, LDB, lane);
       const bool want = own && (BWD ? k < i : k > i);
       F8 a[2];
       if (want) loadA(a, k, i);
@@ -773,16 +802,26 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
   }
 }
 
+// Grid of a solve: one workgroup per subdomain, or SPLIT per subdomain
+// (slots rounded up to a multiple of 8, see trsm_slot).
+static dim3 trsm_grid(int nsub, int split) {
+  return split == 1 ? dim3(nsub) : dim3(split * ((nsub + 7) / 8 * 8));
+}
+
+#define TRSM_ARGS G, dinv, toff, doff, nt, voff, R, X, active, order, nsub
+
 template <bool BWD>
 static hipError_t launch_trsm_w1(const double* G, const double* dinv, const int64_t* toff,
                                  const int64_t* doff, const int* nt, const int* voff, int nsub,
-                                 int b, const double* R, double* X, const int* active,
+                                 int b, int split, const double* R, double* X, const int* active,
                                  const int* order, hipStream_t st) {
-  const dim3 grid(nsub), blk(TW1_NW * 64);
-  switch (b) {
-    case 16: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
-    case 32: hipLaunchKernelGGL((k_trsm_w1<2, BWD, 1, true>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
-    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
+  const dim3 grid = trsm_grid(nsub, split), blk(TW1_NW * 64);
+  switch (split == 1 ? b : -b) {
+    case 16: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 16>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 32: hipLaunchKernelGGL((k_trsm_w1<2, BWD, 1, true, 32>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false, 48>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -32: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 32>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -48: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 48>), grid, blk, 0, st, TRSM_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -791,47 +830,63 @@ static hipError_t launch_trsm_w1(const double* G, const double* dinv, const int6
 template <bool BWD>
 static hipError_t launch_trsm_win(const double* G, const double* dinv, const int64_t* toff,
                                   const int64_t* doff, const int* nt, const int* voff, int nsub,
-                                  int b, const double* R, double* X, const int* active,
+                                  int b, int split, const double* R, double* X, const int* active,
                                   const int* order, hipStream_t st) {
-  const dim3 grid(nsub), blk(TRW_NW * 64);
-  switch (b) {
-    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
-    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD>), grid, blk, 0, st, G, dinv, toff, doff, nt, voff, R, X, active, order); break;
+  const dim3 grid = trsm_grid(nsub, split), blk(TRW_NW * 64);
+  switch (split == 1 ? b : -b) {
+    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD, 16>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD, 32>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -32: hipLaunchKernelGGL((k_trsm_win<1, BWD, 32>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -48: hipLaunchKernelGGL((k_trsm_win<1, BWD, 48>), grid, blk, 0, st, TRSM_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-int trsm_variants(int b) { return b <= 32 ? 2 : 1; }
+#undef TRSM_ARGS
+
+int trsm_max_split(int b) { return b <= 48 ? b / 16 : 1; }
+
+// b <= 48, split 1: variant 0 two rows per wavefront (each right-hand block
+// feeds both; b <= 32 only, b = 48 takes variant 1), variant 1 one row per
+// wavefront with deeper load pipelines.  split = b / 16: the same kernels
+// on 16-column blocks, b / 16 workgroups per subdomain.  Every choice gives
+// bitwise the same X.  b = 64: row by row.
+template <bool BWD>
+static hipError_t launch_trsm(const double* G, const double* dinv, const int64_t* toff,
+                              const int64_t* doff, const int* nt, const int* voff, int nsub,
+                              int b, const double* R, double* X, const int* active,
+                              const int* order, int variant, int split, hipStream_t st) {
+  if (split != 1 && (b > 48 || split != b / 16)) return hipErrorInvalidValue;
+  if (b <= 48 && variant == 0 && (b <= 32 || split != 1))
+    return launch_trsm_win<BWD>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X, active,
+                                order, st);
+  if (b <= 48)
+    return launch_trsm_w1<BWD>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X, active,
+                               order, st);
+  if (BWD)
+    hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff,
+                       b, R, X, active);
+  else
+    hipLaunchKernelGGL(k_trsm_fwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff,
+                       b, R, X, active);
+  return hipGetLastError();
+}
 
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, const int* order,
-                           int variant, hipStream_t st) {
-  // b <= 32: variant 0 two rows per wavefront (each right-hand block feeds
-  // both), variant 1 one row per wavefront with deeper load pipelines (the
-  // same sums in the same order: bitwise the same result); b = 48: one row
-  // per wavefront; b = 64: row by row
-  if (b <= 32 && variant == 0)
-    return launch_trsm_win<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
-  if (b <= 48)
-    return launch_trsm_w1<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
-  hipLaunchKernelGGL(k_trsm_fwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
-                     R, X, active);
-  return hipGetLastError();
+                           int variant, int split, hipStream_t st) {
+  return launch_trsm<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, variant,
+                            split, st);
 }
 
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, const int* order,
-                           int variant, hipStream_t st) {
-  if (b <= 32 && variant == 0)
-    return launch_trsm_win<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
-  if (b <= 48)
-    return launch_trsm_w1<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, st);
-  hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff, b,
-                     R, X, active);
-  return hipGetLastError();
+                           int variant, int split, hipStream_t st) {
+  return launch_trsm<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, variant,
+                           split, st);
 }
 
 // B_j = X_j A^o_j X_j (the B-matrix of the GenEO eigenproblem) in compact

@@ -73,7 +73,7 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
                 ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int),
                 ("refine", C.c_int), ("refine_rtol", C.c_double), ("eig_solve", C.c_int),
-                ("tau_sub", C.c_void_p)]
+                ("eig_split", C.c_int), ("tau_sub", C.c_void_p)]
 
 
 class SetupInfo(C.Structure):
@@ -81,7 +81,8 @@ class SetupInfo(C.Structure):
                 ("eig_sweeps", C.c_int), ("eig_block", C.c_int),
                 ("eig_max_resid", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64),
-                ("eig_stalled", C.c_int), ("symv_tiles", C.c_int), ("eig_solve", C.c_int)]
+                ("eig_stalled", C.c_int), ("symv_tiles", C.c_int), ("eig_solve", C.c_int),
+                ("eig_split", C.c_int)]
 
 
 class PcgInfo(C.Structure):
@@ -207,7 +208,10 @@ def opts_from_problem(prob, **kw):
     else:
         o.nev = prob.nev
     o.precision = GENEO_PREC_MIXED if prob.precision == "mixed" else GENEO_PREC_FP64
+    names = {f[0] for f in Opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError("geneo_opts_t has no field %r" % k)
         setattr(o, k, v)
     return o
 

@@ -289,12 +289,12 @@ def make_stream(seed=0, count=200, rate=None, mean_service_s=0.05, sizes2d=(128,
         if u < mix[2] + mix[1]:
             n = int(rng.choice(sizes3d))
             parts = max(1, n // 12)
-            p = synth.config3_layers(seed=int(rng.integers(1 << 30)), n=n, parts=parts, ovl=1,
+            p = synth.layers_3d(seed=int(rng.integers(1 << 30)), n=n, parts=parts, ovl=1,
                                      nev=12, precision="mixed")
         else:
             n = int(rng.choice(sizes2d))
             parts = max(1, n // 32)
-            p = synth.config2_grf(seed=int(rng.integers(1 << 30)), n=n, parts=parts, ovl=2,
+            p = synth.grf_2d(seed=int(rng.integers(1 << 30)), n=n, parts=parts, ovl=2,
                                   precision="mixed", inclusions=max(1, (24 * n * n) // (512 * 512)))
         r = Request(t, rid, "new", problem=p)
         reqs.append(r)

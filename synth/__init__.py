@@ -10,10 +10,10 @@ from .problems import (  # noqa: F401
     Problem,
     darcy_problem,
     elasticity_problem,
-    config1_channels,
-    config2_grf,
-    config3_layers,
-    config4_laminate,
+    channels_2d,
+    grf_2d,
+    layers_3d,
+    laminate_3d,
     layered_2d,
     CONFIGS,
 )

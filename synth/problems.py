@@ -114,37 +114,37 @@ def elasticity_problem(name, cvoigt, ne, parts, ovl, dirichlet, load, h,
 
 # ------------------------------------------------------------- configs ---
 
-def config1_channels(seed=0, n=64, parts=4, ovl=2, nev=8, precision="fp64",
+def channels_2d(seed=0, n=64, parts=4, ovl=2, nev=8, precision="fp64",
                      n_channels=6):
     """2D Darcy, unit square, u=0 on the boundary, f=1, k=1e6 channels."""
     k, starts = F.channel_field(n, n_channels=n_channels, seed=seed,
                                 first_row=2, last_row=n - 4)
-    p = darcy_problem("config1_channels_%d" % n, k, (parts, parts), ovl,
+    p = darcy_problem("channels_%d" % n, k, (parts, parts), ovl,
                       nev=nev, precision=precision)
     p.meta["channel_rows"] = starts.tolist()
     p.meta["seed"] = seed
     return p
 
 
-def config2_grf(seed=0, n=512, parts=16, ovl=2, tau=0.1, nev_max=16,
+def grf_2d(seed=0, n=512, parts=16, ovl=2, tau=0.1, nev_max=16,
                 precision="mixed", inclusions=24):
     """2D Darcy, k = exp(GRF) with discs of k=1e6; threshold selection."""
     g = F.grf_exponential_2d(n, var=4.0, corr=0.05, seed=seed)
     k = np.exp(g)
     if inclusions:
         k[F.inclusions_2d(n, count=inclusions, seed=seed + 1000)] = 1e6
-    p = darcy_problem("config2_grf_%d" % n, k, (parts, parts), ovl,
+    p = darcy_problem("grf_%d" % n, k, (parts, parts), ovl,
                       tau=tau, nev_max=nev_max, nev=nev_max,
                       precision=precision)
     p.meta["seed"] = seed
     return p
 
 
-def config3_layers(seed=0, n=96, parts=8, ovl=1, nev=12, precision="mixed"):
+def layers_3d(seed=0, n=96, parts=8, ovl=1, nev=12, precision="mixed"):
     """3D Darcy on the unit cube with random-thickness z-layers of high contrast."""
     kz = F.z_layers_3d(n, seed=seed)
     k = np.broadcast_to(kz[:, None, None], (n, n, n)).copy()
-    p = darcy_problem("config3_layers_%d" % n, k, (parts, parts, parts), ovl,
+    p = darcy_problem("layers_%d" % n, k, (parts, parts, parts), ovl,
                       nev=nev, precision=precision)
     p.meta["seed"] = seed
     return p
@@ -164,7 +164,7 @@ def laminate_stack():
     return stack
 
 
-def config4_laminate(seed=0, ne=(128, 32, 24), parts=(16, 4, 4), ovl=1,
+def laminate_3d(seed=0, ne=(128, 32, 24), parts=(16, 4, 4), ovl=1,
                      nev=24, precision="mixed"):
     """3D anisotropic elasticity of a clamped laminate under a body load.
 
@@ -184,7 +184,7 @@ def config4_laminate(seed=0, ne=(128, 32, 24), parts=(16, 4, 4), ovl=1,
     C = np.empty((nz, ny, nx, 6, 6))
     for iz in range(nz):
         C[iz] = mats[zmat[iz]]
-    p = elasticity_problem("config4_laminate", C, ne, parts, ovl,
+    p = elasticity_problem("laminate_%dx%dx%d" % tuple(ne), C, ne, parts, ovl,
                            dirichlet=0b000001, load=(0.0, 0.0, -1.0),
                            h=(1.0, 1.0, 1.0), nev=nev, precision=precision)
     p.meta["seed"] = seed
@@ -208,9 +208,10 @@ def layered_2d(n=40, parts=4, ovl=2, layers=8, contrast=1e6, nev=4,
                          dirichlet=dirichlet, nev=nev, precision=precision)
 
 
+# the full-size workloads, by name
 CONFIGS = {
-    "config1": config1_channels,
-    "config2": config2_grf,
-    "config3": config3_layers,
-    "config4": config4_laminate,
+    "channels_64": channels_2d,
+    "grf_512": grf_2d,
+    "layers_96": layers_3d,
+    "laminate_128x32x24": laminate_3d,
 }

@@ -10,10 +10,10 @@ residuals in extended precision), the iteration count, the CG-Lanczos
 condition estimate, the coarse dimension and the per-subdomain eigenvector
 counts.
 
-    python tests/golden/make_fullsize_golden.py config2 [config3 config4]
+    python tests/golden/make_fullsize_golden.py grf_512 [layers_96 laminate_128x32x24]
 
-config2 (512^2 Darcy) takes a few minutes, config3 (96^3) and config4 (the
-laminate) about an hour each on 8 cores.
+grf_512 (512^2 Darcy) takes a few minutes, layers_96 (96^3) and the laminate
+about an hour each on 8 cores.
 """
 import multiprocessing as mp
 import os
@@ -75,7 +75,7 @@ def run(name, procs):
 
 
 def main():
-    names = sys.argv[1:] or ["config2"]
+    names = sys.argv[1:] or ["grf_512"]
     procs = int(os.environ.get("GOLDEN_PROCS", "8"))
     for name in names:
         run(name, procs)

@@ -78,23 +78,23 @@ def _sarkis(prob):
 
 
 SMALL_PROBLEMS = {
-    "config1": lambda: synth.config1_channels(0),
+    "channels": lambda: synth.channels_2d(0),
     "darcy3d_ragged": lambda: synth.darcy_problem(
         "d3", np.exp(np.random.Generator(np.random.PCG64(4)).normal(size=(7, 9, 10))),
         (2, 2, 3), 1, nev=6),
-    "laminate_small": lambda: synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1), nev=8),
+    "laminate_small": lambda: synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1), nev=8),
     "layered_neumann_sides": lambda: synth.layered_2d(n=40, parts=4, ovl=2, layers=8,
                                                       contrast=1e6, nev=4),
     # threshold rule with nev_max = 16: eigen block of 32 columns, the block
     # width of the 512^2 Darcy workload
-    "grf_threshold": lambda: synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2),
+    "grf_threshold": lambda: synth.grf_2d(seed=3, n=48, parts=2, ovl=2, inclusions=2),
     # nev = 24: eigen block of 48 columns
     "layered_wide_block": lambda: synth.layered_2d(n=32, parts=2, ovl=1, layers=4,
                                                    contrast=1e4, nev=24),
     # the smooth (Sarkis) partition of unity, 2D Darcy and 3D elasticity
     "sarkis_layered": lambda: _sarkis(synth.layered_2d(n=40, parts=4, ovl=3, layers=8,
                                                        contrast=1e6, nev=4)),
-    "sarkis_laminate": lambda: _sarkis(synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1),
+    "sarkis_laminate": lambda: _sarkis(synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1),
                                                               ovl=2, nev=8)),
 }
 

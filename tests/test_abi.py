@@ -47,10 +47,10 @@ def test_default_opts():
 
 
 @pytest.mark.parametrize("make", [
-    lambda: synth.config1_channels(0),
-    lambda: synth.config1_channels(0, n=30, parts=3, n_channels=3, ovl=1),
+    lambda: synth.channels_2d(0),
+    lambda: synth.channels_2d(0, n=30, parts=3, n_channels=3, ovl=1),
     lambda: synth.darcy_problem("t", np.ones((7, 9, 10)), (2, 2, 3), 1),
-    lambda: synth.config4_laminate(ne=(16, 4, 5), parts=(4, 1, 1)),
+    lambda: synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1)),
 ])
 def test_q1_sizes_match_oracle(make):
     from paper_1906_10944_amd import geneo as G
@@ -67,7 +67,7 @@ def test_q1_sizes_match_oracle(make):
 
 def test_q1_sizes_rejects_bad_grids():
     from paper_1906_10944_amd import geneo as G
-    p = synth.config1_channels(0)
+    p = synth.channels_2d(0)
     g = G.grid_from_problem(p)
     g.ovl = 0
     with pytest.raises(G.GeneoError) as e:

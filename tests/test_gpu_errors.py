@@ -28,7 +28,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def small():
     need_gpu()
-    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    prob = synth.grf_2d(seed=3, n=48, parts=2, ovl=2, inclusions=2)
     return prob, gpu_assemble(prob)
 
 

@@ -43,7 +43,7 @@ U32 = 2.0 ** -24
 @pytest.fixture(scope="module")
 def full():
     need_gpu()
-    prob = synth.CONFIGS["config2"](seed=0)
+    prob = synth.CONFIGS["grf_512"](seed=0)
     say("[fullsize] ndof", prob.ndof, "nsub", prob.nsub)
     A, b = fem.assemble(prob)
     subs, _ = decomp.build(prob)
@@ -207,7 +207,7 @@ def test_fullsize_pcg_and_operator(full, bench_handle):
 
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                      "fullsize_config2_seed0.npz")
+                      "fullsize_grf_512_seed0.npz")
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])

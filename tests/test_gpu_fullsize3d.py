@@ -40,11 +40,11 @@ U32 = 2.0 ** -24
 U64 = np.finfo(float).eps / 2
 
 # (boundary subdomain, floating interior subdomain)
-SAMPLES = {"config3": (0, 3 + 8 * (3 + 8 * 3)),     # corner; (3, 3, 3)
-           "config4": (0, 7 + 16 * (1 + 4 * 1))}    # clamped end; (7, 1, 1)
+SAMPLES = {"layers_96": (0, 3 + 8 * (3 + 8 * 3)),              # corner; (3, 3, 3)
+           "laminate_128x32x24": (0, 7 + 16 * (1 + 4 * 1))}  # clamped end; (7, 1, 1)
 
 
-@pytest.fixture(scope="module", params=["config3", "config4"])
+@pytest.fixture(scope="module", params=["layers_96", "laminate_128x32x24"])
 def big(request):
     need_gpu()
     prob = synth.CONFIGS[request.param](seed=0)

@@ -29,8 +29,8 @@ def _run(sysm, prob, precision, r):
 def test_reused_blocks_give_the_same_operator(precision):
     need_gpu()
     from paper_1906_10944_amd import geneo as G
-    pb = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
-    pa = synth.config2_grf(seed=4, n=48, parts=2, ovl=2, inclusions=2)
+    pb = synth.grf_2d(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    pa = synth.grf_2d(seed=4, n=48, parts=2, ovl=2, inclusions=2)
     sb, sa = gpu_assemble(pb), gpu_assemble(pa)
     r = np.random.default_rng(7).standard_normal(pb.ndof)
     G.geneo_trim()
@@ -54,7 +54,7 @@ def test_symv_tiles_give_the_same_operator():
     chosen by timing) change the work split, never the arithmetic."""
     need_gpu()
     from paper_1906_10944_amd import geneo as G
-    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    prob = synth.grf_2d(seed=3, n=48, parts=2, ovl=2, inclusions=2)
     sysm = gpu_assemble(prob)
     r = np.random.default_rng(9).standard_normal(prob.ndof)
     outs = {}
@@ -77,7 +77,7 @@ def test_sweep_flags_read_late_or_at_once_give_the_same_operator():
     for bit."""
     need_gpu()
     from paper_1906_10944_amd import geneo as G
-    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    prob = synth.grf_2d(seed=3, n=48, parts=2, ovl=2, inclusions=2)
     sysm = gpu_assemble(prob)
     r = np.random.default_rng(11).standard_normal(prob.ndof)
     L = G.lib()
@@ -99,31 +99,39 @@ def test_sweep_flags_read_late_or_at_once_give_the_same_operator():
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("nev,tau", [(4, None), (None, 0.1)], ids=["b16", "b32"])
+@pytest.mark.parametrize("nev,tau", [(4, None), (None, 0.1), (24, None)],
+                         ids=["b16", "b32", "b48"])
 def test_every_eigen_solve_kernel_gives_the_same_operator(nev, tau):
-    """The eigen sweeps' triangular solves have two kernels for blocks of
-    16 and 32 columns (two tile rows per wavefront, or one with deeper load
-    pipelines) that form the same sums in the same order; the setup times
-    them and keeps the faster one.  Forced either way (and tuned), the
-    sweep count, the eigenvalues, the coarse basis and the operator agree
-    bit for bit."""
+    """The eigen sweeps' triangular solves have two kernels (two tile rows
+    per wavefront, or one with deeper load pipelines), each also on
+    16-column blocks with b / 16 workgroups per subdomain; all form the same
+    sums in the same order, and the setup times them and keeps the fastest.
+    Forced every way (and tuned), the sweep count, the eigenvalues, the
+    coarse basis and the operator agree bit for bit."""
     need_gpu()
     from paper_1906_10944_amd import geneo as G
-    prob = synth.config2_grf(seed=3, n=48, parts=2, ovl=2, inclusions=2)
+    prob = synth.grf_2d(seed=3, n=48, parts=2, ovl=2, inclusions=2)
     if tau is None:
         prob.tau, prob.nev = None, nev
     sysm = gpu_assemble(prob)
     r = np.random.default_rng(13).standard_normal(prob.ndof)
     outs = []
-    for v in (1, 2, 0):
-        h = gpu_setup(sysm, prob, precision=1, eig_solve=v)
+    never, always = -1, prob.nsub
+    for v, sp in ((1, never), (2, never), (1, always), (2, always), (0, 0)):
+        h = gpu_setup(sysm, prob, precision=1, eig_solve=v, eig_split=sp)
         info = G.geneo_get_setup_info(h)
         m, lam = G.geneo_get_eigenvalues(h, prob.nsub)
         zoff, z, ah = G.geneo_get_coarse(h, prob.nsub)
         outs.append((info["eig_sweeps"], m, lam, z, ah, gpu_apply(h, sysm, r)))
-        say("[eig solve] forced", v, "used", info["eig_solve"], "block", info["eig_block"],
-            "sweeps", info["eig_sweeps"])
-        assert info["eig_solve"] == v or (v == 0 and info["eig_solve"] in (1, 2))
+        say("[eig solve] forced", v, sp, "used", info["eig_solve"], info["eig_split"], "block",
+            info["eig_block"], "sweeps", info["eig_sweeps"])
+        assert info["eig_block"] == {4: 16, None: 32, 24: 48}[nev]
+        if v:
+            assert info["eig_solve"] == (v if info["eig_block"] <= 32 else 2)
+        if sp == never or info["eig_block"] == 16:
+            assert info["eig_split"] == 0
+        elif sp == always:
+            assert info["eig_split"] == prob.nsub
         h.close()
     for got in outs[1:]:
         assert got[0] == outs[0][0]

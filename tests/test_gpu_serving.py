@@ -12,10 +12,10 @@ def _stream(t_scale):
     import synth
     from paper_1906_10944_amd.serve import Request
     probs = [
-        synth.config2_grf(seed=3, n=64, parts=2, ovl=2, inclusions=2),
-        synth.config3_layers(seed=4, n=24, parts=2, ovl=1, nev=6),
-        synth.config2_grf(seed=5, n=96, parts=3, ovl=2, inclusions=3),
-        synth.config1_channels(seed=6, n=64, parts=2, n_channels=3, nev=4, precision="mixed"),
+        synth.grf_2d(seed=3, n=64, parts=2, ovl=2, inclusions=2),
+        synth.layers_3d(seed=4, n=24, parts=2, ovl=1, nev=6),
+        synth.grf_2d(seed=5, n=96, parts=3, ovl=2, inclusions=3),
+        synth.channels_2d(seed=6, n=64, parts=2, n_channels=3, nev=4, precision="mixed"),
     ]
     reqs, rid, t = [], 0, 0.0
     for p in probs:
@@ -113,7 +113,7 @@ def test_eviction_with_interleaved_repeats():
     import synth
     from paper_1906_10944_amd.serve import Request, Server, footprint_bytes, resident_bytes
     rng = np.random.Generator(np.random.PCG64(17))
-    probs = [synth.config2_grf(seed=20 + k, n=64, parts=2, ovl=2, inclusions=2) for k in range(4)]
+    probs = [synth.grf_2d(seed=20 + k, n=64, parts=2, ovl=2, inclusions=2) for k in range(4)]
     reqs, rid = [], 0
     for k, p in enumerate(probs):
         reqs.append(Request(0.0, rid, "new", problem=p))

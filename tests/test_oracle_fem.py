@@ -83,7 +83,7 @@ def test_total_load_equals_f_times_volume():
 
 
 def test_dirichlet_elimination():
-    p = synth.config1_channels(0, n=16, parts=2, n_channels=2)
+    p = synth.channels_2d(0, n=16, parts=2, n_channels=2)
     A, b = fem.assemble(p)
     d = fem.dirichlet_mask(p)
     Ad = A.toarray()

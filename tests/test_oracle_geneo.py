@@ -112,7 +112,7 @@ def _rbm_local(prob, dofs):
 
 
 def _small_laminate(nx=12):
-    p4 = synth.config4_laminate(ne=(nx, 2, 5), parts=(3, 1, 1), nev=8)
+    p4 = synth.laminate_3d(ne=(nx, 2, 5), parts=(3, 1, 1), nev=8)
     return p4
 
 
@@ -247,7 +247,7 @@ def test_coarse_cholesky_rejects_repeated_basis_vector():
     """A_H is SPD iff the columns of Z are independent (Def. 2): a repeated
     column makes it singular, and the factor must say so whatever sign the
     rounding leaves on the vanishing pivot."""
-    p = synth.config1_channels(0, n=16, parts=2, n_channels=2, nev=3)
+    p = synth.channels_2d(0, n=16, parts=2, n_channels=2, nev=3)
     A, _ = fem.assemble(p)
     g = geneo.setup(p, A=A)
     Z = g.Z.toarray()

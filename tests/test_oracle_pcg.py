@@ -14,8 +14,8 @@ from oracle import fem, geneo, pcg
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def test_pcg_matches_direct_solve_config1():
-    p = synth.config1_channels(0)
+def test_pcg_matches_direct_solve_channels():
+    p = synth.channels_2d(0)
     A, b = fem.assemble(p)
     g = geneo.setup(p, A=A)
     res = pcg.pcg(A, b, g.apply, rtol=1e-10)
@@ -48,7 +48,7 @@ def test_single_subdomain_geneo_is_exact_inverse():
 
 
 def test_lanczos_kappa_matches_preconditioned_spectrum():
-    p = synth.config1_channels(0, n=24, parts=3, n_channels=3, nev=2)
+    p = synth.channels_2d(0, n=24, parts=3, n_channels=3, nev=2)
     A, b = fem.assemble(p)
     g = geneo.setup(p, A=A)
     free = ~fem.dirichlet_mask(p)

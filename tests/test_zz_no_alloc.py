@@ -38,8 +38,8 @@ def _solve_both(prob, nrhs, refine):
 def test_noalloc_matches_pcg_solve_two_calls_second_smaller():
     need_gpu()
     from paper_1906_10944_amd import geneo as G
-    probs = [synth.config2_grf(seed=5, n=96, parts=3, ovl=2, inclusions=3),
-             synth.config1_channels(1, n=32, parts=2, n_channels=3, nev=4)]
+    probs = [synth.grf_2d(seed=5, n=96, parts=3, ovl=2, inclusions=3),
+             synth.channels_2d(1, n=32, parts=2, n_channels=3, nev=4)]
     # the first handle refines its solutions once (the correction solve and
     # its residual also live in the fixed array), the second does not
     for prob, nrhs, refine in zip(probs, (2, 1), (1, 0)):
@@ -69,7 +69,7 @@ def test_noalloc_matches_pcg_solve_two_calls_second_smaller():
 def test_noalloc_rejects_sizes_beyond_its_array():
     need_gpu()
     from paper_1906_10944_amd import geneo as G
-    prob = synth.config1_channels(1, n=32, parts=2, n_channels=3, nev=4)
+    prob = synth.channels_2d(1, n=32, parts=2, n_channels=3, nev=4)
     sysm = gpu_assemble(prob)
     h = gpu_setup(sysm, prob)
     x = torch.zeros_like(sysm.b)
@@ -78,7 +78,7 @@ def test_noalloc_rejects_sizes_beyond_its_array():
     assert e.value.code == G.GENEO_ERR_ARG and "maxit <= 4096" in str(e.value)
     h.close()
     # 1025^2 = 1,050,625 dofs > 2^20
-    big = synth.config2_grf(seed=1, n=1024, parts=32, ovl=2, inclusions=4)
+    big = synth.grf_2d(seed=1, n=1024, parts=32, ovl=2, inclusions=4)
     sysm = gpu_assemble(big)
     h = gpu_setup(sysm, big, precision=1)
     x = torch.zeros_like(sysm.b)
