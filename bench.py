@@ -196,8 +196,8 @@ def prof_query(G, name):
 
 PROF_KERNELS = ["densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
                 "trtri_dirichlet", "densify_shifted", "chol_shifted_f64", "trsm_bwd",
-                "trsm_fwd", "bapply", "rayleigh_ritz", "orth", "coarse_chol",
-                "lauum_dirichlet", "symv", "symv_cols", "cheb_combine"]
+                "trsm_fwd", "trsm_bwd_split", "trsm_fwd_split", "bapply", "rayleigh_ritz",
+                "orth", "coarse_chol", "lauum_dirichlet", "symv", "symv_cols", "cheb_combine"]
 
 
 def kernel_profile(runner, precision):
@@ -246,6 +246,13 @@ def prof_symbol(name, info):
             ad, bp = {16: (2, "true"), 32: (1, "true"), 48: (1, "false")}[b]
             return "k_trsm_w1<%d, %s, %d, %s, %d>" % (b // 16, bwd, ad, bp, b)
         return "k_trsm_bwd" if bwd == "true" else "k_trsm_fwd"
+    if name in ("trsm_fwd_split", "trsm_bwd_split"):
+        # 16-column blocks; the split kernel is the unsplit one's choice
+        # unless that is the b = 48 default (its split tuning is not reported)
+        b, bwd = info.get("eig_block", 32), "true" if name == "trsm_bwd_split" else "false"
+        if info.get("eig_solve", 1) == 1 and b <= 32:
+            return "k_trsm_win<1, %s, %d>" % (bwd, b)
+        return "16-column k_trsm_win / k_trsm_w1 <1, %s, ..., %d>" % (bwd, b)
     if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
         return "tile-column step kernels"
     return PROF_SYMBOL.get(name, name)

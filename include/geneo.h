@@ -236,6 +236,11 @@ typedef struct {
                          as the host knows): -1 = never, 0 = a limit timed
                          at the first setup of the shape.  Every eig_solve
                          / eig_split choice gives bitwise the same result. */
+  int envelope;       /* 1 = the local factorisations and the eigen solves
+                         skip the tiles outside each matrix's envelope
+                         (left of the first entry of each row: zero in the
+                         Cholesky factor, as no fill reaches them); 0 =
+                         dense.  Both give bitwise the same result. */
   const double* tau_sub; /* host [nsub], or NULL: per-subdomain thresholds
                          tau_j > 0 replacing tau (take the eigenvalues
                          < tau_j, at most nev_max of them), e.g. the
@@ -247,7 +252,7 @@ typedef struct {
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-8, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
  * symv_tiles 0, refine 0, refine_rtol 1e-6, eig_solve 0, eig_split 0,
- * tau_sub NULL. */
+ * envelope 1, tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;
@@ -404,8 +409,10 @@ int geneo_spmv(const geneo_csr_t* A, const double* x, double* y, void* stream);
  * total_ms (event time), launches, bytes and flops (either may be NULL).
  * Names: "densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
  * "trtri_dirichlet", "lauum_dirichlet", "densify_shifted",
- * "chol_shifted_f64", "trsm_bwd", "trsm_fwd", "bapply", "rayleigh_ritz",
- * "cheb_combine", "orth", "coarse_chol", "symv", "symv_cols".  While timing is
+ * "chol_shifted_f64", "trsm_bwd", "trsm_fwd", "trsm_bwd_split",
+ * "trsm_fwd_split" (the eigen solves on 16-column blocks), "bapply",
+ * "rayleigh_ritz", "cheb_combine", "orth", "coarse_chol", "symv",
+ * "symv_cols".  While timing is
  * on, the eigen sweeps read their convergence flags after every sweep
  * (instead of one sweep late), so that the byte counts follow the active
  * set exactly.

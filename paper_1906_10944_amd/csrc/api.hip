@@ -340,6 +340,31 @@ double tridiag_eig(const double* d, const double* e, int n, int k) {
 
 double packed(double n) { return n * (n + 1.0) * 0.5; }
 
+// Work inside tile envelopes (host copy E of the first nonzero tile column
+// per tile row, at the diagonal tile offsets doff): per matrix the stored
+// tiles, and over all matrices the tile products of a left-looking
+// Cholesky, sum over the envelope tiles (i, k) of k - E(i).  Used for the
+// algorithmic bytes and flops of the kernels that skip the zero tiles.
+struct EnvWork {
+  std::vector<double> tiles;  // per matrix (0 for matrices not listed)
+  double prods = 0.0;         // Cholesky tile products
+  double inv_prods = 0.0;     // tile products of X = L^{-1} (sum over the
+                              // tiles (i, c) of i - max(E(i), c))
+};
+EnvWork env_work(const std::vector<int>& E, const std::vector<int64_t>& doff,
+                 const std::vector<int>& nt, const std::vector<int>& jobs) {
+  EnvWork w;
+  w.tiles.assign(nt.size(), 0.0);
+  for (int j : jobs)
+    for (int i = 0; i < nt[j]; ++i) {
+      const double e = E[doff[j] + i], width = i - e + 1;
+      w.tiles[j] += width;
+      w.prods += width * (width - 1.0) * 0.5;
+      w.inv_prods += (e + 1.0) * (i - e) + (i - e - 1.0) * (i - e) * 0.5;
+    }
+  return w;
+}
+
 }  // namespace
 
 // Kernels of the eigen sweeps' triangular solves (see tune_trsm).
@@ -580,6 +605,15 @@ struct SetupScratch {
   DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart,
       cpiv;
   DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol, orderN;
+  // tile envelopes (first nonzero tile column per tile row, last nonzero
+  // tile row per tile column) of the shifted, FP32 and FP64 local matrices
+  DBuf<int> envNE, envNR, envDE, envDR, env64E, env64R;
+  // the envelopes the factorisations and solves use (NULL: dense, option
+  // envelope = 0)
+  const int *uNE = nullptr, *uNR = nullptr, *uDE = nullptr, *uDR = nullptr, *u64E = nullptr,
+            *u64R = nullptr;
+  std::vector<double> envN_tiles;  // stored tiles per shifted factor
+  std::vector<int> envD_host;      // host copy of envDE (timing mode only)
   DBuf<double> bval;
   DBuf<int> brpos;
   DBuf<int2> brows;
@@ -637,7 +671,7 @@ TrsmChoice tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, 
   auto time = [&](int v, int split, int n) {
     auto run = [&]() {
       HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, n, b, X.U.p,
-                             X.T.p, nullptr, X.orderN.p, v, split, sb));
+                             X.T.p, nullptr, X.orderN.p, X.uNE, X.uNR, v, split, sb));
     };
     run();
     HIPCHK(hipEventRecord(e0, sb));
@@ -755,23 +789,34 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
     X.jobs.upload(largest_first(h->nd_host), st);
     X.L32.alloc(h->LD.ntiles * TSQ);
     X.D32.alloc(h->LD.ndiag * TSQ);
-    double pk = 0.0, fl = 0.0;
-    for (int j = 0; j < nsub; ++j) {
-      pk += packed(h->nd_host[j]);
-      fl += std::pow((double)h->nd_host[j], 3) / 3.0;
-    }
+    X.envDE.alloc(h->LD.ndiag);
+    X.envDR.alloc(h->LD.ndiag);
     {
       ProfScope ps("densify_dirichlet", st, 4.0 * h->LD.ntiles * TSQ, 0.0);
       HIPCHK(hipMemsetAsync(X.L32.p, 0, X.L32.n * sizeof(float), st));
+      HIPCHK(launch_env_init(X.envDE.p, h->doffD.p, h->ntD.p, nullptr, nsub, st));
       HIPCHK(launch_densify_dirichlet(true, X.L32.p, h->toffD.p, h->ntD.p, h->voffD.p, X.jobs.p,
                                       nsub, S->sub_ptr, S->sub_idx, h->dmap.p, h->dglob.p,
                                       h->dscale.p, A,
-                                      *std::max_element(h->LD.nt.begin(), h->LD.nt.end()), st));
+                                      *std::max_element(h->LD.nt.begin(), h->LD.nt.end()),
+                                      X.envDE.p, h->doffD.p, st));
+      HIPCHK(launch_env_finish(X.envDE.p, X.envDR.p, h->doffD.p, h->ntD.p, nullptr, nsub, st));
+      if (o.envelope) X.uDE = X.envDE.p, X.uDR = X.envDR.p;
     }
     {
-      ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * pk, fl);
+      // algorithmic work inside the envelopes (read back in the timing mode
+      // only, where it is reported)
+      double tl = 0.0, fl = 0.0;
+      if (prof_on() && X.uDE) {
+        X.envD_host = download(X.envDE.p, h->LD.ndiag, st);
+        const EnvWork ew = env_work(X.envD_host, h->LD.doff, h->LD.nt, all);
+        for (double t : ew.tiles) tl += t;
+        fl = 2.0 * TS * TS * TS * ew.prods + (double)TS * TS * TS * tl;
+      }
+      ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * TSQ * tl, fl);
       HIPCHK(launch_chol_batched(CholRole::LocalF32, X.L32.p, h->toffD.p, h->ntD.p, X.D32.p, h->doffD.p,
-                                 X.status.p, X.jobs.p, nsub, o.pivot_tol, st));
+                                 X.status.p, X.jobs.p, nsub, o.pivot_tol, X.uDE, X.uDR,
+                                 st));
     }
     // the shifted factorisation follows the FP32 one on the device (an
     // event, no host round trip) while the host reads the pivot tests
@@ -807,9 +852,14 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
         fl32 += std::pow((double)h->nd_host[j], 3) / 3.0;
       }
       {
-        ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, fl32);
+        // the inverse of a banded factor is dense; its products skip the
+        // zero tiles of L
+        double flt = fl32;
+        if (!X.envD_host.empty())
+          flt = 2.0 * TS * TS * TS * env_work(X.envD_host, h->LD.doff, h->LD.nt, ok32).inv_prods;
+        ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, flt);
         HIPCHK(launch_trtri(true, X.L32.p, X.D32.p, X.XT32.p, h->toffD.p, h->doffD.p, h->ntD.p,
-                            X.tjobs32.p, (int)tj.size(), st));
+                            X.tjobs32.p, (int)tj.size(), X.uDE, st));
       }
       h->S32.alloc(h->LD.ntiles * TSQ);
       h->W32.alloc(h->LD.ntiles * TS);
@@ -841,6 +891,8 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
     if (!f64list.empty()) {
       X.L64.alloc(tt * TSQ);
       X.D64.alloc(dd * TSQ);
+      X.env64E.alloc(dd);
+      X.env64R.alloc(dd);
       double pk64 = 0.0, fl64 = 0.0;
       int mx = 0;
       for (int j : f64list) {
@@ -851,21 +903,36 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
       {
         ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
         HIPCHK(hipMemsetAsync(X.L64.p, 0, X.L64.n * sizeof(double), st));
+        HIPCHK(launch_env_init(X.env64E.p, h->doff64.p, h->ntD.p, h->jobs64.p, h->njobs64, st));
         HIPCHK(launch_densify_dirichlet(false, X.L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
                                         h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
-                                        h->dmap.p, h->dglob.p, h->dscale.p, A, mx, st));
+                                        h->dmap.p, h->dglob.p, h->dscale.p, A, mx, X.env64E.p,
+                                        h->doff64.p, st));
+        HIPCHK(launch_env_finish(X.env64E.p, X.env64R.p, h->doff64.p, h->ntD.p, h->jobs64.p,
+                                 h->njobs64, st));
+        if (h->opts.envelope) X.u64E = X.env64E.p, X.u64R = X.env64R.p;
       }
       {
         // a few refactors (mixed mode): tile-column steps over many short
-        // workgroups, which leave the CUs to the eigen sweeps in between; a
-        // full batch (FP64 mode): one workgroup per matrix
+        // workgroups, which leave the CUs to the eigen sweeps in between
+        // (dense); a full batch (FP64 mode): one workgroup per matrix,
+        // inside the envelopes
+        const bool steps = h->njobs64 <= kStepCholMax;
+        if (!steps && prof_on() && X.u64E) {
+          const EnvWork ew = env_work(download(X.env64E.p, dd, st), doff64,
+                                      h->LD.nt, f64list);
+          pk64 = 0.0;
+          for (double t : ew.tiles) pk64 += TSQ * t;
+          fl64 = 2.0 * TS * TS * TS * ew.prods + (double)TS * pk64;
+        }
         ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
-        if (h->njobs64 <= kStepCholMax) {
+        if (steps) {
           HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
                                    h->jobs64.p, h->njobs64, mx, X.status.p, st));
         } else {
           HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p,
-                                     h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0, st));
+                                     h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0,
+                                     X.u64E, X.u64R, st));
         }
       }
       std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
@@ -876,7 +943,7 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
       {
         ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
         HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, X.XT64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                            X.tjobs64.p, (int)tj.size(), st));
+                            X.tjobs64.p, (int)tj.size(), X.u64E, st));
       }
       h->S64.alloc(tt * TSQ);
       h->W64.alloc(tt * TS);
@@ -1017,21 +1084,35 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   if (after) HIPCHK(hipStreamWaitEvent(sb, after, 0));
   eigen_prepare(h, X, LN, S, Ao, nnzB, sb);
   tm[0].start(sb);
-  double pkN = 0.0, flN = 0.0;
-  for (int j = 0; j < nsub; ++j) {
-    pkN += packed(h->nN_host[j]);
-    flN += std::pow((double)h->nN_host[j], 3) / 3.0;
-  }
+  X.envNE.alloc(LN.ndiag);
+  X.envNR.alloc(LN.ndiag);
   {
     ProfScope ps("densify_shifted", sb, 8.0 * LN.ntiles * TSQ, 0.0);
     HIPCHK(hipMemsetAsync(X.G.p, 0, X.G.n * sizeof(double), sb));
+    HIPCHK(launch_env_init(X.envNE.p, X.doffN.p, X.ntN.p, nullptr, nsub, sb));
     HIPCHK(launch_densify_shifted(X.G.p, X.toffN.p, X.ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
-                                  o.sigma, sb));
+                                  o.sigma, X.envNE.p, X.doffN.p, sb));
+    HIPCHK(launch_env_finish(X.envNE.p, X.envNR.p, X.doffN.p, X.ntN.p, nullptr, nsub, sb));
+    if (o.envelope) X.uNE = X.envNE.p, X.uNR = X.envNR.p;
+  }
+  // algorithmic work inside the envelopes: read back in the timing mode
+  // only (where it is reported); otherwise the dense counts stand in
+  double tlN = 0.0, flN = 0.0;
+  if (prof_on() && X.uNE) {
+    std::vector<int> all(nsub);
+    for (int j = 0; j < nsub; ++j) all[j] = j;
+    const EnvWork ew = env_work(download(X.envNE.p, LN.ndiag, sb), LN.doff, LN.nt, all);
+    X.envN_tiles = ew.tiles;
+    for (double t : ew.tiles) tlN += t;
+    flN = 2.0 * TS * TS * TS * ew.prods + (double)TS * TS * TS * tlN;
+  } else {
+    X.envN_tiles.assign(nsub, 0.0);
+    for (int j = 0; j < nsub; ++j) X.envN_tiles[j] = packed(LN.nt[j]);
   }
   {
-    ProfScope ps("chol_shifted_f64", sb, 2.0 * 8.0 * pkN, flN);
+    ProfScope ps("chol_shifted_f64", sb, 2.0 * 8.0 * TSQ * tlN, flN);
     HIPCHK(launch_chol_batched(CholRole::ShiftedF64, X.G.p, X.toffN.p, X.ntN.p, X.DG.p, X.doffN.p, X.status2.p,
-                               X.jobsN.p, nsub, 0.0, sb));
+                               X.jobsN.p, nsub, 0.0, X.uNE, X.uNR, sb));
     X.pin_st2 = t_arena.active ? (int*)t_arena.take((size_t)nsub * sizeof(int)) : nullptr;
     if (X.pin_st2)
       HIPCHK(hipMemcpyAsync(X.pin_st2, X.status2.p, (size_t)nsub * sizeof(int),
@@ -1150,14 +1231,15 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     for (int j = 0; j < nsub; ++j) {
       if (!act[j]) continue;
       double nn = h->nN_host[j];
-      gb += 8.0 * packed(nn);
+      gb += 8.0 * TSQ * X.envN_tiles[j];
       vb += 2.0 * 8.0 * nn * b;
-      tf += 2.0 * packed(nn) * b;
+      tf += 2.0 * TSQ * X.envN_tiles[j] * b;
     }
     {
-      ProfScope ps("trsm_bwd", sb, gb + vb, tf);
+      ProfScope ps(ts(nact) > 1 ? "trsm_bwd_split" : "trsm_bwd", sb, gb + vb, tf);
       HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                             X.U.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact), sb));
+                             X.U.p, X.T.p, X.active.p, X.orderN.p, X.uNE, X.uNR,
+                             tv(nact), ts(nact), sb));
     }
     {
       // the B entries, the T rows they reach (once each) and the W rows
@@ -1167,9 +1249,10 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                            b, X.T.p, X.W.p, X.active.p, sb));
     }
     {
-      ProfScope ps("trsm_fwd", sb, gb + vb, tf);
+      ProfScope ps(ts(nact) > 1 ? "trsm_fwd_split" : "trsm_fwd", sb, gb + vb, tf);
       HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b,
-                             X.W.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact), sb));
+                             X.W.p, X.T.p, X.active.p, X.orderN.p, X.uNE, X.uNR,
+                             tv(nact), ts(nact), sb));
     }
     {
       ProfScope ps("rayleigh_ritz", sb, 2.0 * vb, 0.0);
@@ -1218,9 +1301,10 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
       }
       for (int k = 1; k < o.eig_cheb; ++k) {
         {
-          ProfScope ps("trsm_bwd", sb, gb + vb, tf);
+          ProfScope ps(ts(nact) > 1 ? "trsm_bwd_split" : "trsm_bwd", sb, gb + vb, tf);
           HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
-                                 b, X.U.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact),
+                                 b, X.U.p, X.T.p, X.active.p, X.orderN.p, X.uNE, X.uNR,
+                             tv(nact), ts(nact),
                                  sb));
         }
         {
@@ -1229,9 +1313,10 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
                                X.voffN.p, b, X.T.p, X.W.p, X.active.p, sb));
         }
         {
-          ProfScope ps("trsm_fwd", sb, gb + vb, tf);
+          ProfScope ps(ts(nact) > 1 ? "trsm_fwd_split" : "trsm_fwd", sb, gb + vb, tf);
           HIPCHK(launch_trsm_fwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub,
-                                 b, X.W.p, X.T.p, X.active.p, X.orderN.p, tv(nact), ts(nact),
+                                 b, X.W.p, X.T.p, X.active.p, X.orderN.p, X.uNE, X.uNR,
+                             tv(nact), ts(nact),
                                  sb));
         }
         {
@@ -1268,7 +1353,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   }
   // eigenvectors p = G^{-T} y
   HIPCHK(launch_trsm_bwd(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.voffN.p, nsub, b, X.Y.p,
-                         X.T.p, nullptr, X.orderN.p, tv(nsub), ts(nsub), sb));
+                         X.T.p, nullptr, X.orderN.p, X.uNE, X.uNR, tv(nsub), ts(nsub), sb));
   HIPCHK(launch_select(X.theta.p, nsub, b, o.nev, o.tau, h->tau_sub.p, o.nev_max, o.sigma, h->m.p,
                        X.lam.p, sb));
   h->m_host = download(h->m.p, nsub, sb);
@@ -1345,7 +1430,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     X.ljobsH.upload(lj, sb);
     X.XTH.alloc(tri_tiles(h->ntc) * TSQ);
     HIPCHK(launch_trtri(false, X.AHt.p, X.DH.p, X.XTH.p, h->htoff.p, X.hdoff.p, h->hnt.p,
-                        X.tjobsH.p, (int)tj.size(), sb));
+                        X.tjobsH.p, (int)tj.size(), nullptr, sb));
     h->SH.alloc(tri_tiles(h->ntc) * TSQ);
     h->WH.alloc(tri_tiles(h->ntc) * TS);
     HIPCHK(launch_lauum(false, X.XTH.p, h->SH.p, h->htoff.p, h->hnt.p, X.ljobsH.p, (int)lj.size(),
@@ -1984,6 +2069,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->refine_rtol = 1e-6;
   o->eig_solve = 0;
   o->eig_split = 0;
+  o->envelope = 1;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -2069,6 +2155,7 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "refine must be 0..8 with 0 < refine_rtol < 1");
     if (o.eig_solve < 0 || o.eig_solve > 2) fail(GENEO_ERR_ARG, "eig_solve must be 0, 1 or 2");
     if (o.eig_split < -1) fail(GENEO_ERR_ARG, "eig_split must be -1, 0 or positive");
+    if (o.envelope != 0 && o.envelope != 1) fail(GENEO_ERR_ARG, "envelope must be 0 or 1");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     settle_thread();  // the setup's scratch blocks become reusable

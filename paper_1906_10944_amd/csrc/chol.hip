@@ -155,18 +155,23 @@ template <> struct Vec16<double> { typedef double2 t; };
 // Bulk update, one item per wavefront per round, panel rows staged in LDS
 // chunk by chunk (double-buffered; one barrier per chunk).  All wavefronts
 // take part in staging and barriers, also those without an item.
+// Envelope (Ej: first nonzero tile column per tile row, NULL = dense;
+// rlast: the last tile row with a nonzero tile in the panel): only rows
+// k0 .. rlast are updated, row i from tile column Ej[i] on, and the panel
+// rows are staged from column Ej[k0] on (the smallest start of any item).
 template <typename T, int NW, int KB>
 __device__ __forceinline__ void bulk_staged(T* A, int nt, int k0, int kn, int w, int tid,
-                                            int lane, T* sY) {
+                                            int lane, T* sY, const int* Ej, int rlast) {
   typedef PotrfCfg<T, NW, KB> Cfg;
   typedef typename Mfma<T>::acc Acc;
   typedef typename Vec16<T>::t VT;
   constexpr int CH = Cfg::CH, LDI = Cfg::LDI, VEC = Cfg::VEC;
   const int fi = lane & 15, fg = lane >> 4;
   const int frag = fi * TS + 8 * fg;
-  const int nit = 2 * (nt - k0);
+  const int nit = 2 * (rlast - k0 + 1);
   const int nround = (nit + NW - 1) / NW;
-  const int nch = (k0 + CH - 1) / CH;
+  const int jbeg = Ej ? min(Ej[k0], k0) : 0;
+  const int nch = (k0 - jbeg + CH - 1) / CH;
   for (int rd = 0; rd < nround; ++rd) {
     const int it = rd * NW + w;
     const bool act = it < nit;
@@ -182,7 +187,7 @@ __device__ __forceinline__ void bulk_staged(T* A, int nt, int k0, int kn, int w,
         const int e = tid + u * NW * 64;
         const int c = e / (CH * TSQ / VEC), rem = e % (CH * TSQ / VEC);
         const int jl = rem / (TSQ / VEC), off = (rem % (TSQ / VEC)) * VEC;
-        const int jj = ch * CH + jl;
+        const int jj = jbeg + ch * CH + jl;
         if (e < Cfg::NVEC && jj < k0)
           stg[u] = *reinterpret_cast<const VT*>(A + tile_idx(k0 + min(c, kn - 1), jj) * TSQ + off);
       }
@@ -194,7 +199,7 @@ __device__ __forceinline__ void bulk_staged(T* A, int nt, int k0, int kn, int w,
         const int e = tid + u * NW * 64;
         const int c = e / (CH * TSQ / VEC), rem = e % (CH * TSQ / VEC);
         const int jl = rem / (TSQ / VEC), off = (rem % (TSQ / VEC)) * VEC;
-        if (e < Cfg::NVEC && ch * CH + jl < k0)
+        if (e < Cfg::NVEC && jbeg + ch * CH + jl < k0)
           *reinterpret_cast<VT*>(buf + ((c * CH + jl) * TS + off / TS) * LDI + off % TS) = stg[u];
       }
     };
@@ -202,15 +207,19 @@ __device__ __forceinline__ void bulk_staged(T* A, int nt, int k0, int kn, int w,
     store(0);
     block_sync();
     const T* X = A + tile_idx(i, 0) * TSQ + rq * 16 * TS + frag;
+    // the item's first nonzero tile (tiles left of it are zero: their
+    // products would add nothing)
+    const int js = Ej ? max(jbeg, min(Ej[i], k0)) : 0;
     V8<T> x0;
-    if (act) ld8(x0, X);
+    if (act && js < k0) ld8(x0, X + (int64_t)js * TSQ);
     for (int ch = 0; ch < nch; ++ch) {
       if (ch + 1 < nch) fetch(ch + 1);
       if (act) {
         const T* buf = sY + (ch & 1) * Cfg::YBUF;
-        const int jend = min(CH, k0 - ch * CH);
+        const int jend = min(CH, k0 - jbeg - ch * CH);
         for (int jl = 0; jl < jend; ++jl) {
-          const int jj = ch * CH + jl;
+          const int jj = jbeg + ch * CH + jl;
+          if (jj < js) continue;
           V8<T> x1;
           ld8(x1, X + (int64_t)min(jj + 1, k0 - 1) * TSQ);
 #pragma unroll
@@ -257,7 +266,7 @@ __device__ __forceinline__ void bulk_staged(T* A, int nt, int k0, int kn, int w,
 // their operands from memory; partial sums meet in LDS in slice order.
 template <typename T, int NW, int KB>
 __device__ __forceinline__ void bulk_split(T* A, int nt, int k0, int kn, int w, int lane,
-                                           T* sPart) {
+                                           T* sPart, const int* Ej) {
   typedef PotrfCfg<T, NW, KB> Cfg;
   typedef typename Mfma<T>::acc Acc;
   const int fi = lane & 15, fg = lane >> 4;
@@ -275,9 +284,13 @@ __device__ __forceinline__ void bulk_split(T* A, int nt, int k0, int kn, int w, 
     const T* Y[KB];
 #pragma unroll
     for (int c = 0; c < KB; ++c) Y[c] = A + tile_idx(k0 + min(c, kn - 1), 0) * TSQ + frag;
+    // slice sl takes jj = sl, sl + ns, ... (as in the dense order), from
+    // the first of them at or right of the row's first nonzero tile
+    const int e = Ej ? Ej[i] : 0;
+    const int j0 = e > sl ? sl + (e - sl + ns - 1) / ns * ns : sl;
     V8<T> x0;
-    ld8(x0, X + (int64_t)sl * TSQ);
-    for (int jj = sl; jj < k0; jj += ns) {
+    if (j0 < k0) ld8(x0, X + (int64_t)j0 * TSQ);
+    for (int jj = j0; jj < k0; jj += ns) {
       V8<T> x1;
       ld8(x1, X + (int64_t)min(jj + ns, k0 - 1) * TSQ);
 #pragma unroll
@@ -328,11 +341,12 @@ __device__ __forceinline__ void bulk_split(T* A, int nt, int k0, int kn, int w, 
 // Bulk update with the panel rows read through the caches; one item per
 // wavefront per round, the next jj's operands prefetched into registers.
 template <typename T, int NW, int KB>
-__device__ __forceinline__ void bulk_direct(T* A, int nt, int k0, int kn, int w, int lane) {
+__device__ __forceinline__ void bulk_direct(T* A, int nt, int k0, int kn, int w, int lane,
+                                            const int* Ej, int rlast) {
   typedef typename Mfma<T>::acc Acc;
   const int fi = lane & 15, fg = lane >> 4;
   const int frag = fi * TS + 8 * fg;
-  const int nit = 2 * (nt - k0);
+  const int nit = 2 * (rlast - k0 + 1);
   for (int it = w; it < nit; it += NW) {
     const int i = k0 + (it >> 1), rq = it & 1;
     Acc acc[KB][2];
@@ -342,13 +356,16 @@ __device__ __forceinline__ void bulk_direct(T* A, int nt, int k0, int kn, int w,
     const T* Y[KB];
 #pragma unroll
     for (int c = 0; c < KB; ++c) Y[c] = A + tile_idx(k0 + min(c, kn - 1), 0) * TSQ + frag;
+    const int js = Ej ? min(Ej[i], k0) : 0;
     V8<T> x0, y0[KB][2];
-    ld8(x0, X);
+    if (js < k0) {
+      ld8(x0, X + (int64_t)js * TSQ);
 #pragma unroll
-    for (int c = 0; c < KB; ++c)
+      for (int c = 0; c < KB; ++c)
 #pragma unroll
-      for (int cq = 0; cq < 2; ++cq) ld8(y0[c][cq], Y[c] + cq * 16 * TS);
-    for (int jj = 0; jj < k0; ++jj) {
+        for (int cq = 0; cq < 2; ++cq) ld8(y0[c][cq], Y[c] + (int64_t)js * TSQ + cq * 16 * TS);
+    }
+    for (int jj = js; jj < k0; ++jj) {
       const int jn = min(jj + 1, k0 - 1);
       V8<T> x1, y1[KB][2];
       ld8(x1, X + (int64_t)jn * TSQ);
@@ -384,7 +401,8 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
                                            const int* __restrict__ ntl, T* __restrict__ dinv,
                                            const int64_t* __restrict__ doff,
                                            int* __restrict__ status, const int* __restrict__ jobs,
-                                           double pivtol) {
+                                           double pivtol, const int* __restrict__ envE,
+                                           const int* __restrict__ envR) {
   typedef PotrfCfg<T, NW, KB> Cfg;
   typedef typename Mfma<T>::acc Acc;
   constexpr int LDI = Cfg::LDI;
@@ -392,6 +410,11 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
   const int nt = ntl[j];
   T* A = tiles + toff[j] * TSQ;
   T* Di = dinv + doff[j] * TSQ;
+  // envelope: rows i take tiles from column Ej[i] on; column k has
+  // nonzero tiles down to row last(k)
+  const int* Ej = envE ? envE + doff[j] : nullptr;
+  const int* Rj = envR ? envR + doff[j] : nullptr;
+  auto last = [&](int k) { return Rj ? min(max(Rj[k], k), nt - 1) : nt - 1; };
   __shared__ __align__(16) T sX[TS][LDI];
   __shared__ T sRp[TS];
   __shared__ __align__(16) unsigned char sShared[Cfg::SHARED_BYTES];
@@ -406,21 +429,23 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
     // ---- bulk update of the panel with columns 0 .. k0-1
     if (k0 > 0) {
       // split only while every item gets at least one of the NWS slices
-      if (2 * (nt - k0) < Cfg::NWS) bulk_split<T, NW, KB>(A, nt, k0, kn, w, lane, sBuf);
-      else if (STAGED) bulk_staged<T, NW, KB>(A, nt, k0, kn, w, tid, lane, sBuf);
-      else bulk_direct<T, NW, KB>(A, nt, k0, kn, w, lane);
+      const int rl = last(k0 + kn - 1);
+      if (2 * (nt - k0) < Cfg::NWS) bulk_split<T, NW, KB>(A, nt, k0, kn, w, lane, sBuf, Ej);
+      else if (STAGED) bulk_staged<T, NW, KB>(A, nt, k0, kn, w, tid, lane, sBuf, Ej, rl);
+      else bulk_direct<T, NW, KB>(A, nt, k0, kn, w, lane, Ej, rl);
     }
     // ---- panel factorization
     for (int c = k0; c < k0 + kn; ++c) {
       if (c > k0) {
         // rank-32 update of the panel columns c' >= c with column c-1:
         // A(i, c') -= L(i, c-1) L(c', c-1)^T for i >= c'
-        const int pc = c - 1;
+        // (rows below last(pc) have a zero tile in column pc)
+        const int pc = c - 1, rl = last(pc);
         int nit = 0;
-        for (int cc = c; cc < k0 + kn; ++cc) nit += 2 * (nt - cc);
+        for (int cc = c; cc < k0 + kn; ++cc) nit += 2 * max(0, rl + 1 - cc);
         for (int it = w; it < nit; it += NW) {
           int cc = c, rem = it;
-          while (rem >= 2 * (nt - cc)) rem -= 2 * (nt - cc++);
+          while (rem >= 2 * max(0, rl + 1 - cc)) rem -= 2 * max(0, rl + 1 - cc++);
           const int i = cc + (rem >> 1), rq = rem & 1;
           V8<T> x, y[2];
           ld8(x, A + tile_idx(i, pc) * TSQ + rq * 16 * TS + frag);
@@ -450,8 +475,8 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
       }
       block_sync();
       if (sfail) return;
-      // L(i, c) = A(i, c) Dinv(c)^T for i > c
-      const int nit = 2 * (nt - c - 1);
+      // L(i, c) = A(i, c) Dinv(c)^T for c < i <= last(c)
+      const int nit = 2 * (last(c) - c);
       for (int it = w; it < nit; it += NW) {
         const int i = c + 1 + (it >> 1), rq = it & 1;
         T* X = A + tile_idx(i, c) * TSQ + rq * 16 * TS;
@@ -487,44 +512,44 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ tiles, const int64_t*
 // One entry point per role, so that traces and profiles tell them apart:
 // local Dirichlet factors (FP32, or FP64 for the subdomains that fail the
 // FP32 pivot test) and the shifted Neumann factors of the eigensolver.
-__global__ __launch_bounds__(POTRF32_NW * 64) void k_potrf_local_f32(float* tiles,
-                                                                     const int64_t* toff,
-                                                                     const int* nt, float* dinv,
-                                                                     const int64_t* doff,
-                                                                     int* status, const int* jobs,
-                                                                     double pivtol) {
-  potrf_body<float, POTRF32_NW, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+__global__ __launch_bounds__(POTRF32_NW * 64) void k_potrf_local_f32(
+    float* tiles, const int64_t* toff, const int* nt, float* dinv, const int64_t* doff,
+    int* status, const int* jobs, double pivtol, const int* envE, const int* envR) {
+  potrf_body<float, POTRF32_NW, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol, envE,
+                                         envR);
 }
-__global__ __launch_bounds__(512) void k_potrf_local_f64(double* tiles, const int64_t* toff,
-                                                         const int* nt, double* dinv,
-                                                         const int64_t* doff, int* status,
-                                                         const int* jobs, double pivtol) {
-  potrf_body<double, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+__global__ __launch_bounds__(512) void k_potrf_local_f64(
+    double* tiles, const int64_t* toff, const int* nt, double* dinv, const int64_t* doff,
+    int* status, const int* jobs, double pivtol, const int* envE, const int* envR) {
+  potrf_body<double, 8, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol, envE, envR);
 }
 #define POTRF64S_NW 12
 __global__ __launch_bounds__(POTRF64S_NW * 64) void k_potrf_shifted_f64(
     double* tiles, const int64_t* toff, const int* nt, double* dinv, const int64_t* doff,
-    int* status, const int* jobs, double pivtol) {
-  potrf_body<double, POTRF64S_NW, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol);
+    int* status, const int* jobs, double pivtol, const int* envE, const int* envR) {
+  potrf_body<double, POTRF64S_NW, 4, true>(tiles, toff, nt, dinv, doff, status, jobs, pivtol,
+                                           envE, envR);
 }
 
 hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
                                void* dinv, const int64_t* doff, int* status, const int* jobs,
-                               int njobs, double pivtol, hipStream_t st) {
+                               int njobs, double pivtol, const int* envE, const int* envR,
+                               hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
+  if (!envE != !envR) return hipErrorInvalidValue;
   const dim3 grid(njobs), blk(512);
   switch (role) {
     case CholRole::LocalF32:
       hipLaunchKernelGGL(k_potrf_local_f32, grid, dim3(POTRF32_NW * 64), 0, st, (float*)tiles, toff, nt,
-                         (float*)dinv, doff, status, jobs, pivtol);
+                         (float*)dinv, doff, status, jobs, pivtol, envE, envR);
       break;
     case CholRole::LocalF64:
       hipLaunchKernelGGL(k_potrf_local_f64, grid, blk, 0, st, (double*)tiles, toff, nt,
-                         (double*)dinv, doff, status, jobs, pivtol);
+                         (double*)dinv, doff, status, jobs, pivtol, envE, envR);
       break;
     case CholRole::ShiftedF64:
       hipLaunchKernelGGL(k_potrf_shifted_f64, grid, dim3(POTRF64S_NW * 64), 0, st, (double*)tiles, toff, nt,
-                         (double*)dinv, doff, status, jobs, pivtol);
+                         (double*)dinv, doff, status, jobs, pivtol, envE, envR);
       break;
   }
   return hipGetLastError();
@@ -559,13 +584,18 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
                                                           const int64_t* __restrict__ toff,
                                                           const int64_t* __restrict__ doff,
                                                           const int* __restrict__ ntl,
-                                                          const int2* __restrict__ jobs) {
+                                                          const int2* __restrict__ jobs,
+                                                          const int* __restrict__ envE) {
   typedef typename Mfma<T>::acc Acc;
   constexpr int NCQ = 2 * NCT, b = 32 * NCT, LDI = DiagLd<T>::v;
   constexpr int TW_NW = TwCfg<T>::NW, TW_MR = TwCfg<T>::MR, TW_W = TW_NW * TW_MR;
   const int j = jobs[blockIdx.x].x, c0 = jobs[blockIdx.x].y;
   const int nt = ntl[j];
   if (c0 >= nt) return;
+  // envelope of L (NULL: dense): row k of L is zero left of tile column
+  // E(k), so its products there are skipped (X itself is dense)
+  const int* Ej = envE ? envE + doff[j] : nullptr;
+  auto first = [&](int k) { return Ej ? Ej[k] : 0; };
   const T* Lj = L + toff[j] * TSQ;
   const T* Dj = dinv + doff[j] * TSQ;
   T* Xj = X + toff[j] * TSQ;
@@ -626,9 +656,11 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
     for (int m = 0; m < TW_MR; ++m) {
       const int k = krow[m];
       if (k >= p1 || p0 == c0) continue;
+      const int jlo = max(c0, first(k));
+      if (jlo >= p0) continue;
       V8<T> a[2];
-      afrag_neg(a, Lj + tile_idx(k, c0) * TSQ);
-      for (int jj = c0; jj < p0; ++jj) {
+      afrag_neg(a, Lj + tile_idx(k, jlo) * TSQ);
+      for (int jj = jlo; jj < p0; ++jj) {
         V8<T> a1[2];
         afrag_neg(a1, Lj + tile_idx(k, min(jj + 1, p0 - 1)) * TSQ);
 #pragma unroll
@@ -698,7 +730,7 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
 #pragma unroll
       for (int m = 0; m < TW_MR; ++m) {
         const int k = krow[m];
-        if (k >= p1 || k <= i) continue;
+        if (k >= p1 || k <= i || first(k) > i) continue;
         V8<T> a[2];
         afrag_neg(a, Lj + tile_idx(k, i) * TSQ);
 #pragma unroll
@@ -717,14 +749,16 @@ int trtri_cols_per_job(bool fp32) { return fp32 ? 2 : 1; }
 
 hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
                         const int64_t* toff, const int64_t* doff, const int* nt,
-                        const int2* jobs, int njobs, hipStream_t st) {
+                        const int2* jobs, int njobs, const int* envE, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   if (fp32)
     hipLaunchKernelGGL((k_trtri_win<float, 2>), dim3(njobs), dim3(TwCfg<float>::NW * 64), 0, st,
-                       (const float*)L, (const float*)dinv, (float*)X, toff, doff, nt, jobs);
+                       (const float*)L, (const float*)dinv, (float*)X, toff, doff, nt, jobs,
+                       envE);
   else
     hipLaunchKernelGGL((k_trtri_win<double, 1>), dim3(njobs), dim3(TwCfg<double>::NW * 64), 0, st,
-                       (const double*)L, (const double*)dinv, (double*)X, toff, doff, nt, jobs);
+                       (const double*)L, (const double*)dinv, (double*)X, toff, doff, nt, jobs,
+                       envE);
   return hipGetLastError();
 }
 

@@ -9,9 +9,66 @@
 // (subdomain[, group of 256 rows]) and every thread owns whole rows (a unit
 // diagonal first, the identity on padding rows, then the row's entries), so
 // no two threads write the same entry.
+//
+// Tile envelope.  Each fill also records, per tile row i of a matrix, the
+// first tile column E(i) that holds an entry of the matrix's pattern
+// (atomic minimum over the rows of the tile row, from E(i) = i).  A
+// Cholesky factor has no entries left of the first entry of each row of
+// its matrix, so tiles (i, jj < E(i)) of the factor are zero.
+// k_env_finish then makes E nondecreasing (E(i) = min over rows >= i: a
+// superset of the nonzero tiles) and forms R(k) = the last tile row i with
+// E(i) <= k, the last nonzero tile of tile column k.  Box subdomains in
+// lexicographic order give banded matrices: E(i) trails i by about the
+// band width in tiles.
 #include "internal.h"
 
 namespace geneo {
+
+__global__ __launch_bounds__(256) void k_env_init(int* __restrict__ env,
+                                                  const int64_t* __restrict__ doff,
+                                                  const int* __restrict__ ntl,
+                                                  const int* __restrict__ jobs) {
+  const int j = jobs ? jobs[blockIdx.x] : blockIdx.x, nt = ntl[j];
+  int* E = env + doff[j];
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) E[i] = i;
+}
+
+__global__ __launch_bounds__(64) void k_env_finish(int* __restrict__ envE, int* __restrict__ envR,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int* __restrict__ ntl,
+                                                   const int* __restrict__ jobs, int njobs) {
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  if (q >= njobs) return;
+  const int j = jobs ? jobs[q] : q;
+  const int nt = ntl[j];
+  int* E = envE + doff[j];
+  int* R = envR + doff[j];
+  int m = nt;
+  for (int i = nt - 1; i >= 0; --i) {
+    m = min(m, min(E[i], i));
+    E[i] = max(m, 0);
+  }
+  int i = nt - 1;
+  for (int k = nt - 1; k >= 0; --k) {
+    while (E[i] > k) --i;  // stops at i = k at the latest (E(k) <= k)
+    R[k] = i;
+  }
+}
+
+hipError_t launch_env_init(int* env, const int64_t* doff, const int* nt, const int* jobs,
+                           int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env_init, dim3(njobs), dim3(256), 0, st, env, doff, nt, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_env_finish(int* envE, int* envR, const int64_t* doff, const int* nt,
+                             const int* jobs, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env_finish, dim3((njobs + 63) / 64), dim3(64), 0, st, envE, envR, doff, nt,
+                     jobs, njobs);
+  return hipGetLastError();
+}
 
 template <typename T>
 __device__ __forceinline__ T* tile_elem(T* base, int r, int c) {
@@ -36,7 +93,8 @@ __global__ __launch_bounds__(256) void k_densify_dirichlet(
     const int* __restrict__ voff, const int* __restrict__ jobs, const int* __restrict__ sub_ptr,
     const int* __restrict__ sub_idx, const int* __restrict__ dmap, const int* __restrict__ dglob,
     const double* __restrict__ dscale, const int* __restrict__ rowptr,
-    const int* __restrict__ col, const double* __restrict__ val) {
+    const int* __restrict__ col, const double* __restrict__ val, int* __restrict__ env,
+    const int64_t* __restrict__ doff) {
   const int j = jobs[blockIdx.x];
   const int nt = ntl[j];
   T* base = tiles + toff[j] * TSQ;
@@ -48,13 +106,16 @@ __global__ __launch_bounds__(256) void k_densify_dirichlet(
     int g = dglob[v0 + d];
     if (g < 0) continue;
     double sd = dscale[v0 + d];
+    int first = d;
     for (int p = rowptr[g]; p < rowptr[g + 1]; ++p) {
       int a = bsearch_row(Nj, n, col[p]);
       if (a < 0) continue;
       int dc = dmap[s0 + a];
       if (dc < 0 || dc > d) continue;
       *tile_elem(base, d, dc) = (T)(val[p] * sd * dscale[v0 + dc]);
+      first = min(first, dc);
     }
+    if (env && first / TS < d / TS) atomicMin(env + doff[j] + d / TS, first / TS);
   }
 }
 
@@ -62,17 +123,17 @@ hipError_t launch_densify_dirichlet(bool fp32, void* tiles, const int64_t* toff,
                                     const int* voff, const int* jobs, int njobs,
                                     const int* sub_ptr, const int* sub_idx, const int* dmap,
                                     const int* dglob, const double* dscale, const geneo_csr_t* A,
-                                    int ntmax, hipStream_t st) {
+                                    int ntmax, int* env, const int64_t* doff, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   const dim3 grid(njobs, std::max(1, (ntmax * TS + 255) / 256));
   if (fp32)
     hipLaunchKernelGGL(k_densify_dirichlet<float>, grid, dim3(256), 0, st, (float*)tiles,
                        toff, nt, voff, jobs, sub_ptr, sub_idx, dmap, dglob, dscale, A->rowptr,
-                       A->col, A->val);
+                       A->col, A->val, env, doff);
   else
     hipLaunchKernelGGL(k_densify_dirichlet<double>, grid, dim3(256), 0, st,
                        (double*)tiles, toff, nt, voff, jobs, sub_ptr, sub_idx, dmap, dglob,
-                       dscale, A->rowptr, A->col, A->val);
+                       dscale, A->rowptr, A->col, A->val, env, doff);
   return hipGetLastError();
 }
 
@@ -81,7 +142,8 @@ __global__ __launch_bounds__(256) void k_densify_shifted(
     const int* __restrict__ sub_ptr, const double* __restrict__ pou,
     const int* __restrict__ an_rp, const int* __restrict__ an_col,
     const double* __restrict__ an_val, const int* __restrict__ ao_rp,
-    const int* __restrict__ ao_col, const double* __restrict__ ao_val, double sigma) {
+    const int* __restrict__ ao_col, const double* __restrict__ ao_val, double sigma,
+    int* __restrict__ env, const int64_t* __restrict__ doff) {
   const int j = blockIdx.x;
   const int nt = ntl[j];
   double* base = tiles + toff[j] * TSQ;
@@ -89,29 +151,38 @@ __global__ __launch_bounds__(256) void k_densify_shifted(
   for (int a = blockIdx.y * blockDim.x + threadIdx.x; a < nt * TS; a += blockDim.x * gridDim.y) {
     *tile_elem(base, a, a) = 1.0;
     if (a >= n) continue;
+    int first = a;
     for (int p = an_rp[s0 + a]; p < an_rp[s0 + a + 1]; ++p) {
       int c = an_col[p];
-      if (c <= a) *tile_elem(base, a, c) = an_val[p];
+      if (c <= a) {
+        *tile_elem(base, a, c) = an_val[p];
+        first = min(first, c);
+      }
     }
     double mua = pou[s0 + a];
     if (mua != 0.0) {
       for (int p = ao_rp[s0 + a]; p < ao_rp[s0 + a + 1]; ++p) {
         int c = ao_col[p];
-        if (c <= a) *tile_elem(base, a, c) -= sigma * mua * ao_val[p] * pou[s0 + c];
+        if (c <= a) {
+          *tile_elem(base, a, c) -= sigma * mua * ao_val[p] * pou[s0 + c];
+          first = min(first, c);
+        }
       }
     }
+    if (env && first / TS < a / TS) atomicMin(env + doff[j] + a / TS, first / TS);
   }
 }
 
 hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int* nt, int nsub,
                                   const int* sub_ptr, const double* pou,
                                   const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
-                                  double sigma, hipStream_t st) {
+                                  double sigma, int* env, const int64_t* doff, hipStream_t st) {
   // one workgroup per subdomain: measured faster here than splitting the
   // rows over several (the Dirichlet fill, launched for fewer matrices,
   // splits them)
   hipLaunchKernelGGL(k_densify_shifted, dim3(nsub), dim3(256), 0, st, tiles, toff, nt, sub_ptr,
-                     pou, An->rowptr, An->col, An->val, Ao->rowptr, Ao->col, Ao->val, sigma);
+                     pou, An->rowptr, An->col, An->val, Ao->rowptr, Ao->col, Ao->val, sigma, env,
+                     doff);
   return hipGetLastError();
 }
 

@@ -40,28 +40,43 @@ hipError_t launch_pairs(const uint8_t* adj, int nsub, int* cnt, int* off, int2* 
                         int* npairs_dev, hipStream_t st, bool count_only);
 
 // ------------------------------------------------------------- dense.hip
+// Tile envelopes (per matrix, one int per tile row at the matrix's diagonal
+// tile offset doff): E(i) = first tile column of tile row i that may hold a
+// nonzero (nondecreasing), R(k) = last tile row with E(i) <= k.  The fills
+// lower E from env_init's E(i) = i (when env is not NULL); env_finish makes
+// E nondecreasing and forms R.  Both over the matrices jobs[0 .. njobs)
+// (jobs NULL: 0 .. njobs-1).
+hipError_t launch_env_init(int* env, const int64_t* doff, const int* nt, const int* jobs,
+                           int njobs, hipStream_t st);
+hipError_t launch_env_finish(int* envE, int* envR, const int64_t* doff, const int* nt,
+                             const int* jobs, int njobs, hipStream_t st);
 hipError_t launch_densify_dirichlet(bool fp32, void* tiles, const int64_t* toff,
                                     const int* nt, const int* voff, const int* jobs,
                                     int njobs, const int* sub_ptr, const int* sub_idx,
                                     const int* dmap, const int* dglob, const double* dscale,
                                     const geneo_csr_t* A, int ntmax /* max tile count */,
-                                    hipStream_t st);
+                                    int* env, const int64_t* doff, hipStream_t st);
 hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int* nt,
                                   int nsub, const int* sub_ptr, const double* pou,
                                   const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
-                                  double sigma, hipStream_t st);
+                                  double sigma, int* env, const int64_t* doff, hipStream_t st);
 
 // -------------------------------------------------------------- chol.hip
+// envE / envR: the matrices' tile envelopes (NULL: dense).  Tiles outside
+// the envelope are zero and are neither read nor written: the factors are
+// bitwise those of the dense factorisation.
 enum class CholRole { LocalF32, LocalF64, ShiftedF64 };
 hipError_t launch_chol_batched(CholRole role, void* tiles, const int64_t* toff, const int* nt,
                                void* dinv, const int64_t* doff, int* status, const int* jobs,
-                               int njobs, double pivtol, hipStream_t st);
+                               int njobs, double pivtol, const int* envE, const int* envR,
+                               hipStream_t st);
 // jobs[] = (matrix, first tile column c0) with c0 a multiple of
 // trtri_cols_per_job(fp32); tile columns c0 .. c0 + that - 1 are done.
+// envE: the envelope of L (NULL: dense); X = L^{-1} is written in full.
 int trtri_cols_per_job(bool fp32);
 hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
                         const int64_t* toff, const int64_t* doff, const int* nt,
-                        const int2* jobs, int njobs, hipStream_t st);
+                        const int2* jobs, int njobs, const int* envE, hipStream_t st);
 // S = X^T X (= A^{-1} for X = L^{-1}) from the transposed tiles k_trtri_win
 // writes; jobs[] = (matrix, I << 16 | J0) for the output tiles (I, J0 ..
 // J0 + lauum_tiles_per_job() - 1), J <= I, in the packed layout of toff.
@@ -153,17 +168,20 @@ hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
 // (split = 1) or b / 16 per subdomain, each on 16 of the b columns
 // (split = trsm_max_split(b) > 1), for the first nsub entries of `order`
 // (may be NULL = by index); `variant` (0 or 1) picks the kernel (0 is not
-// available unsplit for b = 48).  Every variant and split gives bitwise the
-// same X.
+// available unsplit for b = 48).  envE / envR: the factors' tile envelopes
+// (NULL: dense); the zero tiles outside them are skipped.  Every variant
+// and split gives bitwise the same X, and so does the envelope.
 int trsm_max_split(int b);
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
-                           const int* order, int variant, int split, hipStream_t st);
+                           const int* order, const int* envE, const int* envR, int variant,
+                           int split, hipStream_t st);
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,
-                           const int* order, int variant, int split, hipStream_t st);
+                           const int* order, const int* envE, const int* envR, int variant,
+                           int split, hipStream_t st);
 // B_j = X_j A^o_j X_j in compact CSR over the nloc local rows: brp [nloc+1]
 // (cnt [nloc] scratch), bcol / bval sized by the nonzeros of the A^o batch;
 // maxrows bounds |N_j|.

@@ -305,9 +305,13 @@ __global__ __launch_bounds__(1024) void k_trsm_fwd(const double* __restrict__ G,
                                                    const int* __restrict__ voff, int b,
                                                    const double* __restrict__ R,
                                                    double* __restrict__ X,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active,
+                                                   const int* __restrict__ envE,
+                                                   const int* __restrict__ envR) {
   const int j = blockIdx.x;
   if (active && !active[j]) return;
+  const int* Ej = envE ? envE + doff[j] : nullptr;
+  const int* Rl = envR ? envR + doff[j] : nullptr;
   __shared__ double spart[TRSM_WAVES][256];
   __shared__ double sacc[TS][TRSM_MAXB + 1];
   const int nt = ntl[j];
@@ -323,8 +327,10 @@ __global__ __launch_bounds__(1024) void k_trsm_fwd(const double* __restrict__ G,
   const bool worker = sl < ns;
   for (int i = 0; i < nt; ++i) {
     d4_t acc = acc_zero<double>();
+    // slice sl takes k = sl, sl + ns, ...; tiles left of E(i) are zero
+    const int e = Ej ? Ej[i] : 0;
     if (worker)
-      for (int k = sl; k < i; k += ns)
+      for (int k = e > sl ? sl + (e - sl + ns - 1) / ns * ns : sl; k < i; k += ns)
         q_xy<double>(acc, Gj + tile_idx(i, k) * TSQ + rq * 16 * TS, TS,
                      Xj + (int64_t)k * TS * b + cq * 16, b, lane);
     if (w < TRSM_WAVES) {
@@ -354,9 +360,13 @@ __global__ __launch_bounds__(1024) void k_trsm_bwd(const double* __restrict__ G,
                                                    const int* __restrict__ voff, int b,
                                                    const double* __restrict__ R,
                                                    double* __restrict__ X,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active,
+                                                   const int* __restrict__ envE,
+                                                   const int* __restrict__ envR) {
   const int j = blockIdx.x;
   if (active && !active[j]) return;
+  const int* Ej = envE ? envE + doff[j] : nullptr;
+  const int* Rl = envR ? envR + doff[j] : nullptr;
   __shared__ double spart[TRSM_WAVES][256];
   __shared__ double sacc[TS][TRSM_MAXB + 1];
   const int nt = ntl[j];
@@ -373,8 +383,10 @@ __global__ __launch_bounds__(1024) void k_trsm_bwd(const double* __restrict__ G,
   for (int k = nt - 1; k >= 0; --k) {
     d4_t acc = acc_zero<double>();
     // sum_{i>k} G_ik^T X_i : contraction over the rows of G_ik
+    // (tiles below R(k) are zero)
+    const int iend = Rl ? min(nt, Rl[k] + 1) : nt;
     if (worker)
-      for (int i = k + 1 + sl; i < nt; i += ns)
+      for (int i = k + 1 + sl; i < iend; i += ns)
         q_xTy<double>(acc, Gj + tile_idx(i, k) * TSQ + rq * 16, TS,
                       Xj + (int64_t)i * TS * b + cq * 16, b, lane);
     if (w < TRSM_WAVES) {
@@ -533,7 +545,8 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
                                                          double* __restrict__ X,
                                                          const int* __restrict__ active,
                                                          const int* __restrict__ order,
-                                                         int nsub) {
+                                                         int nsub, const int* __restrict__ envE,
+                                                         const int* __restrict__ envR) {
   constexpr int b = 16 * NCQ;  // columns solved by this workgroup
   static_assert(LDB % b == 0, "column blocks");
   int part;
@@ -551,6 +564,12 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int fi = lane & 15, fg = lane >> 4;
   const int nwin = (nt + TRW_W - 1) / TRW_W;
+  // envelope: row k has nonzero tiles from column E(k), column k down to
+  // row R(k) (all others are zero: their products are skipped)
+  const int* Ej = envE ? envE + doff[j] : nullptr;
+  const int* Rl = envR ? envR + doff[j] : nullptr;
+  auto first = [&](int k) { return Ej ? Ej[k] : 0; };
+  auto last = [&](int k) { return Rl ? Rl[k] : nt - 1; };
   for (int wi = 0; wi < nwin; ++wi) {
     // window rows [p0, p1); BWD windows run from the bottom
     const int p0 = BWD ? max(0, nt - (wi + 1) * TRW_W) : wi * TRW_W;
@@ -573,11 +592,12 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
     }
     // ---- left-looking update from the finished rows
     // FWD: acc_k -= sum_{jj < p0} G_k,jj X_jj      BWD: acc_k -= sum_{jj >= p1} G_jj,k^T X_jj
-    const int jlo = BWD ? p1 : 0, jhi = BWD ? nt : p0;
 #pragma unroll
     for (int m = 0; m < TRW_MR; ++m) {
       const int k = krow[m];
-      if (k >= p1 || jlo >= jhi) continue;
+      if (k >= p1) continue;
+      const int jlo = BWD ? p1 : first(k), jhi = BWD ? min(nt, last(k) + 1) : p0;
+      if (jlo >= jhi) continue;
       const double* t0 = BWD ? Gj + tile_idx(jlo, k) * TSQ : Gj + tile_idx(k, jlo) * TSQ;
       F8 a[2];
       auto load = [&](const double* t, F8 (&aa)[2]) {
@@ -627,7 +647,9 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
           else afrag(aa[rq], t, rq * 16, fi, fg);
         }
       };
-      auto wants = [&](int k) { return k < p1 && (BWD ? k < i : k > i); };
+      auto wants = [&](int k) {
+        return k < p1 && (BWD ? k < i && i <= last(k) : k > i && first(k) <= i);
+      };
       F8 a0[2];
       if (wants(krow[0])) load_neg(a0, krow[0]);
       block_sync();
@@ -682,7 +704,8 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
                                                         double* __restrict__ X,
                                                         const int* __restrict__ active,
                                                         const int* __restrict__ order,
-                                                        int nsub) {
+                                                        int nsub, const int* __restrict__ envE,
+                                                        const int* __restrict__ envR) {
   static_assert(AD == 1 || AD == 2, "factor tiles in flight");
   constexpr int b = 16 * NCQ;  // columns solved by this workgroup
   static_assert(LDB % b == 0, "column blocks");
@@ -701,6 +724,11 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int fi = lane & 15, fg = lane >> 4;
   const int nwin = (nt + TW1_NW - 1) / TW1_NW;
+  // envelope (as in k_trsm_win)
+  const int* Ej = envE ? envE + doff[j] : nullptr;
+  const int* Rl = envR ? envR + doff[j] : nullptr;
+  auto first = [&](int k) { return Ej ? Ej[k] : 0; };
+  auto last = [&](int k) { return Rl ? Rl[k] : nt - 1; };
   // factor tile (k, jj) (FWD) or (jj, k) read transposed (BWD)
   auto loadA = [&](F8 (&aa)[2], int k, int jj) {
     const double* t = BWD ? Gj + tile_idx(jj, k) * TSQ : Gj + tile_idx(k, jj) * TSQ;
@@ -729,7 +757,8 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
                                : 0.0;
     // ---- left-looking update from the finished rows
     // FWD: acc_k += sum_{jj < p0} G_k,jj X_jj      BWD: acc_k += sum_{jj >= p1} G_jj,k^T X_jj
-    const int jlo = BWD ? p1 : 0, jhi = BWD ? nt : p0;
+    const int jlo = BWD ? p1 : (own ? first(k) : 0);
+    const int jhi = BWD ? (own ? min(nt, last(k) + 1) : nt) : p0;
     if (own && jlo < jhi && BP) {
       // whole next right-hand block in flight during this step's products
       F8 a0[2], a1[2], a2[2];
@@ -785,7 +814,7 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
       if (w == i - p0)
         trw_finish<NCQ, BWD, true>(acc, Dj + (int64_t)i * TSQ, sTmp, sXo,
                                    Xj + (int64_t)i * TS * LDB, LDB, lane);
-      const bool want = own && (BWD ? k < i : k > i);
+      const bool want = own && (BWD ? k < i && i <= last(k) : k > i && first(k) <= i);
       F8 a[2];
       if (want) loadA(a, k, i);
       block_sync();
@@ -808,13 +837,14 @@ static dim3 trsm_grid(int nsub, int split) {
   return split == 1 ? dim3(nsub) : dim3(split * ((nsub + 7) / 8 * 8));
 }
 
-#define TRSM_ARGS G, dinv, toff, doff, nt, voff, R, X, active, order, nsub
+#define TRSM_ARGS G, dinv, toff, doff, nt, voff, R, X, active, order, nsub, envE, envR
 
 template <bool BWD>
 static hipError_t launch_trsm_w1(const double* G, const double* dinv, const int64_t* toff,
                                  const int64_t* doff, const int* nt, const int* voff, int nsub,
                                  int b, int split, const double* R, double* X, const int* active,
-                                 const int* order, hipStream_t st) {
+                                 const int* order, const int* envE, const int* envR,
+                                  hipStream_t st) {
   const dim3 grid = trsm_grid(nsub, split), blk(TW1_NW * 64);
   switch (split == 1 ? b : -b) {
     case 16: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 16>), grid, blk, 0, st, TRSM_ARGS); break;
@@ -831,7 +861,8 @@ template <bool BWD>
 static hipError_t launch_trsm_win(const double* G, const double* dinv, const int64_t* toff,
                                   const int64_t* doff, const int* nt, const int* voff, int nsub,
                                   int b, int split, const double* R, double* X, const int* active,
-                                  const int* order, hipStream_t st) {
+                                  const int* order, const int* envE, const int* envR,
+                                  hipStream_t st) {
   const dim3 grid = trsm_grid(nsub, split), blk(TRW_NW * 64);
   switch (split == 1 ? b : -b) {
     case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD, 16>), grid, blk, 0, st, TRSM_ARGS); break;
@@ -856,37 +887,41 @@ template <bool BWD>
 static hipError_t launch_trsm(const double* G, const double* dinv, const int64_t* toff,
                               const int64_t* doff, const int* nt, const int* voff, int nsub,
                               int b, const double* R, double* X, const int* active,
-                              const int* order, int variant, int split, hipStream_t st) {
+                              const int* order, const int* envE, const int* envR, int variant,
+                              int split, hipStream_t st) {
   if (split != 1 && (b > 48 || split != b / 16)) return hipErrorInvalidValue;
+  if (!envE != !envR) return hipErrorInvalidValue;
   if (b <= 48 && variant == 0 && (b <= 32 || split != 1))
     return launch_trsm_win<BWD>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X, active,
-                                order, st);
+                                order, envE, envR, st);
   if (b <= 48)
     return launch_trsm_w1<BWD>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X, active,
-                               order, st);
+                               order, envE, envR, st);
   if (BWD)
     hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff,
-                       b, R, X, active);
+                       b, R, X, active, envE, envR);
   else
     hipLaunchKernelGGL(k_trsm_fwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff,
-                       b, R, X, active);
+                       b, R, X, active, envE, envR);
   return hipGetLastError();
 }
 
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, const int* order,
-                           int variant, int split, hipStream_t st) {
-  return launch_trsm<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, variant,
-                            split, st);
+                           const int* envE, const int* envR, int variant, int split,
+                           hipStream_t st) {
+  return launch_trsm<false>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, envE,
+                            envR, variant, split, st);
 }
 
 hipError_t launch_trsm_bwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub, int b,
                            const double* R, double* X, const int* active, const int* order,
-                           int variant, int split, hipStream_t st) {
-  return launch_trsm<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, variant,
-                           split, st);
+                           const int* envE, const int* envR, int variant, int split,
+                           hipStream_t st) {
+  return launch_trsm<true>(G, dinv, toff, doff, nt, voff, nsub, b, R, X, active, order, envE,
+                           envR, variant, split, st);
 }
 
 // B_j = X_j A^o_j X_j (the B-matrix of the GenEO eigenproblem) in compact
