@@ -228,8 +228,10 @@ typedef struct {
   int eig_solve;      /* kernel of the eigen sweeps' triangular solves
                          (b <= 48): 1 = two tile rows per wavefront (b <= 32,
                          or 16-column blocks), 2 = one row per wavefront with
-                         deeper load pipelines, 0 = the faster, timed on the
-                         device at the first setup of each problem shape */
+                         deeper load pipelines, both with 8 wavefronts per
+                         subdomain; 3, 4 = the same with 4 (two subdomains
+                         per CU); 0 = the fastest, timed on the device at the
+                         first setup of each problem shape */
   int eig_split;      /* 16-column blocks on b / 16 workgroups per
                          subdomain (b = 32, 48) in the sweeps that start
                          with at most this many subdomains active (as far
@@ -310,7 +312,7 @@ typedef struct {
   int eig_stalled;        /* subdomains stopped at their rounding floor */
   int symv_tiles;         /* tiles per wavefront of the local products */
   int eig_solve;          /* triangular-solve kernel of the eigen sweeps'
-                             unsplit solves (1 or 2, see geneo_opts_t) */
+                             unsplit solves (1 .. 4, see geneo_opts_t) */
   int eig_split;          /* the sweeps' solves are split into 16-column
                              blocks while at most this many subdomains are
                              active (0 = never) */

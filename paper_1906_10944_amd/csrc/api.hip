@@ -607,7 +607,7 @@ struct SetupScratch {
   DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol, orderN;
   // tile envelopes (first nonzero tile column per tile row, last nonzero
   // tile row per tile column) of the shifted, FP32 and FP64 local matrices
-  DBuf<int> envNE, envNR, envDE, envDR, env64E, env64R;
+  DBuf<int> envNE, envNR, envDE, envDR, env64E, env64R, envHE, envHR;
   // the envelopes the factorisations and solves use (NULL: dense, option
   // envelope = 0)
   const int *uNE = nullptr, *uNR = nullptr, *uDE = nullptr, *uDR = nullptr, *u64E = nullptr,
@@ -682,22 +682,26 @@ TrsmChoice tune_trsm(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN, 
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     return ms;
   };
-  float tu = 0.f;
-  if (b <= 32) {
-    const float t0 = time(0, 1, nsub), t1 = time(1, 1, nsub);
-    c.variant = t1 < t0 ? 1 : 0;
-    tu = std::min(t0, t1);
-  } else {
-    tu = time(1, 1, nsub);
-  }
+  // the fastest of the variants a launch of this shape can take (b = 48
+  // unsplit has only the one-row-per-wavefront kernels)
+  auto fastest = [&](int split, int n, int& best) {
+    float bt = 0.f;
+    best = -1;
+    for (int v = 0; v < trsm_variants(); ++v) {
+      if (b == 48 && split == 1 && (v & 1) == 0) continue;
+      const float t = time(v, split, n);
+      if (best < 0 || t < bt) bt = t, best = v;
+    }
+    return bt;
+  };
+  const float tu = fastest(1, nsub, c.variant);
   if (nsplit > 1) {
     // with at most ncu / nsplit subdomains active the split solves fill
     // the CUs that the unsplit ones leave idle
     const int n1 = std::max(1, std::min(nsub, ncu / nsplit));
     const float tu1 = n1 == nsub ? tu : time(c.variant, 1, n1);
-    const float s0 = time(0, nsplit, n1), s1 = time(1, nsplit, n1);
-    c.split_variant = s1 < s0 ? 1 : 0;
-    if (std::min(s0, s1) < tu1) {
+    const float ts1 = fastest(nsplit, n1, c.split_variant);
+    if (ts1 < tu1) {
       c.split_limit = n1;
       if (n1 < nsub && time(c.split_variant, nsplit, nsub) < tu) c.split_limit = nsub;
     }
@@ -775,9 +779,10 @@ std::vector<int2> lauum_job_list(const std::vector<int>& mats, const std::vector
 // Local Dirichlet factors A_j = R_j A R_j^T and their inverses, on
 // stream st.  Returns after the work is enqueued and the pivot tests are
 // read back.
-std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const geneo_csr_t* A,
-                                  const geneo_subdomains_t* S, hipStream_t st,
-                                  const std::function<void(hipEvent_t)>& after_fp32) {
+std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
+                                             const geneo_csr_t* A, const geneo_subdomains_t* S,
+                                             hipStream_t st,
+                                             const std::function<void(hipEvent_t)>& after_fp32) {
   const geneo_opts_t& o = h->opts;
   const int nsub = h->nsub;
   std::vector<int> all(nsub);
@@ -838,8 +843,8 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
   // that failed the pivot test and their inverses go back to the caller as
   // a step to enqueue later: nothing before the PCG needs them, and the
   // eigen sweeps, once few subdomains are active, leave most CUs idle.
-  return [h, &X, A, S, st, nsub, mixed, f64list = std::move(f64list),
-          ok32 = std::move(inv32)]() mutable {
+  return [h, &X, A, S, nsub, mixed, f64list = std::move(f64list),
+          ok32 = std::move(inv32)](hipStream_t st) mutable {
     if (!ok32.empty()) {
       std::vector<int2> tj = trtri_job_list(ok32, h->LD.nt, true);
       X.tjobs32.upload(tj, st);
@@ -928,7 +933,8 @@ std::function<void()> setup_local(geneo_handle_s* h, SetupScratch& X, const gene
         ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
         if (steps) {
           HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                                   h->jobs64.p, h->njobs64, mx, X.status.p, st));
+                                   h->jobs64.p, h->njobs64, mx, X.status.p, st, nullptr,
+                                   X.u64R));
         } else {
           HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p,
                                      h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0,
@@ -1166,7 +1172,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     h->trsm = tune_trsm(h, X, LN, sb);
     if (o.eig_solve > 0) h->trsm.variant = h->trsm.split_variant = o.eig_solve - 1;
   }
-  if (b > 32) h->trsm.variant = 1;  // the only unsplit kernel of b = 48
+  if (b > 32 && (h->trsm.variant & 1) == 0) h->trsm.variant += 1;  // unsplit b = 48
   if (o.eig_split != 0) h->trsm.split_limit = std::min(std::max(o.eig_split, 0), nsub);
   if (trsm_max_split(b) == 1) h->trsm.split_limit = 0;
   h->info.eig_solve = h->trsm.variant + 1;
@@ -1399,6 +1405,29 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     X.pairs.alloc(np);
     HIPCHK(launch_pairs(X.adj.p, nsub, X.pcnt.p, X.poff.p, X.pairs.p, X.npairs.p, sb, false));
     h->ntc = (nc + TS - 1) / TS;
+    // tile envelope of A_H: its blocks are nonzero only for adjacent pairs
+    // (the rows of subdomain i start at the first adjacent subdomain's
+    // columns); box subdomains in lexicographic order make it banded
+    // (without the option: E(t) = 0, dense)
+    std::vector<int> envHE(h->ntc, 0), envHR(h->ntc, h->ntc - 1);
+    if (o.envelope) {
+      for (int t = 0; t < h->ntc; ++t) envHE[t] = t;
+      const std::vector<int2> pr = download(X.pairs.p, np, sb);
+      std::vector<int> first(nsub, nsub);
+      for (const int2& q : pr)  // (i, j), j <= i
+        if (h->m_host[q.y] > 0) first[q.x] = std::min(first[q.x], q.y);
+      for (int i = 0; i < nsub; ++i)
+        if (h->m_host[i] > 0 && first[i] < nsub)
+          for (int r = coff[i]; r < coff[i + 1]; ++r)
+            envHE[r / TS] = std::min(envHE[r / TS], coff[first[i]] / TS);
+      for (int t = h->ntc - 2; t >= 0; --t) envHE[t] = std::min(envHE[t], envHE[t + 1]);
+      for (int k = h->ntc - 1, i = h->ntc - 1; k >= 0; --k) {
+        while (envHE[i] > k) --i;
+        envHR[k] = i;
+      }
+      X.envHE.upload(envHE, sb);
+      X.envHR.upload(envHR, sb);
+    }
     X.AHt.alloc(tri_tiles(h->ntc) * TSQ);
     X.DH.alloc((size_t)h->ntc * TSQ);
     HIPCHK(launch_coarse_init(X.AHt.p, h->ntc, nc, sb));
@@ -1418,9 +1447,13 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     X.hdoff.upload(std::vector<int64_t>{0}, sb);
     X.hjob.upload(std::vector<int>{0}, sb);
     {
-      ProfScope ps("coarse_chol", sb, 8.0 * packed(nc), std::pow((double)nc, 3) / 3.0);
+      const EnvWork ew = env_work(envHE, std::vector<int64_t>{0}, std::vector<int>{h->ntc},
+                                  std::vector<int>{0});
+      ProfScope ps("coarse_chol", sb, 2.0 * 8.0 * TSQ * ew.tiles[0],
+                   2.0 * TS * TS * TS * ew.prods + (double)TS * TS * TS * ew.tiles[0]);
       HIPCHK(launch_chol_steps(X.AHt.p, X.DH.p, h->htoff.p, X.hdoff.p, h->hnt.p, X.hjob.p, 1,
-                               h->ntc, X.cst.p, sb, X.cpiv.p));
+                               h->ntc, X.cst.p, sb, X.cpiv.p, o.envelope ? X.envHR.p : nullptr,
+                               o.envelope ? envHR.data() : nullptr));
     }
     X.check_cst = true;  // read at the end of the setup (a failed factor only costs its inverse)
     h->bytes_symvH = 8.0 * packed(nc) + 16.0 * nc;
@@ -1430,7 +1463,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
     X.ljobsH.upload(lj, sb);
     X.XTH.alloc(tri_tiles(h->ntc) * TSQ);
     HIPCHK(launch_trtri(false, X.AHt.p, X.DH.p, X.XTH.p, h->htoff.p, X.hdoff.p, h->hnt.p,
-                        X.tjobsH.p, (int)tj.size(), nullptr, sb));
+                        X.tjobsH.p, (int)tj.size(), o.envelope ? X.envHE.p : nullptr, sb));
     h->SH.alloc(tri_tiles(h->ntc) * TSQ);
     h->WH.alloc(tri_tiles(h->ntc) * TS);
     HIPCHK(launch_lauum(false, X.XTH.p, h->SH.p, h->htoff.p, h->hnt.p, X.ljobsH.p, (int)lj.size(),
@@ -1546,11 +1579,11 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   // waiting on either.
   LocalLayout LN;
   tmL.start(st);
-  std::function<void()> local_step = setup_local(h, X, A, S, st, [&](hipEvent_t after) {
+  std::function<void(hipStream_t)> local_step = setup_local(h, X, A, S, st, [&](hipEvent_t after) {
     if (coarse) setup_shifted(h, X, LN, S, An, Ao, h->hs, tmC, after);
   });
   const std::function<void()> local_rest = [&]() {
-    local_step();
+    local_step(st);
     tmL.stop(st);
   };
   if (coarse) setup_coarse(h, X, LN, S, An, Ao, h->hs, tmC, local_rest);
@@ -2153,7 +2186,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "symv_tiles must be 0, 8, 16 or 32");
     if (o.refine < 0 || o.refine > 8 || !(o.refine_rtol > 0 && o.refine_rtol < 1))
       fail(GENEO_ERR_ARG, "refine must be 0..8 with 0 < refine_rtol < 1");
-    if (o.eig_solve < 0 || o.eig_solve > 2) fail(GENEO_ERR_ARG, "eig_solve must be 0, 1 or 2");
+    if (o.eig_solve < 0 || o.eig_solve > trsm_variants())
+      fail(GENEO_ERR_ARG, "eig_solve must be 0 .. " + std::to_string(trsm_variants()));
     if (o.eig_split < -1) fail(GENEO_ERR_ARG, "eig_split must be -1, 0 or positive");
     if (o.envelope != 0 && o.envelope != 1) fail(GENEO_ERR_ARG, "envelope must be 0 or 1");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);

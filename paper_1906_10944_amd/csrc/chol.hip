@@ -873,17 +873,20 @@ __global__ __launch_bounds__(64) void k_step_potrf(double* __restrict__ A, doubl
   if (threadIdx.x == 0 && (f || k == 0)) status[j] = f ? k * TS + f : 0;
 }
 
-// L_ik = A_ik Linv_kk^T, one workgroup per tile i > k
+// L_ik = A_ik Linv_kk^T, one workgroup per tile i > k (down to the last
+// nonzero tile R(k) of column k when the envelope envR is given)
 __global__ __launch_bounds__(256) void k_step_trsm(double* __restrict__ A,
                                                    const double* __restrict__ Di,
                                                    const int64_t* __restrict__ toff,
                                                    const int64_t* __restrict__ doff,
                                                    const int* __restrict__ ntl,
                                                    const int* __restrict__ jobs, int k,
-                                                   const int* __restrict__ status) {
+                                                   const int* __restrict__ status,
+                                                   const int* __restrict__ envR) {
   const int j = jobs[blockIdx.y];
   const int i = k + 1 + blockIdx.x;
   if (i >= ntl[j] || status[j]) return;
+  if (envR && i > envR[doff[j] + k]) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rq = w >> 1, cq = w & 1;
   double* X = A + (toff[j] + tile_idx(i, k)) * TSQ;
@@ -895,12 +898,15 @@ __global__ __launch_bounds__(256) void k_step_trsm(double* __restrict__ A,
   for (int v = 0; v < 4; ++v) X[(rq * 16 + acc_row<double>(lane, v)) * TS + cq * 16 + acc_col(lane)] = acc[v];
 }
 
-// A_ij -= L_ik L_jk^T for k < j <= i; blockIdx.x enumerates the trailing tiles
+// A_ij -= L_ik L_jk^T for k < j <= i (<= R(k) with the envelope: below it
+// L_ik is zero); blockIdx.x enumerates the trailing tiles
 __global__ __launch_bounds__(256) void k_step_update(double* __restrict__ A,
                                                      const int64_t* __restrict__ toff,
+                                                     const int64_t* __restrict__ doff,
                                                      const int* __restrict__ ntl,
                                                      const int* __restrict__ jobs, int k,
-                                                     const int* __restrict__ status) {
+                                                     const int* __restrict__ status,
+                                                     const int* __restrict__ envR) {
   const int j = jobs[blockIdx.y];
   const int nt = ntl[j];
   if (status[j]) return;
@@ -913,6 +919,7 @@ __global__ __launch_bounds__(256) void k_step_update(double* __restrict__ A,
   i += k + 1;
   jj += k + 1;
   if (i >= nt) return;
+  if (envR && i > envR[doff[j] + k]) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rq = w >> 1, cq = w & 1;
   if (i == jj && rq == 0 && cq == 1) return;
@@ -927,17 +934,19 @@ __global__ __launch_bounds__(256) void k_step_update(double* __restrict__ A,
 
 hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
                              const int64_t* doff, const int* nt, const int* jobs, int njobs,
-                             int maxnt, int* status, hipStream_t st, const double* pivtol) {
+                             int maxnt, int* status, hipStream_t st, const double* pivtol,
+                             const int* envR, const int* rlast) {
   if (njobs <= 0) return hipSuccess;
   for (int k = 0; k < maxnt; ++k) {
     hipLaunchKernelGGL(k_step_potrf, dim3(njobs), dim3(64), 0, st, tiles, dinv, toff, doff, nt,
                        jobs, k, status, pivtol);
-    const int rem = maxnt - k - 1;
+    // tile rows below the diagonal that the step reaches
+    const int rem = (rlast ? std::min(rlast[k], maxnt - 1) : maxnt - 1) - k;
     if (rem > 0) {
       hipLaunchKernelGGL(k_step_trsm, dim3(rem, njobs), dim3(256), 0, st, tiles, dinv, toff,
-                         doff, nt, jobs, k, status);
+                         doff, nt, jobs, k, status, envR);
       hipLaunchKernelGGL(k_step_update, dim3(rem * (rem + 1) / 2, njobs), dim3(256), 0, st,
-                         tiles, toff, nt, jobs, k, status);
+                         tiles, toff, doff, nt, jobs, k, status, envR);
     }
   }
   return hipGetLastError();

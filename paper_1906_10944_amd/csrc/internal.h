@@ -88,11 +88,15 @@ hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff,
 // step over all of them (maxnt = largest tile order): for a few matrices,
 // where one workgroup per matrix would hold CUs for the whole
 // factorisation.  status[j] = 0 or TS k + f at the first failed pivot: a
-// pivot d fails unless d > *pivtol (pivtol: device, NULL = 0).
+// pivot d fails unless d > *pivtol (pivtol: device, NULL = 0).  envR
+// (device, at doff; NULL = dense): the last nonzero tile row of each tile
+// column, below which the steps skip the zero tiles; rlast (host [maxnt],
+// NULL = dense): its largest value over the matrices, which sizes the grids.
 hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
                              const int64_t* doff, const int* nt, const int* jobs, int njobs,
                              int maxnt, int* status, hipStream_t st,
-                             const double* pivtol = nullptr);
+                             const double* pivtol = nullptr, const int* envR = nullptr,
+                             const int* rlast = nullptr);
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
@@ -167,11 +171,12 @@ hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st);
 // Triangular solves with the shifted factors, one workgroup per subdomain
 // (split = 1) or b / 16 per subdomain, each on 16 of the b columns
 // (split = trsm_max_split(b) > 1), for the first nsub entries of `order`
-// (may be NULL = by index); `variant` (0 or 1) picks the kernel (0 is not
-// available unsplit for b = 48).  envE / envR: the factors' tile envelopes
+// (may be NULL = by index); `variant` (0 .. trsm_variants() - 1) picks the
+// kernel (0 and 2 are not available unsplit for b = 48: 1 and 3 run).  envE / envR: the factors' tile envelopes
 // (NULL: dense); the zero tiles outside them are skipped.  Every variant
 // and split gives bitwise the same X, and so does the envelope.
 int trsm_max_split(int b);
+int trsm_variants();
 hipError_t launch_trsm_fwd(const double* G, const double* dinv, const int64_t* toff,
                            const int64_t* doff, const int* nt, const int* voff, int nsub,
                            int b, const double* R, double* X, const int* active,

@@ -410,10 +410,10 @@ __global__ __launch_bounds__(1024) void k_trsm_bwd(const double* __restrict__ G,
 
 // ----------------------------------------- windowed multi-RHS substitution ---
 // Forward G X = R and backward G^T X = R for the eigen sweeps, one
-// workgroup of 8 wavefronts per subdomain.  The tile rows are taken in
-// windows of TRW_W = 16; the 32 x b blocks of the current window stay in
+// workgroup of NW (8 or 4) wavefronts per subdomain.  The tile rows are
+// taken in windows of 2 NW; the 32 x b blocks of the current window stay in
 // registers as matrix-core accumulators (wavefront w owns window rows
-// w and w + 8).  Each window first takes its update from all finished rows
+// w and w + NW).  Each window first takes its update from all finished rows
 // (left-looking; factor tiles streamed with the next one prefetched, no
 // barriers), then is solved right-looking: the owner of row i forms
 // X_i = Dinv_i acc_i (or Dinv_i^T acc_i) and publishes it, transposed, in
@@ -421,9 +421,7 @@ __global__ __launch_bounds__(1024) void k_trsm_bwd(const double* __restrict__ G,
 // from its later rows.  b = 16 * NCQ right-hand sides, b <= 32 (wider
 // blocks take the row-by-row kernels above: their accumulators would not
 // fit in registers).
-#define TRW_NW 8
 #define TRW_MR 2
-#define TRW_W (TRW_NW * TRW_MR)
 
 struct F8 { double v[8]; };
 
@@ -534,8 +532,8 @@ __device__ __forceinline__ int trsm_slot(int bid, int& part) {
   return (bid & 7) + 8 * (bid / (8 * SPLIT));
 }
 
-template <int NCQ, bool BWD, int LDB>
-__global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restrict__ G,
+template <int NCQ, bool BWD, int LDB, int NW>
+__global__ __launch_bounds__(NW * 64, 2) void k_trsm_win(const double* __restrict__ G,
                                                          const double* __restrict__ dinv,
                                                          const int64_t* __restrict__ toff,
                                                          const int64_t* __restrict__ doff,
@@ -563,7 +561,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
   double* Xj = X + (int64_t)voff[j] * LDB + part * b;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int fi = lane & 15, fg = lane >> 4;
-  const int nwin = (nt + TRW_W - 1) / TRW_W;
+  const int nwin = (nt + NW * TRW_MR - 1) / (NW * TRW_MR);
   // envelope: row k has nonzero tiles from column E(k), column k down to
   // row R(k) (all others are zero: their products are skipped)
   const int* Ej = envE ? envE + doff[j] : nullptr;
@@ -572,13 +570,13 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
   auto last = [&](int k) { return Rl ? Rl[k] : nt - 1; };
   for (int wi = 0; wi < nwin; ++wi) {
     // window rows [p0, p1); BWD windows run from the bottom
-    const int p0 = BWD ? max(0, nt - (wi + 1) * TRW_W) : wi * TRW_W;
-    const int p1 = BWD ? nt - wi * TRW_W : min(nt, p0 + TRW_W);
+    const int p0 = BWD ? max(0, nt - (wi + 1) * NW * TRW_MR) : wi * NW * TRW_MR;
+    const int p1 = BWD ? nt - wi * NW * TRW_MR : min(nt, p0 + NW * TRW_MR);
     d4_t acc[TRW_MR][2][NCQ];
     int krow[TRW_MR];
 #pragma unroll
     for (int m = 0; m < TRW_MR; ++m) {
-      krow[m] = p0 + w + TRW_NW * m;
+      krow[m] = p0 + w + NW * m;
       const bool own = krow[m] < p1;
 #pragma unroll
       for (int rq = 0; rq < 2; ++rq)
@@ -627,7 +625,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
     // ---- right-looking solve inside the window
     for (int st = 0; st < p1 - p0; ++st) {
       const int i = BWD ? p1 - 1 - st : p0 + st;
-      const int li = i - p0, ow = li % TRW_NW, om = li / TRW_NW;
+      const int li = i - p0, ow = li % NW, om = li / NW;
       double* sXo = sX[st & 1];
       if (w == ow) {
 #pragma unroll
@@ -681,7 +679,7 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
 }
 
 // Windowed substitution with deeper load pipelines.  One workgroup of
-// TW1_NW = 8 wavefronts per subdomain; windows of 8 tile rows, wavefront w
+// NW (8 or 4) wavefronts per subdomain; windows of NW tile rows, wavefront w
 // owning window row p0 + w (its 32 x b block as matrix-core accumulators,
 // holding -R + the products so far).  The left-looking update streams the
 // row's factor tiles with AD tiles in flight beyond the one in use and,
@@ -691,10 +689,9 @@ __global__ __launch_bounds__(TRW_NW * 64) void k_trsm_win(const double* __restri
 // sides is 32 MFMAs, about one HBM round trip).  AD and BP are chosen per
 // block width so that the pipelines fit in 256 VGPRs without spills.  The
 // substitution inside the window is the right-looking one of k_trsm_win.
-#define TW1_NW 8
 
-template <int NCQ, bool BWD, int AD, bool BP, int LDB>
-__global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restrict__ G,
+template <int NCQ, bool BWD, int AD, bool BP, int LDB, int NW>
+__global__ __launch_bounds__(NW * 64, 2) void k_trsm_w1(const double* __restrict__ G,
                                                         const double* __restrict__ dinv,
                                                         const int64_t* __restrict__ toff,
                                                         const int64_t* __restrict__ doff,
@@ -723,7 +720,7 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
   double* Xj = X + (int64_t)voff[j] * LDB + part * b;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int fi = lane & 15, fg = lane >> 4;
-  const int nwin = (nt + TW1_NW - 1) / TW1_NW;
+  const int nwin = (nt + NW - 1) / NW;
   // envelope (as in k_trsm_win)
   const int* Ej = envE ? envE + doff[j] : nullptr;
   const int* Rl = envR ? envR + doff[j] : nullptr;
@@ -741,8 +738,8 @@ __global__ __launch_bounds__(TW1_NW * 64) void k_trsm_w1(const double* __restric
   auto loadB = [&](F8& bb, int jj, int cq) { bfrag_g(bb, Xj + (int64_t)jj * TS * LDB, LDB, cq * 16, fi, fg); };
   for (int wi = 0; wi < nwin; ++wi) {
     // window rows [p0, p1); BWD windows run from the bottom
-    const int p0 = BWD ? max(0, nt - (wi + 1) * TW1_NW) : wi * TW1_NW;
-    const int p1 = BWD ? nt - wi * TW1_NW : min(nt, p0 + TW1_NW);
+    const int p0 = BWD ? max(0, nt - (wi + 1) * NW) : wi * NW;
+    const int p1 = BWD ? nt - wi * NW : min(nt, p0 + NW);
     const int k = p0 + w;
     const bool own = k < p1;
     d4_t acc[2][NCQ];
@@ -839,36 +836,36 @@ static dim3 trsm_grid(int nsub, int split) {
 
 #define TRSM_ARGS G, dinv, toff, doff, nt, voff, R, X, active, order, nsub, envE, envR
 
-template <bool BWD>
+template <bool BWD, int NW>
 static hipError_t launch_trsm_w1(const double* G, const double* dinv, const int64_t* toff,
                                  const int64_t* doff, const int* nt, const int* voff, int nsub,
                                  int b, int split, const double* R, double* X, const int* active,
                                  const int* order, const int* envE, const int* envR,
-                                  hipStream_t st) {
-  const dim3 grid = trsm_grid(nsub, split), blk(TW1_NW * 64);
+                                 hipStream_t st) {
+  const dim3 grid = trsm_grid(nsub, split), blk(NW * 64);
   switch (split == 1 ? b : -b) {
-    case 16: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 16>), grid, blk, 0, st, TRSM_ARGS); break;
-    case 32: hipLaunchKernelGGL((k_trsm_w1<2, BWD, 1, true, 32>), grid, blk, 0, st, TRSM_ARGS); break;
-    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false, 48>), grid, blk, 0, st, TRSM_ARGS); break;
-    case -32: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 32>), grid, blk, 0, st, TRSM_ARGS); break;
-    case -48: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 48>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 16: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 16, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 32: hipLaunchKernelGGL((k_trsm_w1<2, BWD, 1, true, 32, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 48: hipLaunchKernelGGL((k_trsm_w1<3, BWD, 1, false, 48, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -32: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 32, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -48: hipLaunchKernelGGL((k_trsm_w1<1, BWD, 2, true, 48, NW>), grid, blk, 0, st, TRSM_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <bool BWD>
+template <bool BWD, int NW>
 static hipError_t launch_trsm_win(const double* G, const double* dinv, const int64_t* toff,
                                   const int64_t* doff, const int* nt, const int* voff, int nsub,
                                   int b, int split, const double* R, double* X, const int* active,
                                   const int* order, const int* envE, const int* envR,
                                   hipStream_t st) {
-  const dim3 grid = trsm_grid(nsub, split), blk(TRW_NW * 64);
+  const dim3 grid = trsm_grid(nsub, split), blk(NW * 64);
   switch (split == 1 ? b : -b) {
-    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD, 16>), grid, blk, 0, st, TRSM_ARGS); break;
-    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD, 32>), grid, blk, 0, st, TRSM_ARGS); break;
-    case -32: hipLaunchKernelGGL((k_trsm_win<1, BWD, 32>), grid, blk, 0, st, TRSM_ARGS); break;
-    case -48: hipLaunchKernelGGL((k_trsm_win<1, BWD, 48>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 16: hipLaunchKernelGGL((k_trsm_win<1, BWD, 16, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case 32: hipLaunchKernelGGL((k_trsm_win<2, BWD, 32, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -32: hipLaunchKernelGGL((k_trsm_win<1, BWD, 32, NW>), grid, blk, 0, st, TRSM_ARGS); break;
+    case -48: hipLaunchKernelGGL((k_trsm_win<1, BWD, 48, NW>), grid, blk, 0, st, TRSM_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -878,10 +875,15 @@ static hipError_t launch_trsm_win(const double* G, const double* dinv, const int
 
 int trsm_max_split(int b) { return b <= 48 ? b / 16 : 1; }
 
-// b <= 48, split 1: variant 0 two rows per wavefront (each right-hand block
-// feeds both; b <= 32 only, b = 48 takes variant 1), variant 1 one row per
-// wavefront with deeper load pipelines.  split = b / 16: the same kernels
-// on 16-column blocks, b / 16 workgroups per subdomain.  Every choice gives
+int trsm_variants() { return 4; }
+
+// b <= 48: variant 0 two rows per wavefront, 8 wavefronts (windows of 16
+// rows; b <= 32 unsplit), variant 1 one row per wavefront with deeper load
+// pipelines, 8 wavefronts (windows of 8), variants 2 and 3 the same with 4
+// wavefronts (half the window; two workgroups fit a CU, so two subdomains'
+// substitution chains interleave).  split = b / 16: the same kernels on
+// 16-column blocks, b / 16 workgroups per subdomain.  Every choice forms
+// each row's sum over the columns in ascending order, whatever the window:
 // bitwise the same X.  b = 64: row by row.
 template <bool BWD>
 static hipError_t launch_trsm(const double* G, const double* dinv, const int64_t* toff,
@@ -890,13 +892,21 @@ static hipError_t launch_trsm(const double* G, const double* dinv, const int64_t
                               const int* order, const int* envE, const int* envR, int variant,
                               int split, hipStream_t st) {
   if (split != 1 && (b > 48 || split != b / 16)) return hipErrorInvalidValue;
-  if (!envE != !envR) return hipErrorInvalidValue;
-  if (b <= 48 && variant == 0 && (b <= 32 || split != 1))
-    return launch_trsm_win<BWD>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X, active,
-                                order, envE, envR, st);
-  if (b <= 48)
-    return launch_trsm_w1<BWD>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X, active,
-                               order, envE, envR, st);
+  if (!envE != !envR || variant < 0 || variant > 3) return hipErrorInvalidValue;
+  // b = 48 unsplit has no two-rows kernel (its accumulators would spill)
+  if (b == 48 && split == 1 && (variant & 1) == 0) variant += 1;
+  if (b <= 48) {
+    switch (variant) {
+      case 0: return launch_trsm_win<BWD, 8>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X,
+                                             active, order, envE, envR, st);
+      case 1: return launch_trsm_w1<BWD, 8>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X,
+                                            active, order, envE, envR, st);
+      case 2: return launch_trsm_win<BWD, 4>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X,
+                                             active, order, envE, envR, st);
+      default: return launch_trsm_w1<BWD, 4>(G, dinv, toff, doff, nt, voff, nsub, b, split, R, X,
+                                             active, order, envE, envR, st);
+    }
+  }
   if (BWD)
     hipLaunchKernelGGL(k_trsm_bwd, dim3(nsub), dim3(1024), 0, st, G, dinv, toff, doff, nt, voff,
                        b, R, X, active, envE, envR);

@@ -102,10 +102,11 @@ def test_sweep_flags_read_late_or_at_once_give_the_same_operator():
 @pytest.mark.parametrize("nev,tau", [(4, None), (None, 0.1), (24, None)],
                          ids=["b16", "b32", "b48"])
 def test_every_eigen_solve_kernel_gives_the_same_operator(nev, tau):
-    """The eigen sweeps' triangular solves have two kernels (two tile rows
-    per wavefront, or one with deeper load pipelines), each also on
-    16-column blocks with b / 16 workgroups per subdomain; all form the same
-    sums in the same order, and the setup times them and keeps the fastest.
+    """The eigen sweeps' triangular solves have four kernels (two tile rows
+    per wavefront, or one with deeper load pipelines; 8 or 4 wavefronts per
+    subdomain), each also on 16-column blocks with b / 16 workgroups per
+    subdomain; all form the same sums in the same order, and the setup
+    times them and keeps the fastest.
     Forced every way (and tuned), the sweep count, the eigenvalues, the
     coarse basis and the operator agree bit for bit."""
     need_gpu()
@@ -117,7 +118,8 @@ def test_every_eigen_solve_kernel_gives_the_same_operator(nev, tau):
     r = np.random.default_rng(13).standard_normal(prob.ndof)
     outs = []
     never, always = -1, prob.nsub
-    for v, sp in ((1, never), (2, never), (1, always), (2, always), (0, 0)):
+    for v, sp in ((1, never), (2, never), (3, never), (4, never), (1, always), (2, always),
+                  (3, always), (4, always), (0, 0)):
         h = gpu_setup(sysm, prob, precision=1, eig_solve=v, eig_split=sp)
         info = G.geneo_get_setup_info(h)
         m, lam = G.geneo_get_eigenvalues(h, prob.nsub)
@@ -127,7 +129,8 @@ def test_every_eigen_solve_kernel_gives_the_same_operator(nev, tau):
             info["eig_block"], "sweeps", info["eig_sweeps"])
         assert info["eig_block"] == {4: 16, None: 32, 24: 48}[nev]
         if v:
-            assert info["eig_solve"] == (v if info["eig_block"] <= 32 else 2)
+            # b = 48 unsplit has only the one-row kernels (2 and 4)
+            assert info["eig_solve"] == (v if info["eig_block"] <= 32 or v % 2 == 0 else v + 1)
         if sp == never or info["eig_block"] == 16:
             assert info["eig_split"] == 0
         elif sp == always:
@@ -139,7 +142,8 @@ def test_every_eigen_solve_kernel_gives_the_same_operator(nev, tau):
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("case", ["layers3d_mixed", "laminate_mixed", "grf36_fp64"])
+@pytest.mark.parametrize("case", ["layers3d_mixed", "layers3d_fp64", "laminate_mixed",
+                                  "grf36_fp64"])
 def test_envelope_gives_the_same_operator_as_dense(case):
     """The factorisations and the eigen solves skip the tiles outside each
     matrix's envelope (zero in the factors: no fill-in reaches them).  The
@@ -147,11 +151,12 @@ def test_envelope_gives_the_same_operator_as_dense(case):
     computation's bit for bit: sweeps, eigenvalues, coarse basis and
     matrix, apply and PCG solution.  The FP64 case has more than 32
     subdomains, so its local factors take the batched kernel (fewer take the
-    dense tile-column steps)."""
+    tile-column steps, as does the coarse matrix)."""
     need_gpu()
     from paper_1906_10944_amd import geneo as G
     prob, prec = {
         "layers3d_mixed": (lambda: synth.layers_3d(seed=4, n=24, parts=2, ovl=1, nev=6), 1),
+        "layers3d_fp64": (lambda: synth.layers_3d(seed=4, n=24, parts=2, ovl=1, nev=6), 0),
         "laminate_mixed": (lambda: synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1), nev=8), 1),
         "grf36_fp64": (lambda: synth.grf_2d(seed=7, n=96, parts=6, ovl=2, inclusions=3), 0),
     }[case]
