@@ -1025,7 +1025,23 @@ __global__ __launch_bounds__(256) void k_bapply(const int* __restrict__ sub_ptr,
   const int g = sub_ptr[j] + a;
   const double* Xj = X + (int64_t)voff[j] * b;
   double s = 0.0;
-  for (int p = brp[g]; p < brp[g + 1]; ++p) s += bval[p] * Xj[(int64_t)bcol[p] * b + c];
+  // entries in batches of 8: all index and value loads, then all the
+  // gathers of X, are in flight together; the sum keeps the entry order
+  const int p0 = brp[g], p1 = brp[g + 1];
+  for (int p = p0; p < p1; p += 8) {
+    int cc[8];
+    double vv[8], xx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cc[u] = p + u < p1 ? bcol[p + u] : 0;
+      vv[u] = p + u < p1 ? bval[p + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xx[u] = p + u < p1 ? Xj[(int64_t)cc[u] * b + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (p + u < p1) s += vv[u] * xx[u];
+  }
   Y[((int64_t)voff[j] + a) * b + c] = s;
 }
 
