@@ -96,25 +96,38 @@ def build(prob):
     for b in boxes:
         mult[_box_ids([x[0] for x in b], [x[1] for x in b], estr)] += 1
 
+    s20 = getattr(prob, "element", "q1") == "s20"
+    if s20:
+        # serendipity nodes: lattice of half-edge steps (coordinates scaled by 2)
+        xyz = fem.s20_node_coords(prob)
     subs = []
     icount = np.zeros(prob.ndof, dtype=np.int64)
     for j, b in enumerate(boxes):
         lo = [x[0] for x in b]
         hi = [x[1] for x in b]
         elems = _box_ids(lo, hi, estr)
-        nodes = _box_ids(lo, [h + 1 for h in hi], nstr)
+        if s20:
+            inbox = np.ones(prob.nnodes, dtype=bool)
+            for ax in range(dim):
+                inbox &= (xyz[:, ax] >= 2 * lo[ax]) & (xyz[:, ax] <= 2 * hi[ax])
+            nodes = np.flatnonzero(inbox)
+            coords = [xyz[nodes, ax] for ax in range(dim)]
+            sc = 2
+        else:
+            nodes = _box_ids(lo, [h + 1 for h in hi], nstr)
+            coords = []
+            k = nodes.copy()
+            for ax in range(dim):
+                coords.append(k % nn[ax])
+                k //= nn[ax]
+            sc = 1
         # artificial boundary: box face strictly inside the grid
-        coords = []
-        k = nodes.copy()
-        for ax in range(dim):
-            coords.append(k % nn[ax])
-            k //= nn[ax]
         art = np.zeros(len(nodes), dtype=bool)
         for ax in range(dim):
             if lo[ax] > 0:
-                art |= coords[ax] == lo[ax]
+                art |= coords[ax] == sc * lo[ax]
             if hi[ax] < ne[ax]:
-                art |= coords[ax] == hi[ax]
+                art |= coords[ax] == sc * hi[ax]
         if c == 1:
             dofs = nodes
             interior = ~art

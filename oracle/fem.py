@@ -1,4 +1,5 @@
-"""Q1 finite elements on a structured box grid (oracle; test infrastructure).
+"""Q1 and 20-node serendipity finite elements on a structured box grid
+(oracle; test infrastructure).
 
 Discretises the Darcy form (Sec. 2, eq. (2)) and the linear-elasticity form
 (Sec. 2, eq. (3), no traction term) with a conforming space of continuous
@@ -140,6 +141,114 @@ def elasticity_element_matrix(h, C):
     return K
 
 
+# --------------------------------------------- 20-node serendipity bricks
+#
+# The quadratic serendipity brick (the element of the paper's composite
+# experiments, Sec. 5.3): nodes at the 8 vertices and the 12 edge midpoints.
+# Nodes of a mesh of ne bricks live on the lattice of half-edge steps,
+# coordinates 0 .. 2 ne per axis, at the points with at most one odd
+# coordinate; they are numbered lexicographically (x fastest) over those
+# points, which keeps the matrices banded.  Element integrals use the tensor
+# 3-point Gauss rule, exact for the products of the shape gradients (degree
+# at most 4 per coordinate) with a constant coefficient.
+
+_G3 = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)])  # on [-1, 1]
+_W3 = np.array([5.0, 8.0, 5.0]) / 9.0
+
+
+def s20_offsets():
+    """Local nodes as lattice offsets in {0, 1, 2}^3: the 8 vertices (bit i of
+    the index = coordinate i), then the midpoints of the edges along x, y
+    and z (4 each, the other two coordinates in bit order)."""
+    corners = [[2 * ((a >> i) & 1) for i in range(3)] for a in range(8)]
+    edges = []
+    for ax in range(3):
+        o1, o2 = [o for o in range(3) if o != ax]
+        for b in range(4):
+            o = [0, 0, 0]
+            o[ax] = 1
+            o[o1] = 2 * (b & 1)
+            o[o2] = 2 * (b >> 1)
+            edges.append(o)
+    return np.array(corners + edges)
+
+
+def s20_shape_and_grad(xi):
+    """Serendipity shape values and gradients at xi in the reference brick
+    [-1, 1]^3: a vertex node at c in {-1, 1}^3 has
+    N = (c . xi - 2) prod_i (1 + c_i xi_i) / 8, an edge midpoint with c_a = 0
+    has N = (1 - xi_a^2) prod_{i != a} (1 + c_i xi_i) / 4."""
+    off = s20_offsets()
+    N = np.zeros(20)
+    dN = np.zeros((20, 3))
+    for a, o in enumerate(off):
+        c = o - 1
+        t = 1.0 + c * xi
+        if np.all(c != 0):
+            s = float(np.dot(c, xi)) - 2.0
+            p = t[0] * t[1] * t[2]
+            N[a] = p * s / 8.0
+            for i in range(3):
+                pi = np.prod([t[j] for j in range(3) if j != i])
+                dN[a, i] = (c[i] * pi * s + p * c[i]) / 8.0
+        else:
+            ax = int(np.flatnonzero(c == 0)[0])
+            q = 1.0 - xi[ax] ** 2
+            o1, o2 = [i for i in range(3) if i != ax]
+            N[a] = q * t[o1] * t[o2] / 4.0
+            dN[a, ax] = -2.0 * xi[ax] * t[o1] * t[o2] / 4.0
+            dN[a, o1] = q * c[o1] * t[o2] / 4.0
+            dN[a, o2] = q * c[o2] * t[o1] / 4.0
+    return N, dN
+
+
+def s20_quadrature():
+    """Tensor 3-point Gauss points on [-1, 1]^3 and their weights (sum 8)."""
+    pts, wts = [], []
+    for idx in itertools.product(range(3), repeat=3):
+        pts.append([_G3[i] for i in reversed(idx)])
+        wts.append(np.prod([_W3[i] for i in idx]))
+    return np.array(pts), np.array(wts)
+
+
+def s20_element_matrix(h, C):
+    """Element matrix of int C eps(v):eps(w) over one serendipity brick,
+    dofs node-major (3 per node)."""
+    h = np.asarray(h, dtype=np.float64)
+    pts, wts = s20_quadrature()
+    jac = np.prod(h) / 8.0
+    K = np.zeros((60, 60))
+    for x, w in zip(pts, wts):
+        _, dN = s20_shape_and_grad(x)
+        B = strain_matrix(dN * (2.0 / h)[None, :])
+        K += w * jac * B.T @ C @ B
+    return K
+
+
+def s20_node_count_before(ne, x, y, z):
+    """Node number of lattice point (x, y, z) (vectorised): the valid points
+    (at most one odd coordinate) before it in lexicographic order."""
+    nx, ny = ne[0], ne[1]
+    even_layer = (ny + 1) * (2 * nx + 1) + ny * (nx + 1)
+    odd_layer = (nx + 1) * (ny + 1)
+    x, y, z = (np.asarray(v, dtype=np.int64) for v in (x, y, z))
+    base = (z + 1) // 2 * even_layer + z // 2 * odd_layer
+    ev = (z % 2) == 0
+    # even z: rows y' < y hold 2 nx + 1 (even y') or nx + 1 (odd y') points
+    in_even = (y + 1) // 2 * (2 * nx + 1) + y // 2 * (nx + 1) + np.where(y % 2 == 0, x, x // 2)
+    in_odd = y // 2 * (nx + 1) + x // 2
+    return base + np.where(ev, in_even, in_odd)
+
+
+def s20_node_coords(prob):
+    """Lattice coordinates (nnodes, 3) of the nodes, in node order."""
+    L = [2 * n + 1 for n in prob.ne]
+    z, y, x = np.meshgrid(np.arange(L[2]), np.arange(L[1]), np.arange(L[0]), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    keep = (x % 2) + (y % 2) + (z % 2) <= 1
+    return np.stack([x[keep], y[keep], z[keep]], axis=1)
+
+
 def voigt_full(c21):
     """Symmetric 6x6 matrix from its 21 upper-triangle entries (row major)."""
     C = np.zeros((6, 6))
@@ -149,8 +258,15 @@ def voigt_full(c21):
 
 def element_nodes(prob):
     """(nelem, 2^d) global node numbers of every element, vertex order as in
-    :func:`_local_offsets`."""
+    :func:`_local_offsets` (serendipity: (nelem, 20), order of
+    :func:`s20_offsets`)."""
     ne = prob.ne
+    if getattr(prob, "element", "q1") == "s20":
+        ez, ey, ex = np.meshgrid(*[np.arange(n) for n in reversed(ne)], indexing="ij")
+        ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+        off = s20_offsets()
+        return np.stack([s20_node_count_before(ne, 2 * ex + o[0], 2 * ey + o[1], 2 * ez + o[2])
+                         for o in off], axis=1)
     dim = prob.dim
     nn = [n + 1 for n in ne]
     grids = np.meshgrid(*[np.arange(n) for n in reversed(ne)], indexing="ij")
@@ -188,7 +304,9 @@ def element_matrices(prob, elems=None):
         return prob.coeff[elems][:, None, None] * Kref[None]
     coeff = prob.coeff[elems]
     uniq, inv = np.unique(coeff, axis=0, return_inverse=True)
-    Ku = np.array([elasticity_element_matrix(prob.h, voigt_full(c)) for c in uniq])
+    kmat = s20_element_matrix if getattr(prob, "element", "q1") == "s20" \
+        else elasticity_element_matrix
+    Ku = np.array([kmat(prob.h, voigt_full(c)) for c in uniq])
     return Ku[inv.ravel()]
 
 
@@ -196,6 +314,17 @@ def element_load(prob, f=None):
     """Element load vectors int f phi_a; ``f`` is the constant body load of
     ``prob`` unless a callable f(x) -> (ncomp,) values is given."""
     dim, c = prob.dim, prob.ncomp
+    if getattr(prob, "element", "q1") == "s20":
+        # int N_a over the brick by the 3-point rule, times the load
+        assert f is None
+        pts, wts = s20_quadrature()
+        jac = np.prod(np.asarray(prob.h)) / 8.0
+        ia = np.zeros(20)
+        for x, w in zip(pts, wts):
+            ia += w * jac * s20_shape_and_grad(x)[0]
+        load = np.asarray(prob.load, dtype=np.float64)
+        out = np.broadcast_to(ia[None, :, None] * load[None, None, :], (prob.nelem, 20, c))
+        return out.reshape(prob.nelem, 20 * c).copy()
     pts, wts = quadrature(dim)
     h = np.asarray(prob.h)
     vol = np.prod(h)
@@ -226,6 +355,15 @@ def element_load(prob, f=None):
 
 def dirichlet_mask(prob):
     """Boolean mask over dofs: True where a homogeneous Dirichlet condition holds."""
+    if getattr(prob, "element", "q1") == "s20":
+        xyz = s20_node_coords(prob)
+        m = np.zeros(prob.nnodes, dtype=bool)
+        for ax in range(3):
+            if prob.dirichlet >> (2 * ax) & 1:
+                m |= xyz[:, ax] == 0
+            if prob.dirichlet >> (2 * ax + 1) & 1:
+                m |= xyz[:, ax] == 2 * prob.ne[ax]
+        return np.repeat(m, prob.ncomp)
     nn = [n + 1 for n in prob.ne]
     coords = np.meshgrid(*[np.arange(n) for n in reversed(nn)], indexing="ij")
     coords = [g.ravel() for g in reversed(coords)]

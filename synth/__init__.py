@@ -14,6 +14,7 @@ from .problems import (  # noqa: F401
     grf_2d,
     layers_3d,
     laminate_3d,
+    laminate_s20,
     layered_2d,
     CONFIGS,
 )

@@ -48,6 +48,8 @@ class Problem:
     nev_max: Optional[int] = None     # ... capped at nev_max
     precision: str = "fp64"           # "fp64" or "mixed"
     pou: str = "constant"             # partition of unity: "constant" or "sarkis"
+    element: str = "q1"               # "q1" (trilinear) or "s20" (20-node serendipity
+                                      # bricks, 3D elasticity)
     rtol: float = 1e-10
     maxit: int = 2000
     meta: dict = field(default_factory=dict)
@@ -58,7 +60,12 @@ class Problem:
 
     @property
     def nnodes(self):
-        return int(np.prod([n + 1 for n in self.ne]))
+        corners = int(np.prod([n + 1 for n in self.ne]))
+        if self.element == "q1":
+            return corners
+        # serendipity bricks: the vertices and one node per element edge
+        edges = sum(self.ne[ax] * corners // (self.ne[ax] + 1) for ax in range(3))
+        return corners + edges
 
     @property
     def ndof(self):
@@ -82,6 +89,9 @@ class Problem:
             assert self.dim == 3 and self.coeff.shape == (self.nelem, 21)
         assert len(self.load) == self.ncomp
         assert self.pou in ("constant", "sarkis")
+        assert self.element in ("q1", "s20")
+        if self.element == "s20":
+            assert self.dim == 3 and self.ncomp == 3 and self.pou == "constant"
         for n, p in zip(self.ne, self.parts):
             assert 1 <= p <= n
 
@@ -189,6 +199,26 @@ def laminate_3d(seed=0, ne=(128, 32, 24), parts=(16, 4, 4), ovl=1,
                            h=(1.0, 1.0, 1.0), nev=nev, precision=precision)
     p.meta["seed"] = seed
     return p
+
+
+def laminate_s20(ne=(32, 8, 6), parts=(4, 2, 1), ovl=1, nev=16, precision="mixed"):
+    """The clamped laminate of :func:`laminate_3d` on 20-node serendipity
+    bricks (the element of the paper's composite experiments, Sec. 5.3):
+    the same materials, clamp and load; one-element plies alternating 0 and
+    90 degrees, each followed by a one-element resin layer; unit elements.
+    The default, 32 x 8 x 6 bricks, has 23,175 dofs, near the 30,000 of the
+    paper's composite plate."""
+    ply = F.ply_stiffness(160.0, 10.0, 10.0, 5.0, 5.0, 5.0, 0.3, 0.3, 0.3)
+    mats = [ply, F.isotropic_stiffness(4.0, 0.35), F.rotate_z90(ply)]
+    nx, ny, nz = ne
+    C = np.empty((nz, ny, nx, 6, 6))
+    for iz in range(nz):
+        # ply 0, resin, ply 90, resin, ply 0, ...
+        C[iz] = mats[0] if iz % 4 == 0 else mats[2] if iz % 4 == 2 else mats[1]
+    return elasticity_problem("laminate_s20_%dx%dx%d" % tuple(ne), C, ne, parts, ovl,
+                              dirichlet=0b000001, load=(0.0, 0.0, -1.0),
+                              h=(1.0, 1.0, 1.0), nev=nev, precision=precision,
+                              element="s20")
 
 
 def layered_2d(n=40, parts=4, ovl=2, layers=8, contrast=1e6, nev=4,

@@ -227,3 +227,47 @@ def test_dropped_poisson_coupling_is_caught(monkeypatch):
         return orig(h, C2)
     monkeypatch.setattr(fem, "elasticity_element_matrix", bad)
     assert not _elasticity_pins_hold()
+
+
+# ---------------------------------------------- serendipity brick mutations
+
+def _s20_pins():
+    """The serendipity pins of tests/test_oracle_s20.py, all at once."""
+    import test_oracle_s20 as T
+    try:
+        T.test_shape_functions_interpolate_and_sum_to_one()
+        T.test_shape_functions_reproduce_quadratics()
+        T.test_element_rigid_modes_span_the_kernel()
+        T.test_element_energy_of_linear_fields()
+        T.test_element_energy_of_quadratic_fields()
+        T.test_consistent_load_closed_form()
+    except AssertionError:
+        return False
+    return True
+
+
+def test_s20_pins_hold_on_the_real_oracle():
+    assert _s20_pins()
+
+
+def test_s20_wrong_vertex_shape_function_is_caught(monkeypatch):
+    """Vertex functions with (c . xi - 1) instead of (c . xi - 2)."""
+    real = fem.s20_shape_and_grad
+
+    def wrong(xi):
+        N, dN = real(xi)
+        off = fem.s20_offsets()[:8] - 1
+        for a in range(8):
+            t = np.prod(1.0 + off[a] * xi)
+            N[a] += t / 8.0
+        return N, dN
+    monkeypatch.setattr(fem, "s20_shape_and_grad", wrong)
+    assert not _s20_pins()
+
+
+def test_s20_two_point_rule_is_caught(monkeypatch):
+    """The 2-point Gauss rule (exact for Q1 products, not for the
+    serendipity brick's degree-4 integrands)."""
+    monkeypatch.setattr(fem, "_G3", np.array([-1.0 / np.sqrt(3.0), 1.0 / np.sqrt(3.0), 0.0]))
+    monkeypatch.setattr(fem, "_W3", np.array([1.0, 1.0, 0.0]))
+    assert not _s20_pins()
