@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="layers_96",
-                    choices=["channels_64", "grf_512", "layers_96", "laminate_128x32x24"])
+                    choices=["channels_64", "grf_512", "layers_96", "laminate_128x32x24",
+                             "laminate_s20_32x8x6"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")

@@ -80,9 +80,18 @@ typedef struct {
   double load[3];     /* constant body load per component */
   int pou;            /* partition of unity: GENEO_POU_CONSTANT or
                          GENEO_POU_SARKIS (see geneo_assemble_q1) */
+  int element;        /* GENEO_ELEM_Q1, or GENEO_ELEM_S20: 20-node
+                         serendipity bricks (the element of the paper's
+                         composite experiments, Sec. 5.3; 3D elasticity,
+                         piecewise-constant partition of unity).  Nodes: the
+                         points of the half-step lattice (coordinates 0 ..
+                         2 ne per axis) with at most one odd coordinate,
+                         numbered lexicographically (x fastest) over those;
+                         element integrals by the 3-point Gauss rule. */
 } geneo_grid_t;
 
 enum { GENEO_POU_CONSTANT = 0, GENEO_POU_SARKIS = 1 };
+enum { GENEO_ELEM_Q1 = 0, GENEO_ELEM_S20 = 1 };
 
 /* Sizes of the arrays geneo_assemble_q1 writes. */
 typedef struct {

@@ -1,4 +1,5 @@
-// Structured Q1 assembly on the device: the global stiffness matrix of the
+// Structured Q1 assembly on the device (serendipity bricks: s20.hip): the
+// global stiffness matrix of the
 // Darcy form (eq. (2)) or the elasticity form (eq. (3), no traction) with
 // symmetric elimination of homogeneous Dirichlet conditions, the load
 // vector, the overlapping box subdomains (Sec. 3) with their sets, the
@@ -420,6 +421,15 @@ int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err) {
     return GENEO_ERR_ARG;
   }
   g->pou = grid->pou;
+  if (grid->element != GENEO_ELEM_Q1 && grid->element != GENEO_ELEM_S20) {
+    *err = "unknown element";
+    return GENEO_ERR_ARG;
+  }
+  g->element = grid->element;
+  if (g->element == GENEO_ELEM_S20 && (g->dim != 3 || g->ncomp != 3 || g->pou != GENEO_POU_CONSTANT)) {
+    *err = "serendipity bricks: 3D elasticity with the piecewise-constant partition of unity";
+    return GENEO_ERR_ARG;
+  }
   g->nsub = 1;
   double vol = 1.0;
   for (int ax = 0; ax < 3; ++ax) {
@@ -481,10 +491,15 @@ int q1_make_geom(const geneo_grid_t* grid, Q1Geom* g, std::string* err) {
       }
       g->kref[a][b] = s / (g->dim == 2 ? 6.0 : 36.0);
     }
+  if (g->element == GENEO_ELEM_S20) s20_tables(g);
   return GENEO_OK;
 }
 
 void q1_sizes(const Q1Geom& g, geneo_q1_sizes_t* s) {
+  if (g.element == GENEO_ELEM_S20) {
+    s20_sizes(g, s);
+    return;
+  }
   int64_t nodes = 1, nzn = 1;
   for (int ax = 0; ax < 3; ++ax) {
     nodes *= g.nn[ax];
@@ -516,6 +531,9 @@ hipError_t q1_launch_all(const Q1Geom* dgeom, const Q1Geom& g, const geneo_q1_si
                          double* b, int* sub_ptr, int* sub_idx, uint8_t* flags, double* pou,
                          int* loc_rowptr, int* loc_col, double* an, double* ao,
                          int64_t* nzoff, hipStream_t st) {
+  if (g.element == GENEO_ELEM_S20)
+    return s20_launch_all(dgeom, g, s, coeff, A_rowptr, A_col, A_val, b, sub_ptr, sub_idx, flags,
+                          pou, loc_rowptr, loc_col, an, ao, st);
   int64_t nrows = s.ndof;
   int bs = 256;
   hipLaunchKernelGGL(k_q1_global, dim3((unsigned)((nrows + bs - 1) / bs)), dim3(bs), 0, st,

@@ -18,6 +18,8 @@ GENEO_PREC_FP64 = 0
 GENEO_PREC_MIXED = 1
 GENEO_POU_CONSTANT = 0
 GENEO_POU_SARKIS = 1
+GENEO_ELEM_Q1 = 0
+GENEO_ELEM_S20 = 1
 
 GENEO_ERR_ARG = 1
 GENEO_ERR_OOM = 2
@@ -44,7 +46,8 @@ class GeneoError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int), ("ncomp", C.c_int), ("ne", C.c_int * 3),
                 ("h", C.c_double * 3), ("parts", C.c_int * 3), ("ovl", C.c_int),
-                ("dirichlet", C.c_int), ("load", C.c_double * 3), ("pou", C.c_int)]
+                ("dirichlet", C.c_int), ("load", C.c_double * 3), ("pou", C.c_int),
+                ("element", C.c_int)]
 
 
 class Q1Sizes(C.Structure):
@@ -165,6 +168,7 @@ def grid_from_problem(prob):
     for c in range(prob.ncomp):
         g.load[c] = prob.load[c]
     g.pou = GENEO_POU_SARKIS if getattr(prob, "pou", "constant") == "sarkis" else GENEO_POU_CONSTANT
+    g.element = GENEO_ELEM_S20 if getattr(prob, "element", "q1") == "s20" else GENEO_ELEM_Q1
     return g
 
 

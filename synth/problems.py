@@ -201,13 +201,13 @@ def laminate_3d(seed=0, ne=(128, 32, 24), parts=(16, 4, 4), ovl=1,
     return p
 
 
-def laminate_s20(ne=(32, 8, 6), parts=(4, 2, 1), ovl=1, nev=16, precision="mixed"):
+def laminate_s20(seed=0, ne=(32, 8, 6), parts=(4, 2, 1), ovl=1, nev=16, precision="mixed"):
     """The clamped laminate of :func:`laminate_3d` on 20-node serendipity
     bricks (the element of the paper's composite experiments, Sec. 5.3):
     the same materials, clamp and load; one-element plies alternating 0 and
     90 degrees, each followed by a one-element resin layer; unit elements.
     The default, 32 x 8 x 6 bricks, has 23,175 dofs, near the 30,000 of the
-    paper's composite plate."""
+    paper's composite plate.  ``seed`` is unused (the stack is fixed)."""
     ply = F.ply_stiffness(160.0, 10.0, 10.0, 5.0, 5.0, 5.0, 0.3, 0.3, 0.3)
     mats = [ply, F.isotropic_stiffness(4.0, 0.35), F.rotate_z90(ply)]
     nx, ny, nz = ne
@@ -215,10 +215,12 @@ def laminate_s20(ne=(32, 8, 6), parts=(4, 2, 1), ovl=1, nev=16, precision="mixed
     for iz in range(nz):
         # ply 0, resin, ply 90, resin, ply 0, ...
         C[iz] = mats[0] if iz % 4 == 0 else mats[2] if iz % 4 == 2 else mats[1]
-    return elasticity_problem("laminate_s20_%dx%dx%d" % tuple(ne), C, ne, parts, ovl,
-                              dirichlet=0b000001, load=(0.0, 0.0, -1.0),
-                              h=(1.0, 1.0, 1.0), nev=nev, precision=precision,
-                              element="s20")
+    p = elasticity_problem("laminate_s20_%dx%dx%d" % tuple(ne), C, ne, parts, ovl,
+                           dirichlet=0b000001, load=(0.0, 0.0, -1.0),
+                           h=(1.0, 1.0, 1.0), nev=nev, precision=precision,
+                           element="s20")
+    p.meta["seed"] = seed
+    return p
 
 
 def layered_2d(n=40, parts=4, ovl=2, layers=8, contrast=1e6, nev=4,
@@ -244,4 +246,5 @@ CONFIGS = {
     "grf_512": grf_2d,
     "layers_96": layers_3d,
     "laminate_128x32x24": laminate_3d,
+    "laminate_s20_32x8x6": laminate_s20,
 }

@@ -83,6 +83,7 @@ SMALL_PROBLEMS = {
         "d3", np.exp(np.random.Generator(np.random.PCG64(4)).normal(size=(7, 9, 10))),
         (2, 2, 3), 1, nev=6),
     "laminate_small": lambda: synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1), nev=8),
+    "laminate_s20": lambda: synth.laminate_s20(ne=(8, 4, 3), parts=(2, 2, 1), nev=8),
     "layered_neumann_sides": lambda: synth.layered_2d(n=40, parts=4, ovl=2, layers=8,
                                                       contrast=1e6, nev=4),
     # threshold rule with nev_max = 16: eigen block of 32 columns, the block

@@ -51,6 +51,8 @@ def test_default_opts():
     lambda: synth.channels_2d(0, n=30, parts=3, n_channels=3, ovl=1),
     lambda: synth.darcy_problem("t", np.ones((7, 9, 10)), (2, 2, 3), 1),
     lambda: synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1)),
+    lambda: synth.laminate_s20(ne=(6, 4, 3), parts=(3, 2, 1)),
+    lambda: synth.laminate_s20(ne=(5, 3, 4), parts=(2, 1, 2), ovl=2),
 ])
 def test_q1_sizes_match_oracle(make):
     from paper_1906_10944_amd import geneo as G
@@ -63,6 +65,8 @@ def test_q1_sizes_match_oracle(make):
     assert s["nsub"] == len(subs)
     assert s["nloc"] == sum(len(x.dofs) for x in subs)
     assert s["nmax"] == max(len(x.dofs) for x in subs)
+    # the batched local pattern: the couplings within each N_j
+    assert s["nnz_loc"] == sum(A[x.dofs][:, x.dofs].nnz for x in subs)
 
 
 def test_q1_sizes_rejects_bad_grids():
@@ -75,6 +79,11 @@ def test_q1_sizes_rejects_bad_grids():
     assert e.value.code == 1
     g = G.grid_from_problem(p)
     g.parts[0] = 100
+    with pytest.raises(G.GeneoError):
+        G.geneo_q1_sizes(g)
+    # serendipity bricks are 3D elasticity only
+    g = G.grid_from_problem(p)
+    g.element = G.GENEO_ELEM_S20
     with pytest.raises(G.GeneoError):
         G.geneo_q1_sizes(g)
 
