@@ -11,8 +11,9 @@ grid (912,673 dofs), 8^3 subdomains of 12^3 elements with one-element
 overlap, z-layers of random thickness 2-6 alternating k = 1 and
 k = 10^U(4,6), 12 eigenvectors per subdomain, FP32 local factors with FP64
 eigen, coarse and PCG.  The same JSON line also carries, as nested objects,
-the FP64 form of the same workload, the 512^2 Darcy workload and the
-serving stream's p50/p99 latency.
+the FP64 form of the same workload, the 512^2 Darcy workload, the
+serendipity laminate (20-node bricks, 23,175 dofs) and the serving
+stream's p50/p99 latency.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
 GPU.
@@ -30,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+# workloads reported as nested objects of the headline line
+NESTED = ("grf_512", "laminate_s20_32x8x6")
 
 
 def parse():
@@ -44,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-nested", action="store_true",
-                    help="skip the nested 512^2 workload and serving objects")
+                    help="skip the nested workloads and the serving object")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
                     help="further setup option (geneo_opts_t field, integer or float)")
@@ -507,10 +510,10 @@ def main():
     head.pop("steps")
     head.pop("warmup")
     out.update(head)
-    if not args.no_nested and args.config != "grf_512":
-        p2 = make_problem("grf_512", args.seed)
-        line = workload_line(p2, args, max(1, min(args.steps, 10)), 2, False)
-        out["grf_512"] = line
+    for name in ([] if args.no_nested else NESTED):
+        if name != args.config:
+            p2 = make_problem(name, args.seed)
+            out[name] = workload_line(p2, args, max(1, min(args.steps, 10)), 2, False)
     if not args.no_cpu_baseline:
         log("oracle baseline on a sample of %s" % prob.name)
         out["cpu_baseline"] = cpu_baseline(prob, out["iters"], args.cpu_budget_s)

@@ -41,10 +41,12 @@ U64 = np.finfo(float).eps / 2
 
 # (boundary subdomain, floating interior subdomain)
 SAMPLES = {"layers_96": (0, 3 + 8 * (3 + 8 * 3)),              # corner; (3, 3, 3)
-           "laminate_128x32x24": (0, 7 + 16 * (1 + 4 * 1))}  # clamped end; (7, 1, 1)
+           "laminate_128x32x24": (0, 7 + 16 * (1 + 4 * 1)),  # clamped end; (7, 1, 1)
+           "laminate_s20_32x8x6": (0, 2 + 4 * 1)}             # clamped end; (2, 1, 0)
 
 
-@pytest.fixture(scope="module", params=["layers_96", "laminate_128x32x24"])
+@pytest.fixture(scope="module", params=["layers_96", "laminate_128x32x24",
+                                        "laminate_s20_32x8x6"])
 def big(request):
     need_gpu()
     prob = synth.CONFIGS[request.param](seed=0)
