@@ -252,6 +252,14 @@ typedef struct {
                          (left of the first entry of each row: zero in the
                          Cholesky factor, as no fill reaches them); 0 =
                          dense.  Both give bitwise the same result. */
+  int shifted_steps;  /* the shifted factorisations A_N,j - sigma B_j by
+                         tile-column steps, each step one launch over all
+                         subdomains with a workgroup per trailing tile (for
+                         few large subdomains, where one workgroup per
+                         matrix would leave most compute units idle):
+                         1 = always, -1 = never (one workgroup per matrix),
+                         0 = when there are at most 32 subdomains.  The
+                         two differ in rounding order only. */
   const double* tau_sub; /* host [nsub], or NULL: per-subdomain thresholds
                          tau_j > 0 replacing tau (take the eigenvalues
                          < tau_j, at most nev_max of them), e.g. the
@@ -263,7 +271,7 @@ typedef struct {
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-8, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
  * symv_tiles 0, refine 0, refine_rtol 1e-6, eig_solve 0, eig_split 0,
- * envelope 1, tau_sub NULL. */
+ * envelope 1, shifted_steps 0, tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;

@@ -1115,10 +1115,25 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
     X.envN_tiles.assign(nsub, 0.0);
     for (int j = 0; j < nsub; ++j) X.envN_tiles[j] = packed(LN.nt[j]);
   }
+  // few subdomains: tile-column steps over many workgroups (the rows each
+  // step reaches come from the envelopes, read back here)
+  const bool steps = o.shifted_steps > 0 || (o.shifted_steps == 0 && nsub <= kStepCholMax);
+  std::vector<int> rlast;
+  if (steps && X.uNR) {
+    const std::vector<int> R = download(X.envNR.p, LN.ndiag, sb);
+    rlast.assign(LN.maxnt, 0);
+    for (int j = 0; j < nsub; ++j)
+      for (int k = 0; k < LN.nt[j]; ++k) rlast[k] = std::max(rlast[k], R[LN.doff[j] + k]);
+  }
   {
     ProfScope ps("chol_shifted_f64", sb, 2.0 * 8.0 * TSQ * tlN, flN);
-    HIPCHK(launch_chol_batched(CholRole::ShiftedF64, X.G.p, X.toffN.p, X.ntN.p, X.DG.p, X.doffN.p, X.status2.p,
-                               X.jobsN.p, nsub, 0.0, X.uNE, X.uNR, sb));
+    if (steps)
+      HIPCHK(launch_chol_steps(X.G.p, X.DG.p, X.toffN.p, X.doffN.p, X.ntN.p, X.jobsN.p, nsub,
+                               LN.maxnt, X.status2.p, sb, nullptr, X.uNR,
+                               X.uNR ? rlast.data() : nullptr));
+    else
+      HIPCHK(launch_chol_batched(CholRole::ShiftedF64, X.G.p, X.toffN.p, X.ntN.p, X.DG.p,
+                                 X.doffN.p, X.status2.p, X.jobsN.p, nsub, 0.0, X.uNE, X.uNR, sb));
     X.pin_st2 = t_arena.active ? (int*)t_arena.take((size_t)nsub * sizeof(int)) : nullptr;
     if (X.pin_st2)
       HIPCHK(hipMemcpyAsync(X.pin_st2, X.status2.p, (size_t)nsub * sizeof(int),
@@ -2103,6 +2118,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->eig_solve = 0;
   o->eig_split = 0;
   o->envelope = 1;
+  o->shifted_steps = 0;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -2190,6 +2206,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "eig_solve must be 0 .. " + std::to_string(trsm_variants()));
     if (o.eig_split < -1) fail(GENEO_ERR_ARG, "eig_split must be -1, 0 or positive");
     if (o.envelope != 0 && o.envelope != 1) fail(GENEO_ERR_ARG, "envelope must be 0 or 1");
+    if (o.shifted_steps < -1 || o.shifted_steps > 1)
+      fail(GENEO_ERR_ARG, "shifted_steps must be -1, 0 or 1");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     settle_thread();  // the setup's scratch blocks become reusable

@@ -76,7 +76,8 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("coarse", C.c_int), ("eig_stall", C.c_int),
                 ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int),
                 ("refine", C.c_int), ("refine_rtol", C.c_double), ("eig_solve", C.c_int),
-                ("eig_split", C.c_int), ("envelope", C.c_int), ("tau_sub", C.c_void_p)]
+                ("eig_split", C.c_int), ("envelope", C.c_int), ("shifted_steps", C.c_int),
+                ("tau_sub", C.c_void_p)]
 
 
 class SetupInfo(C.Structure):

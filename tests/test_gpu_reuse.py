@@ -149,9 +149,10 @@ def test_envelope_gives_the_same_operator_as_dense(case):
     matrix's envelope (zero in the factors: no fill-in reaches them).  The
     products skipped are exact zeros, so the operator equals the dense
     computation's bit for bit: sweeps, eigenvalues, coarse basis and
-    matrix, apply and PCG solution.  The FP64 case has more than 32
-    subdomains, so its local factors take the batched kernel (fewer take the
-    tile-column steps, as does the coarse matrix)."""
+    matrix, apply and PCG solution.  The 2D case has more than 32
+    subdomains, so its factorisations take the batched kernels (with fewer,
+    the shifted ones and the FP64 refactors take the tile-column steps, as
+    does the coarse matrix)."""
     need_gpu()
     from paper_1906_10944_amd import geneo as G
     prob, prec = {
@@ -177,3 +178,33 @@ def test_envelope_gives_the_same_operator_as_dense(case):
     assert outs[0][:2] == outs[1][:2]
     for a, b in zip(outs[0][2:], outs[1][2:]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["layers3d_mixed", "laminate_s20"])
+def test_shifted_steps_match_the_batched_factorisation(case):
+    """The shifted factorisations by tile-column steps (one launch per step
+    over all subdomains) and by one workgroup per matrix differ in rounding
+    order only: the same eigenvector counts, eigenvalues within 1e-8
+    relative, PCG iterations within one and solutions within 1e-8."""
+    need_gpu()
+    from paper_1906_10944_amd import geneo as G
+    prob = {
+        "layers3d_mixed": lambda: synth.layers_3d(seed=4, n=24, parts=2, ovl=1, nev=6),
+        "laminate_s20": lambda: synth.laminate_s20(ne=(8, 4, 3), parts=(2, 2, 1), nev=8),
+    }[case]()
+    sysm = gpu_assemble(prob)
+    outs = []
+    for steps in (-1, 1):
+        h = gpu_setup(sysm, prob, precision=1, shifted_steps=steps)
+        m, lam = G.geneo_get_eigenvalues(h, prob.nsub)
+        x, inf = gpu_pcg(h, sysm)
+        outs.append((m, lam, inf["iters"], x))
+        say("[shifted steps]", case, steps, "nc", int(m.sum()), "iters", inf["iters"])
+        h.close()
+    (m0, l0, i0, x0), (m1, l1, i1, x1) = outs
+    assert np.array_equal(m0, m1)
+    for j in range(prob.nsub):
+        k = int(m0[j])
+        assert np.allclose(l0[j, :k], l1[j, :k], rtol=1e-8, atol=1e-12), j
+    assert abs(i0 - i1) <= 1
+    assert np.linalg.norm(x0 - x1) <= 1e-8 * np.linalg.norm(x0)
