@@ -125,6 +125,7 @@ class Runner:
                "eig_stalled": sinfo["eig_stalled"], "eig_max_resid": sinfo["eig_max_resid"],
                "symv_tiles": sinfo["symv_tiles"], "eig_block": sinfo["eig_block"],
                "eig_solve": sinfo["eig_solve"], "eig_split": sinfo["eig_split"],
+               "local_solve": sinfo["local_solve"],
                "t_phase_ms": sinfo["t_phase_ms"]}
         self.last = (sysm, h, x)
         return out
@@ -201,7 +202,8 @@ def prof_query(G, name):
 PROF_KERNELS = ["densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
                 "trtri_dirichlet", "densify_shifted", "chol_shifted_f64", "trsm_bwd",
                 "trsm_fwd", "trsm_bwd_split", "trsm_fwd_split", "bapply", "rayleigh_ritz",
-                "orth", "coarse_chol", "lauum_dirichlet", "symv", "symv_cols", "cheb_combine"]
+                "orth", "coarse_chol", "lauum_dirichlet", "local_solve", "symv", "symv_cols",
+                "cheb_combine"]
 
 
 def kernel_profile(runner, precision):
@@ -228,10 +230,11 @@ def kernel_profile(runner, precision):
 # kernel symbol of each event-timed launch site (as rocprofv3 names it)
 PROF_SYMBOL = {"densify_dirichlet": "k_densify_dirichlet", "chol_dirichlet_f32": "k_potrf_local_f32",
                "chol_dirichlet_f64": "k_potrf_local_f64", "trtri_dirichlet": "k_trtri_win<float, 2>",
+               "lauum_dirichlet": "k_lauum<float>",
                "densify_shifted": "k_densify_shifted", "chol_shifted_f64": "k_potrf_shifted_f64",
                "bapply": "k_bapply", "rayleigh_ritz": "rayleigh-ritz kernels",
                "orth": "orthonormalisation kernels", "cheb_combine": "k_cheb",
-               "coarse_chol": "tile-column step kernels", "lauum_dirichlet": "k_lauum<float>",
+               "coarse_chol": "tile-column step kernels", "local_solve": "k_local_solve_f32",
                "symv": "k_symv_rows", "symv_cols": "k_symv_cols"}
 COMPUTE_BOUND = ("chol_dirichlet_f32", "chol_dirichlet_f64", "chol_shifted_f64", "trtri_dirichlet",
                  "lauum_dirichlet", "coarse_chol")
@@ -259,10 +262,14 @@ def prof_symbol(name, info):
         return "16-column k_trsm_win / k_trsm_w1 <1, %s, ..., %d>" % (bwd, b)
     if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
         return "tile-column step kernels"
+    if name == "chol_shifted_f64" and info.get("nsub", 0) <= 32:
+        return "tile-column step kernels"
+    if name == "local_solve" and info.get("fallback_fp64", 0) >= info.get("nsub", 1):
+        return "k_local_solve_f64"
     return PROF_SYMBOL.get(name, name)
 
 
-APPLY_KERNELS = ("symv", "symv_cols")
+APPLY_KERNELS = ("local_solve", "symv", "symv_cols")
 
 
 def measured_traffic(symbol, workload):
@@ -455,6 +462,7 @@ def workload_line(prob, args, steps, warmup, full):
         "eig_max_resid": last["eig_max_resid"], "eig_block": last["eig_block"],
         "symv_tiles": last["symv_tiles"], "eig_solve": last["eig_solve"],
         "eig_split": last["eig_split"], "fallback_fp64": last["fallback_fp64"],
+        "local_solve": {1: "triangular", 2: "inverse"}.get(last["local_solve"], "?"),
         "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
         "setup_phase_ms": last["t_phase_ms"][:6],
     }

@@ -195,6 +195,10 @@ typedef struct {
 } geneo_csr_batch_t;
 
 enum { GENEO_PREC_FP64 = 0, GENEO_PREC_MIXED = 1 };
+/* Forms of the local solves A_j^{-1} r_j of the apply (Def. 2), option
+ * local_solve: forward and backward substitution with the banded Cholesky
+ * factor, or one product with the symmetric inverse formed in the setup. */
+enum { GENEO_LOCAL_AUTO = 0, GENEO_LOCAL_TRIANGULAR = 1, GENEO_LOCAL_INVERSE = 2 };
 
 typedef struct {
   int nev;            /* eigenvectors per subdomain when tau <= 0 */
@@ -260,6 +264,18 @@ typedef struct {
                          1 = always, -1 = never (one workgroup per matrix),
                          0 = when there are at most 32 subdomains.  The
                          two differ in rounding order only. */
+  int local_solve;    /* form of the apply's local solves:
+                         GENEO_LOCAL_TRIANGULAR (two substitutions with the
+                         Cholesky factor, inside its envelope: two reads of
+                         the band per apply, row-by-row latency),
+                         GENEO_LOCAL_INVERSE (one fully parallel product
+                         with A_j^{-1} = L^{-T} L^{-1}, formed in the setup:
+                         one read of the dense packed inverse), or
+                         GENEO_LOCAL_AUTO (0): the one with the smaller
+                         estimated time per iteration for the problem's
+                         sizes (large banded 3D subdomains: triangular;
+                         small or few subdomains: inverse).  The two agree
+                         up to rounding. */
   const double* tau_sub; /* host [nsub], or NULL: per-subdomain thresholds
                          tau_j > 0 replacing tau (take the eigenvalues
                          < tau_j, at most nev_max of them), e.g. the
@@ -271,7 +287,7 @@ typedef struct {
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-8, eig_maxit 300,
  * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
  * symv_tiles 0, refine 0, refine_rtol 1e-6, eig_solve 0, eig_split 0,
- * envelope 1, shifted_steps 0, tau_sub NULL. */
+ * envelope 1, shifted_steps 0, local_solve 0, tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);
 
 typedef struct geneo_handle_s* geneo_handle_t;
@@ -325,7 +341,10 @@ typedef struct {
   double t_phase_ms[8];   /* 0 index lists, 1 local factors, 2 shifted
                              factors, 3 eigen sweeps, 4 basis + Galerkin,
                              5 coarse factor, 6-7 reserved */
-  int64_t bytes_local_factors;  /* bytes of the inverse local factors */
+  int64_t bytes_local_factors;  /* bytes of what the apply keeps for the
+                                   local solves: the Cholesky factors with
+                                   their inverted diagonal tiles, or the
+                                   symmetric inverses */
   int eig_stalled;        /* subdomains stopped at their rounding floor */
   int symv_tiles;         /* tiles per wavefront of the local products */
   int eig_solve;          /* triangular-solve kernel of the eigen sweeps'
@@ -333,6 +352,8 @@ typedef struct {
   int eig_split;          /* the sweeps' solves are split into 16-column
                              blocks while at most this many subdomains are
                              active (0 = never) */
+  int local_solve;        /* GENEO_LOCAL_TRIANGULAR or GENEO_LOCAL_INVERSE:
+                             the form the apply uses */
 } geneo_setup_info_t;
 
 int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);
@@ -342,10 +363,10 @@ int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);
  * row filled with the further computed Ritz values or +inf). */
 int geneo_get_eigenvalues(geneo_handle_t h, int* m, double* lam, int ldl);
 
-/* Host copy of the precision of each local inverse A_j^{-1} (Sec. 3):
- * fp64 [nsub] receives 1 where it is kept in FP64 (FP64 mode, or in mixed
- * mode a subdomain whose FP32 factor failed the pivot test) and 0 where it
- * is FP32. */
+/* Host copy of the precision of each local solve with A_j (Sec. 3): fp64
+ * [nsub] receives 1 where the Cholesky factor of A_j is kept in FP64 (FP64
+ * mode, or in mixed mode a subdomain whose FP32 factor failed the pivot
+ * test) and 0 where it is FP32. */
 int geneo_get_local_precision(geneo_handle_t h, int* fp64);
 
 /* Host copies of the coarse basis (Def. 4) as dense columns over N_j:
@@ -427,11 +448,11 @@ int geneo_spmv(const geneo_csr_t* A, const double* x, double* y, void* stream);
  * geneo_prof_query sums the records of one kernel name (host pointers):
  * total_ms (event time), launches, bytes and flops (either may be NULL).
  * Names: "densify_dirichlet", "chol_dirichlet_f32", "chol_dirichlet_f64",
- * "trtri_dirichlet", "lauum_dirichlet", "densify_shifted",
- * "chol_shifted_f64", "trsm_bwd", "trsm_fwd", "trsm_bwd_split",
- * "trsm_fwd_split" (the eigen solves on 16-column blocks), "bapply",
- * "rayleigh_ritz", "cheb_combine", "orth", "coarse_chol", "symv",
- * "symv_cols".  While timing is
+ * "densify_shifted", "chol_shifted_f64", "trsm_bwd", "trsm_fwd",
+ * "trsm_bwd_split", "trsm_fwd_split" (the eigen solves on 16-column
+ * blocks), "bapply", "rayleigh_ritz", "cheb_combine", "orth",
+ * "coarse_chol", "local_solve" (the apply's local solves), "symv" and
+ * "symv_cols" (its coarse product).  While timing is
  * on, the eigen sweeps read their convergence flags after every sweep
  * (instead of one sweep late), so that the byte counts follow the active
  * set exactly.

@@ -382,7 +382,20 @@ struct geneo_handle_s {
   DBuf<int> sub_ptr, sub_idx, dmap, nd, ntD, voffD, dglob, didx, jobs32, jobs64;
   DBuf<int64_t> toffD, doffD, toff64, doff64;
   DBuf<double> dscale;
-  DBuf<float> S32, W32;  // symmetric inverses A_j^{-1} (FP32 subdomains), symv partials
+  // Cholesky factors of the scaled local Dirichlet matrices (packed tiles)
+  // with their inverted diagonal tiles and tile envelopes: FP32, and FP64
+  // for the subdomains in f64list (tiles at toff64 / doff64)
+  DBuf<float> L32, D32;
+  DBuf<double> L64, D64;
+  DBuf<int> envDE, envDR, env64E, env64R;
+  // the envelopes the factorisations and solves use (NULL: dense, option
+  // envelope = 0)
+  const int *uDE = nullptr, *uDR = nullptr, *u64E = nullptr, *u64R = nullptr;
+  // local solves of the apply: GENEO_LOCAL_TRIANGULAR (the factors above)
+  // or GENEO_LOCAL_INVERSE (symmetric inverses A_j^{-1} in S32 / S64, FP32
+  // / FP64 subdomains, with the partial sums of their products in W32 / W64)
+  int local_form = GENEO_LOCAL_TRIANGULAR;
+  DBuf<float> S32, W32;
   DBuf<double> S64, W64;
   int njobs32 = 0, njobs64 = 0;
   DBuf<int> optr;
@@ -393,9 +406,12 @@ struct geneo_handle_s {
   DBuf<int> m, zoff, coff, hnt;
   DBuf<double> tau_sub;  // per-subdomain thresholds (opts.tau_sub), else empty
   TrsmChoice trsm;  // kernels of the eigen sweeps' triangular solves
-  // apply job list of the symmetric products: (subdomain, 1 if its inverse
-  // is FP64) for every subdomain, then (nsub, 2) for the coarse inverse
+  // job list of the coarse symmetric product: (nsub, 2) for the coarse
+  // inverse when there is a coarse space
   DBuf<int2> ajobs;
+  // subdomains of the triangular local solves with FP32 and FP64 factors
+  DBuf<int> lsj32, lsj64;
+  int nlsj32 = 0, nlsj64 = 0;
   DBuf<double> rz_part, rr_part;  // PCG partial sums: r.z per 256 rows, r.r per PCG block
   std::vector<int2> ljobs_host;
   int najobs = 0, amaxnt = 0;
@@ -405,7 +421,7 @@ struct geneo_handle_s {
   DBuf<int> cstart;        // first row chunk per tile row; row partials per job
   DBuf<double> Rpart;
   int nchunk = 0, ntasks = 0;
-  std::vector<int64_t> toff64_host;
+  std::vector<int64_t> toff64_host, doff64_host;
   DBuf<int64_t> htoff;
   DBuf<double> Z, SH, WH, rH, yH, AHdense;
   std::vector<int> m_host, nd_host, nN_host, sub_ptr_host;
@@ -425,7 +441,8 @@ struct geneo_handle_s {
   DBuf<PcgScalars> sc;
   DBuf<int> done;
   int lpr = 8;
-  double bytes_symv32 = 0.0, bytes_symv64 = 0.0, bytes_symvH = 0.0;  // algorithmic bytes per apply
+  // algorithmic bytes per apply: local solves (either form), coarse product
+  double bytes_local = 0.0, bytes_symvH = 0.0;
   std::vector<int> f64list;                         // subdomains with FP64 local factors
   geneo_setup_info_t info{};
   // pinned host words of the PCG loop: done flags of two chunks, scalars
@@ -456,7 +473,8 @@ void check_csr(const geneo_csr_t* A) {
     fail(GENEO_ERR_ARG, "invalid CSR matrix");
 }
 
-// Arguments of the symmetric products of the apply (rev: reverse walk).
+// Arguments of the symmetric products of the apply (rev: reverse walk):
+// the coarse inverse, and the local inverses in the inverse form.
 SymvArgs symv_args(const geneo_handle_s* h, bool rev) {
   SymvArgs sa;
   sa.S32 = h->S32.p;
@@ -483,6 +501,33 @@ SymvArgs symv_args(const geneo_handle_s* h, bool rev) {
   sa.nchunk = h->nchunk;
   sa.R = h->Rpart.p;
   return sa;
+}
+
+// Arguments of the local solves of the apply.
+LocalSolveArgs local_solve_args(const geneo_handle_s* h) {
+  LocalSolveArgs a;
+  a.L32 = h->L32.p;
+  a.D32 = h->D32.p;
+  a.L64 = h->L64.p;
+  a.D64 = h->D64.p;
+  a.toff32 = h->toffD.p;
+  a.doff32 = h->doffD.p;
+  a.toff64 = h->toff64.p;
+  a.doff64 = h->doff64.p;
+  a.E32 = h->uDE;
+  a.R32 = h->uDR;
+  a.E64 = h->u64E;
+  a.R64 = h->u64R;
+  a.nt = h->ntD.p;
+  a.voff = h->voffD.p;
+  a.jobs32 = h->lsj32.p;
+  a.njobs32 = h->nlsj32;
+  a.jobs64 = h->lsj64.p;
+  a.njobs64 = h->nlsj64;
+  a.maxnt = h->LD.maxnt;
+  a.x = h->xl.p;
+  a.y = h->yl.p;
+  return a;
 }
 
 // Device work of one PCG solve: the vectors r, z, the two alternating p
@@ -517,14 +562,22 @@ hipError_t apply_enqueue(geneo_handle_s* h, const double* r, double* z, const in
                              h->coff.p, h->nsub, h->rH.p, done, st)))
       return e;
   }
-  const SymvArgs sa = symv_args(h, rev);
-  {
-    ProfScope ps("symv", st, h->bytes_symv32 + h->bytes_symv64 + h->bytes_symvH, 0.0);
-    if ((e = symv_rows(sa, done, st))) return e;
+  if (h->local_form == GENEO_LOCAL_TRIANGULAR) {
+    ProfScope ps("local_solve", st, h->bytes_local, 0.0);
+    if ((e = local_solve(local_solve_args(h), done, st))) return e;
   }
-  {
-    ProfScope ps("symv_cols", st, 0.0, 0.0);
-    if ((e = symv_cols(sa, done, st))) return e;
+  if (h->najobs > 0) {
+    const SymvArgs sa = symv_args(h, rev);
+    {
+      ProfScope ps("symv", st,
+                   h->bytes_symvH + (h->local_form == GENEO_LOCAL_INVERSE ? h->bytes_local : 0.0),
+                   0.0);
+      if ((e = symv_rows(sa, done, st))) return e;
+    }
+    {
+      ProfScope ps("symv_cols", st, 0.0, 0.0);
+      if ((e = symv_cols(sa, done, st))) return e;
+    }
   }
   return combine(r, h->optr.p, h->oent.p, h->dscale.p, h->yl.p, h->Z.p, h->yH.p, h->n, h->nc > 0,
                  z, done, h->rz_part.p, st);
@@ -599,19 +652,19 @@ __global__ void k_max_resid(const double* resid, const int* m, int nsub, int b, 
 struct SetupScratch {
   DBuf<int> status, status2, jobs, jobsN, ntN, voffN, active, pcnt, poff, npairs, woffd, cst;
   DBuf<int64_t> toffN, doffN, hdoff;
-  DBuf<float> L32, D32, XT32;
+  DBuf<float> XT32;
   DBuf<double> XT64, XTH;
   DBuf<int2> ljobs32, ljobs64, ljobsH;
-  DBuf<double> L64, D64, G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart,
+  DBuf<double> G, DG, U, P, W, T, Y, theta, resid, lam, mr, Wg, AHt, DH, eG, eM, epart,
       cpiv;
   DBuf<int> ebad, scount, sflag, hjob, bcnt, brp, bcol, orderN;
   // tile envelopes (first nonzero tile column per tile row, last nonzero
-  // tile row per tile column) of the shifted, FP32 and FP64 local matrices
-  DBuf<int> envNE, envNR, envDE, envDR, env64E, env64R, envHE, envHR;
-  // the envelopes the factorisations and solves use (NULL: dense, option
-  // envelope = 0)
-  const int *uNE = nullptr, *uNR = nullptr, *uDE = nullptr, *uDR = nullptr, *u64E = nullptr,
-            *u64R = nullptr;
+  // tile row per tile column) of the shifted matrices and the coarse matrix
+  // (those of the local Dirichlet factors are kept by the handle)
+  DBuf<int> envNE, envNR, envHE, envHR;
+  // the shifted envelopes the factorisation and the eigen solves use (NULL:
+  // dense, option envelope = 0)
+  const int *uNE = nullptr, *uNR = nullptr;
   std::vector<double> envN_tiles;  // stored tiles per shifted factor
   std::vector<int> envD_host;      // host copy of envDE (timing mode only)
   DBuf<double> bval;
@@ -776,8 +829,63 @@ std::vector<int2> lauum_job_list(const std::vector<int>& mats, const std::vector
   return lj;
 }
 
-// Local Dirichlet factors A_j = R_j A R_j^T and their inverses, on
-// stream st.  Returns after the work is enqueued and the pivot tests are
+// Algorithmic bytes of one local_solve launch: each factor's tiles inside
+// its envelope read twice (forward and backward), its inverted diagonal
+// tiles in place of the diagonal tiles of L, and its vectors read and
+// written once.  E32 / E64: host copies of the envelopes (empty: dense).
+double local_solve_bytes(const geneo_handle_s* h, const std::vector<int>& E32,
+                         const std::vector<int>& E64) {
+  std::vector<char> is64(h->nsub, 0);
+  for (int j : h->f64list) is64[j] = 1;
+  double bytes = 0.0;
+  for (int j = 0; j < h->nsub; ++j) {
+    const int nt = h->LD.nt[j];
+    const std::vector<int>& E = is64[j] ? E64 : E32;
+    const int64_t d0 = is64[j] ? (j < (int)h->doff64_host.size() ? h->doff64_host[j] : 0)
+                               : h->LD.doff[j];
+    double off = 0.0;
+    for (int i = 0; i < nt; ++i)
+      off += (size_t)(d0 + i) < E.size() ? i - E[d0 + i] : i;
+    bytes += 2.0 * (is64[j] ? 8.0 : 4.0) * TSQ * (off + nt) + 16.0 * nt * TS;
+  }
+  return bytes;
+}
+
+// Form of the local solves of the apply (option local_solve; 0 = by this
+// estimate of the time per PCG iteration, from measurements on MI355X):
+//  * triangular: forward and backward substitution tile row by tile row,
+//    all subdomains at once (two workgroups per CU), each row about 3 us
+//    of dependent latency: 2 nt_max rows per round of 2 * CUs subdomains;
+//  * inverse: one pass over the packed inverses at about 5 TB/s, plus the
+//    inverse factor and the symmetric product of the setup (2 n^3 / 3 flop
+//    per subdomain at about 80 TFLOP/s) spread over 50 iterations.
+// Small local problems or few subdomains favour the inverse (one fully
+// parallel pass), large banded 3D problems the substitution (two reads of
+// the envelope instead of one of the dense inverse, and no inverse to
+// form).  Both are exact up to rounding; matrices too large for the
+// substitution's LDS take the inverse.
+int choose_local_form(const geneo_handle_s* h) {
+  if (h->opts.local_solve == GENEO_LOCAL_TRIANGULAR || h->opts.local_solve == GENEO_LOCAL_INVERSE)
+    return h->opts.local_solve;
+  if (local_solve_check(h->LD.maxnt) != hipSuccess) return GENEO_LOCAL_INVERSE;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const double rounds = std::ceil(h->nsub / (2.0 * std::max(ncu, 1)));
+  const double t_tri = 2.0 * h->LD.maxnt * 3e-6 * rounds;
+  std::vector<char> is64(h->nsub, 0);
+  for (int j : h->f64list) is64[j] = 1;
+  double bytes = 0.0, flops = 0.0;
+  for (int j = 0; j < h->nsub; ++j) {
+    const double nn = h->nd_host[j];
+    bytes += (is64[j] ? 8.0 : 4.0) * packed(nn);
+    flops += 2.0 * nn * nn * nn / 3.0;
+  }
+  const double t_inv = bytes / 5e12 + flops / 80e12 / 50.0;
+  return t_tri <= t_inv ? GENEO_LOCAL_TRIANGULAR : GENEO_LOCAL_INVERSE;
+}
+
+// Local Dirichlet factors of A_j = R_j A R_j^T, on stream st.  Returns after the work is enqueued and the pivot tests are
 // read back.
 std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
                                              const geneo_csr_t* A, const geneo_subdomains_t* S,
@@ -792,35 +900,35 @@ std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
   X.status.alloc(nsub);
   if (mixed) {
     X.jobs.upload(largest_first(h->nd_host), st);
-    X.L32.alloc(h->LD.ntiles * TSQ);
-    X.D32.alloc(h->LD.ndiag * TSQ);
-    X.envDE.alloc(h->LD.ndiag);
-    X.envDR.alloc(h->LD.ndiag);
+    h->L32.alloc(h->LD.ntiles * TSQ);
+    h->D32.alloc(h->LD.ndiag * TSQ);
+    h->envDE.alloc(h->LD.ndiag);
+    h->envDR.alloc(h->LD.ndiag);
     {
       ProfScope ps("densify_dirichlet", st, 4.0 * h->LD.ntiles * TSQ, 0.0);
-      HIPCHK(hipMemsetAsync(X.L32.p, 0, X.L32.n * sizeof(float), st));
-      HIPCHK(launch_env_init(X.envDE.p, h->doffD.p, h->ntD.p, nullptr, nsub, st));
-      HIPCHK(launch_densify_dirichlet(true, X.L32.p, h->toffD.p, h->ntD.p, h->voffD.p, X.jobs.p,
+      HIPCHK(hipMemsetAsync(h->L32.p, 0, h->L32.n * sizeof(float), st));
+      HIPCHK(launch_env_init(h->envDE.p, h->doffD.p, h->ntD.p, nullptr, nsub, st));
+      HIPCHK(launch_densify_dirichlet(true, h->L32.p, h->toffD.p, h->ntD.p, h->voffD.p, X.jobs.p,
                                       nsub, S->sub_ptr, S->sub_idx, h->dmap.p, h->dglob.p,
                                       h->dscale.p, A,
                                       *std::max_element(h->LD.nt.begin(), h->LD.nt.end()),
-                                      X.envDE.p, h->doffD.p, st));
-      HIPCHK(launch_env_finish(X.envDE.p, X.envDR.p, h->doffD.p, h->ntD.p, nullptr, nsub, st));
-      if (o.envelope) X.uDE = X.envDE.p, X.uDR = X.envDR.p;
+                                      h->envDE.p, h->doffD.p, st));
+      HIPCHK(launch_env_finish(h->envDE.p, h->envDR.p, h->doffD.p, h->ntD.p, nullptr, nsub, st));
+      if (o.envelope) h->uDE = h->envDE.p, h->uDR = h->envDR.p;
     }
     {
       // algorithmic work inside the envelopes (read back in the timing mode
       // only, where it is reported)
       double tl = 0.0, fl = 0.0;
-      if (prof_on() && X.uDE) {
-        X.envD_host = download(X.envDE.p, h->LD.ndiag, st);
+      if (prof_on() && h->uDE) {
+        X.envD_host = download(h->envDE.p, h->LD.ndiag, st);
         const EnvWork ew = env_work(X.envD_host, h->LD.doff, h->LD.nt, all);
         for (double t : ew.tiles) tl += t;
         fl = 2.0 * TS * TS * TS * ew.prods + (double)TS * TS * TS * tl;
       }
       ProfScope ps("chol_dirichlet_f32", st, 2.0 * 4.0 * TSQ * tl, fl);
-      HIPCHK(launch_chol_batched(CholRole::LocalF32, X.L32.p, h->toffD.p, h->ntD.p, X.D32.p, h->doffD.p,
-                                 X.status.p, X.jobs.p, nsub, o.pivot_tol, X.uDE, X.uDR,
+      HIPCHK(launch_chol_batched(CholRole::LocalF32, h->L32.p, h->toffD.p, h->ntD.p, h->D32.p, h->doffD.p,
+                                 X.status.p, X.jobs.p, nsub, o.pivot_tol, h->uDE, h->uDR,
                                  st));
     }
     // the shifted factorisation follows the FP32 one on the device (an
@@ -839,12 +947,95 @@ std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
     f64list = all;
     after_fp32(nullptr);
   }
-  // The inverses of the FP32 factors, the FP64 refactors of the subdomains
-  // that failed the pivot test and their inverses go back to the caller as
-  // a step to enqueue later: nothing before the PCG needs them, and the
-  // eigen sweeps, once few subdomains are active, leave most CUs idle.
+  // The FP64 refactors of the subdomains that failed the pivot test (all
+  // subdomains in FP64 mode) and, in the inverse form of the local solves,
+  // the inverses go back to the caller as a step to enqueue later: nothing
+  // before the PCG needs them, and the eigen sweeps, once few subdomains
+  // are active, leave most CUs idle.
   return [h, &X, A, S, nsub, mixed, f64list = std::move(f64list),
           ok32 = std::move(inv32)](hipStream_t st) mutable {
+    h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
+    h->njobs64 = (int)f64list.size();
+    h->jobs64.upload(f64list, st);
+    std::vector<int64_t> toff64(nsub, 0), doff64(nsub, 0);
+    int64_t tt = 0, dd = 0;
+    for (int j : f64list) {
+      toff64[j] = tt;
+      doff64[j] = dd;
+      tt += tri_tiles(h->LD.nt[j]);
+      dd += h->LD.nt[j];
+    }
+    h->toff64.upload(toff64, st);
+    h->doff64.upload(doff64, st);
+    h->toff64_host = toff64;
+    h->doff64_host = doff64;
+    {
+      std::vector<int2> lj(nsub);
+      std::vector<char> f(nsub, 0);
+      for (int j : f64list) f[j] = 1;
+      for (int j = 0; j < nsub; ++j) lj[j] = make_int2(j, f[j]);
+      h->ljobs_host = lj;
+    }
+    if (!f64list.empty()) {
+      h->L64.alloc(tt * TSQ);
+      h->D64.alloc(dd * TSQ);
+      h->env64E.alloc(dd);
+      h->env64R.alloc(dd);
+      double pk64 = 0.0, fl64 = 0.0;
+      int mx = 0;
+      for (int j : f64list) {
+        mx = std::max(mx, h->LD.nt[j]);
+        pk64 += packed(h->nd_host[j]);
+        fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
+      }
+      {
+        ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
+        HIPCHK(hipMemsetAsync(h->L64.p, 0, h->L64.n * sizeof(double), st));
+        HIPCHK(launch_env_init(h->env64E.p, h->doff64.p, h->ntD.p, h->jobs64.p, h->njobs64, st));
+        HIPCHK(launch_densify_dirichlet(false, h->L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
+                                        h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
+                                        h->dmap.p, h->dglob.p, h->dscale.p, A, mx, h->env64E.p,
+                                        h->doff64.p, st));
+        HIPCHK(launch_env_finish(h->env64E.p, h->env64R.p, h->doff64.p, h->ntD.p, h->jobs64.p,
+                                 h->njobs64, st));
+        if (h->opts.envelope) h->u64E = h->env64E.p, h->u64R = h->env64R.p;
+      }
+      {
+        // a few refactors (mixed mode): tile-column steps over many short
+        // workgroups, which leave the CUs to the eigen sweeps in between
+        // (dense); a full batch (FP64 mode): one workgroup per matrix,
+        // inside the envelopes
+        const bool steps = h->njobs64 <= kStepCholMax;
+        if (!steps && prof_on() && h->u64E) {
+          const EnvWork ew = env_work(download(h->env64E.p, dd, st), doff64,
+                                      h->LD.nt, f64list);
+          pk64 = 0.0;
+          for (double t : ew.tiles) pk64 += TSQ * t;
+          fl64 = 2.0 * TS * TS * TS * ew.prods + (double)TS * pk64;
+        }
+        ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
+        if (steps) {
+          HIPCHK(launch_chol_steps(h->L64.p, h->D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
+                                   h->jobs64.p, h->njobs64, mx, X.status.p, st, nullptr,
+                                   h->u64R));
+        } else {
+          HIPCHK(launch_chol_batched(CholRole::LocalF64, h->L64.p, h->toff64.p, h->ntD.p, h->D64.p,
+                                     h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0,
+                                     h->u64E, h->u64R, st));
+        }
+      }
+    }
+    h->f64list = f64list;
+    h->local_form = choose_local_form(h);
+    if (h->local_form == GENEO_LOCAL_TRIANGULAR) {
+      h->bytes_local = local_solve_bytes(
+          h, X.envD_host,
+          prof_on() && h->u64E ? download(h->env64E.p, h->env64E.n, st) : std::vector<int>{});
+      h->info.bytes_local_factors = (int64_t)(h->L32.n + h->D32.n) * 4 +
+                                    (int64_t)(h->L64.n + h->D64.n) * 8;
+      return;
+    }
+    // inverse form: X_j = L_j^{-1}, then A_j^{-1} = X_j^T X_j
     if (!ok32.empty()) {
       std::vector<int2> tj = trtri_job_list(ok32, h->LD.nt, true);
       X.tjobs32.upload(tj, st);
@@ -863,8 +1054,8 @@ std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
         if (!X.envD_host.empty())
           flt = 2.0 * TS * TS * TS * env_work(X.envD_host, h->LD.doff, h->LD.nt, ok32).inv_prods;
         ProfScope ps("trtri_dirichlet", st, 2.0 * 4.0 * pk32, flt);
-        HIPCHK(launch_trtri(true, X.L32.p, X.D32.p, X.XT32.p, h->toffD.p, h->doffD.p, h->ntD.p,
-                            X.tjobs32.p, (int)tj.size(), X.uDE, st));
+        HIPCHK(launch_trtri(true, h->L32.p, h->D32.p, X.XT32.p, h->toffD.p, h->doffD.p, h->ntD.p,
+                            X.tjobs32.p, (int)tj.size(), h->uDE, st));
       }
       h->S32.alloc(h->LD.ntiles * TSQ);
       h->W32.alloc(h->LD.ntiles * TS);
@@ -872,74 +1063,13 @@ std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
       HIPCHK(launch_lauum(true, X.XT32.p, h->S32.p, h->toffD.p, h->ntD.p, X.ljobs32.p,
                           (int)lj.size(), st));
     }
-    h->info.fallback_fp64 = mixed ? (int)f64list.size() : 0;
-    h->njobs64 = (int)f64list.size();
-    h->jobs64.upload(f64list, st);
-    std::vector<int64_t> toff64(nsub, 0), doff64(nsub, 0);
-    int64_t tt = 0, dd = 0;
-    for (int j : f64list) {
-      toff64[j] = tt;
-      doff64[j] = dd;
-      tt += tri_tiles(h->LD.nt[j]);
-      dd += h->LD.nt[j];
-    }
-    h->toff64.upload(toff64, st);
-    h->doff64.upload(doff64, st);
-    h->toff64_host = toff64;
-    {
-      std::vector<int2> lj(nsub);
-      std::vector<char> f(nsub, 0);
-      for (int j : f64list) f[j] = 1;
-      for (int j = 0; j < nsub; ++j) lj[j] = make_int2(j, f[j]);
-      h->ljobs_host = lj;
-    }
     if (!f64list.empty()) {
-      X.L64.alloc(tt * TSQ);
-      X.D64.alloc(dd * TSQ);
-      X.env64E.alloc(dd);
-      X.env64R.alloc(dd);
+      int64_t tt = 0;
       double pk64 = 0.0, fl64 = 0.0;
-      int mx = 0;
       for (int j : f64list) {
-        mx = std::max(mx, h->LD.nt[j]);
+        tt += tri_tiles(h->LD.nt[j]);
         pk64 += packed(h->nd_host[j]);
         fl64 += std::pow((double)h->nd_host[j], 3) / 3.0;
-      }
-      {
-        ProfScope ps("densify_dirichlet", st, 8.0 * tt * TSQ, 0.0);
-        HIPCHK(hipMemsetAsync(X.L64.p, 0, X.L64.n * sizeof(double), st));
-        HIPCHK(launch_env_init(X.env64E.p, h->doff64.p, h->ntD.p, h->jobs64.p, h->njobs64, st));
-        HIPCHK(launch_densify_dirichlet(false, X.L64.p, h->toff64.p, h->ntD.p, h->voffD.p,
-                                        h->jobs64.p, h->njobs64, S->sub_ptr, S->sub_idx,
-                                        h->dmap.p, h->dglob.p, h->dscale.p, A, mx, X.env64E.p,
-                                        h->doff64.p, st));
-        HIPCHK(launch_env_finish(X.env64E.p, X.env64R.p, h->doff64.p, h->ntD.p, h->jobs64.p,
-                                 h->njobs64, st));
-        if (h->opts.envelope) X.u64E = X.env64E.p, X.u64R = X.env64R.p;
-      }
-      {
-        // a few refactors (mixed mode): tile-column steps over many short
-        // workgroups, which leave the CUs to the eigen sweeps in between
-        // (dense); a full batch (FP64 mode): one workgroup per matrix,
-        // inside the envelopes
-        const bool steps = h->njobs64 <= kStepCholMax;
-        if (!steps && prof_on() && X.u64E) {
-          const EnvWork ew = env_work(download(X.env64E.p, dd, st), doff64,
-                                      h->LD.nt, f64list);
-          pk64 = 0.0;
-          for (double t : ew.tiles) pk64 += TSQ * t;
-          fl64 = 2.0 * TS * TS * TS * ew.prods + (double)TS * pk64;
-        }
-        ProfScope ps("chol_dirichlet_f64", st, 2.0 * 8.0 * pk64, fl64);
-        if (steps) {
-          HIPCHK(launch_chol_steps(X.L64.p, X.D64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                                   h->jobs64.p, h->njobs64, mx, X.status.p, st, nullptr,
-                                   X.u64R));
-        } else {
-          HIPCHK(launch_chol_batched(CholRole::LocalF64, X.L64.p, h->toff64.p, h->ntD.p, X.D64.p,
-                                     h->doff64.p, X.status.p, h->jobs64.p, h->njobs64, 0.0,
-                                     X.u64E, X.u64R, st));
-        }
       }
       std::vector<int2> tj = trtri_job_list(f64list, h->LD.nt, false);
       X.tjobs64.upload(tj, st);
@@ -948,8 +1078,8 @@ std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
       X.XT64.alloc(tt * TSQ);
       {
         ProfScope ps("trtri_dirichlet", st, 2.0 * 8.0 * pk64, fl64);
-        HIPCHK(launch_trtri(false, X.L64.p, X.D64.p, X.XT64.p, h->toff64.p, h->doff64.p, h->ntD.p,
-                            X.tjobs64.p, (int)tj.size(), X.u64E, st));
+        HIPCHK(launch_trtri(false, h->L64.p, h->D64.p, X.XT64.p, h->toff64.p, h->doff64.p,
+                            h->ntD.p, X.tjobs64.p, (int)tj.size(), h->u64E, st));
       }
       h->S64.alloc(tt * TSQ);
       h->W64.alloc(tt * TS);
@@ -957,18 +1087,16 @@ std::function<void(hipStream_t)> setup_local(geneo_handle_s* h, SetupScratch& X,
       HIPCHK(launch_lauum(false, X.XT64.p, h->S64.p, h->toff64.p, h->ntD.p, X.ljobs64.p,
                           (int)lj.size(), st));
     }
-    double b32 = 0.0, b64 = 0.0;
+    double b = 0.0;
     std::vector<char> is64(nsub, 0);
     for (int j : f64list) is64[j] = 1;
     for (int j = 0; j < nsub; ++j) {
-      double nn = h->nd_host[j];
-      if (is64[j]) b64 += 8.0 * packed(nn) + 16.0 * nn;
-      else b32 += 4.0 * packed(nn) + 16.0 * nn;
+      const double nn = h->nd_host[j];
+      b += (is64[j] ? 8.0 : 4.0) * packed(nn) + 16.0 * nn;
     }
-    h->bytes_symv32 = b32;
-    h->bytes_symv64 = b64;
-    h->info.bytes_local_factors = (int64_t)(h->S32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->S64.n * 8;
-    h->f64list = f64list;
+    h->bytes_local = b;
+    h->info.bytes_local_factors =
+        (int64_t)(h->S32.p ? h->LD.ntiles * TSQ * 4 : 0) + (int64_t)h->S64.n * 8;
   };
 }
 
@@ -1636,11 +1764,24 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
   HIPCHK(owner_entries(h->olist.p, h->nloc, h->sub_ptr.p, h->dmap.p, h->voffD.p, h->zoff.p,
                        h->m.p, h->coff.p, h->oent.p, st));
   {
-    std::vector<int2> aj = h->ljobs_host;
+    {
+      std::vector<int> j32, j64;
+      for (const int2& jb : h->ljobs_host) (jb.y ? j64 : j32).push_back(jb.x);
+      h->nlsj32 = (int)j32.size();
+      h->nlsj64 = (int)j64.size();
+      h->lsj32.upload(j32, st);
+      h->lsj64.upload(j64, st);
+    }
+    if (h->local_form == GENEO_LOCAL_TRIANGULAR && local_solve_check(h->LD.maxnt) != hipSuccess)
+      fail(GENEO_ERR_ARG, "local Dirichlet matrices of " + std::to_string(h->LD.maxnt * TS) +
+                              " rows or more exceed the triangular local solves' LDS");
+    std::vector<int2> aj;
+    if (h->local_form == GENEO_LOCAL_INVERSE) aj = h->ljobs_host;
     if (h->nc > 0) aj.push_back(make_int2(nsub, 2));
     h->ajobs.upload(aj, st);
     h->najobs = (int)aj.size();
-    h->amaxnt = std::max(h->LD.maxnt, h->nc > 0 ? h->ntc : 0);
+    h->amaxnt = std::max(h->local_form == GENEO_LOCAL_INVERSE ? h->LD.maxnt : 1,
+                         h->nc > 0 ? h->ntc : 0);
     const int cw = symv_chunk_tiles();
     std::vector<int> cs(h->amaxnt + 1);
     for (int i = 0; i <= h->amaxnt; ++i) cs[i] = (int)symv_tasks_before(i, cw);
@@ -1689,11 +1830,19 @@ void setup_impl(geneo_handle_s* h, const geneo_csr_t* A, const geneo_subdomains_
                              both ? h->tasks_rev.p : nullptr, st));
     };
     int g = o.symv_tiles / cw;
-    if (g == 0) g = tune_symv_group(h, st, build);
+    if (g == 0) g = h->najobs > 0 ? tune_symv_group(h, st, build) : 1;
     build(g, true);
     h->info.symv_tiles = g * cw;
   }
   HIPCHK(hipStreamSynchronize(st));
+  if (h->local_form == GENEO_LOCAL_INVERSE) {
+    // the apply reads only the inverses
+    h->L32.release();
+    h->D32.release();
+    h->L64.release();
+    h->D64.release();
+  }
+  h->info.local_solve = h->local_form;
   h->info.t_phase_ms[0] = tm0.ms();
   h->info.t_phase_ms[1] = tmL.ms();
   if (coarse) {
@@ -2119,6 +2268,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->eig_split = 0;
   o->envelope = 1;
   o->shifted_steps = 0;
+  o->local_solve = 0;
 }
 
 int geneo_q1_sizes(const geneo_grid_t* grid, geneo_q1_sizes_t* sizes) {
@@ -2208,6 +2358,8 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
     if (o.envelope != 0 && o.envelope != 1) fail(GENEO_ERR_ARG, "envelope must be 0 or 1");
     if (o.shifted_steps < -1 || o.shifted_steps > 1)
       fail(GENEO_ERR_ARG, "shifted_steps must be -1, 0 or 1");
+    if (o.local_solve < 0 || o.local_solve > 2)
+      fail(GENEO_ERR_ARG, "local_solve must be 0, 1 or 2");
     setup_impl(h.get(), A, S, An, Ao, (hipStream_t)stream);
     *out = h.release();
     settle_thread();  // the setup's scratch blocks become reusable

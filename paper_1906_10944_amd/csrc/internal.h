@@ -100,6 +100,27 @@ hipError_t launch_chol_steps(double* tiles, double* dinv, const int64_t* toff,
 
 // ------------------------------------------------------------- solve.hip
 // `done` (device flag, may be NULL): skip the work once PCG has converged.
+// Local solves of the apply, y_j = L_j^{-T} L_j^{-1} x_j with the Cholesky
+// factor L_j of each subdomain's scaled Dirichlet matrix (packed tiles at
+// toff, inverted diagonal tiles at doff, tile envelopes E / R at doff or
+// NULL for dense): the subdomains jobs32[0 .. njobs32-1] with FP32
+// factors, then jobs64[0 .. njobs64-1] with FP64 ones (two launches).
+// Vectors at voff[j] (nt[j] * TS entries) in x and y.
+struct LocalSolveArgs {
+  const float *L32 = nullptr, *D32 = nullptr;
+  const double *L64 = nullptr, *D64 = nullptr;
+  const int64_t *toff32 = nullptr, *doff32 = nullptr, *toff64 = nullptr, *doff64 = nullptr;
+  const int *E32 = nullptr, *R32 = nullptr, *E64 = nullptr, *R64 = nullptr;
+  const int *nt = nullptr, *voff = nullptr;
+  const int *jobs32 = nullptr, *jobs64 = nullptr;
+  int njobs32 = 0, njobs64 = 0, maxnt = 0;
+  const double* x = nullptr;
+  double* y = nullptr;
+};
+hipError_t local_solve(const LocalSolveArgs& a, const int* done, hipStream_t st);
+// hipSuccess if matrices of maxnt tile rows fit the local solves' LDS (and
+// raises the kernel's LDS limit where they need more than the default)
+hipError_t local_solve_check(int maxnt);
 // y = S x for the symmetric inverses (packed lower tiles, diagonal tiles in
 // full) of all subdomains and the coarse matrix: symv_rows forms the
 // partial sums R and W, symv_cols then adds them into y (stream order).

@@ -1,13 +1,18 @@
-// Products with the packed symmetric inverses and triangular solves with the
-// packed tile factors.
+// Local solves, triangular solves with the packed tile factors, and products
+// with packed symmetric inverses.
 //
+//  * k_local_solve_f32 / _f64: the local Dirichlet solves of the apply in
+//    the triangular form, y = L^{-T} L^{-1} x with each subdomain's banded
+//    Cholesky factor (FP32 or FP64), one workgroup per subdomain, inside
+//    the factor's tile envelope.  Bound by two reads of the envelope and by
+//    the latency of the row-by-row substitution.
 //  * k_symv_rows / k_symv_cols: y = S x for the symmetric inverses S =
-//    A^{-1} of the local Dirichlet matrices and of the coarse matrix, all
-//    in one launch each.  The first reads every stored tile once (one
-//    wavefront per chunk of up to 8 tiles of a tile row) and leaves partial
-//    sums: its chunk's share of the row sums and the transposed products of
-//    the off-diagonal tiles; the second adds those in a fixed order.
-//    HBM-bound on the one read of S.
+//    A^{-1} of the local Dirichlet matrices (in the inverse form) and of
+//    the coarse matrix, all in one launch each.  The first reads every
+//    stored tile once (one wavefront per chunk of up to 8 tiles of a tile
+//    row) and leaves partial sums: its chunk's share of the row sums and
+//    the transposed products of the off-diagonal tiles; the second adds
+//    those in a fixed order.  HBM-bound on the one read of S.
 //  * k_trsm_win: X = G^{-1} R and X = G^{-T} R with b <= 32 right-hand sides
 //    for the shift-and-invert eigen sweeps (FP64, one workgroup per
 //    subdomain): windows of 16 tile rows held in registers, a left-looking
@@ -268,6 +273,263 @@ hipError_t symv_rows(const SymvArgs& a, const int* done, hipStream_t st) {
 hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st) {
   if (a.njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_symv_cols, dim3((a.maxnt + 7) / 8, a.njobs), dim3(256), 0, st, a, done);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ local solves ---
+// y = L^{-T} L^{-1} x for one subdomain's banded Cholesky factor, one
+// workgroup of LS_NW wavefronts per subdomain, all of its vector in LDS
+// (FP64).  Forward, tile row i: s_i = x_i - sum_{E(i) <= k < i} L_ik y_k,
+// y_i = Dinv_i s_i; backward, in place: t_i = y_i - sum_{i < k <= R(i)}
+// L_ki^T z_k, z_i = Dinv_i^T t_i.  The off-diagonal tiles of a row are
+// dealt to the wavefronts by their distance from the diagonal (wavefront w
+// takes distances w + 1, w + 1 + LS_NW, ...); each leaves its 32 partial
+// sums in LDS, and after one barrier every wavefront adds them in the same
+// fixed order and applies the inverted diagonal tile itself (the same
+// arithmetic everywhere, so the copies of y_i the wavefronts write to LDS
+// are equal, and each reads back only its own writes: one barrier per tile
+// row).  The factor tiles of row i + 1 (LS_MT per wavefront, with the
+// diagonal tile and x_{i+1}) are loaded while row i is completed.  Lane (r, h) takes entry r of the
+// row (backward: column) and half h of the 32 entries it is summed over,
+// FP32 tiles converted to FP64 as used.
+#define LS_NW 8
+#define LS_MT 1
+
+template <typename T> struct Frag16 { T v[16]; };
+// entries [r][16h .. 16h+15] of a tile
+template <typename T>
+__device__ __forceinline__ void frag_row(Frag16<T>& f, const T* t, int r, int h) {
+  const T* p = t + r * TS + 16 * h;
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float4 a = reinterpret_cast<const float4*>(p)[u];
+      f.v[4 * u] = a.x;
+      f.v[4 * u + 1] = a.y;
+      f.v[4 * u + 2] = a.z;
+      f.v[4 * u + 3] = a.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double2 a = reinterpret_cast<const double2*>(p)[u];
+      f.v[2 * u] = a.x;
+      f.v[2 * u + 1] = a.y;
+    }
+  }
+}
+// entries [16h .. 16h+15][c] of a tile
+template <typename T>
+__device__ __forceinline__ void frag_col(Frag16<T>& f, const T* t, int c, int h) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) f.v[q] = t[(16 * h + q) * TS + c];
+}
+// sum_q f_q v_q over 16 consecutive LDS entries, in order
+template <typename T>
+__device__ __forceinline__ double dot16(const Frag16<T>& f, const double* v) {
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double2 b = reinterpret_cast<const double2*>(v)[u];
+    s += (double)f.v[2 * u] * b.x;
+    s += (double)f.v[2 * u + 1] * b.y;
+  }
+  return s;
+}
+
+template <typename T>
+__device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ Dj,
+                                const int* __restrict__ Ej, const int* __restrict__ Rj, int nt,
+                                const double* __restrict__ xj, double* __restrict__ yj,
+                                double* ys, double (*part)[LS_NW][TS], double (*sv)[TS],
+                                int* sE, int* sR) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 31, h = lane >> 5;
+  // the envelope in LDS (dense: E = 0, R = nt - 1)
+  for (int e = threadIdx.x; e < nt; e += blockDim.x) {
+    sE[e] = Ej ? Ej[e] : 0;
+    sR[e] = Rj ? Rj[e] : nt - 1;
+  }
+  block_sync();
+  auto first = [&](int i) { return sE[i]; };
+  auto last = [&](int k) { return sR[k]; };
+  // row sum of entry r from the partials (fixed order), then this lane's
+  // 16 entries of the sums through the wavefront's own LDS row
+  auto gather = [&](double(*pp)[TS], double base, double (&o)[16]) {
+    double t = pp[0][r];
+#pragma unroll
+    for (int ww = 1; ww < LS_NW; ++ww) t += pp[ww][r];
+    if (lane < TS) sv[w][r] = base - t;
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double2 b = reinterpret_cast<const double2*>(sv[w] + 16 * h)[u];
+      o[2 * u] = b.x;
+      o[2 * u + 1] = b.y;
+    }
+  };
+  // The off-diagonal tiles of row i + 1 are loaded into the registers of
+  // row i's right after their last use, so they arrive during the barrier,
+  // the reduction and the diagonal product.  The diagonal tiles (and x)
+  // alternate between two sets, rows unrolled by two: no register holding
+  // a load in flight is ever copied (that would wait for the load).  Every
+  // prefetch is issued (row and tile indices clamped into the matrix, the
+  // products of tiles outside the envelope skipped where they are used), so
+  // the number of loads in flight is the same on every path and the waits
+  // for the older ones can be partial.
+  Frag16<T> a[LS_MT], d0, d1;
+  double x0 = 0.0, x1 = 0.0;
+  // ---- forward: ys = L^{-1} x
+  auto fetch_f = [&](Frag16<T>& fd, double& fx, int i) {
+    const int e = first(i);
+#pragma unroll
+    for (int m = 0; m < LS_MT; ++m)
+      frag_row(a[m], Lj + tile_idx(i, max(i - 1 - w - LS_NW * m, e)) * TSQ, r, h);
+    frag_row(fd, Dj + (int64_t)i * TSQ, r, h);
+    fx = xj[i * TS + r];
+  };
+  auto fwd_row = [&](int i, const Frag16<T>& cd, double cx, Frag16<T>& nd, double& nx) {
+    const int e = first(i);
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < LS_MT; ++m) {
+      const int k = i - 1 - w - LS_NW * m;
+      if (k >= e) s += dot16(a[m], ys + k * TS + 16 * h);
+    }
+    for (int k = i - 1 - w - LS_NW * LS_MT; k >= e; k -= LS_NW) {
+      Frag16<T> t;
+      frag_row(t, Lj + tile_idx(i, k) * TSQ, r, h);
+      s += dot16(t, ys + k * TS + 16 * h);
+    }
+    fetch_f(nd, nx, min(i + 1, nt - 1));
+    s += __shfl_xor(s, 32);
+    double(*pp)[TS] = part[i & 1];
+    if (lane < TS) pp[w][r] = s;
+    block_sync();
+    double sc[16];
+    gather(pp, cx, sc);
+    double y = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y += (double)cd.v[q] * sc[q];
+    y += __shfl_xor(y, 32);
+    if (lane < TS) ys[i * TS + r] = y;
+    wave_sync();
+  };
+  fetch_f(d0, x0, 0);
+  int i = 0;
+  for (; i + 1 < nt; i += 2) {
+    fwd_row(i, d0, x0, d1, x1);
+    fwd_row(i + 1, d1, x1, d0, x0);
+  }
+  if (i < nt) fwd_row(i, d0, x0, d1, x1);
+  // the last forward row's partials are read before the backward rows
+  // rewrite either buffer
+  block_sync();
+  // ---- backward, in place: ys = L^{-T} ys
+  auto fetch_b = [&](Frag16<T>& fd, int i) {
+    const int rl = last(i);
+#pragma unroll
+    for (int m = 0; m < LS_MT; ++m)
+      frag_col(a[m], Lj + tile_idx(min(i + 1 + w + LS_NW * m, rl), i) * TSQ, r, h);
+    frag_col(fd, Dj + (int64_t)i * TSQ, r, h);
+  };
+  auto bwd_row = [&](int i, const Frag16<T>& cd, Frag16<T>& nd) {
+    const int rl = last(i);
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < LS_MT; ++m) {
+      const int k = i + 1 + w + LS_NW * m;
+      if (k <= rl) s += dot16(a[m], ys + k * TS + 16 * h);
+    }
+    for (int k = i + 1 + w + LS_NW * LS_MT; k <= rl; k += LS_NW) {
+      Frag16<T> t;
+      frag_col(t, Lj + tile_idx(k, i) * TSQ, r, h);
+      s += dot16(t, ys + k * TS + 16 * h);
+    }
+    fetch_b(nd, max(i - 1, 0));
+    s += __shfl_xor(s, 32);
+    // y_i[r], read by every wavefront before the barrier after which z_i
+    // overwrites it
+    const double yr = ys[i * TS + r];
+    double(*pp)[TS] = part[i & 1];
+    if (lane < TS) pp[w][r] = s;
+    block_sync();
+    double tc[16];
+    gather(pp, yr, tc);
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) z += (double)cd.v[q] * tc[q];
+    z += __shfl_xor(z, 32);
+    if (lane < TS) ys[i * TS + r] = z;
+    wave_sync();
+  };
+  fetch_b(d0, nt - 1);
+  i = nt - 1;
+  for (; i >= 1; i -= 2) {
+    bwd_row(i, d0, d1);
+    bwd_row(i - 1, d1, d0);
+  }
+  if (i == 0) bwd_row(0, d0, d1);
+  block_sync();
+  for (int e = threadIdx.x; e < nt * TS; e += blockDim.x) yj[e] = ys[e];
+}
+
+// one launch per factor precision (its registers set the occupancy: two
+// workgroups per CU with FP32 factors, one with FP64)
+template <typename T>
+__device__ __forceinline__ void local_solve_block(const LocalSolveArgs& A, int j) {
+  extern __shared__ double lsmem[];
+  double(*part)[LS_NW][TS] = reinterpret_cast<double(*)[LS_NW][TS]>(lsmem);
+  double(*sv)[TS] = reinterpret_cast<double(*)[TS]>(lsmem + 2 * LS_NW * TS);
+  double* ys = lsmem + 3 * LS_NW * TS;
+  int* sE = reinterpret_cast<int*>(ys + A.maxnt * TS);
+  int* sR = sE + A.maxnt;
+  constexpr bool f64 = sizeof(T) == 8;
+  const int nt = A.nt[j];
+  const int64_t to = f64 ? A.toff64[j] : A.toff32[j], dof = f64 ? A.doff64[j] : A.doff32[j];
+  const T* L = f64 ? (const T*)A.L64 : (const T*)A.L32;
+  const T* D = f64 ? (const T*)A.D64 : (const T*)A.D32;
+  const int* E = f64 ? A.E64 : A.E32;
+  const int* R = f64 ? A.R64 : A.R32;
+  local_solve_job<T>(L + to * TSQ, D + dof * TSQ, E ? E + dof : nullptr, R ? R + dof : nullptr,
+                     nt, A.x + A.voff[j], A.y + A.voff[j], ys, part, sv, sE, sR);
+}
+__global__ __launch_bounds__(LS_NW * 64) void k_local_solve_f32(LocalSolveArgs A,
+                                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  local_solve_block<float>(A, A.jobs32[blockIdx.x]);
+}
+__global__ __launch_bounds__(LS_NW * 64) void k_local_solve_f64(LocalSolveArgs A,
+                                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  local_solve_block<double>(A, A.jobs64[blockIdx.x]);
+}
+
+static size_t local_solve_lds(int maxnt) {
+  return (size_t)(3 * LS_NW + maxnt) * TS * sizeof(double) + 2 * (size_t)maxnt * sizeof(int);
+}
+
+hipError_t local_solve_check(int maxnt) {
+  const size_t lds = local_solve_lds(maxnt);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds <= 64 * 1024) return hipSuccess;
+  // above the default limit of dynamic LDS (set once, thread-safe)
+  static const hipError_t e = [] {
+    hipError_t r = hipFuncSetAttribute((const void*)k_local_solve_f32,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void*)k_local_solve_f64,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return r;
+  }();
+  return e;
+}
+
+hipError_t local_solve(const LocalSolveArgs& a, const int* done, hipStream_t st) {
+  const size_t lds = local_solve_lds(a.maxnt);
+  if (a.njobs32 > 0)
+    hipLaunchKernelGGL(k_local_solve_f32, dim3(a.njobs32), dim3(LS_NW * 64), lds, st, a, done);
+  if (a.njobs64 > 0)
+    hipLaunchKernelGGL(k_local_solve_f64, dim3(a.njobs64), dim3(LS_NW * 64), lds, st, a, done);
   return hipGetLastError();
 }
 

@@ -20,6 +20,9 @@ GENEO_POU_CONSTANT = 0
 GENEO_POU_SARKIS = 1
 GENEO_ELEM_Q1 = 0
 GENEO_ELEM_S20 = 1
+GENEO_LOCAL_AUTO = 0
+GENEO_LOCAL_TRIANGULAR = 1
+GENEO_LOCAL_INVERSE = 2
 
 GENEO_ERR_ARG = 1
 GENEO_ERR_OOM = 2
@@ -77,7 +80,7 @@ class Opts(C.Structure):
                 ("eig_floor", C.c_double), ("eig_cheb", C.c_int), ("symv_tiles", C.c_int),
                 ("refine", C.c_int), ("refine_rtol", C.c_double), ("eig_solve", C.c_int),
                 ("eig_split", C.c_int), ("envelope", C.c_int), ("shifted_steps", C.c_int),
-                ("tau_sub", C.c_void_p)]
+                ("local_solve", C.c_int), ("tau_sub", C.c_void_p)]
 
 
 class SetupInfo(C.Structure):
@@ -86,7 +89,7 @@ class SetupInfo(C.Structure):
                 ("eig_max_resid", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64),
                 ("eig_stalled", C.c_int), ("symv_tiles", C.c_int), ("eig_solve", C.c_int),
-                ("eig_split", C.c_int)]
+                ("eig_split", C.c_int), ("local_solve", C.c_int)]
 
 
 class PcgInfo(C.Structure):

@@ -36,9 +36,9 @@ def _part_sizes(n, parts, ovl):
 
 def footprint_bytes(prob):
     """Upper estimate of the device memory a setup + solve of ``prob`` needs:
-    the assembled system, the local Cholesky factors, inverse factors and
-    symmetric inverses, the transient shifted factors and eigen blocks, and
-    the coarse data."""
+    the assembled system, the local Cholesky factors with their inverted
+    diagonal tiles, the transient shifted factors and eigen blocks, and the
+    coarse data."""
     sizes = G.geneo_q1_sizes(G.grid_from_problem(prob))
     axes = [_part_sizes(prob.ne[a], prob.parts[a], prob.ovl) for a in range(prob.dim)]
     tot_loc = 0
@@ -52,7 +52,7 @@ def footprint_bytes(prob):
         loc_factor = tiles * (4 if prob.precision == "mixed" else 8)
         shifted = tiles * 8 * 2                 # factor + scratch copy
         eig = nt * 32 * 64 * 8 * 4              # U, W, T, Y at the largest block
-        tot_loc += 3 * loc_factor + loc_factor // 32 + shifted + eig
+        tot_loc += loc_factor + nt * 1024 * 8 + shifted + eig
     system = sizes["nnz"] * 12 + sizes["ndof"] * 64 + sizes["nnz_loc"] * 20 + sizes["nloc"] * 40
     nc = prob.nsub * (prob.nev_max if prob.tau else prob.nev)
     coarse = 3 * nc * nc * 8
@@ -61,8 +61,8 @@ def footprint_bytes(prob):
 
 def resident_bytes(prob):
     """Device memory an operator keeps after its setup: the system, the local
-    symmetric inverses (and their partial-sum buffers), the coarse basis and
-    the coarse inverse."""
+    Cholesky factors (and their inverted diagonal tiles), the coarse basis
+    and the coarse inverse."""
     sizes = G.geneo_q1_sizes(G.grid_from_problem(prob))
     axes = [_part_sizes(prob.ne[a], prob.parts[a], prob.ovl) for a in range(prob.dim)]
     fac = 0
@@ -72,7 +72,7 @@ def resident_bytes(prob):
             elo, ehi = axes[a][i]
             nn *= (ehi - elo + 1)
         nt = (nn + 31) // 32
-        fac += nt * (nt + 1) // 2 * (1024 + 32) * (4 if prob.precision == "mixed" else 8)
+        fac += (nt * (nt + 1) // 2 + nt) * 1024 * (4 if prob.precision == "mixed" else 8)
     system = sizes["nnz"] * 12 + sizes["ndof"] * 64 + sizes["nnz_loc"] * 20 + sizes["nloc"] * 40
     nc = prob.nsub * (prob.nev_max if prob.tau else prob.nev)
     return int(system + fac + 2 * nc * nc * 8)

@@ -112,6 +112,19 @@ def cluster_end(lam, m, rel=1e-6):
     return e
 
 
+def kappa_local(A, subs):
+    """Largest condition number of the diagonally scaled local Dirichlet
+    matrices (the matrices both the oracle and the device factor)."""
+    from oracle import geneo
+    k = 1.0
+    for s in subs:
+        AD = geneo.dirichlet_matrix(A, s)
+        d = 1.0 / np.sqrt(np.diag(AD))
+        ev = np.linalg.eigvalsh(AD * d[:, None] * d[None, :])
+        k = max(k, ev[-1] / ev[0])
+    return k
+
+
 def kappa_spd(M):
     """Condition number of a dense SPD matrix (Lanczos on M and on M^{-1}
     through its Cholesky factor above 2000 rows)."""

@@ -25,7 +25,7 @@ import scipy.sparse as sp
 
 from gpu_common import (SMALL_PROBLEMS, csr_to_scipy, gpu_apply, gpu_assemble, gpu_pcg,
                         gpu_setup, kappa_spd, local_dense, need_gpu, say,
-                        span_contamination)
+                        span_contamination, kappa_local)
 from oracle import decomp, fem, geneo, pcg
 
 pytestmark = pytest.mark.gpu
@@ -99,22 +99,13 @@ def solved(case):
     return g, h, info
 
 
-def _kappa_local(A, subs):
-    """Largest condition number of the diagonally scaled local Dirichlet
-    matrices (the matrices both sides factor)."""
-    k = 1.0
-    for s in subs:
-        AD = geneo.dirichlet_matrix(A, s)
-        d = 1.0 / np.sqrt(np.diag(AD))
-        ev = np.linalg.eigvalsh(AD * d[:, None] * d[None, :])
-        k = max(k, ev[-1] / ev[0])
-    return k
-
-
-def test_one_level_apply(case):
+@pytest.mark.parametrize("form", [1, 2], ids=["triangular", "inverse"])
+def test_one_level_apply(case, form):
+    """Both forms of the device's local solves (substitution with the banded
+    factors, product with the symmetric inverses) against the oracle."""
     name, prob, A, b, subs, sysm = case
     g = geneo.setup(prob, A=A, subs=subs, coarse=False)
-    h = gpu_setup(sysm, prob, precision=0, coarse=0)
+    h = gpu_setup(sysm, prob, precision=0, coarse=0, local_solve=form)
     rng = np.random.Generator(np.random.PCG64(11))
     r = rng.normal(size=prob.ndof)
     z = gpu_apply(h, sysm, r)
@@ -122,7 +113,7 @@ def test_one_level_apply(case):
     # both sides solve with a backward-stable FP64 factorisation of the same
     # scaled matrices: each forward error is O(u kappa), so they may differ
     # by that much (10 u kappa, floor 1e-12)
-    tol = max(1e-12, 10 * np.finfo(float).eps / 2 * _kappa_local(A, subs))
+    tol = max(1e-12, 10 * np.finfo(float).eps / 2 * kappa_local(A, subs))
     mx = np.abs(z - zo).max() / np.abs(zo).max()
     say("[one-level] rel diff %.3e max-abs %.3e tol %.3e" %
         (np.linalg.norm(z - zo) / np.linalg.norm(zo), mx, tol))
@@ -236,7 +227,7 @@ def test_two_level_apply(case, solved):
         zc = Z @ np.linalg.solve(AH, Z.T @ r)
         kH = _cond(AH)
     zo = z1 + zc
-    kl = _kappa_local(A, subs)
+    kl = kappa_local(A, subs)
     tol_abs = 10 * u * (kl * np.linalg.norm(z1) + kH * np.linalg.norm(zc)) \
         + 1e-13 * np.linalg.norm(zo)
     diff = np.linalg.norm(z - zo)

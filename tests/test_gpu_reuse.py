@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import synth
 
-from gpu_common import gpu_apply, gpu_assemble, gpu_pcg, gpu_setup, need_gpu, say
+from gpu_common import gpu_apply, gpu_assemble, gpu_pcg, gpu_setup, kappa_local, need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -208,3 +208,54 @@ def test_shifted_steps_match_the_batched_factorisation(case):
         assert np.allclose(l0[j, :k], l1[j, :k], rtol=1e-8, atol=1e-12), j
     assert abs(i0 - i1) <= 1
     assert np.linalg.norm(x0 - x1) <= 1e-8 * np.linalg.norm(x0)
+
+
+@pytest.mark.parametrize("case", ["layers3d_mixed", "laminate_fp64", "grf36_mixed", "laminate_s20"])
+def test_local_solve_forms_agree(case):
+    """The apply's local solves by substitution with the banded factors and
+    by the product with the symmetric inverses agree to rounding: the same
+    setup (eigenvalues and coarse matrix bit for bit: the form only changes
+    the apply), one-level and two-level applies within twice the O(u kappa)
+    bound of each, PCG iterations within two (the applies differ by O(u
+    kappa), which on an ill-conditioned mixed-precision case moves the count)
+    and solutions within 1e-8."""
+    need_gpu()
+    from paper_1906_10944_amd import geneo as G
+    prob, prec = {
+        "layers3d_mixed": (lambda: synth.layers_3d(seed=4, n=24, parts=2, ovl=1, nev=6), 1),
+        "laminate_fp64": (lambda: synth.laminate_3d(ne=(16, 4, 5), parts=(4, 1, 1), nev=8), 0),
+        "grf36_mixed": (lambda: synth.grf_2d(seed=7, n=96, parts=6, ovl=2, inclusions=3), 1),
+        "laminate_s20": (lambda: synth.laminate_s20(ne=(8, 4, 3), parts=(2, 2, 1), nev=8), 1),
+    }[case]
+    prob = prob()
+    sysm = gpu_assemble(prob)
+    r = np.random.default_rng(23).standard_normal(prob.ndof)
+    outs = []
+    for form in (G.GENEO_LOCAL_TRIANGULAR, G.GENEO_LOCAL_INVERSE):
+        h1 = gpu_setup(sysm, prob, precision=prec, coarse=0, local_solve=form)
+        z1 = gpu_apply(h1, sysm, r)
+        h1.close()
+        h = gpu_setup(sysm, prob, precision=prec, local_solve=form)
+        info = G.geneo_get_setup_info(h)
+        assert info["local_solve"] == form
+        m, lam = G.geneo_get_eigenvalues(h, prob.nsub)
+        _, _, ah = G.geneo_get_coarse(h, prob.nsub)
+        x, inf = gpu_pcg(h, sysm)
+        outs.append((m, lam, ah, z1, gpu_apply(h, sysm, r), inf["iters"], x))
+        say("[local form]", case, form, "iters", inf["iters"])
+        h.close()
+    (m0, l0, a0, z10, z0, i0, x0), (m1, l1, a1, z11, z1, i1, x1) = outs
+    assert np.array_equal(m0, m1) and np.array_equal(l0, l1) and np.array_equal(a0, a1)
+    # each form is within O(u kappa) of the exact local solves (u of the
+    # factors' precision, kappa of the scaled local matrices): 2 x 10 u kappa
+    from oracle import decomp, fem
+    A, _ = fem.assemble(prob)
+    subs, _ = decomp.build(prob)
+    u = 2.0 ** -24 if prec else 2.0 ** -53
+    tol = max(1e-12, 20 * u * kappa_local(A, subs))
+    say("   one-level %.2e two-level %.2e tol %.2e" % (
+        np.linalg.norm(z10 - z11) / np.linalg.norm(z11), np.linalg.norm(z0 - z1) / np.linalg.norm(z1), tol))
+    assert np.linalg.norm(z10 - z11) <= tol * np.linalg.norm(z11)
+    assert np.linalg.norm(z0 - z1) <= tol * np.linalg.norm(z1)
+    assert abs(i0 - i1) <= 2
+    assert np.linalg.norm(x0 - x1) <= 1e-8 * np.linalg.norm(x1)
