@@ -285,7 +285,7 @@ typedef struct {
 
 /* Fills the defaults: nev 8, tau 0 (fixed count), nev_max 16,
  * sigma -1e-3, FP64, pivot_tol 1e-3, eig_tol 1e-8, eig_maxit 300,
- * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 3,
+ * eig_block 0, seed 0, coarse 1, eig_stall 10, eig_floor 1e-6, eig_cheb 4,
  * symv_tiles 0, refine 0, refine_rtol 1e-6, eig_solve 0, eig_split 0,
  * envelope 1, shifted_steps 0, local_solve 0, tau_sub NULL. */
 void geneo_default_opts(geneo_opts_t* opts);

@@ -2259,7 +2259,7 @@ void geneo_default_opts(geneo_opts_t* o) {
   o->coarse = 1;
   o->eig_stall = 10;
   o->eig_floor = 1e-6;
-  o->eig_cheb = 3;
+  o->eig_cheb = 4;
   o->symv_tiles = 0;
   o->tau_sub = nullptr;
   o->refine = 0;

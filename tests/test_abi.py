@@ -43,7 +43,7 @@ def test_default_opts():
     assert o.sigma == -1e-3 and o.nev == 8 and o.coarse == 1 and o.precision == 0
     # the last fields too: a layout mismatch between the header and the
     # binding would show here
-    assert o.eig_stall == 10 and o.eig_floor == 1e-6 and o.eig_cheb == 3 and o.symv_tiles == 0
+    assert o.eig_stall == 10 and o.eig_floor == 1e-6 and o.eig_cheb == 4 and o.symv_tiles == 0
 
 
 @pytest.mark.parametrize("make", [
