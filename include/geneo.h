@@ -254,8 +254,12 @@ typedef struct {
   int envelope;       /* 1 = the local factorisations and the eigen solves
                          skip the tiles outside each matrix's envelope
                          (left of the first entry of each row: zero in the
-                         Cholesky factor, as no fill reaches them); 0 =
-                         dense.  Both give bitwise the same result. */
+                         Cholesky factor, as no fill reaches them), and the
+                         shifted matrices clear only their envelope tiles;
+                         0 = dense.  Both give bitwise the same result.
+                         2 = as 1, with the shifted matrices' tiles outside
+                         the envelope filled with NaN (a check that nothing
+                         reads them). */
   int shifted_steps;  /* the shifted factorisations A_N,j - sigma B_j by
                          tile-column steps, each step one launch over all
                          subdomains with a workgroup per trailing tile (for

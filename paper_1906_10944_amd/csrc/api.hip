@@ -1222,12 +1222,26 @@ void setup_shifted(geneo_handle_s* h, SetupScratch& X, LocalLayout& LN,
   X.envNR.alloc(LN.ndiag);
   {
     ProfScope ps("densify_shifted", sb, 8.0 * LN.ntiles * TSQ, 0.0);
-    HIPCHK(hipMemsetAsync(X.G.p, 0, X.G.n * sizeof(double), sb));
     HIPCHK(launch_env_init(X.envNE.p, X.doffN.p, X.ntN.p, nullptr, nsub, sb));
-    HIPCHK(launch_densify_shifted(X.G.p, X.toffN.p, X.ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
-                                  o.sigma, X.envNE.p, X.doffN.p, sb));
-    HIPCHK(launch_env_finish(X.envNE.p, X.envNR.p, X.doffN.p, X.ntN.p, nullptr, nsub, sb));
-    if (o.envelope) X.uNE = X.envNE.p, X.uNR = X.envNR.p;
+    if (o.envelope) {
+      // envelope from the patterns, then only its tiles are cleared (option
+      // envelope = 2 fills all others with NaN first: a check that nothing
+      // reads them)
+      HIPCHK(launch_env_shifted(X.ntN.p, nsub, LN.maxnt, S->sub_ptr, An, Ao, X.envNE.p, X.doffN.p,
+                                sb));
+      HIPCHK(launch_env_finish(X.envNE.p, X.envNR.p, X.doffN.p, X.ntN.p, nullptr, nsub, sb));
+      if (o.envelope == 2) HIPCHK(hipMemsetAsync(X.G.p, 0xff, X.G.n * sizeof(double), sb));
+      HIPCHK(launch_env_clear(X.G.p, X.toffN.p, X.ntN.p, nsub, LN.maxnt, X.envNE.p, X.doffN.p,
+                              sb));
+      HIPCHK(launch_densify_shifted(X.G.p, X.toffN.p, X.ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
+                                    o.sigma, nullptr, X.doffN.p, sb));
+      X.uNE = X.envNE.p, X.uNR = X.envNR.p;
+    } else {
+      HIPCHK(hipMemsetAsync(X.G.p, 0, X.G.n * sizeof(double), sb));
+      HIPCHK(launch_densify_shifted(X.G.p, X.toffN.p, X.ntN.p, nsub, S->sub_ptr, S->pou, An, Ao,
+                                    o.sigma, X.envNE.p, X.doffN.p, sb));
+      HIPCHK(launch_env_finish(X.envNE.p, X.envNR.p, X.doffN.p, X.ntN.p, nullptr, nsub, sb));
+    }
   }
   // algorithmic work inside the envelopes: read back in the timing mode
   // only (where it is reported); otherwise the dense counts stand in
@@ -2355,7 +2369,7 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
     if (o.eig_solve < 0 || o.eig_solve > trsm_variants())
       fail(GENEO_ERR_ARG, "eig_solve must be 0 .. " + std::to_string(trsm_variants()));
     if (o.eig_split < -1) fail(GENEO_ERR_ARG, "eig_split must be -1, 0 or positive");
-    if (o.envelope != 0 && o.envelope != 1) fail(GENEO_ERR_ARG, "envelope must be 0 or 1");
+    if (o.envelope < 0 || o.envelope > 2) fail(GENEO_ERR_ARG, "envelope must be 0, 1 or 2");
     if (o.shifted_steps < -1 || o.shifted_steps > 1)
       fail(GENEO_ERR_ARG, "shifted_steps must be -1, 0 or 1");
     if (o.local_solve < 0 || o.local_solve > 2)

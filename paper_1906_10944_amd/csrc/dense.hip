@@ -5,7 +5,9 @@
 //    stored in FP32 (mixed mode) or FP64.
 //  * Shifted matrices C_j = A_N,j - sigma X_j A^o_j X_j over N_j (the matrix
 //    of the shift-and-invert transform of Sec. 4.4), FP64.
-// The caller clears the tiles (one device-wide fill); the grid is
+// The caller clears the tiles (one device-wide fill, or for the shifted
+// matrices just their envelope tiles, found from the patterns first); the
+// grid is
 // (subdomain[, group of 256 rows]) and every thread owns whole rows (a unit
 // diagonal first, the identity on padding rows, then the row's entries), so
 // no two threads write the same entry.
@@ -171,6 +173,64 @@ __global__ __launch_bounds__(256) void k_densify_shifted(
     }
     if (env && first / TS < a / TS) atomicMin(env + doff[j] + a / TS, first / TS);
   }
+}
+
+// Envelope of the shifted matrices from the patterns alone (the first
+// column of each row among the entries of A_N,j and A^o_j at or left of the
+// diagonal; padding rows: the diagonal), without writing a tile: a pass
+// over the column indices, so that only the envelope tiles need clearing
+// before the fill.  Grid (subdomain, group of 256 rows).
+__global__ __launch_bounds__(256) void k_env_shifted(const int* __restrict__ ntl,
+                                                     const int* __restrict__ sub_ptr,
+                                                     const int* __restrict__ an_rp,
+                                                     const int* __restrict__ an_col,
+                                                     const int* __restrict__ ao_rp,
+                                                     const int* __restrict__ ao_col,
+                                                     int* __restrict__ env,
+                                                     const int64_t* __restrict__ doff) {
+  const int j = blockIdx.x;
+  const int nt = ntl[j];
+  const int s0 = sub_ptr[j], n = sub_ptr[j + 1] - s0;
+  const int a = blockIdx.y * blockDim.x + threadIdx.x;
+  if (a >= nt * TS) return;
+  int first = a;
+  if (a < n) {
+    for (int p = an_rp[s0 + a]; p < an_rp[s0 + a + 1]; ++p) first = min(first, an_col[p]);
+    for (int p = ao_rp[s0 + a]; p < ao_rp[s0 + a + 1]; ++p) first = min(first, ao_col[p]);
+  }
+  if (first / TS < a / TS) atomicMin(env + doff[j] + a / TS, first / TS);
+}
+
+// Zeroes tiles E(i) .. i of tile row blockIdx.y of matrix blockIdx.x (they
+// are consecutive in the packed layout).
+__global__ __launch_bounds__(256) void k_env_clear(double* __restrict__ tiles,
+                                                   const int64_t* __restrict__ toff,
+                                                   const int* __restrict__ ntl,
+                                                   const int* __restrict__ envE,
+                                                   const int64_t* __restrict__ doff) {
+  const int j = blockIdx.x, i = blockIdx.y;
+  if (i >= ntl[j]) return;
+  const int e = envE[doff[j] + i];
+  double2* t = reinterpret_cast<double2*>(tiles + (toff[j] + tile_idx(i, e)) * TSQ);
+  const int nv = (i - e + 1) * TSQ / 2;
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) t[v] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_env_shifted(const int* nt, int nsub, int ntmax, const int* sub_ptr,
+                              const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao, int* env,
+                              const int64_t* doff, hipStream_t st) {
+  if (nsub <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env_shifted, dim3(nsub, (ntmax * TS + 255) / 256), dim3(256), 0, st, nt,
+                     sub_ptr, An->rowptr, An->col, Ao->rowptr, Ao->col, env, doff);
+  return hipGetLastError();
+}
+
+hipError_t launch_env_clear(double* tiles, const int64_t* toff, const int* nt, int nsub,
+                            int ntmax, const int* envE, const int64_t* doff, hipStream_t st) {
+  if (nsub <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env_clear, dim3(nsub, ntmax), dim3(256), 0, st, tiles, toff, nt, envE,
+                     doff);
+  return hipGetLastError();
 }
 
 hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int* nt, int nsub,

@@ -60,6 +60,14 @@ hipError_t launch_densify_shifted(double* tiles, const int64_t* toff, const int*
                                   int nsub, const int* sub_ptr, const double* pou,
                                   const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao,
                                   double sigma, int* env, const int64_t* doff, hipStream_t st);
+// The shifted matrices' envelope from the patterns of A_N,j and A^o_j
+// (lowers E from env_init's values; env_finish follows), and the zeroing of
+// each matrix's envelope tiles (ntmax = largest tile count).
+hipError_t launch_env_shifted(const int* nt, int nsub, int ntmax, const int* sub_ptr,
+                              const geneo_csr_batch_t* An, const geneo_csr_batch_t* Ao, int* env,
+                              const int64_t* doff, hipStream_t st);
+hipError_t launch_env_clear(double* tiles, const int64_t* toff, const int* nt, int nsub,
+                            int ntmax, const int* envE, const int64_t* doff, hipStream_t st);
 
 // -------------------------------------------------------------- chol.hip
 // envE / envR: the matrices' tile envelopes (NULL: dense).  Tiles outside
