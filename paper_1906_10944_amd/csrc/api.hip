@@ -638,13 +638,21 @@ __global__ void k_count_active(const int* a, int n, int* out) {
   }
 }
 
-__global__ void k_max_resid(const double* resid, const int* m, int nsub, int b, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < nsub; ++j)
-      for (int c = 0; c < m[j]; ++c) mx = fmax(mx, resid[(int64_t)j * b + c]);
-    *out = mx;
+// Largest Ritz residual of the selected pairs (setup info), one block of
+// 256 threads over the subdomains (a maximum: any order gives the same).
+__global__ __launch_bounds__(256) void k_max_resid(const double* resid, const int* m, int nsub,
+                                                   int b, double* out) {
+  __shared__ double sm[256];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < nsub; j += blockDim.x)
+    for (int c = 0; c < m[j]; ++c) mx = fmax(mx, resid[(int64_t)j * b + c]);
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = sm[0];
 }
 
 // Scratch buffers of one setup call: kept alive until the call returns so
@@ -1543,7 +1551,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   h->Z.alloc(zs);
   HIPCHK(launch_basis(X.T.p, X.voffN.p, b, S->sub_ptr, S->pou, h->dmap.p, h->m.p, h->zoff.p,
                       h->nd.p, nsub, h->Z.p, sb));
-  hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(1), 0, sb, X.resid.p, h->m.p, nsub, b, X.mr.p);
+  hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(256), 0, sb, X.resid.p, h->m.p, nsub, b, X.mr.p);
   if (nc > 0) {
     X.woffd.upload(woff, sb);
     X.Wg.alloc(ws);

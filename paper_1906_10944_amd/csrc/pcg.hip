@@ -512,35 +512,53 @@ hipError_t residual0(const double* b, const double* q, double* r, int n, hipStre
 // e by a fused multiply-add) and error-free sums (Knuth's TwoSum) as in
 // the Dot2 algorithm of Ogita, Rump and Oishi ("Accurate sum and dot
 // product", SIAM J. Sci. Comput. 26, 2005).  The explicit _rn operations
-// keep the compiler from contracting the products into the sums.  One
-// thread per row: used a few times per solve, for the residuals of
-// iterative refinement and the reported true residual.
+// keep the compiler from contracting the products into the sums.  LPR
+// lanes per row, each over every LPR-th entry, their double-double partial
+// sums combined in a fixed order: used a few times per solve, for the
+// residuals of iterative refinement and the reported true residual.
+template <int LPR>
 __global__ __launch_bounds__(256) void k_residual_dd(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ col,
                                                      const double* __restrict__ val,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x,
                                                      double* __restrict__ r) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = b[i], c = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const double a = val[k], xv = x[col[k]];
-    const double p = __dmul_rn(a, xv);
-    const double ep = fma(a, xv, -p);            // a xv = p + ep
-    const double t = __dadd_rn(s, -p);
-    const double bv = __dsub_rn(t, s);
-    const double es = __dadd_rn(__dsub_rn(s, __dsub_rn(t, bv)), __dsub_rn(-p, bv));  // s - p = t + es
-    s = t;
-    c = __dadd_rn(c, __dsub_rn(es, ep));
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / LPR, sub = threadIdx.x % LPR;
+  // lane sub of row i: b_i (lane 0) minus its share of the entries (every
+  // LPR-th), as a double-double (s, c)
+  double s = 0.0, c = 0.0;
+  if (i < n) {
+    if (sub == 0) s = b[i];
+    for (int k = rp[i] + sub; k < rp[i + 1]; k += LPR) {
+      const double a = val[k], xv = x[col[k]];
+      const double p = __dmul_rn(a, xv);
+      const double ep = fma(a, xv, -p);            // a xv = p + ep
+      const double t = __dadd_rn(s, -p);
+      const double bv = __dsub_rn(t, s);
+      const double es = __dadd_rn(__dsub_rn(s, __dsub_rn(t, bv)), __dsub_rn(-p, bv));  // s - p = t + es
+      s = t;
+      c = __dadd_rn(c, __dsub_rn(es, ep));
+    }
   }
-  r[i] = __dadd_rn(s, c);
+  // the lanes' pairs added in a fixed tree: s by an error-free sum (the
+  // same in both lanes of each exchange), the errors into c
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    const double s2 = __shfl_xor(s, o, LPR), c2 = __shfl_xor(c, o, LPR);
+    const double t = __dadd_rn(s, s2);
+    const double bv = __dsub_rn(t, s);
+    const double e = __dadd_rn(__dsub_rn(s, __dsub_rn(t, bv)), __dsub_rn(s2, bv));
+    s = t;
+    c = __dadd_rn(__dadd_rn(c, c2), e);
+  }
+  if (i < n && sub == 0) r[i] = __dadd_rn(s, c);
 }
 
 hipError_t residual_dd(const geneo_csr_t* A, const double* b, const double* x, double* r,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_dd, dim3((A->n + 255) / 256), dim3(256), 0, st, A->n, A->rowptr,
-                     A->col, A->val, b, x, r);
+  constexpr int LPR = 8;
+  hipLaunchKernelGGL(k_residual_dd<LPR>, dim3((A->n + 256 / LPR - 1) / (256 / LPR)), dim3(256), 0,
+                     st, A->n, A->rowptr, A->col, A->val, b, x, r);
   return hipGetLastError();
 }
 
