@@ -125,7 +125,7 @@ class Runner:
                "eig_stalled": sinfo["eig_stalled"], "eig_max_resid": sinfo["eig_max_resid"],
                "symv_tiles": sinfo["symv_tiles"], "eig_block": sinfo["eig_block"],
                "eig_solve": sinfo["eig_solve"], "eig_split": sinfo["eig_split"],
-               "local_solve": sinfo["local_solve"],
+               "local_solve": sinfo["local_solve"], "eig_solve_split": sinfo["eig_solve_split"],
                "t_phase_ms": sinfo["t_phase_ms"]}
         self.last = (sysm, h, x)
         return out
@@ -244,22 +244,23 @@ def prof_symbol(name, info):
     """The kernel a launch site ran, where it depends on the setup: the eigen
     block width picks the solve kernel, the number of FP64 refactors their
     factorisation."""
-    if name in ("trsm_fwd", "trsm_bwd"):
-        # the unsplit solves (the kernel the setup's tuning chose)
-        b, bwd = info.get("eig_block", 32), "true" if name == "trsm_bwd" else "false"
-        if b <= 32 and info.get("eig_solve", 1) == 1:
-            return "k_trsm_win<%d, %s, %d>" % (b // 16, bwd, b)
-        if b <= 48:
-            ad, bp = {16: (2, "true"), 32: (1, "true"), 48: (1, "false")}[b]
-            return "k_trsm_w1<%d, %s, %d, %s, %d>" % (b // 16, bwd, ad, bp, b)
-        return "k_trsm_bwd" if bwd == "true" else "k_trsm_fwd"
-    if name in ("trsm_fwd_split", "trsm_bwd_split"):
-        # 16-column blocks; the split kernel is the unsplit one's choice
-        # unless that is the b = 48 default (its split tuning is not reported)
-        b, bwd = info.get("eig_block", 32), "true" if name == "trsm_bwd_split" else "false"
-        if info.get("eig_solve", 1) == 1 and b <= 32:
-            return "k_trsm_win<1, %s, %d>" % (bwd, b)
-        return "16-column k_trsm_win / k_trsm_w1 <1, %s, ..., %d>" % (bwd, b)
+    if name in ("trsm_fwd", "trsm_bwd", "trsm_fwd_split", "trsm_bwd_split"):
+        # the kernel the setup's tuning chose (1, 2: 8 wavefronts; 3, 4: 4;
+        # 1, 3 two tile rows per wavefront, 2, 4 one), unsplit or on
+        # 16-column blocks
+        split = name.endswith("split")
+        b = info.get("eig_block", 32)
+        bwd = "true" if name.startswith("trsm_bwd") else "false"
+        v = info.get("eig_solve_split" if split else "eig_solve", 1)
+        if b > 48:
+            return "k_trsm_bwd" if bwd == "true" else "k_trsm_fwd"
+        ncq = 1 if split else b // 16
+        nw = 8 if v in (1, 2) else 4
+        if v in (2, 4) or (ncq, b) == (3, 48):
+            ad, bp = {(1, 16): (2, "true"), (2, 32): (1, "true"), (3, 48): (1, "false"),
+                      (1, 32): (2, "true"), (1, 48): (2, "true")}[(ncq, b)]
+            return "k_trsm_w1<%d, %s, %d, %s, %d, %d>" % (ncq, bwd, ad, bp, b, nw)
+        return "k_trsm_win<%d, %s, %d, %d>" % (ncq, bwd, b, nw)
     if name == "chol_dirichlet_f64" and 0 < info.get("fallback_fp64", 0) <= 32:
         return "tile-column step kernels"
     if name == "chol_shifted_f64" and info.get("nsub", 0) <= 32:
@@ -463,6 +464,7 @@ def workload_line(prob, args, steps, warmup, full):
         "symv_tiles": last["symv_tiles"], "eig_solve": last["eig_solve"],
         "eig_split": last["eig_split"], "fallback_fp64": last["fallback_fp64"],
         "local_solve": {1: "triangular", 2: "inverse"}.get(last["local_solve"], "?"),
+        "eig_solve_split": last["eig_solve_split"],
         "setup_ms": last["t_setup_ms"], "solve_ms": last["t_solve_ms"],
         "setup_phase_ms": last["t_phase_ms"][:6],
     }

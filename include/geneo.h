@@ -358,6 +358,8 @@ typedef struct {
                              active (0 = never) */
   int local_solve;        /* GENEO_LOCAL_TRIANGULAR or GENEO_LOCAL_INVERSE:
                              the form the apply uses */
+  int eig_solve_split;    /* kernel of the split (16-column) solves, 1 .. 4
+                             as eig_solve */
 } geneo_setup_info_t;
 
 int geneo_get_setup_info(geneo_handle_t h, geneo_setup_info_t* info);

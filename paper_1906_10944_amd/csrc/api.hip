@@ -1342,6 +1342,7 @@ void setup_coarse(geneo_handle_s* h, SetupScratch& X, const LocalLayout& LN,
   if (trsm_max_split(b) == 1) h->trsm.split_limit = 0;
   h->info.eig_solve = h->trsm.variant + 1;
   h->info.eig_split = h->trsm.split_limit;
+  h->info.eig_solve_split = h->trsm.split_variant + 1;
   // kernel and split of the solves while (at most) na subdomains are active
   auto tv = [&](int na) { return na <= h->trsm.split_limit ? h->trsm.split_variant : h->trsm.variant; };
   auto ts = [&](int na) { return na <= h->trsm.split_limit ? trsm_max_split(b) : 1; };

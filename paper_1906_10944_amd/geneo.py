@@ -89,7 +89,7 @@ class SetupInfo(C.Structure):
                 ("eig_max_resid", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_phase_ms", C.c_double * 8), ("bytes_local_factors", C.c_int64),
                 ("eig_stalled", C.c_int), ("symv_tiles", C.c_int), ("eig_solve", C.c_int),
-                ("eig_split", C.c_int), ("local_solve", C.c_int)]
+                ("eig_split", C.c_int), ("local_solve", C.c_int), ("eig_solve_split", C.c_int)]
 
 
 class PcgInfo(C.Structure):
