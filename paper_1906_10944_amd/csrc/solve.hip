@@ -676,7 +676,7 @@ __global__ __launch_bounds__(1024) void k_trsm_bwd(const double* __restrict__ G,
 // taken in windows of 2 NW; the 32 x b blocks of the current window stay in
 // registers as matrix-core accumulators (wavefront w owns window rows
 // w and w + NW).  Each window first takes its update from all finished rows
-// (left-looking; factor tiles streamed with the next one prefetched, no
+// (left-looking; factor tiles streamed with the next one in flight, no
 // barriers), then is solved right-looking: the owner of row i forms
 // X_i = Dinv_i acc_i (or Dinv_i^T acc_i) and publishes it, transposed, in
 // LDS; after one barrier every wavefront subtracts G_ki X_i (G_ik^T X_i)
@@ -834,55 +834,66 @@ __global__ __launch_bounds__(NW * 64, 2) void k_trsm_win(const double* __restric
     // window rows [p0, p1); BWD windows run from the bottom
     const int p0 = BWD ? max(0, nt - (wi + 1) * NW * TRW_MR) : wi * NW * TRW_MR;
     const int p1 = BWD ? nt - wi * NW * TRW_MR : min(nt, p0 + NW * TRW_MR);
+    // acc holds -R_k + the products so far (negation is exact, so this is
+    // bitwise the negated R_k - products); the owner negates at the end
     d4_t acc[TRW_MR][2][NCQ];
     int krow[TRW_MR];
 #pragma unroll
     for (int m = 0; m < TRW_MR; ++m) {
       krow[m] = p0 + w + NW * m;
       const bool own = krow[m] < p1;
+      const int kr = min(krow[m], nt - 1);   // every load issued, in range
 #pragma unroll
       for (int rq = 0; rq < 2; ++rq)
 #pragma unroll
         for (int cq = 0; cq < NCQ; ++cq)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[m][rq][cq][v] = own ? Rj[((int64_t)krow[m] * TS + rq * 16 + acc_row<double>(lane, v)) * LDB +
-                                         cq * 16 + acc_col(lane)]
-                                    : 0.0;
+          for (int v = 0; v < 4; ++v) {
+            const double r = Rj[((int64_t)kr * TS + rq * 16 + acc_row<double>(lane, v)) * LDB +
+                                cq * 16 + acc_col(lane)];
+            acc[m][rq][cq][v] = own ? -r : 0.0;
+          }
     }
+    auto load_a = [&](const double* t, F8 (&aa)[2]) {
+#pragma unroll
+      for (int rq = 0; rq < 2; ++rq) {
+        if (BWD) afrag_tr(aa[rq], t, rq * 16, fi, fg);
+        else afrag(aa[rq], t, rq * 16, fi, fg);
+      }
+    };
     // ---- left-looking update from the finished rows
-    // FWD: acc_k -= sum_{jj < p0} G_k,jj X_jj      BWD: acc_k -= sum_{jj >= p1} G_jj,k^T X_jj
+    // FWD: acc_k += sum_{jj < p0} G_k,jj X_jj      BWD: acc_k += sum_{jj >= p1} G_jj,k^T X_jj
+    // Each step first issues the loads of X_jj, then those of the next
+    // factor tile, then the products: the wait for X_jj and the current
+    // tile leaves the next tile in flight.  Two tile buffers alternate
+    // (no register copy of a load in flight, which would wait for it).
 #pragma unroll
     for (int m = 0; m < TRW_MR; ++m) {
       const int k = krow[m];
       if (k >= p1) continue;
       const int jlo = BWD ? p1 : first(k), jhi = BWD ? min(nt, last(k) + 1) : p0;
       if (jlo >= jhi) continue;
-      const double* t0 = BWD ? Gj + tile_idx(jlo, k) * TSQ : Gj + tile_idx(k, jlo) * TSQ;
-      F8 a[2];
-      auto load = [&](const double* t, F8 (&aa)[2]) {
-#pragma unroll
-        for (int rq = 0; rq < 2; ++rq) {
-          if (BWD) afrag_tr(aa[rq], t, rq * 16, fi, fg);
-          else afrag(aa[rq], t, rq * 16, fi, fg);
-#pragma unroll
-          for (int s = 0; s < 8; ++s) aa[rq].v[s] = -aa[rq].v[s];
-        }
+      auto tile = [&](int jj) {
+        return BWD ? Gj + tile_idx(jj, k) * TSQ : Gj + tile_idx(k, jj) * TSQ;
       };
-      load(t0, a);
-      for (int jj = jlo; jj < jhi; ++jj) {
-        const int jn = min(jj + 1, jhi - 1);
-        F8 a1[2];
-        load(BWD ? Gj + tile_idx(jn, k) * TSQ : Gj + tile_idx(k, jn) * TSQ, a1);
+      auto step = [&](const F8 (&cur)[2], F8 (&nxt)[2], int jj) {
+        F8 bf[NCQ];
 #pragma unroll
-        for (int cq = 0; cq < NCQ; ++cq) {
-          F8 bf;
-          bfrag_g(bf, Xj + (int64_t)jj * TS * LDB, LDB, cq * 16, fi, fg);
-          trw_mma<NCQ>(acc[m], a, bf, cq);
-        }
+        for (int cq = 0; cq < NCQ; ++cq)
+          bfrag_g(bf[cq], Xj + (int64_t)jj * TS * LDB, LDB, cq * 16, fi, fg);
+        load_a(tile(min(jj + 1, jhi - 1)), nxt);
 #pragma unroll
-        for (int rq = 0; rq < 2; ++rq) a[rq] = a1[rq];
+        for (int cq = 0; cq < NCQ; ++cq) trw_mma<NCQ>(acc[m], cur, bf[cq], cq);
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      F8 a0[2], a1[2];
+      load_a(tile(jlo), a0);
+      int jj = jlo;
+      for (; jj + 1 < jhi; jj += 2) {
+        step(a0, a1, jj);
+        step(a1, a0, jj + 1);
       }
+      if (jj < jhi) step(a0, a1, jj);
     }
     // ---- right-looking solve inside the window
     for (int st = 0; st < p1 - p0; ++st) {
@@ -893,25 +904,22 @@ __global__ __launch_bounds__(NW * 64, 2) void k_trsm_win(const double* __restric
 #pragma unroll
         for (int m = 0; m < TRW_MR; ++m)
           if (m == om)
-            trw_finish<NCQ, BWD>(acc[m], Dj + (int64_t)i * TSQ, sTmp, sXo,
-                                 Xj + (int64_t)i * TS * LDB, LDB, lane);
+            trw_finish<NCQ, BWD, true>(acc[m], Dj + (int64_t)i * TSQ, sTmp, sXo,
+                                       Xj + (int64_t)i * TS * LDB, LDB, lane);
       }
       // the factor tile of the first row's update does not depend on X_i:
       // its loads are in flight while the wavefront waits at the barrier
-      // (the second row's load then overlaps the first row's products)
-      auto load_neg = [&](F8 (&aa)[2], int k) {
-        const double* t = BWD ? Gj + tile_idx(i, k) * TSQ : Gj + tile_idx(k, i) * TSQ;
-#pragma unroll
-        for (int rq = 0; rq < 2; ++rq) {
-          if (BWD) afrag_tr(aa[rq], t, rq * 16, fi, fg);
-          else afrag(aa[rq], t, rq * 16, fi, fg);
-        }
+      // (the second row's load then overlaps the first row's products;
+      // loading both before the barrier would hold 64 more registers
+      // through the owner's product)
+      auto tile_i = [&](int k) {
+        return BWD ? Gj + tile_idx(i, k) * TSQ : Gj + tile_idx(k, i) * TSQ;
       };
       auto wants = [&](int k) {
         return k < p1 && (BWD ? k < i && i <= last(k) : k > i && first(k) <= i);
       };
       F8 a0[2];
-      if (wants(krow[0])) load_neg(a0, krow[0]);
+      if (wants(krow[0])) load_a(tile_i(krow[0]), a0);
       block_sync();
 #pragma unroll
       for (int m = 0; m < TRW_MR; ++m) {
@@ -922,12 +930,8 @@ __global__ __launch_bounds__(NW * 64, 2) void k_trsm_win(const double* __restric
           a[0] = a0[0];
           a[1] = a0[1];
         } else {
-          load_neg(a, k);
+          load_a(tile_i(k), a);
         }
-#pragma unroll
-        for (int rq = 0; rq < 2; ++rq)
-#pragma unroll
-          for (int s = 0; s < 8; ++s) a[rq].v[s] = -a[rq].v[s];
 #pragma unroll
         for (int cq = 0; cq < NCQ; ++cq) {
           F8 bf;
