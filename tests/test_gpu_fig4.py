@@ -76,7 +76,15 @@ def test_fig4_kappa_grows_with_fewer_than_four_vectors(sweep):
 @pytest.mark.parametrize("m", [3, 4])
 def test_fig4_against_oracle(sweep, m):
     """m = 3 cuts every subdomain's spectrum at a wide gap: the coarse space
-    is unique and iterations and condition estimate are compared.  m = 4
+    is unique and the condition estimates are compared (to 1e-6).  The
+    iteration count is compared within +-2 plus the spread that a 1e-10
+    relative perturbation of the oracle's own coarse basis produces: the
+    64 subdomains' first discarded eigenpairs leave a tight cluster of
+    small eigenvalues in the preconditioned operator, and the number of
+    steps CG spends on that cluster (at kappa ~ 5e5, to 1e-10) depends on
+    how tightly it clusters, a property below any eigen solver's
+    tolerance (a 1e-12 perturbation of the basis already moves the
+    oracle's count, while its kappa is unchanged to 1e-9).  m = 4
     cuts a pair of equal eigenvalues (the mirror-symmetric overlap strips of
     interior subdomains, checked here on the oracle's spectra): both sides
     hold a valid GenEO space, not the same one, so the comparison is the
@@ -93,8 +101,19 @@ def test_fig4_against_oracle(sweep, m):
                                                    min(gaps)))
     if m == 3:
         assert min(gaps) > 1e-3
-        assert abs(it - ref.iters) <= 2
-        assert kg == pytest.approx(ko, rel=1e-3)
+        rng = np.random.Generator(np.random.PCG64(7))
+        Zp = g.Z.copy()
+        Zp.data = Zp.data * (1.0 + 1e-10 * rng.standard_normal(len(Zp.data)))
+        g.Z = Zp
+        AH = (Zp.T @ (A @ Zp)).toarray()
+        g.AH = 0.5 * (AH + AH.T)
+        g.LH = geneo.coarse_cholesky(g.AH)
+        refp = pcg.pcg(A, b, g.apply, rtol=1e-10)
+        spread = abs(refp.iters - ref.iters)
+        say("   oracle with its coarse basis perturbed by 1e-10: it %d kappa %.4f (spread %d)" %
+            (refp.iters, pcg.kappa_estimate(refp.alphas, refp.betas), spread))
+        assert abs(it - ref.iters) <= 2 + spread
+        assert kg == pytest.approx(ko, rel=1e-6)
     else:
         assert min(gaps) < 1e-6
         sysm = gpu_assemble(p)
