@@ -612,27 +612,25 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
   // B fragment of X(jj, C) from memory: column cq*16 + fi of the block,
   // rows 8 fg .. 8 fg + 7 of tile (jj, c0 + cq / 2), i.e. 8 consecutive
   // entries of a row of the stored (transposed) tile; zero above the diagonal
+  // X(jj, tc) is zero for tc > jj: the load is issued anyway (from a tile
+  // in range) and the values replaced, so the number of loads in flight is
+  // the same on every path
   auto bfrag_mem = [&](V8<T>& f, int jj, int cq) {
     const int tc = c0 + (cq >> 1);
+    ld8(f, Xj + tile_idx(jj, min(tc, jj)) * TSQ + ((cq & 1) * 16 + fi) * TS + 8 * fg);
     if (tc > jj) {
 #pragma unroll
       for (int s = 0; s < 8; ++s) f.v[s] = (T)0;
-      return;
     }
-    ld8(f, Xj + tile_idx(jj, tc) * TSQ + ((cq & 1) * 16 + fi) * TS + 8 * fg);
   };
   auto bfrag_lds = [&](V8<T>& f, const T* sT, int cq) {
     const T* p = sT + (cq * 16 + fi) * LDI + 8 * fg;
 #pragma unroll
     for (int s = 0; s < 8; ++s) f.v[s] = p[s];
   };
-  auto afrag_neg = [&](V8<T> (&a)[2], const T* t) {
+  auto afrag = [&](V8<T> (&a)[2], const T* t) {
 #pragma unroll
-    for (int rq = 0; rq < 2; ++rq) {
-      ld8(a[rq], t + (rq * 16 + fi) * TS + 8 * fg);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) a[rq].v[s] = -a[rq].v[s];
-    }
+    for (int rq = 0; rq < 2; ++rq) ld8(a[rq], t + (rq * 16 + fi) * TS + 8 * fg);
   };
   for (int p0 = c0; p0 < nt; p0 += TW_W) {
     const int p1 = min(nt, p0 + TW_W);
@@ -648,9 +646,11 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int r = rq * 16 + acc_row<T>(lane, v), col = cq * 16 + acc_col(lane);
-            acc[m][rq][cq][v] = (krow[m] == c0 + (col >> 5) && r == (col & 31)) ? (T)1 : (T)0;
+            acc[m][rq][cq][v] = (krow[m] == c0 + (col >> 5) && r == (col & 31)) ? (T)-1 : (T)0;
           }
     }
+    // acc holds -E + the products so far (negation is exact: bitwise the
+    // negated E - products), negated again where the owner reads it
     // ---- update from the finished rows c0 .. p0-1
 #pragma unroll
     for (int m = 0; m < TW_MR; ++m) {
@@ -658,20 +658,24 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
       if (k >= p1 || p0 == c0) continue;
       const int jlo = max(c0, first(k));
       if (jlo >= p0) continue;
-      V8<T> a[2];
-      afrag_neg(a, Lj + tile_idx(k, jlo) * TSQ);
-      for (int jj = jlo; jj < p0; ++jj) {
-        V8<T> a1[2];
-        afrag_neg(a1, Lj + tile_idx(k, min(jj + 1, p0 - 1)) * TSQ);
+      // X(jj, .) loaded before the next factor tile, two tile buffers
+      // alternating: the wait for X leaves the next tile in flight
+      auto step = [&](const V8<T> (&cur)[2], V8<T> (&nxt)[2], int jj) {
+        V8<T> bf[NCQ];
 #pragma unroll
-        for (int cq = 0; cq < NCQ; ++cq) {
-          V8<T> bf;
-          bfrag_mem(bf, jj, cq);
-          mma(acc[m], a, bf, cq);
-        }
-        a[0] = a1[0];
-        a[1] = a1[1];
+        for (int cq = 0; cq < NCQ; ++cq) bfrag_mem(bf[cq], jj, cq);
+        afrag(nxt, Lj + tile_idx(k, min(jj + 1, p0 - 1)) * TSQ);
+#pragma unroll
+        for (int cq = 0; cq < NCQ; ++cq) mma(acc[m], cur, bf[cq], cq);
+      };
+      V8<T> a0[2], a1[2];
+      afrag(a0, Lj + tile_idx(k, jlo) * TSQ);
+      int jj = jlo;
+      for (; jj + 1 < p0; jj += 2) {
+        step(a0, a1, jj);
+        step(a1, a0, jj + 1);
       }
+      if (jj < p0) step(a0, a1, jj);
     }
     // ---- right-looking solve inside the window
     for (int st = 0; st < p1 - p0; ++st) {
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
             for (int cq = 0; cq < NCQ; ++cq)
 #pragma unroll
               for (int v = 0; v < 4; ++v)
-                sTmp[(cq * 16 + acc_col(lane)) * LDI + rq * 16 + acc_row<T>(lane, v)] = acc[m][rq][cq][v];
+                sTmp[(cq * 16 + acc_col(lane)) * LDI + rq * 16 + acc_row<T>(lane, v)] = -acc[m][rq][cq][v];
           wave_sync();
           V8<T> a[2];
 #pragma unroll
@@ -732,7 +736,7 @@ __global__ __launch_bounds__(TwCfg<T>::NW * 64) void k_trtri_win(const T* __rest
         const int k = krow[m];
         if (k >= p1 || k <= i || first(k) > i) continue;
         V8<T> a[2];
-        afrag_neg(a, Lj + tile_idx(k, i) * TSQ);
+        afrag(a, Lj + tile_idx(k, i) * TSQ);
 #pragma unroll
         for (int cq = 0; cq < NCQ; ++cq) {
           V8<T> bf;
@@ -806,22 +810,28 @@ __global__ __launch_bounds__(LA_NW * 64) void k_lauum(const T* __restrict__ XT, 
       ld8(fb[h], tb + h * 16 * TS);
     }
   };
-  load(a, b, I);
-  for (int K = I; K < nt; ++K) {
-    V8<T> an[2], bn[2];
-    load(an, bn, K + 1 < nt ? K + 1 : K);
+  // two fragment sets alternate (rows unrolled by two): a register copy of
+  // a load in flight would wait for it, so K + 1's loads are issued into
+  // the other set and stay in flight during K's products
+  auto step = [&](const V8<T> (&ca)[2], const V8<T> (&cb)[2], V8<T> (&na)[2], V8<T> (&nb)[2],
+                  int K) {
+    load(na, nb, K + 1 < nt ? K + 1 : K);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int rq = 0; rq < 2; ++rq)
 #pragma unroll
-        for (int cq = 0; cq < 2; ++cq) acc[rq][cq] = Mfma<T>::run(a[rq].v[s], b[cq].v[s], acc[rq][cq]);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      a[h] = an[h];
-      b[h] = bn[h];
-    }
+        for (int cq = 0; cq < 2; ++cq)
+          acc[rq][cq] = Mfma<T>::run(ca[rq].v[s], cb[cq].v[s], acc[rq][cq]);
+  };
+  V8<T> a1[2], b1[2];
+  load(a, b, I);
+  int K = I;
+  for (; K + 1 < nt; K += 2) {
+    step(a, b, a1, b1, K);
+    step(a1, b1, a, b, K + 1);
   }
+  if (K < nt) step(a, b, a1, b1, K);
   T* Sj = S + (toff[j] + tile_idx(I, J)) * TSQ;
 #pragma unroll
   for (int rq = 0; rq < 2; ++rq)
