@@ -278,22 +278,28 @@ hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st) {
 
 // ------------------------------------------------------ local solves ---
 // y = L^{-T} L^{-1} x for one subdomain's banded Cholesky factor, one
-// workgroup of LS_NW wavefronts per subdomain, all of its vector in LDS
+// workgroup of NW wavefronts per subdomain, all of its vector in LDS
 // (FP64).  Forward, tile row i: s_i = x_i - sum_{E(i) <= k < i} L_ik y_k,
 // y_i = Dinv_i s_i; backward, in place: t_i = y_i - sum_{i < k <= R(i)}
 // L_ki^T z_k, z_i = Dinv_i^T t_i.  The off-diagonal tiles of a row are
 // dealt to the wavefronts by their distance from the diagonal (wavefront w
-// takes distances w + 1, w + 1 + LS_NW, ...); each leaves its 32 partial
+// takes distances w + 1, w + 1 + NW, ...); each leaves its 32 partial
 // sums in LDS, and after one barrier every wavefront adds them in the same
 // fixed order and applies the inverted diagonal tile itself (the same
 // arithmetic everywhere, so the copies of y_i the wavefronts write to LDS
 // are equal, and each reads back only its own writes: one barrier per tile
-// row).  The factor tiles of row i + 1 (LS_MT per wavefront, with the
-// diagonal tile and x_{i+1}) are loaded while row i is completed.  Lane (r, h) takes entry r of the
+// row).  The off-diagonal tiles of row i + 2 (MT per wavefront) and the
+// diagonal tile and x of row i + 1 are loaded while row i is completed.  Lane (r, h) takes entry r of the
 // row (backward: column) and half h of the 32 entries it is summed over,
 // FP32 tiles converted to FP64 as used.
-#define LS_NW 8
-#define LS_MT 1
+// FP32 factors: 4 wavefronts of 2 tiles per row (168 registers, three
+// waves per SIMD); FP64 factors, whose tiles take twice the registers: 8
+// wavefronts of 1 tile.
+#define LS32_NW 4
+#define LS32_MT 2
+#define LS64_NW 8
+#define LS64_MT 1
+#define LS_NW_MAX 8
 
 template <typename T> struct Frag16 { T v[16]; };
 // entries [r][16h .. 16h+15] of a tile
@@ -337,11 +343,11 @@ __device__ __forceinline__ double dot16(const Frag16<T>& f, const double* v) {
   return s;
 }
 
-template <typename T>
+template <typename T, int NW, int MT>
 __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ Dj,
                                 const int* __restrict__ Ej, const int* __restrict__ Rj, int nt,
                                 const double* __restrict__ xj, double* __restrict__ yj,
-                                double* ys, double (*part)[LS_NW][TS], double (*sv)[TS],
+                                double* ys, double (*part)[NW][TS], double (*sv)[TS],
                                 int* sE, int* sR) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 31, h = lane >> 5;
   // the envelope in LDS (dense: E = 0, R = nt - 1)
@@ -357,7 +363,7 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
   auto gather = [&](double(*pp)[TS], double base, double (&o)[16]) {
     double t = pp[0][r];
 #pragma unroll
-    for (int ww = 1; ww < LS_NW; ++ww) t += pp[ww][r];
+    for (int ww = 1; ww < NW; ++ww) t += pp[ww][r];
     if (lane < TS) sv[w][r] = base - t;
     wave_sync();
 #pragma unroll
@@ -376,31 +382,40 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
   // products of tiles outside the envelope skipped where they are used), so
   // the number of loads in flight is the same on every path and the waits
   // for the older ones can be partial.
-  Frag16<T> a[LS_MT], d0, d1;
+  Frag16<T> a0[MT], a1[MT], d0, d1;
   double x0 = 0.0, x1 = 0.0;
   // ---- forward: ys = L^{-1} x
-  auto fetch_f = [&](Frag16<T>& fd, double& fx, int i) {
+  // The off-diagonal tiles of row i + 2 are loaded into the buffer of row
+  // i right after its last use (two buffers, by row parity), the diagonal
+  // tile and x of row i + 1 just before them: each load has two rows (one
+  // for the diagonal) to arrive, and the waits for the older loads leave
+  // the newer ones in flight.
+  auto fetch_band_f = [&](Frag16<T> (&ab)[MT], int i) {
     const int e = first(i);
 #pragma unroll
-    for (int m = 0; m < LS_MT; ++m)
-      frag_row(a[m], Lj + tile_idx(i, max(i - 1 - w - LS_NW * m, e)) * TSQ, r, h);
+    for (int m = 0; m < MT; ++m)
+      frag_row(ab[m], Lj + tile_idx(i, max(i - 1 - w - NW * m, e)) * TSQ, r, h);
+  };
+  auto fetch_diag_f = [&](Frag16<T>& fd, double& fx, int i) {
     frag_row(fd, Dj + (int64_t)i * TSQ, r, h);
     fx = xj[i * TS + r];
   };
-  auto fwd_row = [&](int i, const Frag16<T>& cd, double cx, Frag16<T>& nd, double& nx) {
+  auto fwd_row = [&](int i, Frag16<T> (&ab)[MT], const Frag16<T>& cd, double cx,
+                     Frag16<T>& nd, double& nx) {
     const int e = first(i);
     double s = 0.0;
 #pragma unroll
-    for (int m = 0; m < LS_MT; ++m) {
-      const int k = i - 1 - w - LS_NW * m;
-      if (k >= e) s += dot16(a[m], ys + k * TS + 16 * h);
+    for (int m = 0; m < MT; ++m) {
+      const int k = i - 1 - w - NW * m;
+      if (k >= e) s += dot16(ab[m], ys + k * TS + 16 * h);
     }
-    for (int k = i - 1 - w - LS_NW * LS_MT; k >= e; k -= LS_NW) {
+    for (int k = i - 1 - w - NW * MT; k >= e; k -= NW) {
       Frag16<T> t;
       frag_row(t, Lj + tile_idx(i, k) * TSQ, r, h);
       s += dot16(t, ys + k * TS + 16 * h);
     }
-    fetch_f(nd, nx, min(i + 1, nt - 1));
+    fetch_diag_f(nd, nx, min(i + 1, nt - 1));
+    fetch_band_f(ab, min(i + 2, nt - 1));
     s += __shfl_xor(s, 32);
     double(*pp)[TS] = part[i & 1];
     if (lane < TS) pp[w][r] = s;
@@ -414,38 +429,40 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
     if (lane < TS) ys[i * TS + r] = y;
     wave_sync();
   };
-  fetch_f(d0, x0, 0);
+  fetch_band_f(a0, 0);
+  fetch_diag_f(d0, x0, 0);
+  fetch_band_f(a1, min(1, nt - 1));
   int i = 0;
   for (; i + 1 < nt; i += 2) {
-    fwd_row(i, d0, x0, d1, x1);
-    fwd_row(i + 1, d1, x1, d0, x0);
+    fwd_row(i, a0, d0, x0, d1, x1);
+    fwd_row(i + 1, a1, d1, x1, d0, x0);
   }
-  if (i < nt) fwd_row(i, d0, x0, d1, x1);
+  if (i < nt) fwd_row(i, a0, d0, x0, d1, x1);
   // the last forward row's partials are read before the backward rows
   // rewrite either buffer
   block_sync();
-  // ---- backward, in place: ys = L^{-T} ys
-  auto fetch_b = [&](Frag16<T>& fd, int i) {
+  // ---- backward, in place: ys = L^{-T} ys (the same load pipeline)
+  auto fetch_band_b = [&](Frag16<T> (&ab)[MT], int i) {
     const int rl = last(i);
 #pragma unroll
-    for (int m = 0; m < LS_MT; ++m)
-      frag_col(a[m], Lj + tile_idx(min(i + 1 + w + LS_NW * m, rl), i) * TSQ, r, h);
-    frag_col(fd, Dj + (int64_t)i * TSQ, r, h);
+    for (int m = 0; m < MT; ++m)
+      frag_col(ab[m], Lj + tile_idx(min(i + 1 + w + NW * m, rl), i) * TSQ, r, h);
   };
-  auto bwd_row = [&](int i, const Frag16<T>& cd, Frag16<T>& nd) {
+  auto bwd_row = [&](int i, Frag16<T> (&ab)[MT], const Frag16<T>& cd, Frag16<T>& nd) {
     const int rl = last(i);
     double s = 0.0;
 #pragma unroll
-    for (int m = 0; m < LS_MT; ++m) {
-      const int k = i + 1 + w + LS_NW * m;
-      if (k <= rl) s += dot16(a[m], ys + k * TS + 16 * h);
+    for (int m = 0; m < MT; ++m) {
+      const int k = i + 1 + w + NW * m;
+      if (k <= rl) s += dot16(ab[m], ys + k * TS + 16 * h);
     }
-    for (int k = i + 1 + w + LS_NW * LS_MT; k <= rl; k += LS_NW) {
+    for (int k = i + 1 + w + NW * MT; k <= rl; k += NW) {
       Frag16<T> t;
       frag_col(t, Lj + tile_idx(k, i) * TSQ, r, h);
       s += dot16(t, ys + k * TS + 16 * h);
     }
-    fetch_b(nd, max(i - 1, 0));
+    frag_col(nd, Dj + (int64_t)max(i - 1, 0) * TSQ, r, h);
+    fetch_band_b(ab, max(i - 2, 0));
     s += __shfl_xor(s, 32);
     // y_i[r], read by every wavefront before the barrier after which z_i
     // overwrites it
@@ -462,25 +479,27 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
     if (lane < TS) ys[i * TS + r] = z;
     wave_sync();
   };
-  fetch_b(d0, nt - 1);
+  fetch_band_b(a0, nt - 1);
+  frag_col(d0, Dj + (int64_t)(nt - 1) * TSQ, r, h);
+  fetch_band_b(a1, max(nt - 2, 0));
   i = nt - 1;
   for (; i >= 1; i -= 2) {
-    bwd_row(i, d0, d1);
-    bwd_row(i - 1, d1, d0);
+    bwd_row(i, a0, d0, d1);
+    bwd_row(i - 1, a1, d1, d0);
   }
-  if (i == 0) bwd_row(0, d0, d1);
+  if (i == 0) bwd_row(0, a0, d0, d1);
   block_sync();
   for (int e = threadIdx.x; e < nt * TS; e += blockDim.x) yj[e] = ys[e];
 }
 
 // one launch per factor precision (its registers set the occupancy: two
 // workgroups per CU with FP32 factors, one with FP64)
-template <typename T>
+template <typename T, int NW, int MT>
 __device__ __forceinline__ void local_solve_block(const LocalSolveArgs& A, int j) {
   extern __shared__ double lsmem[];
-  double(*part)[LS_NW][TS] = reinterpret_cast<double(*)[LS_NW][TS]>(lsmem);
-  double(*sv)[TS] = reinterpret_cast<double(*)[TS]>(lsmem + 2 * LS_NW * TS);
-  double* ys = lsmem + 3 * LS_NW * TS;
+  double(*part)[NW][TS] = reinterpret_cast<double(*)[NW][TS]>(lsmem);
+  double(*sv)[TS] = reinterpret_cast<double(*)[TS]>(lsmem + 2 * NW * TS);
+  double* ys = lsmem + 3 * NW * TS;
   int* sE = reinterpret_cast<int*>(ys + A.maxnt * TS);
   int* sR = sE + A.maxnt;
   constexpr bool f64 = sizeof(T) == 8;
@@ -490,22 +509,22 @@ __device__ __forceinline__ void local_solve_block(const LocalSolveArgs& A, int j
   const T* D = f64 ? (const T*)A.D64 : (const T*)A.D32;
   const int* E = f64 ? A.E64 : A.E32;
   const int* R = f64 ? A.R64 : A.R32;
-  local_solve_job<T>(L + to * TSQ, D + dof * TSQ, E ? E + dof : nullptr, R ? R + dof : nullptr,
+  local_solve_job<T, NW, MT>(L + to * TSQ, D + dof * TSQ, E ? E + dof : nullptr, R ? R + dof : nullptr,
                      nt, A.x + A.voff[j], A.y + A.voff[j], ys, part, sv, sE, sR);
 }
-__global__ __launch_bounds__(LS_NW * 64) void k_local_solve_f32(LocalSolveArgs A,
+__global__ __launch_bounds__(LS32_NW * 64) void k_local_solve_f32(LocalSolveArgs A,
                                                                    const int* __restrict__ done) {
   if (done && *done) return;
-  local_solve_block<float>(A, A.jobs32[blockIdx.x]);
+  local_solve_block<float, LS32_NW, LS32_MT>(A, A.jobs32[blockIdx.x]);
 }
-__global__ __launch_bounds__(LS_NW * 64) void k_local_solve_f64(LocalSolveArgs A,
+__global__ __launch_bounds__(LS64_NW * 64) void k_local_solve_f64(LocalSolveArgs A,
                                                                 const int* __restrict__ done) {
   if (done && *done) return;
-  local_solve_block<double>(A, A.jobs64[blockIdx.x]);
+  local_solve_block<double, LS64_NW, LS64_MT>(A, A.jobs64[blockIdx.x]);
 }
 
 static size_t local_solve_lds(int maxnt) {
-  return (size_t)(3 * LS_NW + maxnt) * TS * sizeof(double) + 2 * (size_t)maxnt * sizeof(int);
+  return (size_t)(3 * LS_NW_MAX + maxnt) * TS * sizeof(double) + 2 * (size_t)maxnt * sizeof(int);
 }
 
 hipError_t local_solve_check(int maxnt) {
@@ -527,9 +546,9 @@ hipError_t local_solve_check(int maxnt) {
 hipError_t local_solve(const LocalSolveArgs& a, const int* done, hipStream_t st) {
   const size_t lds = local_solve_lds(a.maxnt);
   if (a.njobs32 > 0)
-    hipLaunchKernelGGL(k_local_solve_f32, dim3(a.njobs32), dim3(LS_NW * 64), lds, st, a, done);
+    hipLaunchKernelGGL(k_local_solve_f32, dim3(a.njobs32), dim3(LS32_NW * 64), lds, st, a, done);
   if (a.njobs64 > 0)
-    hipLaunchKernelGGL(k_local_solve_f64, dim3(a.njobs64), dim3(LS_NW * 64), lds, st, a, done);
+    hipLaunchKernelGGL(k_local_solve_f64, dim3(a.njobs64), dim3(LS64_NW * 64), lds, st, a, done);
   return hipGetLastError();
 }
 
