@@ -287,9 +287,4 @@ hipError_t launch_spmv(const geneo_csr_t* A, const double* x, double* y, int lpr
                        hipStream_t st);
 hipError_t launch_gather_local(const double* r, const int* dglob, const double* dscale,
                                int64_t nvec, double* xl, hipStream_t st);
-hipError_t launch_restrict_coarse(const double* r, const double* Z, const int* zoff,
-                                  const int* m, const int* nd, const int* didx,
-                                  const int* sub_ptr, const int* sub_idx, const int* coff,
-                                  int nsub, double* rH, hipStream_t st);
-
 }  // namespace geneo
