@@ -69,11 +69,10 @@ template <> struct DiagLd<double> { static constexpr int v = TS + 2; };
 // X = L^{-1} by forward substitution, reading the rows of L from the lanes
 // that hold them.  Writes L (zeros above the diagonal) to Lout, X to Xout
 // and, if sX is not null, to sX.  Returns 1 + the first in-tile row whose
-// pivot fails d > pivtol, else 0.  Kept out of line: inlined, its unrolled
-// register arrays would raise the register count of the calling kernel.
+// pivot fails d > pivtol, else 0.
 template <typename T, int LDI>
-__device__ __noinline__ int diag_tile(const T* D, T* Lout, T* Xout, T (*sX)[LDI], T* sRp,
-                                      int lane, double pivtol) {
+__device__ __forceinline__ int diag_tile_body(const T* D, T* Lout, T* Xout, T (*sX)[LDI], T* sRp,
+                                              int lane, double pivtol) {
   const int r = lane & (TS - 1);
   const bool writer = lane < TS;
   T a[TS];
@@ -125,6 +124,15 @@ __device__ __noinline__ int diag_tile(const T* D, T* Lout, T* Xout, T (*sX)[LDI]
   }
   wave_sync();
   return fail;
+}
+
+// Out of line for the multi-wavefront kernels (inlined, its unrolled
+// register arrays would raise their register count); a kernel that runs it
+// alone inlines the body.
+template <typename T, int LDI>
+__device__ __noinline__ int diag_tile(const T* D, T* Lout, T* Xout, T (*sX)[LDI], T* sRp,
+                                      int lane, double pivtol) {
+  return diag_tile_body<T, LDI>(D, Lout, Xout, sX, sRp, lane, pivtol);
 }
 
 template <typename T, int NW, int KB>
@@ -878,8 +886,8 @@ __global__ __launch_bounds__(64) void k_step_potrf(double* __restrict__ A, doubl
   const int j = jobs[blockIdx.x];
   if (k >= ntl[j] || (k > 0 && status[j])) return;
   double* D = A + (toff[j] + tile_idx(k, k)) * TSQ;
-  const int f = diag_tile<double, TS + 2>(D, D, Di + (doff[j] + k) * TSQ, nullptr, sRp,
-                                          threadIdx.x, pivtol ? *pivtol : 0.0);
+  const int f = diag_tile_body<double, TS + 2>(D, D, Di + (doff[j] + k) * TSQ, nullptr, sRp,
+                                               threadIdx.x, pivtol ? *pivtol : 0.0);
   if (threadIdx.x == 0 && (f || k == 0)) status[j] = f ? k * TS + f : 0;
 }
 
