@@ -227,7 +227,13 @@ typedef struct {
                          on [0, a] (a = smallest Ritz value of the block)
                          before it is orthonormalised: eig_cheb - 1 extra
                          shifted solves per sweep, faster convergence of the
-                         wanted pairs.  0 or 1: plain subspace iteration. */
+                         wanted pairs.  0 or 1: plain subspace iteration.
+                         At most 6 (GENEO_ERR_ARG above): the filter grows
+                         like x^degree, and a floating subdomain's kernel
+                         modes (Ritz values near 1/|sigma|) would outgrow the
+                         smallest wanted ones by more than 1/u and erase
+                         them (degree 8 stalls every floating subdomain of
+                         the 96^3 layers). */
   int symv_tiles;     /* tiles per wavefront in the products with the local
                          inverses: 8, 16 or 32, or 0 = the fastest of these,
                          timed on the device at the first setup of each

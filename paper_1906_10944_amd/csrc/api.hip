@@ -2373,9 +2373,10 @@ int geneo_setup(const geneo_csr_t* A, const geneo_subdomains_t* S, const geneo_c
       fail(GENEO_ERR_ARG, "invalid eigenvector count");
     if (o.eig_block && (o.eig_block % 16 || o.eig_block > 64))
       fail(GENEO_ERR_ARG, "eig_block must be a multiple of 16 up to 64");
-    if (o.eig_maxit < 1 || !(o.eig_tol > 0) || o.eig_stall < 0 || !(o.eig_floor >= 0) ||
-        o.eig_cheb < 0 || o.eig_cheb > 16)
+    if (o.eig_maxit < 1 || !(o.eig_tol > 0) || o.eig_stall < 0 || !(o.eig_floor >= 0))
       fail(GENEO_ERR_ARG, "invalid eigen tolerances");
+    if (o.eig_cheb < 0 || o.eig_cheb > 6)
+      fail(GENEO_ERR_ARG, "eig_cheb must be 0..6");
     if (o.symv_tiles != 0 && o.symv_tiles != 8 && o.symv_tiles != 16 && o.symv_tiles != 32)
       fail(GENEO_ERR_ARG, "symv_tiles must be 0, 8, 16 or 32");
     if (o.refine < 0 || o.refine > 8 || !(o.refine_rtol > 0 && o.refine_rtol < 1))

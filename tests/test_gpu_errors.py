@@ -117,6 +117,20 @@ def test_eigen_no_convergence(small):
     _healthy(prob, sysm)
 
 
+def test_chebyshev_degree_above_six_is_rejected(small):
+    """Degrees above 6 are refused before any work: the filter would let a
+    floating subdomain's kernel modes outgrow the smallest wanted Ritz
+    vectors by more than 1/u."""
+    from paper_1906_10944_amd import geneo as G
+    prob, sysm = small
+    with pytest.raises(G.GeneoError) as e:
+        gpu_setup(sysm, prob, precision=1, eig_cheb=7)
+    assert e.value.code == G.GENEO_ERR_ARG and "eig_cheb" in str(e.value)
+    h = gpu_setup(sysm, prob, precision=1, eig_cheb=6)
+    h.close()
+    _healthy(prob, sysm)
+
+
 def test_pcg_start_cases(small):
     """The PCG start runs on the device: a zero right-hand side and an initial
     guess that already meets the tolerance both stop before the first
