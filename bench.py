@@ -15,8 +15,8 @@ the FP64 form of the same workload, the 512^2 Darcy workload, the
 serendipity laminate (20-node bricks, 23,175 dofs) and the serving
 stream's p50/p99 latency.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
-GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the library maps all
+subdomains onto one GPU.
 """
 import argparse
 import json
@@ -491,8 +491,8 @@ def workload_line(prob, args, steps, warmup, full):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported"
-                          % args.gpus}))
+        print(json.dumps({"error": "the library maps all subdomains onto one GPU; --gpus %d "
+                          "is not supported" % args.gpus}))
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
