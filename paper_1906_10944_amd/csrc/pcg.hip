@@ -26,7 +26,24 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
   double s = 0.0;
   if (row < n) {
     const int p1 = rp[row + 1];
-    for (int p = rp[row] + sub; p < p1; p += LPR) s += val[p] * x[col[p]];
+    // a lane's entries in batches of 4: the index and value loads, then the
+    // gathers, all in flight before the first product; the sum keeps the
+    // entry order
+    for (int p = rp[row] + sub; p < p1; p += 4 * LPR) {
+      int cc[4];
+      double vv[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(p + u * LPR, p1 - 1);  // in range; extra terms unused
+        cc[u] = col[q];
+        vv[u] = val[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = x[cc[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (p + u * LPR < p1) s += vv[u] * xv[u];
+    }
   }
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
@@ -244,9 +261,23 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ r,
       covered = true;
       s += dscale[o.x] * yl[o.x];
       if (use_coarse) {
+        // columns in batches of 8: the batch's loads are all in flight
+        // before the first product (one round trip per batch, not per
+        // column); the sum keeps the column order
         const double* zr = Z + o.y;
         const double* yh = yH + o.z;
-        for (int c = 0; c < o.w; ++c) s += zr[c] * yh[c];
+        for (int c0 = 0; c0 < o.w; c0 += 8) {
+          double zv[8], hv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int c = min(c0 + u, o.w - 1);  // in range; extra terms unused
+            zv[u] = zr[c];
+            hv[u] = yh[c];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (c0 + u < o.w) s += zv[u] * hv[u];
+        }
       }
     }
     rg = r[g];
@@ -442,7 +473,22 @@ __global__ __launch_bounds__(256) void k_p_spmv(int n, const int* __restrict__ r
     double s = 0.0;
     if (row < n) {
       const int p1 = rp[row + 1];
-      for (int k = rp[row] + sub; k < p1; k += LPR) s += val[k] * pnew(col[k]);
+      // batches of 4 entries per lane, as in k_spmv
+      for (int k = rp[row] + sub; k < p1; k += 4 * LPR) {
+        int cc[4];
+        double vv[4], pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = min(k + u * LPR, p1 - 1);
+          cc[u] = col[q];
+          vv[u] = val[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pv[u] = pnew(cc[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k + u * LPR < p1) s += vv[u] * pv[u];
+      }
     }
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
