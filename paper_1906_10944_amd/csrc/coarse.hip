@@ -102,9 +102,22 @@ __global__ __launch_bounds__(256) void k_coarse_blocks(
       }
       __syncthreads();
       if (pq < npq)
-        for (int d = rg; d < cnt; d += G) {
-          const int b = match[d];
-          if (b >= 0) s += Zi[(int64_t)(base + d) * mi + p] * Wj[(int64_t)b * mj + q];
+        // rows in batches of 8: the batch's loads are all in flight before
+        // the first product (rows outside N_j load row 0 of W_j and are
+        // skipped); the sum keeps the row order
+        for (int d0 = rg; d0 < cnt; d0 += 8 * G) {
+          int bb[8];
+          double zv[8], wv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int d = min(d0 + u * G, cnt - 1);
+            bb[u] = d0 + u * G < cnt ? match[d] : -1;
+            zv[u] = Zi[(int64_t)(base + d) * mi + p];
+            wv[u] = Wj[(int64_t)max(bb[u], 0) * mj + q];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (bb[u] >= 0) s += zv[u] * wv[u];
         }
     }
     red[threadIdx.x] = s;
@@ -136,9 +149,20 @@ __global__ __launch_bounds__(256) void k_coarse_blocks(
       if (t >= npq) break;
       int p = t / mj, q = t % mj;
       double s = 0.0;
-      for (int d = 0; d < cnt; ++d) {
-        int b = match[d];
-        if (b >= 0) s += Zi[(int64_t)(base + d) * mi + p] * Wj[(int64_t)b * mj + q];
+      // batches of 8 rows, as above
+      for (int d0 = 0; d0 < cnt; d0 += 8) {
+        int bb[8];
+        double zv[8], wv[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int d = min(d0 + v, cnt - 1);
+          bb[v] = d0 + v < cnt ? match[d] : -1;
+          zv[v] = Zi[(int64_t)(base + d) * mi + p];
+          wv[v] = Wj[(int64_t)max(bb[v], 0) * mj + q];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          if (bb[v] >= 0) s += zv[v] * wv[v];
       }
       acc[u] += s;
     }
