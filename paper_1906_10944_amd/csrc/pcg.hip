@@ -152,13 +152,21 @@ __device__ __forceinline__ void restrict_block(int j, const double* __restrict__
     double s[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) s[c] = 0.0;
-#pragma unroll 4
-    for (int d = threadIdx.x; d < n; d += 256) {
-      const double rv = r[gj[d]];
-      const double* zr = Zj + (int64_t)d * mj + c0;
+    // rows in batches of 4 (stride 256): the index loads, then the gathers
+    // of r, all in flight before the first product; rows in order
+    for (int d0 = threadIdx.x; d0 < n; d0 += 4 * 256) {
+      double rv[4];
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (c < nc) s[c] += zr[c] * rv;
+      for (int u = 0; u < 4; ++u) rv[u] = r[gj[min(d0 + 256 * u, n - 1)]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int d = d0 + 256 * u;
+        if (d >= n) break;
+        const double* zr = Zj + (int64_t)d * mj + c0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < nc) s[c] += zr[c] * rv[u];
+      }
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c) {

@@ -1243,15 +1243,32 @@ __global__ __launch_bounds__(256) void k_bcompact(const int* __restrict__ sub_pt
   int k = 0;
   const int o = FILL ? brp[s0 + a] : 0;
   if (mua != 0.0) {
-    for (int p = rp[s0 + a]; p < rp[s0 + a + 1]; ++p) {
-      const int q = colx[p];
-      const double w = mua * val[p] * pou[s0 + q];
-      if (w == 0.0) continue;
-      if (FILL) {
-        bcol[o + k] = q;
-        bval[o + k] = w;
+    // entries in batches of 8: the index and value loads, then the
+    // partition-of-unity gathers, all in flight before the first entry is
+    // kept or dropped (in entry order)
+    const int p1 = rp[s0 + a + 1];
+    for (int p0 = rp[s0 + a]; p0 < p1; p0 += 8) {
+      int qq[8];
+      double vv[8], mq[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(p0 + u, p1 - 1);  // in range; extra entries unused
+        qq[u] = colx[p];
+        vv[u] = val[p];
       }
-      ++k;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mq[u] = pou[s0 + qq[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (p0 + u >= p1) break;
+        const double w = mua * vv[u] * mq[u];
+        if (w == 0.0) continue;
+        if (FILL) {
+          bcol[o + k] = qq[u];
+          bval[o + k] = w;
+        }
+        ++k;
+      }
     }
   }
   if (!FILL) cnt[s0 + a] = k;
