@@ -43,9 +43,26 @@ __global__ __launch_bounds__(256) void k_galerkin_w(const int* __restrict__ rp,
   for (int t = blockIdx.y * blockDim.x + threadIdx.x; t < n * mj; t += blockDim.x * gridDim.y) {
     int a = t / mj, c = t % mj;
     double s = 0.0;
-    for (int p = rp[s0 + a]; p < rp[s0 + a + 1]; ++p) {
-      int d = dmap[s0 + colx[p]];
-      if (d >= 0) s += val[p] * Zj[(int64_t)d * mj + c];
+    // entries in batches of 8: index and value loads, then the dmap
+    // gathers, then the Z gathers, each level in flight together; the sum
+    // keeps the entry order (entries outside D_j load row 0 and are skipped)
+    const int p1 = rp[s0 + a + 1];
+    for (int p0 = rp[s0 + a]; p0 < p1; p0 += 8) {
+      int dd[8];
+      double vv[8], zv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(p0 + u, p1 - 1);
+        dd[u] = colx[p];
+        vv[u] = val[p];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dd[u] = p0 + u < p1 ? dmap[s0 + dd[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) zv[u] = Zj[(int64_t)max(dd[u], 0) * mj + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (dd[u] >= 0) s += vv[u] * zv[u];
     }
     Wj[(int64_t)a * mj + c] = s;
   }

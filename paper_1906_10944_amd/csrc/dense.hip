@@ -77,16 +77,29 @@ __device__ __forceinline__ T* tile_elem(T* base, int r, int c) {
   return base + tile_idx(r / TS, c / TS) * TSQ + (r % TS) * TS + (c % TS);
 }
 
-__device__ __forceinline__ int bsearch_row(const int* a, int n, int key) {
-  int lo = 0, hi = n - 1;
-  while (lo <= hi) {
-    int mid = (lo + hi) >> 1;
-    int v = a[mid];
-    if (v == key) return mid;
-    if (v < key) lo = mid + 1;
-    else hi = mid - 1;
+// bsearch_row for 8 keys at once: branch-free halving steps, the same
+// number for every key, so the 8 probes of a step are in flight together.
+// pos[u] = index of key[u] in the sorted a[0..n), or -1.
+__device__ __forceinline__ void bsearch_row8(const int* a, int n, const int (&key)[8],
+                                             int (&pos)[8]) {
+  int base[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) base[u] = 0;
+  for (int len = n; len > 1;) {
+    const int half = len >> 1;
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a[base[u] + half];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (v[u] <= key[u]) base[u] += half;
+    len -= half;
   }
-  return -1;
+  int v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = n > 0 ? a[base[u]] : key[u] + 1;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) pos[u] = v[u] == key[u] ? base[u] : -1;
 }
 
 template <typename T>
@@ -109,13 +122,30 @@ __global__ __launch_bounds__(256) void k_densify_dirichlet(
     if (g < 0) continue;
     double sd = dscale[v0 + d];
     int first = d;
-    for (int p = rowptr[g]; p < rowptr[g + 1]; ++p) {
-      int a = bsearch_row(Nj, n, col[p]);
-      if (a < 0) continue;
-      int dc = dmap[s0 + a];
-      if (dc < 0 || dc > d) continue;
-      *tile_elem(base, d, dc) = (T)(val[p] * sd * dscale[v0 + dc]);
-      first = min(first, dc);
+    // the row's entries in batches of 8, each level of loads (index and
+    // value, the searches' probes, dmap, dscale) in flight together
+    const int p1 = rowptr[g + 1];
+    for (int p0 = rowptr[g]; p0 < p1; p0 += 8) {
+      int key[8], a8[8], dc8[8];
+      double v8[8], sc8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(p0 + u, p1 - 1);
+        key[u] = col[p];
+        v8[u] = val[p];
+      }
+      bsearch_row8(Nj, n, key, a8);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dc8[u] = p0 + u < p1 && a8[u] >= 0 ? dmap[s0 + a8[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sc8[u] = dscale[v0 + max(dc8[u], 0)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int dc = dc8[u];
+        if (dc < 0 || dc > d) continue;
+        *tile_elem(base, d, dc) = (T)(v8[u] * sd * sc8[u]);
+        first = min(first, dc);
+      }
     }
     if (env && first / TS < d / TS) atomicMin(env + doff[j] + d / TS, first / TS);
   }
@@ -154,20 +184,44 @@ __global__ __launch_bounds__(256) void k_densify_shifted(
     *tile_elem(base, a, a) = 1.0;
     if (a >= n) continue;
     int first = a;
-    for (int p = an_rp[s0 + a]; p < an_rp[s0 + a + 1]; ++p) {
-      int c = an_col[p];
-      if (c <= a) {
-        *tile_elem(base, a, c) = an_val[p];
-        first = min(first, c);
+    // entries in batches of 8, each level of loads in flight together
+    // (the columns of a row are distinct, so a batch's updates are too)
+    const int pa1 = an_rp[s0 + a + 1];
+    for (int p0 = an_rp[s0 + a]; p0 < pa1; p0 += 8) {
+      int c8[8];
+      double v8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = min(p0 + u, pa1 - 1);
+        c8[u] = an_col[p];
+        v8[u] = an_val[p];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (p0 + u >= pa1 || c8[u] > a) continue;
+        *tile_elem(base, a, c8[u]) = v8[u];
+        first = min(first, c8[u]);
       }
     }
     double mua = pou[s0 + a];
     if (mua != 0.0) {
-      for (int p = ao_rp[s0 + a]; p < ao_rp[s0 + a + 1]; ++p) {
-        int c = ao_col[p];
-        if (c <= a) {
-          *tile_elem(base, a, c) -= sigma * mua * ao_val[p] * pou[s0 + c];
-          first = min(first, c);
+      const int po1 = ao_rp[s0 + a + 1];
+      for (int p0 = ao_rp[s0 + a]; p0 < po1; p0 += 8) {
+        int c8[8];
+        double v8[8], m8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int p = min(p0 + u, po1 - 1);
+          c8[u] = ao_col[p];
+          v8[u] = ao_val[p];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m8[u] = pou[s0 + c8[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (p0 + u >= po1 || c8[u] > a) continue;
+          *tile_elem(base, a, c8[u]) -= sigma * mua * v8[u] * m8[u];
+          first = min(first, c8[u]);
         }
       }
     }
