@@ -1260,14 +1260,14 @@ __global__ __launch_bounds__(256) void k_bcompact(const int* __restrict__ sub_pt
       for (int u = 0; u < 8; ++u) mq[u] = pou[s0 + qq[u]];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (p0 + u >= p1) break;
+        // every value is used (no early exit), so the loads stay batched
         const double w = mua * vv[u] * mq[u];
-        if (w == 0.0) continue;
-        if (FILL) {
+        const bool keep = p0 + u < p1 && w != 0.0;
+        if (FILL && keep) {
           bcol[o + k] = qq[u];
           bval[o + k] = w;
         }
-        ++k;
+        k += keep ? 1 : 0;
       }
     }
   }
