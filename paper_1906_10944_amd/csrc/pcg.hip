@@ -158,14 +158,18 @@ __device__ __forceinline__ void restrict_block(int j, const double* __restrict__
       double rv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) rv[u] = r[gj[min(d0 + 256 * u, n - 1)]];
-#pragma unroll
+#pragma unroll 1
       for (int u = 0; u < 4; ++u) {
         const int d = d0 + 256 * u;
         if (d >= n) break;
         const double* zr = Zj + (int64_t)d * mj + c0;
+        // the row's 16 loads issued together (columns past nc read column
+        // nc - 1 and feed only accumulators that are never stored)
+        double zv[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-          if (c < nc) s[c] += zr[c] * rv[u];
+        for (int c = 0; c < 16; ++c) zv[c] = zr[min(c, nc - 1)];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) s[c] += zv[c] * rv[u];
       }
     }
 #pragma unroll
