@@ -777,9 +777,10 @@ hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
 // k_lauum: the symmetric inverse S = X^T X = A^{-1} from the inverse factor
 // X = L^{-1} (transposed tiles, as k_trtri_win leaves them): S(I, J) =
 // sum_{K >= I} X(K, I)^T X(K, J) for J <= I, written row-major in the packed
-// format, the diagonal tiles in full.  One wavefront per output tile; the
-// LA_NW wavefronts of a workgroup take consecutive tiles of one tile row,
-// so they read the same X(K, I) (served from L1).  With the transposed
+// format, the diagonal tiles in full.  One wavefront per two output tiles
+// (J, J + 1) of a tile row, which share the fragments of X(K, I); the
+// LA_NW wavefronts of a workgroup take consecutive pairs of one tile row,
+// so they also read the same X(K, I) (served from L1).  With the transposed
 // tiles both operands of every product are rows of stored tiles: each lane
 // reads 8 consecutive entries (two vector loads) per fragment, the next
 // K's fragments loaded while the current ones are multiplied.  Jobs come
@@ -787,6 +788,7 @@ hipError_t launch_trtri(bool fp32, const void* L, const void* dinv, void* X,
 // the job list (block b runs on XCD b % 8), so each XCD works on its own
 // matrices and keeps their factors in its L2.
 #define LA_NW 4
+#define LA_TW 2  // output tiles per wavefront
 
 template <typename T>
 __global__ __launch_bounds__(LA_NW * 64) void k_lauum(const T* __restrict__ XT, T* __restrict__ S,
@@ -798,59 +800,75 @@ __global__ __launch_bounds__(LA_NW * 64) void k_lauum(const T* __restrict__ XT, 
   const int q = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (q >= njobs) return;
   const int2 jb = jobs[q];
-  const int j = jb.x, I = jb.y >> 16, J = (jb.y & 0xffff) + (threadIdx.x >> 6);
+  // wavefront w takes the output tiles J and J + 1 of row I: both use the
+  // fragments of X(K, I), loaded once per K for the two
+  const int j = jb.x, I = jb.y >> 16, J = (jb.y & 0xffff) + LA_TW * (threadIdx.x >> 6);
   if (J > I) return;  // no barriers below: a wavefront may leave early
+  const bool two = J + 1 <= I;
+  const int J1 = two ? J + 1 : J;  // a second copy of tile J when J + 1 > I (not stored)
   const int nt = ntl[j];
   const int lane = threadIdx.x & 63, fi = lane & 15, fg = lane >> 4;
   const T* Xj = XT + toff[j] * TSQ + fi * TS + 8 * fg;
-  Acc acc[2][2];
+  Acc acc[2][2][2];
 #pragma unroll
-  for (int rq = 0; rq < 2; ++rq)
+  for (int o = 0; o < 2; ++o)
 #pragma unroll
-    for (int cq = 0; cq < 2; ++cq) acc[rq][cq] = acc_zero<T>();
-  V8<T> a[2], b[2];
-  auto load = [&](V8<T> (&fa)[2], V8<T> (&fb)[2], int K) {
+    for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+      for (int cq = 0; cq < 2; ++cq) acc[o][rq][cq] = acc_zero<T>();
+  struct Ops {
+    V8<T> a[2], b[2][2];
+  };
+  auto load = [&](Ops& f, int K) {
     const T* ta = Xj + tile_idx(K, I) * TSQ;
-    const T* tb = Xj + tile_idx(K, J) * TSQ;
+    const T* tb0 = Xj + tile_idx(K, J) * TSQ;
+    const T* tb1 = Xj + tile_idx(K, J1) * TSQ;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      ld8(fa[h], ta + h * 16 * TS);
-      ld8(fb[h], tb + h * 16 * TS);
+      ld8(f.a[h], ta + h * 16 * TS);
+      ld8(f.b[0][h], tb0 + h * 16 * TS);
+      ld8(f.b[1][h], tb1 + h * 16 * TS);
     }
   };
-  // two fragment sets alternate (rows unrolled by two): a register copy of
-  // a load in flight would wait for it, so K + 1's loads are issued into
-  // the other set and stay in flight during K's products
-  auto step = [&](const V8<T> (&ca)[2], const V8<T> (&cb)[2], V8<T> (&na)[2], V8<T> (&nb)[2],
-                  int K) {
-    load(na, nb, K + 1 < nt ? K + 1 : K);
+  // two operand sets alternate (K unrolled by two): a register copy of a
+  // load in flight would wait for it, so K + 1's loads are issued into the
+  // other set and stay in flight during K's products; each tile's products
+  // are added in K order, as with one tile per wavefront
+  auto step = [&](const Ops& c, Ops& n, int K) {
+    load(n, K + 1 < nt ? K + 1 : K);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int rq = 0; rq < 2; ++rq)
+      for (int o = 0; o < 2; ++o)
 #pragma unroll
-        for (int cq = 0; cq < 2; ++cq)
-          acc[rq][cq] = Mfma<T>::run(ca[rq].v[s], cb[cq].v[s], acc[rq][cq]);
+        for (int rq = 0; rq < 2; ++rq)
+#pragma unroll
+          for (int cq = 0; cq < 2; ++cq)
+            acc[o][rq][cq] = Mfma<T>::run(c.a[rq].v[s], c.b[o][cq].v[s], acc[o][rq][cq]);
   };
-  V8<T> a1[2], b1[2];
-  load(a, b, I);
+  Ops f0, f1;
+  load(f0, I);
   int K = I;
   for (; K + 1 < nt; K += 2) {
-    step(a, b, a1, b1, K);
-    step(a1, b1, a, b, K + 1);
+    step(f0, f1, K);
+    step(f1, f0, K + 1);
   }
-  if (K < nt) step(a, b, a1, b1, K);
-  T* Sj = S + (toff[j] + tile_idx(I, J)) * TSQ;
+  if (K < nt) step(f0, f1, K);
 #pragma unroll
-  for (int rq = 0; rq < 2; ++rq)
+  for (int o = 0; o < 2; ++o) {
+    if (o == 1 && !two) break;
+    T* Sj = S + (toff[j] + tile_idx(I, J + o)) * TSQ;
 #pragma unroll
-    for (int cq = 0; cq < 2; ++cq)
+    for (int rq = 0; rq < 2; ++rq)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Sj[(rq * 16 + acc_row<T>(lane, v)) * TS + cq * 16 + acc_col(lane)] = acc[rq][cq][v];
+      for (int cq = 0; cq < 2; ++cq)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          Sj[(rq * 16 + acc_row<T>(lane, v)) * TS + cq * 16 + acc_col(lane)] = acc[o][rq][cq][v];
+  }
 }
 
-int lauum_tiles_per_job() { return LA_NW; }
+int lauum_tiles_per_job() { return LA_NW * LA_TW; }
 
 hipError_t launch_lauum(bool fp32, const void* XT, void* S, const int64_t* toff, const int* nt,
                         const int2* jobs, int njobs, hipStream_t st) {
