@@ -881,11 +881,11 @@ int choose_local_form(const geneo_handle_s* h) {
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   // triangular: two passes of maxnt tile-row steps, measured at about
   // 2.4 us per step for FP32 factors (three workgroups per compute unit)
-  // and 3 us for FP64 factors (one workgroup of 8 wavefronts per unit)
+  // and 3 us for FP64 factors (two workgroups per unit)
   const int n64 = (int)h->f64list.size(), n32 = h->nsub - n64;
   const double cu = std::max(ncu, 1);
   const double t_tri = 2.0 * h->LD.maxnt *
-                       (2.4e-6 * std::ceil(n32 / (3.0 * cu)) + 3e-6 * std::ceil(n64 / cu));
+                       (2.4e-6 * std::ceil(n32 / (3.0 * cu)) + 3e-6 * std::ceil(n64 / (2.0 * cu)));
   std::vector<char> is64(h->nsub, 0);
   for (int j : h->f64list) is64[j] = 1;
   double bytes = 0.0, flops = 0.0;

@@ -292,13 +292,14 @@ hipError_t symv_cols(const SymvArgs& a, const int* done, hipStream_t st) {
 // diagonal tile and x of row i + 1 are loaded while row i is completed.  Lane (r, h) takes entry r of the
 // row (backward: column) and half h of the 32 entries it is summed over,
 // FP32 tiles converted to FP64 as used.
-// FP32 factors: 4 wavefronts of 2 tiles per row (168 registers, three
-// waves per SIMD); FP64 factors, whose tiles take twice the registers: 8
-// wavefronts of 1 tile.
+// FP32 factors: 4 wavefronts of 2 tiles per row, band tiles two rows ahead
+// (168 registers, three workgroups per CU); FP64 factors, whose tiles take
+// twice the registers: 4 wavefronts of 2 tiles, band tiles one row ahead,
+// so that two workgroups fit on a CU.
 #define LS32_NW 4
 #define LS32_MT 2
-#define LS64_NW 8
-#define LS64_MT 1
+#define LS64_NW 4
+#define LS64_MT 2
 #define LS_NW_MAX 8
 
 template <typename T> struct Frag16 { T v[16]; };
@@ -343,7 +344,7 @@ __device__ __forceinline__ double dot16(const Frag16<T>& f, const double* v) {
   return s;
 }
 
-template <typename T, int NW, int MT>
+template <typename T, int NW, int MT, int PD>
 __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ Dj,
                                 const int* __restrict__ Ej, const int* __restrict__ Rj, int nt,
                                 const double* __restrict__ xj, double* __restrict__ yj,
@@ -383,6 +384,9 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
   // the number of loads in flight is the same on every path and the waits
   // for the older ones can be partial.
   Frag16<T> a0[MT], a1[MT], d0, d1;
+  // PD = 2: two band buffers by row parity; PD = 1: one buffer, the next
+  // row's tiles loaded into it (fewer registers)
+  Frag16<T>(&b1)[MT] = PD == 2 ? a1 : a0;
   double x0 = 0.0, x1 = 0.0;
   // ---- forward: ys = L^{-1} x
   // The off-diagonal tiles of row i + 2 are loaded into the buffer of row
@@ -415,7 +419,7 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
       s += dot16(t, ys + k * TS + 16 * h);
     }
     fetch_diag_f(nd, nx, min(i + 1, nt - 1));
-    fetch_band_f(ab, min(i + 2, nt - 1));
+    fetch_band_f(ab, min(i + PD, nt - 1));
     s += __shfl_xor(s, 32);
     double(*pp)[TS] = part[i & 1];
     if (lane < TS) pp[w][r] = s;
@@ -431,11 +435,11 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
   };
   fetch_band_f(a0, 0);
   fetch_diag_f(d0, x0, 0);
-  fetch_band_f(a1, min(1, nt - 1));
+  if (PD == 2) fetch_band_f(a1, min(1, nt - 1));
   int i = 0;
   for (; i + 1 < nt; i += 2) {
     fwd_row(i, a0, d0, x0, d1, x1);
-    fwd_row(i + 1, a1, d1, x1, d0, x0);
+    fwd_row(i + 1, b1, d1, x1, d0, x0);
   }
   if (i < nt) fwd_row(i, a0, d0, x0, d1, x1);
   // the last forward row's partials are read before the backward rows
@@ -462,7 +466,7 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
       s += dot16(t, ys + k * TS + 16 * h);
     }
     frag_col(nd, Dj + (int64_t)max(i - 1, 0) * TSQ, r, h);
-    fetch_band_b(ab, max(i - 2, 0));
+    fetch_band_b(ab, max(i - PD, 0));
     s += __shfl_xor(s, 32);
     // y_i[r], read by every wavefront before the barrier after which z_i
     // overwrites it
@@ -481,20 +485,20 @@ __device__ void local_solve_job(const T* __restrict__ Lj, const T* __restrict__ 
   };
   fetch_band_b(a0, nt - 1);
   frag_col(d0, Dj + (int64_t)(nt - 1) * TSQ, r, h);
-  fetch_band_b(a1, max(nt - 2, 0));
+  if (PD == 2) fetch_band_b(a1, max(nt - 2, 0));
   i = nt - 1;
   for (; i >= 1; i -= 2) {
     bwd_row(i, a0, d0, d1);
-    bwd_row(i - 1, a1, d1, d0);
+    bwd_row(i - 1, b1, d1, d0);
   }
   if (i == 0) bwd_row(0, a0, d0, d1);
   block_sync();
   for (int e = threadIdx.x; e < nt * TS; e += blockDim.x) yj[e] = ys[e];
 }
 
-// one launch per factor precision (its registers set the occupancy: two
-// workgroups per CU with FP32 factors, one with FP64)
-template <typename T, int NW, int MT>
+// one launch per factor precision (its registers set the occupancy: three
+// workgroups per CU with FP32 factors, two with FP64)
+template <typename T, int NW, int MT, int PD>
 __device__ __forceinline__ void local_solve_block(const LocalSolveArgs& A, int j) {
   extern __shared__ double lsmem[];
   double(*part)[NW][TS] = reinterpret_cast<double(*)[NW][TS]>(lsmem);
@@ -509,18 +513,18 @@ __device__ __forceinline__ void local_solve_block(const LocalSolveArgs& A, int j
   const T* D = f64 ? (const T*)A.D64 : (const T*)A.D32;
   const int* E = f64 ? A.E64 : A.E32;
   const int* R = f64 ? A.R64 : A.R32;
-  local_solve_job<T, NW, MT>(L + to * TSQ, D + dof * TSQ, E ? E + dof : nullptr, R ? R + dof : nullptr,
+  local_solve_job<T, NW, MT, PD>(L + to * TSQ, D + dof * TSQ, E ? E + dof : nullptr, R ? R + dof : nullptr,
                      nt, A.x + A.voff[j], A.y + A.voff[j], ys, part, sv, sE, sR);
 }
 __global__ __launch_bounds__(LS32_NW * 64) void k_local_solve_f32(LocalSolveArgs A,
                                                                    const int* __restrict__ done) {
   if (done && *done) return;
-  local_solve_block<float, LS32_NW, LS32_MT>(A, A.jobs32[blockIdx.x]);
+  local_solve_block<float, LS32_NW, LS32_MT, 2>(A, A.jobs32[blockIdx.x]);
 }
 __global__ __launch_bounds__(LS64_NW * 64) void k_local_solve_f64(LocalSolveArgs A,
                                                                 const int* __restrict__ done) {
   if (done && *done) return;
-  local_solve_block<double, LS64_NW, LS64_MT>(A, A.jobs64[blockIdx.x]);
+  local_solve_block<double, LS64_NW, LS64_MT, 1>(A, A.jobs64[blockIdx.x]);
 }
 
 static size_t local_solve_lds(int maxnt) {
